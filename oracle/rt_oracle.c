@@ -1,0 +1,354 @@
+/*
+ * rt_oracle.c -- plain, slow FP64 CPU reference for the short-characteristics
+ * formal solution of Davis, Stone & Jiang (2012), "A Radiation Transfer Solver
+ * for Athena using Short Characteristics" (arXiv:1201.2222).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include, link
+ * or call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header, table or constant with the
+ * HIP implementation.
+ *
+ * What it computes (paper section 3.3, eq. rtdisc, and section 3.2, eqs.
+ * Jsum/Hsum/Ksum): for every ray k and every vertex x0 of the radiation grid
+ * (vertices = cell centres), the intensity I0 is integrated along the short
+ * characteristic from the upwind point x- on the face of the upwind cell box:
+ *
+ *     I0 = I- exp(-dtau) + psi- S- + psi0 S0                  (first order form)
+ *
+ * where I-, S- and chi- are bilinear interpolants on that face (section 3.3,
+ * "first-order (linear) interpolation"), dtau is the trapezoid optical depth of
+ * the segment, and psi-, psi0 integrate a source function that is linear in
+ * optical depth between S- and S0.  Moments J = sum w I, H_i = sum w mu_i I,
+ * K_ij = sum w mu_i mu_j I.  The diagonal of the Lambda operator (section 3.4,
+ * eq. dsjacobi) is Lambda_ii = sum_k w_k psi0_k.
+ *
+ * Sweep order: each ray is swept on its own over the whole grid in row-major
+ * order (x fastest) starting from the upwind corner of its octant, the order of
+ * the paper's Fig. f:sweep generalised to 3D.  Every upwind vertex then lies
+ * earlier in that order, so I- is always known.
+ *
+ * Boundaries (section 3.5, and the iteration of section 3 for periodic
+ * boundaries): a ghost vertex just outside the grid takes chi and S (and B) from
+ * the boundary vertex (periodic axes wrap instead of clamp).  Its intensity is
+ *   vacuum  : 0
+ *   thermal : B of that boundary vertex
+ *   fixed   : a caller-given array
+ *   periodic: the intensity the previous sweep produced at the wrapped vertex
+ *             ("fixed from the previous iteration"); before any sweep has run,
+ *             S of the wrapped vertex.
+ * When a ghost vertex lies outside a non-periodic face and another face at the
+ * same time, the non-periodic face with the highest axis (z, then y, then x)
+ * gives the intensity.
+ *
+ * Arithmetic is plain FP64 in the order written; build with
+ * -ffp-contract=off so that no multiply-add is fused.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_VACUUM 0
+#define ORC_THERMAL 1
+#define ORC_PERIODIC 2
+#define ORC_FIXED 3
+
+typedef struct {
+    int32_t n[3];      /* nx, ny, nz (x fastest in memory) */
+    int32_t nf;        /* frequency bins */
+    int32_t na;        /* rays */
+    int32_t bc_lo[3];  /* boundary kind at the low face of each axis */
+    int32_t bc_hi[3];  /* boundary kind at the high face of each axis */
+    int32_t want_hk;   /* non-zero: also accumulate H and K */
+    double h[3];       /* dx, dy, dz */
+} orc_grid;
+
+/* Per-ray geometry of the upwind short characteristic (section 3.3). */
+typedef struct {
+    int sgn[3];     /* direction signs, +1 when the cosine is zero */
+    int d;          /* axis whose face plane the upwind segment crosses first */
+    int a, b;       /* the two other axes, a < b */
+    double s;       /* path length from the upwind face point to the vertex */
+    double fa, fb;  /* fractional offsets of the face point along a and b */
+} orc_ray;
+
+static void ray_geometry(const double mu[3], const double h[3], orc_ray *r)
+{
+    double len[3];
+    for (int q = 0; q < 3; ++q) {
+        r->sgn[q] = (mu[q] < 0.0) ? -1 : 1;
+        len[q] = (mu[q] == 0.0) ? INFINITY : h[q] / fabs(mu[q]);
+    }
+    /* the plane reached first going upwind; on equal lengths z wins over y
+       and y over x */
+    int d = 2;
+    if (len[1] < len[d]) d = 1;
+    if (len[0] < len[d]) d = 0;
+    r->d = d;
+    r->a = (d == 0) ? 1 : 0;
+    r->b = (d == 2) ? 1 : 2;
+    r->s = len[d];
+    double fa = r->s * fabs(mu[r->a]) / h[r->a];
+    double fb = r->s * fabs(mu[r->b]) / h[r->b];
+    r->fa = fa > 1.0 ? 1.0 : fa;
+    r->fb = fb > 1.0 ? 1.0 : fb;
+}
+
+/*
+ * Coefficients of the first-order (linear in tau) integration over one segment
+ * of optical depth dt:  I0 = I- E + psim S- + psi0 S0.
+ *   E = exp(-dt), e0 = 1 - exp(-dt), psi0 = 1 - e0/dt, psim = e0 - psi0.
+ * For small dt, psi0 is summed from its Taylor series
+ *   psi0 = sum_{n>=1} (-1)^(n+1) dt^n / (n+1)!
+ * to avoid the cancellation in 1 - e0/dt.
+ */
+void orc_coeffs(double dt, double *E, double *psim, double *psi0)
+{
+    double e0 = -expm1(-dt);
+    double p0;
+    if (dt < 0.1) {
+        /* terms n = 1..13, summed from the smallest upward */
+        double term[14];
+        double fact = 1.0; /* (n+1)! */
+        double pw = 1.0;   /* dt^n */
+        for (int n = 1; n <= 13; ++n) {
+            pw *= dt;
+            fact *= (double)(n + 1);
+            term[n] = ((n % 2) ? pw : -pw) / fact;
+        }
+        p0 = 0.0;
+        for (int n = 13; n >= 1; --n) p0 += term[n];
+    } else {
+        p0 = 1.0 - e0 / dt;
+    }
+    *E = exp(-dt);
+    *psi0 = p0;
+    *psim = e0 - p0;
+}
+
+static inline int is_periodic(const orc_grid *g, int q)
+{
+    return g->bc_lo[q] == ORC_PERIODIC;
+}
+
+/* Bring an index that may be one step outside [0, n) back inside: wrap on a
+   periodic axis, clamp otherwise.  *out is set when the index was outside. */
+static inline int fold(int x, int n, int periodic, int *out)
+{
+    if (x >= 0 && x < n) return x;
+    *out = 1;
+    if (periodic) return (x < 0) ? x + n : x - n;
+    return (x < 0) ? 0 : n - 1;
+}
+
+static inline int64_t cell_index(const orc_grid *g, int i, int j, int k)
+{
+    return ((int64_t)k * g->n[1] + j) * g->n[0] + i;
+}
+
+/* index inside the plane normal to axis q, with the other two axes in
+   increasing order and the lower one fastest */
+static inline int64_t plane_index(const orc_grid *g, int q, const int u[3])
+{
+    int p1 = (q == 0) ? 1 : 0;
+    int p2 = (q == 2) ? 1 : 2;
+    return (int64_t)u[p2] * g->n[p1] + u[p1];
+}
+
+static inline int64_t plane_size(const orc_grid *g, int q)
+{
+    int p1 = (q == 0) ? 1 : 0;
+    int p2 = (q == 2) ? 1 : 2;
+    return (int64_t)g->n[p1] * g->n[p2];
+}
+
+typedef struct {
+    const orc_grid *g;
+    int f;                    /* bin */
+    int ray;                  /* ray index */
+    const double *chi, *S, *B;  /* this bin's fields */
+    const double *Icur;       /* this ray's intensities of the current sweep */
+    const double *const *fixed;   /* [6]: lo x, hi x, lo y, hi y, lo z, hi z */
+    const double *const *prev;    /* [3]: per periodic axis, previous sweep */
+    int have_prev;
+} orc_ctx;
+
+/* chi and S at vertex v (possibly a ghost vertex) */
+static void vertex_fields(const orc_ctx *c, const int v[3], double *chi, double *S)
+{
+    int u[3], out = 0;
+    for (int q = 0; q < 3; ++q) u[q] = fold(v[q], c->g->n[q], is_periodic(c->g, q), &out);
+    int64_t id = cell_index(c->g, u[0], u[1], u[2]);
+    *chi = c->chi[id];
+    *S = c->S[id];
+}
+
+/* intensity of the current ray at vertex v (possibly a ghost vertex) */
+static double vertex_intensity(const orc_ctx *c, const int v[3])
+{
+    const orc_grid *g = c->g;
+    int u[3], outq[3] = {0, 0, 0};
+    int any = 0;
+    for (int q = 0; q < 3; ++q) {
+        u[q] = fold(v[q], g->n[q], is_periodic(g, q), &outq[q]);
+        any |= outq[q];
+    }
+    if (!any) return c->Icur[cell_index(g, u[0], u[1], u[2])];
+
+    for (int q = 2; q >= 0; --q) {
+        if (!outq[q] || is_periodic(g, q)) continue;
+        int hi = v[q] >= g->n[q];
+        int kind = hi ? g->bc_hi[q] : g->bc_lo[q];
+        if (kind == ORC_VACUUM) return 0.0;
+        if (kind == ORC_THERMAL) return c->B[cell_index(g, u[0], u[1], u[2])];
+        /* fixed incident intensity: [nf][na][plane] */
+        const double *F = c->fixed[2 * q + hi];
+        int64_t ps = plane_size(g, q);
+        return F[((int64_t)c->f * g->na + c->ray) * ps + plane_index(g, q, u)];
+    }
+    /* only periodic axes are outside */
+    if (!c->have_prev) return c->S[cell_index(g, u[0], u[1], u[2])];
+    for (int q = 0; q < 3; ++q) {
+        if (!outq[q]) continue;
+        int64_t ps = plane_size(g, q);
+        return c->prev[q][((int64_t)c->f * g->na + c->ray) * ps + plane_index(g, q, u)];
+    }
+    return 0.0; /* not reached */
+}
+
+/*
+ * One formal solution: every ray swept once over every bin.
+ *   mu  [na][3] direction cosines, w [na] weights (summing to 1)
+ *   chi, B, S  [nf][nz][ny][nx]
+ *   fixed[6]   incident intensity per face ([nf][na][plane]) or NULL
+ *   prev_in[3] periodic memory from the previous sweep ([nf][na][plane]);
+ *              read only when have_prev != 0
+ *   prev_out[3] receives this sweep's intensity on each ray's outgoing plane of
+ *              every periodic axis
+ *   bin_active [nf] or NULL: bins with a zero entry are skipped and their
+ *              outputs left untouched
+ *   J, lam [nf][cells]; H [3][nf][cells]; K [6][nf][cells] (xx yy zz xy xz yz)
+ * Outputs are overwritten.  Returns 0, or -1 when scratch memory runs out.
+ */
+int orc_sweep(const orc_grid *g, const double *mu, const double *w,
+              const double *chi, const double *B, const double *S,
+              const double *const *fixed, const double *const *prev_in,
+              int have_prev, double *const *prev_out, const int32_t *bin_active,
+              double *J, double *H, double *K, double *lam)
+{
+    const int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    const int64_t tot = ncell * g->nf;
+    for (int f = 0; f < g->nf; ++f) {
+        if (bin_active && !bin_active[f]) continue;
+        memset(J + f * ncell, 0, sizeof(double) * ncell);
+        memset(lam + f * ncell, 0, sizeof(double) * ncell);
+        if (g->want_hk) {
+            for (int q = 0; q < 3; ++q) memset(H + q * tot + f * ncell, 0, sizeof(double) * ncell);
+            for (int q = 0; q < 6; ++q) memset(K + q * tot + f * ncell, 0, sizeof(double) * ncell);
+        }
+    }
+    double *Icur = (double *)malloc(sizeof(double) * ncell);
+    if (!Icur) return -1;
+
+    static const int oa[4] = {0, 1, 0, 1};
+    static const int ob[4] = {0, 0, 1, 1};
+
+    for (int f = 0; f < g->nf; ++f) {
+        if (bin_active && !bin_active[f]) continue;
+        const double *chif = chi + f * ncell;
+        const double *Bf = B + f * ncell;
+        const double *Sf = S + f * ncell;
+        for (int ray = 0; ray < g->na; ++ray) {
+            const double *m = mu + 3 * ray;
+            orc_ray r;
+            ray_geometry(m, g->h, &r);
+            double wv[4];
+            wv[0] = (1.0 - r.fa) * (1.0 - r.fb);
+            wv[1] = r.fa * (1.0 - r.fb);
+            wv[2] = (1.0 - r.fa) * r.fb;
+            wv[3] = r.fa * r.fb;
+
+            orc_ctx c = {g, f, ray, chif, Sf, Bf, Icur, fixed, prev_in, have_prev};
+            const double wk = w[ray];
+            const double mx = m[0], my = m[1], mz = m[2];
+
+            for (int kk = 0; kk < g->n[2]; ++kk) {
+                int k = (r.sgn[2] > 0) ? kk : g->n[2] - 1 - kk;
+                for (int jj = 0; jj < g->n[1]; ++jj) {
+                    int j = (r.sgn[1] > 0) ? jj : g->n[1] - 1 - jj;
+                    for (int ii = 0; ii < g->n[0]; ++ii) {
+                        int i = (r.sgn[0] > 0) ? ii : g->n[0] - 1 - ii;
+                        int cpos[3] = {i, j, k};
+                        double Iv[4], Sv[4], Cv[4];
+                        for (int t = 0; t < 4; ++t) {
+                            int v[3] = {i, j, k};
+                            v[r.d] -= r.sgn[r.d];
+                            v[r.a] -= oa[t] * r.sgn[r.a];
+                            v[r.b] -= ob[t] * r.sgn[r.b];
+                            Iv[t] = vertex_intensity(&c, v);
+                            vertex_fields(&c, v, &Cv[t], &Sv[t]);
+                        }
+                        double Im = ((wv[0] * Iv[0] + wv[1] * Iv[1]) + wv[2] * Iv[2]) + wv[3] * Iv[3];
+                        double Sm = ((wv[0] * Sv[0] + wv[1] * Sv[1]) + wv[2] * Sv[2]) + wv[3] * Sv[3];
+                        double Cm = ((wv[0] * Cv[0] + wv[1] * Cv[1]) + wv[2] * Cv[2]) + wv[3] * Cv[3];
+                        int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
+                        double S0 = Sf[id];
+                        double dt = r.s * (Cm + chif[id]) * 0.5;
+                        double E, psim, psi0;
+                        orc_coeffs(dt, &E, &psim, &psi0);
+                        double I0 = (Im * E + psim * Sm) + psi0 * S0;
+                        Icur[id] = I0;
+
+                        int64_t o = (int64_t)f * ncell + id;
+                        J[o] += wk * I0;
+                        lam[o] += wk * psi0;
+                        if (g->want_hk) {
+                            H[0 * tot + o] += wk * mx * I0;
+                            H[1 * tot + o] += wk * my * I0;
+                            H[2 * tot + o] += wk * mz * I0;
+                            K[0 * tot + o] += wk * mx * mx * I0;
+                            K[1 * tot + o] += wk * my * my * I0;
+                            K[2 * tot + o] += wk * mz * mz * I0;
+                            K[3 * tot + o] += wk * mx * my * I0;
+                            K[4 * tot + o] += wk * mx * mz * I0;
+                            K[5 * tot + o] += wk * my * mz * I0;
+                        }
+                    }
+                }
+            }
+            /* keep this ray's intensity on its outgoing plane of every periodic
+               axis for the next sweep */
+            for (int q = 0; q < 3; ++q) {
+                if (!is_periodic(g, q) || !prev_out || !prev_out[q]) continue;
+                int64_t ps = plane_size(g, q);
+                double *P = prev_out[q] + ((int64_t)f * g->na + ray) * ps;
+                int u[3];
+                for (u[2] = 0; u[2] < g->n[2]; ++u[2])
+                    for (u[1] = 0; u[1] < g->n[1]; ++u[1])
+                        for (u[0] = 0; u[0] < g->n[0]; ++u[0]) {
+                            int outc = (r.sgn[q] > 0) ? g->n[q] - 1 : 0;
+                            if (u[q] != outc) continue;
+                            P[plane_index(g, q, u)] = Icur[cell_index(g, u[0], u[1], u[2])];
+                        }
+            }
+        }
+    }
+    free(Icur);
+    return 0;
+}
+
+/* Geometry of one ray, exported for tests: d, a, b, signs; s, fa, fb. */
+void orc_ray_info(const double mu[3], const double h[3], int32_t *iout, double *dout)
+{
+    orc_ray r;
+    ray_geometry(mu, h, &r);
+    iout[0] = r.d;
+    iout[1] = r.a;
+    iout[2] = r.b;
+    iout[3] = r.sgn[0];
+    iout[4] = r.sgn[1];
+    iout[5] = r.sgn[2];
+    dout[0] = r.s;
+    dout[1] = r.fa;
+    dout[2] = r.fb;
+}

@@ -1,0 +1,218 @@
+"""Pins of the oracle's Jacobi ALI (paper section 3.4) and moments epilogue (section 4)
+against facts independent of it: an exact 1D two-stream reduction solved densely,
+the paper's closed forms eq. jana and eq. j1, flux conservation under pure
+scattering, and exact finite-difference identities."""
+import numpy as np
+import pytest
+
+
+def _psi(x):
+    """E, psi_minus, psi_0 of a source linear in tau (series below 1e-2)."""
+    x = np.asarray(x, dtype=np.float64)
+    E = np.exp(-x)
+    e0 = -np.expm1(-x)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        p0 = np.where(x < 1e-2, x / 2 - x ** 2 / 6 + x ** 3 / 24 - x ** 4 / 120 + x ** 5 / 720,
+                      1.0 - e0 / x)
+    return E, e0 - p0, p0
+
+
+def _two_stream_1d(chi, eps, B):
+    """Exact fixed point of the 1D two-stream short-characteristics problem
+    (mu = 1/sqrt 3, unit spacing, thermal ghost below level 0, vacuum above the
+    top), written out independently: build Lambda_1D column by column and solve
+    [1 - (1-eps) Lambda] S = eps B + (1-eps) j_b densely."""
+    n = len(chi)
+    s = np.sqrt(3.0)
+
+    def formal(S, with_bc):
+        up = np.zeros(n)
+        dn = np.zeros(n)
+        I = B[0] if with_bc else 0.0  # thermal ghost carries B of the boundary vertex
+        for k in range(n):
+            km = k - 1 if k > 0 else 0
+            E, pm, p0 = _psi(s * (chi[km] + chi[k]) / 2)
+            I = I * E + pm * S[km] + p0 * S[k]
+            up[k] = I
+        I = 0.0
+        for k in range(n - 1, -1, -1):
+            kp = k + 1 if k < n - 1 else n - 1
+            E, pm, p0 = _psi(s * (chi[kp] + chi[k]) / 2)
+            I = I * E + pm * S[kp] + p0 * S[k]
+            dn[k] = I
+        return 0.5 * (up + dn)
+
+    jb = formal(np.zeros(n), True)
+    L = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        L[:, c] = formal(e, False)
+    S = np.linalg.solve(np.eye(n) - (1 - eps)[:, None] * L, eps * B + (1 - eps) * jb)
+    return S, L @ S + jb
+
+
+def _exp_atmosphere(per_decade, decades=(-3, 3)):
+    """chi per level (bottom first) of an exponential atmosphere whose vertical optical
+    depth at the vertices spans 10^decades with per_decade levels per decade."""
+    n = per_decade * (decades[1] - decades[0]) + 1
+    tau = np.logspace(decades[1], decades[0], n)  # bottom -> top
+    hs = per_decade / np.log(10.0)                 # scale height in cells
+    return tau / hs, tau
+
+
+def test_two_stream_reduction_3d_equals_1d(oracle_mod):
+    """n_mu = 2 on cubic cells: every ray meets the corner vertex of its upwind box, so a
+    horizontally uniform 3D problem is the 1D two-stream problem with mu = 1/sqrt 3.
+    The converged 3D Jacobi ALI equals the dense 1D solution."""
+    o = oracle_mod
+    chi_z, tau = _exp_atmosphere(6, (-2, 2))
+    nz = len(chi_z)
+    eps_z = np.full(nz, 0.05)
+    B_z = 1.0 + 0.5 * np.linspace(0, 1, nz)
+    S1, J1 = _two_stream_1d(chi_z, eps_z, B_z)
+    nx = ny = 2
+    bc = lambda a: np.broadcast_to(a[:, None, None], (nz, ny, nx)).copy()
+    p = o.Problem((nx, ny, nz), bc(chi_z), bc(eps_z), bc(B_z), n_mu=2,
+                  bc_lo=(o.PERIODIC, o.PERIODIC, o.THERMAL), bc_hi=(o.PERIODIC, o.PERIODIC, o.VACUUM))
+    res = p.ali(delta_c=1e-13, max_iter=20000)
+    assert res["converged"]
+    assert np.allclose(res["S"][0], S1[:, None, None], rtol=1e-9)
+    assert np.allclose(res["J"][0], J1[:, None, None], rtol=1e-9)
+
+
+def test_two_stream_approaches_eq_jana(oracle_mod):
+    """The discrete two-stream solution converges with resolution to the paper's
+    Eddington-limit closed form J = B (1 - exp(-sqrt(3 eps) tau)/(1 + sqrt eps))
+    (section 5.1, eq. jana), and S(0) -> sqrt(eps) B at the surface."""
+    eps = 1e-2
+    errs, surf = [], []
+    for per in (9, 18, 36):
+        chi, tau = _exp_atmosphere(per, (-4, 4))
+        S, J = _two_stream_1d(chi, np.full(len(chi), eps), np.ones(len(chi)))
+        Jana = 1.0 - np.exp(-np.sqrt(3 * eps) * tau) / (1 + np.sqrt(eps))
+        errs.append(np.max(np.abs(J - Jana) / Jana))
+        surf.append(S[-1] / np.sqrt(eps))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.03
+    assert abs(surf[2] - 1.0) < abs(surf[0] - 1.0) and abs(surf[2] - 1.0) < 0.02
+
+
+def test_sinusoid_eq_j1(oracle_mod):
+    """Pure absorber, uniform chi, B = B0 + B1 cos(k x), all faces periodic (section 5.4,
+    eq. j1).  For a discrete angle set the exact answer is
+    J1/B1 = sum_k w_k / (1 + (k mu_xk / chi)^2); the short-characteristics solution
+    converges to it with resolution, and for n_mu = 12 it lies within 1% of the
+    continuum value (chi/k) arctan(k/chi)."""
+    o = oracle_mod
+    chi0, L, B1 = 1.0, 4.0, 0.1
+    kw = 2 * np.pi / L
+    mu, w = o.quadrature(4)
+    exact = np.sum(w / (1 + (kw * mu[:, 0] / chi0) ** 2))
+    errs = []
+    for N in (16, 32, 64):
+        x = (np.arange(N) + 0.5) * L / N
+        B = 1.0 + B1 * np.cos(kw * x)
+        p = o.Problem((N, 1, 1), np.full(N, chi0), 1.0, B, mu=mu, w=w, h=(L / N, 1.0, 1.0),
+                      bc_lo=(o.PERIODIC,) * 3, bc_hi=(o.PERIODIC,) * 3)
+        J = p.formal_solve(B, converge_periodic=1e-14, max_sweeps=3000)["J"].ravel()
+        amp = 2.0 / N * np.sum((J - 1.0) * np.cos(kw * x)) / B1
+        errs.append(abs(amp - exact))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.03 * exact
+    m12, w12 = o.quadrature(12)
+    disc = np.sum(w12 / (1 + (kw * m12[:, 0] / chi0) ** 2))
+    cont = (chi0 / kw) * np.arctan(kw / chi0)
+    assert abs(disc - cont) < 0.01 * cont
+
+
+def test_pure_scattering_flux_conservation(oracle_mod):
+    """eps = 0: S = J at the fixed point, so div H = 0 (eq. rade) and the horizontally
+    averaged H_z is the same at every height up to a discretisation error that shrinks
+    with resolution."""
+    o = oracle_mod
+    spreads = []
+    for nz in (12, 24, 48):
+        z = (np.arange(nz) + 0.5) / nz
+        chi_z = 3.0 * np.exp(-3.0 * z) * (10.0 / nz) / (1 - np.exp(-3.0))  # vertical tau ~ 10
+        nx = ny = 2
+        bc = lambda a: np.broadcast_to(a[:, None, None], (nz, ny, nx)).copy()
+        p = o.Problem((nx, ny, nz), bc(chi_z), 0.0, bc(np.ones(nz)), n_mu=4,
+                      bc_lo=(o.PERIODIC, o.PERIODIC, o.THERMAL), bc_hi=(o.PERIODIC, o.PERIODIC, o.VACUUM))
+        res = p.ali(delta_c=1e-11, max_iter=50000)
+        assert res["converged"]
+        Hz = p.sweep(res["S"], want_hk=True)["H"][2, 0].mean(axis=(1, 2))
+        spreads.append((Hz.max() - Hz.min()) / Hz.mean())
+    # first-order scheme: the spread falls roughly in proportion to the cell size
+    assert spreads[0] > spreads[1] > spreads[2]
+    assert spreads[2] < 0.15 and spreads[2] < 0.55 * spreads[0]
+
+
+def test_warm_start_and_fixed_iterations(oracle_mod):
+    """A warm start S0 = eps B + (1-eps) J_prev from a converged J (section 4), on the
+    same problem so its periodic memory is warm too, is converged after one
+    iteration; a cold start from fresh periodic memory is not; fixed_iters runs exactly
+    that many iterations."""
+    o = oracle_mod
+    rng = np.random.default_rng(2)
+    nx, ny, nz = 4, 3, 6
+    n = nx * ny * nz
+    chi = np.exp(rng.normal(0, 1, n))
+    eps = np.full(n, 0.1)
+    B = 1 + rng.random(n)
+    mk = lambda: o.Problem((nx, ny, nz), chi, eps, B, n_mu=4)
+    p = mk()
+    cold = p.ali(delta_c=1e-12, max_iter=5000)
+    assert cold["converged"] and cold["iters"][0] > 5
+    warm = p.ali(delta_c=1e-9, J_prev=cold["J"], max_iter=50)
+    assert warm["iters"][0] == 1
+    assert np.allclose(warm["S"], cold["S"], rtol=1e-10)
+    fresh = mk().ali(delta_c=1e-9, J_prev=cold["J"], max_iter=50)
+    assert fresh["iters"][0] > 1
+    fx = mk().ali(fixed_iters=3)
+    assert fx["iters"][0] == 3
+
+
+def test_divergence_stencil_exact_for_quadratics(oracle_mod):
+    """Second-order differences are exact for quadratic fields: central inside,
+    one-sided on non-periodic faces."""
+    o = oracle_mod
+    nx, ny, nz = 5, 4, 6
+    h = (0.5, 1.0, 2.0)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = i * h[0], j * h[1], k * h[2]
+    H = np.stack([x ** 2 + 3 * y, 2 * y ** 2 - x * z, 0.5 * z ** 2 + x])
+    div = o.divergence(H, h, (False, False, False))
+    assert np.allclose(div, 2 * x + 4 * y + z, rtol=1e-13, atol=1e-12)
+    # periodic axis: a full cosine period is differentiated by the central rule
+    N = 16
+    xs = np.arange(N)
+    Hp = np.zeros((3, 1, 1, N))
+    Hp[0, 0, 0] = np.cos(2 * np.pi * xs / N)
+    dp = o.divergence(Hp, (1.0, 1.0, 1.0), (True, True, True))[0, 0]
+    assert np.allclose(dp, -np.sin(2 * np.pi * xs / N) * np.sin(2 * np.pi / N), atol=1e-14)
+
+
+def test_moments_epilogue_isotropic(oracle_mod):
+    """Isotropic radiation (uniform S, every face periodic): f = K/J = delta/3,
+    H = 0, Q_int = 4 pi eps chi (J - B) and its frequency integral with w_nu."""
+    o = oracle_mod
+    nx, ny, nz = 3, 3, 3
+    n = nx * ny * nz
+    rng = np.random.default_rng(4)
+    chi = np.stack([np.full(n, 0.5), np.full(n, 4.0)])   # bin 0 thin (integral form), bin 1 thick
+    eps = np.stack([np.full(n, 0.3), np.full(n, 0.7)])
+    B = np.stack([np.full(n, 2.0), np.full(n, 1.0)])
+    S = np.stack([np.full(n, 1.5), np.full(n, 1.0)])
+    p = o.Problem((nx, ny, nz), chi, eps, B, n_mu=4, w_nu=np.array([0.25, 0.75]),
+                  bc_lo=(o.PERIODIC,) * 3, bc_hi=(o.PERIODIC,) * 3)
+    m = p.moments(S)
+    assert np.allclose(m["J"][0], 1.5) and np.allclose(m["J"][1], 1.0)
+    assert np.allclose(m["J_int"], 0.25 * 1.5 + 0.75 * 1.0)
+    for c in range(3):
+        assert np.allclose(m["f_int"][c], 1.0 / 3.0, rtol=1e-14)
+    assert np.max(np.abs(m["f_int"][3:])) < 1e-15
+    q0 = 4 * np.pi * 0.3 * 0.5 * (1.5 - 2.0)   # chi dx = 0.5 <= 1: integral form
+    assert np.allclose(m["Q"][0], q0, rtol=1e-13)
+    assert np.max(np.abs(m["Q"][1])) < 1e-12   # chi dx = 4 > 1: -4 pi div H with H = 0
+    assert np.allclose(m["heating"], 0.25 * q0 * n, rtol=1e-12)
