@@ -1,0 +1,189 @@
+/*
+ * rt.h -- C ABI of librtsc, an MI355X (gfx950) implementation of the short-
+ * characteristics radiative transfer solver of Davis, Stone & Jiang (2012),
+ * "A Radiation Transfer Solver for Athena using Short Characteristics".
+ *
+ * The library computes, on one GPU:
+ *   - the formal solution J = Lambda[S] of the static transfer equation
+ *     n.grad I = chi_tot (S - I) (section 2, eq. radtrans) by first-order short
+ *     characteristics on a Cartesian grid whose vertices are cell centres
+ *     (section 3.3, eq. rtdisc with psi+ = 0, bilinear face interpolation);
+ *   - the Jacobi accelerated Lambda iteration with the diagonal operator
+ *     Lambda* (section 3.4, eq. dsjacobi) for S = (1 - eps) J + eps B
+ *     (section 2, eq. sourcefunc), stopped by eq. conv;
+ *   - the moments J, H, K (section 3.2, eqs. Jsum/Hsum/Ksum), the variable
+ *     Eddington tensor f = K/J and the heating rate Q_rad (section 4).
+ *
+ * Conventions shared by every entry point
+ *   - Field layout: FP64, C order [nf][nz][ny][nx] (x fastest), one value per
+ *     vertex and frequency bin.  "cells" = nx*ny*nz.
+ *   - Device pointers are HIP device memory on the context's device; host
+ *     pointers are ordinary host memory.  The caller owns every buffer it passes
+ *     and must keep device buffers alive until the stream work has finished.
+ *     The library owns the per-problem state it allocates (internal copies of
+ *     the fields, Lambda*, the periodic memory, scratch) and frees it in
+ *     rt_problem_destroy.
+ *   - Every argument is validated before any device work is queued: a call that
+ *     returns RT_E_INVALID has changed nothing.  The reason is kept in
+ *     rt_last_error().  No call throws.
+ *   - Streams are hipStream_t values passed as void* (NULL = the null stream).
+ *   - A problem is used by one host thread at a time.
+ */
+#ifndef RTSC_RT_H
+#define RTSC_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RT_OK = 0,
+    RT_NOT_CONVERGED = 1,   /* results valid but max_iter reached */
+    RT_E_INVALID = -1,      /* bad argument; nothing was done */
+    RT_E_OOM = -2,          /* device allocation failed */
+    RT_E_HIP = -3,          /* a HIP runtime call failed */
+    RT_E_NONFINITE = -4,    /* a residual became NaN or Inf */
+    RT_E_UNSUPPORTED = -5   /* valid request this build does not implement */
+} rt_status;
+
+/* Sweep arithmetic.  RT_F64 integrates I itself in FP64 ("plain form").
+ * RT_F32 integrates D = I - S in FP32 (algebraically the same recurrence);
+ * Lambda*, the ALI update, residuals and all sums stay FP64 in both. */
+typedef enum { RT_F64 = 0, RT_F32 = 1 } rt_precision;
+
+/* Boundary kinds (section 3.5): intensity entering through a face is zero
+ * (VACUUM), the thermal source function B of the boundary vertex (THERMAL),
+ * a caller-given array (FIXED), or the intensity the previous sweep produced
+ * at the opposite face (PERIODIC; both faces of the axis must be periodic). */
+typedef enum { RT_BC_VACUUM = 0, RT_BC_THERMAL = 1, RT_BC_PERIODIC = 2, RT_BC_FIXED = 3 } rt_bc_kind;
+
+typedef struct {
+    int32_t nx, ny, nz;       /* grid vertices per axis, each >= 1 */
+    int32_t nf;               /* frequency bins, >= 1 */
+    double dx, dy, dz;        /* vertex spacing, > 0 */
+    int32_t n_mu;             /* angle set LQ_{n_mu}, n_mu in {2,4,6,8,10,12}; used when mu == NULL */
+    int32_t na;               /* number of rays when mu != NULL (multiple of 8) */
+    const double *mu;         /* host [na][3] direction cosines or NULL; na/8 rays per octant */
+    const double *w;          /* host [na] ray weights summing to 1 (with mu) */
+    const double *w_nu;       /* host [nf] frequency quadrature weights, or NULL for all 1 */
+    int32_t bc_lo[3];         /* rt_bc_kind at the low face of x, y, z */
+    int32_t bc_hi[3];         /* rt_bc_kind at the high face of x, y, z */
+    const double *I_fixed[6]; /* device, faces lo-x hi-x lo-y hi-y lo-z hi-z for RT_BC_FIXED:
+                                 [nf][na][n2][n1], (n1, n2) the face's in-plane axes in
+                                 increasing order (x-faces: y,z; y-faces: x,z; z-faces: x,y) */
+    int32_t precision;        /* rt_precision */
+    int32_t tile;             /* tile edge for the sweep (0 = default) */
+} rt_problem_desc;
+
+typedef struct rt_problem rt_problem;
+
+/* Human-readable text of a status / of the last failure on this thread. */
+const char *rt_status_string(rt_status s);
+const char *rt_last_error(void);
+
+/*
+ * rt_quadrature -- the level-symmetric angle set of section 3.2: n_a = n_mu (n_mu + 2)
+ * rays, identical in every octant and invariant under 90-degree rotations.  The
+ * directions per octant are (mu_i, mu_j, mu_k) with i + j + k = n_mu/2 + 2 and
+ * mu_i^2 = mu_1^2 + (i - 1) 2 (1 - 3 mu_1^2)/(n_mu - 2); mu_1 and one weight per
+ * permutation class satisfy sum_k w_k mu_x^2p = 1/(2p+1), p = 0, 2..n_mu/2.
+ * mu_out: host [n_mu(n_mu+2)][3]; w_out: host [n_mu(n_mu+2)]; either may be NULL
+ * to query *na_out only.  Octant-major order: octant o has the signs
+ * (-1)^(o&1), (-1)^(o>>1&1), (-1)^(o>>2&1) on x, y, z.
+ */
+rt_status rt_quadrature(int32_t n_mu, double *mu_out, double *w_out, int32_t *na_out);
+
+/* Device bytes rt_problem_create would allocate for this description. */
+rt_status rt_problem_bytes(const rt_problem_desc *desc, size_t *bytes);
+
+/* Create the per-problem device state on the current HIP device. */
+rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out);
+rt_status rt_problem_destroy(rt_problem *p);
+
+/*
+ * rt_problem_set_fields -- radiative properties per vertex and bin (section 2,
+ * eq. sourcefunc; section 3.1): chi = chi_abs + chi_sc (> 0 or 0), eps =
+ * chi_abs/chi_tot in [0, 1], B the thermal source function.  Device FP64
+ * [nf][nz][ny][nx].  The values are copied; the caller may reuse its buffers once
+ * the stream has passed this call.  Computes Lambda* (the diagonal of section 3.4)
+ * and resets the periodic memory to its cold state.
+ */
+rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *eps,
+                                const double *B, void *stream);
+
+/* Forget the previous sweep: periodic ghosts read S of the wrapped vertex on the
+ * next sweep (cold start of the periodic iteration, section 3). */
+rt_status rt_problem_reset_periodic(rt_problem *p, void *stream);
+
+/*
+ * rt_formal_solve -- one formal solution J = Lambda[S] (section 3.4, eq. formalsol):
+ * every ray is integrated once over the grid (section 3.3).  Periodic ghosts come
+ * from the previous sweep of this problem (section 3's iteration for periodic
+ * boundaries) or, after create/reset, from S.  S: device [nf][cells] FP64 (read);
+ * J: device [nf][cells] FP64 (written); lambda_star: device [nf][cells] or NULL,
+ * receives Lambda*_ii = sum_k w_k psi0_k.  Asynchronous on the stream.
+ */
+rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lambda_star,
+                          void *stream);
+
+typedef struct {
+    double delta_c;        /* stop when max |dS|/S <= delta_c (eq. conv) */
+    int32_t max_iter;      /* give up after this many iterations (RT_NOT_CONVERGED) */
+    int32_t fixed_iters;   /* > 0: run exactly this many iterations, no test */
+    int32_t per_bin_stop;  /* non-zero: a bin stops as soon as it converges */
+    int32_t warm_start;    /* 0: S0 = B; 1: S0 = S_inout; 2: S0 = eps B + (1-eps) J_inout */
+    int32_t check_every;   /* iterations between host checks of convergence (0 = default) */
+} rt_ali_opts;
+
+typedef struct {
+    int32_t iterations;       /* largest iteration count over bins */
+    int32_t bins_converged;
+    double max_rel_dS;        /* largest last residual over bins */
+    double seconds;           /* host wall time of the call */
+} rt_ali_stats;
+
+/*
+ * rt_ali_solve -- Jacobi ALI (section 3.4).  Iteration n: J^n = Lambda[S^n];
+ *   dS = ((1-eps) J^n + eps B - S^n) / (1 - (1-eps) Lambda*)   (eq. dsjacobi)
+ *   S^{n+1} = S^n + dS;  r = max over cells with S^{n+1} != 0 of |dS|/|S^{n+1}|  (eq. conv)
+ * per bin, in FP64.  On return S_inout holds S^{n+1} and J_out holds J^n of each
+ * bin's last iteration.  Start values per opts->warm_start; S_inout, J_out: device
+ * [nf][cells] FP64.  Synchronises the stream every check_every iterations to read
+ * the convergence flags; stats (host, may be NULL) reports them.
+ * Returns RT_OK, RT_NOT_CONVERGED or RT_E_NONFINITE (outputs then undefined).
+ */
+rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+                       rt_ali_stats *stats, void *stream);
+
+/* Per-bin iteration counts and last residuals of the most recent rt_ali_solve
+ * (host arrays [nf]; either may be NULL).  Synchronises the stream. */
+rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream);
+
+typedef struct {
+    double *J;         /* device [nf][cells] or NULL */
+    double *H;         /* device [3][nf][cells] or NULL */
+    double *K;         /* device [6][nf][cells] (xx yy zz xy xz yz) or NULL */
+    double *J_int;     /* device [cells]: sum_nu w_nu J_nu, or NULL */
+    double *H_int;     /* device [3][cells] or NULL */
+    double *K_int;     /* device [6][cells] or NULL */
+    double *f_int;     /* device [6][cells]: K_int/J_int (0 where J_int = 0), or NULL */
+    double *Q_int;     /* device [cells]: sum_nu w_nu Q_nu, or NULL */
+    double *heating;   /* host scalar: sum over cells of Q_int dV, or NULL (synchronises) */
+} rt_moments_out;
+
+/*
+ * rt_moments -- one formal solution on S with moments (section 3.2, eqs.
+ * Jsum/Hsum/Ksum), the Eddington tensor f = K/J and the heating rate of section 4:
+ * Q_nu = 4 pi eps chi (J - B) where chi dx_min <= 1, else -4 pi div H (second-order
+ * differences, wrapped on periodic axes, one-sided at other faces).  Frequency
+ * integrals use w_nu.  Periodic ghosts as in rt_formal_solve.
+ */
+rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTSC_RT_H */

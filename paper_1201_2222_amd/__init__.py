@@ -1,1 +1,268 @@
-"""MI355X-native short-characteristics radiative transfer (Davis, Stone & Jiang 2012)."""
+"""MI355X-native short-characteristics radiative transfer (Davis, Stone & Jiang 2012).
+
+Thin Python binding of the C ABI in ``include/rt.h`` (``librtsc.so``).  The
+functions here only marshal arguments: every step of the formal solution, the
+Lambda iteration and the moments runs in the library's HIP kernels.  PyTorch is
+used for device memory and streams only.  If the library is missing the calls
+raise; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtsc.so")
+
+RT_OK, RT_NOT_CONVERGED = 0, 1
+RT_E_INVALID, RT_E_OOM, RT_E_HIP, RT_E_NONFINITE, RT_E_UNSUPPORTED = -1, -2, -3, -4, -5
+RT_F64, RT_F32 = 0, 1
+RT_BC_VACUUM, RT_BC_THERMAL, RT_BC_PERIODIC, RT_BC_FIXED = 0, 1, 2, 3
+
+# names of the C entry points (include/rt.h); every one is looked up at load time
+EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
+           "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
+           "rt_ali_solve", "rt_ali_bin_stats", "rt_moments")
+
+
+class RtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("nf", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("n_mu", ctypes.c_int32), ("na", ctypes.c_int32),
+                ("mu", ctypes.c_void_p), ("w", ctypes.c_void_p), ("w_nu", ctypes.c_void_p),
+                ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
+                ("I_fixed", ctypes.c_void_p * 6),
+                ("precision", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+class AliOpts(ctypes.Structure):
+    _fields_ = [("delta_c", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
+                ("per_bin_stop", ctypes.c_int32), ("warm_start", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class AliStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("bins_converged", ctypes.c_int32),
+                ("max_rel_dS", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class MomentsOut(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_void_p), ("H", ctypes.c_void_p), ("K", ctypes.c_void_p),
+                ("J_int", ctypes.c_void_p), ("H_int", ctypes.c_void_p), ("K_int", ctypes.c_void_p),
+                ("f_int", ctypes.c_void_p), ("Q_int", ctypes.c_void_p), ("heating", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load librtsc.so from the package directory (built by ``build.py``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"librtsc.so is not built ({LIB_PATH}); run paper_1201_2222_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    lib.rt_status_string.restype = ctypes.c_char_p
+    lib.rt_status_string.argtypes = [ctypes.c_int]
+    lib.rt_last_error.restype = ctypes.c_char_p
+    lib.rt_last_error.argtypes = []
+    lib.rt_quadrature.argtypes = [I32, P, P, P]
+    lib.rt_problem_bytes.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_size_t)]
+    lib.rt_problem_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
+    lib.rt_problem_destroy.argtypes = [P]
+    lib.rt_problem_set_fields.argtypes = [P, P, P, P, P]
+    lib.rt_problem_reset_periodic.argtypes = [P, P]
+    lib.rt_formal_solve.argtypes = [P, P, P, P, P]
+    lib.rt_ali_solve.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
+    lib.rt_ali_bin_stats.argtypes = [P, P, P, P]
+    lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
+    for name in EXPORTS:
+        getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=(RT_OK,)):
+    if status not in allow:
+        lib = load()
+        raise RtError(status, lib.rt_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t, n=None, name="tensor"):
+    """Device pointer of a contiguous float64 CUDA tensor with n elements."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def rt_quadrature(n_mu: int):
+    """Level-symmetric angle set (mu [na, 3], w [na]) generated by the library."""
+    lib = load()
+    na = ctypes.c_int32()
+    _check(lib.rt_quadrature(n_mu, None, None, ctypes.byref(na)))
+    mu = np.zeros((na.value, 3))
+    w = np.zeros(na.value)
+    _check(lib.rt_quadrature(n_mu, mu.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(na)))
+    return mu, w
+
+
+def make_desc(shape, nf=1, h=(1.0, 1.0, 1.0), n_mu=4, bc_lo=(2, 2, 1), bc_hi=(2, 2, 0), precision=RT_F64,
+              mu=None, w=None, w_nu=None, I_fixed=None, tile=0):
+    d = ProblemDesc()
+    d.nx, d.ny, d.nz = (int(x) for x in shape)
+    d.nf = int(nf)
+    d.dx, d.dy, d.dz = (float(x) for x in h)
+    d.n_mu = int(n_mu)
+    keep = []
+    if mu is not None:
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        keep += [mu, w]
+        d.na = len(w)
+        d.mu = mu.ctypes.data
+        d.w = w.ctypes.data
+    if w_nu is not None:
+        w_nu = np.ascontiguousarray(w_nu, dtype=np.float64)
+        keep.append(w_nu)
+        d.w_nu = w_nu.ctypes.data
+    d.bc_lo[:] = [int(x) for x in bc_lo]
+    d.bc_hi[:] = [int(x) for x in bc_hi]
+    if I_fixed is not None:
+        for k, t in enumerate(I_fixed):
+            if t is not None:
+                d.I_fixed[k] = _dptr(t, name="I_fixed").value
+                keep.append(t)
+    d.precision = int(precision)
+    d.tile = int(tile)
+    d._keep = keep
+    return d
+
+
+def rt_problem_bytes(desc: ProblemDesc) -> int:
+    lib = load()
+    b = ctypes.c_size_t()
+    _check(lib.rt_problem_bytes(ctypes.byref(desc), ctypes.byref(b)))
+    return b.value
+
+
+def rt_problem_create(desc: ProblemDesc):
+    lib = load()
+    h = ctypes.c_void_p()
+    _check(lib.rt_problem_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def rt_problem_destroy(p):
+    return _check(load().rt_problem_destroy(p))
+
+
+def rt_problem_set_fields(p, chi, eps, B, stream=None):
+    n = chi.numel()
+    return _check(load().rt_problem_set_fields(p, _dptr(chi, name="chi"), _dptr(eps, n, "eps"),
+                                               _dptr(B, n, "B"), _stream(stream)))
+
+
+def rt_problem_reset_periodic(p, stream=None):
+    return _check(load().rt_problem_reset_periodic(p, _stream(stream)))
+
+
+def rt_formal_solve(p, S, J, lambda_star=None, stream=None):
+    n = S.numel()
+    return _check(load().rt_formal_solve(p, _dptr(S, name="S"), _dptr(J, n, "J"),
+                                         _dptr(lambda_star, n, "lambda_star"), _stream(stream)))
+
+
+def rt_ali_solve(p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True, warm_start=0,
+                 check_every=0, stream=None):
+    """Returns (status, stats dict); status is RT_OK or RT_NOT_CONVERGED, errors raise."""
+    o = AliOpts(float(delta_c), int(max_iter), int(fixed_iters), 1 if per_bin_stop else 0, int(warm_start),
+                int(check_every))
+    st = AliStats()
+    n = S.numel()
+    status = load().rt_ali_solve(p, ctypes.byref(o), _dptr(S, name="S"), _dptr(J, n, "J"), ctypes.byref(st),
+                                 _stream(stream))
+    _check(status, allow=(RT_OK, RT_NOT_CONVERGED))
+    return status, {"iterations": st.iterations, "bins_converged": st.bins_converged,
+                    "max_rel_dS": st.max_rel_dS, "seconds": st.seconds}
+
+
+def rt_ali_bin_stats(p, nf, stream=None):
+    it = np.zeros(nf, dtype=np.int32)
+    rs = np.zeros(nf)
+    _check(load().rt_ali_bin_stats(p, it.ctypes.data_as(ctypes.c_void_p), rs.ctypes.data_as(ctypes.c_void_p),
+                                   _stream(stream)))
+    return it, rs
+
+
+def rt_moments(p, S, J=None, H=None, K=None, J_int=None, H_int=None, K_int=None, f_int=None, Q_int=None,
+               want_heating=False, stream=None):
+    heat = ctypes.c_double(0.0)
+    out = MomentsOut(*[(_dptr(t).value if t is not None else None) for t in (J, H, K, J_int, H_int, K_int,
+                                                                            f_int, Q_int)],
+                     ctypes.addressof(heat) if want_heating else None)
+    _check(load().rt_moments(p, _dptr(S, name="S"), ctypes.byref(out), _stream(stream)))
+    return heat.value if want_heating else None
+
+
+class Problem:
+    """Owner of one ``rt_problem`` handle (marshalling only)."""
+
+    def __init__(self, shape, nf=1, **kw):
+        self.shape = tuple(int(x) for x in shape)
+        self.nf = int(nf)
+        self.desc = make_desc(shape, nf=nf, **kw)
+        self.handle = rt_problem_create(self.desc)
+        self.cells = int(np.prod(self.shape))
+
+    def set_fields(self, chi, eps, B, stream=None):
+        rt_problem_set_fields(self.handle, chi, eps, B, stream)
+
+    def reset_periodic(self, stream=None):
+        rt_problem_reset_periodic(self.handle, stream)
+
+    def formal_solve(self, S, J, lambda_star=None, stream=None):
+        rt_formal_solve(self.handle, S, J, lambda_star, stream)
+
+    def ali_solve(self, S, J, **kw):
+        return rt_ali_solve(self.handle, S, J, **kw)
+
+    def moments(self, S, **kw):
+        return rt_moments(self.handle, S, **kw)
+
+    def close(self):
+        if self.handle:
+            rt_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

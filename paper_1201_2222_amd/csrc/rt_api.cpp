@@ -1,0 +1,734 @@
+// Host runtime and C ABI of librtsc (declarations in include/rt.h).
+//
+// Owns the per-problem device state, the angle set and per-ray geometry, the
+// tile schedule of the wavefront sweep, and the Jacobi ALI driver.  Every step of
+// the formal solution and of the iteration runs in the HIP kernels of
+// rt_kernels.hip; this file only validates, allocates and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "rt_internal.h"
+
+using namespace rtsc;
+
+namespace {
+
+thread_local std::string g_err;
+
+rt_status fail(rt_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(RT_E_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                              \
+    } while (0)
+
+// ---------------------------------------------------------------------------------
+// Level-symmetric angle set (section 3.2).  Per octant: directions (mu_i, mu_j, mu_k)
+// with i + j + k = m + 2 (m = n_mu/2), levels mu_i^2 = a + (i-1) 2(1-3a)/(n_mu-2), one
+// weight per permutation class.  Given a = mu_1^2 the class weights follow linearly
+// from the conditions <mu_x^2p> = 1/(2p+1), p = 0, 2..m-1; a itself is the smallest
+// root in (0, 1/3) of the remaining condition p = m with all weights positive.
+// Evaluated in long double; the root by bracketing and bisection.
+// ---------------------------------------------------------------------------------
+struct LsClass {
+    int i, j, k;
+};
+
+std::vector<LsClass> ls_classes(int m)
+{
+    std::vector<LsClass> c;
+    for (int i = 1; i <= m; ++i)
+        for (int j = i; j <= m; ++j)
+            for (int k = j; k <= m; ++k)
+                if (i + j + k == m + 2) c.push_back({i, j, k});
+    return c;
+}
+
+// sum over the distinct permutations of a class of (level of the first index)^p
+long double class_moment(const LsClass &c, int p, const std::vector<long double> &lev)
+{
+    int t[3] = {c.i, c.j, c.k};
+    std::sort(t, t + 3);
+    long double acc = 0.0L;
+    do {
+        acc += std::pow(lev[t[0] - 1], (long double)p);
+    } while (std::next_permutation(t, t + 3));
+    return acc;
+}
+
+bool ls_weights(int n_mu, long double a, std::vector<long double> &wc, long double &resid)
+{
+    const int m = n_mu / 2;
+    std::vector<LsClass> cls = ls_classes(m);
+    const int nc = (int)cls.size();
+    std::vector<long double> lev(m);
+    const long double step = 2.0L * (1.0L - 3.0L * a) / (n_mu - 2);
+    for (int i = 0; i < m; ++i) lev[i] = a + i * step;
+    std::vector<int> ps;
+    ps.push_back(0);
+    for (int p = 2; p < m; ++p) ps.push_back(p);
+    // augmented system, Gaussian elimination with partial pivoting
+    std::vector<std::vector<long double>> M(nc, std::vector<long double>(nc + 1));
+    for (int r = 0; r < nc; ++r) {
+        for (int c = 0; c < nc; ++c) M[r][c] = class_moment(cls[c], ps[r], lev);
+        M[r][nc] = 1.0L / (2 * ps[r] + 1);
+    }
+    for (int c = 0; c < nc; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < nc; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+        if (std::fabs(M[piv][c]) < 1e-300L) return false;
+        std::swap(M[c], M[piv]);
+        for (int r = 0; r < nc; ++r) {
+            if (r == c) continue;
+            const long double f = M[r][c] / M[c][c];
+            for (int k = c; k <= nc; ++k) M[r][k] -= f * M[c][k];
+        }
+    }
+    wc.assign(nc, 0.0L);
+    for (int c = 0; c < nc; ++c) wc[c] = M[c][nc] / M[c][c];
+    resid = -1.0L / (2 * m + 1);
+    for (int c = 0; c < nc; ++c) resid += wc[c] * class_moment(cls[c], m, lev);
+    return true;
+}
+
+bool level_symmetric(int n_mu, std::vector<double> &mu, std::vector<double> &w)
+{
+    const int m = n_mu / 2;
+    long double a;
+    std::vector<long double> wc;
+    if (n_mu == 2) {
+        a = 1.0L / 3.0L;
+        wc.assign(1, 1.0L);
+    } else {
+        const int N = 4000;
+        const long double lo = 1e-6L, hi = 1.0L / 3.0L - 1e-6L;
+        bool found = false;
+        long double r0 = 0.0L;
+        std::vector<long double> wtmp;
+        bool ok0 = ls_weights(n_mu, lo, wtmp, r0);
+        long double x0 = lo;
+        for (int s = 1; s <= N && !found; ++s) {
+            const long double x1 = lo + (hi - lo) * s / N;
+            long double r1;
+            const bool ok1 = ls_weights(n_mu, x1, wtmp, r1);
+            if (ok0 && ok1 && (r0 == 0.0L || (r0 < 0.0L) != (r1 < 0.0L))) {
+                long double xa = x0, xb = x1, ra = r0;
+                for (int it = 0; it < 200; ++it) {
+                    const long double xm = 0.5L * (xa + xb);
+                    long double rm;
+                    ls_weights(n_mu, xm, wtmp, rm);
+                    if (rm == 0.0L || xm == xa || xm == xb) {
+                        xa = xb = xm;
+                        break;
+                    }
+                    if ((rm < 0.0L) == (ra < 0.0L)) {
+                        xa = xm;
+                        ra = rm;
+                    } else {
+                        xb = xm;
+                    }
+                }
+                const long double root = 0.5L * (xa + xb);
+                long double rr;
+                if (ls_weights(n_mu, root, wc, rr) &&
+                    std::all_of(wc.begin(), wc.end(), [](long double v) { return v > 0.0L; })) {
+                    a = root;
+                    found = true;
+                }
+            }
+            x0 = x1;
+            r0 = r1;
+            ok0 = ok1;
+        }
+        if (!found) return false;
+    }
+    std::vector<long double> lev(m);
+    for (int i = 0; i < m; ++i) lev[i] = (n_mu == 2) ? a : a + i * 2.0L * (1.0L - 3.0L * a) / (n_mu - 2);
+    std::vector<LsClass> cls = (n_mu == 2) ? std::vector<LsClass>{{1, 1, 1}} : ls_classes(m);
+    // directions of one octant in lexicographic order of (i, j, k), with their class weight
+    std::vector<double> mo, wo;
+    for (int i = 1; i <= m; ++i)
+        for (int j = 1; j <= m; ++j)
+            for (int k = 1; k <= m; ++k) {
+                if (i + j + k != m + 2) continue;
+                int t[3] = {i, j, k};
+                std::sort(t, t + 3);
+                int ci = -1;
+                for (size_t c = 0; c < cls.size(); ++c)
+                    if (cls[c].i == t[0] && cls[c].j == t[1] && cls[c].k == t[2]) ci = (int)c;
+                mo.push_back((double)std::sqrt(lev[i - 1]));
+                mo.push_back((double)std::sqrt(lev[j - 1]));
+                mo.push_back((double)std::sqrt(lev[k - 1]));
+                wo.push_back((double)(wc[ci] / 8.0L));
+            }
+    const int per = (int)wo.size();
+    mu.assign((size_t)8 * per * 3, 0.0);
+    w.assign((size_t)8 * per, 0.0);
+    for (int o = 0; o < 8; ++o)
+        for (int r = 0; r < per; ++r) {
+            for (int q = 0; q < 3; ++q) mu[((size_t)o * per + r) * 3 + q] = ((o >> q) & 1 ? -1.0 : 1.0) * mo[r * 3 + q];
+            w[(size_t)o * per + r] = wo[r];
+        }
+    return true;
+}
+
+int octant_of(const double *m) { return (m[0] < 0.0 ? 1 : 0) | (m[1] < 0.0 ? 2 : 0) | (m[2] < 0.0 ? 4 : 0); }
+
+// Short-characteristic geometry of a ray on a uniform grid (section 3.3): the face
+// plane crossed first going upwind, path length and bilinear face weights.
+RayGeo ray_geometry(const double m[3], const double h[3], double wk, int gidx)
+{
+    RayGeo g{};
+    double len[3];
+    for (int q = 0; q < 3; ++q) len[q] = (m[q] == 0.0) ? std::numeric_limits<double>::infinity() : h[q] / std::fabs(m[q]);
+    int d = 2;  // equal lengths: z before y before x
+    if (len[1] < len[d]) d = 1;
+    if (len[0] < len[d]) d = 0;
+    g.d = d;
+    g.a = (d == 0) ? 1 : 0;
+    g.b = (d == 2) ? 1 : 2;
+    g.oct = octant_of(m);
+    g.gidx = gidx;
+    g.s = len[d];
+    const double fa = std::min(1.0, g.s * std::fabs(m[g.a]) / h[g.a]);
+    const double fb = std::min(1.0, g.s * std::fabs(m[g.b]) / h[g.b]);
+    g.w4[0] = (1.0 - fa) * (1.0 - fb);
+    g.w4[1] = fa * (1.0 - fb);
+    g.w4[2] = (1.0 - fa) * fb;
+    g.w4[3] = fa * fb;
+    g.wk = wk;
+    for (int q = 0; q < 3; ++q) g.mu[q] = m[q];
+    return g;
+}
+
+}  // namespace
+
+struct rt_problem {
+    rt_problem_desc desc{};
+    int n[3]{};
+    int nf = 0, na = 0, R = 0;
+    int nt[3]{};
+    int nstages = 0;
+    int64_t cells = 0;
+    int64_t plane[3]{};
+    int periodic[3]{};
+    bool f32 = false;
+    bool cold = true;
+    bool have_fields = false;
+    std::vector<RayGeo> rays;          // octant-major
+    std::vector<double> w_nu;
+    std::vector<int> stage_off;        // [nstages + 1]
+    // device state
+    RayGeo *d_rays = nullptr;
+    int *d_tiles = nullptr;
+    double *chi64 = nullptr, *eps = nullptr, *B = nullptr, *lam = nullptr;
+    float *chi32 = nullptr, *S32 = nullptr;
+    void *face[3]{};                   // Real
+    void *part = nullptr;              // Real [8][nf][cells]
+    int *frozen = nullptr, *parity = nullptr, *iters = nullptr, *flags = nullptr;
+    double *resid = nullptr;
+    unsigned long long *res_bits = nullptr;
+    int *h_flags = nullptr;            // pinned host copy of flags
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+size_t real_size(const rt_problem_desc *d) { return d->precision == RT_F32 ? sizeof(float) : sizeof(double); }
+
+rt_status validate(const rt_problem_desc *d, int *na_out)
+{
+    if (!d) return fail(RT_E_INVALID, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(RT_E_INVALID, "grid dimensions must be >= 1");
+    if (d->nx > 8000 || d->ny > 8000 || d->nz > 8000) return fail(RT_E_INVALID, "grid dimension above 8000");
+    if (d->nf < 1 || d->nf > 65535) return fail(RT_E_INVALID, "nf must be in [1, 65535]");
+    if (!(d->dx > 0.0) || !(d->dy > 0.0) || !(d->dz > 0.0) || !std::isfinite(d->dx) || !std::isfinite(d->dy) ||
+        !std::isfinite(d->dz))
+        return fail(RT_E_INVALID, "dx, dy, dz must be finite and > 0");
+    if (d->precision != RT_F64 && d->precision != RT_F32) return fail(RT_E_INVALID, "unknown precision");
+    if (d->tile != 0 && d->tile != kTile) return fail(RT_E_UNSUPPORTED, "tile edge %d not built (only %d)", d->tile, kTile);
+    for (int q = 0; q < 3; ++q) {
+        for (int k : {d->bc_lo[q], d->bc_hi[q]})
+            if (k < RT_BC_VACUUM || k > RT_BC_FIXED) return fail(RT_E_INVALID, "unknown boundary kind on axis %d", q);
+        if ((d->bc_lo[q] == RT_BC_PERIODIC) != (d->bc_hi[q] == RT_BC_PERIODIC))
+            return fail(RT_E_INVALID, "axis %d periodic on one face only", q);
+        if (d->bc_lo[q] == RT_BC_FIXED && !d->I_fixed[2 * q]) return fail(RT_E_INVALID, "FIXED low face %d without data", q);
+        if (d->bc_hi[q] == RT_BC_FIXED && !d->I_fixed[2 * q + 1]) return fail(RT_E_INVALID, "FIXED high face %d without data", q);
+    }
+    int na;
+    if (d->mu) {
+        if (!d->w) return fail(RT_E_INVALID, "mu given without w");
+        na = d->na;
+        if (na < 8 || na % 8 != 0 || na > 8 * 64) return fail(RT_E_INVALID, "na must be a multiple of 8 in [8, 512]");
+        int cnt[8] = {0};
+        double wsum = 0.0;
+        for (int k = 0; k < na; ++k) {
+            const double *m = d->mu + 3 * k;
+            const double nrm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+            if (!(std::fabs(nrm - 1.0) < 1e-12)) return fail(RT_E_INVALID, "ray %d is not a unit vector", k);
+            if (!(d->w[k] >= 0.0)) return fail(RT_E_INVALID, "ray %d has a negative weight", k);
+            ++cnt[octant_of(m)];
+            wsum += d->w[k];
+        }
+        for (int o = 0; o < 8; ++o)
+            if (cnt[o] != na / 8) return fail(RT_E_INVALID, "every octant needs na/8 rays (octant %d has %d)", o, cnt[o]);
+        if (!(std::fabs(wsum - 1.0) < 1e-12)) return fail(RT_E_INVALID, "ray weights sum to %.17g, not 1", wsum);
+    } else {
+        if (d->n_mu != 2 && d->n_mu != 4 && d->n_mu != 6 && d->n_mu != 8 && d->n_mu != 10 && d->n_mu != 12)
+            return fail(RT_E_INVALID, "n_mu must be 2, 4, 6, 8, 10 or 12");
+        na = d->n_mu * (d->n_mu + 2);
+    }
+    if (d->w_nu)
+        for (int f = 0; f < d->nf; ++f)
+            if (!std::isfinite(d->w_nu[f])) return fail(RT_E_INVALID, "w_nu[%d] is not finite", f);
+    *na_out = na;
+    return RT_OK;
+}
+
+void tile_counts(const rt_problem_desc *d, int nt[3])
+{
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int q = 0; q < 3; ++q) nt[q] = (n[q] + kTile - 1) / kTile;
+}
+
+size_t state_bytes(const rt_problem_desc *d, int na)
+{
+    const int64_t cells = (int64_t)d->nx * d->ny * d->nz;
+    const int64_t nc = cells * d->nf;
+    const size_t rs = real_size(d);
+    int nt[3];
+    tile_counts(d, nt);
+    const int64_t plane[3] = {(int64_t)d->ny * d->nz, (int64_t)d->nx * d->nz, (int64_t)d->nx * d->ny};
+    size_t b = 0;
+    b += (size_t)nc * 8 * 4;                       // chi64, eps, B, lam
+    if (d->precision == RT_F32) b += (size_t)nc * 4 * 2;  // chi32, S32
+    for (int q = 0; q < 3; ++q) b += (size_t)d->nf * na * (nt[q] + 1) * plane[q] * rs;
+    b += (size_t)8 * nc * rs;                      // partials
+    b += (size_t)na * sizeof(RayGeo) + (size_t)nt[0] * nt[1] * nt[2] * 4 + (size_t)d->nf * 32 + 64;
+    return b;
+}
+
+template <typename T>
+rt_status dalloc(rt_problem *p, T **ptr, size_t count)
+{
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, std::max<size_t>(count * sizeof(T), 16));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RT_E_OOM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    }
+    p->allocs.push_back(v);
+    *ptr = static_cast<T *>(v);
+    return RT_OK;
+}
+
+template <typename Real>
+SweepArgs<Real> sweep_args(rt_problem *p, const Real *S)
+{
+    SweepArgs<Real> A{};
+    for (int q = 0; q < 3; ++q) {
+        A.n[q] = p->n[q];
+        A.nt[q] = p->nt[q];
+        A.bc_lo[q] = p->desc.bc_lo[q];
+        A.bc_hi[q] = p->desc.bc_hi[q];
+        A.periodic[q] = p->periodic[q];
+        A.plane[q] = p->plane[q];
+        A.face[q] = static_cast<Real *>(p->face[q]);
+    }
+    A.nf = p->nf;
+    A.na = p->na;
+    A.R = p->R;
+    A.cells = p->cells;
+    A.rays = p->d_rays;
+    A.chi = p->f32 ? reinterpret_cast<const Real *>(p->chi32) : reinterpret_cast<const Real *>(p->chi64);
+    A.S = S;
+    A.B = p->B;
+    for (int k = 0; k < 6; ++k) A.fixed[k] = p->desc.I_fixed[k];
+    A.part = static_cast<Real *>(p->part);
+    A.tiles = p->d_tiles;
+    A.frozen = p->frozen;
+    A.parity = p->parity;
+    return A;
+}
+
+// Waves per sweep workgroup: one per ray of the octant, capped so the dynamic LDS
+// (chi and S tiles, two plane buffers and a partial-sum tile per wave) stays within
+// 64 KiB.
+int sweep_waves(const rt_problem *p)
+{
+    const int real = p->f32 ? 4 : 8;
+    const int tp = kTile + 1;
+    const int budget = (65536 / real - 2 * tp * tp * tp) / (2 * tp * tp + kTile * kTile * kTile);
+    return std::max(1, std::min({p->R, kMaxWaves, budget}));
+}
+
+// One formal solution over every active bin: the tile stages in order.
+template <typename Real>
+rt_status run_sweep(rt_problem *p, const Real *S, hipStream_t st)
+{
+    SweepArgs<Real> A = sweep_args<Real>(p, S);
+    if (p->cold) {
+        HIP_TRY(launch_periodic_cold<Real>(A, st));
+        p->cold = false;
+    }
+    const int W = sweep_waves(p);
+    for (int s = 0; s < p->nstages; ++s) {
+        A.stage_off = p->stage_off[s];
+        A.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
+        if (A.stage_cnt == 0) continue;
+        if constexpr (sizeof(Real) == 8)
+            HIP_TRY(launch_sweep_stage_f64(A, W, st));
+        else
+            HIP_TRY(launch_sweep_stage_f32(A, W, st));
+    }
+    return RT_OK;
+}
+
+rt_status sweep_current_S(rt_problem *p, const double *S64, hipStream_t st)
+{
+    if (p->f32) return run_sweep<float>(p, p->S32, st);
+    return run_sweep<double>(p, S64, st);
+}
+
+AliCtl ctl_of(rt_problem *p)
+{
+    AliCtl c;
+    c.frozen = p->frozen;
+    c.parity = p->parity;
+    c.iters = p->iters;
+    c.resid = p->resid;
+    c.res_bits = p->res_bits;
+    c.flags = p->flags;
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rt_status_string(rt_status s)
+{
+    switch (s) {
+    case RT_OK: return "ok";
+    case RT_NOT_CONVERGED: return "not converged";
+    case RT_E_INVALID: return "invalid argument";
+    case RT_E_OOM: return "out of device memory";
+    case RT_E_HIP: return "HIP runtime error";
+    case RT_E_NONFINITE: return "non-finite residual";
+    case RT_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *rt_last_error(void) { return g_err.c_str(); }
+
+rt_status rt_quadrature(int32_t n_mu, double *mu_out, double *w_out, int32_t *na_out)
+{
+    if (n_mu != 2 && n_mu != 4 && n_mu != 6 && n_mu != 8 && n_mu != 10 && n_mu != 12)
+        return fail(RT_E_INVALID, "n_mu must be 2, 4, 6, 8, 10 or 12");
+    const int na = n_mu * (n_mu + 2);
+    if (na_out) *na_out = na;
+    if (!mu_out && !w_out) return RT_OK;
+    std::vector<double> mu, w;
+    if (!level_symmetric(n_mu, mu, w)) return fail(RT_E_INVALID, "no level-symmetric set for n_mu=%d", n_mu);
+    if ((int)w.size() != na) return fail(RT_E_INVALID, "internal: %zu rays for n_mu=%d", w.size(), n_mu);
+    if (mu_out) std::memcpy(mu_out, mu.data(), sizeof(double) * mu.size());
+    if (w_out) std::memcpy(w_out, w.data(), sizeof(double) * w.size());
+    return RT_OK;
+}
+
+rt_status rt_problem_bytes(const rt_problem_desc *desc, size_t *bytes)
+{
+    int na;
+    rt_status s = validate(desc, &na);
+    if (s != RT_OK) return s;
+    if (!bytes) return fail(RT_E_INVALID, "bytes is NULL");
+    *bytes = state_bytes(desc, na);
+    return RT_OK;
+}
+
+rt_status rt_problem_destroy(rt_problem *p)
+{
+    if (!p) return RT_OK;
+    for (void *v : p->allocs) (void)hipFree(v);
+    if (p->h_flags) (void)hipHostFree(p->h_flags);
+    delete p;
+    return RT_OK;
+}
+
+rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
+{
+    if (!out) return fail(RT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int na;
+    rt_status s = validate(desc, &na);
+    if (s != RT_OK) return s;
+
+    rt_problem *p = new rt_problem();
+    p->desc = *desc;
+    p->desc.mu = nullptr;
+    p->desc.w = nullptr;
+    p->desc.w_nu = nullptr;
+    p->n[0] = desc->nx;
+    p->n[1] = desc->ny;
+    p->n[2] = desc->nz;
+    p->nf = desc->nf;
+    p->na = na;
+    p->R = na / 8;
+    p->f32 = desc->precision == RT_F32;
+    p->cells = (int64_t)desc->nx * desc->ny * desc->nz;
+    p->plane[0] = (int64_t)desc->ny * desc->nz;
+    p->plane[1] = (int64_t)desc->nx * desc->nz;
+    p->plane[2] = (int64_t)desc->nx * desc->ny;
+    for (int q = 0; q < 3; ++q) p->periodic[q] = desc->bc_lo[q] == RT_BC_PERIODIC;
+    tile_counts(desc, p->nt);
+    p->w_nu.assign(desc->nf, 1.0);
+    if (desc->w_nu) std::copy(desc->w_nu, desc->w_nu + desc->nf, p->w_nu.begin());
+
+    // rays, grouped by octant (stable within an octant)
+    std::vector<double> mu, w;
+    if (desc->mu) {
+        mu.assign(desc->mu, desc->mu + 3 * na);
+        w.assign(desc->w, desc->w + na);
+    } else if (!level_symmetric(desc->n_mu, mu, w)) {
+        delete p;
+        return fail(RT_E_INVALID, "no level-symmetric set for n_mu=%d", desc->n_mu);
+    }
+    const double h[3] = {desc->dx, desc->dy, desc->dz};
+    for (int o = 0; o < 8; ++o)
+        for (int k = 0; k < na; ++k)
+            if (octant_of(&mu[3 * k]) == o) p->rays.push_back(ray_geometry(&mu[3 * k], h, w[k], k));
+
+    // tile schedule: tiles sorted by stage tx + ty + tz
+    p->nstages = p->nt[0] + p->nt[1] + p->nt[2] - 2;
+    std::vector<int> tiles;
+    p->stage_off.assign(p->nstages + 1, 0);
+    for (int s2 = 0; s2 < p->nstages; ++s2) {
+        p->stage_off[s2] = (int)tiles.size();
+        for (int tz = 0; tz < p->nt[2]; ++tz)
+            for (int ty = 0; ty < p->nt[1]; ++ty) {
+                const int tx = s2 - ty - tz;
+                if (tx >= 0 && tx < p->nt[0]) tiles.push_back(tx | (ty << 10) | (tz << 20));
+            }
+    }
+    p->stage_off[p->nstages] = (int)tiles.size();
+
+    const int64_t nc = p->cells * p->nf;
+    const size_t rs = real_size(desc);
+#define ALLOC(ptr, cnt)                         \
+    do {                                        \
+        rt_status a_ = dalloc(p, &(ptr), (cnt)); \
+        if (a_ != RT_OK) {                      \
+            rt_problem_destroy(p);              \
+            return a_;                          \
+        }                                       \
+    } while (0)
+    ALLOC(p->d_rays, (size_t)na);
+    ALLOC(p->d_tiles, tiles.size());
+    ALLOC(p->chi64, (size_t)nc);
+    ALLOC(p->eps, (size_t)nc);
+    ALLOC(p->B, (size_t)nc);
+    ALLOC(p->lam, (size_t)nc);
+    if (p->f32) {
+        ALLOC(p->chi32, (size_t)nc);
+        ALLOC(p->S32, (size_t)nc);
+    }
+    for (int q = 0; q < 3; ++q) {
+        unsigned char *fb;
+        ALLOC(fb, (size_t)p->nf * na * (p->nt[q] + 1) * p->plane[q] * rs);
+        p->face[q] = fb;
+    }
+    {
+        unsigned char *pb;
+        ALLOC(pb, (size_t)8 * nc * rs);
+        p->part = pb;
+    }
+    ALLOC(p->frozen, (size_t)p->nf);
+    ALLOC(p->parity, (size_t)p->nf);
+    ALLOC(p->iters, (size_t)p->nf);
+    ALLOC(p->resid, (size_t)p->nf);
+    ALLOC(p->res_bits, (size_t)p->nf);
+    ALLOC(p->flags, 4);
+#undef ALLOC
+    if (hipHostMalloc((void **)&p->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p->h_flags = nullptr;
+        rt_problem_destroy(p);
+        return fail(RT_E_OOM, "pinned host allocation failed");
+    }
+    hipError_t e = hipMemcpy(p->d_rays, p->rays.data(), sizeof(RayGeo) * na, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->frozen, 0, sizeof(int) * p->nf);
+    if (e == hipSuccess) e = hipMemset(p->parity, 0, sizeof(int) * p->nf);
+    if (e == hipSuccess) e = hipMemset(p->flags, 0, sizeof(int) * 4);
+    if (e != hipSuccess) {
+        rt_problem_destroy(p);
+        return fail(RT_E_HIP, "problem initialisation failed: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return RT_OK;
+}
+
+rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *eps, const double *B, void *stream)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    if (!chi || !eps || !B) return fail(RT_E_INVALID, "chi, eps and B are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = sizeof(double) * p->cells * p->nf;
+    HIP_TRY(hipMemcpyAsync(p->chi64, chi, bytes, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->eps, eps, bytes, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->B, B, bytes, hipMemcpyDeviceToDevice, st));
+    if (p->f32) HIP_TRY(launch_convert_f32(p->chi64, p->chi32, p->cells * p->nf, st));
+    HIP_TRY(launch_lambda_star(p->n, p->desc.bc_lo, p->desc.bc_hi, p->nf, p->na, p->d_rays, p->chi64, p->lam, st));
+    HIP_TRY(hipMemsetAsync(p->parity, 0, sizeof(int) * p->nf, st));
+    p->cold = true;
+    p->have_fields = true;
+    return RT_OK;
+}
+
+rt_status rt_problem_reset_periodic(rt_problem *p, void *stream)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    HIP_TRY(hipMemsetAsync(p->parity, 0, sizeof(int) * p->nf, static_cast<hipStream_t>(stream)));
+    p->cold = true;
+    return RT_OK;
+}
+
+rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lambda_star, void *stream)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    if (!S || !J) return fail(RT_E_INVALID, "S and J are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nc = p->cells * p->nf;
+    HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
+    if (p->f32) HIP_TRY(launch_convert_f32(S, p->S32, nc, st));
+    rt_status s = sweep_current_S(p, S, st);
+    if (s != RT_OK) return s;
+    if (p->f32)
+        HIP_TRY(launch_partial_sum<float>(static_cast<float *>(p->part), S, 1, p->nf, p->cells, nullptr, J, st));
+    else
+        HIP_TRY(launch_partial_sum<double>(static_cast<double *>(p->part), S, 0, p->nf, p->cells, nullptr, J, st));
+    HIP_TRY(launch_flip_parity(p->parity, p->frozen, p->nf, st));
+    if (lambda_star) HIP_TRY(hipMemcpyAsync(lambda_star, p->lam, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    return RT_OK;
+}
+
+rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out, rt_ali_stats *stats,
+                       void *stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !opts) return fail(RT_E_INVALID, "problem and opts are required");
+    if (!S_inout || !J_out) return fail(RT_E_INVALID, "S_inout and J_out are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    if (opts->fixed_iters < 0) return fail(RT_E_INVALID, "fixed_iters must be >= 0");
+    if (opts->fixed_iters == 0 && (opts->max_iter < 1 || !(opts->delta_c >= 0.0)))
+        return fail(RT_E_INVALID, "need max_iter >= 1 and delta_c >= 0");
+    if (opts->warm_start < 0 || opts->warm_start > 2) return fail(RT_E_INVALID, "warm_start must be 0, 1 or 2");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nc = p->cells * p->nf;
+    const size_t bytes = sizeof(double) * nc;
+
+    // start value (section 5.1: J = B start; section 4: S from the previous J)
+    if (opts->warm_start == 0)
+        HIP_TRY(hipMemcpyAsync(S_inout, p->B, bytes, hipMemcpyDeviceToDevice, st));
+    else if (opts->warm_start == 2)
+        HIP_TRY(launch_warm_start(p->B, p->eps, J_out, S_inout, nc, st));
+    if (p->f32) HIP_TRY(launch_convert_f32(S_inout, p->S32, nc, st));
+    HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
+    HIP_TRY(hipMemsetAsync(p->iters, 0, sizeof(int) * p->nf, st));
+    HIP_TRY(hipMemsetAsync(p->res_bits, 0, sizeof(unsigned long long) * p->nf, st));
+    HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int) * 4, st));
+
+    const bool fixed = opts->fixed_iters > 0;
+    const int total = fixed ? opts->fixed_iters : opts->max_iter;
+    const int every = opts->check_every > 0 ? opts->check_every : 16;
+    AliCtl ctl = ctl_of(p);
+    int done = 0;
+    bool nonfinite = false;
+    for (int it = 0; it < total && !done;) {
+        const int k = fixed ? total : std::min(every, total - it);
+        for (int j = 0; j < k; ++j) {
+            rt_status s = sweep_current_S(p, S_inout, st);
+            if (s != RT_OK) return s;
+            if (p->f32)
+                HIP_TRY(launch_ali_update<float>(static_cast<float *>(p->part), 1, p->nf, p->cells, p->B, p->eps, p->lam,
+                                                 S_inout, p->S32, J_out, ctl, st));
+            else
+                HIP_TRY(launch_ali_update<double>(static_cast<double *>(p->part), 0, p->nf, p->cells, p->B, p->eps,
+                                                  p->lam, S_inout, nullptr, J_out, ctl, st));
+            HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
+        }
+        it += k;
+        HIP_TRY(hipMemcpyAsync(p->h_flags, p->flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        done = p->h_flags[0];
+        nonfinite = p->h_flags[1] != 0;
+        if (fixed) break;
+    }
+    std::vector<int> iters(p->nf);
+    std::vector<double> resid(p->nf);
+    HIP_TRY(hipMemcpyAsync(iters.data(), p->iters, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(resid.data(), p->resid, sizeof(double) * p->nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int conv = 0, maxit = 0;
+    double maxr = 0.0;
+    for (int f = 0; f < p->nf; ++f) {
+        conv += resid[f] <= opts->delta_c;
+        maxit = std::max(maxit, iters[f]);
+        maxr = std::max(maxr, resid[f]);
+    }
+    if (stats) {
+        stats->iterations = maxit;
+        stats->bins_converged = conv;
+        stats->max_rel_dS = maxr;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (nonfinite) return fail(RT_E_NONFINITE, "non-finite residual during the Lambda iteration");
+    if (!fixed && conv < p->nf) return RT_NOT_CONVERGED;
+    return RT_OK;
+}
+
+rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (iters) HIP_TRY(hipMemcpyAsync(iters, p->iters, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
+    if (resid) HIP_TRY(hipMemcpyAsync(resid, p->resid, sizeof(double) * p->nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return RT_OK;
+}
+
+rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream)
+{
+    (void)S;
+    (void)out;
+    (void)stream;
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    return fail(RT_E_UNSUPPORTED, "rt_moments is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal declarations shared by the host runtime (rt_api.cpp) and the HIP
+// kernels (rt_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtsc {
+
+enum { BC_VACUUM = 0, BC_THERMAL = 1, BC_PERIODIC = 2, BC_FIXED = 3 };
+
+constexpr int kTile = 8;        // tile edge of the wavefront sweep
+constexpr int kMaxWaves = 10;   // waves per sweep workgroup (one ray each at a time)
+
+// Geometry of one ray's upwind short characteristic on a uniform grid
+// (section 3.3): identical for every vertex, so computed once on the host.
+struct RayGeo {
+    int d, a, b;      // axis whose face plane is crossed first going upwind; the others (a < b)
+    int oct;          // octant: bit q set when the direction is negative along axis q
+    int gidx;         // index of the ray in the caller's (or the generated) order
+    int pad;
+    double s;         // path length from the upwind face point to the vertex
+    double w4[4];     // bilinear weights at upwind offsets (0,0) (1,0) (0,1) (1,1) along (a, b)
+    double wk;        // quadrature weight
+    double mu[3];     // direction cosines
+};
+
+// Everything a sweep kernel reads about the problem; passed by value.
+template <typename Real>
+struct SweepArgs {
+    int n[3];
+    int nf, na, R;            // bins, rays, rays per octant
+    int nt[3];                // tiles per axis
+    int bc_lo[3], bc_hi[3];
+    int periodic[3];
+    int64_t cells;
+    int64_t plane[3];         // vertices in the plane normal to each axis
+    const RayGeo *rays;       // [na], octant-major
+    const Real *chi;          // [nf][cells]
+    const Real *S;            // [nf][cells]
+    const double *B;          // [nf][cells]
+    const double *fixed[6];   // FIXED faces (real coordinates), or null
+    Real *face[3];            // [nf][na][nt_q + 1][plane_q]: tile faces + 2 periodic slots
+    Real *part;               // [8][nf][cells] per-octant partial sums of w I (or w D)
+    const int *tiles;         // packed (tx | ty << 10 | tz << 20), sorted by tx + ty + tz
+    int stage_off, stage_cnt;
+    const int *frozen;        // [nf]
+    const int *parity;        // [nf]: periodic slot read this sweep
+};
+
+// Device-side control block of the Lambda iteration.
+struct AliCtl {
+    int *frozen;              // [nf]
+    int *parity;              // [nf]
+    int *iters;               // [nf]
+    double *resid;            // [nf]
+    unsigned long long *res_bits;  // [nf] running max of |dS|/S as bit patterns
+    int *flags;               // [0] all bins stopped, [1] non-finite residual
+};
+
+// Kernel launchers (rt_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, hipStream_t st);
+hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStream_t st);
+
+hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,
+                              const RayGeo *rays, const double *chi, double *lam, hipStream_t st);
+
+// Cold periodic memory: every periodic slot about to be read holds S of the wrapped vertex.
+template <typename Real>
+hipError_t launch_periodic_cold(const SweepArgs<Real> &A, hipStream_t st);
+
+template <typename Real>
+hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,
+                              const int *frozen, double *J, hipStream_t st);
+
+template <typename Real>
+hipError_t launch_ali_update(const Real *part, int dform, int nf, int64_t cells, const double *B,
+                             const double *eps, const double *lam, double *S64, float *S32, double *J,
+                             AliCtl ctl, hipStream_t st);
+
+hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,
+                               hipStream_t st);
+hipError_t launch_flip_parity(int *parity, const int *frozen, int nf, hipStream_t st);
+hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_warm_start(const double *B, const double *eps, const double *J, double *S, int64_t n,
+                             hipStream_t st);
+
+}  // namespace rtsc

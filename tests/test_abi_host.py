@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI that need no GPU: exported symbols, the library's
+angle set against the oracle's independently generated one, argument validation and
+state-size accounting."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rt.h")
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import paper_1201_2222_amd as rt
+    if not os.path.exists(rt.LIB_PATH):
+        from paper_1201_2222_amd import build
+        build.build()
+    rt.load()
+    return rt
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(rt):
+    names = _declared_functions()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", rt.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(rt.EXPORTS) == set(names)
+    lib = rt.load()
+    for n in names:
+        assert getattr(lib, n) is not None
+
+
+@pytest.mark.parametrize("n_mu", [2, 4, 6, 8, 10, 12])
+def test_library_angle_set_matches_oracle(rt, oracle_mod, n_mu):
+    """Two independent implementations of the level-symmetric set (section 3.2)."""
+    mu_l, w_l = rt.rt_quadrature(n_mu)
+    mu_o, w_o = oracle_mod.quadrature(n_mu)
+    assert mu_l.shape == mu_o.shape
+    # the oracle solves for mu_1 in FP64, the library in long double; the last moment
+    # condition is flat in mu_1 near its root, so the two agree to ~1e-14 while each
+    # meets every condition to 1e-16
+    assert np.max(np.abs(mu_l - mu_o)) < 5e-14
+    assert np.max(np.abs(w_l - w_o)) < 1e-14
+    for p in range(n_mu // 2 + 1):
+        assert abs(np.sum(w_l * mu_l[:, 0] ** (2 * p)) - 1.0 / (2 * p + 1)) < 5e-16
+
+
+def test_invalid_arguments_are_rejected(rt):
+    lib = rt.load()
+    b = ctypes.c_size_t()
+    cases = [
+        dict(shape=(0, 4, 4)),
+        dict(shape=(4, 4, 4), nf=0),
+        dict(shape=(4, 4, 4), h=(1.0, -1.0, 1.0)),
+        dict(shape=(4, 4, 4), n_mu=5),
+        dict(shape=(4, 4, 4), bc_lo=(2, 2, 1), bc_hi=(0, 2, 0)),        # periodic on one face only
+        dict(shape=(4, 4, 4), bc_lo=(2, 2, 3), bc_hi=(2, 2, 0)),        # FIXED without data
+        dict(shape=(4, 4, 4), precision=7),
+        dict(shape=(4, 4, 4), bc_lo=(9, 2, 1), bc_hi=(9, 2, 0)),
+    ]
+    for kw in cases:
+        d = rt.make_desc(**kw)
+        st = lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b))
+        assert st == rt.RT_E_INVALID, kw
+        assert len(lib.rt_last_error()) > 0
+    # a ray table whose octants are unequal
+    mu, w = rt.rt_quadrature(4)
+    mu2 = mu.copy()
+    mu2[0] = -mu2[0]
+    d = rt.make_desc((4, 4, 4), mu=mu2, w=w)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID
+    # ... and a valid explicit table
+    d = rt.make_desc((4, 4, 4), mu=mu, w=w)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_OK
+    assert lib.rt_quadrature(3, None, None, None) == rt.RT_E_INVALID
+    assert rt.load().rt_status_string(rt.RT_E_NONFINITE) == b"non-finite residual"
+
+
+def test_state_bytes_scale(rt):
+    small = rt.rt_problem_bytes(rt.make_desc((16, 16, 16)))
+    big = rt.rt_problem_bytes(rt.make_desc((32, 32, 32)))
+    f32 = rt.rt_problem_bytes(rt.make_desc((32, 32, 32), precision=rt.RT_F32))
+    assert 7 * small < big < 9 * small
+    assert f32 < big
