@@ -183,6 +183,25 @@ typedef struct {
  */
 rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream);
 
+/*
+ * Sweep-kernel timing, for measuring the formal solution against its roofline.
+ * While enabled, every sweep stage launch of one formal solution (the first
+ * iteration of each convergence-check interval of rt_ali_solve, and every
+ * rt_formal_solve) is bracketed by HIP events on the call's stream; the durations
+ * are summed when the events have completed.  Enabling (or disabling) resets the
+ * totals.  Timing adds two event records per stage launch to the timed sweeps.
+ */
+typedef struct {
+    double kernel_ms;     /* summed duration of the timed sweep-stage launches */
+    int64_t launches;     /* number of timed launches */
+    int64_t sweeps;       /* number of timed formal solutions */
+    double updates;       /* cell*ray*bin updates done by those launches */
+    int32_t stages;       /* launches per formal solution */
+} rt_profile;
+
+rt_status rt_problem_profile(rt_problem *p, int32_t enable);
+rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ RT_BC_VACUUM, RT_BC_THERMAL, RT_BC_PERIODIC, RT_BC_FIXED = 0, 1, 2, 3
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
-           "rt_ali_solve", "rt_ali_bin_stats", "rt_moments")
+           "rt_ali_solve", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read")
 
 
 class RtError(RuntimeError):
@@ -59,6 +59,11 @@ class MomentsOut(ctypes.Structure):
                 ("f_int", ctypes.c_void_p), ("Q_int", ctypes.c_void_p), ("heating", ctypes.c_void_p)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("launches", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("updates", ctypes.c_double), ("stages", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -85,6 +90,8 @@ def load():
     lib.rt_ali_solve.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_ali_bin_stats.argtypes = [P, P, P, P]
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
+    lib.rt_problem_profile.argtypes = [P, I32]
+    lib.rt_problem_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     _lib = lib
@@ -229,6 +236,17 @@ def rt_moments(p, S, J=None, H=None, K=None, J_int=None, H_int=None, K_int=None,
                      ctypes.addressof(heat) if want_heating else None)
     _check(load().rt_moments(p, _dptr(S, name="S"), ctypes.byref(out), _stream(stream)))
     return heat.value if want_heating else None
+
+
+def rt_problem_profile(p, enable=True):
+    return _check(load().rt_problem_profile(p, 1 if enable else 0))
+
+
+def rt_problem_profile_read(p):
+    out = Profile()
+    _check(load().rt_problem_profile_read(p, ctypes.byref(out)))
+    return {"kernel_ms": out.kernel_ms, "launches": out.launches, "sweeps": out.sweeps, "updates": out.updates,
+            "stages": out.stages}
 
 
 class Problem:

@@ -245,14 +245,23 @@ struct rt_problem {
     RayGeo *d_rays = nullptr;
     int *d_tiles = nullptr;
     double *chi64 = nullptr, *eps = nullptr, *B = nullptr, *lam = nullptr;
-    float *chi32 = nullptr, *S32 = nullptr;
-    void *face[3]{};                   // Real
+    float *chi32 = nullptr;
+    void *face[3]{};                   // Real [nf][na][nt_q - 1][plane_q]
+    double *wrap[3]{};                 // [nf][na][2][plane_q] on periodic axes
     void *part = nullptr;              // Real [8][nf][cells]
     int *frozen = nullptr, *parity = nullptr, *iters = nullptr, *flags = nullptr;
     double *resid = nullptr;
-    unsigned long long *res_bits = nullptr;
+    unsigned long long *blockmax = nullptr;  // [nf][kUpdateBlocks]
+    int waves = 1;                     // waves per sweep workgroup
     int *h_flags = nullptr;            // pinned host copy of flags
+    int *h_frozen = nullptr;           // pinned host copy of frozen
     std::vector<void *> allocs;
+    // sweep-kernel timing (rt_problem_profile)
+    bool prof = false;
+    bool prof_pending = false;
+    std::vector<hipEvent_t> ev;        // start/stop per stage
+    double prof_ms = 0.0, prof_updates = 0.0, prof_pending_updates = 0.0;
+    int64_t prof_launches = 0, prof_sweeps = 0;
 };
 
 namespace {
@@ -322,11 +331,16 @@ size_t state_bytes(const rt_problem_desc *d, int na)
     int nt[3];
     tile_counts(d, nt);
     const int64_t plane[3] = {(int64_t)d->ny * d->nz, (int64_t)d->nx * d->nz, (int64_t)d->nx * d->ny};
+    const int bc_per[3] = {d->bc_lo[0] == RT_BC_PERIODIC, d->bc_lo[1] == RT_BC_PERIODIC, d->bc_lo[2] == RT_BC_PERIODIC};
     size_t b = 0;
     b += (size_t)nc * 8 * 4;                       // chi64, eps, B, lam
-    if (d->precision == RT_F32) b += (size_t)nc * 4 * 2;  // chi32, S32
-    for (int q = 0; q < 3; ++q) b += (size_t)d->nf * na * (nt[q] + 1) * plane[q] * rs;
+    if (d->precision == RT_F32) b += (size_t)nc * 4;  // chi32
+    for (int q = 0; q < 3; ++q) {
+        b += (size_t)d->nf * na * (nt[q] - 1) * plane[q] * rs;          // interior tile faces
+        if (bc_per[q]) b += (size_t)d->nf * na * 2 * plane[q] * 8;      // periodic memory
+    }
     b += (size_t)8 * nc * rs;                      // partials
+    b += (size_t)d->nf * kUpdateBlocks * 8;        // residual block maxima
     b += (size_t)na * sizeof(RayGeo) + (size_t)nt[0] * nt[1] * nt[2] * 4 + (size_t)d->nf * 32 + 64;
     return b;
 }
@@ -346,7 +360,7 @@ rt_status dalloc(rt_problem *p, T **ptr, size_t count)
 }
 
 template <typename Real>
-SweepArgs<Real> sweep_args(rt_problem *p, const Real *S)
+SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
 {
     SweepArgs<Real> A{};
     for (int q = 0; q < 3; ++q) {
@@ -357,6 +371,7 @@ SweepArgs<Real> sweep_args(rt_problem *p, const Real *S)
         A.periodic[q] = p->periodic[q];
         A.plane[q] = p->plane[q];
         A.face[q] = static_cast<Real *>(p->face[q]);
+        A.wrap[q] = p->wrap[q];
     }
     A.nf = p->nf;
     A.na = p->na;
@@ -375,42 +390,67 @@ SweepArgs<Real> sweep_args(rt_problem *p, const Real *S)
 }
 
 // Waves per sweep workgroup: one per ray of the octant, capped so the dynamic LDS
-// (chi and S tiles, two plane buffers and a partial-sum tile per wave) stays within
-// 64 KiB.
-int sweep_waves(const rt_problem *p)
+// (chi and S tiles; plane buffers, halo lines and a partial-sum tile per wave) fits
+// the device's per-workgroup limit.
+int sweep_waves(int R, bool f32, size_t lds_limit)
 {
-    const int real = p->f32 ? 4 : 8;
-    const int tp = kTile + 1;
-    const int budget = (65536 / real - 2 * tp * tp * tp) / (2 * tp * tp + kTile * kTile * kTile);
-    return std::max(1, std::min({p->R, kMaxWaves, budget}));
+    int w = std::min(R, kMaxWaves);
+    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w) > lds_limit) --w;
+    return w;
 }
 
 // One formal solution over every active bin: the tile stages in order.
+// Accumulate the durations of timed sweep stages once their events have completed.
+rt_status collect_timing(rt_problem *p)
+{
+    if (!p->prof_pending) return RT_OK;
+    for (int s = 0; s < p->nstages; ++s) {
+        HIP_TRY(hipEventSynchronize(p->ev[2 * s + 1]));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * s], p->ev[2 * s + 1]));
+        p->prof_ms += ms;
+        ++p->prof_launches;
+    }
+    p->prof_updates += p->prof_pending_updates;
+    ++p->prof_sweeps;
+    p->prof_pending = false;
+    return RT_OK;
+}
+
+// One formal solution over every active bin: the tile stages in order.  With
+// timed set, each stage launch is bracketed by events (active_bins then counts the
+// bins that do work, for the update tally).
 template <typename Real>
-rt_status run_sweep(rt_problem *p, const Real *S, hipStream_t st)
+rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed = false, int active_bins = 0)
 {
     SweepArgs<Real> A = sweep_args<Real>(p, S);
     if (p->cold) {
         HIP_TRY(launch_periodic_cold<Real>(A, st));
         p->cold = false;
     }
-    const int W = sweep_waves(p);
+    timed = timed && p->prof && !p->prof_pending;
+    const int W = p->waves;
     for (int s = 0; s < p->nstages; ++s) {
         A.stage_off = p->stage_off[s];
         A.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
-        if (A.stage_cnt == 0) continue;
+        if (timed) HIP_TRY(hipEventRecord(p->ev[2 * s], st));
         if constexpr (sizeof(Real) == 8)
             HIP_TRY(launch_sweep_stage_f64(A, W, st));
         else
             HIP_TRY(launch_sweep_stage_f32(A, W, st));
+        if (timed) HIP_TRY(hipEventRecord(p->ev[2 * s + 1], st));
+    }
+    if (timed) {
+        p->prof_pending = true;
+        p->prof_pending_updates = (double)p->cells * p->na * active_bins;
     }
     return RT_OK;
 }
 
-rt_status sweep_current_S(rt_problem *p, const double *S64, hipStream_t st)
+rt_status sweep_current_S(rt_problem *p, const double *S64, hipStream_t st, bool timed = false, int active = 0)
 {
-    if (p->f32) return run_sweep<float>(p, p->S32, st);
-    return run_sweep<double>(p, S64, st);
+    if (p->f32) return run_sweep<float>(p, S64, st, timed, active);
+    return run_sweep<double>(p, S64, st, timed, active);
 }
 
 AliCtl ctl_of(rt_problem *p)
@@ -420,7 +460,8 @@ AliCtl ctl_of(rt_problem *p)
     c.parity = p->parity;
     c.iters = p->iters;
     c.resid = p->resid;
-    c.res_bits = p->res_bits;
+    c.blockmax = p->blockmax;
+    c.nblk = kUpdateBlocks;
     c.flags = p->flags;
     return c;
 }
@@ -475,6 +516,8 @@ rt_status rt_problem_destroy(rt_problem *p)
     if (!p) return RT_OK;
     for (void *v : p->allocs) (void)hipFree(v);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
+    if (p->h_frozen) (void)hipHostFree(p->h_frozen);
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     delete p;
     return RT_OK;
 }
@@ -552,14 +595,12 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     ALLOC(p->eps, (size_t)nc);
     ALLOC(p->B, (size_t)nc);
     ALLOC(p->lam, (size_t)nc);
-    if (p->f32) {
-        ALLOC(p->chi32, (size_t)nc);
-        ALLOC(p->S32, (size_t)nc);
-    }
+    if (p->f32) ALLOC(p->chi32, (size_t)nc);
     for (int q = 0; q < 3; ++q) {
         unsigned char *fb;
-        ALLOC(fb, (size_t)p->nf * na * (p->nt[q] + 1) * p->plane[q] * rs);
+        ALLOC(fb, (size_t)p->nf * na * (p->nt[q] - 1) * p->plane[q] * rs);
         p->face[q] = fb;
+        if (p->periodic[q]) ALLOC(p->wrap[q], (size_t)p->nf * na * 2 * p->plane[q]);
     }
     {
         unsigned char *pb;
@@ -570,14 +611,25 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     ALLOC(p->parity, (size_t)p->nf);
     ALLOC(p->iters, (size_t)p->nf);
     ALLOC(p->resid, (size_t)p->nf);
-    ALLOC(p->res_bits, (size_t)p->nf);
+    ALLOC(p->blockmax, (size_t)p->nf * kUpdateBlocks);
     ALLOC(p->flags, 4);
 #undef ALLOC
-    if (hipHostMalloc((void **)&p->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&p->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&p->h_frozen, sizeof(int) * p->nf, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         p->h_flags = nullptr;
         rt_problem_destroy(p);
         return fail(RT_E_OOM, "pinned host allocation failed");
+    }
+    int dev = 0, lds_limit = 65536;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipGetLastError();
+    p->waves = sweep_waves(p->R, p->f32, (size_t)lds_limit);
+    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves) > (size_t)lds_limit) {
+        rt_problem_destroy(p);
+        return fail(RT_E_UNSUPPORTED, "sweep needs %zu bytes of LDS, device allows %d",
+                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves), lds_limit);
     }
     hipError_t e = hipMemcpy(p->d_rays, p->rays.data(), sizeof(RayGeo) * na, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice);
@@ -625,8 +677,9 @@ rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lam
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nc = p->cells * p->nf;
     HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
-    if (p->f32) HIP_TRY(launch_convert_f32(S, p->S32, nc, st));
-    rt_status s = sweep_current_S(p, S, st);
+    rt_status s = collect_timing(p);
+    if (s != RT_OK) return s;
+    s = sweep_current_S(p, S, st, true, p->nf);
     if (s != RT_OK) return s;
     if (p->f32)
         HIP_TRY(launch_partial_sum<float>(static_cast<float *>(p->part), S, 1, p->nf, p->cells, nullptr, J, st));
@@ -657,10 +710,8 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
         HIP_TRY(hipMemcpyAsync(S_inout, p->B, bytes, hipMemcpyDeviceToDevice, st));
     else if (opts->warm_start == 2)
         HIP_TRY(launch_warm_start(p->B, p->eps, J_out, S_inout, nc, st));
-    if (p->f32) HIP_TRY(launch_convert_f32(S_inout, p->S32, nc, st));
     HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
     HIP_TRY(hipMemsetAsync(p->iters, 0, sizeof(int) * p->nf, st));
-    HIP_TRY(hipMemsetAsync(p->res_bits, 0, sizeof(unsigned long long) * p->nf, st));
     HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int) * 4, st));
 
     const bool fixed = opts->fixed_iters > 0;
@@ -669,24 +720,38 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
     AliCtl ctl = ctl_of(p);
     int done = 0;
     bool nonfinite = false;
+    int active = p->nf;
+    {
+        rt_status s = collect_timing(p);
+        if (s != RT_OK) return s;
+    }
     for (int it = 0; it < total && !done;) {
         const int k = fixed ? total : std::min(every, total - it);
         for (int j = 0; j < k; ++j) {
-            rt_status s = sweep_current_S(p, S_inout, st);
+            rt_status s = sweep_current_S(p, S_inout, st, j == 0, active);
             if (s != RT_OK) return s;
             if (p->f32)
                 HIP_TRY(launch_ali_update<float>(static_cast<float *>(p->part), 1, p->nf, p->cells, p->B, p->eps, p->lam,
-                                                 S_inout, p->S32, J_out, ctl, st));
+                                                 S_inout, J_out, ctl, st));
             else
                 HIP_TRY(launch_ali_update<double>(static_cast<double *>(p->part), 0, p->nf, p->cells, p->B, p->eps,
-                                                  p->lam, S_inout, nullptr, J_out, ctl, st));
+                                                  p->lam, S_inout, J_out, ctl, st));
             HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
         }
         it += k;
         HIP_TRY(hipMemcpyAsync(p->h_flags, p->flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+        if (p->prof) HIP_TRY(hipMemcpyAsync(p->h_frozen, p->frozen, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         done = p->h_flags[0];
         nonfinite = p->h_flags[1] != 0;
+        {
+            rt_status s = collect_timing(p);
+            if (s != RT_OK) return s;
+        }
+        if (p->prof) {
+            active = 0;
+            for (int f = 0; f < p->nf; ++f) active += p->h_frozen[f] == 0;
+        }
         if (fixed) break;
     }
     std::vector<int> iters(p->nf);
@@ -719,6 +784,34 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
     if (iters) HIP_TRY(hipMemcpyAsync(iters, p->iters, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
     if (resid) HIP_TRY(hipMemcpyAsync(resid, p->resid, sizeof(double) * p->nf, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return RT_OK;
+}
+
+rt_status rt_problem_profile(rt_problem *p, int32_t enable)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    rt_status s = collect_timing(p);
+    if (s != RT_OK) return s;
+    if (enable && p->ev.empty()) {
+        p->ev.resize(2 * (size_t)p->nstages);
+        for (auto &e : p->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    p->prof = enable != 0;
+    p->prof_ms = p->prof_updates = 0.0;
+    p->prof_launches = p->prof_sweeps = 0;
+    return RT_OK;
+}
+
+rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out)
+{
+    if (!p || !out) return fail(RT_E_INVALID, "problem and out are required");
+    rt_status s = collect_timing(p);
+    if (s != RT_OK) return s;
+    out->kernel_ms = p->prof_ms;
+    out->launches = p->prof_launches;
+    out->sweeps = p->prof_sweeps;
+    out->updates = p->prof_updates;
+    out->stages = p->nstages;
     return RT_OK;
 }
 

@@ -36,10 +36,12 @@ struct SweepArgs {
     int64_t plane[3];         // vertices in the plane normal to each axis
     const RayGeo *rays;       // [na], octant-major
     const Real *chi;          // [nf][cells]
-    const Real *S;            // [nf][cells]
+    const double *S;          // [nf][cells] source function (always FP64)
     const double *B;          // [nf][cells]
     const double *fixed[6];   // FIXED faces (real coordinates), or null
-    Real *face[3];            // [nf][na][nt_q + 1][plane_q]: tile faces + 2 periodic slots
+    Real *face[3];            // [nf][na][nt_q - 1][plane_q]: downwind faces of interior tiles
+                              // (I in the plain form, D = I - S in the difference form)
+    double *wrap[3];          // [nf][na][2][plane_q]: periodic memory (I), slot = parity
     Real *part;               // [8][nf][cells] per-octant partial sums of w I (or w D)
     const int *tiles;         // packed (tx | ty << 10 | tz << 20), sorted by tx + ty + tz
     int stage_off, stage_cnt;
@@ -53,13 +55,18 @@ struct AliCtl {
     int *parity;              // [nf]
     int *iters;               // [nf]
     double *resid;            // [nf]
-    unsigned long long *res_bits;  // [nf] running max of |dS|/S as bit patterns
+    unsigned long long *blockmax;  // [nf][nblk] per-block max of |dS|/S as bit patterns
+    int nblk;                 // update blocks per bin
     int *flags;               // [0] all bins stopped, [1] non-finite residual
 };
+
+constexpr int kUpdateBlocks = 1024;  // update-kernel blocks per bin (grid-stride)
 
 // Kernel launchers (rt_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, hipStream_t st);
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStream_t st);
+// dynamic LDS bytes of one sweep workgroup with the given number of waves
+size_t sweep_lds_bytes(int real_bytes, int waves);
 
 hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,
                               const RayGeo *rays, const double *chi, double *lam, hipStream_t st);
@@ -74,7 +81,7 @@ hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int 
 
 template <typename Real>
 hipError_t launch_ali_update(const Real *part, int dform, int nf, int64_t cells, const double *B,
-                             const double *eps, const double *lam, double *S64, float *S32, double *J,
+                             const double *eps, const double *lam, double *S64, double *J,
                              AliCtl ctl, hipStream_t st);
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,

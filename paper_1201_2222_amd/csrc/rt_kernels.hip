@@ -8,10 +8,12 @@
 // the same tx + ty + tz (one "stage") are independent and run in one launch.
 // Inside a tile each wave takes one ray at a time and sweeps plane by plane along
 // the axis that ray crosses first: all upwind vertices of a plane lie in the
-// previous plane, so the 64 lanes of the wave update a whole T x T plane at once.
+// previous plane, so the lanes of the wave update a whole T x T plane at once.
 // chi and S of the tile plus its upwind halo are staged in LDS once and shared by
-// all rays of the octant; the previous plane of I lives in a small per-wave LDS
-// buffer; neighbour tiles exchange their downwind faces through global memory.
+// all rays of the octant; before its plane loop a wave loads every upwind-halo
+// intensity the ray will need (the neighbour tiles' downwind faces, periodic
+// memory or boundary values) into LDS in one batch, so the plane loop itself
+// touches only LDS.
 #include <hip/hip_runtime.h>
 
 #include "rt_internal.h"
@@ -24,6 +26,8 @@ constexpr int T = kTile;
 constexpr int TP = T + 1;            // tile plus one upwind halo layer
 constexpr int TILE_LDS = TP * TP * TP;
 constexpr int PLANE_LDS = TP * TP;
+constexpr int HALO_LINE = 2 * T + 1; // halo of one plane: T+1 values on the a-line, T on the b-line
+constexpr int WAVE_LDS = 2 * PLANE_LDS + T * HALO_LINE + T * T * T;  // Reals per wave
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -35,13 +39,9 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int64_t plane_index(int q, const int v[3], const int n[3])
-{
-    // plane normal to axis q: the other two axes in increasing order, lower one fastest
-    const int p1 = (q == 0) ? 1 : 0;
-    const int p2 = (q == 2) ? 1 : 2;
-    return (int64_t)v[p2] * n[p1] + v[p1];
-}
+// value of a per-axis quantity for a wave-uniform axis index
+template <typename V>
+__device__ __forceinline__ V sel3(int q, V x, V y, V z) { return q == 0 ? x : (q == 1 ? y : z); }
 
 __device__ __forceinline__ int to_real(int g, int sg, int n) { return sg > 0 ? g : n - 1 - g; }
 
@@ -63,12 +63,11 @@ __device__ __forceinline__ void seg_coeffs(double dt, double &E, double &psim, d
     double p0;
     if (dt < 0.1) {
         // psi0 = dt/2! - dt^2/3! + dt^3/4! - ... (13 terms)
-        double acc;
         const double c[13] = {1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0,
                               1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,
                               1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0,
                               1.0 / 87178291200.0};
-        acc = c[12];
+        double acc = c[12];
 #pragma unroll
         for (int i = 11; i >= 0; --i) acc = c[i] - dt * acc;
         p0 = dt * acc;
@@ -82,7 +81,7 @@ __device__ __forceinline__ void seg_coeffs(double dt, double &E, double &psim, d
 
 // FP32, difference form  D0 = D- E + (S- - S0) g  with g = (1 - e^-dt)/dt = 1 - psi0,
 // which is the plain form rewritten with D = I - S (E + psim + psi0 = 1).  g comes
-// from its Taylor series sum_n (-dt)^n/(n+1)! below dt = 0.5 (9 terms).
+// from its Taylor series sum_n (-dt)^n/(n+1)! below dt = 0.5 (10 terms).
 __device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
 {
     E = __expf(-dt);
@@ -102,243 +101,245 @@ __device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
     }
 }
 
-template <typename Real, bool DFORM>
-struct Tile {
-    const SweepArgs<Real> &A;
-    int oct, f, par;
-    int sg[3], t[3], g0[3], ext[3];
-    const Real *SL;
-    int64_t fbase;  // f * cells
-
-    __device__ Tile(const SweepArgs<Real> &A_) : A(A_) {}
-
-    __device__ __forceinline__ int lds_index(const int gv[3]) const
-    {
-        return ((gv[2] - g0[2] + 1) * TP + (gv[1] - g0[1] + 1)) * TP + (gv[0] - g0[0] + 1);
-    }
-
-    __device__ __forceinline__ int64_t face_offset(int q, int ray, int slot) const
-    {
-        return (((int64_t)f * A.na + ray) * (A.nt[q] + 1) + slot) * A.plane[q];
-    }
-
-    // Value (I, or D = I - S) at a halo vertex gv (flipped coordinates) just upwind
-    // of this tile, for the given ray.
-    __device__ Real halo(const int gv[3], int ray, int gidx) const
-    {
-        bool out[3];
-        bool any = false;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            out[q] = gv[q] < 0;
-            any |= out[q];
-        }
-        if (!any) {
-            // a vertex of an upwind neighbour tile: read that tile's downwind face
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if (gv[q] == g0[q] - 1)
-                    return A.face[q][face_offset(q, ray, t[q] - 1) + plane_index(q, gv, A.n)];
-            return Real(0);
-        }
-        const Real Sg = SL[lds_index(gv)];
-        // a ghost outside a non-periodic face: that face's boundary condition,
-        // the highest axis first
-#pragma unroll
-        for (int q = 2; q >= 0; --q) {
-            if (!out[q] || A.periodic[q]) continue;
-            const int kind = (sg[q] > 0) ? A.bc_lo[q] : A.bc_hi[q];
-            double I = 0.0;
-            if (kind == BC_THERMAL || kind == BC_FIXED) {
-                int u[3];
-#pragma unroll
-                for (int p = 0; p < 3; ++p)
-                    u[p] = fold(to_real(gv[p], sg[p], A.n[p]), A.n[p], A.periodic[p]);
-                if (kind == BC_THERMAL) {
-                    I = A.B[fbase + ((int64_t)u[2] * A.n[1] + u[1]) * A.n[0] + u[0]];
-                } else {
-                    const double *F = A.fixed[2 * q + (sg[q] > 0 ? 0 : 1)];
-                    I = F[((int64_t)f * A.na + gidx) * A.plane[q] + plane_index(q, u, A.n)];
-                }
-            }
-            return DFORM ? Real(I) - Sg : Real(I);
-        }
-        // only periodic axes are outside: the previous sweep's intensity at the
-        // wrapped vertex, kept on the ray's outgoing plane
-        int w[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) w[q] = out[q] ? A.n[q] - 1 : gv[q];
-        int q = out[0] ? 0 : (out[1] ? 1 : 2);
-        const Real I = A.face[q][face_offset(q, ray, A.nt[q] - 1 + par) + plane_index(q, w, A.n)];
-        return DFORM ? I - Sg : I;
-    }
+// Per-workgroup tile description, all scalars (no arrays indexed by a runtime axis).
+struct TileCtx {
+    int f, par;
+    int sgx, sgy, sgz;
+    int tx, ty, tz;
+    int g0x, g0y, g0z;
+    int ex, ey, ez;
+    int64_t fbase;   // f * cells
 };
 
-// dynamic LDS of one sweep workgroup with W waves: chi and S tiles, two plane
-// buffers per wave, one partial-sum tile per wave
-template <typename Real>
-constexpr size_t sweep_lds_bytes(int W)
+__device__ __forceinline__ int lds_cell(const TileCtx &c, int vx, int vy, int vz)
 {
-    return sizeof(Real) * (2 * (size_t)TILE_LDS + (size_t)W * (2 * PLANE_LDS + T * T * T));
+    return ((vz - c.g0z + 1) * TP + (vy - c.g0y + 1)) * TP + (vx - c.g0x + 1);
+}
+
+// Value (I, or D = I - S in the difference form) at a vertex (vx, vy, vz) in
+// flipped coordinates just upwind of the tile, for one ray.
+template <typename Real, bool DFORM>
+__device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, const double *SL, int vx, int vy, int vz,
+                           int ray, int gidx)
+{
+    const bool ox = vx < 0, oy = vy < 0, oz = vz < 0;
+    const int64_t rb = (int64_t)c.f * A.na + ray;
+    if (!(ox || oy || oz)) {
+        // a vertex of an upwind neighbour tile: that tile's downwind face
+        if (vx == c.g0x - 1)
+            return A.face[0][(rb * (A.nt[0] - 1) + (c.tx - 1)) * A.plane[0] + (int64_t)vz * A.n[1] + vy];
+        if (vy == c.g0y - 1)
+            return A.face[1][(rb * (A.nt[1] - 1) + (c.ty - 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx];
+        return A.face[2][(rb * (A.nt[2] - 1) + (c.tz - 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx];
+    }
+    // ghost vertex outside the grid; the staged S is that of the folded vertex
+    const double Sg = SL[lds_cell(c, vx, vy, vz)];
+    const int rx = fold(to_real(vx, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
+    const int ry = fold(to_real(vy, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
+    const int rz = fold(to_real(vz, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
+    // outside a non-periodic face: that face's condition, z before y before x
+    int q = -1;
+    if (oz && !A.periodic[2]) q = 2;
+    else if (oy && !A.periodic[1]) q = 1;
+    else if (ox && !A.periodic[0]) q = 0;
+    if (q >= 0) {
+        const int lo = sel3(q, c.sgx, c.sgy, c.sgz) > 0;
+        const int kind = lo ? sel3(q, A.bc_lo[0], A.bc_lo[1], A.bc_lo[2]) : sel3(q, A.bc_hi[0], A.bc_hi[1], A.bc_hi[2]);
+        double I = 0.0;
+        if (kind == BC_THERMAL) {
+            I = A.B[c.fbase + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx];
+        } else if (kind == BC_FIXED) {
+            const double *F = (q == 0) ? (lo ? A.fixed[0] : A.fixed[1])
+                                       : (q == 1 ? (lo ? A.fixed[2] : A.fixed[3]) : (lo ? A.fixed[4] : A.fixed[5]));
+            const int64_t pidx = (q == 0) ? (int64_t)rz * A.n[1] + ry
+                                          : (q == 1 ? (int64_t)rz * A.n[0] + rx : (int64_t)ry * A.n[0] + rx);
+            const int64_t P = sel3(q, A.plane[0], A.plane[1], A.plane[2]);
+            I = F[((int64_t)c.f * A.na + gidx) * P + pidx];
+        }
+        return DFORM ? Real(I - Sg) : Real(I);
+    }
+    // only periodic axes are outside: the previous sweep's intensity at the
+    // wrapped vertex, kept on the ray's outgoing plane
+    const int wx = ox ? A.n[0] - 1 : vx, wy = oy ? A.n[1] - 1 : vy, wz = oz ? A.n[2] - 1 : vz;
+    double I;
+    if (ox)
+        I = A.wrap[0][(rb * 2 + c.par) * A.plane[0] + (int64_t)wz * A.n[1] + wy];
+    else if (oy)
+        I = A.wrap[1][(rb * 2 + c.par) * A.plane[1] + (int64_t)wz * A.n[0] + wx];
+    else
+        I = A.wrap[2][(rb * 2 + c.par) * A.plane[2] + (int64_t)wy * A.n[0] + wx];
+    return DFORM ? Real(I - Sg) : Real(I);
 }
 
 template <typename Real, bool DFORM>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    Real *chiL = reinterpret_cast<Real *>(lds_raw);
-    Real *SLs = chiL + TILE_LDS;
-    Real *PlBase = SLs + TILE_LDS;
-    const int Wn = blockDim.x >> 6;
-    Real *JwBase = PlBase + (size_t)Wn * 2 * PLANE_LDS;
+    double *SL = reinterpret_cast<double *>(lds_raw);
+    Real *chiL = reinterpret_cast<Real *>(SL + TILE_LDS);
+    Real *waveL = chiL + TILE_LDS;
 
     const int oct = blockIdx.x & 7;
     const int item = blockIdx.x >> 3;
     const int f = blockIdx.y;
-    if (A.frozen[f]) return;
-
-    Tile<Real, DFORM> tl(A);
-    tl.oct = oct;
-    tl.f = f;
-    tl.par = A.parity[f];
-    tl.fbase = (int64_t)f * A.cells;
-    tl.SL = SLs;
+    const int frozen = A.frozen[f];
+    const int par = A.parity[f];
     const int packed = A.tiles[A.stage_off + item];
-    tl.t[0] = packed & 1023;
-    tl.t[1] = (packed >> 10) & 1023;
-    tl.t[2] = (packed >> 20) & 1023;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        tl.sg[q] = (oct >> q) & 1 ? -1 : 1;
-        tl.g0[q] = tl.t[q] * T;
-        tl.ext[q] = min(T, A.n[q] - tl.g0[q]);
-    }
+    if (frozen) return;
+
+    TileCtx c;
+    c.f = f;
+    c.par = par;
+    c.fbase = (int64_t)f * A.cells;
+    c.sgx = (oct & 1) ? -1 : 1;
+    c.sgy = (oct & 2) ? -1 : 1;
+    c.sgz = (oct & 4) ? -1 : 1;
+    c.tx = packed & 1023;
+    c.ty = (packed >> 10) & 1023;
+    c.tz = (packed >> 20) & 1023;
+    c.g0x = c.tx * T;
+    c.g0y = c.ty * T;
+    c.g0z = c.tz * T;
+    c.ex = min(T, A.n[0] - c.g0x);
+    c.ey = min(T, A.n[1] - c.g0y);
+    c.ez = min(T, A.n[2] - c.g0z);
 
     // ---- stage chi and S of the tile and its upwind halo in LDS --------------------
-    const Real *chif = A.chi + tl.fbase;
-    const Real *Sf = A.S + tl.fbase;
+    const Real *chif = A.chi + c.fbase;
+    const double *Sf = A.S + c.fbase;
     for (int idx = threadIdx.x; idx < TILE_LDS; idx += blockDim.x) {
-        const int l[3] = {idx % TP, (idx / TP) % TP, idx / (TP * TP)};
-        int u[3];
-        bool skip = false;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int g = tl.g0[q] + l[q] - 1;
-            skip |= (l[q] > tl.ext[q]);
-            u[q] = fold(to_real(g, tl.sg[q], A.n[q]), A.n[q], A.periodic[q]);
-        }
-        if (skip) continue;
-        const int64_t c = ((int64_t)u[2] * A.n[1] + u[1]) * A.n[0] + u[0];
-        chiL[idx] = chif[c];
-        SLs[idx] = Sf[c];
+        const int lx = idx % TP, ly = (idx / TP) % TP, lz = idx / (TP * TP);
+        if (lx > c.ex || ly > c.ey || lz > c.ez) continue;
+        const int rx = fold(to_real(c.g0x + lx - 1, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
+        const int ry = fold(to_real(c.g0y + ly - 1, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
+        const int rz = fold(to_real(c.g0z + lz - 1, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
+        const int64_t cell = ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
+        chiL[idx] = chif[cell];
+        SL[idx] = Sf[cell];
     }
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int W = Wn;
-    Real *Jmine = JwBase + (size_t)wave * T * T * T;
-    for (int c = lane; c < T * T * T; c += 64) Jmine[c] = Real(0);
+    const int W = blockDim.x >> 6;
+    Real *P0 = waveL + (size_t)wave * WAVE_LDS;
+    Real *P1 = P0 + PLANE_LDS;
+    Real *Hl = P1 + PLANE_LDS;
+    Real *Jw = Hl + T * HALO_LINE;
+    for (int k = lane; k < T * T * T; k += 64) Jw[k] = Real(0);
     __syncthreads();
 
     // ---- per-wave ray sweeps ---------------------------------------------------------
     for (int r = wave; r < A.R; r += W) {
         const int ray = oct * A.R + r;
-        const RayGeo &G = A.rays[ray];
-        const int d = G.d, a = G.a, b = G.b;
-        const Real s_half = Real(0.5 * G.s);
-        const Real w00 = Real(G.w4[0]), w10 = Real(G.w4[1]), w01 = Real(G.w4[2]), w11 = Real(G.w4[3]);
-        const Real wk = Real(G.wk);
-        const int ed = tl.ext[d], ea = tl.ext[a], eb = tl.ext[b];
-        // LDS strides of the d, a, b axes inside the staged tile
-        const int str[3] = {1, TP, TP * TP};
-        const int sd = str[d], sa = str[a], sb = str[b];
-        Real *P0 = PlBase + (size_t)wave * 2 * PLANE_LDS;
-        Real *P1 = P0 + PLANE_LDS;
+        const RayGeo *G = A.rays + ray;
+        const int d = G->d, a = G->a, b = G->b, gidx = G->gidx;
+        const Real s_half = Real(0.5 * G->s);
+        const Real w00 = Real(G->w4[0]), w10 = Real(G->w4[1]), w01 = Real(G->w4[2]), w11 = Real(G->w4[3]);
+        const double w00d = G->w4[0], w10d = G->w4[1], w01d = G->w4[2], w11d = G->w4[3];
+        const Real wk = Real(G->wk);
+        const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
+        const int g0d = sel3(d, c.g0x, c.g0y, c.g0z), g0a = sel3(a, c.g0x, c.g0y, c.g0z),
+                  g0b = sel3(b, c.g0x, c.g0y, c.g0z);
+        // strides of the d, a, b axes in the staged tile and in the partial-sum tile
+        const int sd = sel3(d, 1, TP, TP * TP), sa = sel3(a, 1, TP, TP * TP), sb = sel3(b, 1, TP, TP * TP);
+        const int jd = sel3(d, 1, T, T * T), ja = sel3(a, 1, T, T * T), jb = sel3(b, 1, T, T * T);
 
-        // upwind d-face of the tile (d = -1), with its a and b halo lines
-        for (int e = lane; e < (ea + 1) * (eb + 1); e += 64) {
-            const int ia = e % (ea + 1) - 1, ib = e / (ea + 1) - 1;
-            int gv[3];
-            gv[d] = tl.g0[d] - 1;
-            gv[a] = tl.g0[a] + ia;
-            gv[b] = tl.g0[b] + ib;
-            P0[(ia + 1) + (ib + 1) * TP] = tl.halo(gv, ray, G.gidx);
+        // every upwind-halo value of this ray: the d = -1 face (into P0) and the a/b
+        // lines of planes 0 .. ed-2 (into Hl)
+        const int n1 = (ea + 1) * (eb + 1);
+        const int nl = ea + eb + 1;
+        const int tot = n1 + (ed - 1) * nl;
+        for (int e = lane; e < tot; e += 64) {
+            int vd, ia, ib;
+            Real *dst;
+            if (e < n1) {
+                ia = e % (ea + 1) - 1;
+                ib = e / (ea + 1) - 1;
+                vd = g0d - 1;
+                dst = P0 + (ia + 1) + (ib + 1) * TP;
+            } else {
+                const int e2 = e - n1, p = e2 / nl, k = e2 - p * nl;
+                vd = g0d + p;
+                if (k <= eb) {
+                    ia = -1;
+                    ib = k - 1;
+                } else {
+                    ia = k - eb - 1;
+                    ib = -1;
+                }
+                dst = Hl + p * HALO_LINE + k;
+            }
+            const int va = g0a + ia, vb = g0b + ib;
+            const int vx = d == 0 ? vd : (a == 0 ? va : vb);
+            const int vy = d == 1 ? vd : (a == 1 ? va : vb);
+            const int vz = d == 2 ? vd : (a == 2 ? va : vb);
+            *dst = halo_value<Real, DFORM>(A, c, SL, vx, vy, vz, ray, gidx);
         }
         wave_lds_sync();
 
+        const int64_t rb = (int64_t)f * A.na + ray;
         for (int p = 0; p < ed; ++p) {
             const Real *Pp = (p & 1) ? P1 : P0;
             Real *Pc = (p & 1) ? P0 : P1;
-            for (int c = lane; c < ea * eb; c += 64) {
-                const int ia = c % ea, ib = c / ea;
+            for (int k = lane; k < ea * eb; k += 64) {
+                const int ia = k % ea, ib = k / ea;
                 // staged-tile index of this vertex and of its upwind face vertices
                 const int l0 = (p + 1) * sd + (ia + 1) * sa + (ib + 1) * sb;
                 const int lu = l0 - sd;
-                const int i00 = lu, i10 = lu - sa, i01 = lu - sb, i11 = lu - sa - sb;
                 const int q00 = (ia + 1) + (ib + 1) * TP;
                 const Real Im = w00 * Pp[q00] + w10 * Pp[q00 - 1] + w01 * Pp[q00 - TP] + w11 * Pp[q00 - TP - 1];
-                const Real Sm = w00 * SLs[i00] + w10 * SLs[i10] + w01 * SLs[i01] + w11 * SLs[i11];
-                const Real Cm = w00 * chiL[i00] + w10 * chiL[i10] + w01 * chiL[i01] + w11 * chiL[i11];
-                const Real S0 = SLs[l0];
+                const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - sa] + w01 * chiL[lu - sb] + w11 * chiL[lu - sa - sb];
                 const Real dt = s_half * (Cm + chiL[l0]);
+                const double S0 = SL[l0];
+                const double Sm = w00d * SL[lu] + w10d * SL[lu - sa] + w01d * SL[lu - sb] + w11d * SL[lu - sa - sb];
                 Real v;
                 if constexpr (DFORM) {
                     Real E, g;
                     seg_coeffs(dt, E, g);
-                    v = Im * E + (Sm - S0) * g;
+                    v = Im * E + Real(Sm - S0) * g;   // S- - S0 formed in FP64
                 } else {
                     Real E, pm, p0;
                     seg_coeffs(dt, E, pm, p0);
-                    v = Im * E + pm * Sm + p0 * S0;
+                    v = Im * E + pm * Real(Sm) + p0 * Real(S0);
                 }
                 Pc[q00] = v;
-                int lc[3];
-                lc[d] = p;
-                lc[a] = ia;
-                lc[b] = ib;
-                Jmine[(lc[2] * T + lc[1]) * T + lc[0]] += wk * v;
+                const int lcell = p * jd + ia * ja + ib * jb;
+                Jw[lcell] += wk * v;
 
-                // downwind faces for the neighbour tiles / the next sweep's periodic ghosts
-                const bool on_a = (ia == ea - 1), on_b = (ib == eb - 1), on_d = (p == ed - 1);
-                if (on_a || on_b || on_d) {
-                    int gv[3];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) gv[q] = tl.g0[q] + lc[q];
-                    const int qs[3] = {a, b, d};
-                    const bool on[3] = {on_a, on_b, on_d};
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        if (!on[k]) continue;
-                        const int q = qs[k];
-                        int slot;
-                        Real val = v;
-                        if (tl.t[q] < A.nt[q] - 1) {
-                            slot = tl.t[q];
-                        } else if (A.periodic[q]) {
-                            slot = A.nt[q] - 1 + (tl.par ^ 1);
-                            if constexpr (DFORM) val = v + S0;  // periodic memory keeps I
-                        } else {
-                            continue;
-                        }
-                        A.face[q][tl.face_offset(q, ray, slot) + plane_index(q, gv, A.n)] = val;
+                // downwind faces for the neighbour tiles, or the next sweep's periodic memory
+                const int lx = lcell % T, ly = (lcell / T) % T, lz = lcell / (T * T);
+                const bool fx = lx == c.ex - 1, fy = ly == c.ey - 1, fz = lz == c.ez - 1;
+                if (fx || fy || fz) {
+                    const int vx = c.g0x + lx, vy = c.g0y + ly, vz = c.g0z + lz;
+                    const double Iw = DFORM ? double(v) + S0 : double(v);
+                    if (fx) {
+                        const int64_t pi = (int64_t)vz * A.n[1] + vy;
+                        if (c.tx < A.nt[0] - 1)
+                            A.face[0][(rb * (A.nt[0] - 1) + c.tx) * A.plane[0] + pi] = v;
+                        else if (A.periodic[0])
+                            A.wrap[0][(rb * 2 + (par ^ 1)) * A.plane[0] + pi] = Iw;
+                    }
+                    if (fy) {
+                        const int64_t pi = (int64_t)vz * A.n[0] + vx;
+                        if (c.ty < A.nt[1] - 1)
+                            A.face[1][(rb * (A.nt[1] - 1) + c.ty) * A.plane[1] + pi] = v;
+                        else if (A.periodic[1])
+                            A.wrap[1][(rb * 2 + (par ^ 1)) * A.plane[1] + pi] = Iw;
+                    }
+                    if (fz) {
+                        const int64_t pi = (int64_t)vy * A.n[0] + vx;
+                        if (c.tz < A.nt[2] - 1)
+                            A.face[2][(rb * (A.nt[2] - 1) + c.tz) * A.plane[2] + pi] = v;
+                        else if (A.periodic[2])
+                            A.wrap[2][(rb * 2 + (par ^ 1)) * A.plane[2] + pi] = Iw;
                     }
                 }
             }
-            // halo lines of plane p for the next step
+            // halo lines of plane p for the next step, from the prefetched batch
             if (p + 1 < ed) {
-                for (int e = lane; e < ea + eb + 1; e += 64) {
-                    int ia, ib;
-                    if (e <= eb) {
-                        ia = -1;
-                        ib = e - 1;
-                    } else {
-                        ia = e - eb - 1;
-                        ib = -1;
-                    }
-                    int gv[3];
-                    gv[d] = tl.g0[d] + p;
-                    gv[a] = tl.g0[a] + ia;
-                    gv[b] = tl.g0[b] + ib;
-                    Pc[(ia + 1) + (ib + 1) * TP] = tl.halo(gv, ray, G.gidx);
+                for (int k = lane; k < nl; k += 64) {
+                    const int ia = (k <= eb) ? -1 : k - eb - 1;
+                    const int ib = (k <= eb) ? k - 1 : -1;
+                    Pc[(ia + 1) + (ib + 1) * TP] = Hl[p * HALO_LINE + k];
                 }
             }
             wave_lds_sync();
@@ -348,56 +349,51 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
 
     // ---- fixed-order sum over the waves -> this octant's partial sums --------------
     Real *outp = A.part + ((int64_t)oct * A.nf + f) * A.cells;
-    for (int c = threadIdx.x; c < T * T * T; c += blockDim.x) {
-        const int lc[3] = {c % T, (c / T) % T, c / (T * T)};
-        if (lc[0] >= tl.ext[0] || lc[1] >= tl.ext[1] || lc[2] >= tl.ext[2]) continue;
-        Real acc = JwBase[c];
-        for (int w = 1; w < W; ++w) acc += JwBase[(size_t)w * T * T * T + c];
-        int u[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) u[q] = to_real(tl.g0[q] + lc[q], tl.sg[q], A.n[q]);
-        outp[((int64_t)u[2] * A.n[1] + u[1]) * A.n[0] + u[0]] = acc;
+    for (int k = threadIdx.x; k < T * T * T; k += blockDim.x) {
+        const int lx = k % T, ly = (k / T) % T, lz = k / (T * T);
+        if (lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
+        Real acc = waveL[2 * PLANE_LDS + T * HALO_LINE + k];
+        for (int w = 1; w < W; ++w) acc += waveL[(size_t)w * WAVE_LDS + 2 * PLANE_LDS + T * HALO_LINE + k];
+        const int rx = to_real(c.g0x + lx, c.sgx, A.n[0]);
+        const int ry = to_real(c.g0y + ly, c.sgy, A.n[1]);
+        const int rz = to_real(c.g0z + lz, c.sgz, A.n[2]);
+        outp[((int64_t)rz * A.n[1] + ry) * A.n[0] + rx] = acc;
     }
 }
 
 // ---- Lambda*: diagonal of the formal-solution operator (section 3.4) -----------------
 // Lambda*_ii = sum_k w_k psi0_k: the weight of S at the vertex itself in its own
 // update.  psi0 depends only on the upwind chi, so this is a pointwise kernel.
-__global__ void lambda_star_kernel(int nx, int ny, int nz, int bx0, int bx1, int by0, int by1, int bz0,
-                                   int bz1, int nf, int na, const RayGeo *rays, const double *chi,
-                                   double *lam)
+__global__ void lambda_star_kernel(int nx, int ny, int nz, int px, int py, int pz, int nf, int na,
+                                   const RayGeo *rays, const double *chi, double *lam)
 {
     const int64_t cells = (int64_t)nx * ny * nz;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cells * nf) return;
     const int f = (int)(i / cells);
-    const int64_t c = i - (int64_t)f * cells;
-    const int n[3] = {nx, ny, nz};
-    const int per[3] = {bx0 == BC_PERIODIC, by0 == BC_PERIODIC, bz0 == BC_PERIODIC};
-    (void)bx1; (void)by1; (void)bz1;
-    const int x[3] = {(int)(c % nx), (int)((c / nx) % ny), (int)(c / ((int64_t)nx * ny))};
+    const int64_t cc = i - (int64_t)f * cells;
+    const int x = (int)(cc % nx), y = (int)((cc / nx) % ny), z = (int)(cc / ((int64_t)nx * ny));
     const double *cf = chi + (int64_t)f * cells;
-    const double c0 = cf[c];
+    const double c0 = cf[cc];
     double acc = 0.0;
     for (int k = 0; k < na; ++k) {
-        const RayGeo &G = rays[k];
-        int sg[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) sg[q] = (G.oct >> q) & 1 ? -1 : 1;
+        const RayGeo *G = rays + k;
+        const int d = G->d, a = G->a;
+        const int sx = (G->oct & 1) ? -1 : 1, sy = (G->oct & 2) ? -1 : 1, sz = (G->oct & 4) ? -1 : 1;
         double cm = 0.0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            int u[3] = {x[0], x[1], x[2]};
-            u[G.d] -= sg[G.d];
-            u[G.a] -= (v & 1) * sg[G.a];
-            u[G.b] -= (v >> 1) * sg[G.b];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) u[q] = fold(u[q], n[q], per[q]);
-            cm += G.w4[v] * cf[((int64_t)u[2] * ny + u[1]) * nx + u[0]];
+            const int oa = v & 1, ob = v >> 1;
+            // upwind offset along each axis: 1 on d, oa on a, ob on b (times the sign)
+            const int ox = d == 0 ? 1 : (a == 0 ? oa : ob);
+            const int oy = d == 1 ? 1 : (a == 1 ? oa : ob);
+            const int oz = d == 2 ? 1 : (a == 2 ? oa : ob);
+            const int ux = fold(x - ox * sx, nx, px), uy = fold(y - oy * sy, ny, py), uz = fold(z - oz * sz, nz, pz);
+            cm += G->w4[v] * cf[((int64_t)uz * ny + uy) * nx + ux];
         }
         double E, pm, p0;
-        seg_coeffs(0.5 * G.s * (cm + c0), E, pm, p0);
-        acc += G.wk * p0;
+        seg_coeffs(0.5 * G->s * (cm + c0), E, pm, p0);
+        acc += G->wk * p0;
     }
     lam[i] = acc;
 }
@@ -405,25 +401,25 @@ __global__ void lambda_star_kernel(int nx, int ny, int nz, int bx0, int bx1, int
 template <typename Real>
 __global__ void periodic_cold_kernel(SweepArgs<Real> A, int q)
 {
-    // slot about to be read: nt_q - 1 + parity[f]; value S of the wrapped vertex
-    const int64_t P = A.plane[q];
+    // the periodic slot read next (parity[f]) holds S of the wrapped vertex
+    const int64_t P = sel3(q, A.plane[0], A.plane[1], A.plane[2]);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int ray = blockIdx.y;
     const int f = blockIdx.z;
     if (i >= P) return;
     const int oct = A.rays[ray].oct;
-    const int p1 = (q == 0) ? 1 : 0;
-    const int p2 = (q == 2) ? 1 : 2;
-    int gv[3];
-    gv[q] = A.n[q] - 1;
-    gv[p1] = (int)(i % A.n[p1]);
-    gv[p2] = (int)(i / A.n[p1]);
-    int u[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = to_real(gv[k], (oct >> k) & 1 ? -1 : 1, A.n[k]);
-    const Real Sv = A.S[(int64_t)f * A.cells + ((int64_t)u[2] * A.n[1] + u[1]) * A.n[0] + u[0]];
-    const int slot = A.nt[q] - 1 + A.parity[f];
-    A.face[q][(((int64_t)f * A.na + ray) * (A.nt[q] + 1) + slot) * P + i] = Sv;
+    // flipped coordinates of the outgoing-plane vertex: coordinate n_q - 1 along q
+    const int n1 = (q == 0) ? A.n[1] : A.n[0];
+    const int u1 = (int)(i % n1), u2 = (int)(i / n1);
+    const int vx = (q == 0) ? A.n[0] - 1 : u1;
+    const int vy = (q == 1) ? A.n[1] - 1 : (q == 0 ? u1 : u2);
+    const int vz = (q == 2) ? A.n[2] - 1 : u2;
+    const int rx = to_real(vx, (oct & 1) ? -1 : 1, A.n[0]);
+    const int ry = to_real(vy, (oct & 2) ? -1 : 1, A.n[1]);
+    const int rz = to_real(vz, (oct & 4) ? -1 : 1, A.n[2]);
+    const double Sv = A.S[(int64_t)f * A.cells + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx];
+    double *Wq = (q == 0) ? A.wrap[0] : (q == 1 ? A.wrap[1] : A.wrap[2]);
+    Wq[(((int64_t)f * A.na + ray) * 2 + A.parity[f]) * P + i] = Sv;
 }
 
 template <typename Real>
@@ -453,21 +449,19 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 
 // Jacobi update (eq. dsjacobi) and the per-bin residual max |dS|/S^{n+1} (eq. conv),
 // both in FP64.  With dform the partials hold sum w (I - S), so J - S is summed
-// without cancellation.
+// without cancellation.  Each block writes its max to blockmax (no atomics).
 template <typename Real>
 __global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int dform, int nf, int64_t cells,
                                                          const double *B, const double *eps,
-                                                         const double *lam, double *S64, float *S32,
-                                                         double *Jout, AliCtl ctl)
+                                                         const double *lam, double *S64, double *Jout, AliCtl ctl)
 {
     __shared__ unsigned long long red[4];
     const int f = blockIdx.y;
     if (ctl.frozen[f]) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)nf * cells;
     unsigned long long rb = 0ull;
-    if (c < cells) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = (int64_t)f * cells + c;
-        const int64_t stride = (int64_t)nf * cells;
         double sum = 0.0;
 #pragma unroll
         for (int o = 0; o < 8; ++o) sum += (double)part[o * stride + i];
@@ -483,9 +477,9 @@ __global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int d
         const double dS = num / (1.0 - (1.0 - e) * lam[i]);
         const double Sn = S + dS;
         S64[i] = Sn;
-        if (S32) S32[i] = (float)Sn;
         const double r = (Sn != 0.0) ? fabs(dS) / fabs(Sn) : 0.0;
-        rb = (unsigned long long)__double_as_longlong(r);
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(r);
+        rb = bits > rb ? bits : rb;
     }
     rb = wave_max_u64(rb);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rb;
@@ -493,37 +487,59 @@ __global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int d
     if (threadIdx.x == 0) {
         unsigned long long m = red[0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = red[w] > m ? red[w] : m;
-        if (m) atomicMax(&ctl.res_bits[f], m);
+        ctl.blockmax[(int64_t)f * ctl.nblk + blockIdx.x] = m;
     }
 }
 
-__global__ void ali_finalize_kernel(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode)
+// Per-bin convergence test (eq. conv) after an update: reduce the block maxima,
+// count the iteration, flip the periodic slot, freeze converged bins.
+__global__ void __launch_bounds__(256) ali_finalize_kernel(AliCtl ctl, int nf, double delta_c, int per_bin_stop,
+                                                           int fixed_mode)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int active = 0, all_conv = 1, nonfinite = 0;
-    for (int f = 0; f < nf; ++f) {
-        if (ctl.frozen[f]) continue;
-        const unsigned long long bits = ctl.res_bits[f];
-        ctl.res_bits[f] = 0ull;
-        const double r = __longlong_as_double((long long)bits);
-        ctl.iters[f] += 1;
-        ctl.resid[f] = r;
-        ctl.parity[f] ^= 1;
-        if (!(r <= 1.7976931348623157e308)) nonfinite = 1;
-        const int conv = r <= delta_c;
-        all_conv &= conv;
-        ++active;
-        if (per_bin_stop && conv && !fixed_mode) ctl.frozen[f] = 1;
+    __shared__ unsigned long long red[4];
+    __shared__ int s_all_conv, s_nonfinite, s_active;
+    if (threadIdx.x == 0) {
+        s_all_conv = 1;
+        s_nonfinite = 0;
+        s_active = 0;
     }
-    if (!per_bin_stop && !fixed_mode && active > 0 && all_conv)
-        for (int f = 0; f < nf; ++f) ctl.frozen[f] = 1;
-    int stopped = 1;
-    for (int f = 0; f < nf; ++f) stopped &= ctl.frozen[f] != 0;
-    ctl.flags[0] = stopped;
-    if (nonfinite) {
-        ctl.flags[1] = 1;
-        for (int f = 0; f < nf; ++f) ctl.frozen[f] = 1;
-        ctl.flags[0] = 1;
+    __syncthreads();
+    for (int f = 0; f < nf; ++f) {
+        if (ctl.frozen[f]) continue;   // uniform across the block
+        unsigned long long m = 0ull;
+        for (int k = threadIdx.x; k < ctl.nblk; k += blockDim.x) {
+            const unsigned long long v = ctl.blockmax[(int64_t)f * ctl.nblk + k];
+            m = v > m ? v : m;
+        }
+        m = wave_max_u64(m);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = red[w] > m ? red[w] : m;
+            m = red[0] > m ? red[0] : m;
+            const double r = __longlong_as_double((long long)m);
+            ctl.iters[f] += 1;
+            ctl.resid[f] = r;
+            ctl.parity[f] ^= 1;
+            if (!(r <= 1.7976931348623157e308)) s_nonfinite = 1;
+            const int conv = r <= delta_c;
+            s_all_conv &= conv;
+            s_active += 1;
+            if (per_bin_stop && conv && !fixed_mode) ctl.frozen[f] = 1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (!per_bin_stop && !fixed_mode && s_active > 0 && s_all_conv)
+            for (int f = 0; f < nf; ++f) ctl.frozen[f] = 1;
+        int stopped = 1;
+        for (int f = 0; f < nf; ++f) stopped &= ctl.frozen[f] != 0;
+        ctl.flags[0] = stopped;
+        if (s_nonfinite) {
+            ctl.flags[1] = 1;
+            for (int f = 0; f < nf; ++f) ctl.frozen[f] = 1;
+            ctl.flags[0] = 1;
+        }
     }
 }
 
@@ -549,28 +565,33 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
+size_t sweep_lds_bytes(int real_bytes, int waves)
+{
+    return sizeof(double) * (size_t)TILE_LDS + (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * WAVE_LDS);
+}
+
 hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, hipStream_t st)
 {
     dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nf);
-    hipLaunchKernelGGL((sweep_stage_kernel<double, false>), grid, dim3(64 * waves), sweep_lds_bytes<double>(waves),
-                       st, A);
+    hipLaunchKernelGGL((sweep_stage_kernel<double, false>), grid, dim3(64 * waves), sweep_lds_bytes(8, waves), st, A);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStream_t st)
 {
     dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nf);
-    hipLaunchKernelGGL((sweep_stage_kernel<float, true>), grid, dim3(64 * waves), sweep_lds_bytes<float>(waves),
-                       st, A);
+    hipLaunchKernelGGL((sweep_stage_kernel<float, true>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves), st, A);
     return hipGetLastError();
 }
 
 hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,
                               const RayGeo *rays, const double *chi, double *lam, hipStream_t st)
 {
+    (void)bc_hi;  // periodic axes are periodic on both faces
     const int64_t tot = (int64_t)n[0] * n[1] * n[2] * nf;
     hipLaunchKernelGGL(lambda_star_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, st, n[0], n[1], n[2],
-                       bc_lo[0], bc_hi[0], bc_lo[1], bc_hi[1], bc_lo[2], bc_hi[2], nf, na, rays, chi, lam);
+                       (int)(bc_lo[0] == BC_PERIODIC), (int)(bc_lo[1] == BC_PERIODIC), (int)(bc_lo[2] == BC_PERIODIC),
+                       nf, na, rays, chi, lam);
     return hipGetLastError();
 }
 
@@ -604,23 +625,23 @@ template hipError_t launch_partial_sum<float>(const float *, const double *, int
 
 template <typename Real>
 hipError_t launch_ali_update(const Real *part, int dform, int nf, int64_t cells, const double *B,
-                             const double *eps, const double *lam, double *S64, float *S32, double *J,
+                             const double *eps, const double *lam, double *S64, double *J,
                              AliCtl ctl, hipStream_t st)
 {
-    dim3 grid(blocks_for(cells, 256), (unsigned)nf);
+    dim3 grid((unsigned)ctl.nblk, (unsigned)nf);
     hipLaunchKernelGGL(ali_update_kernel<Real>, grid, dim3(256), 0, st, part, dform, nf, cells, B, eps, lam, S64,
-                       S32, J, ctl);
+                       J, ctl);
     return hipGetLastError();
 }
 template hipError_t launch_ali_update<double>(const double *, int, int, int64_t, const double *, const double *,
-                                              const double *, double *, float *, double *, AliCtl, hipStream_t);
+                                              const double *, double *, double *, AliCtl, hipStream_t);
 template hipError_t launch_ali_update<float>(const float *, int, int, int64_t, const double *, const double *,
-                                             const double *, double *, float *, double *, AliCtl, hipStream_t);
+                                             const double *, double *, double *, AliCtl, hipStream_t);
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,
                                hipStream_t st)
 {
-    hipLaunchKernelGGL(ali_finalize_kernel, dim3(1), dim3(64), 0, st, ctl, nf, delta_c, per_bin_stop, fixed_mode);
+    hipLaunchKernelGGL(ali_finalize_kernel, dim3(1), dim3(256), 0, st, ctl, nf, delta_c, per_bin_stop, fixed_mode);
     return hipGetLastError();
 }
 
