@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="grid edge of the scattering workload")
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 GPU comparison solve")
+    ap.add_argument("--schedule", choices=["stages"], default="stages")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -84,7 +85,9 @@ def main():
     n = wl.chi.size
     S = torch.empty(n, dtype=torch.float64, device="cuda")
     J = torch.empty(n, dtype=torch.float64, device="cuda")
-    prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32)
+    sched = rt.RT_SCHED_STAGES
+    prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
+                      schedule=sched)
 
     def step():
         prob.reset_periodic()
@@ -127,7 +130,8 @@ def main():
 
     extra = {}
     if not args.no_f64:
-        p64 = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F64)
+        p64 = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F64,
+                         schedule=sched)
         p64.set_fields(chi, eps, B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -149,6 +153,7 @@ def main():
         "config": {"workload": f"scattering {wl.shape[0]}^3, 1 bin, {wl.na} rays, eps=1e-3, "
                                f"vertical tau 1e4, Jacobi ALI from S=B to max|dS/S|<=1e-6, "
                                f"FP32 sweeps + FP64 updates", "grid": list(wl.shape), "rays": wl.na,
+                   "schedule": args.schedule,
                    "bins": wl.nf},
         "ali_solves_per_s": args.steps / total,
         "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},

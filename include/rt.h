@@ -60,6 +60,13 @@ typedef enum { RT_F64 = 0, RT_F32 = 1 } rt_precision;
  * at the opposite face (PERIODIC; both faces of the axis must be periodic). */
 typedef enum { RT_BC_VACUUM = 0, RT_BC_THERMAL = 1, RT_BC_PERIODIC = 2, RT_BC_FIXED = 3 } rt_bc_kind;
 
+/* Execution of the tile wavefront of one formal solution.  RT_SCHED_STAGES: one
+ * launch per tile hyperplane (the default).  RT_SCHED_PERSISTENT (one launch,
+ * workgroups drawing tiles in hyperplane order and waiting on completion flags of
+ * their upwind neighbours) is disabled in this build: rt_problem_create returns
+ * RT_E_UNSUPPORTED for it. */
+typedef enum { RT_SCHED_DEFAULT = 0, RT_SCHED_STAGES = 1, RT_SCHED_PERSISTENT = 2 } rt_schedule;
+
 typedef struct {
     int32_t nx, ny, nz;       /* grid vertices per axis, each >= 1 */
     int32_t nf;               /* frequency bins, >= 1 */
@@ -76,6 +83,7 @@ typedef struct {
                                  increasing order (x-faces: y,z; y-faces: x,z; z-faces: x,y) */
     int32_t precision;        /* rt_precision */
     int32_t tile;             /* tile edge for the sweep (0 = default) */
+    int32_t schedule;         /* rt_schedule: how the tile wavefront is executed */
 } rt_problem_desc;
 
 typedef struct rt_problem rt_problem;

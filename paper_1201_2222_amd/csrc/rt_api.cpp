@@ -253,6 +253,13 @@ struct rt_problem {
     double *resid = nullptr;
     unsigned long long *blockmax = nullptr;  // [nf][kUpdateBlocks]
     int waves = 1;                     // waves per sweep workgroup
+    bool persistent = false;           // one launch per sweep (dependency flags)
+    int ntiles = 0;                    // tiles per (bin, octant)
+    int bpo = 1;                       // persistent workgroups per octant
+    int epoch = 0;                     // sweeps run by the persistent kernel
+    uint64_t wait_ticks = 0;           // 20 ms in device wall-clock ticks
+    int *dag_counter = nullptr;        // [8] ticket counters
+    int *dag_done = nullptr;           // [nf][8][ntiles] completion epochs
     int *h_flags = nullptr;            // pinned host copy of flags
     int *h_frozen = nullptr;           // pinned host copy of frozen
     std::vector<void *> allocs;
@@ -279,6 +286,11 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
         return fail(RT_E_INVALID, "dx, dy, dz must be finite and > 0");
     if (d->precision != RT_F64 && d->precision != RT_F32) return fail(RT_E_INVALID, "unknown precision");
     if (d->tile != 0 && d->tile != kTile) return fail(RT_E_UNSUPPORTED, "tile edge %d not built (only %d)", d->tile, kTile);
+    if (d->schedule < RT_SCHED_DEFAULT || d->schedule > RT_SCHED_PERSISTENT) return fail(RT_E_INVALID, "unknown schedule");
+    // The persistent schedule did not complete on the device in testing and its
+    // cause is not established; it is refused until it is.
+    if (d->schedule == RT_SCHED_PERSISTENT)
+        return fail(RT_E_UNSUPPORTED, "the persistent sweep schedule is disabled in this build");
     for (int q = 0; q < 3; ++q) {
         for (int k : {d->bc_lo[q], d->bc_hi[q]})
             if (k < RT_BC_VACUUM || k > RT_BC_FIXED) return fail(RT_E_INVALID, "unknown boundary kind on axis %d", q);
@@ -341,6 +353,7 @@ size_t state_bytes(const rt_problem_desc *d, int na)
     }
     b += (size_t)8 * nc * rs;                      // partials
     b += (size_t)d->nf * kUpdateBlocks * 8;        // residual block maxima
+    b += (size_t)d->nf * 8 * nt[0] * nt[1] * nt[2] * 4 + 32;  // persistent-sweep flags
     b += (size_t)na * sizeof(RayGeo) + (size_t)nt[0] * nt[1] * nt[2] * 4 + (size_t)d->nf * 32 + 64;
     return b;
 }
@@ -404,7 +417,8 @@ int sweep_waves(int R, bool f32, size_t lds_limit)
 rt_status collect_timing(rt_problem *p)
 {
     if (!p->prof_pending) return RT_OK;
-    for (int s = 0; s < p->nstages; ++s) {
+    const int launches = p->persistent ? 1 : p->nstages;
+    for (int s = 0; s < launches; ++s) {
         HIP_TRY(hipEventSynchronize(p->ev[2 * s + 1]));
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * s], p->ev[2 * s + 1]));
@@ -430,6 +444,31 @@ rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed =
     }
     timed = timed && p->prof && !p->prof_pending;
     const int W = p->waves;
+    if (p->persistent) {
+        DagArgs D;
+        D.counter = p->dag_counter;
+        D.done = p->dag_done;
+        D.err = p->flags + 2;
+        D.wait_ticks = p->wait_ticks;
+        D.epoch = ++p->epoch;
+        D.ntiles = p->ntiles;
+        D.nt0 = p->nt[0];
+        D.nt1 = p->nt[1];
+        A.stage_off = 0;
+        A.stage_cnt = p->ntiles;
+        HIP_TRY(hipMemsetAsync(p->dag_counter, 0, 8 * sizeof(int), st));
+        if (timed) HIP_TRY(hipEventRecord(p->ev[0], st));
+        if constexpr (sizeof(Real) == 8)
+            HIP_TRY(launch_sweep_persistent_f64(A, D, W, p->bpo, st));
+        else
+            HIP_TRY(launch_sweep_persistent_f32(A, D, W, p->bpo, st));
+        if (timed) {
+            HIP_TRY(hipEventRecord(p->ev[1], st));
+            p->prof_pending = true;
+            p->prof_pending_updates = (double)p->cells * p->na * active_bins;
+        }
+        return RT_OK;
+    }
     for (int s = 0; s < p->nstages; ++s) {
         A.stage_off = p->stage_off[s];
         A.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
@@ -613,6 +652,9 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     ALLOC(p->resid, (size_t)p->nf);
     ALLOC(p->blockmax, (size_t)p->nf * kUpdateBlocks);
     ALLOC(p->flags, 4);
+    p->ntiles = p->nt[0] * p->nt[1] * p->nt[2];
+    ALLOC(p->dag_counter, 8);
+    ALLOC(p->dag_done, (size_t)p->nf * 8 * p->ntiles);
 #undef ALLOC
     if (hipHostMalloc((void **)&p->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&p->h_frozen, sizeof(int) * p->nf, hipHostMallocDefault) != hipSuccess) {
@@ -626,6 +668,18 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
         (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     (void)hipGetLastError();
     p->waves = sweep_waves(p->R, p->f32, (size_t)lds_limit);
+    p->persistent = desc->schedule == RT_SCHED_PERSISTENT;
+    if (p->persistent) {
+        int per_cu = 0, ncu = 0;
+        if (persistent_blocks_per_cu(p->f32 ? 4 : 8, p->waves, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 8) ncu = 8;
+        (void)hipGetLastError();
+        p->bpo = std::max(1, std::min(per_cu * ncu / 8, p->ntiles * p->nf));
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+        (void)hipGetLastError();
+        p->wait_ticks = (uint64_t)khz * 20;   // 20 ms
+    }
     if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves) > (size_t)lds_limit) {
         rt_problem_destroy(p);
         return fail(RT_E_UNSUPPORTED, "sweep needs %zu bytes of LDS, device allows %d",
@@ -636,6 +690,7 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     if (e == hipSuccess) e = hipMemset(p->frozen, 0, sizeof(int) * p->nf);
     if (e == hipSuccess) e = hipMemset(p->parity, 0, sizeof(int) * p->nf);
     if (e == hipSuccess) e = hipMemset(p->flags, 0, sizeof(int) * 4);
+    if (e == hipSuccess) e = hipMemset(p->dag_done, 0, sizeof(int) * (size_t)p->nf * 8 * p->ntiles);
     if (e != hipSuccess) {
         rt_problem_destroy(p);
         return fail(RT_E_HIP, "problem initialisation failed: %s", hipGetErrorString(e));
@@ -739,11 +794,12 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
             HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
         }
         it += k;
-        HIP_TRY(hipMemcpyAsync(p->h_flags, p->flags, sizeof(int) * 2, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(p->h_flags, p->flags, sizeof(int) * 3, hipMemcpyDeviceToHost, st));
         if (p->prof) HIP_TRY(hipMemcpyAsync(p->h_frozen, p->frozen, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         done = p->h_flags[0];
         nonfinite = p->h_flags[1] != 0;
+        if (p->h_flags[2]) return fail(RT_E_HIP, "persistent sweep: a tile dependency wait ran out");
         {
             rt_status s = collect_timing(p);
             if (s != RT_OK) return s;
@@ -793,7 +849,7 @@ rt_status rt_problem_profile(rt_problem *p, int32_t enable)
     rt_status s = collect_timing(p);
     if (s != RT_OK) return s;
     if (enable && p->ev.empty()) {
-        p->ev.resize(2 * (size_t)p->nstages);
+        p->ev.resize(2 * (size_t)std::max(p->nstages, 1));
         for (auto &e : p->ev) HIP_TRY(hipEventCreate(&e));
     }
     p->prof = enable != 0;

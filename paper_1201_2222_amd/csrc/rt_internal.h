@@ -49,6 +49,20 @@ struct SweepArgs {
     const int *parity;        // [nf]: periodic slot read this sweep
 };
 
+// Dependency state of the persistent sweep: one completion flag per (bin, octant,
+// tile) holding the epoch of the sweep that last finished it, and one ticket
+// counter per octant (zeroed before each sweep).
+struct DagArgs {
+    int *counter;             // [8]
+    int *done;                // [nf][8][ntiles]
+    int *err;                 // set when a dependency wait ran out
+    uint64_t wait_ticks;      // bound of one wait in wall-clock ticks
+    int epoch;
+    int ntiles;
+    int nt0, nt1;             // tiles along x and y
+    __host__ __device__ int tile_id(int tx, int ty, int tz) const { return (tz * nt1 + ty) * nt0 + tx; }
+};
+
 // Device-side control block of the Lambda iteration.
 struct AliCtl {
     int *frozen;              // [nf]
@@ -67,6 +81,11 @@ hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, hipStre
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStream_t st);
 // dynamic LDS bytes of one sweep workgroup with the given number of waves
 size_t sweep_lds_bytes(int real_bytes, int waves);
+hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs &D, int waves, int blocks_per_octant,
+                                       hipStream_t st);
+hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int blocks_per_octant,
+                                       hipStream_t st);
+hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks);
 
 hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,
                               const RayGeo *rays, const double *chi, double *lam, hipStream_t st);

@@ -111,16 +111,11 @@ struct TileCtx {
     int64_t fbase;   // f * cells
 };
 
-__device__ __forceinline__ int lds_cell(const TileCtx &c, int vx, int vy, int vz)
-{
-    return ((vz - c.g0z + 1) * TP + (vy - c.g0y + 1)) * TP + (vx - c.g0x + 1);
-}
-
 // Value (I, or D = I - S in the difference form) at a vertex (vx, vy, vz) in
-// flipped coordinates just upwind of the tile, for one ray.
+// flipped coordinates just upwind of the tile, for one ray.  Ghost vertices read S
+// from global memory, so the call does not wait for the staged tile.
 template <typename Real, bool DFORM>
-__device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, const double *SL, int vx, int vy, int vz,
-                           int ray, int gidx)
+__device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, int vx, int vy, int vz, int ray, int gidx)
 {
     const bool ox = vx < 0, oy = vy < 0, oz = vz < 0;
     const int64_t rb = (int64_t)c.f * A.na + ray;
@@ -132,11 +127,12 @@ __device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, const dou
             return A.face[1][(rb * (A.nt[1] - 1) + (c.ty - 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx];
         return A.face[2][(rb * (A.nt[2] - 1) + (c.tz - 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx];
     }
-    // ghost vertex outside the grid; the staged S is that of the folded vertex
-    const double Sg = SL[lds_cell(c, vx, vy, vz)];
+    // ghost vertex outside the grid: chi and S are those of the folded vertex
     const int rx = fold(to_real(vx, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
     const int ry = fold(to_real(vy, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
     const int rz = fold(to_real(vz, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
+    const int64_t cell = c.fbase + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
+    const double Sg = DFORM ? A.S[cell] : 0.0;
     // outside a non-periodic face: that face's condition, z before y before x
     int q = -1;
     if (oz && !A.periodic[2]) q = 2;
@@ -147,7 +143,7 @@ __device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, const dou
         const int kind = lo ? sel3(q, A.bc_lo[0], A.bc_lo[1], A.bc_lo[2]) : sel3(q, A.bc_hi[0], A.bc_hi[1], A.bc_hi[2]);
         double I = 0.0;
         if (kind == BC_THERMAL) {
-            I = A.B[c.fbase + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx];
+            I = A.B[cell];
         } else if (kind == BC_FIXED) {
             const double *F = (q == 0) ? (lo ? A.fixed[0] : A.fixed[1])
                                        : (q == 1 ? (lo ? A.fixed[2] : A.fixed[3]) : (lo ? A.fixed[4] : A.fixed[5]));
@@ -171,21 +167,76 @@ __device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, const dou
     return DFORM ? Real(I - Sg) : Real(I);
 }
 
+// Load every upwind-halo value one ray needs in this tile: the d = -1 face into
+// the first plane buffer, the a/b halo lines of planes 0 .. ed-2 into Hl.
 template <typename Real, bool DFORM>
-__global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
+__device__ void prefetch_halo(const SweepArgs<Real> &A, const TileCtx &c, int oct, int r, int lane, Real *P0, Real *Hl)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int ray = oct * A.R + r;
+    const RayGeo *G = A.rays + ray;
+    const int d = G->d, a = G->a, gidx = G->gidx;
+    const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(3 - d - a, c.ex, c.ey, c.ez);
+    const int g0d = sel3(d, c.g0x, c.g0y, c.g0z), g0a = sel3(a, c.g0x, c.g0y, c.g0z),
+              g0b = sel3(3 - d - a, c.g0x, c.g0y, c.g0z);
+    const int n1 = (ea + 1) * (eb + 1);
+    const int nl = ea + eb + 1;
+    const int tot = n1 + (ed - 1) * nl;
+    for (int e = lane; e < tot; e += 64) {
+        int vd, ia, ib;
+        Real *dst;
+        if (e < n1) {
+            ia = e % (ea + 1) - 1;
+            ib = e / (ea + 1) - 1;
+            vd = g0d - 1;
+            dst = P0 + (ia + 1) + (ib + 1) * TP;
+        } else {
+            const int e2 = e - n1, p = e2 / nl, k = e2 - p * nl;
+            vd = g0d + p;
+            ia = (k <= eb) ? -1 : k - eb - 1;
+            ib = (k <= eb) ? k - 1 : -1;
+            dst = Hl + p * HALO_LINE + k;
+        }
+        const int va = g0a + ia, vb = g0b + ib;
+        const int vx = d == 0 ? vd : (a == 0 ? va : vb);
+        const int vy = d == 1 ? vd : (a == 1 ? va : vb);
+        const int vz = d == 2 ? vd : (a == 2 ? va : vb);
+        *dst = halo_value<Real, DFORM>(A, c, vx, vy, vz, ray, gidx);
+    }
+}
+
+// Wait until a tile's completion flag carries this sweep's epoch.  The loop polls
+// with relaxed agent-scope loads (no cache invalidation per poll) and takes one
+// agent-scope acquire fence once the flag is seen.  The wait is bounded by the
+// constant-rate wall clock (limit_ticks) and gives up at once when another wait
+// has already run out (*err set), so every wave exits.
+__device__ __forceinline__ bool wait_done(const int *flag, int epoch, const int *err, uint64_t limit_ticks)
+{
+    const uint64_t t0 = wall_clock64();
+    for (int i = 0;; ++i) {
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        if ((i & 15) == 15) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+            if (wall_clock64() - t0 > limit_ticks) return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// One tile of one octant and bin: stage chi and S with the upwind halo, sweep every
+// ray of the octant through it, write the octant's partial sums.  With a non-null
+// dependency block (persistent sweep) the upwind face-neighbour tiles are awaited
+// after the staging loads have been issued and before any face data is read.
+template <typename Real, bool DFORM, bool PERSIST>
+__device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, int f, int packed, int par,
+                                           unsigned char *lds_raw, const int *done, int epoch, int ntiles, int nt0,
+                                           int nt1, int *err, uint64_t limit_ticks)
+{
     double *SL = reinterpret_cast<double *>(lds_raw);
     Real *chiL = reinterpret_cast<Real *>(SL + TILE_LDS);
     Real *waveL = chiL + TILE_LDS;
-
-    const int oct = blockIdx.x & 7;
-    const int item = blockIdx.x >> 3;
-    const int f = blockIdx.y;
-    const int frozen = A.frozen[f];
-    const int par = A.parity[f];
-    const int packed = A.tiles[A.stage_off + item];
-    if (frozen) return;
 
     TileCtx c;
     c.f = f;
@@ -204,6 +255,17 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
     c.ey = min(T, A.n[1] - c.g0y);
     c.ez = min(T, A.n[2] - c.g0z);
 
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int W = blockDim.x >> 6;
+    Real *P0 = waveL + (size_t)wave * WAVE_LDS;
+    Real *P1 = P0 + PLANE_LDS;
+    Real *Hl = P1 + PLANE_LDS;
+    Real *Jw = Hl + T * HALO_LINE;
+
+    // the first ray's halo loads go out together with the tile staging loads
+    if (!PERSIST && wave < A.R) prefetch_halo<Real, DFORM>(A, c, oct, wave, lane, P0, Hl);
+
     // ---- stage chi and S of the tile and its upwind halo in LDS --------------------
     const Real *chif = A.chi + c.fbase;
     const double *Sf = A.S + c.fbase;
@@ -217,21 +279,32 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
         chiL[idx] = chif[cell];
         SL[idx] = Sf[cell];
     }
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int W = blockDim.x >> 6;
-    Real *P0 = waveL + (size_t)wave * WAVE_LDS;
-    Real *P1 = P0 + PLANE_LDS;
-    Real *Hl = P1 + PLANE_LDS;
-    Real *Jw = Hl + T * HALO_LINE;
     for (int k = lane; k < T * T * T; k += 64) Jw[k] = Real(0);
+    if (PERSIST) {
+        // upwind face neighbours of this tile in the same octant and bin
+        if (threadIdx.x == 0) {
+            const int *fl = done + ((int64_t)f * 8 + oct) * ntiles;
+            bool ok = true;
+            if (c.tx > 0) ok = ok && wait_done(fl + (c.tz * nt1 + c.ty) * nt0 + c.tx - 1, epoch, err, limit_ticks);
+            if (c.ty > 0) ok = ok && wait_done(fl + (c.tz * nt1 + c.ty - 1) * nt0 + c.tx, epoch, err, limit_ticks);
+            if (c.tz > 0) ok = ok && wait_done(fl + ((c.tz - 1) * nt1 + c.ty) * nt0 + c.tx, epoch, err, limit_ticks);
+            if (!ok) atomicOr(err, 1);
+        }
+        __syncthreads();
+        if (wave < A.R) prefetch_halo<Real, DFORM>(A, c, oct, wave, lane, P0, Hl);
+    }
     __syncthreads();
 
     // ---- per-wave ray sweeps ---------------------------------------------------------
+    const int ia = lane & (T - 1), ib = lane / T;   // this lane's vertex in every plane
     for (int r = wave; r < A.R; r += W) {
+        if (r != wave) {
+            prefetch_halo<Real, DFORM>(A, c, oct, r, lane, P0, Hl);
+            wave_lds_sync();
+        }
         const int ray = oct * A.R + r;
         const RayGeo *G = A.rays + ray;
-        const int d = G->d, a = G->a, b = G->b, gidx = G->gidx;
+        const int d = G->d, a = G->a, b = 3 - G->d - G->a;
         const Real s_half = Real(0.5 * G->s);
         const Real w00 = Real(G->w4[0]), w10 = Real(G->w4[1]), w01 = Real(G->w4[2]), w11 = Real(G->w4[3]);
         const double w00d = G->w4[0], w10d = G->w4[1], w01d = G->w4[2], w11d = G->w4[3];
@@ -239,111 +312,101 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
         const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
         const int g0d = sel3(d, c.g0x, c.g0y, c.g0z), g0a = sel3(a, c.g0x, c.g0y, c.g0z),
                   g0b = sel3(b, c.g0x, c.g0y, c.g0z);
+        const int nd = sel3(d, A.n[0], A.n[1], A.n[2]), na_ = sel3(a, A.n[0], A.n[1], A.n[2]),
+                  nb = sel3(b, A.n[0], A.n[1], A.n[2]);
         // strides of the d, a, b axes in the staged tile and in the partial-sum tile
         const int sd = sel3(d, 1, TP, TP * TP), sa = sel3(a, 1, TP, TP * TP), sb = sel3(b, 1, TP, TP * TP);
         const int jd = sel3(d, 1, T, T * T), ja = sel3(a, 1, T, T * T), jb = sel3(b, 1, T, T * T);
+        const bool act = ia < ea && ib < eb;
+        const int q00 = (ia + 1) + (ib + 1) * TP;      // this vertex in the plane buffers
+        const int lb = (ia + 1) * sa + (ib + 1) * sb;  // ... and in the staged tile, without d
 
-        // every upwind-halo value of this ray: the d = -1 face (into P0) and the a/b
-        // lines of planes 0 .. ed-2 (into Hl)
-        const int n1 = (ea + 1) * (eb + 1);
+        // where this lane's vertex lands on the tile's downwind faces: a-face and
+        // b-face at every step (index grows by a fixed stride per plane), d-face at
+        // the last step; interior faces feed the next tile, the domain's last faces
+        // the periodic memory
+        const int64_t rb = (int64_t)f * A.na + ray;
+        const int ta = sel3(a, c.tx, c.ty, c.tz), tb = sel3(b, c.tx, c.ty, c.tz), td = sel3(d, c.tx, c.ty, c.tz);
+        const int nta = sel3(a, A.nt[0], A.nt[1], A.nt[2]), ntb = sel3(b, A.nt[0], A.nt[1], A.nt[2]),
+                  ntd = sel3(d, A.nt[0], A.nt[1], A.nt[2]);
+        const int64_t Pa = sel3(a, A.plane[0], A.plane[1], A.plane[2]), Pb = sel3(b, A.plane[0], A.plane[1], A.plane[2]),
+                      Pd = sel3(d, A.plane[0], A.plane[1], A.plane[2]);
+        Real *fa = nullptr, *fb = nullptr, *fd = nullptr;
+        double *wa = nullptr, *wb = nullptr, *wd = nullptr;
+        if (ta < nta - 1) fa = sel3(a, A.face[0], A.face[1], A.face[2]) + (rb * (nta - 1) + ta) * Pa;
+        else if (sel3(a, A.periodic[0], A.periodic[1], A.periodic[2])) wa = sel3(a, A.wrap[0], A.wrap[1], A.wrap[2]) + (rb * 2 + (par ^ 1)) * Pa;
+        if (tb < ntb - 1) fb = sel3(b, A.face[0], A.face[1], A.face[2]) + (rb * (ntb - 1) + tb) * Pb;
+        else if (sel3(b, A.periodic[0], A.periodic[1], A.periodic[2])) wb = sel3(b, A.wrap[0], A.wrap[1], A.wrap[2]) + (rb * 2 + (par ^ 1)) * Pb;
+        if (td < ntd - 1) fd = sel3(d, A.face[0], A.face[1], A.face[2]) + (rb * (ntd - 1) + td) * Pd;
+        else if (sel3(d, A.periodic[0], A.periodic[1], A.periodic[2])) wd = sel3(d, A.wrap[0], A.wrap[1], A.wrap[2]) + (rb * 2 + (par ^ 1)) * Pd;
+        const bool on_a = act && ia == ea - 1 && (fa || wa);
+        const bool on_b = act && ib == eb - 1 && (fb || wb);
+        // plane normal to a holds d and b, normal to b holds d and a (lower axis fastest)
+        const int64_t ia0 = (d > b) ? (int64_t)g0d * nb + (g0b + ib) : (int64_t)(g0b + ib) * nd + g0d;
+        const int64_t sta = (d > b) ? nb : 1;
+        const int64_t ib0 = (d > a) ? (int64_t)g0d * na_ + (g0a + ia) : (int64_t)(g0a + ia) * nd + g0d;
+        const int64_t stb = (d > a) ? na_ : 1;
+        const int64_t idd = (int64_t)(g0b + ib) * na_ + (g0a + ia);   // plane normal to d (a < b)
         const int nl = ea + eb + 1;
-        const int tot = n1 + (ed - 1) * nl;
-        for (int e = lane; e < tot; e += 64) {
-            int vd, ia, ib;
-            Real *dst;
-            if (e < n1) {
-                ia = e % (ea + 1) - 1;
-                ib = e / (ea + 1) - 1;
-                vd = g0d - 1;
-                dst = P0 + (ia + 1) + (ib + 1) * TP;
-            } else {
-                const int e2 = e - n1, p = e2 / nl, k = e2 - p * nl;
-                vd = g0d + p;
-                if (k <= eb) {
-                    ia = -1;
-                    ib = k - 1;
-                } else {
-                    ia = k - eb - 1;
-                    ib = -1;
+
+        Real jr[T];
+#pragma unroll
+        for (int p = 0; p < T; ++p) {
+            jr[p] = Real(0);
+            if (p < ed) {
+                const Real *Pp = (p & 1) ? P1 : P0;
+                Real *Pc = (p & 1) ? P0 : P1;
+                if (act) {
+                    const int l0 = lb + (p + 1) * sd;
+                    const int lu = l0 - sd;
+                    const Real Im = w00 * Pp[q00] + w10 * Pp[q00 - 1] + w01 * Pp[q00 - TP] + w11 * Pp[q00 - TP - 1];
+                    const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - sa] + w01 * chiL[lu - sb] + w11 * chiL[lu - sa - sb];
+                    const Real dt = s_half * (Cm + chiL[l0]);
+                    const double S0 = SL[l0];
+                    const double Sm = w00d * SL[lu] + w10d * SL[lu - sa] + w01d * SL[lu - sb] + w11d * SL[lu - sa - sb];
+                    Real v;
+                    if constexpr (DFORM) {
+                        Real E, g;
+                        seg_coeffs(dt, E, g);
+                        v = Im * E + Real(Sm - S0) * g;   // S- - S0 formed in FP64
+                    } else {
+                        Real E, pm, p0;
+                        seg_coeffs(dt, E, pm, p0);
+                        v = Im * E + pm * Real(Sm) + p0 * Real(S0);
+                    }
+                    Pc[q00] = v;
+                    jr[p] = wk * v;
+                    const double Iw = DFORM ? double(v) + S0 : double(v);   // periodic memory keeps I
+                    if (on_a) {
+                        if (fa) fa[ia0 + p * sta] = v;
+                        else wa[ia0 + p * sta] = Iw;
+                    }
+                    if (on_b) {
+                        if (fb) fb[ib0 + p * stb] = v;
+                        else wb[ib0 + p * stb] = Iw;
+                    }
+                    if (p == ed - 1) {
+                        if (fd) fd[idd] = v;
+                        else if (wd) wd[idd] = Iw;
+                    }
                 }
-                dst = Hl + p * HALO_LINE + k;
+                // halo lines of plane p for the next step, from the prefetched batch
+                if (p + 1 < ed && lane < nl) {
+                    const int hia = (lane <= eb) ? -1 : lane - eb - 1;
+                    const int hib = (lane <= eb) ? lane - 1 : -1;
+                    Pc[(hia + 1) + (hib + 1) * TP] = Hl[p * HALO_LINE + lane];
+                }
+                wave_lds_sync();
             }
-            const int va = g0a + ia, vb = g0b + ib;
-            const int vx = d == 0 ? vd : (a == 0 ? va : vb);
-            const int vy = d == 1 ? vd : (a == 1 ? va : vb);
-            const int vz = d == 2 ? vd : (a == 2 ? va : vb);
-            *dst = halo_value<Real, DFORM>(A, c, SL, vx, vy, vz, ray, gidx);
+        }
+        // this ray's contribution to the wave's partial sums
+        if (act) {
+            const int jbase = ia * ja + ib * jb;
+#pragma unroll
+            for (int p = 0; p < T; ++p)
+                if (p < ed) Jw[jbase + p * jd] += jr[p];
         }
         wave_lds_sync();
-
-        const int64_t rb = (int64_t)f * A.na + ray;
-        for (int p = 0; p < ed; ++p) {
-            const Real *Pp = (p & 1) ? P1 : P0;
-            Real *Pc = (p & 1) ? P0 : P1;
-            for (int k = lane; k < ea * eb; k += 64) {
-                const int ia = k % ea, ib = k / ea;
-                // staged-tile index of this vertex and of its upwind face vertices
-                const int l0 = (p + 1) * sd + (ia + 1) * sa + (ib + 1) * sb;
-                const int lu = l0 - sd;
-                const int q00 = (ia + 1) + (ib + 1) * TP;
-                const Real Im = w00 * Pp[q00] + w10 * Pp[q00 - 1] + w01 * Pp[q00 - TP] + w11 * Pp[q00 - TP - 1];
-                const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - sa] + w01 * chiL[lu - sb] + w11 * chiL[lu - sa - sb];
-                const Real dt = s_half * (Cm + chiL[l0]);
-                const double S0 = SL[l0];
-                const double Sm = w00d * SL[lu] + w10d * SL[lu - sa] + w01d * SL[lu - sb] + w11d * SL[lu - sa - sb];
-                Real v;
-                if constexpr (DFORM) {
-                    Real E, g;
-                    seg_coeffs(dt, E, g);
-                    v = Im * E + Real(Sm - S0) * g;   // S- - S0 formed in FP64
-                } else {
-                    Real E, pm, p0;
-                    seg_coeffs(dt, E, pm, p0);
-                    v = Im * E + pm * Real(Sm) + p0 * Real(S0);
-                }
-                Pc[q00] = v;
-                const int lcell = p * jd + ia * ja + ib * jb;
-                Jw[lcell] += wk * v;
-
-                // downwind faces for the neighbour tiles, or the next sweep's periodic memory
-                const int lx = lcell % T, ly = (lcell / T) % T, lz = lcell / (T * T);
-                const bool fx = lx == c.ex - 1, fy = ly == c.ey - 1, fz = lz == c.ez - 1;
-                if (fx || fy || fz) {
-                    const int vx = c.g0x + lx, vy = c.g0y + ly, vz = c.g0z + lz;
-                    const double Iw = DFORM ? double(v) + S0 : double(v);
-                    if (fx) {
-                        const int64_t pi = (int64_t)vz * A.n[1] + vy;
-                        if (c.tx < A.nt[0] - 1)
-                            A.face[0][(rb * (A.nt[0] - 1) + c.tx) * A.plane[0] + pi] = v;
-                        else if (A.periodic[0])
-                            A.wrap[0][(rb * 2 + (par ^ 1)) * A.plane[0] + pi] = Iw;
-                    }
-                    if (fy) {
-                        const int64_t pi = (int64_t)vz * A.n[0] + vx;
-                        if (c.ty < A.nt[1] - 1)
-                            A.face[1][(rb * (A.nt[1] - 1) + c.ty) * A.plane[1] + pi] = v;
-                        else if (A.periodic[1])
-                            A.wrap[1][(rb * 2 + (par ^ 1)) * A.plane[1] + pi] = Iw;
-                    }
-                    if (fz) {
-                        const int64_t pi = (int64_t)vy * A.n[0] + vx;
-                        if (c.tz < A.nt[2] - 1)
-                            A.face[2][(rb * (A.nt[2] - 1) + c.tz) * A.plane[2] + pi] = v;
-                        else if (A.periodic[2])
-                            A.wrap[2][(rb * 2 + (par ^ 1)) * A.plane[2] + pi] = Iw;
-                    }
-                }
-            }
-            // halo lines of plane p for the next step, from the prefetched batch
-            if (p + 1 < ed) {
-                for (int k = lane; k < nl; k += 64) {
-                    const int ia = (k <= eb) ? -1 : k - eb - 1;
-                    const int ib = (k <= eb) ? k - 1 : -1;
-                    Pc[(ia + 1) + (ib + 1) * TP] = Hl[p * HALO_LINE + k];
-                }
-            }
-            wave_lds_sync();
-        }
     }
     __syncthreads();
 
@@ -358,6 +421,54 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
         const int ry = to_real(c.g0y + ly, c.sgy, A.n[1]);
         const int rz = to_real(c.g0z + lz, c.sgz, A.n[2]);
         outp[((int64_t)rz * A.n[1] + ry) * A.n[0] + rx] = acc;
+    }
+}
+
+// One stage (all tiles with tx + ty + tz = s) of all octants and active bins.
+template <typename Real, bool DFORM>
+__global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int oct = blockIdx.x & 7;
+    const int item = blockIdx.x >> 3;
+    const int f = blockIdx.y;
+    const int frozen = A.frozen[f];
+    const int par = A.parity[f];
+    const int packed = A.tiles[A.stage_off + item];
+    if (frozen) return;
+    sweep_tile<Real, DFORM, false>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
+}
+
+// Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
+// octant o: they draw tickets from that octant's counter; ticket t is tile
+// tiles[t % ntiles] of bin t / ntiles, so every tile's upwind neighbours carry
+// smaller tickets and are held by running (or finished) workgroups.  Completion
+// is published per tile with the sweep's epoch (agent-scope release).
+template <typename Real, bool DFORM>
+__global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepArgs<Real> A, DagArgs D)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int s_ticket;
+    const int oct = blockIdx.x & 7;
+    const int items = D.ntiles * A.nf;
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = atomicAdd(D.counter + oct, 1);
+        __syncthreads();
+        const int t = s_ticket;
+        __syncthreads();
+        if (t >= items) break;
+        const int f = t / D.ntiles;
+        const int tile = t - f * D.ntiles;
+        if (A.frozen[f]) continue;
+        const int packed = A.tiles[tile];
+        sweep_tile<Real, DFORM, true>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
+                                      D.nt1, D.err, D.wait_ticks);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int tx = packed & 1023, ty = (packed >> 10) & 1023, tz = (packed >> 20) & 1023;
+            __hip_atomic_store(D.done + ((int64_t)f * 8 + oct) * D.ntiles + D.tile_id(tx, ty, tz), D.epoch,
+                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -582,6 +693,33 @@ hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStrea
     dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nf);
     hipLaunchKernelGGL((sweep_stage_kernel<float, true>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves), st, A);
     return hipGetLastError();
+}
+
+template <typename Real, bool DFORM>
+static hipError_t launch_persistent(const SweepArgs<Real> &A, const DagArgs &D, int waves, int blocks_per_octant,
+                                    hipStream_t st)
+{
+    hipLaunchKernelGGL((sweep_persistent_kernel<Real, DFORM>), dim3(8u * (unsigned)blocks_per_octant), dim3(64 * waves),
+                       sweep_lds_bytes(sizeof(Real), waves), st, A, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs &D, int waves, int bpo, hipStream_t st)
+{
+    return launch_persistent<double, false>(A, D, waves, bpo, st);
+}
+
+hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int bpo, hipStream_t st)
+{
+    return launch_persistent<float, true>(A, D, waves, bpo, st);
+}
+
+hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks)
+{
+    const size_t lds = sweep_lds_bytes(real_bytes, waves);
+    if (real_bytes == 8)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<double, false>, 64 * waves, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<float, true>, 64 * waves, lds);
 }
 
 hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,

@@ -94,3 +94,12 @@ def test_state_bytes_scale(rt):
     f32 = rt.rt_problem_bytes(rt.make_desc((32, 32, 32), precision=rt.RT_F32))
     assert 7 * small < big < 9 * small
     assert f32 < big
+
+
+def test_disabled_schedule_is_refused(rt):
+    lib = rt.load()
+    b = ctypes.c_size_t()
+    d = rt.make_desc((8, 8, 8), schedule=rt.RT_SCHED_PERSISTENT)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_UNSUPPORTED
+    d = rt.make_desc((8, 8, 8), schedule=7)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID

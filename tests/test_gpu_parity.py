@@ -46,14 +46,14 @@ def _fixed_faces(wl, seed=3):
     return faces
 
 
-def _pair(env, oracle_mod, wl, precision, fixed=None):
+def _pair(env, oracle_mod, wl, precision, fixed=None, schedule=0):
     rt, torch = env
     o = oracle_mod
     op = o.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, h=wl.h, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi,
                    w_nu=wl.w_nu, fixed=fixed)
     dfix = None if fixed is None else [None if a is None else _dev(torch, a) for a in fixed]
     gp = rt.Problem(wl.shape, nf=wl.nf, h=wl.h, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi,
-                    precision=precision, w_nu=wl.w_nu, I_fixed=dfix)
+                    precision=precision, w_nu=wl.w_nu, I_fixed=dfix, schedule=schedule)
     gp._dfix = dfix
     gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
     return op, gp
@@ -71,17 +71,29 @@ CASES = [
 ]
 
 
+SCHEDULES = {"stages": 1, "persistent": 2}
+PERSISTENT_SKIP = ("persistent sweep schedule disabled: its first device run did not complete and the cause "
+                   "is not established (the library refuses the schedule)")
+
+
+def _skip_disabled(schedule):
+    if schedule == "persistent":
+        pytest.skip(PERSISTENT_SKIP)
+
+
 @pytest.mark.parametrize("case", range(len(CASES)))
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_formal_solve_parity(env, oracle_mod, case, precision):
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_formal_solve_parity(env, oracle_mod, case, precision, schedule):
     """Two consecutive formal solutions (the second reads the first one's periodic
     memory) on random S; J and Lambda* against the oracle."""
+    _skip_disabled(schedule)
     rt, torch = env
     shape, n_mu, lo, hi, h, nf = CASES[case]
     wl = W.random_problem(shape, nf=nf, seed=100 + case, n_mu=n_mu, bc_lo=lo, bc_hi=hi, h=h)
     fixed = _fixed_faces(wl) if F in lo + hi else None
     prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
-    op, gp = _pair(env, oracle_mod, wl, prec, fixed)
+    op, gp = _pair(env, oracle_mod, wl, prec, fixed, schedule=SCHEDULES[schedule])
     rng = np.random.default_rng(7 + case)
     tol = TOL64 if precision == "f64" else TOL32
     n = wl.chi.size
@@ -99,12 +111,14 @@ def test_formal_solve_parity(env, oracle_mod, case, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_ali_fixed_iterations_parity(env, oracle_mod, precision):
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_ali_fixed_iterations_parity(env, oracle_mod, precision, schedule):
     """Three Jacobi iterations from S = B on a multi-bin random problem."""
+    _skip_disabled(schedule)
     rt, torch = env
     wl = W.random_problem((17, 10, 12), nf=3, seed=11, n_mu=4, eps_range=(1e-3, 1.0))
     prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
-    op, gp = _pair(env, oracle_mod, wl, prec)
+    op, gp = _pair(env, oracle_mod, wl, prec, schedule=SCHEDULES[schedule])
     ref = op.ali(fixed_iters=3)
     n = wl.chi.size
     S = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -119,10 +133,12 @@ def test_ali_fixed_iterations_parity(env, oracle_mod, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_ali_converged_parity(env, oracle_mod, precision):
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_ali_converged_parity(env, oracle_mod, precision, schedule):
     """Scattering atmosphere (the 128^3 workload's structure at 24^3, two bins with
     different eps): Jacobi ALI to max|dS/S| <= 1e-6 with per-bin stopping.  FP64 must
     take the same iteration counts and agree to 1e-12; FP32 must agree to 2e-5."""
+    _skip_disabled(schedule)
     rt, torch = env
     base = W.scattering(24, eps=1e-2, tau_bottom=1e3)
     wl2 = W.scattering(24, seed=77, eps=1e-1, tau_bottom=1e3)
@@ -131,7 +147,7 @@ def test_ali_converged_parity(env, oracle_mod, precision):
     B = np.concatenate([base.B, wl2.B])
     wl = W.Workload("scat2", base.shape, 4, chi, eps, B, np.ones(2), delta_c=1e-6)
     prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
-    op, gp = _pair(env, oracle_mod, wl, prec)
+    op, gp = _pair(env, oracle_mod, wl, prec, schedule=SCHEDULES[schedule])
     ref = op.ali(delta_c=1e-6, max_iter=5000, per_bin_stop=True)
     n = wl.chi.size
     S = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -168,13 +184,15 @@ def test_workload_plain_full_size(env, oracle_mod):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_workload_scattering_full_size(env, oracle_mod, precision):
-    """The 128^3 scattering workload at full size, in the launch configuration the
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_workload_scattering_full_size(env, oracle_mod, precision, schedule):
+    """The 128^3 scattering workload at full size, in the launch configurations the
     benchmark times: two Jacobi iterations from S = B against the oracle."""
+    _skip_disabled(schedule)
     rt, torch = env
     wl = W.scattering()
     prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
-    op, gp = _pair(env, oracle_mod, wl, prec)
+    op, gp = _pair(env, oracle_mod, wl, prec, schedule=SCHEDULES[schedule])
     ref = op.ali(fixed_iters=2)
     n = wl.chi.size
     S = torch.empty(n, dtype=torch.float64, device="cuda")
