@@ -177,7 +177,7 @@ typedef struct {
     double *J_int;     /* device [cells]: sum_nu w_nu J_nu, or NULL */
     double *H_int;     /* device [3][cells] or NULL */
     double *K_int;     /* device [6][cells] or NULL */
-    double *f_int;     /* device [6][cells]: K_int/J_int (0 where J_int = 0), or NULL */
+    double *f_int;     /* device [6][cells]: K_int/J_int (0 where J_int = 0), or NULL; needs J_int, K_int */
     double *Q_int;     /* device [cells]: sum_nu w_nu Q_nu, or NULL */
     double *heating;   /* host scalar: sum over cells of Q_int dV, or NULL (synchronises) */
 } rt_moments_out;
@@ -185,9 +185,12 @@ typedef struct {
 /*
  * rt_moments -- one formal solution on S with moments (section 3.2, eqs.
  * Jsum/Hsum/Ksum), the Eddington tensor f = K/J and the heating rate of section 4:
- * Q_nu = 4 pi eps chi (J - B) where chi dx_min <= 1, else -4 pi div H (second-order
+ * Q_nu = 4 pi eps chi (J - B) where chi min(dx,dy,dz) <= 1, else -4 pi div H (second-order
  * differences, wrapped on periodic axes, one-sided at other faces).  Frequency
- * integrals use w_nu.  Periodic ghosts as in rt_formal_solve.
+ * integrals use w_nu, bins added in order.  Every output pointer may be NULL; f_int
+ * needs J_int and K_int.  Periodic ghosts as in rt_formal_solve (the periodic memory
+ * advances by one sweep).  Asynchronous unless heating is requested (then the stream
+ * is synchronised to return the FP64 sum over cells of Q_int dV).
  */
 rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream);
 

@@ -259,6 +259,15 @@ struct rt_problem {
     int epoch = 0;                     // sweeps run by the persistent kernel
     uint64_t wait_ticks = 0;           // 20 ms in device wall-clock ticks
     int *dag_counter = nullptr;        // [8] ticket counters
+    // moments epilogue scratch (allocated on first use)
+    int mom_nfc = 0;                   // bins per moments chunk
+    void *mom_part = nullptr;          // Real [8][10][mom_nfc][cells]
+    double *mom_tmp = nullptr;         // [10][mom_nfc][cells]
+    double *mom_q = nullptr;           // [mom_nfc][cells]
+    double *mom_qint = nullptr;        // [cells] when the caller does not ask for Q_int
+    double *mom_wnu = nullptr;         // [nf]
+    double *mom_sum = nullptr;         // [1024 + 1]
+    double *h_sum = nullptr;           // pinned scalar
     int *dag_done = nullptr;           // [nf][8][ntiles] completion epochs
     int *h_flags = nullptr;            // pinned host copy of flags
     int *h_frozen = nullptr;           // pinned host copy of frozen
@@ -396,6 +405,8 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
     A.B = p->B;
     for (int k = 0; k < 6; ++k) A.fixed[k] = p->desc.I_fixed[k];
     A.part = static_cast<Real *>(p->part);
+    A.f0 = 0;
+    A.nfc = p->nf;
     A.tiles = p->d_tiles;
     A.frozen = p->frozen;
     A.parity = p->parity;
@@ -408,7 +419,7 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
 int sweep_waves(int R, bool f32, size_t lds_limit)
 {
     int w = std::min(R, kMaxWaves);
-    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w) > lds_limit) --w;
+    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w, 1) > lds_limit) --w;
     return w;
 }
 
@@ -434,17 +445,33 @@ rt_status collect_timing(rt_problem *p)
 // One formal solution over every active bin: the tile stages in order.  With
 // timed set, each stage launch is bracketed by events (active_bins then counts the
 // bins that do work, for the update tally).
+// Sweep options beyond the plain formal solution: the moments mode (nq = 10) over a
+// chunk of bins into its own partial-sum buffer with one wave per workgroup.
+struct SweepMode {
+    int nq = 1;
+    int f0 = 0;
+    int nfc = -1;
+    void *part = nullptr;
+    int waves = 0;
+};
+
 template <typename Real>
-rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed = false, int active_bins = 0)
+rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed = false, int active_bins = 0,
+                    SweepMode mode = SweepMode())
 {
     SweepArgs<Real> A = sweep_args<Real>(p, S);
+    if (mode.nfc > 0) {
+        A.f0 = mode.f0;
+        A.nfc = mode.nfc;
+    }
+    if (mode.part) A.part = static_cast<Real *>(mode.part);
     if (p->cold) {
         HIP_TRY(launch_periodic_cold<Real>(A, st));
         p->cold = false;
     }
-    timed = timed && p->prof && !p->prof_pending;
-    const int W = p->waves;
-    if (p->persistent) {
+    timed = timed && p->prof && !p->prof_pending && mode.nq == 1;
+    const int W = mode.waves > 0 ? mode.waves : p->waves;
+    if (p->persistent && mode.nq == 1) {
         DagArgs D;
         D.counter = p->dag_counter;
         D.done = p->dag_done;
@@ -474,9 +501,9 @@ rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed =
         A.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
         if (timed) HIP_TRY(hipEventRecord(p->ev[2 * s], st));
         if constexpr (sizeof(Real) == 8)
-            HIP_TRY(launch_sweep_stage_f64(A, W, st));
+            HIP_TRY(launch_sweep_stage_f64(A, W, mode.nq, st));
         else
-            HIP_TRY(launch_sweep_stage_f32(A, W, st));
+            HIP_TRY(launch_sweep_stage_f32(A, W, mode.nq, st));
         if (timed) HIP_TRY(hipEventRecord(p->ev[2 * s + 1], st));
     }
     if (timed) {
@@ -555,6 +582,7 @@ rt_status rt_problem_destroy(rt_problem *p)
     if (!p) return RT_OK;
     for (void *v : p->allocs) (void)hipFree(v);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
+    if (p->h_sum) (void)hipHostFree(p->h_sum);
     if (p->h_frozen) (void)hipHostFree(p->h_frozen);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     delete p;
@@ -680,10 +708,10 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
         (void)hipGetLastError();
         p->wait_ticks = (uint64_t)khz * 20;   // 20 ms
     }
-    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves) > (size_t)lds_limit) {
+    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1) > (size_t)lds_limit) {
         rt_problem_destroy(p);
         return fail(RT_E_UNSUPPORTED, "sweep needs %zu bytes of LDS, device allows %d",
-                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves), lds_limit);
+                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1), lds_limit);
     }
     hipError_t e = hipMemcpy(p->d_rays, p->rays.data(), sizeof(RayGeo) * na, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice);
@@ -740,7 +768,7 @@ rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lam
         HIP_TRY(launch_partial_sum<float>(static_cast<float *>(p->part), S, 1, p->nf, p->cells, nullptr, J, st));
     else
         HIP_TRY(launch_partial_sum<double>(static_cast<double *>(p->part), S, 0, p->nf, p->cells, nullptr, J, st));
-    HIP_TRY(launch_flip_parity(p->parity, p->frozen, p->nf, st));
+    HIP_TRY(launch_flip_parity(p->parity, p->frozen, 0, p->nf, st));
     if (lambda_star) HIP_TRY(hipMemcpyAsync(lambda_star, p->lam, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     return RT_OK;
 }
@@ -873,11 +901,90 @@ rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out)
 
 rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream)
 {
-    (void)S;
-    (void)out;
-    (void)stream;
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
-    return fail(RT_E_UNSUPPORTED, "rt_moments is not built yet");
+    if (!S || !out) return fail(RT_E_INVALID, "S and out are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool want_int = out->J_int || out->H_int || out->K_int || out->f_int || out->Q_int || out->heating;
+    if (!(out->J || out->H || out->K || want_int)) return RT_OK;
+    const int64_t cells = p->cells;
+    const size_t rs = p->f32 ? sizeof(float) : sizeof(double);
+
+    // scratch: bins are processed in chunks so the per-octant moment partials fit
+    if (!p->mom_part) {
+        const size_t per_bin = (size_t)cells * (8 * 10 * rs + 11 * sizeof(double));
+        const size_t budget = (size_t)4 << 30;
+        p->mom_nfc = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->nf, budget / std::max<size_t>(per_bin, 1)));
+        rt_status a;
+        unsigned char *pb = nullptr;
+        if ((a = dalloc(p, &pb, (size_t)8 * 10 * p->mom_nfc * cells * rs)) != RT_OK) return a;
+        p->mom_part = pb;
+        if ((a = dalloc(p, &p->mom_tmp, (size_t)10 * p->mom_nfc * cells)) != RT_OK) return a;
+        if ((a = dalloc(p, &p->mom_q, (size_t)p->mom_nfc * cells)) != RT_OK) return a;
+        if ((a = dalloc(p, &p->mom_qint, (size_t)cells)) != RT_OK) return a;
+        if ((a = dalloc(p, &p->mom_wnu, (size_t)p->nf)) != RT_OK) return a;
+        if ((a = dalloc(p, &p->mom_sum, (size_t)1025)) != RT_OK) return a;
+        if (hipHostMalloc((void **)&p->h_sum, sizeof(double), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p->h_sum = nullptr;
+            return fail(RT_E_OOM, "pinned host allocation failed");
+        }
+        HIP_TRY(hipMemcpy(p->mom_wnu, p->w_nu.data(), sizeof(double) * p->nf, hipMemcpyHostToDevice));
+    }
+    MomConst mc{};
+    mc.m[0] = 1.0;
+    for (const RayGeo &g : p->rays) {
+        const double *m = g.mu;
+        mc.m[1] += g.wk * m[0];
+        mc.m[2] += g.wk * m[1];
+        mc.m[3] += g.wk * m[2];
+        mc.m[4] += g.wk * m[0] * m[0];
+        mc.m[5] += g.wk * m[1] * m[1];
+        mc.m[6] += g.wk * m[2] * m[2];
+        mc.m[7] += g.wk * m[0] * m[1];
+        mc.m[8] += g.wk * m[0] * m[2];
+        mc.m[9] += g.wk * m[1] * m[2];
+    }
+    const double h[3] = {p->desc.dx, p->desc.dy, p->desc.dz};
+    double *Qint = out->Q_int ? out->Q_int : (out->heating ? p->mom_qint : nullptr);
+    HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
+    for (int f0 = 0; f0 < p->nf; f0 += p->mom_nfc) {
+        const int cnt = std::min(p->mom_nfc, p->nf - f0);
+        SweepMode mode;
+        mode.nq = 10;
+        mode.f0 = f0;
+        mode.nfc = cnt;
+        mode.part = p->mom_part;
+        mode.waves = 1;
+        rt_status s = p->f32 ? run_sweep<float>(p, S, st, false, 0, mode) : run_sweep<double>(p, S, st, false, 0, mode);
+        if (s != RT_OK) return s;
+        HIP_TRY(launch_flip_parity(p->parity, p->frozen, f0, cnt, st));
+        if (p->f32)
+            HIP_TRY(launch_moments_combine<float>(static_cast<float *>(p->mom_part), S, 1, f0, cnt, p->nf, cells, mc,
+                                                  out->J, out->H, out->K, p->mom_tmp, st));
+        else
+            HIP_TRY(launch_moments_combine<double>(static_cast<double *>(p->mom_part), S, 0, f0, cnt, p->nf, cells, mc,
+                                                   out->J, out->H, out->K, p->mom_tmp, st));
+        if (Qint) HIP_TRY(launch_moments_q(p->mom_tmp, f0, cnt, p->n, h, p->periodic, p->chi64, p->eps, p->B, p->mom_q, st));
+        if (want_int) {
+            const bool needK = out->K_int || out->f_int;
+            double *Jt = (out->J_int || out->f_int) ? out->J_int : nullptr;
+            HIP_TRY(launch_moments_integrate(p->mom_tmp, p->mom_q, p->mom_wnu, f0, cnt, cells, f0 == 0, Jt, out->H_int,
+                                             needK ? out->K_int : nullptr, Qint, st));
+        }
+    }
+    if (out->f_int) {
+        if (!out->J_int || !out->K_int) return fail(RT_E_INVALID, "f_int needs J_int and K_int buffers");
+        HIP_TRY(launch_eddington(out->J_int, out->K_int, cells, out->f_int, st));
+    }
+    if (out->heating) {
+        const int nblk = (int)std::min<int64_t>(1024, (cells + 255) / 256);
+        HIP_TRY(launch_sum(Qint, cells, h[0] * h[1] * h[2], p->mom_sum, nblk, p->mom_sum + 1024, st));
+        HIP_TRY(hipMemcpyAsync(p->h_sum, p->mom_sum + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        *out->heating = *p->h_sum;
+    }
+    return RT_OK;
 }
 
 }  // extern "C"

@@ -42,7 +42,8 @@ struct SweepArgs {
     Real *face[3];            // [nf][na][nt_q - 1][plane_q]: downwind faces of interior tiles
                               // (I in the plain form, D = I - S in the difference form)
     double *wrap[3];          // [nf][na][2][plane_q]: periodic memory (I), slot = parity
-    Real *part;               // [8][nf][cells] per-octant partial sums of w I (or w D)
+    Real *part;               // [8][nq][nfc][cells] per-octant partial sums of w I (or w D)
+    int f0, nfc;              // bins f0 .. f0 + nfc - 1 are swept by this call
     const int *tiles;         // packed (tx | ty << 10 | tz << 20), sorted by tx + ty + tz
     int stage_off, stage_cnt;
     const int *frozen;        // [nf]
@@ -77,10 +78,11 @@ struct AliCtl {
 constexpr int kUpdateBlocks = 1024;  // update-kernel blocks per bin (grid-stride)
 
 // Kernel launchers (rt_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, hipStream_t st);
-hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStream_t st);
+// nq = 1: partial sums of w I (or w D); nq = 10: also w mu I and w mu mu I (moments)
+hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq, hipStream_t st);
+hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, hipStream_t st);
 // dynamic LDS bytes of one sweep workgroup with the given number of waves
-size_t sweep_lds_bytes(int real_bytes, int waves);
+size_t sweep_lds_bytes(int real_bytes, int waves, int nq);
 hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs &D, int waves, int blocks_per_octant,
                                        hipStream_t st);
 hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int blocks_per_octant,
@@ -105,7 +107,23 @@ hipError_t launch_ali_update(const Real *part, int dform, int nf, int64_t cells,
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,
                                hipStream_t st);
-hipError_t launch_flip_parity(int *parity, const int *frozen, int nf, hipStream_t st);
+hipError_t launch_flip_parity(int *parity, const int *frozen, int f0, int cnt, hipStream_t st);
+
+// Angle-set sums added to the moments of the difference form: m[0] = 1 (J = S + sum w D),
+// m[1..3] = sum w mu_i, m[4..9] = sum w mu_i mu_j (xx yy zz xy xz yz).
+struct MomConst {
+    double m[10];
+};
+template <typename Real>
+hipError_t launch_moments_combine(const Real *part, const double *S, int dform, int f0, int nfc, int nf, int64_t cells,
+                                  const MomConst &mc, double *J, double *H, double *K, double *tmp, hipStream_t st);
+hipError_t launch_moments_q(const double *tmp, int f0, int nfc, const int n[3], const double h[3], const int per[3],
+                            const double *chi, const double *eps, const double *B, double *Qt, hipStream_t st);
+hipError_t launch_moments_integrate(const double *tmp, const double *Qt, const double *w_nu, int f0, int nfc,
+                                    int64_t cells, int first, double *J_int, double *H_int, double *K_int,
+                                    double *Q_int, hipStream_t st);
+hipError_t launch_eddington(const double *J_int, const double *K_int, int64_t cells, double *f_int, hipStream_t st);
+hipError_t launch_sum(const double *x, int64_t n, double scale, double *partial, int nblk, double *out, hipStream_t st);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t st);
 hipError_t launch_warm_start(const double *B, const double *eps, const double *J, double *S, int64_t n,
                              hipStream_t st);

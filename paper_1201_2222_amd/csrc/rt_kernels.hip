@@ -27,7 +27,9 @@ constexpr int TP = T + 1;            // tile plus one upwind halo layer
 constexpr int TILE_LDS = TP * TP * TP;
 constexpr int PLANE_LDS = TP * TP;
 constexpr int HALO_LINE = 2 * T + 1; // halo of one plane: T+1 values on the a-line, T on the b-line
-constexpr int WAVE_LDS = 2 * PLANE_LDS + T * HALO_LINE + T * T * T;  // Reals per wave
+// Reals of LDS per wave: two plane buffers, the halo lines, nq partial-sum tiles
+constexpr int wave_lds(int nq) { return 2 * PLANE_LDS + T * HALO_LINE + nq * T * T * T; }
+constexpr int NMOM = 10;             // moments mode: J, H_x,y,z, K_xx,yy,zz,xy,xz,yz
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -229,7 +231,7 @@ __device__ __forceinline__ bool wait_done(const int *flag, int epoch, const int 
 // ray of the octant through it, write the octant's partial sums.  With a non-null
 // dependency block (persistent sweep) the upwind face-neighbour tiles are awaited
 // after the staging loads have been issued and before any face data is read.
-template <typename Real, bool DFORM, bool PERSIST>
+template <typename Real, bool DFORM, bool PERSIST, int NQ>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, int f, int packed, int par,
                                            unsigned char *lds_raw, const int *done, int epoch, int ntiles, int nt0,
                                            int nt1, int *err, uint64_t limit_ticks)
@@ -258,7 +260,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
-    Real *P0 = waveL + (size_t)wave * WAVE_LDS;
+    Real *P0 = waveL + (size_t)wave * wave_lds(NQ);
     Real *P1 = P0 + PLANE_LDS;
     Real *Hl = P1 + PLANE_LDS;
     Real *Jw = Hl + T * HALO_LINE;
@@ -279,7 +281,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         chiL[idx] = chif[cell];
         SL[idx] = Sf[cell];
     }
-    for (int k = lane; k < T * T * T; k += 64) Jw[k] = Real(0);
+    for (int k = lane; k < NQ * T * T * T; k += 64) Jw[k] = Real(0);
     if (PERSIST) {
         // upwind face neighbours of this tile in the same octant and bin
         if (threadIdx.x == 0) {
@@ -349,7 +351,26 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         const int64_t idd = (int64_t)(g0b + ib) * na_ + (g0a + ia);   // plane normal to d (a < b)
         const int nl = ea + eb + 1;
 
+        // weights of this ray in the accumulated quantities: w (J), and in moments
+        // mode also w mu_i (H) and w mu_i mu_j (K)
+        Real cq[NQ];
+        cq[0] = wk;
+        if constexpr (NQ == NMOM) {
+            const double mx = G->mu[0], my = G->mu[1], mz = G->mu[2], wd = G->wk;
+            cq[1] = Real(wd * mx);
+            cq[2] = Real(wd * my);
+            cq[3] = Real(wd * mz);
+            cq[4] = Real(wd * mx * mx);
+            cq[5] = Real(wd * my * my);
+            cq[6] = Real(wd * mz * mz);
+            cq[7] = Real(wd * mx * my);
+            cq[8] = Real(wd * mx * mz);
+            cq[9] = Real(wd * my * mz);
+        }
+        // J: this ray's 8 contributions are held in registers and added once per ray;
+        // moments mode adds its 10 quantities to the wave's LDS tiles at every step
         Real jr[T];
+        const int jbase = ia * ja + ib * jb;
 #pragma unroll
         for (int p = 0; p < T; ++p) {
             jr[p] = Real(0);
@@ -375,7 +396,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
                         v = Im * E + pm * Real(Sm) + p0 * Real(S0);
                     }
                     Pc[q00] = v;
-                    jr[p] = wk * v;
+                    if constexpr (NQ == 1) {
+                        jr[p] = cq[0] * v;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + jbase + p * jd] += cq[q] * v;
+                    }
                     const double Iw = DFORM ? double(v) + S0 : double(v);   // periodic memory keeps I
                     if (on_a) {
                         if (fa) fa[ia0 + p * sta] = v;
@@ -400,8 +426,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             }
         }
         // this ray's contribution to the wave's partial sums
-        if (act) {
-            const int jbase = ia * ja + ib * jb;
+        if (NQ == 1 && act) {
 #pragma unroll
             for (int p = 0; p < T; ++p)
                 if (p < ed) Jw[jbase + p * jd] += jr[p];
@@ -411,32 +436,35 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     __syncthreads();
 
     // ---- fixed-order sum over the waves -> this octant's partial sums --------------
-    Real *outp = A.part + ((int64_t)oct * A.nf + f) * A.cells;
-    for (int k = threadIdx.x; k < T * T * T; k += blockDim.x) {
+    // layout [8][NQ][nfc][cells], bin f stored at f - f0
+    for (int kq = threadIdx.x; kq < NQ * T * T * T; kq += blockDim.x) {
+        const int q = kq / (T * T * T), k = kq - q * T * T * T;
         const int lx = k % T, ly = (k / T) % T, lz = k / (T * T);
         if (lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
-        Real acc = waveL[2 * PLANE_LDS + T * HALO_LINE + k];
-        for (int w = 1; w < W; ++w) acc += waveL[(size_t)w * WAVE_LDS + 2 * PLANE_LDS + T * HALO_LINE + k];
+        Real acc = waveL[2 * PLANE_LDS + T * HALO_LINE + kq];
+        for (int w = 1; w < W; ++w) acc += waveL[(size_t)w * wave_lds(NQ) + 2 * PLANE_LDS + T * HALO_LINE + kq];
         const int rx = to_real(c.g0x + lx, c.sgx, A.n[0]);
         const int ry = to_real(c.g0y + ly, c.sgy, A.n[1]);
         const int rz = to_real(c.g0z + lz, c.sgz, A.n[2]);
+        Real *outp = A.part + (((int64_t)oct * NQ + q) * A.nfc + (f - A.f0)) * A.cells;
         outp[((int64_t)rz * A.n[1] + ry) * A.n[0] + rx] = acc;
     }
 }
 
-// One stage (all tiles with tx + ty + tz = s) of all octants and active bins.
-template <typename Real, bool DFORM>
+// One stage (all tiles with tx + ty + tz = s) of all octants and the active bins
+// f0 .. f0 + nfc - 1.
+template <typename Real, bool DFORM, int NQ>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int oct = blockIdx.x & 7;
     const int item = blockIdx.x >> 3;
-    const int f = blockIdx.y;
+    const int f = A.f0 + blockIdx.y;
     const int frozen = A.frozen[f];
     const int par = A.parity[f];
     const int packed = A.tiles[A.stage_off + item];
     if (frozen) return;
-    sweep_tile<Real, DFORM, false>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
+    sweep_tile<Real, DFORM, false, NQ>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
 // Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
@@ -461,7 +489,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
         const int tile = t - f * D.ntiles;
         if (A.frozen[f]) continue;
         const int packed = A.tiles[tile];
-        sweep_tile<Real, DFORM, true>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
+        sweep_tile<Real, DFORM, true, 1>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
                                       D.nt1, D.err, D.wait_ticks);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -654,10 +682,10 @@ __global__ void __launch_bounds__(256) ali_finalize_kernel(AliCtl ctl, int nf, d
     }
 }
 
-__global__ void flip_parity_kernel(int *parity, const int *frozen, int nf)
+__global__ void flip_parity_kernel(int *parity, const int *frozen, int f0, int cnt)
 {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < nf && !frozen[f]) parity[f] ^= 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < cnt && !frozen[f0 + k]) parity[f0 + k] ^= 1;
 }
 
 __global__ void convert_f32_kernel(const double *src, float *dst, int64_t n)
@@ -672,26 +700,164 @@ __global__ void warm_start_kernel(const double *B, const double *eps, const doub
     if (i < n) S[i] = eps[i] * B[i] + (1.0 - eps[i]) * J[i];
 }
 
+// ---- moments epilogue (section 3.2 eqs. Jsum/Hsum/Ksum, section 4) -------------------
+// Per-octant partials of w I, w mu_i I, w mu_i mu_j I are summed in fixed octant
+// order; the difference form adds S times the angle set's own sums (1, sum w mu_i,
+// sum w mu_i mu_j).  tmp holds [10][nfc][cells] for the Q and integration kernels.
+template <typename Real>
+__global__ void moments_combine_kernel(const Real *part, const double *S, int dform, int f0, int nfc, int nf,
+                                       int64_t cells, MomConst mc, double *J, double *H, double *K, double *tmp)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cells * nfc) return;
+    const int fl = (int)(i / cells);
+    const int64_t c = i - (int64_t)fl * cells;
+    const int f = f0 + fl;
+    const double Sv = dform ? S[(int64_t)f * cells + c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) acc += (double)part[(((int64_t)o * 10 + q) * nfc + fl) * cells + c];
+        if (dform) acc = (q == 0) ? Sv + acc : acc + Sv * mc.m[q];
+        tmp[((int64_t)q * nfc + fl) * cells + c] = acc;
+        if (q == 0 && J) J[(int64_t)f * cells + c] = acc;
+        if (q >= 1 && q <= 3 && H) H[((int64_t)(q - 1) * nf + f) * cells + c] = acc;
+        if (q >= 4 && K) K[((int64_t)(q - 4) * nf + f) * cells + c] = acc;
+    }
+}
+
+// d/dq of a field F at index i along an axis of n points (stride st, spacing h):
+// central, wrapped when periodic, second-order one-sided at other faces.
+__device__ __forceinline__ double axis_deriv(const double *F, int64_t base, int i, int n, int64_t st, double h,
+                                             int periodic)
+{
+    if (n == 1) return 0.0;
+    if (periodic) {
+        const int ip = (i + 1 == n) ? 0 : i + 1, im = (i == 0) ? n - 1 : i - 1;
+        return (F[base + ip * st] - F[base + im * st]) / (2.0 * h);
+    }
+    if (n == 2) return (F[base + 1 * st] - F[base]) / h;
+    if (i == 0) return (-3.0 * F[base] + 4.0 * F[base + st] - F[base + 2 * st]) / (2.0 * h);
+    if (i == n - 1)
+        return (3.0 * F[base + (int64_t)(n - 1) * st] - 4.0 * F[base + (int64_t)(n - 2) * st] +
+                F[base + (int64_t)(n - 3) * st]) / (2.0 * h);
+    return (F[base + (int64_t)(i + 1) * st] - F[base + (int64_t)(i - 1) * st]) / (2.0 * h);
+}
+
+// Q_nu = 4 pi eps chi (J - B) where chi dx_min <= 1, else -4 pi div H.
+__global__ void moments_q_kernel(const double *tmp, int f0, int nfc, int64_t cells, int nx, int ny, int nz, double hx,
+                                 double hy, double hz, int px, int py, int pz, double hmin, const double *chi,
+                                 const double *eps, const double *B, double *Qt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cells * nfc) return;
+    const int fl = (int)(i / cells);
+    const int64_t c = i - (int64_t)fl * cells;
+    const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+    const double *Hx = tmp + ((int64_t)1 * nfc + fl) * cells;
+    const double *Hy = tmp + ((int64_t)2 * nfc + fl) * cells;
+    const double *Hz = tmp + ((int64_t)3 * nfc + fl) * cells;
+    double div = 0.0;
+    div += axis_deriv(Hx, c - x, x, nx, 1, hx, px);
+    div += axis_deriv(Hy, c - (int64_t)y * nx, y, ny, nx, hy, py);
+    div += axis_deriv(Hz, c - (int64_t)z * nx * ny, z, nz, (int64_t)nx * ny, hz, pz);
+    const int64_t g = (int64_t)(f0 + fl) * cells + c;
+    const double fourpi = 4.0 * 3.14159265358979323846;
+    const double J = tmp[((int64_t)0 * nfc + fl) * cells + c];
+    const double q_int = fourpi * eps[g] * chi[g] * (J - B[g]);
+    const double q_dif = -fourpi * div;
+    Qt[(int64_t)fl * cells + c] = (chi[g] * hmin <= 1.0) ? q_int : q_dif;
+}
+
+// Frequency integrals sum_nu w_nu X_nu, bins added in their order.
+__global__ void moments_integrate_kernel(const double *tmp, const double *Qt, const double *w_nu, int f0, int nfc,
+                                         int64_t cells, int first, double *J_int, double *H_int, double *K_int,
+                                         double *Q_int)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double acc[11];
+#pragma unroll
+    for (int q = 0; q < 11; ++q) acc[q] = 0.0;
+    for (int fl = 0; fl < nfc; ++fl) {
+        const double w = w_nu[f0 + fl];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] += w * tmp[((int64_t)q * nfc + fl) * cells + c];
+        if (Q_int) acc[10] += w * Qt[(int64_t)fl * cells + c];
+    }
+    if (J_int) J_int[c] = first ? acc[0] : J_int[c] + acc[0];
+    if (H_int)
+        for (int q = 0; q < 3; ++q) H_int[q * cells + c] = first ? acc[1 + q] : H_int[q * cells + c] + acc[1 + q];
+    if (K_int)
+        for (int q = 0; q < 6; ++q) K_int[q * cells + c] = first ? acc[4 + q] : K_int[q * cells + c] + acc[4 + q];
+    if (Q_int) Q_int[c] = first ? acc[10] : Q_int[c] + acc[10];
+}
+
+__global__ void eddington_kernel(const double *J_int, const double *K_int, int64_t cells, double *f_int)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double J = J_int[c];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) f_int[q * cells + c] = (J != 0.0) ? K_int[q * cells + c] / J : 0.0;
+}
+
+// Deterministic FP64 sum: per-block sums (fixed tree), then one thread in block order.
+__global__ void __launch_bounds__(256) block_sum_kernel(const double *x, int64_t n, double *partial)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void final_sum_kernel(const double *partial, int nblk, double scale, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partial[b];
+    *out = acc * scale;
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
 
-size_t sweep_lds_bytes(int real_bytes, int waves)
+size_t sweep_lds_bytes(int real_bytes, int waves, int nq)
 {
-    return sizeof(double) * (size_t)TILE_LDS + (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * WAVE_LDS);
+    return sizeof(double) * (size_t)TILE_LDS +
+           (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * (size_t)wave_lds(nq));
 }
 
-hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, hipStream_t st)
+hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq, hipStream_t st)
 {
-    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nf);
-    hipLaunchKernelGGL((sweep_stage_kernel<double, false>), grid, dim3(64 * waves), sweep_lds_bytes(8, waves), st, A);
+    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
+    if (nq == NMOM)
+        hipLaunchKernelGGL((sweep_stage_kernel<double, false, NMOM>), grid, dim3(64 * waves),
+                           sweep_lds_bytes(8, waves, nq), st, A);
+    else
+        hipLaunchKernelGGL((sweep_stage_kernel<double, false, 1>), grid, dim3(64 * waves), sweep_lds_bytes(8, waves, 1),
+                           st, A);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, hipStream_t st)
+hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, hipStream_t st)
 {
-    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nf);
-    hipLaunchKernelGGL((sweep_stage_kernel<float, true>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves), st, A);
+    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
+    if (nq == NMOM)
+        hipLaunchKernelGGL((sweep_stage_kernel<float, true, NMOM>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves, nq),
+                           st, A);
+    else
+        hipLaunchKernelGGL((sweep_stage_kernel<float, true, 1>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves, 1),
+                           st, A);
     return hipGetLastError();
 }
 
@@ -700,7 +866,7 @@ static hipError_t launch_persistent(const SweepArgs<Real> &A, const DagArgs &D, 
                                     hipStream_t st)
 {
     hipLaunchKernelGGL((sweep_persistent_kernel<Real, DFORM>), dim3(8u * (unsigned)blocks_per_octant), dim3(64 * waves),
-                       sweep_lds_bytes(sizeof(Real), waves), st, A, D);
+                       sweep_lds_bytes(sizeof(Real), waves, 1), st, A, D);
     return hipGetLastError();
 }
 
@@ -716,7 +882,7 @@ hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs 
 
 hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks)
 {
-    const size_t lds = sweep_lds_bytes(real_bytes, waves);
+    const size_t lds = sweep_lds_bytes(real_bytes, waves, 1);
     if (real_bytes == 8)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<double, false>, 64 * waves, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<float, true>, 64 * waves, lds);
@@ -783,9 +949,58 @@ hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_s
     return hipGetLastError();
 }
 
-hipError_t launch_flip_parity(int *parity, const int *frozen, int nf, hipStream_t st)
+hipError_t launch_flip_parity(int *parity, const int *frozen, int f0, int cnt, hipStream_t st)
 {
-    hipLaunchKernelGGL(flip_parity_kernel, dim3(blocks_for(nf, 64)), dim3(64), 0, st, parity, frozen, nf);
+    hipLaunchKernelGGL(flip_parity_kernel, dim3(blocks_for(cnt, 64)), dim3(64), 0, st, parity, frozen, f0, cnt);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_moments_combine(const Real *part, const double *S, int dform, int f0, int nfc, int nf, int64_t cells,
+                                  const MomConst &mc, double *J, double *H, double *K, double *tmp, hipStream_t st)
+{
+    hipLaunchKernelGGL(moments_combine_kernel<Real>, dim3(blocks_for(cells * nfc, 256)), dim3(256), 0, st, part, S,
+                       dform, f0, nfc, nf, cells, mc, J, H, K, tmp);
+    return hipGetLastError();
+}
+template hipError_t launch_moments_combine<double>(const double *, const double *, int, int, int, int, int64_t,
+                                                   const MomConst &, double *, double *, double *, double *,
+                                                   hipStream_t);
+template hipError_t launch_moments_combine<float>(const float *, const double *, int, int, int, int, int64_t,
+                                                  const MomConst &, double *, double *, double *, double *,
+                                                  hipStream_t);
+
+hipError_t launch_moments_q(const double *tmp, int f0, int nfc, const int n[3], const double h[3], const int per[3],
+                            const double *chi, const double *eps, const double *B, double *Qt, hipStream_t st)
+{
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    const double hmin = fmin(h[0], fmin(h[1], h[2]));
+    hipLaunchKernelGGL(moments_q_kernel, dim3(blocks_for(cells * nfc, 256)), dim3(256), 0, st, tmp, f0, nfc, cells,
+                       n[0], n[1], n[2], h[0], h[1], h[2], per[0], per[1], per[2], hmin, chi, eps, B, Qt);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_integrate(const double *tmp, const double *Qt, const double *w_nu, int f0, int nfc,
+                                    int64_t cells, int first, double *J_int, double *H_int, double *K_int,
+                                    double *Q_int, hipStream_t st)
+{
+    hipLaunchKernelGGL(moments_integrate_kernel, dim3(blocks_for(cells, 256)), dim3(256), 0, st, tmp, Qt, w_nu, f0, nfc,
+                       cells, first, J_int, H_int, K_int, Q_int);
+    return hipGetLastError();
+}
+
+hipError_t launch_eddington(const double *J_int, const double *K_int, int64_t cells, double *f_int, hipStream_t st)
+{
+    hipLaunchKernelGGL(eddington_kernel, dim3(blocks_for(cells, 256)), dim3(256), 0, st, J_int, K_int, cells, f_int);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double *x, int64_t n, double scale, double *partial, int nblk, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(block_sum_kernel, dim3((unsigned)nblk), dim3(256), 0, st, x, n, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(64), 0, st, partial, nblk, scale, out);
     return hipGetLastError();
 }
 
