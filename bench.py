@@ -5,7 +5,8 @@ A step is one whole pass of the hot path over the 128^3 scattering workload
 (grey coherent scattering, eps = 1e-3, exponentially stratified opacity with a
 vertical optical depth of 1e4, 48 rays): ingest of chi/eps/B with Lambda*, then
 Jacobi ALI from S = B with FP32 difference-form sweeps and FP64 updates and
-residuals until max |dS|/S <= 1e-6.  Inputs are resident in HBM before the timed
+residuals until max |dS|/S <= 1e-6, then the moments epilogue (J, H, K, f = K/J,
+Q and the heating sum) on the converged S.  Inputs are resident in HBM before the timed
 region.  The JSON line reports cell*ray*bin updates per second over the timed
 steps, ALI solves/s, p50/p99 solve latency, the sweep kernel against its roofline
 (VALU-bound; durations from HIP events inside the library, see rt_problem_profile),
@@ -66,6 +67,10 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 GPU comparison solve")
     ap.add_argument("--schedule", choices=["stages"], default="stages")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="profiling mode: run exactly this many ALI iterations per step instead of converging")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (for scaling rocprofv3 FETCH/WRITE_SIZE) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -79,12 +84,23 @@ def main():
     from paper_1201_2222_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "copies": 3}), flush=True)
+        return
     wl = W.scattering(args.n)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     chi, eps, B = dev(wl.chi), dev(wl.eps), dev(wl.B)
     n = wl.chi.size
     S = torch.empty(n, dtype=torch.float64, device="cuda")
     J = torch.empty(n, dtype=torch.float64, device="cuda")
+    cells = wl.cells
+    mom = {k: torch.empty(m * cells, dtype=torch.float64, device="cuda")
+           for k, m in (("J_int", 1), ("H_int", 3), ("K_int", 6), ("f_int", 6), ("Q_int", 1))}
     sched = rt.RT_SCHED_STAGES
     prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
                       schedule=sched)
@@ -92,9 +108,11 @@ def main():
     def step():
         prob.reset_periodic()
         prob.set_fields(chi, eps, B)
-        status, st = prob.ali_solve(S, J, delta_c=wl.delta_c, max_iter=50000, per_bin_stop=True)
+        status, st = prob.ali_solve(S, J, delta_c=wl.delta_c, max_iter=50000, per_bin_stop=True,
+                                    fixed_iters=args.fixed_iters)
         if status != rt.RT_OK:
             raise RuntimeError(f"ALI did not converge: {st}")
+        st["heating"] = prob.moments(S, want_heating=True, **mom)   # moments epilogue on the converged S
         return st
 
     for _ in range(args.warmup):
@@ -117,7 +135,8 @@ def main():
     rt.rt_problem_profile(prob.handle, False)
     J32 = J.cpu().numpy()
 
-    updates = float(wl.cells * wl.na * wl.nf * sum(iters))
+    # one sweep per ALI iteration plus the moments sweep
+    updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + len(iters)))
     value = updates / total
     kernel_s = prof["kernel_ms"] / 1e3
     achieved = prof["updates"] * OPS_PER_UPDATE_F32 / kernel_s / 1e12 if kernel_s > 0 else 0.0
@@ -158,6 +177,8 @@ def main():
         "ali_solves_per_s": args.steps / total,
         "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
         "iterations": iters,
+        "heating": st["heating"],
+        "profiling_fixed_iters": args.fixed_iters or None,
         "roofline": roofline,
     }
     out.update(extra)
