@@ -234,6 +234,7 @@ struct rt_problem {
     int nstages = 0;
     int64_t cells = 0;
     int64_t plane[3]{};
+    int64_t pplane[3]{};               // face planes padded by the row and column at -1
     int periodic[3]{};
     bool f32 = false;
     bool cold = true;
@@ -246,7 +247,7 @@ struct rt_problem {
     int *d_tiles = nullptr;
     double *chi64 = nullptr, *eps = nullptr, *B = nullptr, *lam = nullptr;
     float *chi32 = nullptr;
-    void *face[3]{};                   // Real [nf][na][nt_q - 1][plane_q]
+    void *face[3]{};                   // Real [nf][na][nt_q][pplane_q]
     double *wrap[3]{};                 // [nf][na][2][plane_q] on periodic axes
     void *part = nullptr;              // Real [8][nf][cells]
     int *frozen = nullptr, *parity = nullptr, *iters = nullptr, *flags = nullptr;
@@ -352,12 +353,14 @@ size_t state_bytes(const rt_problem_desc *d, int na)
     int nt[3];
     tile_counts(d, nt);
     const int64_t plane[3] = {(int64_t)d->ny * d->nz, (int64_t)d->nx * d->nz, (int64_t)d->nx * d->ny};
+    const int64_t pplane[3] = {(int64_t)(d->ny + 1) * (d->nz + 1), (int64_t)(d->nx + 1) * (d->nz + 1),
+                               (int64_t)(d->nx + 1) * (d->ny + 1)};
     const int bc_per[3] = {d->bc_lo[0] == RT_BC_PERIODIC, d->bc_lo[1] == RT_BC_PERIODIC, d->bc_lo[2] == RT_BC_PERIODIC};
     size_t b = 0;
     b += (size_t)nc * 8 * 4;                       // chi64, eps, B, lam
     if (d->precision == RT_F32) b += (size_t)nc * 4;  // chi32
     for (int q = 0; q < 3; ++q) {
-        b += (size_t)d->nf * na * (nt[q] - 1) * plane[q] * rs;          // interior tile faces
+        b += (size_t)d->nf * na * nt[q] * pplane[q] * rs;               // padded face planes
         if (bc_per[q]) b += (size_t)d->nf * na * 2 * plane[q] * 8;      // periodic memory
     }
     b += (size_t)8 * nc * rs;                      // partials
@@ -392,6 +395,7 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
         A.bc_hi[q] = p->desc.bc_hi[q];
         A.periodic[q] = p->periodic[q];
         A.plane[q] = p->plane[q];
+        A.pplane[q] = p->pplane[q];
         A.face[q] = static_cast<Real *>(p->face[q]);
         A.wrap[q] = p->wrap[q];
     }
@@ -414,7 +418,7 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
 }
 
 // Waves per sweep workgroup: one per ray of the octant, capped so the dynamic LDS
-// (chi and S tiles; plane buffers, halo lines and a partial-sum tile per wave) fits
+// (chi and S tiles; a cube of I and a partial-sum tile per wave) fits
 // the device's per-workgroup limit.
 int sweep_waves(int R, bool f32, size_t lds_limit)
 {
@@ -469,6 +473,7 @@ rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed =
         HIP_TRY(launch_periodic_cold<Real>(A, st));
         p->cold = false;
     }
+    HIP_TRY(launch_ghost_fill<Real>(A, st));
     timed = timed && p->prof && !p->prof_pending && mode.nq == 1;
     const int W = mode.waves > 0 ? mode.waves : p->waves;
     if (p->persistent && mode.nq == 1) {
@@ -613,6 +618,9 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     p->plane[0] = (int64_t)desc->ny * desc->nz;
     p->plane[1] = (int64_t)desc->nx * desc->nz;
     p->plane[2] = (int64_t)desc->nx * desc->ny;
+    p->pplane[0] = (int64_t)(desc->ny + 1) * (desc->nz + 1);
+    p->pplane[1] = (int64_t)(desc->nx + 1) * (desc->nz + 1);
+    p->pplane[2] = (int64_t)(desc->nx + 1) * (desc->ny + 1);
     for (int q = 0; q < 3; ++q) p->periodic[q] = desc->bc_lo[q] == RT_BC_PERIODIC;
     tile_counts(desc, p->nt);
     p->w_nu.assign(desc->nf, 1.0);
@@ -665,7 +673,7 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     if (p->f32) ALLOC(p->chi32, (size_t)nc);
     for (int q = 0; q < 3; ++q) {
         unsigned char *fb;
-        ALLOC(fb, (size_t)p->nf * na * (p->nt[q] - 1) * p->plane[q] * rs);
+        ALLOC(fb, (size_t)p->nf * na * p->nt[q] * p->pplane[q] * rs);
         p->face[q] = fb;
         if (p->periodic[q]) ALLOC(p->wrap[q], (size_t)p->nf * na * 2 * p->plane[q]);
     }

@@ -34,13 +34,17 @@ struct SweepArgs {
     int periodic[3];
     int64_t cells;
     int64_t plane[3];         // vertices in the plane normal to each axis
+    int64_t pplane[3];        // same, padded by one vertex row and column at -1
     const RayGeo *rays;       // [na], octant-major
     const Real *chi;          // [nf][cells]
     const double *S;          // [nf][cells] source function (always FP64)
     const double *B;          // [nf][cells]
     const double *fixed[6];   // FIXED faces (real coordinates), or null
-    Real *face[3];            // [nf][na][nt_q - 1][plane_q]: downwind faces of interior tiles
-                              // (I in the plain form, D = I - S in the difference form)
+    Real *face[3];            // [nf][na][nt_q][pplane_q]: slot t holds the plane at flipped
+                              // coordinate t * tile - 1 along q (slot 0: the ghost plane); its
+                              // vertices inside the grid are written by the tiles, its ghost
+                              // vertices before the sweep (I in the plain form, D = I - S in
+                              // the difference form)
     double *wrap[3];          // [nf][na][2][plane_q]: periodic memory (I), slot = parity
     Real *part;               // [8][nq][nfc][cells] per-octant partial sums of w I (or w D)
     int f0, nfc;              // bins f0 .. f0 + nfc - 1 are swept by this call
@@ -95,6 +99,11 @@ hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_h
 // Cold periodic memory: every periodic slot about to be read holds S of the wrapped vertex.
 template <typename Real>
 hipError_t launch_periodic_cold(const SweepArgs<Real> &A, hipStream_t st);
+
+// Ghost vertices of the padded face planes of the bins f0 .. f0 + nfc - 1, for the
+// sweep about to run.
+template <typename Real>
+hipError_t launch_ghost_fill(const SweepArgs<Real> &A, hipStream_t st);
 
 template <typename Real>
 hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,

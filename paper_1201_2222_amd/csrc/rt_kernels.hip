@@ -25,10 +25,8 @@ namespace {
 constexpr int T = kTile;
 constexpr int TP = T + 1;            // tile plus one upwind halo layer
 constexpr int TILE_LDS = TP * TP * TP;
-constexpr int PLANE_LDS = TP * TP;
-constexpr int HALO_LINE = 2 * T + 1; // halo of one plane: T+1 values on the a-line, T on the b-line
-// Reals of LDS per wave: two plane buffers, the halo lines, nq partial-sum tiles
-constexpr int wave_lds(int nq) { return 2 * PLANE_LDS + T * HALO_LINE + nq * T * T * T; }
+// Reals of LDS per wave: the cube of I (or D) of its current ray, nq partial-sum tiles
+constexpr int wave_lds(int nq) { return TILE_LDS + nq * T * T * T; }
 constexpr int NMOM = 10;             // moments mode: J, H_x,y,z, K_xx,yy,zz,xy,xz,yz
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -113,28 +111,20 @@ struct TileCtx {
     int64_t fbase;   // f * cells
 };
 
-// Value (I, or D = I - S in the difference form) at a vertex (vx, vy, vz) in
-// flipped coordinates just upwind of the tile, for one ray.  Ghost vertices read S
-// from global memory, so the call does not wait for the staged tile.
-template <typename Real, bool DFORM>
-__device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, int vx, int vy, int vz, int ray, int gidx)
+// Where the value of one ray at a ghost vertex (vx, vy, vz) in flipped coordinates
+// (a coordinate of -1) comes from: *src (nullptr: zero incident intensity), and in
+// the difference form minus S at *scell.  chi and S of a ghost are those of the
+// folded vertex.
+template <typename Real>
+__device__ __forceinline__ void ghost_source(const SweepArgs<Real> &A, const TileCtx &c, int vx, int vy, int vz,
+                                             int ray, int gidx, const double *&src, int64_t &scell)
 {
     const bool ox = vx < 0, oy = vy < 0, oz = vz < 0;
     const int64_t rb = (int64_t)c.f * A.na + ray;
-    if (!(ox || oy || oz)) {
-        // a vertex of an upwind neighbour tile: that tile's downwind face
-        if (vx == c.g0x - 1)
-            return A.face[0][(rb * (A.nt[0] - 1) + (c.tx - 1)) * A.plane[0] + (int64_t)vz * A.n[1] + vy];
-        if (vy == c.g0y - 1)
-            return A.face[1][(rb * (A.nt[1] - 1) + (c.ty - 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx];
-        return A.face[2][(rb * (A.nt[2] - 1) + (c.tz - 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx];
-    }
-    // ghost vertex outside the grid: chi and S are those of the folded vertex
     const int rx = fold(to_real(vx, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
     const int ry = fold(to_real(vy, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
     const int rz = fold(to_real(vz, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
-    const int64_t cell = c.fbase + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
-    const double Sg = DFORM ? A.S[cell] : 0.0;
+    scell = c.fbase + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
     // outside a non-periodic face: that face's condition, z before y before x
     int q = -1;
     if (oz && !A.periodic[2]) q = 2;
@@ -143,66 +133,207 @@ __device__ Real halo_value(const SweepArgs<Real> &A, const TileCtx &c, int vx, i
     if (q >= 0) {
         const int lo = sel3(q, c.sgx, c.sgy, c.sgz) > 0;
         const int kind = lo ? sel3(q, A.bc_lo[0], A.bc_lo[1], A.bc_lo[2]) : sel3(q, A.bc_hi[0], A.bc_hi[1], A.bc_hi[2]);
-        double I = 0.0;
+        src = nullptr;
         if (kind == BC_THERMAL) {
-            I = A.B[cell];
+            src = A.B + scell;
         } else if (kind == BC_FIXED) {
             const double *F = (q == 0) ? (lo ? A.fixed[0] : A.fixed[1])
                                        : (q == 1 ? (lo ? A.fixed[2] : A.fixed[3]) : (lo ? A.fixed[4] : A.fixed[5]));
             const int64_t pidx = (q == 0) ? (int64_t)rz * A.n[1] + ry
                                           : (q == 1 ? (int64_t)rz * A.n[0] + rx : (int64_t)ry * A.n[0] + rx);
             const int64_t P = sel3(q, A.plane[0], A.plane[1], A.plane[2]);
-            I = F[((int64_t)c.f * A.na + gidx) * P + pidx];
+            src = F + ((int64_t)c.f * A.na + gidx) * P + pidx;
         }
-        return DFORM ? Real(I - Sg) : Real(I);
+        return;
     }
     // only periodic axes are outside: the previous sweep's intensity at the
     // wrapped vertex, kept on the ray's outgoing plane
     const int wx = ox ? A.n[0] - 1 : vx, wy = oy ? A.n[1] - 1 : vy, wz = oz ? A.n[2] - 1 : vz;
-    double I;
     if (ox)
-        I = A.wrap[0][(rb * 2 + c.par) * A.plane[0] + (int64_t)wz * A.n[1] + wy];
+        src = A.wrap[0] + (rb * 2 + c.par) * A.plane[0] + (int64_t)wz * A.n[1] + wy;
     else if (oy)
-        I = A.wrap[1][(rb * 2 + c.par) * A.plane[1] + (int64_t)wz * A.n[0] + wx];
+        src = A.wrap[1] + (rb * 2 + c.par) * A.plane[1] + (int64_t)wz * A.n[0] + wx;
     else
-        I = A.wrap[2][(rb * 2 + c.par) * A.plane[2] + (int64_t)wy * A.n[0] + wx];
-    return DFORM ? Real(I - Sg) : Real(I);
+        src = A.wrap[2] + (rb * 2 + c.par) * A.plane[2] + (int64_t)wy * A.n[0] + wx;
 }
 
-// Load every upwind-halo value one ray needs in this tile: the d = -1 face into
-// the first plane buffer, the a/b halo lines of planes 0 .. ed-2 into Hl.
-template <typename Real, bool DFORM>
-__device__ void prefetch_halo(const SweepArgs<Real> &A, const TileCtx &c, int oct, int r, int lane, Real *P0, Real *Hl)
+// The upwind shell of one ray's LDS cube: the planes x = -1, y = -1 and z = -1 of
+// the tile in flipped local coordinates, edges and corner included (the cube has
+// the staged tile's layout), 217 vertices, four per lane.  Each comes from the
+// padded face plane of its axis at the tile's slot: the downwind face of the
+// upwind neighbour tile, or a ghost value written before the sweep.  shell_load
+// issues the loads into registers and shell_store writes them into the cube, so
+// the loads of the next ray are in flight while a ray is swept.
+constexpr int SHELL_X = TP * TP, SHELL_Y = T * TP, SHELL_Z = T * T;
+constexpr int SHELL_PER_LANE = (SHELL_X + SHELL_Y + SHELL_Z + 63) / 64;
+
+template <typename Real>
+struct Shell {
+    Real v[SHELL_PER_LANE];
+    int slot[SHELL_PER_LANE];    // cube index, -1: none
+};
+
+template <typename Real>
+__device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileCtx &c, int ray, int lane, Shell<Real> &sh)
 {
-    const int ray = oct * A.R + r;
-    const RayGeo *G = A.rays + ray;
-    const int d = G->d, a = G->a, gidx = G->gidx;
-    const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(3 - d - a, c.ex, c.ey, c.ez);
-    const int g0d = sel3(d, c.g0x, c.g0y, c.g0z), g0a = sel3(a, c.g0x, c.g0y, c.g0z),
-              g0b = sel3(3 - d - a, c.g0x, c.g0y, c.g0z);
-    const int n1 = (ea + 1) * (eb + 1);
-    const int nl = ea + eb + 1;
-    const int tot = n1 + (ed - 1) * nl;
-    for (int e = lane; e < tot; e += 64) {
-        int vd, ia, ib;
-        Real *dst;
-        if (e < n1) {
-            ia = e % (ea + 1) - 1;
-            ib = e / (ea + 1) - 1;
-            vd = g0d - 1;
-            dst = P0 + (ia + 1) + (ib + 1) * TP;
+    const int64_t rb = (int64_t)c.f * A.na + ray;
+#pragma unroll
+    for (int k = 0; k < SHELL_PER_LANE; ++k) {
+        const int e = lane + 64 * k;
+        int lx, ly, lz;
+        const Real *src;
+        if (e < SHELL_X) {
+            lx = -1;
+            ly = e % TP - 1;
+            lz = e / TP - 1;
+            src = A.face[0] + (rb * A.nt[0] + c.tx) * A.pplane[0] + (int64_t)(c.g0z + lz + 1) * (A.n[1] + 1) +
+                  (c.g0y + ly + 1);
+        } else if (e < SHELL_X + SHELL_Y) {
+            const int e2 = e - SHELL_X;
+            ly = -1;
+            lx = e2 % T;
+            lz = e2 / T - 1;
+            src = A.face[1] + (rb * A.nt[1] + c.ty) * A.pplane[1] + (int64_t)(c.g0z + lz + 1) * (A.n[0] + 1) +
+                  (c.g0x + lx + 1);
         } else {
-            const int e2 = e - n1, p = e2 / nl, k = e2 - p * nl;
-            vd = g0d + p;
-            ia = (k <= eb) ? -1 : k - eb - 1;
-            ib = (k <= eb) ? k - 1 : -1;
-            dst = Hl + p * HALO_LINE + k;
+            const int e3 = e - SHELL_X - SHELL_Y;
+            lz = -1;
+            lx = e3 % T;
+            ly = e3 / T;
+            src = A.face[2] + (rb * A.nt[2] + c.tz) * A.pplane[2] + (int64_t)(c.g0y + ly + 1) * (A.n[0] + 1) +
+                  (c.g0x + lx + 1);
         }
-        const int va = g0a + ia, vb = g0b + ib;
-        const int vx = d == 0 ? vd : (a == 0 ? va : vb);
-        const int vy = d == 1 ? vd : (a == 1 ? va : vb);
-        const int vz = d == 2 ? vd : (a == 2 ? va : vb);
-        *dst = halo_value<Real, DFORM>(A, c, vx, vy, vz, ray, gidx);
+        const bool ok = e < SHELL_X + SHELL_Y + SHELL_Z && lx < c.ex && ly < c.ey && lz < c.ez;
+        sh.slot[k] = ok ? ((lz + 1) * TP + (ly + 1)) * TP + (lx + 1) : -1;
+        sh.v[k] = ok ? *src : Real(0);
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void shell_store(const Shell<Real> &sh, Real *Ic)
+{
+#pragma unroll
+    for (int k = 0; k < SHELL_PER_LANE; ++k)
+        if (sh.slot[k] >= 0) Ic[sh.slot[k]] = sh.v[k];
+}
+
+// The downwind faces of the tile for one ray, read from its cube after the sweep:
+// interior faces go to the next tile's slot of the padded face planes; the grid's
+// last faces on periodic axes feed the next sweep's periodic memory (which keeps I,
+// in FP64).
+template <typename Real, bool DFORM>
+__device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray, int lane, const Real *Ic,
+                            const double *SL)
+{
+    const int64_t rb = (int64_t)c.f * A.na + ray;
+    const int u = lane % T, w = lane / T;   // T * T == 64 face vertices, one per lane
+    // x face: (y, z) = (u, w)
+    if (u < c.ey && w < c.ez) {
+        const int li = ((w + 1) * TP + (u + 1)) * TP + c.ex;
+        const int vy = c.g0y + u, vz = c.g0z + w;
+        if (c.tx < A.nt[0] - 1)
+            A.face[0][(rb * A.nt[0] + c.tx + 1) * A.pplane[0] + (int64_t)(vz + 1) * (A.n[1] + 1) + (vy + 1)] = Ic[li];
+        else if (A.periodic[0])
+            A.wrap[0][(rb * 2 + (c.par ^ 1)) * A.plane[0] + (int64_t)vz * A.n[1] + vy] =
+                DFORM ? double(Ic[li]) + SL[li] : double(Ic[li]);
+    }
+    // y face: (x, z) = (u, w)
+    if (u < c.ex && w < c.ez) {
+        const int li = ((w + 1) * TP + c.ey) * TP + (u + 1);
+        const int vx = c.g0x + u, vz = c.g0z + w;
+        if (c.ty < A.nt[1] - 1)
+            A.face[1][(rb * A.nt[1] + c.ty + 1) * A.pplane[1] + (int64_t)(vz + 1) * (A.n[0] + 1) + (vx + 1)] = Ic[li];
+        else if (A.periodic[1])
+            A.wrap[1][(rb * 2 + (c.par ^ 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx] =
+                DFORM ? double(Ic[li]) + SL[li] : double(Ic[li]);
+    }
+    // z face: (x, y) = (u, w)
+    if (u < c.ex && w < c.ey) {
+        const int li = (c.ez * TP + (w + 1)) * TP + (u + 1);
+        const int vx = c.g0x + u, vy = c.g0y + w;
+        if (c.tz < A.nt[2] - 1)
+            A.face[2][(rb * A.nt[2] + c.tz + 1) * A.pplane[2] + (int64_t)(vy + 1) * (A.n[0] + 1) + (vx + 1)] = Ic[li];
+        else if (A.periodic[2])
+            A.wrap[2][(rb * 2 + (c.par ^ 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx] =
+                DFORM ? double(Ic[li]) + SL[li] : double(Ic[li]);
+    }
+}
+
+constexpr int lds_stride(int q) { return q == 0 ? 1 : (q == 1 ? TP : TP * TP); }
+constexpr int tile_stride(int q) { return q == 0 ? 1 : (q == 1 ? T : T * T); }
+
+// Plane-by-plane sweep of one ray through the tile along its first-crossed axis D
+// (all strides compile-time).  Lane (ia, ib) owns one vertex of every plane.
+template <typename Real, bool DFORM, int NQ, int D>
+__device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int eb, int lane, Real *Ic,
+                                           const Real *chiL, const double *SL, Real *Jw)
+{
+    constexpr int DA = (D == 0) ? 1 : 0, DB = (D == 2) ? 1 : 2;
+    constexpr int SD = lds_stride(D), SA = lds_stride(DA), SB = lds_stride(DB);
+    constexpr int JD = tile_stride(D), JA = tile_stride(DA), JB = tile_stride(DB);
+    const int ia = lane & (T - 1), ib = lane / T;
+    const bool act = ia < ea && ib < eb;
+    const int lb = (ia + 1) * SA + (ib + 1) * SB;
+    const int jbase = ia * JA + ib * JB;
+    const Real s_half = Real(0.5 * G->s);
+    const Real w00 = Real(G->w4[0]), w10 = Real(G->w4[1]), w01 = Real(G->w4[2]), w11 = Real(G->w4[3]);
+    const double w00d = G->w4[0], w10d = G->w4[1], w01d = G->w4[2], w11d = G->w4[3];
+    // weights of this ray in the accumulated quantities: w (J), and in moments mode
+    // also w mu_i (H) and w mu_i mu_j (K)
+    Real cq[NQ];
+    cq[0] = Real(G->wk);
+    if constexpr (NQ == NMOM) {
+        const double mx = G->mu[0], my = G->mu[1], mz = G->mu[2], wd = G->wk;
+        cq[1] = Real(wd * mx);
+        cq[2] = Real(wd * my);
+        cq[3] = Real(wd * mz);
+        cq[4] = Real(wd * mx * mx);
+        cq[5] = Real(wd * my * my);
+        cq[6] = Real(wd * mz * mz);
+        cq[7] = Real(wd * mx * my);
+        cq[8] = Real(wd * mx * mz);
+        cq[9] = Real(wd * my * mz);
+    }
+    // J: the ray's T contributions stay in registers and are added once; moments mode
+    // adds its 10 quantities to the wave's LDS tiles at every step
+    Real jr[T];
+#pragma unroll
+    for (int p = 0; p < T; ++p) {
+        jr[p] = Real(0);
+        if (p < ed) {
+            if (act) {
+                const int l0 = lb + (p + 1) * SD;
+                const int lu = l0 - SD;
+                const Real Im = w00 * Ic[lu] + w10 * Ic[lu - SA] + w01 * Ic[lu - SB] + w11 * Ic[lu - SA - SB];
+                const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - SA] + w01 * chiL[lu - SB] + w11 * chiL[lu - SA - SB];
+                const Real dt = s_half * (Cm + chiL[l0]);
+                const double S0 = SL[l0];
+                const double Sm = w00d * SL[lu] + w10d * SL[lu - SA] + w01d * SL[lu - SB] + w11d * SL[lu - SA - SB];
+                Real v;
+                if constexpr (DFORM) {
+                    Real E, g;
+                    seg_coeffs(dt, E, g);
+                    v = Im * E + Real(Sm - S0) * g;   // S- - S0 formed in FP64
+                } else {
+                    Real E, pm, p0;
+                    seg_coeffs(dt, E, pm, p0);
+                    v = Im * E + pm * Real(Sm) + p0 * Real(S0);
+                }
+                Ic[l0] = v;
+                if constexpr (NQ == 1) {
+                    jr[p] = cq[0] * v;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + jbase + p * JD] += cq[q] * v;
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+    if (NQ == 1 && act) {
+#pragma unroll
+        for (int p = 0; p < T; ++p)
+            if (p < ed) Jw[jbase + p * JD] += jr[p];
     }
 }
 
@@ -228,9 +359,9 @@ __device__ __forceinline__ bool wait_done(const int *flag, int epoch, const int 
 }
 
 // One tile of one octant and bin: stage chi and S with the upwind halo, sweep every
-// ray of the octant through it, write the octant's partial sums.  With a non-null
-// dependency block (persistent sweep) the upwind face-neighbour tiles are awaited
-// after the staging loads have been issued and before any face data is read.
+// ray of the octant through it, write the octant's partial sums.  In the persistent
+// sweep (PERSIST) the upwind face-neighbour tiles are awaited after the staging loads
+// have been issued and before any face data is read.
 template <typename Real, bool DFORM, bool PERSIST, int NQ>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, int f, int packed, int par,
                                            unsigned char *lds_raw, const int *done, int epoch, int ntiles, int nt0,
@@ -260,28 +391,47 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
-    Real *P0 = waveL + (size_t)wave * wave_lds(NQ);
-    Real *P1 = P0 + PLANE_LDS;
-    Real *Hl = P1 + PLANE_LDS;
-    Real *Jw = Hl + T * HALO_LINE;
+    Real *Ic = waveL + (size_t)wave * wave_lds(NQ);   // this wave's cube of I (or D)
+    Real *Jw = Ic + TILE_LDS;                         // and its partial-sum tiles
 
-    // the first ray's halo loads go out together with the tile staging loads
-    if (!PERSIST && wave < A.R) prefetch_halo<Real, DFORM>(A, c, oct, wave, lane, P0, Hl);
+    // the first ray's shell loads go out together with the tile staging loads
+    Shell<Real> sh;
+    if (!PERSIST && wave < A.R) shell_load<Real>(A, c, oct * A.R + wave, lane, sh);
 
     // ---- stage chi and S of the tile and its upwind halo in LDS --------------------
+    // each pass issues all of its loads before the first LDS store
     const Real *chif = A.chi + c.fbase;
     const double *Sf = A.S + c.fbase;
-    for (int idx = threadIdx.x; idx < TILE_LDS; idx += blockDim.x) {
-        const int lx = idx % TP, ly = (idx / TP) % TP, lz = idx / (TP * TP);
-        if (lx > c.ex || ly > c.ey || lz > c.ez) continue;
-        const int rx = fold(to_real(c.g0x + lx - 1, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
-        const int ry = fold(to_real(c.g0y + ly - 1, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
-        const int rz = fold(to_real(c.g0z + lz - 1, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
-        const int64_t cell = ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
-        chiL[idx] = chif[cell];
-        SL[idx] = Sf[cell];
+    constexpr int STAGE_K = 3;   // one pass for four or more waves
+    for (int base = 0; base < TILE_LDS; base += STAGE_K * (int)blockDim.x) {
+        Real cv[STAGE_K];
+        double sv[STAGE_K];
+        int li[STAGE_K];
+#pragma unroll
+        for (int k = 0; k < STAGE_K; ++k) {
+            const int idx = base + k * (int)blockDim.x + (int)threadIdx.x;
+            const int lx = idx % TP, ly = (idx / TP) % TP, lz = idx / (TP * TP);
+            li[k] = -1;
+            cv[k] = Real(0);
+            sv[k] = 0.0;
+            if (idx >= TILE_LDS || lx > c.ex || ly > c.ey || lz > c.ez) continue;
+            const int rx = fold(to_real(c.g0x + lx - 1, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
+            const int ry = fold(to_real(c.g0y + ly - 1, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
+            const int rz = fold(to_real(c.g0z + lz - 1, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
+            const int64_t cell = ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
+            li[k] = idx;
+            cv[k] = chif[cell];
+            sv[k] = Sf[cell];
+        }
+#pragma unroll
+        for (int k = 0; k < STAGE_K; ++k) {
+            if (li[k] < 0) continue;
+            chiL[li[k]] = cv[k];
+            SL[li[k]] = sv[k];
+        }
     }
     for (int k = lane; k < NQ * T * T * T; k += 64) Jw[k] = Real(0);
+    if (!PERSIST && wave < A.R) shell_store<Real>(sh, Ic);
     if (PERSIST) {
         // upwind face neighbours of this tile in the same octant and bin
         if (threadIdx.x == 0) {
@@ -293,145 +443,35 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             if (!ok) atomicOr(err, 1);
         }
         __syncthreads();
-        if (wave < A.R) prefetch_halo<Real, DFORM>(A, c, oct, wave, lane, P0, Hl);
+        if (wave < A.R) {
+            shell_load<Real>(A, c, oct * A.R + wave, lane, sh);
+            shell_store<Real>(sh, Ic);
+        }
     }
     __syncthreads();
 
     // ---- per-wave ray sweeps ---------------------------------------------------------
-    const int ia = lane & (T - 1), ib = lane / T;   // this lane's vertex in every plane
     for (int r = wave; r < A.R; r += W) {
-        if (r != wave) {
-            prefetch_halo<Real, DFORM>(A, c, oct, r, lane, P0, Hl);
-            wave_lds_sync();
-        }
         const int ray = oct * A.R + r;
         const RayGeo *G = A.rays + ray;
+        // the next ray's shell loads are in flight while this ray is swept
+        const bool more = r + W < A.R;
+        if (more) shell_load<Real>(A, c, ray + W, lane, sh);
         const int d = G->d, a = G->a, b = 3 - G->d - G->a;
-        const Real s_half = Real(0.5 * G->s);
-        const Real w00 = Real(G->w4[0]), w10 = Real(G->w4[1]), w01 = Real(G->w4[2]), w11 = Real(G->w4[3]);
-        const double w00d = G->w4[0], w10d = G->w4[1], w01d = G->w4[2], w11d = G->w4[3];
-        const Real wk = Real(G->wk);
         const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
-        const int g0d = sel3(d, c.g0x, c.g0y, c.g0z), g0a = sel3(a, c.g0x, c.g0y, c.g0z),
-                  g0b = sel3(b, c.g0x, c.g0y, c.g0z);
-        const int nd = sel3(d, A.n[0], A.n[1], A.n[2]), na_ = sel3(a, A.n[0], A.n[1], A.n[2]),
-                  nb = sel3(b, A.n[0], A.n[1], A.n[2]);
-        // strides of the d, a, b axes in the staged tile and in the partial-sum tile
-        const int sd = sel3(d, 1, TP, TP * TP), sa = sel3(a, 1, TP, TP * TP), sb = sel3(b, 1, TP, TP * TP);
-        const int jd = sel3(d, 1, T, T * T), ja = sel3(a, 1, T, T * T), jb = sel3(b, 1, T, T * T);
-        const bool act = ia < ea && ib < eb;
-        const int q00 = (ia + 1) + (ib + 1) * TP;      // this vertex in the plane buffers
-        const int lb = (ia + 1) * sa + (ib + 1) * sb;  // ... and in the staged tile, without d
-
-        // where this lane's vertex lands on the tile's downwind faces: a-face and
-        // b-face at every step (index grows by a fixed stride per plane), d-face at
-        // the last step; interior faces feed the next tile, the domain's last faces
-        // the periodic memory
-        const int64_t rb = (int64_t)f * A.na + ray;
-        const int ta = sel3(a, c.tx, c.ty, c.tz), tb = sel3(b, c.tx, c.ty, c.tz), td = sel3(d, c.tx, c.ty, c.tz);
-        const int nta = sel3(a, A.nt[0], A.nt[1], A.nt[2]), ntb = sel3(b, A.nt[0], A.nt[1], A.nt[2]),
-                  ntd = sel3(d, A.nt[0], A.nt[1], A.nt[2]);
-        const int64_t Pa = sel3(a, A.plane[0], A.plane[1], A.plane[2]), Pb = sel3(b, A.plane[0], A.plane[1], A.plane[2]),
-                      Pd = sel3(d, A.plane[0], A.plane[1], A.plane[2]);
-        Real *fa = nullptr, *fb = nullptr, *fd = nullptr;
-        double *wa = nullptr, *wb = nullptr, *wd = nullptr;
-        if (ta < nta - 1) fa = sel3(a, A.face[0], A.face[1], A.face[2]) + (rb * (nta - 1) + ta) * Pa;
-        else if (sel3(a, A.periodic[0], A.periodic[1], A.periodic[2])) wa = sel3(a, A.wrap[0], A.wrap[1], A.wrap[2]) + (rb * 2 + (par ^ 1)) * Pa;
-        if (tb < ntb - 1) fb = sel3(b, A.face[0], A.face[1], A.face[2]) + (rb * (ntb - 1) + tb) * Pb;
-        else if (sel3(b, A.periodic[0], A.periodic[1], A.periodic[2])) wb = sel3(b, A.wrap[0], A.wrap[1], A.wrap[2]) + (rb * 2 + (par ^ 1)) * Pb;
-        if (td < ntd - 1) fd = sel3(d, A.face[0], A.face[1], A.face[2]) + (rb * (ntd - 1) + td) * Pd;
-        else if (sel3(d, A.periodic[0], A.periodic[1], A.periodic[2])) wd = sel3(d, A.wrap[0], A.wrap[1], A.wrap[2]) + (rb * 2 + (par ^ 1)) * Pd;
-        const bool on_a = act && ia == ea - 1 && (fa || wa);
-        const bool on_b = act && ib == eb - 1 && (fb || wb);
-        // plane normal to a holds d and b, normal to b holds d and a (lower axis fastest)
-        const int64_t ia0 = (d > b) ? (int64_t)g0d * nb + (g0b + ib) : (int64_t)(g0b + ib) * nd + g0d;
-        const int64_t sta = (d > b) ? nb : 1;
-        const int64_t ib0 = (d > a) ? (int64_t)g0d * na_ + (g0a + ia) : (int64_t)(g0a + ia) * nd + g0d;
-        const int64_t stb = (d > a) ? na_ : 1;
-        const int64_t idd = (int64_t)(g0b + ib) * na_ + (g0a + ia);   // plane normal to d (a < b)
-        const int nl = ea + eb + 1;
-
-        // weights of this ray in the accumulated quantities: w (J), and in moments
-        // mode also w mu_i (H) and w mu_i mu_j (K)
-        Real cq[NQ];
-        cq[0] = wk;
-        if constexpr (NQ == NMOM) {
-            const double mx = G->mu[0], my = G->mu[1], mz = G->mu[2], wd = G->wk;
-            cq[1] = Real(wd * mx);
-            cq[2] = Real(wd * my);
-            cq[3] = Real(wd * mz);
-            cq[4] = Real(wd * mx * mx);
-            cq[5] = Real(wd * my * my);
-            cq[6] = Real(wd * mz * mz);
-            cq[7] = Real(wd * mx * my);
-            cq[8] = Real(wd * mx * mz);
-            cq[9] = Real(wd * my * mz);
-        }
-        // J: this ray's 8 contributions are held in registers and added once per ray;
-        // moments mode adds its 10 quantities to the wave's LDS tiles at every step
-        Real jr[T];
-        const int jbase = ia * ja + ib * jb;
-#pragma unroll
-        for (int p = 0; p < T; ++p) {
-            jr[p] = Real(0);
-            if (p < ed) {
-                const Real *Pp = (p & 1) ? P1 : P0;
-                Real *Pc = (p & 1) ? P0 : P1;
-                if (act) {
-                    const int l0 = lb + (p + 1) * sd;
-                    const int lu = l0 - sd;
-                    const Real Im = w00 * Pp[q00] + w10 * Pp[q00 - 1] + w01 * Pp[q00 - TP] + w11 * Pp[q00 - TP - 1];
-                    const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - sa] + w01 * chiL[lu - sb] + w11 * chiL[lu - sa - sb];
-                    const Real dt = s_half * (Cm + chiL[l0]);
-                    const double S0 = SL[l0];
-                    const double Sm = w00d * SL[lu] + w10d * SL[lu - sa] + w01d * SL[lu - sb] + w11d * SL[lu - sa - sb];
-                    Real v;
-                    if constexpr (DFORM) {
-                        Real E, g;
-                        seg_coeffs(dt, E, g);
-                        v = Im * E + Real(Sm - S0) * g;   // S- - S0 formed in FP64
-                    } else {
-                        Real E, pm, p0;
-                        seg_coeffs(dt, E, pm, p0);
-                        v = Im * E + pm * Real(Sm) + p0 * Real(S0);
-                    }
-                    Pc[q00] = v;
-                    if constexpr (NQ == 1) {
-                        jr[p] = cq[0] * v;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + jbase + p * jd] += cq[q] * v;
-                    }
-                    const double Iw = DFORM ? double(v) + S0 : double(v);   // periodic memory keeps I
-                    if (on_a) {
-                        if (fa) fa[ia0 + p * sta] = v;
-                        else wa[ia0 + p * sta] = Iw;
-                    }
-                    if (on_b) {
-                        if (fb) fb[ib0 + p * stb] = v;
-                        else wb[ib0 + p * stb] = Iw;
-                    }
-                    if (p == ed - 1) {
-                        if (fd) fd[idd] = v;
-                        else if (wd) wd[idd] = Iw;
-                    }
-                }
-                // halo lines of plane p for the next step, from the prefetched batch
-                if (p + 1 < ed && lane < nl) {
-                    const int hia = (lane <= eb) ? -1 : lane - eb - 1;
-                    const int hib = (lane <= eb) ? lane - 1 : -1;
-                    Pc[(hia + 1) + (hib + 1) * TP] = Hl[p * HALO_LINE + lane];
-                }
-                wave_lds_sync();
-            }
-        }
-        // this ray's contribution to the wave's partial sums
-        if (NQ == 1 && act) {
-#pragma unroll
-            for (int p = 0; p < T; ++p)
-                if (p < ed) Jw[jbase + p * jd] += jr[p];
-        }
+        if (d == 0)
+            ray_planes<Real, DFORM, NQ, 0>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+        else if (d == 1)
+            ray_planes<Real, DFORM, NQ, 1>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+        else
+            ray_planes<Real, DFORM, NQ, 2>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         wave_lds_sync();
+        write_faces<Real, DFORM>(A, c, ray, lane, Ic, SL);
+        wave_lds_sync();
+        if (more) {
+            shell_store<Real>(sh, Ic);
+            wave_lds_sync();
+        }
     }
     __syncthreads();
 
@@ -441,8 +481,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         const int q = kq / (T * T * T), k = kq - q * T * T * T;
         const int lx = k % T, ly = (k / T) % T, lz = k / (T * T);
         if (lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
-        Real acc = waveL[2 * PLANE_LDS + T * HALO_LINE + kq];
-        for (int w = 1; w < W; ++w) acc += waveL[(size_t)w * wave_lds(NQ) + 2 * PLANE_LDS + T * HALO_LINE + kq];
+        Real acc = waveL[TILE_LDS + kq];
+        for (int w = 1; w < W; ++w) acc += waveL[(size_t)w * wave_lds(NQ) + TILE_LDS + kq];
         const int rx = to_real(c.g0x + lx, c.sgx, A.n[0]);
         const int ry = to_real(c.g0y + ly, c.sgy, A.n[1]);
         const int rz = to_real(c.g0z + lz, c.sgz, A.n[2]);
@@ -559,6 +599,74 @@ __global__ void periodic_cold_kernel(SweepArgs<Real> A, int q)
     const double Sv = A.S[(int64_t)f * A.cells + ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx];
     double *Wq = (q == 0) ? A.wrap[0] : (q == 1 ? A.wrap[1] : A.wrap[2]);
     Wq[(((int64_t)f * A.na + ray) * 2 + A.parity[f]) * P + i] = Sv;
+}
+
+// Entries of the padded face planes along axis q that hold ghost vertices: the
+// whole slot-0 plane and, in each further slot, the row and column at -1.
+template <typename Real>
+__device__ __forceinline__ int64_t ghost_count(const SweepArgs<Real> &A, int q)
+{
+    const int na_ = (q == 0) ? A.n[1] : A.n[0], nb_ = (q == 2) ? A.n[1] : A.n[2];
+    return (int64_t)(na_ + 1) * (nb_ + 1) + (int64_t)(sel3(q, A.nt[0], A.nt[1], A.nt[2]) - 1) * (na_ + nb_ + 1);
+}
+
+// Ghost values of one sweep (section 3.3 boundary conditions: vacuum, thermal,
+// given incident intensity, periodic memory) written where the tiles read them.
+// blockIdx.y: ray, blockIdx.z: bin - f0.
+template <typename Real, bool DFORM>
+__global__ void ghost_fill_kernel(SweepArgs<Real> A)
+{
+    const int ray = blockIdx.y;
+    const int f = A.f0 + (int)blockIdx.z;
+    if (A.frozen[f]) return;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int q = 0;
+    int64_t cq = ghost_count(A, 0);
+    if (e >= cq) {
+        e -= cq;
+        q = 1;
+        cq = ghost_count(A, 1);
+        if (e >= cq) {
+            e -= cq;
+            q = 2;
+            if (e >= ghost_count(A, 2)) return;
+        }
+    }
+    const int na_ = (q == 0) ? A.n[1] : A.n[0], nb_ = (q == 2) ? A.n[1] : A.n[2];
+    const int64_t P0 = (int64_t)(na_ + 1) * (nb_ + 1);
+    int t, ia, ib;
+    if (e < P0) {
+        t = 0;
+        ia = (int)(e % (na_ + 1)) - 1;
+        ib = (int)(e / (na_ + 1)) - 1;
+    } else {
+        const int64_t e2 = e - P0;
+        const int L = na_ + nb_ + 1;
+        t = 1 + (int)(e2 / L);
+        const int k = (int)(e2 % L);
+        ia = (k <= nb_) ? -1 : k - nb_ - 1;
+        ib = (k <= nb_) ? k - 1 : -1;
+    }
+    const int vq = t * T - 1;
+    const int vx = (q == 0) ? vq : ia;
+    const int vy = (q == 1) ? vq : (q == 0 ? ia : ib);
+    const int vz = (q == 2) ? vq : ib;
+    const RayGeo *G = A.rays + ray;
+    TileCtx c;
+    c.f = f;
+    c.par = A.parity[f];
+    c.fbase = (int64_t)f * A.cells;
+    c.sgx = (G->oct & 1) ? -1 : 1;
+    c.sgy = (G->oct & 2) ? -1 : 1;
+    c.sgz = (G->oct & 4) ? -1 : 1;
+    const double *src;
+    int64_t scell;
+    ghost_source(A, c, vx, vy, vz, ray, G->gidx, src, scell);
+    const double I = src ? *src : 0.0;
+    const Real v = DFORM ? Real(I - A.S[scell]) : Real(I);
+    const int ntq = sel3(q, A.nt[0], A.nt[1], A.nt[2]);
+    Real *Fq = (q == 0) ? A.face[0] : (q == 1 ? A.face[1] : A.face[2]);
+    Fq[(((int64_t)f * A.na + ray) * ntq + t) * P0 + (int64_t)(ib + 1) * (na_ + 1) + (ia + 1)] = v;
 }
 
 template <typename Real>
@@ -913,6 +1021,22 @@ hipError_t launch_periodic_cold(const SweepArgs<Real> &A, hipStream_t st)
 }
 template hipError_t launch_periodic_cold<double>(const SweepArgs<double> &, hipStream_t);
 template hipError_t launch_periodic_cold<float>(const SweepArgs<float> &, hipStream_t);
+
+template <typename Real>
+hipError_t launch_ghost_fill(const SweepArgs<Real> &A, hipStream_t st)
+{
+    int64_t tot = 0;
+    for (int q = 0; q < 3; ++q) {
+        const int na_ = (q == 0) ? A.n[1] : A.n[0], nb_ = (q == 2) ? A.n[1] : A.n[2];
+        tot += (int64_t)(na_ + 1) * (nb_ + 1) + (int64_t)(A.nt[q] - 1) * (na_ + nb_ + 1);
+    }
+    dim3 grid(blocks_for(tot, 256), (unsigned)A.na, (unsigned)A.nfc);
+    constexpr bool dform = sizeof(Real) == 4;   // FP32 sweeps use the difference form
+    hipLaunchKernelGGL((ghost_fill_kernel<Real, dform>), grid, dim3(256), 0, st, A);
+    return hipGetLastError();
+}
+template hipError_t launch_ghost_fill<double>(const SweepArgs<double> &, hipStream_t);
+template hipError_t launch_ghost_fill<float>(const SweepArgs<float> &, hipStream_t);
 
 template <typename Real>
 hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,
