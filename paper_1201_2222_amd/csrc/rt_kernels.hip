@@ -29,6 +29,15 @@ constexpr int TILE_LDS = TP * TP * TP;
 constexpr int wave_lds(int nq) { return TILE_LDS + nq * T * T * T; }
 constexpr int NMOM = 10;             // moments mode: J, H_x,y,z, K_xx,yy,zz,xy,xz,yz
 
+// Workgroup barrier for LDS traffic only: no wait for outstanding global stores
+// (__syncthreads also orders global memory, which makes it wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ void wave_lds_sync()
 {
     // make this wave's LDS stores visible to its other lanes (lgkmcnt(0)) and keep
@@ -227,35 +236,55 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
 {
     const int64_t rb = (int64_t)c.f * A.na + ray;
     const int u = lane % T, w = lane / T;   // T * T == 64 face vertices, one per lane
+    // every address and value first, then the stores back to back (a register that a
+    // store still reads must not be reused before the store has completed)
+    Real *pf[3] = {nullptr, nullptr, nullptr};
+    double *pw[3] = {nullptr, nullptr, nullptr};
+    Real vf[3];
+    double vw[3];
     // x face: (y, z) = (u, w)
-    if (u < c.ey && w < c.ez) {
+    {
         const int li = ((w + 1) * TP + (u + 1)) * TP + c.ex;
         const int vy = c.g0y + u, vz = c.g0z + w;
-        if (c.tx < A.nt[0] - 1)
-            A.face[0][(rb * A.nt[0] + c.tx + 1) * A.pplane[0] + (int64_t)(vz + 1) * (A.n[1] + 1) + (vy + 1)] = Ic[li];
-        else if (A.periodic[0])
-            A.wrap[0][(rb * 2 + (c.par ^ 1)) * A.plane[0] + (int64_t)vz * A.n[1] + vy] =
-                DFORM ? double(Ic[li]) + SL[li] : double(Ic[li]);
+        vf[0] = Ic[li];
+        vw[0] = DFORM ? double(vf[0]) + SL[li] : double(vf[0]);
+        if (u < c.ey && w < c.ez) {
+            if (c.tx < A.nt[0] - 1)
+                pf[0] = A.face[0] + (rb * A.nt[0] + c.tx + 1) * A.pplane[0] + (int64_t)(vz + 1) * (A.n[1] + 1) + (vy + 1);
+            else if (A.periodic[0])
+                pw[0] = A.wrap[0] + (rb * 2 + (c.par ^ 1)) * A.plane[0] + (int64_t)vz * A.n[1] + vy;
+        }
     }
     // y face: (x, z) = (u, w)
-    if (u < c.ex && w < c.ez) {
+    {
         const int li = ((w + 1) * TP + c.ey) * TP + (u + 1);
         const int vx = c.g0x + u, vz = c.g0z + w;
-        if (c.ty < A.nt[1] - 1)
-            A.face[1][(rb * A.nt[1] + c.ty + 1) * A.pplane[1] + (int64_t)(vz + 1) * (A.n[0] + 1) + (vx + 1)] = Ic[li];
-        else if (A.periodic[1])
-            A.wrap[1][(rb * 2 + (c.par ^ 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx] =
-                DFORM ? double(Ic[li]) + SL[li] : double(Ic[li]);
+        vf[1] = Ic[li];
+        vw[1] = DFORM ? double(vf[1]) + SL[li] : double(vf[1]);
+        if (u < c.ex && w < c.ez) {
+            if (c.ty < A.nt[1] - 1)
+                pf[1] = A.face[1] + (rb * A.nt[1] + c.ty + 1) * A.pplane[1] + (int64_t)(vz + 1) * (A.n[0] + 1) + (vx + 1);
+            else if (A.periodic[1])
+                pw[1] = A.wrap[1] + (rb * 2 + (c.par ^ 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx;
+        }
     }
     // z face: (x, y) = (u, w)
-    if (u < c.ex && w < c.ey) {
+    {
         const int li = (c.ez * TP + (w + 1)) * TP + (u + 1);
         const int vx = c.g0x + u, vy = c.g0y + w;
-        if (c.tz < A.nt[2] - 1)
-            A.face[2][(rb * A.nt[2] + c.tz + 1) * A.pplane[2] + (int64_t)(vy + 1) * (A.n[0] + 1) + (vx + 1)] = Ic[li];
-        else if (A.periodic[2])
-            A.wrap[2][(rb * 2 + (c.par ^ 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx] =
-                DFORM ? double(Ic[li]) + SL[li] : double(Ic[li]);
+        vf[2] = Ic[li];
+        vw[2] = DFORM ? double(vf[2]) + SL[li] : double(vf[2]);
+        if (u < c.ex && w < c.ey) {
+            if (c.tz < A.nt[2] - 1)
+                pf[2] = A.face[2] + (rb * A.nt[2] + c.tz + 1) * A.pplane[2] + (int64_t)(vy + 1) * (A.n[0] + 1) + (vx + 1);
+            else if (A.periodic[2])
+                pw[2] = A.wrap[2] + (rb * 2 + (c.par ^ 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (pf[q]) *pf[q] = vf[q];
+        if (pw[q]) *pw[q] = vw[q];
     }
 }
 
@@ -294,8 +323,28 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int 
         cq[8] = Real(wd * mx * mz);
         cq[9] = Real(wd * my * mz);
     }
-    // J: the ray's T contributions stay in registers and are added once; moments mode
-    // adds its 10 quantities to the wave's LDS tiles at every step
+    // Per plane, v = I- E + c with the attenuation E and the source term c of the
+    // segment (computed in the step: this keeps few values live).
+    auto coeffs = [&](int p, Real &E, Real &cc) {
+        const int l0 = lb + (p + 1) * SD;
+        const int lu = l0 - SD;
+        const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - SA] + w01 * chiL[lu - SB] + w11 * chiL[lu - SA - SB];
+        const Real dt = s_half * (Cm + chiL[l0]);
+        const double S0 = SL[l0];
+        const double Sm = w00d * SL[lu] + w10d * SL[lu - SA] + w01d * SL[lu - SB] + w11d * SL[lu - SA - SB];
+        if constexpr (DFORM) {
+            Real g;
+            seg_coeffs(dt, E, g);
+            cc = Real(Sm - S0) * g;   // S- - S0 formed in FP64
+        } else {
+            Real pm, p0;
+            seg_coeffs(dt, E, pm, p0);
+            cc = pm * Real(Sm) + p0 * Real(S0);
+        }
+    };
+    // The recurrence along the ray, one plane per step.  J: the ray's T contributions
+    // stay in registers and are added once; moments mode adds its 10 quantities to
+    // the wave's LDS tiles at every step.
     Real jr[T];
 #pragma unroll
     for (int p = 0; p < T; ++p) {
@@ -304,21 +353,10 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int 
             if (act) {
                 const int l0 = lb + (p + 1) * SD;
                 const int lu = l0 - SD;
+                Real E, cc;
+                coeffs(p, E, cc);
                 const Real Im = w00 * Ic[lu] + w10 * Ic[lu - SA] + w01 * Ic[lu - SB] + w11 * Ic[lu - SA - SB];
-                const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - SA] + w01 * chiL[lu - SB] + w11 * chiL[lu - SA - SB];
-                const Real dt = s_half * (Cm + chiL[l0]);
-                const double S0 = SL[l0];
-                const double Sm = w00d * SL[lu] + w10d * SL[lu - SA] + w01d * SL[lu - SB] + w11d * SL[lu - SA - SB];
-                Real v;
-                if constexpr (DFORM) {
-                    Real E, g;
-                    seg_coeffs(dt, E, g);
-                    v = Im * E + Real(Sm - S0) * g;   // S- - S0 formed in FP64
-                } else {
-                    Real E, pm, p0;
-                    seg_coeffs(dt, E, pm, p0);
-                    v = Im * E + pm * Real(Sm) + p0 * Real(S0);
-                }
+                const Real v = Im * E + cc;
                 Ic[l0] = v;
                 if constexpr (NQ == 1) {
                     jr[p] = cq[0] * v;
@@ -358,16 +396,31 @@ __device__ __forceinline__ bool wait_done(const int *flag, int epoch, const int 
     }
 }
 
+// A wave's ray geometry goes through LDS: lanes 0 .. GEO_WORDS - 1 load one word
+// each (issued with the other loads of the tile), then store it in the wave's slot.
+constexpr int GEO_BYTES = 128;
+constexpr int GEO_WORDS = sizeof(RayGeo) / 4;
+static_assert(sizeof(RayGeo) <= GEO_BYTES && sizeof(RayGeo) % 4 == 0, "ray geometry slot");
+
+template <typename Real>
+__device__ __forceinline__ uint32_t geo_load(const SweepArgs<Real> &A, int ray, bool valid, int lane)
+{
+    return (valid && lane < GEO_WORDS) ? reinterpret_cast<const uint32_t *>(A.rays + ray)[lane] : 0u;
+}
+
 // One tile of one octant and bin: stage chi and S with the upwind halo, sweep every
 // ray of the octant through it, write the octant's partial sums.  In the persistent
 // sweep (PERSIST) the upwind face-neighbour tiles are awaited after the staging loads
 // have been issued and before any face data is read.
-template <typename Real, bool DFORM, bool PERSIST, int NQ>
+template <typename Real, bool DFORM, bool PERSIST, int NQ, bool MULTI>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, int f, int packed, int par,
                                            unsigned char *lds_raw, const int *done, int epoch, int ntiles, int nt0,
                                            int nt1, int *err, uint64_t limit_ticks)
 {
-    double *SL = reinterpret_cast<double *>(lds_raw);
+    const int W = blockDim.x >> 6;
+    // LDS: per-wave ray geometry, staged S and chi, per-wave cube and partial sums
+    uint32_t *geoL = reinterpret_cast<uint32_t *>(lds_raw);
+    double *SL = reinterpret_cast<double *>(lds_raw + W * GEO_BYTES);
     Real *chiL = reinterpret_cast<Real *>(SL + TILE_LDS);
     Real *waveL = chiL + TILE_LDS;
 
@@ -388,14 +441,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     c.ey = min(T, A.n[1] - c.g0y);
     c.ez = min(T, A.n[2] - c.g0z);
 
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int W = blockDim.x >> 6;
     Real *Ic = waveL + (size_t)wave * wave_lds(NQ);   // this wave's cube of I (or D)
     Real *Jw = Ic + TILE_LDS;                         // and its partial-sum tiles
+    uint32_t *geo = geoL + wave * (GEO_BYTES / 4);    // and the geometry of its ray
+    const RayGeo *G = reinterpret_cast<const RayGeo *>(geo);
 
-    // the first ray's shell loads go out together with the tile staging loads
+    // the first ray's geometry and shell loads go out together with the staging loads
     Shell<Real> sh;
+    uint32_t gword = geo_load(A, oct * A.R + wave, wave < A.R, lane);
     if (!PERSIST && wave < A.R) shell_load<Real>(A, c, oct * A.R + wave, lane, sh);
 
     // ---- stage chi and S of the tile and its upwind halo in LDS --------------------
@@ -431,6 +486,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         }
     }
     for (int k = lane; k < NQ * T * T * T; k += 64) Jw[k] = Real(0);
+    if (lane < GEO_WORDS) geo[lane] = gword;
     if (!PERSIST && wave < A.R) shell_store<Real>(sh, Ic);
     if (PERSIST) {
         // upwind face neighbours of this tile in the same octant and bin
@@ -448,16 +504,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             shell_store<Real>(sh, Ic);
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- per-wave ray sweeps ---------------------------------------------------------
-    for (int r = wave; r < A.R; r += W) {
-        const int ray = oct * A.R + r;
-        const RayGeo *G = A.rays + ray;
-        // the next ray's shell loads are in flight while this ray is swept
-        const bool more = r + W < A.R;
-        if (more) shell_load<Real>(A, c, ray + W, lane, sh);
-        const int d = G->d, a = G->a, b = 3 - G->d - G->a;
+    // The faces of a wave's last ray are written after the partial sums, so no wait
+    // for their stores stands between the sweep and the sum.
+    int last = -1;
+    auto sweep_ray = [&](int ray) {
+        const int d = __builtin_amdgcn_readfirstlane(G->d), a = __builtin_amdgcn_readfirstlane(G->a);
+        const int b = 3 - d - a;
         const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
         if (d == 0)
             ray_planes<Real, DFORM, NQ, 0>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
@@ -466,14 +521,35 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         else
             ray_planes<Real, DFORM, NQ, 2>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         wave_lds_sync();
-        write_faces<Real, DFORM>(A, c, ray, lane, Ic, SL);
-        wave_lds_sync();
-        if (more) {
-            shell_store<Real>(sh, Ic);
-            wave_lds_sync();
+    };
+    if constexpr (!MULTI) {
+        // at most one ray per wave: straight-line code, nothing kept live across rays
+        if (wave < A.R) {
+            last = oct * A.R + wave;
+            sweep_ray(last);
+        }
+    } else {
+        for (int r = wave; r < A.R; r += W) {
+            const int ray = oct * A.R + r;
+            // the next ray's geometry and shell loads are in flight while this ray is swept
+            const bool more = r + W < A.R;
+            if (more) {
+                gword = geo_load(A, ray + W, true, lane);
+                shell_load<Real>(A, c, ray + W, lane, sh);
+            }
+            sweep_ray(ray);
+            if (more) {
+                write_faces<Real, DFORM>(A, c, ray, lane, Ic, SL);
+                wave_lds_sync();
+                shell_store<Real>(sh, Ic);
+                if (lane < GEO_WORDS) geo[lane] = gword;
+                wave_lds_sync();
+            } else {
+                last = ray;
+            }
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // ---- fixed-order sum over the waves -> this octant's partial sums --------------
     // layout [8][NQ][nfc][cells], bin f stored at f - f0
@@ -489,11 +565,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         Real *outp = A.part + (((int64_t)oct * NQ + q) * A.nfc + (f - A.f0)) * A.cells;
         outp[((int64_t)rz * A.n[1] + ry) * A.n[0] + rx] = acc;
     }
+    if (last >= 0) write_faces<Real, DFORM>(A, c, last, lane, Ic, SL);
 }
 
 // One stage (all tiles with tx + ty + tz = s) of all octants and the active bins
 // f0 .. f0 + nfc - 1.
-template <typename Real, bool DFORM, int NQ>
+template <typename Real, bool DFORM, int NQ, bool MULTI>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -504,7 +581,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
     const int par = A.parity[f];
     const int packed = A.tiles[A.stage_off + item];
     if (frozen) return;
-    sweep_tile<Real, DFORM, false, NQ>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
+    sweep_tile<Real, DFORM, false, NQ, MULTI>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
 // Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
@@ -529,7 +606,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
         const int tile = t - f * D.ntiles;
         if (A.frozen[f]) continue;
         const int packed = A.tiles[tile];
-        sweep_tile<Real, DFORM, true, 1>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
+        sweep_tile<Real, DFORM, true, 1, true>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
                                       D.nt1, D.err, D.wait_ticks);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -941,31 +1018,36 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 size_t sweep_lds_bytes(int real_bytes, int waves, int nq)
 {
-    return sizeof(double) * (size_t)TILE_LDS +
+    return (size_t)waves * GEO_BYTES + sizeof(double) * (size_t)TILE_LDS +
            (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * (size_t)wave_lds(nq));
+}
+
+template <typename Real, bool DFORM, int NQ>
+static void launch_stage(const SweepArgs<Real> &A, int waves, hipStream_t st)
+{
+    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
+    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, NQ);
+    if (A.R > waves)
+        hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, true>), grid, dim3(64 * waves), lds, st, A);
+    else
+        hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, false>), grid, dim3(64 * waves), lds, st, A);
 }
 
 hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq, hipStream_t st)
 {
-    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
     if (nq == NMOM)
-        hipLaunchKernelGGL((sweep_stage_kernel<double, false, NMOM>), grid, dim3(64 * waves),
-                           sweep_lds_bytes(8, waves, nq), st, A);
+        launch_stage<double, false, NMOM>(A, waves, st);
     else
-        hipLaunchKernelGGL((sweep_stage_kernel<double, false, 1>), grid, dim3(64 * waves), sweep_lds_bytes(8, waves, 1),
-                           st, A);
+        launch_stage<double, false, 1>(A, waves, st);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, hipStream_t st)
 {
-    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
     if (nq == NMOM)
-        hipLaunchKernelGGL((sweep_stage_kernel<float, true, NMOM>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves, nq),
-                           st, A);
+        launch_stage<float, true, NMOM>(A, waves, st);
     else
-        hipLaunchKernelGGL((sweep_stage_kernel<float, true, 1>), grid, dim3(64 * waves), sweep_lds_bytes(4, waves, 1),
-                           st, A);
+        launch_stage<float, true, 1>(A, waves, st);
     return hipGetLastError();
 }
 
