@@ -423,7 +423,7 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
 int sweep_waves(int R, bool f32, size_t lds_limit)
 {
     int w = std::min(R, kMaxWaves);
-    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w, 1) > lds_limit) --w;
+    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w, 1, R > w) > lds_limit) --w;
     return w;
 }
 
@@ -716,10 +716,10 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
         (void)hipGetLastError();
         p->wait_ticks = (uint64_t)khz * 20;   // 20 ms
     }
-    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1) > (size_t)lds_limit) {
+    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves) > (size_t)lds_limit) {
         rt_problem_destroy(p);
         return fail(RT_E_UNSUPPORTED, "sweep needs %zu bytes of LDS, device allows %d",
-                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1), lds_limit);
+                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves), lds_limit);
     }
     hipError_t e = hipMemcpy(p->d_rays, p->rays.data(), sizeof(RayGeo) * na, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice);
@@ -963,7 +963,9 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
         mode.f0 = f0;
         mode.nfc = cnt;
         mode.part = p->mom_part;
-        mode.waves = 1;
+        // one ray per wave: the partial sums come from the waves' cubes and the
+        // LDS is that of the J sweep; otherwise one wave with ten accumulated tiles
+        mode.waves = p->R <= p->waves ? p->waves : 1;
         rt_status s = p->f32 ? run_sweep<float>(p, S, st, false, 0, mode) : run_sweep<double>(p, S, st, false, 0, mode);
         if (s != RT_OK) return s;
         HIP_TRY(launch_flip_parity(p->parity, p->frozen, f0, cnt, st));

@@ -86,7 +86,7 @@ constexpr int kUpdateBlocks = 1024;  // update-kernel blocks per bin (grid-strid
 hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq, hipStream_t st);
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, hipStream_t st);
 // dynamic LDS bytes of one sweep workgroup with the given number of waves
-size_t sweep_lds_bytes(int real_bytes, int waves, int nq);
+size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi);
 hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs &D, int waves, int blocks_per_octant,
                                        hipStream_t st);
 hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int blocks_per_octant,

@@ -25,8 +25,9 @@ namespace {
 constexpr int T = kTile;
 constexpr int TP = T + 1;            // tile plus one upwind halo layer
 constexpr int TILE_LDS = TP * TP * TP;
-// Reals of LDS per wave: the cube of I (or D) of its current ray, nq partial-sum tiles
-constexpr int wave_lds(int nq) { return TILE_LDS + nq * T * T * T; }
+// Reals of LDS per wave: the cube of I (or D) of its current ray, and when a wave
+// sweeps several rays of a tile (multi) nq partial-sum tiles that accumulate them
+constexpr int wave_lds(int nq, bool multi) { return TILE_LDS + (multi ? nq * T * T * T : 0); }
 constexpr int NMOM = 10;             // moments mode: J, H_x,y,z, K_xx,yy,zz,xy,xz,yz
 
 // Workgroup barrier for LDS traffic only: no wait for outstanding global stores
@@ -36,6 +37,16 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Order of one wave's LDS accesses across lanes.  The LDS executes a wave's
+// operations in issue order, so a store followed by loads of other lanes' words
+// needs no wait; this only keeps the compiler from moving LDS accesses across.
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -93,21 +104,20 @@ __device__ __forceinline__ void seg_coeffs(double dt, double &E, double &psim, d
 // from its Taylor series sum_n (-dt)^n/(n+1)! below dt = 0.5 (10 terms).
 __device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
 {
+    // both forms are evaluated and one is selected: no branch in the sweep step
     E = __expf(-dt);
-    if (dt < 0.5f) {
-        float acc = 1.0f / 3628800.0f;                    // 1/10!
-        acc = 1.0f / 362880.0f - dt * acc;                // 1/9!
-        acc = 1.0f / 40320.0f - dt * acc;
-        acc = 1.0f / 5040.0f - dt * acc;
-        acc = 1.0f / 720.0f - dt * acc;
-        acc = 1.0f / 120.0f - dt * acc;
-        acc = 1.0f / 24.0f - dt * acc;
-        acc = 1.0f / 6.0f - dt * acc;
-        acc = 0.5f - dt * acc;
-        g = 1.0f - dt * acc;
-    } else {
-        g = (1.0f - E) * __builtin_amdgcn_rcpf(dt);
-    }
+    float acc = 1.0f / 3628800.0f;                    // 1/10!
+    acc = 1.0f / 362880.0f - dt * acc;                // 1/9!
+    acc = 1.0f / 40320.0f - dt * acc;
+    acc = 1.0f / 5040.0f - dt * acc;
+    acc = 1.0f / 720.0f - dt * acc;
+    acc = 1.0f / 120.0f - dt * acc;
+    acc = 1.0f / 24.0f - dt * acc;
+    acc = 1.0f / 6.0f - dt * acc;
+    acc = 0.5f - dt * acc;
+    const float gs = 1.0f - dt * acc;
+    const float gc = (1.0f - E) * __builtin_amdgcn_rcpf(dt);
+    g = dt < 0.5f ? gs : gc;
 }
 
 // Per-workgroup tile description, all scalars (no arrays indexed by a runtime axis).
@@ -293,7 +303,35 @@ constexpr int tile_stride(int q) { return q == 0 ? 1 : (q == 1 ? T : T * T); }
 
 // Plane-by-plane sweep of one ray through the tile along its first-crossed axis D
 // (all strides compile-time).  Lane (ia, ib) owns one vertex of every plane.
-template <typename Real, bool DFORM, int NQ, int D>
+// Weight of a ray in accumulated quantity q: w (J); moments mode also w mu_i (H)
+// and w mu_i mu_j (K, order xx yy zz xy xz yz).  Products formed as in the sweep.
+template <typename Real, int NQ>
+__device__ __forceinline__ Real ray_weight(const RayGeo *G, int q)
+{
+    const double wd = G->wk;
+    if (NQ == 1 || q == 0) return Real(wd);
+    const double mx = G->mu[0], my = G->mu[1], mz = G->mu[2];
+    switch (q) {
+    case 1: return Real(wd * mx);
+    case 2: return Real(wd * my);
+    case 3: return Real(wd * mz);
+    case 4: return Real(wd * mx * mx);
+    case 5: return Real(wd * my * my);
+    case 6: return Real(wd * mz * mz);
+    case 7: return Real(wd * mx * my);
+    case 8: return Real(wd * mx * mz);
+    default: return Real(wd * my * mz);
+    }
+}
+
+// Upwind and own chi and S of one vertex of a plane, as loaded from the staged tile.
+template <typename Real>
+struct SegIn {
+    Real c00, c10, c01, c11, c0;
+    double s00, s10, s01, s11, s0;
+};
+
+template <typename Real, bool ACC, int NQ, int D, bool DFORM>
 __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int eb, int lane, Real *Ic,
                                            const Real *chiL, const double *SL, Real *Jw)
 {
@@ -310,68 +348,73 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int 
     // weights of this ray in the accumulated quantities: w (J), and in moments mode
     // also w mu_i (H) and w mu_i mu_j (K)
     Real cq[NQ];
-    cq[0] = Real(G->wk);
-    if constexpr (NQ == NMOM) {
-        const double mx = G->mu[0], my = G->mu[1], mz = G->mu[2], wd = G->wk;
-        cq[1] = Real(wd * mx);
-        cq[2] = Real(wd * my);
-        cq[3] = Real(wd * mz);
-        cq[4] = Real(wd * mx * mx);
-        cq[5] = Real(wd * my * my);
-        cq[6] = Real(wd * mz * mz);
-        cq[7] = Real(wd * mx * my);
-        cq[8] = Real(wd * mx * mz);
-        cq[9] = Real(wd * my * mz);
-    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) cq[q] = ray_weight<Real, NQ>(G, q);
     // Per plane, v = I- E + c with the attenuation E and the source term c of the
-    // segment (computed in the step: this keeps few values live).
-    auto coeffs = [&](int p, Real &E, Real &cc) {
+    // segment; they do not depend on the intensity, so their loads run two planes
+    // ahead and their arithmetic one plane ahead of the recurrence.
+    auto load_seg = [&](int p) {
         const int l0 = lb + (p + 1) * SD;
         const int lu = l0 - SD;
-        const Real Cm = w00 * chiL[lu] + w10 * chiL[lu - SA] + w01 * chiL[lu - SB] + w11 * chiL[lu - SA - SB];
-        const Real dt = s_half * (Cm + chiL[l0]);
-        const double S0 = SL[l0];
-        const double Sm = w00d * SL[lu] + w10d * SL[lu - SA] + w01d * SL[lu - SB] + w11d * SL[lu - SA - SB];
+        SegIn<Real> x;
+        x.c00 = chiL[lu];
+        x.c10 = chiL[lu - SA];
+        x.c01 = chiL[lu - SB];
+        x.c11 = chiL[lu - SA - SB];
+        x.c0 = chiL[l0];
+        x.s00 = SL[lu];
+        x.s10 = SL[lu - SA];
+        x.s01 = SL[lu - SB];
+        x.s11 = SL[lu - SA - SB];
+        x.s0 = SL[l0];
+        return x;
+    };
+    auto seg = [&](const SegIn<Real> &x, Real &E, Real &cc) {
+        const Real Cm = w00 * x.c00 + w10 * x.c10 + w01 * x.c01 + w11 * x.c11;
+        const Real dt = s_half * (Cm + x.c0);
+        const double Sm = w00d * x.s00 + w10d * x.s10 + w01d * x.s01 + w11d * x.s11;
         if constexpr (DFORM) {
             Real g;
             seg_coeffs(dt, E, g);
-            cc = Real(Sm - S0) * g;   // S- - S0 formed in FP64
+            cc = Real(Sm - x.s0) * g;   // S- - S0 formed in FP64
         } else {
             Real pm, p0;
             seg_coeffs(dt, E, pm, p0);
-            cc = pm * Real(Sm) + p0 * Real(S0);
+            cc = pm * Real(Sm) + p0 * Real(x.s0);
         }
     };
-    // The recurrence along the ray, one plane per step.  J: the ray's T contributions
-    // stay in registers and are added once; moments mode adds its 10 quantities to
-    // the wave's LDS tiles at every step.
-    Real jr[T];
+    // The recurrence along the ray, one plane per step.  Every lane steps (no
+    // branch): a lane outside a ragged tile writes only entries no active lane reads.
+    // When the wave sweeps several rays of the tile (ACC), w v (and in moments mode
+    // w mu v, w mu mu v) is added to its partial-sum tiles per vertex; with one ray
+    // per wave the cube itself keeps v for the sum over the waves.
+    Real E, cc;
+    seg(load_seg(0), E, cc);
+    SegIn<Real> nx = load_seg(1);
 #pragma unroll
     for (int p = 0; p < T; ++p) {
-        jr[p] = Real(0);
         if (p < ed) {
-            if (act) {
-                const int l0 = lb + (p + 1) * SD;
-                const int lu = l0 - SD;
-                Real E, cc;
-                coeffs(p, E, cc);
-                const Real Im = w00 * Ic[lu] + w10 * Ic[lu - SA] + w01 * Ic[lu - SB] + w11 * Ic[lu - SA - SB];
-                const Real v = Im * E + cc;
-                Ic[l0] = v;
-                if constexpr (NQ == 1) {
-                    jr[p] = cq[0] * v;
-                } else {
+            const int l0 = lb + (p + 1) * SD;
+            const int lu = l0 - SD;
+            const Real i00 = Ic[lu], i10 = Ic[lu - SA], i01 = Ic[lu - SB], i11 = Ic[lu - SA - SB];
+            SegIn<Real> nn;
+            if (p + 2 < T) nn = load_seg(p + 2);   // inside the cube even past a ragged edge
+            Real En = Real(0), ccn = Real(0);
+            if (p + 1 < T) seg(nx, En, ccn);
+            const Real v = (w00 * i00 + w10 * i10 + w01 * i01 + w11 * i11) * E + cc;
+            Ic[l0] = v;
+            if constexpr (ACC) {
+                const int j = jbase + p * JD;
+                if (act) {
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + jbase + p * JD] += cq[q] * v;
+                    for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + j] += cq[q] * v;
                 }
             }
-            wave_lds_sync();
+            wave_lds_order();
+            E = En;
+            cc = ccn;
+            if (p + 2 < T) nx = nn;
         }
-    }
-    if (NQ == 1 && act) {
-#pragma unroll
-        for (int p = 0; p < T; ++p)
-            if (p < ed) Jw[jbase + p * JD] += jr[p];
     }
 }
 
@@ -443,8 +486,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    Real *Ic = waveL + (size_t)wave * wave_lds(NQ);   // this wave's cube of I (or D)
-    Real *Jw = Ic + TILE_LDS;                         // and its partial-sum tiles
+    Real *Ic = waveL + (size_t)wave * wave_lds(NQ, MULTI);   // this wave's cube of I (or D)
+    Real *Jw = Ic + TILE_LDS;                                // and its partial-sum tiles (MULTI)
     uint32_t *geo = geoL + wave * (GEO_BYTES / 4);    // and the geometry of its ray
     const RayGeo *G = reinterpret_cast<const RayGeo *>(geo);
 
@@ -454,9 +497,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     if (!PERSIST && wave < A.R) shell_load<Real>(A, c, oct * A.R + wave, lane, sh);
 
     // ---- stage chi and S of the tile and its upwind halo in LDS --------------------
-    // each pass issues all of its loads before the first LDS store
+    // each pass issues all of its loads before the first LDS store.  Inside the grid
+    // the real cell index is linear in the flipped local coordinates (strides dX, dY,
+    // dZ); only tiles whose upwind halo leaves the grid fold indices per axis.
     const Real *chif = A.chi + c.fbase;
     const double *Sf = A.S + c.fbase;
+    const int dX = c.sgx, dY = c.sgy * A.n[0], dZ = c.sgz * A.n[0] * A.n[1];
+    const bool inner = c.tx > 0 && c.ty > 0 && c.tz > 0;
+    const int64_t cellH = inner ? ((int64_t)to_real(c.g0z - 1, c.sgz, A.n[2]) * A.n[1] +
+                                   to_real(c.g0y - 1, c.sgy, A.n[1])) * A.n[0] + to_real(c.g0x - 1, c.sgx, A.n[0])
+                                : 0;
     constexpr int STAGE_K = 3;   // one pass for four or more waves
     for (int base = 0; base < TILE_LDS; base += STAGE_K * (int)blockDim.x) {
         Real cv[STAGE_K];
@@ -470,10 +520,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             cv[k] = Real(0);
             sv[k] = 0.0;
             if (idx >= TILE_LDS || lx > c.ex || ly > c.ey || lz > c.ez) continue;
-            const int rx = fold(to_real(c.g0x + lx - 1, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
-            const int ry = fold(to_real(c.g0y + ly - 1, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
-            const int rz = fold(to_real(c.g0z + lz - 1, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
-            const int64_t cell = ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
+            int64_t cell;
+            if (inner) {
+                cell = cellH + (lx * dX + ly * dY + lz * dZ);
+            } else {
+                const int rx = fold(to_real(c.g0x + lx - 1, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
+                const int ry = fold(to_real(c.g0y + ly - 1, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
+                const int rz = fold(to_real(c.g0z + lz - 1, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
+                cell = ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
+            }
             li[k] = idx;
             cv[k] = chif[cell];
             sv[k] = Sf[cell];
@@ -485,7 +540,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             SL[li[k]] = sv[k];
         }
     }
-    for (int k = lane; k < NQ * T * T * T; k += 64) Jw[k] = Real(0);
+    if (MULTI)   // several rays per wave accumulate; one ray stores
+        for (int k = lane; k < NQ * T * T * T; k += 64) Jw[k] = Real(0);
     if (lane < GEO_WORDS) geo[lane] = gword;
     if (!PERSIST && wave < A.R) shell_store<Real>(sh, Ic);
     if (PERSIST) {
@@ -515,11 +571,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         const int b = 3 - d - a;
         const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
         if (d == 0)
-            ray_planes<Real, DFORM, NQ, 0>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 0, DFORM>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         else if (d == 1)
-            ray_planes<Real, DFORM, NQ, 1>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 1, DFORM>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         else
-            ray_planes<Real, DFORM, NQ, 2>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 2, DFORM>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         wave_lds_sync();
     };
     if constexpr (!MULTI) {
@@ -553,17 +609,57 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
 
     // ---- fixed-order sum over the waves -> this octant's partial sums --------------
     // layout [8][NQ][nfc][cells], bin f stored at f - f0
-    for (int kq = threadIdx.x; kq < NQ * T * T * T; kq += blockDim.x) {
-        const int q = kq / (T * T * T), k = kq - q * T * T * T;
-        const int lx = k % T, ly = (k / T) % T, lz = k / (T * T);
-        if (lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
-        Real acc = waveL[TILE_LDS + kq];
-        for (int w = 1; w < W; ++w) acc += waveL[(size_t)w * wave_lds(NQ) + TILE_LDS + kq];
-        const int rx = to_real(c.g0x + lx, c.sgx, A.n[0]);
-        const int ry = to_real(c.g0y + ly, c.sgy, A.n[1]);
-        const int rz = to_real(c.g0z + lz, c.sgz, A.n[2]);
-        Real *outp = A.part + (((int64_t)oct * NQ + q) * A.nfc + (f - A.f0)) * A.cells;
-        outp[((int64_t)rz * A.n[1] + ry) * A.n[0] + rx] = acc;
+    const int64_t cell0 = ((int64_t)to_real(c.g0z, c.sgz, A.n[2]) * A.n[1] + to_real(c.g0y, c.sgy, A.n[1])) * A.n[0] +
+                          to_real(c.g0x, c.sgx, A.n[0]);
+    // a pass computes all of its sums before its stores (a register a store still
+    // reads must not be reused before the store has completed)
+    constexpr int COMB_K = 2;
+    // Loads of absent waves (w >= W) read wave 0 and are weighted by zero: no
+    // branch on W, every load of a vertex goes out at once, and adding the zeros
+    // leaves the sum in wave order unchanged.
+    Real wkw[kMaxWaves];   // J weights of the waves' rays (one ray per wave), 0 beyond W
+#pragma unroll
+    for (int w = 0; w < kMaxWaves; ++w) {
+        const int wr = w < W ? w : 0;
+        wkw[w] = ray_weight<Real, 1>(reinterpret_cast<const RayGeo *>(geoL + wr * (GEO_BYTES / 4)), 0) *
+                 Real(w < W ? 1 : 0);
+    }
+    for (int base = 0; base < NQ * T * T * T; base += COMB_K * (int)blockDim.x) {
+        Real acc[COMB_K];
+        Real *dst[COMB_K];
+#pragma unroll
+        for (int i = 0; i < COMB_K; ++i) {
+            const int kq = base + i * (int)blockDim.x + (int)threadIdx.x;
+            const int q = kq / (T * T * T), k = kq - q * T * T * T;
+            const int lx = k % T, ly = (k / T) % T, lz = k / (T * T);
+            dst[i] = nullptr;
+            acc[i] = Real(0);
+            if (kq >= NQ * T * T * T || lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
+            // the accumulated tiles (MULTI), or w v from each wave's cube
+            Real vw[kMaxWaves];
+            const int ci = ((lz + 1) * TP + (ly + 1)) * TP + (lx + 1);
+#pragma unroll
+            for (int w = 0; w < kMaxWaves; ++w) {
+                const int wr = w < W ? w : 0;
+                if constexpr (MULTI) {
+                    const Real val = waveL[wr * wave_lds(NQ, true) + TILE_LDS + kq];
+                    vw[w] = w < W ? val : Real(0);
+                } else {
+                    Real cw = wkw[w];
+                    if constexpr (NQ != 1)
+                        cw = ray_weight<Real, NQ>(reinterpret_cast<const RayGeo *>(geoL + wr * (GEO_BYTES / 4)), q) *
+                             Real(w < W ? 1 : 0);
+                    vw[w] = cw * waveL[wr * wave_lds(NQ, false) + ci];
+                }
+            }
+            acc[i] = vw[0];
+#pragma unroll
+            for (int w = 1; w < kMaxWaves; ++w) acc[i] += vw[w];
+            dst[i] = A.part + (((int64_t)oct * NQ + q) * A.nfc + (f - A.f0)) * A.cells + cell0 + (lx * dX + ly * dY + lz * dZ);
+        }
+#pragma unroll
+        for (int i = 0; i < COMB_K; ++i)
+            if (dst[i]) *dst[i] = acc[i];
     }
     if (last >= 0) write_faces<Real, DFORM>(A, c, last, lane, Ic, SL);
 }
@@ -580,7 +676,8 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
     const int frozen = A.frozen[f];
     const int par = A.parity[f];
     const int packed = A.tiles[A.stage_off + item];
-    if (frozen) return;
+    // the three loads go out together (every value takes part in the test)
+    if (frozen | (packed < 0) | (par < 0)) return;
     sweep_tile<Real, DFORM, false, NQ, MULTI>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
@@ -1016,18 +1113,19 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
-size_t sweep_lds_bytes(int real_bytes, int waves, int nq)
+size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi)
 {
     return (size_t)waves * GEO_BYTES + sizeof(double) * (size_t)TILE_LDS +
-           (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * (size_t)wave_lds(nq));
+           (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * (size_t)wave_lds(nq, multi));
 }
 
 template <typename Real, bool DFORM, int NQ>
 static void launch_stage(const SweepArgs<Real> &A, int waves, hipStream_t st)
 {
     dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
-    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, NQ);
-    if (A.R > waves)
+    const bool multi = A.R > waves;
+    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, NQ, multi);
+    if (multi)
         hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, true>), grid, dim3(64 * waves), lds, st, A);
     else
         hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, false>), grid, dim3(64 * waves), lds, st, A);
@@ -1056,7 +1154,7 @@ static hipError_t launch_persistent(const SweepArgs<Real> &A, const DagArgs &D, 
                                     hipStream_t st)
 {
     hipLaunchKernelGGL((sweep_persistent_kernel<Real, DFORM>), dim3(8u * (unsigned)blocks_per_octant), dim3(64 * waves),
-                       sweep_lds_bytes(sizeof(Real), waves, 1), st, A, D);
+                       sweep_lds_bytes(sizeof(Real), waves, 1, true), st, A, D);
     return hipGetLastError();
 }
 
@@ -1072,7 +1170,7 @@ hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs 
 
 hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks)
 {
-    const size_t lds = sweep_lds_bytes(real_bytes, waves, 1);
+    const size_t lds = sweep_lds_bytes(real_bytes, waves, 1, true);
     if (real_bytes == 8)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<double, false>, 64 * waves, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<float, true>, 64 * waves, lds);
