@@ -35,6 +35,27 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_UPDATE_F32 = 12 + 2 + 5 + 6 + 3 + 1
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per sweep-stage launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (calibrated against a plain copy), or None when the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
+                                                                                   "kernel_source_sha256:")))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def _pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -141,8 +162,9 @@ def main():
     kernel_s = prof["kernel_ms"] / 1e3
     achieved = prof["updates"] * OPS_PER_UPDATE_F32 / kernel_s / 1e12 if kernel_s > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "kernel": "sweep_stage_kernel<float, true>",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(),
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": "sweep_stage_kernel<float, true, 1, false>",
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
                 "ops_per_update": OPS_PER_UPDATE_F32}

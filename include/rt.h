@@ -196,14 +196,15 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
 
 /*
  * Sweep-kernel timing, for measuring the formal solution against its roofline.
- * While enabled, every sweep stage launch of one formal solution (the first
- * iteration of each convergence-check interval of rt_ali_solve, and every
- * rt_formal_solve) is bracketed by HIP events on the call's stream; the durations
- * are summed when the events have completed.  Enabling (or disabling) resets the
- * totals.  Timing adds two event records per stage launch to the timed sweeps.
+ * While enabled, the stage launches of one formal solution (the first iteration of
+ * each convergence-check interval of rt_ali_solve, and every rt_formal_solve) are
+ * bracketed by two HIP events on the call's stream, after the ghost-value pass and
+ * after the last stage; the durations are summed when the events have completed,
+ * so a launch's share includes the gap to the next launch.  Enabling (or
+ * disabling) resets the totals.
  */
 typedef struct {
-    double kernel_ms;     /* summed duration of the timed sweep-stage launches */
+    double kernel_ms;     /* summed duration of the timed back-to-back stage launches */
     int64_t launches;     /* number of timed launches */
     int64_t sweeps;       /* number of timed formal solutions */
     double updates;       /* cell*ray*bin updates done by those launches */

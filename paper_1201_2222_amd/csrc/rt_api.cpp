@@ -276,7 +276,7 @@ struct rt_problem {
     // sweep-kernel timing (rt_problem_profile)
     bool prof = false;
     bool prof_pending = false;
-    std::vector<hipEvent_t> ev;        // start/stop per stage
+    std::vector<hipEvent_t> ev;        // start/stop of a timed sweep
     double prof_ms = 0.0, prof_updates = 0.0, prof_pending_updates = 0.0;
     int64_t prof_launches = 0, prof_sweeps = 0;
 };
@@ -428,18 +428,17 @@ int sweep_waves(int R, bool f32, size_t lds_limit)
 }
 
 // One formal solution over every active bin: the tile stages in order.
-// Accumulate the durations of timed sweep stages once their events have completed.
+// Accumulate the duration of a timed sweep once its events have completed: two
+// events bracket the back-to-back stage launches (per-launch events would delay
+// every launch), so a launch's share includes the gap to the next launch.
 rt_status collect_timing(rt_problem *p)
 {
     if (!p->prof_pending) return RT_OK;
-    const int launches = p->persistent ? 1 : p->nstages;
-    for (int s = 0; s < launches; ++s) {
-        HIP_TRY(hipEventSynchronize(p->ev[2 * s + 1]));
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, p->ev[2 * s], p->ev[2 * s + 1]));
-        p->prof_ms += ms;
-        ++p->prof_launches;
-    }
+    HIP_TRY(hipEventSynchronize(p->ev[1]));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+    p->prof_ms += ms;
+    p->prof_launches += p->persistent ? 1 : p->nstages;
     p->prof_updates += p->prof_pending_updates;
     ++p->prof_sweeps;
     p->prof_pending = false;
@@ -504,12 +503,12 @@ rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed =
     for (int s = 0; s < p->nstages; ++s) {
         A.stage_off = p->stage_off[s];
         A.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
-        if (timed) HIP_TRY(hipEventRecord(p->ev[2 * s], st));
+        if (timed && s == 0) HIP_TRY(hipEventRecord(p->ev[0], st));
         if constexpr (sizeof(Real) == 8)
             HIP_TRY(launch_sweep_stage_f64(A, W, mode.nq, st));
         else
             HIP_TRY(launch_sweep_stage_f32(A, W, mode.nq, st));
-        if (timed) HIP_TRY(hipEventRecord(p->ev[2 * s + 1], st));
+        if (timed && s == p->nstages - 1) HIP_TRY(hipEventRecord(p->ev[1], st));
     }
     if (timed) {
         p->prof_pending = true;
@@ -885,7 +884,7 @@ rt_status rt_problem_profile(rt_problem *p, int32_t enable)
     rt_status s = collect_timing(p);
     if (s != RT_OK) return s;
     if (enable && p->ev.empty()) {
-        p->ev.resize(2 * (size_t)std::max(p->nstages, 1));
+        p->ev.resize(2);
         for (auto &e : p->ev) HIP_TRY(hipEventCreate(&e));
     }
     p->prof = enable != 0;
