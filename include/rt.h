@@ -170,6 +170,27 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
  * (host arrays [nf]; either may be NULL).  Synchronises the stream. */
 rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream);
 
+/*
+ * rt_ali_solve_batch -- rt_ali_solve for n independent problems at once (bins and
+ * problems do not couple, section 3.1).  Each problem keeps its own grid, rays,
+ * bins, boundaries and precision; they may all differ.  Problems of the same sweep
+ * precision and waves per workgroup share every launch: per iteration one ghost-value
+ * launch, one launch per stage index covering that hyperplane of all of them, one
+ * update and one convergence launch.  A problem that meets the stopping rule (or its
+ * max_iter / fixed_iters) leaves the batch at the next check; the others go on.
+ * Results per problem are those rt_ali_solve gives for it alone (identical
+ * arithmetic).  problems: host array [n] of distinct problems with fields set;
+ * S_inout, J_out: host arrays [n] of device pointers as for rt_ali_solve; stats,
+ * results: host arrays [n] or NULL (per-problem RT_OK / RT_NOT_CONVERGED /
+ * RT_E_NONFINITE; stats.seconds = wall time until that problem left the batch).
+ * opts apply to every problem.  Returns RT_E_NONFINITE if any problem hit a
+ * non-finite residual, else RT_NOT_CONVERGED if any did not converge, else RT_OK.
+ * Synchronises the stream every check_every iterations.
+ */
+rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_ali_opts *opts,
+                             double *const *S_inout, double *const *J_out, rt_ali_stats *stats,
+                             rt_status *results, void *stream);
+
 typedef struct {
     double *J;         /* device [nf][cells] or NULL */
     double *H;         /* device [3][nf][cells] or NULL */

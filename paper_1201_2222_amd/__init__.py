@@ -25,7 +25,8 @@ RT_SCHED_DEFAULT, RT_SCHED_STAGES, RT_SCHED_PERSISTENT = 0, 1, 2
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
-           "rt_ali_solve", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read")
+           "rt_ali_solve", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
+           "rt_ali_solve_batch")
 
 
 class RtError(RuntimeError):
@@ -93,6 +94,7 @@ def load():
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
     lib.rt_problem_profile.argtypes = [P, I32]
     lib.rt_problem_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
+    lib.rt_ali_solve_batch.argtypes = [P, I32, ctypes.POINTER(AliOpts), P, P, P, P, P]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     _lib = lib
@@ -220,6 +222,29 @@ def rt_ali_solve(p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_s
     _check(status, allow=(RT_OK, RT_NOT_CONVERGED))
     return status, {"iterations": st.iterations, "bins_converged": st.bins_converged,
                     "max_rel_dS": st.max_rel_dS, "seconds": st.seconds}
+
+
+def rt_ali_solve_batch(problems, S_list, J_list, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True,
+                       warm_start=0, check_every=0, stream=None):
+    """Batched ALI over independent problems (handles); returns (status, [per-problem status],
+    [per-problem stats dict]).  RT_E_NONFINITE is returned, not raised, so the per-problem
+    results can be inspected; other errors raise."""
+    n = len(problems)
+    if len(S_list) != n or len(J_list) != n:
+        raise ValueError("problems, S_list and J_list must have the same length")
+    o = AliOpts(float(delta_c), int(max_iter), int(fixed_iters), 1 if per_bin_stop else 0, int(warm_start),
+                int(check_every))
+    probs = (ctypes.c_void_p * n)(*[ctypes.c_void_p(h.value if isinstance(h, ctypes.c_void_p) else h)
+                                    for h in problems])
+    Sp = (ctypes.c_void_p * n)(*[_dptr(S, name="S").value for S in S_list])
+    Jp = (ctypes.c_void_p * n)(*[_dptr(J, S.numel(), "J").value for S, J in zip(S_list, J_list)])
+    st = (AliStats * n)()
+    res = (ctypes.c_int * n)()
+    status = load().rt_ali_solve_batch(probs, n, ctypes.byref(o), Sp, Jp, st, res, _stream(stream))
+    _check(status, allow=(RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE))
+    stats = [{"iterations": x.iterations, "bins_converged": x.bins_converged, "max_rel_dS": x.max_rel_dS,
+              "seconds": x.seconds} for x in st]
+    return status, list(res), stats
 
 
 def rt_ali_bin_stats(p, nf, stream=None):

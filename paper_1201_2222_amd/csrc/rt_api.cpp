@@ -245,6 +245,7 @@ struct rt_problem {
     // device state
     RayGeo *d_rays = nullptr;
     int *d_tiles = nullptr;
+    int *d_stage_tab = nullptr;        // device copy of stage_off (batched launches)
     double *chi64 = nullptr, *eps = nullptr, *B = nullptr, *lam = nullptr;
     float *chi32 = nullptr;
     void *face[3]{};                   // Real [nf][na][nt_q][pplane_q]
@@ -414,6 +415,8 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
     A.tiles = p->d_tiles;
     A.frozen = p->frozen;
     A.parity = p->parity;
+    A.stage_tab = p->d_stage_tab;
+    A.nstages = p->nstages;
     return A;
 }
 
@@ -523,6 +526,30 @@ rt_status sweep_current_S(rt_problem *p, const double *S64, hipStream_t st, bool
     return run_sweep<double>(p, S64, st, timed, active);
 }
 
+// Start values of an ALI solve (section 5.1: J = B start, S = B; section 4: S from
+// the previous J) and cleared per-bin control words.
+rt_status ali_start(rt_problem *p, const rt_ali_opts *opts, double *S, const double *J, hipStream_t st)
+{
+    const int64_t nc = p->cells * p->nf;
+    if (opts->warm_start == 0)
+        HIP_TRY(hipMemcpyAsync(S, p->B, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    else if (opts->warm_start == 2)
+        HIP_TRY(launch_warm_start(p->B, p->eps, J, S, nc, st));
+    HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
+    HIP_TRY(hipMemsetAsync(p->iters, 0, sizeof(int) * p->nf, st));
+    HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int) * 4, st));
+    return RT_OK;
+}
+
+rt_status check_ali_opts(const rt_ali_opts *opts)
+{
+    if (opts->fixed_iters < 0) return fail(RT_E_INVALID, "fixed_iters must be >= 0");
+    if (opts->fixed_iters == 0 && (opts->max_iter < 1 || !(opts->delta_c >= 0.0)))
+        return fail(RT_E_INVALID, "need max_iter >= 1 and delta_c >= 0");
+    if (opts->warm_start < 0 || opts->warm_start > 2) return fail(RT_E_INVALID, "warm_start must be 0, 1 or 2");
+    return RT_OK;
+}
+
 AliCtl ctl_of(rt_problem *p)
 {
     AliCtl c;
@@ -534,6 +561,297 @@ AliCtl ctl_of(rt_problem *p)
     c.nblk = kUpdateBlocks;
     c.flags = p->flags;
     return c;
+}
+
+// ---------------------------------------------------------------------------------
+// Batched Jacobi ALI over independent problems on one stream.  Problems with the same
+// sweep precision and waves per workgroup form a class; per iteration a class runs
+// one ghost-value launch, one launch per stage index covering that stage of all its
+// problems (grid y = problem), one update launch and one finalize launch, so the many
+// small stages of small problems share launches.  Problems retire at the convergence
+// checks and new ones can join there (the serving loop).
+// ---------------------------------------------------------------------------------
+struct BatchItem {
+    rt_problem *p = nullptr;
+    double *S = nullptr, *J = nullptr;
+    rt_ali_opts opts{};
+    int issued = 0;        // iterations issued so far
+    int total = 0;         // fixed_iters, or max_iter
+    bool nonfinite = false;
+    uint64_t tag = 0;      // caller's handle (batch index, server ticket)
+};
+
+int64_t ghost_entries(const rt_problem *p)
+{
+    int64_t t = 0;
+    for (int q = 0; q < 3; ++q) {
+        const int na_ = (q == 0) ? p->n[1] : p->n[0], nb_ = (q == 2) ? p->n[1] : p->n[2];
+        t += (int64_t)(na_ + 1) * (nb_ + 1) + (int64_t)(p->nt[q] - 1) * (na_ + nb_ + 1);
+    }
+    return t;
+}
+
+class BatchRunner {
+  public:
+    explicit BatchRunner(hipStream_t st) : st_(st) {}
+    ~BatchRunner()
+    {
+        for (Class &c : classes_) free_class(c);
+        for (Class &c : spare_) free_class(c);
+        if (d_done_) (void)hipFree(d_done_);
+        if (h_done_) (void)hipHostFree(h_done_);
+    }
+    size_t size() const { return items_.size(); }
+    const std::vector<BatchItem> &items() const { return items_; }
+
+    // Queue start values and the cold periodic memory of a new member.
+    rt_status add(const BatchItem &it)
+    {
+        rt_problem *p = it.p;
+        rt_status s = ali_start(p, &it.opts, it.S, it.J, st_);
+        if (s != RT_OK) return s;
+        if (p->cold) {
+            if (p->f32)
+                HIP_TRY(launch_periodic_cold<float>(sweep_args<float>(p, it.S), st_));
+            else
+                HIP_TRY(launch_periodic_cold<double>(sweep_args<double>(p, it.S), st_));
+            p->cold = false;
+        }
+        items_.push_back(it);
+        dirty_ = true;
+        return RT_OK;
+    }
+
+    // Issue the next iterations of every member (up to `every`, never past a member's
+    // total), then read the stop flags (synchronises the stream).  Members that stopped
+    // or reached their total move to `finished`.
+    rt_status chunk(int every, std::vector<BatchItem> &finished)
+    {
+        if (items_.empty()) return RT_OK;
+        if (dirty_) {
+            rt_status s = rebuild();
+            if (s != RT_OK) return s;
+        }
+        int k = every;
+        for (const BatchItem &it : items_) k = std::min(k, it.total - it.issued);
+        k = std::max(k, 1);
+        for (int j = 0; j < k; ++j)
+            for (Class &c : classes_) {
+                const int n = (int)c.idx.size();
+                if (c.f32) {
+                    const SweepArgs<float> *a = static_cast<const SweepArgs<float> *>(c.d_args);
+                    HIP_TRY(launch_ghost_fill_batch<float>(a, n, c.max_ghost, c.max_na, st_));
+                    for (size_t st = 0; st < c.max_items.size(); ++st)
+                        HIP_TRY(launch_sweep_batch_stage_f32(a, n, (int)st, c.max_items[st], c.waves, c.multi, st_));
+                    HIP_TRY(launch_ali_update_batch<float>(c.d_upd, n, kBatchUpdateBlocks, c.max_nf, st_));
+                } else {
+                    const SweepArgs<double> *a = static_cast<const SweepArgs<double> *>(c.d_args);
+                    HIP_TRY(launch_ghost_fill_batch<double>(a, n, c.max_ghost, c.max_na, st_));
+                    for (size_t st = 0; st < c.max_items.size(); ++st)
+                        HIP_TRY(launch_sweep_batch_stage_f64(a, n, (int)st, c.max_items[st], c.waves, c.multi, st_));
+                    HIP_TRY(launch_ali_update_batch<double>(c.d_upd, n, kBatchUpdateBlocks, c.max_nf, st_));
+                }
+                HIP_TRY(launch_ali_finalize_batch(c.d_upd, n, d_done_ + 2 * c.done_off, st_));
+            }
+        for (BatchItem &it : items_) it.issued += k;
+        HIP_TRY(hipMemcpyAsync(h_done_, d_done_, sizeof(int) * 2 * items_.size(), hipMemcpyDeviceToHost, st_));
+        HIP_TRY(hipStreamSynchronize(st_));
+        std::vector<int> pos(items_.size());   // member -> its slot in the flag array
+        for (const Class &c : classes_)
+            for (size_t j = 0; j < c.idx.size(); ++j) pos[c.idx[j]] = c.done_off + (int)j;
+        std::vector<BatchItem> keep;
+        for (size_t i = 0; i < items_.size(); ++i) {
+            BatchItem it = items_[i];
+            const int g = pos[i];
+            it.nonfinite = h_done_[2 * g + 1] != 0;
+            if (h_done_[2 * g] || it.issued >= it.total)
+                finished.push_back(it);
+            else
+                keep.push_back(it);
+        }
+        if (keep.size() != items_.size()) dirty_ = true;
+        items_.swap(keep);
+        if (dirty_ && !items_.empty()) return rebuild();   // class indices follow the new order
+        return RT_OK;
+    }
+
+  private:
+    struct Class {
+        bool f32 = false;
+        int waves = 1;
+        bool multi = false;
+        std::vector<int> idx;                 // members (positions in items_)
+        std::vector<unsigned char> h_args;    // SweepArgs<Real> per member
+        std::vector<BatchUpdate> h_upd;
+        void *d_args = nullptr;
+        BatchUpdate *d_upd = nullptr;
+        size_t cap = 0;                       // members the device arrays hold
+        std::vector<int> max_items;           // per stage index: max workgroups over members
+        int64_t max_ghost = 0;
+        int max_na = 0, max_nf = 0, done_off = 0;
+    };
+    hipStream_t st_;
+    std::vector<BatchItem> items_;
+    std::vector<Class> classes_, spare_;
+    int *d_done_ = nullptr;
+    int *h_done_ = nullptr;
+    size_t done_cap_ = 0;
+    bool dirty_ = true;
+
+    static void free_class(Class &c)
+    {
+        if (c.d_args) (void)hipFree(c.d_args);
+        if (c.d_upd) (void)hipFree(c.d_upd);
+        c.d_args = nullptr;
+        c.d_upd = nullptr;
+        c.cap = 0;
+    }
+
+    template <typename Real>
+    void fill_args(Class &c)
+    {
+        c.h_args.assign(c.idx.size() * sizeof(SweepArgs<Real>), 0);
+        SweepArgs<Real> *a = reinterpret_cast<SweepArgs<Real> *>(c.h_args.data());
+        for (size_t j = 0; j < c.idx.size(); ++j) {
+            const BatchItem &it = items_[c.idx[j]];
+            a[j] = sweep_args<Real>(it.p, it.S);
+        }
+    }
+
+    rt_status rebuild()
+    {
+        // keep the device arrays of the old classes for reuse
+        for (Class &c : classes_) {
+            c.idx.clear();
+            spare_.push_back(std::move(c));
+        }
+        classes_.clear();
+        for (size_t i = 0; i < items_.size(); ++i) {
+            const rt_problem *p = items_[i].p;
+            const bool multi = p->R > p->waves;
+            Class *cls = nullptr;
+            for (Class &c : classes_)
+                if (c.f32 == p->f32 && c.waves == p->waves && c.multi == multi) cls = &c;
+            if (!cls) {
+                Class c;
+                if (!spare_.empty()) {
+                    c = std::move(spare_.back());
+                    spare_.pop_back();
+                }
+                c.f32 = p->f32;
+                c.waves = p->waves;
+                c.multi = multi;
+                classes_.push_back(std::move(c));
+                cls = &classes_.back();
+            }
+            cls->idx.push_back((int)i);
+        }
+        int off = 0;
+        for (Class &c : classes_) {
+            const size_t n = c.idx.size();
+            if (c.f32)
+                fill_args<float>(c);
+            else
+                fill_args<double>(c);
+            c.h_upd.resize(n);
+            c.max_items.clear();
+            c.max_ghost = 0;
+            c.max_na = c.max_nf = 0;
+            for (size_t j = 0; j < n; ++j) {
+                const BatchItem &it = items_[c.idx[j]];
+                rt_problem *p = it.p;
+                BatchUpdate &u = c.h_upd[j];
+                u.part = p->part;
+                u.B = p->B;
+                u.eps = p->eps;
+                u.lam = p->lam;
+                u.S64 = it.S;
+                u.J = it.J;
+                u.cells = p->cells;
+                u.nf = p->nf;
+                u.dform = p->f32 ? 1 : 0;
+                u.ctl = ctl_of(p);
+                u.ctl.nblk = kBatchUpdateBlocks;
+                u.fixed_mode = it.opts.fixed_iters > 0 ? 1 : 0;
+                u.delta_c = it.opts.delta_c;
+                u.per_bin_stop = it.opts.per_bin_stop ? 1 : 0;
+                if ((int)c.max_items.size() < p->nstages) c.max_items.resize(p->nstages, 0);
+                for (int s2 = 0; s2 < p->nstages; ++s2)
+                    c.max_items[s2] = std::max(c.max_items[s2], (p->stage_off[s2 + 1] - p->stage_off[s2]) * 8 * p->nf);
+                c.max_ghost = std::max(c.max_ghost, ghost_entries(p) * p->nf);
+                c.max_na = std::max(c.max_na, p->na);
+                c.max_nf = std::max(c.max_nf, p->nf);
+            }
+            if (c.cap < n) {
+                free_class(c);
+                const size_t cap = std::max<size_t>(n, 8);
+                const size_t asz = c.f32 ? sizeof(SweepArgs<float>) : sizeof(SweepArgs<double>);
+                hipError_t e = hipMalloc(&c.d_args, cap * std::max(sizeof(SweepArgs<float>), sizeof(SweepArgs<double>)));
+                if (e == hipSuccess) e = hipMalloc((void **)&c.d_upd, cap * sizeof(BatchUpdate));
+                (void)asz;
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    free_class(c);
+                    return fail(RT_E_OOM, "batch descriptor allocation failed");
+                }
+                c.cap = cap;
+            }
+            HIP_TRY(hipMemcpyAsync(c.d_args, c.h_args.data(), c.h_args.size(), hipMemcpyHostToDevice, st_));
+            HIP_TRY(hipMemcpyAsync(c.d_upd, c.h_upd.data(), n * sizeof(BatchUpdate), hipMemcpyHostToDevice, st_));
+            c.done_off = off;
+            off += (int)n;
+        }
+        if (done_cap_ < items_.size()) {
+            if (d_done_) (void)hipFree(d_done_);
+            if (h_done_) (void)hipHostFree(h_done_);
+            d_done_ = nullptr;
+            h_done_ = nullptr;
+            const size_t cap = std::max<size_t>(items_.size(), 64);
+            hipError_t e = hipMalloc((void **)&d_done_, sizeof(int) * 2 * cap);
+            if (e == hipSuccess) e = hipHostMalloc((void **)&h_done_, sizeof(int) * 2 * cap, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                done_cap_ = 0;
+                return fail(RT_E_OOM, "batch flag allocation failed");
+            }
+            done_cap_ = cap;
+        }
+        // host arrays must outlive the copies: wait for them here
+        HIP_TRY(hipStreamSynchronize(st_));
+        dirty_ = false;
+        return RT_OK;
+    }
+};
+
+// Per-problem results of an ALI solve, read from the device (synchronises).
+rt_status ali_stats(rt_problem *p, const rt_ali_opts *opts, bool nonfinite, double seconds, rt_ali_stats *stats,
+                    hipStream_t st, rt_status *result)
+{
+    std::vector<int> iters(p->nf);
+    std::vector<double> resid(p->nf);
+    HIP_TRY(hipMemcpyAsync(iters.data(), p->iters, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(resid.data(), p->resid, sizeof(double) * p->nf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int conv = 0, maxit = 0;
+    double maxr = 0.0;
+    for (int f = 0; f < p->nf; ++f) {
+        conv += resid[f] <= opts->delta_c;
+        maxit = std::max(maxit, iters[f]);
+        maxr = std::max(maxr, resid[f]);
+    }
+    if (stats) {
+        stats->iterations = maxit;
+        stats->bins_converged = conv;
+        stats->max_rel_dS = maxr;
+        stats->seconds = seconds;
+    }
+    if (nonfinite)
+        *result = RT_E_NONFINITE;
+    else if (opts->fixed_iters == 0 && conv < p->nf)
+        *result = RT_NOT_CONVERGED;
+    else
+        *result = RT_OK;
+    return RT_OK;
 }
 
 }  // namespace
@@ -665,6 +983,7 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     } while (0)
     ALLOC(p->d_rays, (size_t)na);
     ALLOC(p->d_tiles, tiles.size());
+    ALLOC(p->d_stage_tab, p->stage_off.size());
     ALLOC(p->chi64, (size_t)nc);
     ALLOC(p->eps, (size_t)nc);
     ALLOC(p->B, (size_t)nc);
@@ -722,6 +1041,8 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     }
     hipError_t e = hipMemcpy(p->d_rays, p->rays.data(), sizeof(RayGeo) * na, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_stage_tab, p->stage_off.data(), sizeof(int) * p->stage_off.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->frozen, 0, sizeof(int) * p->nf);
     if (e == hipSuccess) e = hipMemset(p->parity, 0, sizeof(int) * p->nf);
     if (e == hipSuccess) e = hipMemset(p->flags, 0, sizeof(int) * 4);
@@ -787,22 +1108,20 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
     if (!p || !opts) return fail(RT_E_INVALID, "problem and opts are required");
     if (!S_inout || !J_out) return fail(RT_E_INVALID, "S_inout and J_out are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
-    if (opts->fixed_iters < 0) return fail(RT_E_INVALID, "fixed_iters must be >= 0");
-    if (opts->fixed_iters == 0 && (opts->max_iter < 1 || !(opts->delta_c >= 0.0)))
-        return fail(RT_E_INVALID, "need max_iter >= 1 and delta_c >= 0");
-    if (opts->warm_start < 0 || opts->warm_start > 2) return fail(RT_E_INVALID, "warm_start must be 0, 1 or 2");
+    {
+        rt_status so = check_ali_opts(opts);
+        if (so != RT_OK) return so;
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nc = p->cells * p->nf;
     const size_t bytes = sizeof(double) * nc;
 
-    // start value (section 5.1: J = B start; section 4: S from the previous J)
-    if (opts->warm_start == 0)
-        HIP_TRY(hipMemcpyAsync(S_inout, p->B, bytes, hipMemcpyDeviceToDevice, st));
-    else if (opts->warm_start == 2)
-        HIP_TRY(launch_warm_start(p->B, p->eps, J_out, S_inout, nc, st));
-    HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
-    HIP_TRY(hipMemsetAsync(p->iters, 0, sizeof(int) * p->nf, st));
-    HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int) * 4, st));
+    (void)nc;
+    (void)bytes;
+    {
+        rt_status s0 = ali_start(p, opts, S_inout, J_out, st);
+        if (s0 != RT_OK) return s0;
+    }
 
     const bool fixed = opts->fixed_iters > 0;
     const int total = fixed ? opts->fixed_iters : opts->max_iter;
@@ -994,6 +1313,64 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
         *out->heating = *p->h_sum;
     }
     return RT_OK;
+}
+
+rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_ali_opts *opts, double *const *S_inout,
+                             double *const *J_out, rt_ali_stats *stats, rt_status *results, void *stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!problems || !opts || !S_inout || !J_out) return fail(RT_E_INVALID, "problems, opts, S_inout and J_out are required");
+    if (n < 1) return fail(RT_E_INVALID, "n must be >= 1");
+    {
+        rt_status so = check_ali_opts(opts);
+        if (so != RT_OK) return so;
+    }
+    for (int i = 0; i < n; ++i) {
+        rt_problem *p = problems[i];
+        if (!p) return fail(RT_E_INVALID, "problem %d is NULL", i);
+        if (!S_inout[i] || !J_out[i]) return fail(RT_E_INVALID, "S_inout/J_out of problem %d missing", i);
+        if (!p->have_fields) return fail(RT_E_INVALID, "problem %d: rt_problem_set_fields has not been called", i);
+        for (int j = 0; j < i; ++j)
+            if (problems[j] == p) return fail(RT_E_INVALID, "problem %d appears twice in the batch", i);
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BatchRunner run(st);
+    for (int i = 0; i < n; ++i) {
+        BatchItem it;
+        it.p = problems[i];
+        it.S = S_inout[i];
+        it.J = J_out[i];
+        it.opts = *opts;
+        it.total = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
+        it.tag = (uint64_t)i;
+        rt_status s = run.add(it);
+        if (s != RT_OK) return s;
+    }
+    const int every = opts->fixed_iters > 0 ? opts->fixed_iters : (opts->check_every > 0 ? opts->check_every : 16);
+    std::vector<BatchItem> finished;
+    std::vector<double> secs(n, 0.0);
+    std::vector<char> nonfin(n, 0);
+    while (run.size() > 0) {
+        const size_t before = finished.size();
+        rt_status s = run.chunk(every, finished);
+        if (s != RT_OK) return s;
+        const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (size_t k = before; k < finished.size(); ++k) {
+            secs[finished[k].tag] = t;
+            nonfin[finished[k].tag] = finished[k].nonfinite;
+        }
+    }
+    rt_status worst = RT_OK;
+    for (int i = 0; i < n; ++i) {
+        rt_status r = RT_OK;
+        rt_status s = ali_stats(problems[i], opts, nonfin[i] != 0, secs[i], stats ? &stats[i] : nullptr, st, &r);
+        if (s != RT_OK) return s;
+        if (results) results[i] = r;
+        if (r == RT_E_NONFINITE) worst = RT_E_NONFINITE;
+        else if (r == RT_NOT_CONVERGED && worst == RT_OK) worst = RT_NOT_CONVERGED;
+    }
+    if (worst == RT_E_NONFINITE) return fail(RT_E_NONFINITE, "non-finite residual in at least one problem of the batch");
+    return worst;
 }
 
 }  // extern "C"

@@ -52,6 +52,8 @@ struct SweepArgs {
     int stage_off, stage_cnt;
     const int *frozen;        // [nf]
     const int *parity;        // [nf]: periodic slot read this sweep
+    const int *stage_tab;     // [nstages + 1] offsets of the stages in tiles (batched launches)
+    int nstages;
 };
 
 // Dependency state of the persistent sweep: one completion flag per (bin, octant,
@@ -80,6 +82,19 @@ struct AliCtl {
 };
 
 constexpr int kUpdateBlocks = 1024;  // update-kernel blocks per bin (grid-stride)
+constexpr int kBatchUpdateBlocks = 128;  // per bin and problem in a batched update
+
+// One problem of a batched Jacobi update (rt_ali_solve_batch).
+struct BatchUpdate {
+    const void *part;         // Real [8][nf][cells]
+    const double *B, *eps, *lam;
+    double *S64, *J;
+    int64_t cells;
+    int nf, dform;
+    AliCtl ctl;               // ctl.nblk = kBatchUpdateBlocks
+    double delta_c;           // stopping rule of this problem's solve
+    int per_bin_stop, fixed_mode;
+};
 
 // Kernel launchers (rt_kernels.hip).  All return hipError_t of the launch.
 // nq = 1: partial sums of w I (or w D); nq = 10: also w mu I and w mu mu I (moments)
@@ -104,6 +119,19 @@ hipError_t launch_periodic_cold(const SweepArgs<Real> &A, hipStream_t st);
 // sweep about to run.
 template <typename Real>
 hipError_t launch_ghost_fill(const SweepArgs<Real> &A, hipStream_t st);
+
+// Batched launches over the problems of one batch class (device arrays of per-problem
+// arguments; sizes are the maxima over the problems).
+hipError_t launch_sweep_batch_stage_f64(const SweepArgs<double> *args, int nprob, int s, int max_items, int waves,
+                                        bool multi, hipStream_t st);
+hipError_t launch_sweep_batch_stage_f32(const SweepArgs<float> *args, int nprob, int s, int max_items, int waves,
+                                        bool multi, hipStream_t st);
+template <typename Real>
+hipError_t launch_ghost_fill_batch(const SweepArgs<Real> *args, int nprob, int64_t max_entries, int max_na,
+                                   hipStream_t st);
+template <typename Real>
+hipError_t launch_ali_update_batch(const BatchUpdate *bu, int nprob, int nblk, int max_nf, hipStream_t st);
+hipError_t launch_ali_finalize_batch(const BatchUpdate *bu, int nprob, int *done, hipStream_t st);
 
 template <typename Real>
 hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,

@@ -681,6 +681,29 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
     sweep_tile<Real, DFORM, false, NQ, MULTI>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
+// Batched form: one launch runs stage s of every problem of a batch class (same
+// precision and waves per workgroup).  blockIdx.y is the problem; x runs over its
+// bins, tiles of stage s and octants.  Problems with fewer stages, and blocks beyond
+// a problem's stage, exit at once.
+template <typename Real, bool DFORM, bool MULTI>
+__global__ void __launch_bounds__(64 * kMaxWaves) sweep_batch_stage_kernel(const SweepArgs<Real> *args, int s)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const SweepArgs<Real> &A = args[blockIdx.y];
+    if (s >= A.nstages) return;
+    const int off = A.stage_tab[s];
+    const int per = (A.stage_tab[s + 1] - off) * 8;
+    if ((int)blockIdx.x >= per * A.nf) return;
+    const int f = (int)blockIdx.x / per;
+    const int rem = (int)blockIdx.x - f * per;
+    const int oct = rem & 7;
+    const int frozen = A.frozen[f];
+    const int par = A.parity[f];
+    const int packed = A.tiles[off + (rem >> 3)];
+    if (frozen | (packed < 0) | (par < 0)) return;
+    sweep_tile<Real, DFORM, false, 1, MULTI>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
+}
+
 // Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
 // octant o: they draw tickets from that octant's counter; ticket t is tile
 // tiles[t % ntiles] of bin t / ntiles, so every tile's upwind neighbours carry
@@ -788,14 +811,12 @@ __device__ __forceinline__ int64_t ghost_count(const SweepArgs<Real> &A, int q)
 // given incident intensity, periodic memory) written where the tiles read them.
 // blockIdx.y: ray, blockIdx.z: bin - f0.
 template <typename Real, bool DFORM>
-__global__ void ghost_fill_kernel(SweepArgs<Real> A)
+__device__ __forceinline__ void ghost_fill_one(const SweepArgs<Real> &A, int ray, int f, int64_t e)
 {
-    const int ray = blockIdx.y;
-    const int f = A.f0 + (int)blockIdx.z;
     if (A.frozen[f]) return;
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int q = 0;
     int64_t cq = ghost_count(A, 0);
+    if (e < 0) return;
     if (e >= cq) {
         e -= cq;
         q = 1;
@@ -844,6 +865,33 @@ __global__ void ghost_fill_kernel(SweepArgs<Real> A)
 }
 
 template <typename Real>
+__device__ __forceinline__ int64_t ghost_total(const SweepArgs<Real> &A)
+{
+    return ghost_count(A, 0) + ghost_count(A, 1) + ghost_count(A, 2);
+}
+
+// blockIdx.y: ray, blockIdx.z: bin - f0.
+template <typename Real, bool DFORM>
+__global__ void ghost_fill_kernel(SweepArgs<Real> A)
+{
+    ghost_fill_one<Real, DFORM>(A, blockIdx.y, A.f0 + (int)blockIdx.z, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched form: blockIdx.z is the problem, blockIdx.y the ray, x runs over bins and entries.
+template <typename Real, bool DFORM>
+__global__ void ghost_fill_batch_kernel(const SweepArgs<Real> *args)
+{
+    const SweepArgs<Real> &A = args[blockIdx.z];
+    const int ray = blockIdx.y;
+    if (ray >= A.na) return;
+    const int64_t tot = ghost_total(A);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tot * A.nf) return;
+    const int f = (int)(i / tot);
+    ghost_fill_one<Real, DFORM>(A, ray, f, i - (int64_t)f * tot);
+}
+
+template <typename Real>
 __global__ void partial_sum_kernel(const Real *part, const double *S, int dform, int nf, int64_t cells,
                                    const int *frozen, double *J)
 {
@@ -872,16 +920,15 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // both in FP64.  With dform the partials hold sum w (I - S), so J - S is summed
 // without cancellation.  Each block writes its max to blockmax (no atomics).
 template <typename Real>
-__global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int dform, int nf, int64_t cells,
-                                                         const double *B, const double *eps,
-                                                         const double *lam, double *S64, double *Jout, AliCtl ctl)
+__device__ __forceinline__ void ali_update_body(const Real *part, int dform, int nf, int64_t cells, const double *B,
+                                                const double *eps, const double *lam, double *S64, double *Jout,
+                                                const AliCtl &ctl, int f)
 {
     __shared__ unsigned long long red[4];
-    const int f = blockIdx.y;
     if (ctl.frozen[f]) return;
     const int64_t stride = (int64_t)nf * cells;
     unsigned long long rb = 0ull;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)ctl.nblk * blockDim.x) {
         const int64_t i = (int64_t)f * cells + c;
         double sum = 0.0;
 #pragma unroll
@@ -912,10 +959,28 @@ __global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int d
     }
 }
 
+template <typename Real>
+__global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int dform, int nf, int64_t cells,
+                                                         const double *B, const double *eps,
+                                                         const double *lam, double *S64, double *Jout, AliCtl ctl)
+{
+    ali_update_body<Real>(part, dform, nf, cells, B, eps, lam, S64, Jout, ctl, blockIdx.y);
+}
+
+// Batched form: blockIdx.z is the problem, blockIdx.y the bin, x the ctl.nblk blocks.
+template <typename Real>
+__global__ void __launch_bounds__(256) ali_update_batch_kernel(const BatchUpdate *bu)
+{
+    const BatchUpdate &U = bu[blockIdx.z];
+    if ((int)blockIdx.y >= U.nf || (int)blockIdx.x >= U.ctl.nblk) return;
+    ali_update_body<Real>(static_cast<const Real *>(U.part), U.dform, U.nf, U.cells, U.B, U.eps, U.lam, U.S64, U.J,
+                          U.ctl, blockIdx.y);
+}
+
 // Per-bin convergence test (eq. conv) after an update: reduce the block maxima,
 // count the iteration, flip the periodic slot, freeze converged bins.
-__global__ void __launch_bounds__(256) ali_finalize_kernel(AliCtl ctl, int nf, double delta_c, int per_bin_stop,
-                                                           int fixed_mode)
+__device__ __forceinline__ void ali_finalize_body(const AliCtl &ctl, int nf, double delta_c, int per_bin_stop,
+                                                  int fixed_mode)
 {
     __shared__ unsigned long long red[4];
     __shared__ int s_all_conv, s_nonfinite, s_active;
@@ -961,6 +1026,25 @@ __global__ void __launch_bounds__(256) ali_finalize_kernel(AliCtl ctl, int nf, d
             for (int f = 0; f < nf; ++f) ctl.frozen[f] = 1;
             ctl.flags[0] = 1;
         }
+    }
+}
+
+__global__ void __launch_bounds__(256) ali_finalize_kernel(AliCtl ctl, int nf, double delta_c, int per_bin_stop,
+                                                           int fixed_mode)
+{
+    ali_finalize_body(ctl, nf, delta_c, per_bin_stop, fixed_mode);
+}
+
+// Batched form: one block per problem; the problem's stop flags are also copied into
+// done[2 p], done[2 p + 1] so the host reads one array for the whole batch.
+__global__ void __launch_bounds__(256) ali_finalize_batch_kernel(const BatchUpdate *bu, int *done)
+{
+    const BatchUpdate &U = bu[blockIdx.x];
+    ali_finalize_body(U.ctl, U.nf, U.delta_c, U.per_bin_stop, U.fixed_mode);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        done[2 * blockIdx.x] = U.ctl.flags[0];
+        done[2 * blockIdx.x + 1] = U.ctl.flags[1];
     }
 }
 
@@ -1150,6 +1234,32 @@ hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, 
 }
 
 template <typename Real, bool DFORM>
+static void launch_batch_stage(const SweepArgs<Real> *args, int nprob, int s, int max_items, int waves, bool multi,
+                               hipStream_t st)
+{
+    dim3 grid((unsigned)max_items, (unsigned)nprob);
+    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, 1, multi);
+    if (multi)
+        hipLaunchKernelGGL((sweep_batch_stage_kernel<Real, DFORM, true>), grid, dim3(64 * waves), lds, st, args, s);
+    else
+        hipLaunchKernelGGL((sweep_batch_stage_kernel<Real, DFORM, false>), grid, dim3(64 * waves), lds, st, args, s);
+}
+
+hipError_t launch_sweep_batch_stage_f64(const SweepArgs<double> *args, int nprob, int s, int max_items, int waves,
+                                        bool multi, hipStream_t st)
+{
+    launch_batch_stage<double, false>(args, nprob, s, max_items, waves, multi, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_batch_stage_f32(const SweepArgs<float> *args, int nprob, int s, int max_items, int waves,
+                                        bool multi, hipStream_t st)
+{
+    launch_batch_stage<float, true>(args, nprob, s, max_items, waves, multi, st);
+    return hipGetLastError();
+}
+
+template <typename Real, bool DFORM>
 static hipError_t launch_persistent(const SweepArgs<Real> &A, const DagArgs &D, int waves, int blocks_per_octant,
                                     hipStream_t st)
 {
@@ -1217,6 +1327,34 @@ hipError_t launch_ghost_fill(const SweepArgs<Real> &A, hipStream_t st)
 }
 template hipError_t launch_ghost_fill<double>(const SweepArgs<double> &, hipStream_t);
 template hipError_t launch_ghost_fill<float>(const SweepArgs<float> &, hipStream_t);
+
+template <typename Real>
+hipError_t launch_ghost_fill_batch(const SweepArgs<Real> *args, int nprob, int64_t max_entries, int max_na,
+                                   hipStream_t st)
+{
+    dim3 grid(blocks_for(max_entries, 256), (unsigned)max_na, (unsigned)nprob);
+    constexpr bool dform = sizeof(Real) == 4;
+    hipLaunchKernelGGL((ghost_fill_batch_kernel<Real, dform>), grid, dim3(256), 0, st, args);
+    return hipGetLastError();
+}
+template hipError_t launch_ghost_fill_batch<double>(const SweepArgs<double> *, int, int64_t, int, hipStream_t);
+template hipError_t launch_ghost_fill_batch<float>(const SweepArgs<float> *, int, int64_t, int, hipStream_t);
+
+template <typename Real>
+hipError_t launch_ali_update_batch(const BatchUpdate *bu, int nprob, int nblk, int max_nf, hipStream_t st)
+{
+    hipLaunchKernelGGL(ali_update_batch_kernel<Real>, dim3((unsigned)nblk, (unsigned)max_nf, (unsigned)nprob),
+                       dim3(256), 0, st, bu);
+    return hipGetLastError();
+}
+template hipError_t launch_ali_update_batch<double>(const BatchUpdate *, int, int, int, hipStream_t);
+template hipError_t launch_ali_update_batch<float>(const BatchUpdate *, int, int, int, hipStream_t);
+
+hipError_t launch_ali_finalize_batch(const BatchUpdate *bu, int nprob, int *done, hipStream_t st)
+{
+    hipLaunchKernelGGL(ali_finalize_batch_kernel, dim3((unsigned)nprob), dim3(256), 0, st, bu, done);
+    return hipGetLastError();
+}
 
 template <typename Real>
 hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,
