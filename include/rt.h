@@ -46,7 +46,8 @@ typedef enum {
     RT_E_OOM = -2,          /* device allocation failed */
     RT_E_HIP = -3,          /* a HIP runtime call failed */
     RT_E_NONFINITE = -4,    /* a residual became NaN or Inf */
-    RT_E_UNSUPPORTED = -5   /* valid request this build does not implement */
+    RT_E_UNSUPPORTED = -5,  /* valid request this build does not implement */
+    RT_E_BUSY = -6          /* rt_server_poll: the request is queued or running */
 } rt_status;
 
 /* Sweep arithmetic.  RT_F64 integrates I itself in FP64 ("plain form").
@@ -190,6 +191,44 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
 rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_ali_opts *opts,
                              double *const *S_inout, double *const *J_out, rt_ali_stats *stats,
                              rt_status *results, void *stream);
+
+/*
+ * Serving loop: ALI solves submitted at any time run together in one batch (as in
+ * rt_ali_solve_batch) on a worker thread of the server with its own stream on the
+ * device that was current at rt_server_create.  Requests are admitted in arrival
+ * order at the batch's convergence checks while the summed rt_problem_bytes of the
+ * admitted problems stays within hbm_budget (a request larger than the budget runs
+ * alone); the rest wait in the queue.  A problem keeps its device state between
+ * requests, so a request with opts.warm_start = 1 or 2 continues from the caller's
+ * S or J and the problem's periodic memory (warm starts for later snapshots,
+ * section 4).  While a request is queued or running the caller must not use its
+ * problem, S or J.  check_every: iterations between checks (0 = 16).
+ */
+typedef struct rt_server rt_server;
+
+rt_status rt_server_create(size_t hbm_budget, int32_t check_every, rt_server **out);
+
+/* Queue an ALI solve (arguments as for rt_ali_solve); *ticket identifies it.
+ * The problem must not be part of another queued or running request. */
+rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opts, double *S_inout,
+                           double *J_out, uint64_t *ticket);
+
+/* RT_E_BUSY while the request is queued or running; RT_OK once it has finished,
+ * with *result its solve status (RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE, or the
+ * error that stopped the batch) and *stats its statistics (seconds = time from
+ * submission to completion, queueing included).  Either output may be NULL.  A
+ * finished ticket can be polled until rt_server_release; unknown tickets give
+ * RT_E_INVALID.  Never blocks on the device. */
+rt_status rt_server_poll(rt_server *srv, uint64_t ticket, rt_ali_stats *stats, rt_status *result);
+
+/* Forget a finished ticket's record. */
+rt_status rt_server_release(rt_server *srv, uint64_t ticket);
+
+/* Counts of queued and running requests (either may be NULL). */
+rt_status rt_server_load(rt_server *srv, int32_t *queued, int32_t *running);
+
+/* Finish every queued and running request, stop the worker and free the server. */
+rt_status rt_server_destroy(rt_server *srv);
 
 typedef struct {
     double *J;         /* device [nf][cells] or NULL */

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librtsc.so")
 
 RT_OK, RT_NOT_CONVERGED = 0, 1
-RT_E_INVALID, RT_E_OOM, RT_E_HIP, RT_E_NONFINITE, RT_E_UNSUPPORTED = -1, -2, -3, -4, -5
+RT_E_INVALID, RT_E_OOM, RT_E_HIP, RT_E_NONFINITE, RT_E_UNSUPPORTED, RT_E_BUSY = -1, -2, -3, -4, -5, -6
 RT_F64, RT_F32 = 0, 1
 RT_BC_VACUUM, RT_BC_THERMAL, RT_BC_PERIODIC, RT_BC_FIXED = 0, 1, 2, 3
 RT_SCHED_DEFAULT, RT_SCHED_STAGES, RT_SCHED_PERSISTENT = 0, 1, 2
@@ -26,7 +26,8 @@ RT_SCHED_DEFAULT, RT_SCHED_STAGES, RT_SCHED_PERSISTENT = 0, 1, 2
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
            "rt_ali_solve", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
-           "rt_ali_solve_batch")
+           "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
+           "rt_server_load", "rt_server_destroy")
 
 
 class RtError(RuntimeError):
@@ -95,6 +96,12 @@ def load():
     lib.rt_problem_profile.argtypes = [P, I32]
     lib.rt_problem_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
     lib.rt_ali_solve_batch.argtypes = [P, I32, ctypes.POINTER(AliOpts), P, P, P, P, P]
+    lib.rt_server_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
+    lib.rt_server_submit.argtypes = [P, P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.rt_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(AliStats), ctypes.POINTER(ctypes.c_int)]
+    lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
+    lib.rt_server_load.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.rt_server_destroy.argtypes = [P]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     _lib = lib
@@ -245,6 +252,48 @@ def rt_ali_solve_batch(problems, S_list, J_list, delta_c=1e-6, max_iter=10000, f
     stats = [{"iterations": x.iterations, "bins_converged": x.bins_converged, "max_rel_dS": x.max_rel_dS,
               "seconds": x.seconds} for x in st]
     return status, list(res), stats
+
+
+def rt_server_create(hbm_budget, check_every=0):
+    h = ctypes.c_void_p()
+    _check(load().rt_server_create(int(hbm_budget), int(check_every), ctypes.byref(h)))
+    return h
+
+
+def rt_server_submit(srv, p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True, warm_start=0,
+                     check_every=0):
+    o = AliOpts(float(delta_c), int(max_iter), int(fixed_iters), 1 if per_bin_stop else 0, int(warm_start),
+                int(check_every))
+    t = ctypes.c_uint64()
+    _check(load().rt_server_submit(srv, p, ctypes.byref(o), _dptr(S, name="S"), _dptr(J, S.numel(), "J"),
+                                   ctypes.byref(t)))
+    return t.value
+
+
+def rt_server_poll(srv, ticket):
+    """None while the request is queued or running, else (result status, stats dict)."""
+    st = AliStats()
+    res = ctypes.c_int()
+    status = load().rt_server_poll(srv, ctypes.c_uint64(ticket), ctypes.byref(st), ctypes.byref(res))
+    if status == RT_E_BUSY:
+        return None
+    _check(status)
+    return res.value, {"iterations": st.iterations, "bins_converged": st.bins_converged,
+                       "max_rel_dS": st.max_rel_dS, "seconds": st.seconds}
+
+
+def rt_server_release(srv, ticket):
+    return _check(load().rt_server_release(srv, ctypes.c_uint64(ticket)))
+
+
+def rt_server_load(srv):
+    q, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().rt_server_load(srv, ctypes.byref(q), ctypes.byref(r)))
+    return q.value, r.value
+
+
+def rt_server_destroy(srv):
+    return _check(load().rt_server_destroy(srv))
 
 
 def rt_ali_bin_stats(p, nf, stream=None):

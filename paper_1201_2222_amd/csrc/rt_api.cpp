@@ -8,6 +8,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -868,6 +873,7 @@ const char *rt_status_string(rt_status s)
     case RT_E_HIP: return "HIP runtime error";
     case RT_E_NONFINITE: return "non-finite residual";
     case RT_E_UNSUPPORTED: return "unsupported";
+    case RT_E_BUSY: return "busy";
     }
     return "unknown status";
 }
@@ -1374,3 +1380,222 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------
+// Serving loop (rt_server_*): a worker thread owns a stream and a BatchRunner; it
+// admits queued requests at the batch's checks within the HBM budget, runs one check
+// interval of the whole batch, and records the requests that finished.
+// ---------------------------------------------------------------------------------
+struct rt_server {
+    struct Request {
+        BatchItem item;
+        size_t bytes = 0;
+        std::chrono::steady_clock::time_point t_submit;
+        bool done = false;
+        rt_status result = RT_OK;
+        rt_ali_stats stats{};
+    };
+    int device = 0;
+    size_t budget = 0;
+    int every = 16;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<uint64_t> queue;              // waiting tickets, arrival order
+    std::map<uint64_t, Request> reqs;        // every unreleased ticket
+    size_t running_bytes = 0;
+    int running = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    bool dead = false;                       // the worker has exited after a failure
+    std::thread worker;
+
+    void finish(uint64_t t, rt_status r, const rt_ali_stats &st)
+    {
+        Request &q = reqs[t];
+        q.done = true;
+        q.result = r;
+        q.stats = st;
+        q.stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - q.t_submit).count();
+        running_bytes -= q.bytes;
+        --running;
+    }
+
+    void run()
+    {
+        (void)hipSetDevice(device);
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            std::lock_guard<std::mutex> lk(mu);
+            dead = true;
+            for (uint64_t t : queue) {
+                reqs[t].done = true;
+                reqs[t].result = RT_E_HIP;
+            }
+            queue.clear();
+            cv.notify_all();
+            return;
+        }
+        {
+            BatchRunner batch(st);
+            for (;;) {
+                std::vector<uint64_t> admit;
+                {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return stop || !queue.empty() || batch.size() > 0; });
+                    if (stop && queue.empty() && batch.size() == 0) break;
+                    while (!queue.empty()) {
+                        Request &q = reqs[queue.front()];
+                        if (running > 0 && running_bytes + q.bytes > budget) break;
+                        admit.push_back(queue.front());
+                        running_bytes += q.bytes;
+                        ++running;
+                        queue.pop_front();
+                    }
+                }
+                for (uint64_t t : admit) {
+                    BatchItem it;
+                    {
+                        std::lock_guard<std::mutex> lk(mu);
+                        it = reqs[t].item;
+                    }
+                    rt_status s = batch.add(it);
+                    if (s != RT_OK) {
+                        std::lock_guard<std::mutex> lk(mu);
+                        finish(t, s, rt_ali_stats{});
+                    }
+                }
+                if (batch.size() == 0) continue;
+                std::vector<BatchItem> fin;
+                rt_status s = batch.chunk(every, fin);
+                if (s != RT_OK) {
+                    // the stream or a launch failed: every running request ends with it
+                    std::lock_guard<std::mutex> lk(mu);
+                    for (const BatchItem &b : batch.items()) finish(b.tag, s, rt_ali_stats{});
+                    for (const BatchItem &b : fin) finish(b.tag, s, rt_ali_stats{});
+                    break;
+                }
+                for (const BatchItem &b : fin) {
+                    rt_ali_stats sts{};
+                    rt_status r = RT_OK;
+                    rt_status s2 = ali_stats(b.p, &b.opts, b.nonfinite, 0.0, &sts, st, &r);
+                    std::lock_guard<std::mutex> lk(mu);
+                    finish(b.tag, s2 != RT_OK ? s2 : r, sts);
+                }
+                cv.notify_all();
+            }
+        }
+        {
+            // anything still queued after a failure ends with that failure
+            std::lock_guard<std::mutex> lk(mu);
+            for (uint64_t t : queue) {
+                Request &q = reqs[t];
+                q.done = true;
+                q.result = RT_E_HIP;
+            }
+            queue.clear();
+        }
+        if (st) (void)hipStreamDestroy(st);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            dead = true;
+        }
+        cv.notify_all();
+    }
+};
+
+extern "C" {
+
+rt_status rt_server_create(size_t hbm_budget, int32_t check_every, rt_server **out)
+{
+    if (!out) return fail(RT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (check_every < 0) return fail(RT_E_INVALID, "check_every must be >= 0");
+    rt_server *srv = new rt_server();
+    srv->budget = hbm_budget;
+    srv->every = check_every > 0 ? check_every : 16;
+    HIP_TRY(hipGetDevice(&srv->device));
+    srv->worker = std::thread([srv] { srv->run(); });
+    *out = srv;
+    return RT_OK;
+}
+
+rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+                           uint64_t *ticket)
+{
+    if (!srv || !p || !opts || !S_inout || !J_out || !ticket)
+        return fail(RT_E_INVALID, "server, problem, opts, S_inout, J_out and ticket are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    {
+        rt_status so = check_ali_opts(opts);
+        if (so != RT_OK) return so;
+    }
+    rt_server::Request q;
+    q.item.p = p;
+    q.item.S = S_inout;
+    q.item.J = J_out;
+    q.item.opts = *opts;
+    q.item.total = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
+    q.bytes = state_bytes(&p->desc, p->na);
+    q.t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return fail(RT_E_INVALID, "server is shutting down");
+    if (srv->dead) return fail(RT_E_HIP, "server worker stopped after a device failure");
+    for (const auto &kv : srv->reqs)
+        if (!kv.second.done && kv.second.item.p == p) return fail(RT_E_INVALID, "problem already has a pending request");
+    const uint64_t t = srv->next_ticket++;
+    q.item.tag = t;
+    srv->reqs[t] = q;
+    srv->queue.push_back(t);
+    *ticket = t;
+    srv->cv.notify_all();
+    return RT_OK;
+}
+
+rt_status rt_server_poll(rt_server *srv, uint64_t ticket, rt_ali_stats *stats, rt_status *result)
+{
+    if (!srv) return fail(RT_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(RT_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second.done) return RT_E_BUSY;
+    if (stats) *stats = it->second.stats;
+    if (result) *result = it->second.result;
+    return RT_OK;
+}
+
+rt_status rt_server_release(rt_server *srv, uint64_t ticket)
+{
+    if (!srv) return fail(RT_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(RT_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second.done) return fail(RT_E_INVALID, "ticket %llu has not finished", (unsigned long long)ticket);
+    srv->reqs.erase(it);
+    return RT_OK;
+}
+
+rt_status rt_server_load(rt_server *srv, int32_t *queued, int32_t *running)
+{
+    if (!srv) return fail(RT_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (queued) *queued = (int32_t)srv->queue.size();
+    if (running) *running = srv->running;
+    return RT_OK;
+}
+
+rt_status rt_server_destroy(rt_server *srv)
+{
+    if (!srv) return RT_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    delete srv;
+    return RT_OK;
+}
+
+}  // extern "C"
+

@@ -18,6 +18,10 @@ Workloads (grid, rays, physics):
   multifreq  192^3 x 64 log-spaced bins in x = [0.05, 50], chi_abs = kappa0 x^-3 rho
              with rho lognormal(0, 0.8), grey electron scattering with vertical tau
              10, Planck B_nu with T lognormal(0, 0.3), 80 rays.
+  batched    one of many uneven problems solved together (seed 1004 + index): each
+             axis 24..96 cells, 24/48/80 rays, 1..16 bins, eps = 10^U[-4, 0], grey
+             chi lognormal(0, 1) scaled to a vertical tau of 10, T ~ U[0.5, 1.5],
+             B = T^4 for one bin, else Planck bins on x = [0.05, 50].
 """
 from __future__ import annotations
 
@@ -146,3 +150,33 @@ def random_problem(shape, nf=1, seed=0, n_mu=4, eps_range=(1e-2, 1.0), chi_sigma
     B = rng.uniform(0.5, 1.5, fs) ** 4
     return Workload("random", tuple(shape), n_mu, chi, eps, B, rng.uniform(0.5, 1.5, nf),
                     bc_lo=tuple(bc_lo), bc_hi=tuple(bc_hi), h=tuple(h))
+
+
+def _planck_bins(nf, T):
+    x = np.logspace(np.log10(0.05), np.log10(50.0), nf)
+    w = np.zeros(nf)
+    w[1:] += 0.5 * np.diff(x)
+    w[:-1] += 0.5 * np.diff(x)
+    B = np.stack([x[b] ** 3 / np.expm1(x[b] / T) for b in range(nf)])
+    return B, w
+
+
+def batched_problem(index, seed=1004, min_n=24, max_n=96):
+    """Problem ``index`` of the uneven batch (sizes, rays, bins and eps drawn per problem)."""
+    rng = np.random.default_rng(seed + index)
+    nx, ny, nz = (int(v) for v in rng.integers(min_n, max_n + 1, 3))
+    n_mu = int(rng.choice([4, 6, 8]))
+    nf = int(rng.integers(1, 17))
+    eps = float(10.0 ** rng.uniform(-4.0, 0.0))
+    shape = (nx, ny, nz)
+    chi1 = np.exp(rng.normal(0.0, 1.0, (nz, ny, nx)))
+    chi1 *= 10.0 / chi1.sum(axis=0).mean()
+    T = rng.uniform(0.5, 1.5, (nz, ny, nx))
+    if nf == 1:
+        B = (T ** 4)[None]
+        w = np.ones(1)
+    else:
+        B, w = _planck_bins(nf, T)
+    chi = np.broadcast_to(chi1[None], B.shape).copy()
+    epsa = np.full(B.shape, eps)
+    return Workload("batched", shape, n_mu, chi, epsa, B, w, delta_c=1e-6, meta={"eps": eps, "index": index})

@@ -104,3 +104,28 @@ def test_disabled_schedule_is_refused(rt):
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_UNSUPPORTED
     d = rt.make_desc((8, 8, 8), schedule=7)
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID
+
+
+def test_batch_and_server_argument_errors(rt):
+    """Argument checks of the batched solve and the serving loop, which run before any
+    device work (no GPU needed)."""
+    lib = rt.load()
+    o = rt.AliOpts(1e-6, 100, 0, 1, 0, 0)
+    # empty or NULL batches
+    assert lib.rt_ali_solve_batch(None, 0, ctypes.byref(o), None, None, None, None, None) == rt.RT_E_INVALID
+    probs = (ctypes.c_void_p * 1)(None)
+    ptrs = (ctypes.c_void_p * 1)(None)
+    assert lib.rt_ali_solve_batch(probs, 1, ctypes.byref(o), ptrs, ptrs, None, None, None) == rt.RT_E_INVALID
+    bad = rt.AliOpts(1e-6, 0, 0, 1, 0, 0)    # max_iter 0 without fixed_iters
+    assert lib.rt_ali_solve_batch(probs, 0, ctypes.byref(bad), ptrs, ptrs, None, None, None) == rt.RT_E_INVALID
+    # server calls on a NULL server
+    st = rt.AliStats()
+    res = ctypes.c_int()
+    assert lib.rt_server_poll(None, ctypes.c_uint64(1), ctypes.byref(st), ctypes.byref(res)) == rt.RT_E_INVALID
+    assert lib.rt_server_release(None, ctypes.c_uint64(1)) == rt.RT_E_INVALID
+    assert lib.rt_server_load(None, None, None) == rt.RT_E_INVALID
+    assert lib.rt_server_destroy(None) == rt.RT_OK
+    t = ctypes.c_uint64()
+    assert lib.rt_server_submit(None, None, ctypes.byref(o), None, None, ctypes.byref(t)) == rt.RT_E_INVALID
+    assert lib.rt_server_create(0, -1, ctypes.byref(ctypes.c_void_p())) == rt.RT_E_INVALID
+    assert lib.rt_status_string(rt.RT_E_BUSY) == b"busy"

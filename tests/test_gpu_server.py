@@ -1,0 +1,99 @@
+"""Serving loop (rt_server_*) through the C ABI: requests admitted under an HBM budget
+into a running batch give exactly the single-solve results; warm starts continue
+from device-resident state; argument errors are reported."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1201_2222_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P, V, T = W.PERIODIC, W.VACUUM, W.THERMAL
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1201_2222_amd as rt
+    assert torch.cuda.is_available()
+    rt.load()
+    return rt, torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+SPECS = [((14, 12, 10), 2, 4, "f32", (1e-2, 1.0)), ((16, 9, 13), 1, 6, "f32", (1e-3, 0.1)),
+         ((10, 10, 10), 3, 2, "f64", (0.05, 1.0)), ((20, 8, 12), 1, 4, "f32", (0.3, 1.0)),
+         ((9, 11, 7), 2, 6, "f64", (0.01, 0.2))]
+
+
+def _make(rt, torch, k, spec):
+    shape, nf, n_mu, prec, er = spec
+    wl = W.random_problem(shape, nf=nf, seed=700 + k, n_mu=n_mu, eps_range=er)
+    p = rt.Problem(shape, nf=nf, n_mu=n_mu, w_nu=wl.w_nu, precision=rt.RT_F32 if prec == "f32" else rt.RT_F64)
+    p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+    n = wl.chi.size
+    return p, torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda")
+
+
+def _wait(rt, srv, tickets, limit=120.0):
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                r = rt.rt_server_poll(srv, t)
+                if r is not None:
+                    out[t] = r
+        assert time.time() - t0 < limit, "server requests did not finish"
+        time.sleep(0.002)
+    return out
+
+
+def test_server_queue_matches_single(env):
+    rt, torch = env
+    probs = [_make(rt, torch, k, s) for k, s in enumerate(SPECS)]
+    budget = max(rt.rt_problem_bytes(p.desc) for p, _, _ in probs) * 2   # at most ~two at a time
+    srv = rt.rt_server_create(budget, check_every=8)
+    tickets = [rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=3000) for p, S, J in probs]
+    q, r = rt.rt_server_load(srv)
+    assert q + r <= len(tickets)
+    res = _wait(rt, srv, tickets)
+    for (p, S, J), t, spec, k in zip(probs, tickets, SPECS, range(len(SPECS))):
+        status, st = res[t]
+        assert status == rt.RT_OK
+        p2, S2, J2 = _make(rt, torch, k, spec)
+        s2, st2 = p2.ali_solve(S2, J2, delta_c=1e-6, max_iter=3000, check_every=8)
+        torch.cuda.synchronize()
+        assert st["iterations"] == st2["iterations"]
+        assert np.array_equal(S.cpu().numpy(), S2.cpu().numpy())
+        assert np.array_equal(J.cpu().numpy(), J2.cpu().numpy())
+        rt.rt_server_release(srv, t)
+        p2.close()
+    rt.rt_server_destroy(srv)
+    for p, _, _ in probs:
+        p.close()
+
+
+def test_server_warm_start_and_errors(env):
+    rt, torch = env
+    p, S, J = _make(rt, torch, 0, SPECS[0])
+    srv = rt.rt_server_create(1 << 34)
+    t1 = rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=3000)
+    with pytest.raises(rt.RtError):
+        rt.rt_server_submit(srv, p.handle, S, J)          # problem already pending
+    cold = _wait(rt, srv, [t1])[t1]
+    assert cold[0] == rt.RT_OK
+    # the same problem again, warm-started from the converged S and its periodic memory
+    t2 = rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=3000, warm_start=1)
+    warm = _wait(rt, srv, [t2])[t2]
+    assert warm[0] == rt.RT_OK and warm[1]["iterations"] < cold[1]["iterations"]
+    with pytest.raises(rt.RtError):
+        rt.rt_server_poll(srv, 987654)
+    with pytest.raises(rt.RtError):
+        rt.rt_server_submit(srv, p.handle, S, J, fixed_iters=-2)
+    rt.rt_server_destroy(srv)
+    p.close()
