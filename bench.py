@@ -79,6 +79,228 @@ def cpu_baseline(wl, sweeps):
                       f"{updates / 1e6:.1f} M updates in {dt:.1f} s, FP64, one thread"}
 
 
+def _wait_all(rt, srv, tickets, label):
+    """Poll the server until every ticket has finished; one progress line per finished
+    request (the work itself reports progress)."""
+    done, t0 = {}, time.perf_counter()
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t in done:
+                continue
+            r = rt.rt_server_poll(srv, t)
+            if r is not None:
+                done[t] = r
+                print(f"{label}: {len(done)}/{len(tickets)} done at {time.perf_counter() - t0:.2f} s "
+                      f"({r[1]['iterations']} iterations)", file=sys.stderr, flush=True)
+        time.sleep(0.001)
+    return done
+
+
+def bench_batched(args, rt, W, torch, np):
+    """Many uneven problems solved together: one server, all requests submitted at once."""
+    count = args.count
+    free, _ = torch.cuda.mem_get_info()
+    probs = []
+    t_gen = time.perf_counter()
+    for k in range(count):
+        wl = W.batched_problem(k)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
+                       precision=rt.RT_F32)
+        p.set_fields(dev(wl.chi), dev(wl.eps), dev(wl.B))
+        S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+        J = torch.empty_like(S)
+        probs.append((p, S, J, wl.cells, wl.na, wl.nf))
+        print(f"batched: problem {k} set up ({wl.shape[0]}x{wl.shape[1]}x{wl.shape[2]}, {wl.na} rays, "
+              f"{wl.nf} bins, eps {wl.meta['eps']:.1e})", file=sys.stderr, flush=True)
+        del wl
+    torch.cuda.synchronize()
+    print(f"batched: {count} problems set up in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    budget = int(0.8 * free)
+    srv = rt.rt_server_create(budget, check_every=16)
+    t0 = time.perf_counter()
+    tickets = [rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=args.max_iter,
+                                   fixed_iters=args.fixed_iters) for p, S, J, *_ in probs]
+    done = _wait_all(rt, srv, tickets, "batched")
+    total = time.perf_counter() - t0
+    rt.rt_server_destroy(srv)
+    updates, lat, iters, notconv = 0.0, [], [], 0
+    for (p, S, J, cells, na, nf), t in zip(probs, tickets):
+        status, st = done[t]
+        notconv += status != rt.RT_OK
+        it_bins, _ = rt.rt_ali_bin_stats(p.handle, nf)
+        updates += float(cells) * na * float(np.sum(it_bins))
+        lat.append(st["seconds"])
+        iters.append(st["iterations"])
+    seq = None
+    if args.seq_sample > 0:
+        # the same kind of problems one at a time, for the batching gain
+        k = min(args.seq_sample, count)
+        t1 = time.perf_counter()
+        seq_updates = 0.0
+        for p, S, J, cells, na, nf in probs[:k]:
+            p.ali_solve(S, J, delta_c=1e-6, max_iter=args.max_iter)
+            it_bins, _ = rt.rt_ali_bin_stats(p.handle, nf)
+            seq_updates += float(cells) * na * float(np.sum(it_bins))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        seq = {"problems": k, "seconds": dt, "updates_per_s": seq_updates / dt, "solves_per_s": k / dt}
+        print(f"batched: {k} problems one at a time in {dt:.2f} s", file=sys.stderr, flush=True)
+    for p, *_ in probs:
+        p.close()
+    return {
+        "metric": METRIC, "value": updates / total, "unit": "updates/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": total * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded, generated on the host)",
+        "config": {"workload": f"batched: {count} uneven problems (axes 24..96, 24/48/80 rays, 1..16 bins, "
+                               f"eps 1e-4..1), Jacobi ALI to max|dS/S|<=1e-6 per bin, FP32 sweeps",
+                   "problems": count},
+        "ali_solves_per_s": count / total,
+        "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
+        "iterations": {"min": int(min(iters)), "median": float(np.median(iters)), "max": int(max(iters))},
+        "not_converged": notconv, "one_at_a_time": seq,
+    }
+
+
+def bench_multifreq(args, rt, W, torch, np):
+    """192^3 x 80 rays on a subset of the 64 frequency bins (bins are independent, so a
+    subset is one GPU's share of the full problem): Jacobi ALI iterations on all bins."""
+    nf_total = 64
+    bins = np.linspace(0, nf_total - 1, args.bins).round().astype(int)
+    wl = W.multifreq(n=args.mf_n, nf=nf_total, bins=bins)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    chi, eps, B = dev(wl.chi), dev(wl.eps), dev(wl.B)
+    print(f"multifreq: {wl.shape[0]}^3 x {len(bins)} bins set up", file=sys.stderr, flush=True)
+    prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
+                      precision=rt.RT_F32)
+    prob.set_fields(chi, eps, B)
+    S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+    J = torch.empty_like(S)
+    prob.ali_solve(S, J, fixed_iters=1)
+    torch.cuda.synchronize()
+    rt.rt_problem_profile(prob.handle, True)
+    t0 = time.perf_counter()
+    status, st = prob.ali_solve(S, J, fixed_iters=args.mf_iters, check_every=args.mf_iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = rt.rt_problem_profile_read(prob.handle)
+    rt.rt_problem_profile(prob.handle, False)
+    print(f"multifreq: {args.mf_iters} iterations in {dt:.2f} s", file=sys.stderr, flush=True)
+    updates = float(wl.cells) * wl.na * wl.nf * args.mf_iters
+    kernel_s = prof["kernel_ms"] / 1e3
+    achieved = prof["updates"] * OPS_PER_UPDATE_F32 / kernel_s / 1e12 if kernel_s > 0 else 0.0
+    prob.close()
+    return {
+        "metric": METRIC, "value": updates / dt, "unit": "updates/s", "n_gpus": 1, "steps": args.mf_iters,
+        "warmup": 1, "ms_per_step": dt / args.mf_iters * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded, generated on the host)",
+        "config": {"workload": f"multifreq {wl.shape[0]}^3, {wl.na} rays, {wl.nf} of {nf_total} bins "
+                               f"(x_nu in [0.05, 50]), Jacobi ALI iterations, FP32 sweeps", "bins": bins.tolist()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "sweep_updates_per_s": prof["updates"] / kernel_s if kernel_s > 0 else None},
+    }
+
+
+def bench_serving(args, rt, W, torch, np):
+    """Serving loop: a pool of request problems (some of them drifting snapshot streams
+    that are warm-started) behind one server; capacity at saturation, then Poisson
+    arrivals at fractions of it and at the overload rate, latency from arrival to
+    completion (queueing included)."""
+    rng = np.random.default_rng(2005)
+    pool, streams = [], []
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for k in range(args.pool):
+        wl = W.serving_problem(k)
+        p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
+                       precision=rt.RT_F32)
+        p.set_fields(dev(wl.chi), dev(wl.eps), dev(wl.B))
+        S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+        J = torch.empty_like(S)
+        entry = {"p": p, "S": S, "J": J, "nf": wl.nf, "busy": False, "stream": k < args.streams, "step": 0,
+                 "T": wl.meta["T"] if k < args.streams else None, "wl": wl if k < args.streams else None,
+                 "cells": wl.cells, "na": wl.na}
+        pool.append(entry)
+        print(f"serving: pool problem {k} ({wl.shape[0]}^3, {wl.nf} bins) set up", file=sys.stderr, flush=True)
+        if k >= args.streams:
+            del wl
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    srv = rt.rt_server_create(int(0.8 * free), check_every=16)
+
+    def submit(e, warm):
+        if e["stream"] and warm:
+            e["step"] += 1
+            T = W.drift(e["T"], e["step"])
+            e["T"] = T
+            wl = e["wl"]
+            x = np.logspace(np.log10(0.05), np.log10(50.0), wl.nf)
+            B = np.stack([x[b] ** 3 / np.expm1(x[b] / T) for b in range(wl.nf)])
+            e["p"].set_fields(dev(wl.chi), dev(wl.eps), dev(B))
+            torch.cuda.synchronize()
+            return rt.rt_server_submit(srv, e["p"].handle, e["S"], e["J"], delta_c=1e-6, max_iter=args.max_iter,
+                                       warm_start=2)
+        return rt.rt_server_submit(srv, e["p"].handle, e["S"], e["J"], delta_c=1e-6, max_iter=args.max_iter)
+
+    # capacity: every pool problem at once, cold
+    t0 = time.perf_counter()
+    tickets = [submit(e, False) for e in pool]
+    done = _wait_all(rt, srv, tickets, "serving capacity")
+    cap_s = time.perf_counter() - t0
+    capacity = len(pool) / cap_s
+    for t in tickets:
+        rt.rt_server_release(srv, t)
+
+    def run_rate(rate, nreq, label):
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+        backlog, inflight, lat, t_start = [], {}, [], time.perf_counter()
+        nxt = 0
+        while nxt < nreq or backlog or inflight:
+            now = time.perf_counter() - t_start
+            while nxt < nreq and arrivals[nxt] <= now:
+                backlog.append(arrivals[nxt])
+                nxt += 1
+            # admit backlog to idle problems (30% of requests go to the drifting streams)
+            while backlog:
+                want_stream = rng.random() < 0.3
+                idle = [e for e in pool if not e["busy"] and e["stream"] == want_stream] or \
+                       [e for e in pool if not e["busy"]]
+                if not idle:
+                    break
+                e = idle[rng.integers(len(idle))]
+                e["busy"] = True
+                t = submit(e, warm=e["stream"])
+                inflight[t] = (e, backlog.pop(0))
+            for t in list(inflight):
+                r = rt.rt_server_poll(srv, t)
+                if r is not None:
+                    e, arr = inflight.pop(t)
+                    e["busy"] = False
+                    lat.append(time.perf_counter() - t_start - arr)
+                    rt.rt_server_release(srv, t)
+                    print(f"{label}: {len(lat)}/{nreq} done, latency {lat[-1] * 1e3:.0f} ms", file=sys.stderr,
+                          flush=True)
+            time.sleep(0.0005)
+        span = time.perf_counter() - t_start
+        return {"rate_per_s": rate, "requests": nreq, "solves_per_s": nreq / span,
+                "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3}}
+
+    curve = [run_rate(f * capacity, args.requests, f"serving {f:.2f}x") for f in (0.25, 0.5, 0.9)]
+    over = run_rate(200.0, args.requests * 2, "serving 200/s")
+    rt.rt_server_destroy(srv)
+    for e in pool:
+        e["p"].close()
+    return {
+        "metric": METRIC, "value": over["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": over["requests"],
+        "warmup": 0, "ms_per_step": 1e3 / over["solves_per_s"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded, generated on the host)",
+        "config": {"workload": f"serving: pool of {args.pool} request problems (N 32..160 cubed, 8..32 bins, "
+                               f"48 rays, eps 1e-4..1; {args.streams} drifting warm-started streams), Poisson "
+                               f"arrivals, Jacobi ALI to 1e-6 per bin, FP32 sweeps"},
+        "capacity_solves_per_s": capacity, "latency_vs_rate": curve, "overload_200_per_s": over,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +312,19 @@ def main():
     ap.add_argument("--schedule", choices=["stages"], default="stages")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="profiling mode: run exactly this many ALI iterations per step instead of converging")
+    ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
+    ap.add_argument("--streams", type=int, default=4, help="serving: pool problems that are drifting streams")
+    ap.add_argument("--requests", type=int, default=24, help="serving: requests per arrival rate")
+    ap.add_argument("--workload", choices=["scattering", "batched", "multifreq", "serving"], default="scattering",
+                    help="scattering: the single-problem benchmark (default); batched: many uneven problems; "
+                         "multifreq: 192^3 x 80 rays on a subset of 64 bins")
+    ap.add_argument("--bins", type=int, default=8, help="multifreq: bins of the 64 to run")
+    ap.add_argument("--mf-n", type=int, default=192, help="multifreq: grid edge")
+    ap.add_argument("--mf-iters", type=int, default=3, help="multifreq: timed Jacobi iterations")
+    ap.add_argument("--count", type=int, default=96, help="problems of the batched workload")
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--seq-sample", type=int, default=0,
+                    help="batched workload: also solve this many of its problems one at a time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (for scaling rocprofv3 FETCH/WRITE_SIZE) and exit")
     args = ap.parse_args()
@@ -112,6 +347,15 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args, rt, W, torch, np)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args, rt, W, torch, np)), flush=True)
+        return
+    if args.workload == "multifreq":
+        print(json.dumps(bench_multifreq(args, rt, W, torch, np)), flush=True)
         return
     wl = W.scattering(args.n)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()

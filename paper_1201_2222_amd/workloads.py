@@ -22,6 +22,10 @@ Workloads (grid, rays, physics):
              axis 24..96 cells, 24/48/80 rays, 1..16 bins, eps = 10^U[-4, 0], grey
              chi lognormal(0, 1) scaled to a vertical tau of 10, T ~ U[0.5, 1.5],
              B = T^4 for one bin, else Planck bins on x = [0.05, 50].
+  serving    request problems (seed 1005 + index): cubic N log-uniform in [32, 160],
+             8..32 Planck bins, 48 rays, eps = 10^U[-4, 0], chi and T as batched;
+             drifting snapshot streams scale T by 1 + 0.02 h with h a smooth 8-mode
+             field (max |h| = 1) per step.
 """
 from __future__ import annotations
 
@@ -180,3 +184,29 @@ def batched_problem(index, seed=1004, min_n=24, max_n=96):
     chi = np.broadcast_to(chi1[None], B.shape).copy()
     epsa = np.full(B.shape, eps)
     return Workload("batched", shape, n_mu, chi, epsa, B, w, delta_c=1e-6, meta={"eps": eps, "index": index})
+
+
+def serving_problem(index, seed=1005, min_n=32, max_n=160):
+    """One request problem of the serving workload."""
+    rng = np.random.default_rng(seed + index)
+    n = int(round(np.exp(rng.uniform(np.log(min_n), np.log(max_n)))))
+    nf = int(rng.integers(8, 33))
+    eps = float(10.0 ** rng.uniform(-4.0, 0.0))
+    shape = (n, n, n)
+    chi1 = np.exp(rng.normal(0.0, 1.0, (n, n, n)))
+    chi1 *= 10.0 / chi1.sum(axis=0).mean()
+    T = rng.uniform(0.5, 1.5, (n, n, n))
+    B, w = _planck_bins(nf, T)
+    chi = np.broadcast_to(chi1[None], B.shape).copy()
+    epsa = np.full(B.shape, eps)
+    return Workload("serving", shape, 6, chi, epsa, B, w, delta_c=1e-6,
+                    meta={"eps": eps, "index": index, "T": T})
+
+
+def drift(T, step, seed=1005):
+    """Next snapshot of a drifting stream: T (1 + 0.02 h) with a smooth 8-mode field h
+    drawn for this step (max |h| = 1)."""
+    rng = np.random.default_rng(seed * 1000 + step)
+    nz, ny, nx = T.shape
+    h = _fourier_field(rng, (nx, ny, nz))
+    return T * (1.0 + 0.02 * h)
