@@ -511,6 +511,7 @@ rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed =
     for (int s = 0; s < p->nstages; ++s) {
         A.stage_off = p->stage_off[s];
         A.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
+        A.stage = s;
         if (timed && s == 0) HIP_TRY(hipEventRecord(p->ev[0], st));
         if constexpr (sizeof(Real) == 8)
             HIP_TRY(launch_sweep_stage_f64(A, W, mode.nq, st));
@@ -783,7 +784,7 @@ class BatchRunner {
                 if ((int)c.max_items.size() < p->nstages) c.max_items.resize(p->nstages, 0);
                 for (int s2 = 0; s2 < p->nstages; ++s2)
                     c.max_items[s2] = std::max(c.max_items[s2], (p->stage_off[s2 + 1] - p->stage_off[s2]) * 8 * p->nf);
-                c.max_ghost = std::max(c.max_ghost, ghost_entries(p) * p->nf);
+                c.max_ghost = std::max(c.max_ghost, ghost_entries(p));
                 c.max_na = std::max(c.max_na, p->na);
                 c.max_nf = std::max(c.max_nf, p->nf);
             }

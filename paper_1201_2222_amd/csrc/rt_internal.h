@@ -50,6 +50,7 @@ struct SweepArgs {
     int f0, nfc;              // bins f0 .. f0 + nfc - 1 are swept by this call
     const int *tiles;         // packed (tx | ty << 10 | tz << 20), sorted by tx + ty + tz
     int stage_off, stage_cnt;
+    int stage;                // tx + ty + tz of the tiles of this launch
     const int *frozen;        // [nf]
     const int *parity;        // [nf]: periodic slot read this sweep
     const int *stage_tab;     // [nstages + 1] offsets of the stages in tiles (batched launches)

@@ -811,34 +811,35 @@ __device__ __forceinline__ int64_t ghost_count(const SweepArgs<Real> &A, int q)
 // given incident intensity, periodic memory) written where the tiles read them.
 // blockIdx.y: ray, blockIdx.z: bin - f0.
 template <typename Real, bool DFORM>
-__device__ __forceinline__ void ghost_fill_one(const SweepArgs<Real> &A, int ray, int f, int64_t e)
+__device__ __forceinline__ void ghost_fill_one(const SweepArgs<Real> &A, int oct, int f, int e)
 {
+    // entries of one ray's planes stay far below 2^31 (32-bit index arithmetic)
     if (A.frozen[f]) return;
     int q = 0;
-    int64_t cq = ghost_count(A, 0);
+    int cq = (int)ghost_count(A, 0);
     if (e < 0) return;
     if (e >= cq) {
         e -= cq;
         q = 1;
-        cq = ghost_count(A, 1);
+        cq = (int)ghost_count(A, 1);
         if (e >= cq) {
             e -= cq;
             q = 2;
-            if (e >= ghost_count(A, 2)) return;
+            if (e >= (int)ghost_count(A, 2)) return;
         }
     }
     const int na_ = (q == 0) ? A.n[1] : A.n[0], nb_ = (q == 2) ? A.n[1] : A.n[2];
-    const int64_t P0 = (int64_t)(na_ + 1) * (nb_ + 1);
+    const int P0 = (na_ + 1) * (nb_ + 1);
     int t, ia, ib;
     if (e < P0) {
         t = 0;
-        ia = (int)(e % (na_ + 1)) - 1;
-        ib = (int)(e / (na_ + 1)) - 1;
+        ia = e % (na_ + 1) - 1;
+        ib = e / (na_ + 1) - 1;
     } else {
-        const int64_t e2 = e - P0;
+        const int e2 = e - P0;
         const int L = na_ + nb_ + 1;
-        t = 1 + (int)(e2 / L);
-        const int k = (int)(e2 % L);
+        t = 1 + e2 / L;
+        const int k = e2 % L;
         ia = (k <= nb_) ? -1 : k - nb_ - 1;
         ib = (k <= nb_) ? k - 1 : -1;
     }
@@ -846,22 +847,27 @@ __device__ __forceinline__ void ghost_fill_one(const SweepArgs<Real> &A, int ray
     const int vx = (q == 0) ? vq : ia;
     const int vy = (q == 1) ? vq : (q == 0 ? ia : ib);
     const int vz = (q == 2) ? vq : ib;
-    const RayGeo *G = A.rays + ray;
     TileCtx c;
     c.f = f;
     c.par = A.parity[f];
     c.fbase = (int64_t)f * A.cells;
-    c.sgx = (G->oct & 1) ? -1 : 1;
-    c.sgy = (G->oct & 2) ? -1 : 1;
-    c.sgz = (G->oct & 4) ? -1 : 1;
-    const double *src;
-    int64_t scell;
-    ghost_source(A, c, vx, vy, vz, ray, G->gidx, src, scell);
-    const double I = src ? *src : 0.0;
-    const Real v = DFORM ? Real(I - A.S[scell]) : Real(I);
+    c.sgx = (oct & 1) ? -1 : 1;
+    c.sgy = (oct & 2) ? -1 : 1;
+    c.sgz = (oct & 4) ? -1 : 1;
     const int ntq = sel3(q, A.nt[0], A.nt[1], A.nt[2]);
     Real *Fq = (q == 0) ? A.face[0] : (q == 1 ? A.face[1] : A.face[2]);
-    Fq[(((int64_t)f * A.na + ray) * ntq + t) * P0 + (int64_t)(ib + 1) * (na_ + 1) + (ia + 1)] = v;
+    const int64_t pos = (int64_t)t * P0 + (ib + 1) * (na_ + 1) + (ia + 1);
+    // S of the folded vertex is the same for every ray of the octant: loaded once
+    double Sg = 0.0;
+    for (int r = 0; r < A.R; ++r) {
+        const int ray = oct * A.R + r;
+        const double *src;
+        int64_t scell;
+        ghost_source(A, c, vx, vy, vz, ray, A.rays[ray].gidx, src, scell);
+        if (DFORM && r == 0) Sg = A.S[scell];
+        const double I = src ? *src : 0.0;
+        Fq[((int64_t)f * A.na + ray) * ntq * P0 + pos] = DFORM ? Real(I - Sg) : Real(I);
+    }
 }
 
 template <typename Real>
@@ -870,25 +876,23 @@ __device__ __forceinline__ int64_t ghost_total(const SweepArgs<Real> &A)
     return ghost_count(A, 0) + ghost_count(A, 1) + ghost_count(A, 2);
 }
 
-// blockIdx.y: ray, blockIdx.z: bin - f0.
+// blockIdx.y: octant, blockIdx.z: bin - f0; a thread writes its entry for every ray
+// of the octant.
 template <typename Real, bool DFORM>
 __global__ void ghost_fill_kernel(SweepArgs<Real> A)
 {
-    ghost_fill_one<Real, DFORM>(A, blockIdx.y, A.f0 + (int)blockIdx.z, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    ghost_fill_one<Real, DFORM>(A, blockIdx.y, A.f0 + (int)blockIdx.z, (int)(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
-// Batched form: blockIdx.z is the problem, blockIdx.y the ray, x runs over bins and entries.
+// Batched form: blockIdx.z is the problem, blockIdx.y the octant, x the entries; each
+// thread fills its entry for every bin and every ray of the octant.
 template <typename Real, bool DFORM>
 __global__ void ghost_fill_batch_kernel(const SweepArgs<Real> *args)
 {
     const SweepArgs<Real> &A = args[blockIdx.z];
-    const int ray = blockIdx.y;
-    if (ray >= A.na) return;
-    const int64_t tot = ghost_total(A);
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= tot * A.nf) return;
-    const int f = (int)(i / tot);
-    ghost_fill_one<Real, DFORM>(A, ray, f, i - (int64_t)f * tot);
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= (int)ghost_total(A)) return;
+    for (int f = 0; f < A.nf; ++f) ghost_fill_one<Real, DFORM>(A, blockIdx.y, f, e);
 }
 
 template <typename Real>
@@ -1320,7 +1324,7 @@ hipError_t launch_ghost_fill(const SweepArgs<Real> &A, hipStream_t st)
         const int na_ = (q == 0) ? A.n[1] : A.n[0], nb_ = (q == 2) ? A.n[1] : A.n[2];
         tot += (int64_t)(na_ + 1) * (nb_ + 1) + (int64_t)(A.nt[q] - 1) * (na_ + nb_ + 1);
     }
-    dim3 grid(blocks_for(tot, 256), (unsigned)A.na, (unsigned)A.nfc);
+    dim3 grid(blocks_for(tot, 256), 8u, (unsigned)A.nfc);
     constexpr bool dform = sizeof(Real) == 4;   // FP32 sweeps use the difference form
     hipLaunchKernelGGL((ghost_fill_kernel<Real, dform>), grid, dim3(256), 0, st, A);
     return hipGetLastError();
@@ -1332,7 +1336,8 @@ template <typename Real>
 hipError_t launch_ghost_fill_batch(const SweepArgs<Real> *args, int nprob, int64_t max_entries, int max_na,
                                    hipStream_t st)
 {
-    dim3 grid(blocks_for(max_entries, 256), (unsigned)max_na, (unsigned)nprob);
+    (void)max_na;
+    dim3 grid(blocks_for(max_entries, 256), 8u, (unsigned)nprob);
     constexpr bool dform = sizeof(Real) == 4;
     hipLaunchKernelGGL((ghost_fill_batch_kernel<Real, dform>), grid, dim3(256), 0, st, args);
     return hipGetLastError();
