@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("nf", ctypes.c_int32), ("na", ctypes.c_int32),
                 ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
-                ("want_hk", ctypes.c_int32), ("h", ctypes.c_double * 3)]
+                ("want_hk", ctypes.c_int32), ("h", ctypes.c_double * 3), ("order", ctypes.c_int32)]
 
 
 _lib = None
@@ -61,6 +61,10 @@ def _load():
         lib.orc_coeffs.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         lib.orc_ray_info.argtypes = [P, P, P, P]
+        D = ctypes.POINTER(ctypes.c_double)
+        lib.orc_bezier_coeffs.argtypes = [ctypes.c_double, D, D, D, D]
+        lib.orc_control_point.argtypes = [ctypes.c_double] * 5
+        lib.orc_control_point.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -188,6 +192,19 @@ def coeffs(dt: float):
     return E.value, pm.value, p0.value
 
 
+def bezier_coeffs(dt: float):
+    """(E, alpha, beta, gamma) of the second-order Bezier segment integration."""
+    lib = _load()
+    v = [ctypes.c_double() for _ in range(4)]
+    lib.orc_bezier_coeffs(float(dt), *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v)
+
+
+def control_point(Sm, S0, Sp, h1, h2):
+    """Clamped Bezier control point of the source function at the vertex."""
+    return _load().orc_control_point(float(Sm), float(S0), float(Sp), float(h1), float(h2))
+
+
 def ray_info(mu, h=(1.0, 1.0, 1.0)):
     """(d, a, b, signs, s, fa, fb) of the short characteristic of one ray."""
     lib = _load()
@@ -214,8 +231,11 @@ class Problem:
 
     def __init__(self, shape, chi, eps, B, n_mu=4, mu=None, w=None, h=(1.0, 1.0, 1.0),
                  bc_lo=(PERIODIC, PERIODIC, THERMAL), bc_hi=(PERIODIC, PERIODIC, VACUUM),
-                 w_nu=None, fixed=None):
+                 w_nu=None, fixed=None, order=0):
         nx, ny, nz = shape
+        if order not in (0, 1):
+            raise ValueError("order is 0 (first order) or 1 (second order, Bezier)")
+        self.order = int(order)
         self.n = (int(nx), int(ny), int(nz))
         chi = np.asarray(chi, dtype=np.float64)
         self.nf = chi.size // (nx * ny * nz)
@@ -281,6 +301,7 @@ class Problem:
         g.bc_hi[:] = list(self.bc_hi)
         g.want_hk = 1 if want_hk else 0
         g.h[:] = list(self.h)
+        g.order = self.order
         shp = self.chi.shape
         J = np.zeros(shp)
         lam = np.zeros(shp)

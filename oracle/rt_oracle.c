@@ -15,12 +15,28 @@
  *
  *     I0 = I- exp(-dtau) + psi- S- + psi0 S0                  (first order form)
  *
+ * or, in the second-order form of eq. rtdisc with Bezier interpolation of the
+ * source function (order = 1), a quadratic Bezier curve in optical depth from S0
+ * back to S- whose control point Sc = S0 - dtau-/2 (dS/dtau)0 is clamped to the
+ * interval [min(S-, S0), max(S-, S0)] (no overshoot); (dS/dtau)0 is the
+ * derivative of the parabola through S-, S0 and the downwind S+ (optical depth
+ * intervals dtau- and dtau+), so
+ *
+ *     I0 = I- exp(-dtau-) + alpha S- + beta S0 + gamma Sc,
+ *
+ * with alpha, beta, gamma the integrals of exp(-t) against the Bezier basis.
+ *
  * where I-, S- and chi- are bilinear interpolants on that face (section 3.3,
  * "first-order (linear) interpolation"), dtau is the trapezoid optical depth of
  * the segment, and psi-, psi0 integrate a source function that is linear in
  * optical depth between S- and S0.  Moments J = sum w I, H_i = sum w mu_i I,
  * K_ij = sum w mu_i mu_j I.  The diagonal of the Lambda operator (section 3.4,
- * eq. dsjacobi) is Lambda_ii = sum_k w_k psi0_k.
+ * eq. dsjacobi) is Lambda_ii = sum_k w_k psi0_k (first order); for the second-order
+ * form it is taken as sum_k w_k beta_k, the weight of S0 with the control point held
+ * fixed.  The diagonal only sets how the Jacobi iteration approaches its fixed point;
+ * counting the control point as S0 too (beta + gamma) overestimates the response
+ * where the control point is clamped, and the iteration then cycles between the
+ * clamped and unclamped states instead of converging.
  *
  * Sweep order: each ray is swept on its own over the whole grid in row-major
  * order (x fastest) starting from the upwind corner of its octant, the order of
@@ -61,6 +77,7 @@ typedef struct {
     int32_t bc_hi[3];  /* boundary kind at the high face of each axis */
     int32_t want_hk;   /* non-zero: also accumulate H and K */
     double h[3];       /* dx, dy, dz */
+    int32_t order;     /* 0: first order (linear), 1: second order (Bezier) */
 } orc_grid;
 
 /* Per-ray geometry of the upwind short characteristic (section 3.3). */
@@ -124,6 +141,85 @@ void orc_coeffs(double dt, double *E, double *psim, double *psi0)
     *E = exp(-dt);
     *psi0 = p0;
     *psim = e0 - p0;
+}
+
+/*
+ * Coefficients of the second-order (quadratic Bezier in optical depth) integration
+ * over one upwind segment of optical depth dt, t measured from x0 upwind:
+ *   S(u) = (1-u)^2 S0 + 2u(1-u) Sc + u^2 S-,  u = t/dt,
+ *   I0 = I- E + alpha S- + beta S0 + gamma Sc,
+ *   alpha = int_0^dt (t/dt)^2 e^-t dt', gamma = int 2 (t/dt)(1 - t/dt) e^-t,
+ *   beta  = int (1 - t/dt)^2 e^-t.
+ * With e0 = 1 - e^-dt, e1 = int t e^-t = 1 - e^-dt (1 + dt),
+ * e2 = int t^2 e^-t = 2 - e^-dt (dt^2 + 2 dt + 2):
+ *   alpha = e2/dt^2, gamma = 2 e1/dt - 2 e2/dt^2, beta = e0 - alpha - gamma.
+ * Below dt = 0.5 the three come from their series (n >= 0)
+ *   alpha = sum (-1)^n (n+1)(n+2) dt^(n+1) / (n+3)!,
+ *   gamma = sum (-1)^n 2(n+1) dt^(n+1) / (n+3)!,
+ *   beta  = sum (-1)^n 2 dt^(n+1) / (n+3)!,
+ * which avoid the cancellation in e1 and e2 (30 terms, summed from the smallest).
+ */
+void orc_bezier_coeffs(double dt, double *E, double *alpha, double *beta, double *gamma)
+{
+    *E = exp(-dt);
+    if (dt < 0.5) {
+        double ta[30], tb[30], tg[30];
+        double pw = 1.0;      /* dt^(n+1) */
+        double fact = 6.0;    /* (n+3)! */
+        for (int n = 0; n < 30; ++n) {
+            pw *= dt;
+            if (n > 0) fact *= (double)(n + 3);
+            double sg = (n % 2) ? -1.0 : 1.0;
+            ta[n] = sg * (double)((n + 1) * (n + 2)) * pw / fact;
+            tg[n] = sg * 2.0 * (double)(n + 1) * pw / fact;
+            tb[n] = sg * 2.0 * pw / fact;
+        }
+        double a = 0.0, b = 0.0, c = 0.0;
+        for (int n = 29; n >= 0; --n) {
+            a += ta[n];
+            b += tb[n];
+            c += tg[n];
+        }
+        *alpha = a;
+        *beta = b;
+        *gamma = c;
+        return;
+    }
+    double e0 = -expm1(-dt);
+    double ed = exp(-dt);
+    double e1 = 1.0 - ed * (1.0 + dt);
+    double e2 = 2.0 - ed * (dt * dt + 2.0 * dt + 2.0);
+    *alpha = e2 / (dt * dt);
+    *gamma = 2.0 * e1 / dt - 2.0 * e2 / (dt * dt);
+    *beta = e0 - *alpha - *gamma;
+}
+
+/*
+ * Control point of the Bezier source function at x0: Sc = S0 - h1/2 S', with S' the
+ * derivative at x0 of the parabola through (-h1, S-), (0, S0), (h2, S+) in optical
+ * depth, S' = (h2 d- + h1 d+)/(h1 + h2), d- = (S0 - S-)/h1, d+ = (S+ - S0)/h2;
+ * clamped to [min(S-, S0), max(S-, S0)].  Degenerate intervals: with h2 = 0 the
+ * one-sided slope d- is used; with h1 = 0 the segment carries no weight and Sc = S0.
+ */
+double orc_control_point(double Sm, double S0, double Sp, double h1, double h2)
+{
+    double Sc;
+    if (!(h1 > 0.0)) {
+        Sc = S0;
+    } else if (!(h2 > 0.0)) {
+        double dm = (S0 - Sm) / h1;
+        Sc = S0 - 0.5 * h1 * dm;
+    } else {
+        double dm = (S0 - Sm) / h1;
+        double dp = (Sp - S0) / h2;
+        double Sd = (h2 * dm + h1 * dp) / (h1 + h2);
+        Sc = S0 - 0.5 * h1 * Sd;
+    }
+    double lo = Sm < S0 ? Sm : S0;
+    double hi = Sm < S0 ? S0 : Sm;
+    if (Sc < lo) Sc = lo;
+    if (Sc > hi) Sc = hi;
+    return Sc;
 }
 
 static inline int is_periodic(const orc_grid *g, int q)
@@ -294,14 +390,36 @@ int orc_sweep(const orc_grid *g, const double *mu, const double *w,
                         int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
                         double S0 = Sf[id];
                         double dt = r.s * (Cm + chif[id]) * 0.5;
-                        double E, psim, psi0;
-                        orc_coeffs(dt, &E, &psim, &psi0);
-                        double I0 = (Im * E + psim * Sm) + psi0 * S0;
+                        double I0, ldiag;
+                        if (g->order == 1) {
+                            /* downwind point: the mirror image of the upwind one */
+                            double Sp4[4], Cp4[4];
+                            for (int t = 0; t < 4; ++t) {
+                                int v[3] = {i, j, k};
+                                v[r.d] += r.sgn[r.d];
+                                v[r.a] += oa[t] * r.sgn[r.a];
+                                v[r.b] += ob[t] * r.sgn[r.b];
+                                vertex_fields(&c, v, &Cp4[t], &Sp4[t]);
+                            }
+                            double Sp = ((wv[0] * Sp4[0] + wv[1] * Sp4[1]) + wv[2] * Sp4[2]) + wv[3] * Sp4[3];
+                            double Cp = ((wv[0] * Cp4[0] + wv[1] * Cp4[1]) + wv[2] * Cp4[2]) + wv[3] * Cp4[3];
+                            double dtp = r.s * (chif[id] + Cp) * 0.5;
+                            double Sc = orc_control_point(Sm, S0, Sp, dt, dtp);
+                            double E, al, be, ga;
+                            orc_bezier_coeffs(dt, &E, &al, &be, &ga);
+                            I0 = ((Im * E + al * Sm) + be * S0) + ga * Sc;
+                            ldiag = be;
+                        } else {
+                            double E, psim, psi0;
+                            orc_coeffs(dt, &E, &psim, &psi0);
+                            I0 = (Im * E + psim * Sm) + psi0 * S0;
+                            ldiag = psi0;
+                        }
                         Icur[id] = I0;
 
                         int64_t o = (int64_t)f * ncell + id;
                         J[o] += wk * I0;
-                        lam[o] += wk * psi0;
+                        lam[o] += wk * ldiag;
                         if (g->want_hk) {
                             H[0 * tot + o] += wk * mx * I0;
                             H[1 * tot + o] += wk * my * I0;
