@@ -5,9 +5,12 @@
  *
  * The library computes, on one GPU:
  *   - the formal solution J = Lambda[S] of the static transfer equation
- *     n.grad I = chi_tot (S - I) (section 2, eq. radtrans) by first-order short
+ *     n.grad I = chi_tot (S - I) (section 2, eq. radtrans) by short
  *     characteristics on a Cartesian grid whose vertices are cell centres
- *     (section 3.3, eq. rtdisc with psi+ = 0, bilinear face interpolation);
+ *     (section 3.3, eq. rtdisc, bilinear face interpolation): first order (psi+ = 0,
+ *     S linear in optical depth along the segment) or second order (S a quadratic
+ *     Bezier curve whose control point uses the downwind S, clamped so no new
+ *     extrema appear);
  *   - the Jacobi accelerated Lambda iteration with the diagonal operator
  *     Lambda* (section 3.4, eq. dsjacobi) for S = (1 - eps) J + eps B
  *     (section 2, eq. sourcefunc), stopped by eq. conv;
@@ -68,6 +71,17 @@ typedef enum { RT_BC_VACUUM = 0, RT_BC_THERMAL = 1, RT_BC_PERIODIC = 2, RT_BC_FI
  * RT_E_UNSUPPORTED for it. */
 typedef enum { RT_SCHED_DEFAULT = 0, RT_SCHED_STAGES = 1, RT_SCHED_PERSISTENT = 2 } rt_schedule;
 
+/* Order of the short-characteristic integration (section 3.3, eq. rtdisc).
+ * RT_SC_LINEAR: S varies linearly in optical depth between the upwind point and the
+ * vertex, I0 = I- e^-dtau + psi- S- + psi0 S0.
+ * RT_SC_BEZIER: S is the quadratic Bezier curve from S0 to S- with control point
+ * Sc = S0 - (dtau-/2) dS/dtau, the slope taken from the parabola through S-, S0 and
+ * the downwind S+ (interpolated at the mirror image of the upwind point, optical depth
+ * dtau+ = trapezoid of chi0 and chi+), then clamped to [min(S-, S0), max(S-, S0)];
+ * I0 = I- e^-dtau + alpha S- + beta S0 + gamma Sc.  Where dtau+ = 0 the one-sided
+ * slope (S0 - S-)/dtau- is used.  Lambda* (section 3.4) is sum_k w_k beta_k. */
+typedef enum { RT_SC_LINEAR = 0, RT_SC_BEZIER = 1 } rt_sc_order;
+
 typedef struct {
     int32_t nx, ny, nz;       /* grid vertices per axis, each >= 1 */
     int32_t nf;               /* frequency bins, >= 1 */
@@ -85,6 +99,7 @@ typedef struct {
     int32_t precision;        /* rt_precision */
     int32_t tile;             /* tile edge for the sweep (0 = default) */
     int32_t schedule;         /* rt_schedule: how the tile wavefront is executed */
+    int32_t order;            /* rt_sc_order: first- or second-order segments */
 } rt_problem_desc;
 
 typedef struct rt_problem rt_problem;

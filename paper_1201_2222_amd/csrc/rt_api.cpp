@@ -307,6 +307,7 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
     // cause is not established; it is refused until it is.
     if (d->schedule == RT_SCHED_PERSISTENT)
         return fail(RT_E_UNSUPPORTED, "the persistent sweep schedule is disabled in this build");
+    if (d->order != RT_SC_LINEAR && d->order != RT_SC_BEZIER) return fail(RT_E_INVALID, "unknown order");
     for (int q = 0; q < 3; ++q) {
         for (int k : {d->bc_lo[q], d->bc_hi[q]})
             if (k < RT_BC_VACUUM || k > RT_BC_FIXED) return fail(RT_E_INVALID, "unknown boundary kind on axis %d", q);
@@ -422,16 +423,17 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
     A.parity = p->parity;
     A.stage_tab = p->d_stage_tab;
     A.nstages = p->nstages;
+    A.order = p->desc.order;
     return A;
 }
 
 // Waves per sweep workgroup: one per ray of the octant, capped so the dynamic LDS
 // (chi and S tiles; a cube of I and a partial-sum tile per wave) fits
 // the device's per-workgroup limit.
-int sweep_waves(int R, bool f32, size_t lds_limit)
+int sweep_waves(int R, bool f32, int order, size_t lds_limit)
 {
     int w = std::min(R, kMaxWaves);
-    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w, 1, R > w) > lds_limit) --w;
+    while (w > 1 && sweep_lds_bytes(f32 ? 4 : 8, w, 1, R > w, order) > lds_limit) --w;
     return w;
 }
 
@@ -648,13 +650,15 @@ class BatchRunner {
                     const SweepArgs<float> *a = static_cast<const SweepArgs<float> *>(c.d_args);
                     HIP_TRY(launch_ghost_fill_batch<float>(a, n, c.max_ghost, c.max_na, st_));
                     for (size_t st = 0; st < c.max_items.size(); ++st)
-                        HIP_TRY(launch_sweep_batch_stage_f32(a, n, (int)st, c.max_items[st], c.waves, c.multi, st_));
+                        HIP_TRY(launch_sweep_batch_stage_f32(a, n, (int)st, c.max_items[st], c.waves, c.multi,
+                                                             c.order, st_));
                     HIP_TRY(launch_ali_update_batch<float>(c.d_upd, n, kBatchUpdateBlocks, c.max_nf, st_));
                 } else {
                     const SweepArgs<double> *a = static_cast<const SweepArgs<double> *>(c.d_args);
                     HIP_TRY(launch_ghost_fill_batch<double>(a, n, c.max_ghost, c.max_na, st_));
                     for (size_t st = 0; st < c.max_items.size(); ++st)
-                        HIP_TRY(launch_sweep_batch_stage_f64(a, n, (int)st, c.max_items[st], c.waves, c.multi, st_));
+                        HIP_TRY(launch_sweep_batch_stage_f64(a, n, (int)st, c.max_items[st], c.waves, c.multi,
+                                                             c.order, st_));
                     HIP_TRY(launch_ali_update_batch<double>(c.d_upd, n, kBatchUpdateBlocks, c.max_nf, st_));
                 }
                 HIP_TRY(launch_ali_finalize_batch(c.d_upd, n, d_done_ + 2 * c.done_off, st_));
@@ -686,6 +690,7 @@ class BatchRunner {
         bool f32 = false;
         int waves = 1;
         bool multi = false;
+        int order = 0;
         std::vector<int> idx;                 // members (positions in items_)
         std::vector<unsigned char> h_args;    // SweepArgs<Real> per member
         std::vector<BatchUpdate> h_upd;
@@ -737,7 +742,8 @@ class BatchRunner {
             const bool multi = p->R > p->waves;
             Class *cls = nullptr;
             for (Class &c : classes_)
-                if (c.f32 == p->f32 && c.waves == p->waves && c.multi == multi) cls = &c;
+                if (c.f32 == p->f32 && c.waves == p->waves && c.multi == multi && c.order == p->desc.order)
+                    cls = &c;
             if (!cls) {
                 Class c;
                 if (!spare_.empty()) {
@@ -747,6 +753,7 @@ class BatchRunner {
                 c.f32 = p->f32;
                 c.waves = p->waves;
                 c.multi = multi;
+                c.order = p->desc.order;
                 classes_.push_back(std::move(c));
                 cls = &classes_.back();
             }
@@ -1028,7 +1035,7 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     (void)hipGetLastError();
-    p->waves = sweep_waves(p->R, p->f32, (size_t)lds_limit);
+    p->waves = sweep_waves(p->R, p->f32, desc->order, (size_t)lds_limit);
     p->persistent = desc->schedule == RT_SCHED_PERSISTENT;
     if (p->persistent) {
         int per_cu = 0, ncu = 0;
@@ -1041,10 +1048,10 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
         (void)hipGetLastError();
         p->wait_ticks = (uint64_t)khz * 20;   // 20 ms
     }
-    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves) > (size_t)lds_limit) {
+    if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves, desc->order) > (size_t)lds_limit) {
         rt_problem_destroy(p);
         return fail(RT_E_UNSUPPORTED, "sweep needs %zu bytes of LDS, device allows %d",
-                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves), lds_limit);
+                    sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves, desc->order), lds_limit);
     }
     hipError_t e = hipMemcpy(p->d_rays, p->rays.data(), sizeof(RayGeo) * na, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tiles, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice);
@@ -1072,7 +1079,8 @@ rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *
     HIP_TRY(hipMemcpyAsync(p->eps, eps, bytes, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(p->B, B, bytes, hipMemcpyDeviceToDevice, st));
     if (p->f32) HIP_TRY(launch_convert_f32(p->chi64, p->chi32, p->cells * p->nf, st));
-    HIP_TRY(launch_lambda_star(p->n, p->desc.bc_lo, p->desc.bc_hi, p->nf, p->na, p->d_rays, p->chi64, p->lam, st));
+    HIP_TRY(launch_lambda_star(p->n, p->desc.bc_lo, p->desc.bc_hi, p->nf, p->na, p->desc.order, p->d_rays, p->chi64,
+                               p->lam, st));
     HIP_TRY(hipMemsetAsync(p->parity, 0, sizeof(int) * p->nf, st));
     p->cold = true;
     p->have_fields = true;

@@ -55,6 +55,7 @@ struct SweepArgs {
     const int *parity;        // [nf]: periodic slot read this sweep
     const int *stage_tab;     // [nstages + 1] offsets of the stages in tiles (batched launches)
     int nstages;
+    int order;                // 0: first-order segments, 1: second order (Bezier source)
 };
 
 // Dependency state of the persistent sweep: one completion flag per (bin, octant,
@@ -102,14 +103,14 @@ struct BatchUpdate {
 hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq, hipStream_t st);
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, hipStream_t st);
 // dynamic LDS bytes of one sweep workgroup with the given number of waves
-size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi);
+size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi, int order);
 hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs &D, int waves, int blocks_per_octant,
                                        hipStream_t st);
 hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int blocks_per_octant,
                                        hipStream_t st);
 hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks);
 
-hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,
+hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na, int order,
                               const RayGeo *rays, const double *chi, double *lam, hipStream_t st);
 
 // Cold periodic memory: every periodic slot about to be read holds S of the wrapped vertex.
@@ -124,9 +125,9 @@ hipError_t launch_ghost_fill(const SweepArgs<Real> &A, hipStream_t st);
 // Batched launches over the problems of one batch class (device arrays of per-problem
 // arguments; sizes are the maxima over the problems).
 hipError_t launch_sweep_batch_stage_f64(const SweepArgs<double> *args, int nprob, int s, int max_items, int waves,
-                                        bool multi, hipStream_t st);
+                                        bool multi, int order, hipStream_t st);
 hipError_t launch_sweep_batch_stage_f32(const SweepArgs<float> *args, int nprob, int s, int max_items, int waves,
-                                        bool multi, hipStream_t st);
+                                        bool multi, int order, hipStream_t st);
 template <typename Real>
 hipError_t launch_ghost_fill_batch(const SweepArgs<Real> *args, int nprob, int64_t max_entries, int max_na,
                                    hipStream_t st);

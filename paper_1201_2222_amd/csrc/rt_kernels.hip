@@ -25,6 +25,13 @@ namespace {
 constexpr int T = kTile;
 constexpr int TP = T + 1;            // tile plus one upwind halo layer
 constexpr int TILE_LDS = TP * TP * TP;
+// chi and S are staged with the upwind halo, and for the second-order form also the
+// downwind layer (the downwind point of each vertex lies in the next plane):
+// edge TP, or TP + 1 with ORD = 1.
+template <int ORD>
+constexpr int stage_edge() { return ORD ? TP + 1 : TP; }
+template <int ORD>
+constexpr int stage_cells() { return stage_edge<ORD>() * stage_edge<ORD>() * stage_edge<ORD>(); }
 // Reals of LDS per wave: the cube of I (or D) of its current ray, and when a wave
 // sweeps several rays of a tile (multi) nq partial-sum tiles that accumulate them
 constexpr int wave_lds(int nq, bool multi) { return TILE_LDS + (multi ? nq * T * T * T : 0); }
@@ -118,6 +125,96 @@ __device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
     const float gs = 1.0f - dt * acc;
     const float gc = (1.0f - E) * __builtin_amdgcn_rcpf(dt);
     g = dt < 0.5f ? gs : gc;
+}
+
+// ---- second-order segment (section 3.3, eq. rtdisc with Bezier source) -------------
+// Over an upwind segment of optical depth x the source is the quadratic Bezier curve
+// from S0 (u = 0) through the control point Sc to S- (u = 1), u = t/x, and
+//   I0 = I- E + alpha S- + beta S0 + gamma Sc,
+//   alpha = int_0^x u^2 e^-t, gamma = int 2u(1-u) e^-t, beta = int (1-u)^2 e^-t.
+// With e1 = 1 - E(1 + x), e2 = 2 - E(x^2 + 2x + 2):  alpha = e2/x^2,
+// gamma = 2 e1/x - 2 e2/x^2, beta = (1 - E) - alpha - gamma.  For small x these
+// cancel; there all three follow from the one series F3(x) = sum_n (-x)^n/(n+3)!:
+//   beta = 2x F3,  gamma = x (1 - 2(x + 2) F3),  alpha = x ((x^2 + 2x + 2) F3 - x/2)
+// (substitute (1 - E) = x - x^2/2 + x^3 F3 into the closed forms).  One series keeps
+// the number of distinct constants, which the compiler holds in scalar registers
+// across the sweep, small.
+// 1/(n+3)!, n = 0 .. 15
+#define RT_INV_FACT3                                                                                         \
+    {1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0,          \
+     1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0, 1.0 / 87178291200.0,        \
+     1.0 / 1307674368000.0, 1.0 / 20922789888000.0, 1.0 / 355687428096000.0, 1.0 / 6402373705728000.0}
+
+// FP64 (plain form and Lambda*): series below x = 0.5 (16 terms).
+__device__ __forceinline__ void bezier_coeffs(double x, double &E, double &al, double &be, double &ga)
+{
+    E = exp(-x);
+    if (x < 0.5) {
+        constexpr int N = 16;
+        const double c[N] = RT_INV_FACT3;
+        double f = c[N - 1];
+#pragma unroll
+        for (int n = N - 2; n >= 0; --n) f = c[n] - x * f;
+        be = 2.0 * x * f;
+        ga = x * (1.0 - 2.0 * (x + 2.0) * f);
+        al = x * (((x + 2.0) * x + 2.0) * f - 0.5 * x);
+    } else {
+        const double e0 = -expm1(-x);
+        const double e1 = 1.0 - E * (1.0 + x);
+        const double e2 = 2.0 - E * (x * x + 2.0 * x + 2.0);
+        al = e2 / (x * x);
+        ga = 2.0 * e1 / x - 2.0 * e2 / (x * x);
+        be = e0 - al - ga;
+    }
+}
+
+// FP32, difference form: with E + alpha + beta + gamma = 1 the plain form becomes
+//   D0 = D- E + (E + alpha)(S- - S0) + gamma (Sc - S0),
+// so only E, E + alpha and gamma are needed.  Series below x = 1 (10 terms); both
+// branches are evaluated and one selected.
+__device__ __forceinline__ void bezier_coeffs(float x, float &E, float &Ea, float &ga)
+{
+    E = __expf(-x);
+    constexpr int N = 10;
+    const double c[16] = RT_INV_FACT3;
+    float f = float(c[N - 1]);
+#pragma unroll
+    for (int n = N - 2; n >= 0; --n) f = float(c[n]) - x * f;
+    const float as = x * (((x + 2.0f) * x + 2.0f) * f - 0.5f * x);
+    const float gs = x * (1.0f - 2.0f * (x + 2.0f) * f);
+    const float r = __builtin_amdgcn_rcpf(x);
+    const float e1 = 1.0f - E * (1.0f + x);
+    const float e2 = 2.0f - E * ((x + 2.0f) * x + 2.0f);
+    const float ac = e2 * r * r;
+    const float gc = 2.0f * e1 * r - 2.0f * ac;
+    const bool small = x < 1.0f;
+    Ea = E + (small ? as : ac);
+    ga = small ? gs : gc;
+}
+
+// Control point relative to S0 (section 3.3): Sc - S0 = -(h1/2) S' with S' the slope
+// at the vertex of the parabola through (-h1, S-), (0, S0), (h2, S+) in optical depth.
+// With a = S- - S0, b = S+ - S0 and t = h1/h2 this is (a - b t^2) / (2 (1 + t)); with
+// h2 = 0 the one-sided slope gives a/2 (and h1 = 0 leaves the segment without
+// weight).  The result is clamped to lie between S- and S0, i.e. between a and 0.
+// t is capped where t^2 would overflow; there the value is clamped anyway, and for
+// b = 0 it stays ~0 as it should.
+__device__ __forceinline__ float fdiv(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double fdiv(double n, double d) { return n / d; }
+
+template <typename Real>
+__device__ __forceinline__ Real control_offset(Real a, Real b, Real h1, Real h2)
+{
+    constexpr Real tmax = sizeof(Real) == 4 ? Real(1e18) : Real(1e150);
+    const bool one_sided = !(h2 > Real(0));
+    Real t = fdiv(h1, one_sided ? Real(1) : h2);
+    t = t < tmax ? t : tmax;
+    Real dc = fdiv(a - b * t * t, Real(2) * (Real(1) + t));
+    dc = one_sided ? Real(0.5) * a : dc;
+    const Real lo = a < Real(0) ? a : Real(0), hi = a < Real(0) ? Real(0) : a;
+    dc = dc < lo ? lo : dc;
+    dc = dc > hi ? hi : dc;
+    return dc;
 }
 
 // Per-workgroup tile description, all scalars (no arrays indexed by a runtime axis).
@@ -240,10 +337,11 @@ __device__ __forceinline__ void shell_store(const Shell<Real> &sh, Real *Ic)
 // interior faces go to the next tile's slot of the padded face planes; the grid's
 // last faces on periodic axes feed the next sweep's periodic memory (which keeps I,
 // in FP64).
-template <typename Real, bool DFORM>
+template <typename Real, bool DFORM, int ORD>
 __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray, int lane, const Real *Ic,
                             const double *SL)
 {
+    constexpr int SE = stage_edge<ORD>();   // edge of the staged S cube
     const int64_t rb = (int64_t)c.f * A.na + ray;
     const int u = lane % T, w = lane / T;   // T * T == 64 face vertices, one per lane
     // every address and value first, then the stores back to back (a register that a
@@ -255,9 +353,10 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
     // x face: (y, z) = (u, w)
     {
         const int li = ((w + 1) * TP + (u + 1)) * TP + c.ex;
+        const int ls = ((w + 1) * SE + (u + 1)) * SE + c.ex;
         const int vy = c.g0y + u, vz = c.g0z + w;
         vf[0] = Ic[li];
-        vw[0] = DFORM ? double(vf[0]) + SL[li] : double(vf[0]);
+        vw[0] = DFORM ? double(vf[0]) + SL[ls] : double(vf[0]);
         if (u < c.ey && w < c.ez) {
             if (c.tx < A.nt[0] - 1)
                 pf[0] = A.face[0] + (rb * A.nt[0] + c.tx + 1) * A.pplane[0] + (int64_t)(vz + 1) * (A.n[1] + 1) + (vy + 1);
@@ -268,9 +367,10 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
     // y face: (x, z) = (u, w)
     {
         const int li = ((w + 1) * TP + c.ey) * TP + (u + 1);
+        const int ls = ((w + 1) * SE + c.ey) * SE + (u + 1);
         const int vx = c.g0x + u, vz = c.g0z + w;
         vf[1] = Ic[li];
-        vw[1] = DFORM ? double(vf[1]) + SL[li] : double(vf[1]);
+        vw[1] = DFORM ? double(vf[1]) + SL[ls] : double(vf[1]);
         if (u < c.ex && w < c.ez) {
             if (c.ty < A.nt[1] - 1)
                 pf[1] = A.face[1] + (rb * A.nt[1] + c.ty + 1) * A.pplane[1] + (int64_t)(vz + 1) * (A.n[0] + 1) + (vx + 1);
@@ -281,9 +381,10 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
     // z face: (x, y) = (u, w)
     {
         const int li = (c.ez * TP + (w + 1)) * TP + (u + 1);
+        const int ls = (c.ez * SE + (w + 1)) * SE + (u + 1);
         const int vx = c.g0x + u, vy = c.g0y + w;
         vf[2] = Ic[li];
-        vw[2] = DFORM ? double(vf[2]) + SL[li] : double(vf[2]);
+        vw[2] = DFORM ? double(vf[2]) + SL[ls] : double(vf[2]);
         if (u < c.ex && w < c.ey) {
             if (c.tz < A.nt[2] - 1)
                 pf[2] = A.face[2] + (rb * A.nt[2] + c.tz + 1) * A.pplane[2] + (int64_t)(vy + 1) * (A.n[0] + 1) + (vx + 1);
@@ -299,6 +400,8 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
 }
 
 constexpr int lds_stride(int q) { return q == 0 ? 1 : (q == 1 ? TP : TP * TP); }
+template <int ORD>
+constexpr int stage_stride(int q) { return q == 0 ? 1 : (q == 1 ? stage_edge<ORD>() : stage_edge<ORD>() * stage_edge<ORD>()); }
 constexpr int tile_stride(int q) { return q == 0 ? 1 : (q == 1 ? T : T * T); }
 
 // Plane-by-plane sweep of one ray through the tile along its first-crossed axis D
@@ -324,23 +427,30 @@ __device__ __forceinline__ Real ray_weight(const RayGeo *G, int q)
     }
 }
 
-// Upwind and own chi and S of one vertex of a plane, as loaded from the staged tile.
+// Upwind and own chi and S of one vertex of a plane, as loaded from the staged tile,
+// and for the second-order form the downwind chi (p..) and S (t..).
 template <typename Real>
 struct SegIn {
     Real c00, c10, c01, c11, c0;
     double s00, s10, s01, s11, s0;
+    Real p00, p10, p01, p11;
+    double t00, t10, t01, t11;
 };
 
-template <typename Real, bool ACC, int NQ, int D, bool DFORM>
+// ORD = 0: first order (linear source between S- and S0).  ORD = 1: second order
+// (quadratic Bezier source with the control point from S-, S0 and the downwind S+).
+template <typename Real, bool ACC, int NQ, int D, bool DFORM, int ORD>
 __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int eb, int lane, Real *Ic,
                                            const Real *chiL, const double *SL, Real *Jw)
 {
     constexpr int DA = (D == 0) ? 1 : 0, DB = (D == 2) ? 1 : 2;
     constexpr int SD = lds_stride(D), SA = lds_stride(DA), SB = lds_stride(DB);
+    constexpr int XD = stage_stride<ORD>(D), XA = stage_stride<ORD>(DA), XB = stage_stride<ORD>(DB);
     constexpr int JD = tile_stride(D), JA = tile_stride(DA), JB = tile_stride(DB);
     const int ia = lane & (T - 1), ib = lane / T;
     const bool act = ia < ea && ib < eb;
-    const int lb = (ia + 1) * SA + (ib + 1) * SB;
+    const int lb = (ia + 1) * SA + (ib + 1) * SB;    // in the cube of I
+    const int ls = (ia + 1) * XA + (ib + 1) * XB;    // in the staged chi and S
     const int jbase = ia * JA + ib * JB;
     const Real s_half = Real(0.5 * G->s);
     const Real w00 = Real(G->w4[0]), w10 = Real(G->w4[1]), w01 = Real(G->w4[2]), w11 = Real(G->w4[3]);
@@ -354,26 +464,53 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int 
     // segment; they do not depend on the intensity, so their loads run two planes
     // ahead and their arithmetic one plane ahead of the recurrence.
     auto load_seg = [&](int p) {
-        const int l0 = lb + (p + 1) * SD;
-        const int lu = l0 - SD;
+        const int l0 = ls + (p + 1) * XD;
+        const int lu = l0 - XD;
         SegIn<Real> x;
         x.c00 = chiL[lu];
-        x.c10 = chiL[lu - SA];
-        x.c01 = chiL[lu - SB];
-        x.c11 = chiL[lu - SA - SB];
+        x.c10 = chiL[lu - XA];
+        x.c01 = chiL[lu - XB];
+        x.c11 = chiL[lu - XA - XB];
         x.c0 = chiL[l0];
         x.s00 = SL[lu];
-        x.s10 = SL[lu - SA];
-        x.s01 = SL[lu - SB];
-        x.s11 = SL[lu - SA - SB];
+        x.s10 = SL[lu - XA];
+        x.s01 = SL[lu - XB];
+        x.s11 = SL[lu - XA - XB];
         x.s0 = SL[l0];
+        if constexpr (ORD == 1) {
+            // the downwind point mirrors the upwind one through the vertex
+            const int ld = l0 + XD;
+            x.p00 = chiL[ld];
+            x.p10 = chiL[ld + XA];
+            x.p01 = chiL[ld + XB];
+            x.p11 = chiL[ld + XA + XB];
+            x.t00 = SL[ld];
+            x.t10 = SL[ld + XA];
+            x.t01 = SL[ld + XB];
+            x.t11 = SL[ld + XA + XB];
+        }
         return x;
     };
     auto seg = [&](const SegIn<Real> &x, Real &E, Real &cc) {
         const Real Cm = w00 * x.c00 + w10 * x.c10 + w01 * x.c01 + w11 * x.c11;
         const Real dt = s_half * (Cm + x.c0);
         const double Sm = w00d * x.s00 + w10d * x.s10 + w01d * x.s01 + w11d * x.s11;
-        if constexpr (DFORM) {
+        if constexpr (ORD == 1) {
+            const Real Cp = w00 * x.p00 + w10 * x.p10 + w01 * x.p01 + w11 * x.p11;
+            const Real dtp = s_half * (x.c0 + Cp);   // optical depth of the downwind segment
+            const double Sp = w00d * x.t00 + w10d * x.t10 + w01d * x.t01 + w11d * x.t11;
+            if constexpr (DFORM) {
+                Real Ea, ga;
+                bezier_coeffs(dt, E, Ea, ga);
+                const Real a = Real(Sm - x.s0), b = Real(Sp - x.s0);   // differences formed in FP64
+                cc = Ea * a + ga * control_offset<Real>(a, b, dt, dtp);
+            } else {
+                double al, be, ga;
+                bezier_coeffs(dt, E, al, be, ga);
+                const double Sc = x.s0 + control_offset<double>(Sm - x.s0, Sp - x.s0, dt, dtp);
+                cc = (al * Sm + be * x.s0) + ga * Sc;
+            }
+        } else if constexpr (DFORM) {
             Real g;
             seg_coeffs(dt, E, g);
             cc = Real(Sm - x.s0) * g;   // S- - S0 formed in FP64
@@ -455,17 +592,18 @@ __device__ __forceinline__ uint32_t geo_load(const SweepArgs<Real> &A, int ray, 
 // ray of the octant through it, write the octant's partial sums.  In the persistent
 // sweep (PERSIST) the upwind face-neighbour tiles are awaited after the staging loads
 // have been issued and before any face data is read.
-template <typename Real, bool DFORM, bool PERSIST, int NQ, bool MULTI>
+template <typename Real, bool DFORM, bool PERSIST, int NQ, bool MULTI, int ORD>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, int f, int packed, int par,
                                            unsigned char *lds_raw, const int *done, int epoch, int ntiles, int nt0,
                                            int nt1, int *err, uint64_t limit_ticks)
 {
     const int W = blockDim.x >> 6;
+    constexpr int SE = stage_edge<ORD>(), NS = stage_cells<ORD>();
     // LDS: per-wave ray geometry, staged S and chi, per-wave cube and partial sums
     uint32_t *geoL = reinterpret_cast<uint32_t *>(lds_raw);
     double *SL = reinterpret_cast<double *>(lds_raw + W * GEO_BYTES);
-    Real *chiL = reinterpret_cast<Real *>(SL + TILE_LDS);
-    Real *waveL = chiL + TILE_LDS;
+    Real *chiL = reinterpret_cast<Real *>(SL + NS);
+    Real *waveL = chiL + NS;
 
     TileCtx c;
     c.f = f;
@@ -497,29 +635,31 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     if (!PERSIST && wave < A.R) shell_load<Real>(A, c, oct * A.R + wave, lane, sh);
 
     // ---- stage chi and S of the tile and its upwind halo in LDS --------------------
-    // each pass issues all of its loads before the first LDS store.  Inside the grid
-    // the real cell index is linear in the flipped local coordinates (strides dX, dY,
-    // dZ); only tiles whose upwind halo leaves the grid fold indices per axis.
+    // (second order: also the downwind layer).  Each pass issues all of its loads
+    // before the first LDS store.  Inside the grid the real cell index is linear in
+    // the flipped local coordinates (strides dX, dY, dZ); only tiles whose staged
+    // region leaves the grid fold indices per axis.
     const Real *chif = A.chi + c.fbase;
     const double *Sf = A.S + c.fbase;
     const int dX = c.sgx, dY = c.sgy * A.n[0], dZ = c.sgz * A.n[0] * A.n[1];
-    const bool inner = c.tx > 0 && c.ty > 0 && c.tz > 0;
+    const bool inner = c.tx > 0 && c.ty > 0 && c.tz > 0 &&
+                       (ORD == 0 || (c.g0x + T < A.n[0] && c.g0y + T < A.n[1] && c.g0z + T < A.n[2]));
     const int64_t cellH = inner ? ((int64_t)to_real(c.g0z - 1, c.sgz, A.n[2]) * A.n[1] +
                                    to_real(c.g0y - 1, c.sgy, A.n[1])) * A.n[0] + to_real(c.g0x - 1, c.sgx, A.n[0])
                                 : 0;
-    constexpr int STAGE_K = 3;   // one pass for four or more waves
-    for (int base = 0; base < TILE_LDS; base += STAGE_K * (int)blockDim.x) {
+    constexpr int STAGE_K = ORD ? 4 : 3;   // one pass for four or more waves
+    for (int base = 0; base < NS; base += STAGE_K * (int)blockDim.x) {
         Real cv[STAGE_K];
         double sv[STAGE_K];
         int li[STAGE_K];
 #pragma unroll
         for (int k = 0; k < STAGE_K; ++k) {
             const int idx = base + k * (int)blockDim.x + (int)threadIdx.x;
-            const int lx = idx % TP, ly = (idx / TP) % TP, lz = idx / (TP * TP);
+            const int lx = idx % SE, ly = (idx / SE) % SE, lz = idx / (SE * SE);
             li[k] = -1;
             cv[k] = Real(0);
             sv[k] = 0.0;
-            if (idx >= TILE_LDS || lx > c.ex || ly > c.ey || lz > c.ez) continue;
+            if (idx >= NS || lx > c.ex + ORD || ly > c.ey + ORD || lz > c.ez + ORD) continue;
             int64_t cell;
             if (inner) {
                 cell = cellH + (lx * dX + ly * dY + lz * dZ);
@@ -571,11 +711,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         const int b = 3 - d - a;
         const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
         if (d == 0)
-            ray_planes<Real, MULTI, NQ, 0, DFORM>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 0, DFORM, ORD>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         else if (d == 1)
-            ray_planes<Real, MULTI, NQ, 1, DFORM>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 1, DFORM, ORD>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         else
-            ray_planes<Real, MULTI, NQ, 2, DFORM>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 2, DFORM, ORD>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
         wave_lds_sync();
     };
     if constexpr (!MULTI) {
@@ -595,7 +735,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             }
             sweep_ray(ray);
             if (more) {
-                write_faces<Real, DFORM>(A, c, ray, lane, Ic, SL);
+                write_faces<Real, DFORM, ORD>(A, c, ray, lane, Ic, SL);
                 wave_lds_sync();
                 shell_store<Real>(sh, Ic);
                 if (lane < GEO_WORDS) geo[lane] = gword;
@@ -661,12 +801,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         for (int i = 0; i < COMB_K; ++i)
             if (dst[i]) *dst[i] = acc[i];
     }
-    if (last >= 0) write_faces<Real, DFORM>(A, c, last, lane, Ic, SL);
+    if (last >= 0) write_faces<Real, DFORM, ORD>(A, c, last, lane, Ic, SL);
 }
 
 // One stage (all tiles with tx + ty + tz = s) of all octants and the active bins
 // f0 .. f0 + nfc - 1.
-template <typename Real, bool DFORM, int NQ, bool MULTI>
+template <typename Real, bool DFORM, int NQ, bool MULTI, int ORD>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -678,14 +818,14 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<R
     const int packed = A.tiles[A.stage_off + item];
     // the three loads go out together (every value takes part in the test)
     if (frozen | (packed < 0) | (par < 0)) return;
-    sweep_tile<Real, DFORM, false, NQ, MULTI>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
+    sweep_tile<Real, DFORM, false, NQ, MULTI, ORD>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
 // Batched form: one launch runs stage s of every problem of a batch class (same
 // precision and waves per workgroup).  blockIdx.y is the problem; x runs over its
 // bins, tiles of stage s and octants.  Problems with fewer stages, and blocks beyond
 // a problem's stage, exit at once.
-template <typename Real, bool DFORM, bool MULTI>
+template <typename Real, bool DFORM, bool MULTI, int ORD>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_batch_stage_kernel(const SweepArgs<Real> *args, int s)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -701,7 +841,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_batch_stage_kernel(const
     const int par = A.parity[f];
     const int packed = A.tiles[off + (rem >> 3)];
     if (frozen | (packed < 0) | (par < 0)) return;
-    sweep_tile<Real, DFORM, false, 1, MULTI>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
+    sweep_tile<Real, DFORM, false, 1, MULTI, ORD>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
 // Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
@@ -726,7 +866,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
         const int tile = t - f * D.ntiles;
         if (A.frozen[f]) continue;
         const int packed = A.tiles[tile];
-        sweep_tile<Real, DFORM, true, 1, true>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
+        sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
                                       D.nt1, D.err, D.wait_ticks);
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -739,8 +879,11 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
 
 // ---- Lambda*: diagonal of the formal-solution operator (section 3.4) -----------------
 // Lambda*_ii = sum_k w_k psi0_k: the weight of S at the vertex itself in its own
-// update.  psi0 depends only on the upwind chi, so this is a pointwise kernel.
-__global__ void lambda_star_kernel(int nx, int ny, int nz, int px, int py, int pz, int nf, int na,
+// update.  psi0 depends only on the upwind chi, so this is a pointwise kernel.  In the
+// second-order form the weight taken is beta_k, the coefficient of S0 itself; the
+// control point's share gamma_k is left out (it enters only through the clamped
+// parabola and makes the Jacobi iteration cycle where the clamp switches).
+__global__ void lambda_star_kernel(int nx, int ny, int nz, int px, int py, int pz, int nf, int na, int order,
                                    const RayGeo *rays, const double *chi, double *lam)
 {
     const int64_t cells = (int64_t)nx * ny * nz;
@@ -767,8 +910,14 @@ __global__ void lambda_star_kernel(int nx, int ny, int nz, int px, int py, int p
             const int ux = fold(x - ox * sx, nx, px), uy = fold(y - oy * sy, ny, py), uz = fold(z - oz * sz, nz, pz);
             cm += G->w4[v] * cf[((int64_t)uz * ny + uy) * nx + ux];
         }
+        const double dt = 0.5 * G->s * (cm + c0);
         double E, pm, p0;
-        seg_coeffs(0.5 * G->s * (cm + c0), E, pm, p0);
+        if (order) {
+            double ga;
+            bezier_coeffs(dt, E, pm, p0, ga);
+        } else {
+            seg_coeffs(dt, E, pm, p0);
+        }
         acc += G->wk * p0;
     }
     lam[i] = acc;
@@ -1201,22 +1350,32 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
-size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi)
+size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi, int order)
 {
-    return (size_t)waves * GEO_BYTES + sizeof(double) * (size_t)TILE_LDS +
-           (size_t)real_bytes * ((size_t)TILE_LDS + (size_t)waves * (size_t)wave_lds(nq, multi));
+    const size_t staged = order ? (size_t)stage_cells<1>() : (size_t)stage_cells<0>();
+    return (size_t)waves * GEO_BYTES + sizeof(double) * staged +
+           (size_t)real_bytes * (staged + (size_t)waves * (size_t)wave_lds(nq, multi));
+}
+
+template <typename Real, bool DFORM, int NQ, int ORD>
+static void launch_stage_ord(const SweepArgs<Real> &A, int waves, hipStream_t st)
+{
+    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
+    const bool multi = A.R > waves;
+    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, NQ, multi, ORD);
+    if (multi)
+        hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, true, ORD>), grid, dim3(64 * waves), lds, st, A);
+    else
+        hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, false, ORD>), grid, dim3(64 * waves), lds, st, A);
 }
 
 template <typename Real, bool DFORM, int NQ>
 static void launch_stage(const SweepArgs<Real> &A, int waves, hipStream_t st)
 {
-    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
-    const bool multi = A.R > waves;
-    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, NQ, multi);
-    if (multi)
-        hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, true>), grid, dim3(64 * waves), lds, st, A);
+    if (A.order)
+        launch_stage_ord<Real, DFORM, NQ, 1>(A, waves, st);
     else
-        hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, false>), grid, dim3(64 * waves), lds, st, A);
+        launch_stage_ord<Real, DFORM, NQ, 0>(A, waves, st);
 }
 
 hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq, hipStream_t st)
@@ -1237,29 +1396,35 @@ hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, 
     return hipGetLastError();
 }
 
-template <typename Real, bool DFORM>
+template <typename Real, bool DFORM, int ORD>
 static void launch_batch_stage(const SweepArgs<Real> *args, int nprob, int s, int max_items, int waves, bool multi,
                                hipStream_t st)
 {
     dim3 grid((unsigned)max_items, (unsigned)nprob);
-    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, 1, multi);
+    const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, 1, multi, ORD);
     if (multi)
-        hipLaunchKernelGGL((sweep_batch_stage_kernel<Real, DFORM, true>), grid, dim3(64 * waves), lds, st, args, s);
+        hipLaunchKernelGGL((sweep_batch_stage_kernel<Real, DFORM, true, ORD>), grid, dim3(64 * waves), lds, st, args, s);
     else
-        hipLaunchKernelGGL((sweep_batch_stage_kernel<Real, DFORM, false>), grid, dim3(64 * waves), lds, st, args, s);
+        hipLaunchKernelGGL((sweep_batch_stage_kernel<Real, DFORM, false, ORD>), grid, dim3(64 * waves), lds, st, args, s);
 }
 
 hipError_t launch_sweep_batch_stage_f64(const SweepArgs<double> *args, int nprob, int s, int max_items, int waves,
-                                        bool multi, hipStream_t st)
+                                        bool multi, int order, hipStream_t st)
 {
-    launch_batch_stage<double, false>(args, nprob, s, max_items, waves, multi, st);
+    if (order)
+        launch_batch_stage<double, false, 1>(args, nprob, s, max_items, waves, multi, st);
+    else
+        launch_batch_stage<double, false, 0>(args, nprob, s, max_items, waves, multi, st);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_batch_stage_f32(const SweepArgs<float> *args, int nprob, int s, int max_items, int waves,
-                                        bool multi, hipStream_t st)
+                                        bool multi, int order, hipStream_t st)
 {
-    launch_batch_stage<float, true>(args, nprob, s, max_items, waves, multi, st);
+    if (order)
+        launch_batch_stage<float, true, 1>(args, nprob, s, max_items, waves, multi, st);
+    else
+        launch_batch_stage<float, true, 0>(args, nprob, s, max_items, waves, multi, st);
     return hipGetLastError();
 }
 
@@ -1268,7 +1433,7 @@ static hipError_t launch_persistent(const SweepArgs<Real> &A, const DagArgs &D, 
                                     hipStream_t st)
 {
     hipLaunchKernelGGL((sweep_persistent_kernel<Real, DFORM>), dim3(8u * (unsigned)blocks_per_octant), dim3(64 * waves),
-                       sweep_lds_bytes(sizeof(Real), waves, 1, true), st, A, D);
+                       sweep_lds_bytes(sizeof(Real), waves, 1, true, 0), st, A, D);
     return hipGetLastError();
 }
 
@@ -1284,20 +1449,20 @@ hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs 
 
 hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks)
 {
-    const size_t lds = sweep_lds_bytes(real_bytes, waves, 1, true);
+    const size_t lds = sweep_lds_bytes(real_bytes, waves, 1, true, 0);
     if (real_bytes == 8)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<double, false>, 64 * waves, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_kernel<float, true>, 64 * waves, lds);
 }
 
-hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na,
+hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na, int order,
                               const RayGeo *rays, const double *chi, double *lam, hipStream_t st)
 {
     (void)bc_hi;  // periodic axes are periodic on both faces
     const int64_t tot = (int64_t)n[0] * n[1] * n[2] * nf;
     hipLaunchKernelGGL(lambda_star_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, st, n[0], n[1], n[2],
                        (int)(bc_lo[0] == BC_PERIODIC), (int)(bc_lo[1] == BC_PERIODIC), (int)(bc_lo[2] == BC_PERIODIC),
-                       nf, na, rays, chi, lam);
+                       nf, na, order, rays, chi, lam);
     return hipGetLastError();
 }
 

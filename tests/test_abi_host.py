@@ -69,6 +69,7 @@ def test_invalid_arguments_are_rejected(rt):
         dict(shape=(4, 4, 4), bc_lo=(2, 2, 3), bc_hi=(2, 2, 0)),        # FIXED without data
         dict(shape=(4, 4, 4), precision=7),
         dict(shape=(4, 4, 4), bc_lo=(9, 2, 1), bc_hi=(9, 2, 0)),
+        dict(shape=(4, 4, 4), order=2),
     ]
     for kw in cases:
         d = rt.make_desc(**kw)
