@@ -33,19 +33,26 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # quarter-rate exp 4), g = (1 - E)/dtau (sub 1 + quarter-rate rcp 4 + mul 1),
 # D update (3), accumulation of w D (1).
 OPS_PER_UPDATE_F32 = 12 + 2 + 5 + 6 + 3 + 1
+# Second-order (Bezier) FP32 update, closed-form branch: 5 bilinear interpolations
+# (I-, S-, chi-, S+, chi+: 20), dtau- and dtau+ (4), exp (5), E + alpha and gamma from
+# e1, e2 with one reciprocal (15), S- - S0 and S+ - S0 formed in FP64 and converted (4),
+# the control point (t = h1/h2 by reciprocal 5, a - b t^2 2, / 2(1 + t) by reciprocal
+# 6, clamp between a and 0 4: 17), D update (3), accumulation (1).
+OPS_PER_UPDATE_BEZ_F32 = 20 + 4 + 5 + 15 + 4 + 17 + 3 + 1
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md")
+TRAFFIC_PROFILE = {"linear": os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md"),
+                   "bezier": os.path.join(ROOT, "profiles", "sweep_stage_f32_bezier_scattering128_traffic.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(order="linear"):
     """HBM bytes per sweep-stage launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summary (calibrated against a plain copy), or None when the kernel source has changed
     since the counters were taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILE[order]).read()
         fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
                                                                                    "kernel_source_sha256:")))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
@@ -61,13 +68,13 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def cpu_baseline(wl, sweeps):
+def cpu_baseline(wl, sweeps, order=0):
     """FP64 oracle (single thread, as it stands) timed on a bounded number of formal
     solutions of the same workload."""
     import numpy as np
     import oracle
     oracle.build(force=False)
-    op = oracle.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi)
+    op = oracle.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, order=order)
     S = wl.B.copy()
     t0 = time.perf_counter()
     for _ in range(sweeps):
@@ -75,7 +82,8 @@ def cpu_baseline(wl, sweeps):
     dt = time.perf_counter() - t0
     updates = wl.cells * wl.na * wl.nf * sweeps
     return {"value": updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} formal solutions (sweeps) of the {wl.shape[0]}^3 x {wl.na}-ray workload, "
+            "sample": f"{sweeps} formal solutions (sweeps) of the {wl.shape[0]}^3 x {wl.na}-ray workload"
+                      f"{' (second order)' if order else ''}, "
                       f"{updates / 1e6:.1f} M updates in {dt:.1f} s, FP64, one thread"}
 
 
@@ -310,6 +318,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 GPU comparison solve")
     ap.add_argument("--schedule", choices=["stages"], default="stages")
+    ap.add_argument("--order", choices=["linear", "bezier"], default="linear",
+                    help="scattering: first-order or second-order (Bezier) short characteristics")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="profiling mode: run exactly this many ALI iterations per step instead of converging")
     ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
@@ -367,8 +377,10 @@ def main():
     mom = {k: torch.empty(m * cells, dtype=torch.float64, device="cuda")
            for k, m in (("J_int", 1), ("H_int", 3), ("K_int", 6), ("f_int", 6), ("Q_int", 1))}
     sched = rt.RT_SCHED_STAGES
+    order = rt.RT_SC_BEZIER if args.order == "bezier" else rt.RT_SC_LINEAR
+    ops_per_update = OPS_PER_UPDATE_BEZ_F32 if order else OPS_PER_UPDATE_F32
     prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
-                      schedule=sched)
+                      schedule=sched, order=order)
 
     def step():
         prob.reset_periodic()
@@ -404,19 +416,19 @@ def main():
     updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + len(iters)))
     value = updates / total
     kernel_s = prof["kernel_ms"] / 1e3
-    achieved = prof["updates"] * OPS_PER_UPDATE_F32 / kernel_s / 1e12 if kernel_s > 0 else 0.0
+    achieved = prof["updates"] * ops_per_update / kernel_s / 1e12 if kernel_s > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(),
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(args.order),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "sweep_stage_kernel<float, true, 1, false>",
+                "kernel": f"sweep_stage_kernel<float, true, 1, false, {order}>",
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
-                "ops_per_update": OPS_PER_UPDATE_F32}
+                "ops_per_update": ops_per_update}
 
     extra = {}
     if not args.no_f64:
         p64 = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F64,
-                         schedule=sched)
+                         schedule=sched, order=order)
         p64.set_fields(chi, eps, B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -437,7 +449,9 @@ def main():
         "data": "synthetic (seeded, generated on the host)",
         "config": {"workload": f"scattering {wl.shape[0]}^3, 1 bin, {wl.na} rays, eps=1e-3, "
                                f"vertical tau 1e4, Jacobi ALI from S=B to max|dS/S|<=1e-6, "
-                               f"FP32 sweeps + FP64 updates", "grid": list(wl.shape), "rays": wl.na,
+                               f"FP32 sweeps + FP64 updates"
+                               f"{', second-order (Bezier) segments' if order else ''}",
+                   "grid": list(wl.shape), "rays": wl.na, "order": args.order,
                    "schedule": args.schedule,
                    "bins": wl.nf},
         "ali_solves_per_s": args.steps / total,
@@ -449,7 +463,7 @@ def main():
     }
     out.update(extra)
     if args.cpu_sweeps > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps, order)
     prob.close()
     print(json.dumps(out), flush=True)
 
