@@ -15,6 +15,7 @@
 #include <thread>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -297,6 +298,8 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(RT_E_INVALID, "grid dimensions must be >= 1");
     if (d->nx > 8000 || d->ny > 8000 || d->nz > 8000) return fail(RT_E_INVALID, "grid dimension above 8000");
     if (d->nf < 1 || d->nf > 65535) return fail(RT_E_INVALID, "nf must be in [1, 65535]");
+    if ((int64_t)d->nx * d->ny * d->nz > INT32_MAX)
+        return fail(RT_E_UNSUPPORTED, "more than 2^31 - 1 vertices per bin (the sweep indexes a bin with 32 bits)");
     if (!(d->dx > 0.0) || !(d->dy > 0.0) || !(d->dz > 0.0) || !std::isfinite(d->dx) || !std::isfinite(d->dy) ||
         !std::isfinite(d->dz))
         return fail(RT_E_INVALID, "dx, dy, dz must be finite and > 0");

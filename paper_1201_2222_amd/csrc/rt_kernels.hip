@@ -72,12 +72,12 @@ __device__ __forceinline__ V sel3(int q, V x, V y, V z) { return q == 0 ? x : (q
 
 __device__ __forceinline__ int to_real(int g, int sg, int n) { return sg > 0 ? g : n - 1 - g; }
 
-// One-step-outside index brought back in: wrap on periodic axes, clamp otherwise.
+// One-step-outside index brought back in: wrap on periodic axes, clamp otherwise
+// (selects, no branch).
 __device__ __forceinline__ int fold(int x, int n, int periodic)
 {
-    if (x >= 0 && x < n) return x;
-    if (periodic) return x < 0 ? x + n : x - n;
-    return x < 0 ? 0 : n - 1;
+    const int lo = periodic ? x + n : 0, hi = periodic ? x - n : n - 1;
+    return x < 0 ? lo : (x >= n ? hi : x);
 }
 
 // ---- segment integration -------------------------------------------------------
@@ -275,13 +275,16 @@ __device__ __forceinline__ void ghost_source(const SweepArgs<Real> &A, const Til
 
 // The upwind shell of one ray's LDS cube: the planes x = -1, y = -1 and z = -1 of
 // the tile in flipped local coordinates, edges and corner included (the cube has
-// the staged tile's layout), 217 vertices, four per lane.  Each comes from the
-// padded face plane of its axis at the tile's slot: the downwind face of the
-// upwind neighbour tile, or a ghost value written before the sweep.  shell_load
-// issues the loads into registers and shell_store writes them into the cube, so
-// the loads of the next ray are in flight while a ray is swept.
-constexpr int SHELL_X = TP * TP, SHELL_Y = T * TP, SHELL_Z = T * T;
-constexpr int SHELL_PER_LANE = (SHELL_X + SHELL_Y + SHELL_Z + 63) / 64;
+// the staged tile's layout), 217 vertices.  Each comes from the padded face plane of
+// its axis at the tile's slot: the downwind face of the upwind neighbour tile, or a
+// ghost value written before the sweep.  Lane l loads vertex (u, w) = (l & 7, l >> 3)
+// of the interior (8 x 8) of each of the three planes, and lanes 0 .. 24 one of the 25
+// vertices on the cube's edges at -1: x plane row z = -1 (9, corner included), x plane
+// column y = -1 (8), y plane row z = -1 (8).  Offsets inside a slot are 32-bit and
+// the slot bases wave-uniform.  shell_load issues the loads into registers and
+// shell_store writes them into the cube, so the loads of the next ray are in flight
+// while a ray is swept.
+constexpr int SHELL_PER_LANE = 4;
 
 template <typename Real>
 struct Shell {
@@ -293,36 +296,45 @@ template <typename Real>
 __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileCtx &c, int ray, int lane, Shell<Real> &sh)
 {
     const int64_t rb = (int64_t)c.f * A.na + ray;
-#pragma unroll
-    for (int k = 0; k < SHELL_PER_LANE; ++k) {
-        const int e = lane + 64 * k;
-        int lx, ly, lz;
-        const Real *src;
-        if (e < SHELL_X) {
-            lx = -1;
-            ly = e % TP - 1;
-            lz = e / TP - 1;
-            src = A.face[0] + (rb * A.nt[0] + c.tx) * A.pplane[0] + (int64_t)(c.g0z + lz + 1) * (A.n[1] + 1) +
-                  (c.g0y + ly + 1);
-        } else if (e < SHELL_X + SHELL_Y) {
-            const int e2 = e - SHELL_X;
-            ly = -1;
-            lx = e2 % T;
-            lz = e2 / T - 1;
-            src = A.face[1] + (rb * A.nt[1] + c.ty) * A.pplane[1] + (int64_t)(c.g0z + lz + 1) * (A.n[0] + 1) +
-                  (c.g0x + lx + 1);
-        } else {
-            const int e3 = e - SHELL_X - SHELL_Y;
-            lz = -1;
-            lx = e3 % T;
-            ly = e3 / T;
-            src = A.face[2] + (rb * A.nt[2] + c.tz) * A.pplane[2] + (int64_t)(c.g0y + ly + 1) * (A.n[0] + 1) +
-                  (c.g0x + lx + 1);
-        }
-        const bool ok = e < SHELL_X + SHELL_Y + SHELL_Z && lx < c.ex && ly < c.ey && lz < c.ez;
-        sh.slot[k] = ok ? ((lz + 1) * TP + (ly + 1)) * TP + (lx + 1) : -1;
-        sh.v[k] = ok ? *src : Real(0);
+    const Real *bx = A.face[0] + (rb * A.nt[0] + c.tx) * A.pplane[0];
+    const Real *by = A.face[1] + (rb * A.nt[1] + c.ty) * A.pplane[1];
+    const Real *bz = A.face[2] + (rb * A.nt[2] + c.tz) * A.pplane[2];
+    const int px = A.n[1] + 1;    // row pitch of an x plane (y fastest, then z)
+    const int pxy = A.n[0] + 1;   // row pitch of y and z planes (x fastest)
+    const int u = lane & (T - 1), w = lane / T;
+    // interiors: x plane (y, z) = (u, w); y plane (x, z) = (u, w); z plane (x, y) = (u, w)
+    const bool okx = u < c.ey && w < c.ez, oky = u < c.ex && w < c.ez, okz = u < c.ex && w < c.ey;
+    const uint32_t ox = (uint32_t)((c.g0z + w + 1) * px + (c.g0y + u + 1));
+    const uint32_t oy = (uint32_t)((c.g0z + w + 1) * pxy + (c.g0x + u + 1));
+    const uint32_t oz = (uint32_t)((c.g0y + w + 1) * pxy + (c.g0x + u + 1));
+    sh.slot[0] = okx ? ((w + 1) * TP + (u + 1)) * TP : -1;
+    sh.slot[1] = oky ? (w + 1) * TP * TP + (u + 1) : -1;
+    sh.slot[2] = okz ? (w + 1) * TP + (u + 1) : -1;
+    sh.v[0] = okx ? bx[ox] : Real(0);
+    sh.v[1] = oky ? by[oy] : Real(0);
+    sh.v[2] = okz ? bz[oz] : Real(0);
+    // edges
+    const int e = lane;
+    const bool row_x = e < TP, col_x = e >= TP && e < TP + T, row_y = e >= TP + T && e < TP + 2 * T;
+    const int j = row_x ? e : (col_x ? e - TP : e - TP - T);   // position along the edge
+    bool oke;
+    uint32_t oe;
+    int se;
+    if (row_x) {            // x plane, z = -1, y = j - 1
+        oke = j <= c.ey;
+        oe = (uint32_t)(c.g0z * px + c.g0y + j);
+        se = j * TP;
+    } else if (col_x) {     // x plane, y = -1, z = j
+        oke = j < c.ez;
+        oe = (uint32_t)((c.g0z + j + 1) * px + c.g0y);
+        se = (j + 1) * TP * TP;
+    } else {                // y plane, z = -1, x = j
+        oke = row_y && j < c.ex;
+        oe = (uint32_t)(c.g0z * pxy + c.g0x + j + 1);
+        se = j + 1;
     }
+    sh.slot[3] = oke ? se : -1;
+    sh.v[3] = oke ? (row_y ? by : bx)[oe] : Real(0);
 }
 
 template <typename Real>
@@ -344,58 +356,47 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
     constexpr int SE = stage_edge<ORD>();   // edge of the staged S cube
     const int64_t rb = (int64_t)c.f * A.na + ray;
     const int u = lane % T, w = lane / T;   // T * T == 64 face vertices, one per lane
-    // every address and value first, then the stores back to back (a register that a
-    // store still reads must not be reused before the store has completed)
-    Real *pf[3] = {nullptr, nullptr, nullptr};
-    double *pw[3] = {nullptr, nullptr, nullptr};
-    Real vf[3];
-    double vw[3];
-    // x face: (y, z) = (u, w)
-    {
-        const int li = ((w + 1) * TP + (u + 1)) * TP + c.ex;
-        const int ls = ((w + 1) * SE + (u + 1)) * SE + c.ex;
-        const int vy = c.g0y + u, vz = c.g0z + w;
-        vf[0] = Ic[li];
-        vw[0] = DFORM ? double(vf[0]) + SL[ls] : double(vf[0]);
-        if (u < c.ey && w < c.ez) {
-            if (c.tx < A.nt[0] - 1)
-                pf[0] = A.face[0] + (rb * A.nt[0] + c.tx + 1) * A.pplane[0] + (int64_t)(vz + 1) * (A.n[1] + 1) + (vy + 1);
-            else if (A.periodic[0])
-                pw[0] = A.wrap[0] + (rb * 2 + (c.par ^ 1)) * A.plane[0] + (int64_t)vz * A.n[1] + vy;
-        }
+    // Per axis q the face goes to the next tile's slot of the padded planes (interior)
+    // or, behind the grid's last tile on a periodic axis, to the periodic memory; the
+    // choice is wave-uniform.  Bases are wave-uniform, offsets 32-bit.  Every value
+    // first, then the stores back to back (a register that a store still reads must
+    // not be reused before the store has completed).
+    const bool inx = c.tx < A.nt[0] - 1, iny = c.ty < A.nt[1] - 1, inz = c.tz < A.nt[2] - 1;
+    Real *fx = A.face[0] + (rb * A.nt[0] + c.tx + 1) * A.pplane[0];
+    Real *fy = A.face[1] + (rb * A.nt[1] + c.ty + 1) * A.pplane[1];
+    Real *fz = A.face[2] + (rb * A.nt[2] + c.tz + 1) * A.pplane[2];
+    double *wx = A.wrap[0] + (rb * 2 + (c.par ^ 1)) * A.plane[0];
+    double *wy = A.wrap[1] + (rb * 2 + (c.par ^ 1)) * A.plane[1];
+    double *wz = A.wrap[2] + (rb * 2 + (c.par ^ 1)) * A.plane[2];
+    const bool px = !inx && A.periodic[0], py = !iny && A.periodic[1], pz = !inz && A.periodic[2];
+    // x face: (y, z) = (u, w); y face: (x, z) = (u, w); z face: (x, y) = (u, w)
+    const bool okx = u < c.ey && w < c.ez, oky = u < c.ex && w < c.ez, okz = u < c.ex && w < c.ey;
+    const Real vx = Ic[((w + 1) * TP + (u + 1)) * TP + c.ex];
+    const Real vy = Ic[((w + 1) * TP + c.ey) * TP + (u + 1)];
+    const Real vz = Ic[(c.ez * TP + (w + 1)) * TP + (u + 1)];
+    double ix = double(vx), iy = double(vy), iz = double(vz);
+    if constexpr (DFORM) {   // the periodic memory keeps I = D + S
+        ix += SL[((w + 1) * SE + (u + 1)) * SE + c.ex];
+        iy += SL[((w + 1) * SE + c.ey) * SE + (u + 1)];
+        iz += SL[(c.ez * SE + (w + 1)) * SE + (u + 1)];
     }
-    // y face: (x, z) = (u, w)
-    {
-        const int li = ((w + 1) * TP + c.ey) * TP + (u + 1);
-        const int ls = ((w + 1) * SE + c.ey) * SE + (u + 1);
-        const int vx = c.g0x + u, vz = c.g0z + w;
-        vf[1] = Ic[li];
-        vw[1] = DFORM ? double(vf[1]) + SL[ls] : double(vf[1]);
-        if (u < c.ex && w < c.ez) {
-            if (c.ty < A.nt[1] - 1)
-                pf[1] = A.face[1] + (rb * A.nt[1] + c.ty + 1) * A.pplane[1] + (int64_t)(vz + 1) * (A.n[0] + 1) + (vx + 1);
-            else if (A.periodic[1])
-                pw[1] = A.wrap[1] + (rb * 2 + (c.par ^ 1)) * A.plane[1] + (int64_t)vz * A.n[0] + vx;
-        }
+    const uint32_t ofx = (uint32_t)((c.g0z + w + 1) * (A.n[1] + 1) + (c.g0y + u + 1));
+    const uint32_t ofy = (uint32_t)((c.g0z + w + 1) * (A.n[0] + 1) + (c.g0x + u + 1));
+    const uint32_t ofz = (uint32_t)((c.g0y + w + 1) * (A.n[0] + 1) + (c.g0x + u + 1));
+    const uint32_t owx = (uint32_t)((c.g0z + w) * A.n[1] + (c.g0y + u));
+    const uint32_t owy = (uint32_t)((c.g0z + w) * A.n[0] + (c.g0x + u));
+    const uint32_t owz = (uint32_t)((c.g0y + w) * A.n[0] + (c.g0x + u));
+    if (okx) {
+        if (inx) fx[ofx] = vx;
+        else if (px) wx[owx] = ix;
     }
-    // z face: (x, y) = (u, w)
-    {
-        const int li = (c.ez * TP + (w + 1)) * TP + (u + 1);
-        const int ls = (c.ez * SE + (w + 1)) * SE + (u + 1);
-        const int vx = c.g0x + u, vy = c.g0y + w;
-        vf[2] = Ic[li];
-        vw[2] = DFORM ? double(vf[2]) + SL[ls] : double(vf[2]);
-        if (u < c.ex && w < c.ey) {
-            if (c.tz < A.nt[2] - 1)
-                pf[2] = A.face[2] + (rb * A.nt[2] + c.tz + 1) * A.pplane[2] + (int64_t)(vy + 1) * (A.n[0] + 1) + (vx + 1);
-            else if (A.periodic[2])
-                pw[2] = A.wrap[2] + (rb * 2 + (c.par ^ 1)) * A.plane[2] + (int64_t)vy * A.n[0] + vx;
-        }
+    if (oky) {
+        if (iny) fy[ofy] = vy;
+        else if (py) wy[owy] = iy;
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        if (pf[q]) *pf[q] = vf[q];
-        if (pw[q]) *pw[q] = vw[q];
+    if (okz) {
+        if (inz) fz[ofz] = vz;
+        else if (pz) wz[owz] = iz;
     }
 }
 
@@ -638,15 +639,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     // (second order: also the downwind layer).  Each pass issues all of its loads
     // before the first LDS store.  Inside the grid the real cell index is linear in
     // the flipped local coordinates (strides dX, dY, dZ); only tiles whose staged
-    // region leaves the grid fold indices per axis.
+    // region leaves the grid fold indices per axis.  Indices inside a bin are 32-bit
+    // (the library refuses bins of 2^31 or more vertices); lanes without an entry load
+    // vertex 0 and store nothing, so the loads need no branch.
     const Real *chif = A.chi + c.fbase;
     const double *Sf = A.S + c.fbase;
     const int dX = c.sgx, dY = c.sgy * A.n[0], dZ = c.sgz * A.n[0] * A.n[1];
     const bool inner = c.tx > 0 && c.ty > 0 && c.tz > 0 &&
                        (ORD == 0 || (c.g0x + T < A.n[0] && c.g0y + T < A.n[1] && c.g0z + T < A.n[2]));
-    const int64_t cellH = inner ? ((int64_t)to_real(c.g0z - 1, c.sgz, A.n[2]) * A.n[1] +
-                                   to_real(c.g0y - 1, c.sgy, A.n[1])) * A.n[0] + to_real(c.g0x - 1, c.sgx, A.n[0])
-                                : 0;
+    const int cellH = inner ? (to_real(c.g0z - 1, c.sgz, A.n[2]) * A.n[1] + to_real(c.g0y - 1, c.sgy, A.n[1])) *
+                                      A.n[0] + to_real(c.g0x - 1, c.sgx, A.n[0])
+                            : 0;
     constexpr int STAGE_K = ORD ? 4 : 3;   // one pass for four or more waves
     for (int base = 0; base < NS; base += STAGE_K * (int)blockDim.x) {
         Real cv[STAGE_K];
@@ -656,22 +659,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         for (int k = 0; k < STAGE_K; ++k) {
             const int idx = base + k * (int)blockDim.x + (int)threadIdx.x;
             const int lx = idx % SE, ly = (idx / SE) % SE, lz = idx / (SE * SE);
-            li[k] = -1;
-            cv[k] = Real(0);
-            sv[k] = 0.0;
-            if (idx >= NS || lx > c.ex + ORD || ly > c.ey + ORD || lz > c.ez + ORD) continue;
-            int64_t cell;
+            const bool ok = idx < NS && lx <= c.ex + ORD && ly <= c.ey + ORD && lz <= c.ez + ORD;
+            int cell;
             if (inner) {
                 cell = cellH + (lx * dX + ly * dY + lz * dZ);
             } else {
                 const int rx = fold(to_real(c.g0x + lx - 1, c.sgx, A.n[0]), A.n[0], A.periodic[0]);
                 const int ry = fold(to_real(c.g0y + ly - 1, c.sgy, A.n[1]), A.n[1], A.periodic[1]);
                 const int rz = fold(to_real(c.g0z + lz - 1, c.sgz, A.n[2]), A.n[2], A.periodic[2]);
-                cell = ((int64_t)rz * A.n[1] + ry) * A.n[0] + rx;
+                cell = (rz * A.n[1] + ry) * A.n[0] + rx;
             }
-            li[k] = idx;
-            cv[k] = chif[cell];
-            sv[k] = Sf[cell];
+            const uint32_t uc = ok ? (uint32_t)cell : 0u;
+            li[k] = ok ? idx : -1;
+            cv[k] = chif[uc];
+            sv[k] = Sf[uc];
         }
 #pragma unroll
         for (int k = 0; k < STAGE_K; ++k) {
@@ -764,17 +765,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         wkw[w] = ray_weight<Real, 1>(reinterpret_cast<const RayGeo *>(geoL + wr * (GEO_BYTES / 4)), 0) *
                  Real(w < W ? 1 : 0);
     }
+    // this octant's partial sums of bin f, quantity 0, at the tile's first vertex
+    Real *pbase = A.part + ((int64_t)oct * NQ * A.nfc + (f - A.f0)) * A.cells + cell0;
+    const int64_t qstride = (int64_t)A.nfc * A.cells;
     for (int base = 0; base < NQ * T * T * T; base += COMB_K * (int)blockDim.x) {
         Real acc[COMB_K];
-        Real *dst[COMB_K];
+        int64_t off[COMB_K];
+        bool ok[COMB_K];
 #pragma unroll
         for (int i = 0; i < COMB_K; ++i) {
             const int kq = base + i * (int)blockDim.x + (int)threadIdx.x;
             const int q = kq / (T * T * T), k = kq - q * T * T * T;
             const int lx = k % T, ly = (k / T) % T, lz = k / (T * T);
-            dst[i] = nullptr;
+            ok[i] = kq < NQ * T * T * T && lx < c.ex && ly < c.ey && lz < c.ez;
+            off[i] = (NQ == 1 ? 0 : q * qstride) + (lx * dX + ly * dY + lz * dZ);
             acc[i] = Real(0);
-            if (kq >= NQ * T * T * T || lx >= c.ex || ly >= c.ey || lz >= c.ez) continue;
+            if (!ok[i]) continue;
             // the accumulated tiles (MULTI), or w v from each wave's cube
             Real vw[kMaxWaves];
             const int ci = ((lz + 1) * TP + (ly + 1)) * TP + (lx + 1);
@@ -795,11 +801,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             acc[i] = vw[0];
 #pragma unroll
             for (int w = 1; w < kMaxWaves; ++w) acc[i] += vw[w];
-            dst[i] = A.part + (((int64_t)oct * NQ + q) * A.nfc + (f - A.f0)) * A.cells + cell0 + (lx * dX + ly * dY + lz * dZ);
         }
 #pragma unroll
         for (int i = 0; i < COMB_K; ++i)
-            if (dst[i]) *dst[i] = acc[i];
+            if (ok[i]) pbase[off[i]] = acc[i];
     }
     if (last >= 0) write_faces<Real, DFORM, ORD>(A, c, last, lane, Ic, SL);
 }
