@@ -24,14 +24,23 @@ namespace {
 
 constexpr int T = kTile;
 constexpr int TP = T + 1;            // tile plus one upwind halo layer
-constexpr int TILE_LDS = TP * TP * TP;
+// LDS cubes are stored with row pitch CUBE_P and plane pitch CUBE_Q (x fastest):
+// with the lanes of a wave on an 8 x 8 plane, pitches 9 and 88 give no LDS bank
+// conflicts for rays crossing x or y planes first and two-way conflicts for z (a
+// dense 9^3 cube has two-way conflicts on all three).
+constexpr int CUBE_P = 9, CUBE_Q = 88;
+constexpr int TILE_LDS = (TP - 1) * (1 + CUBE_P + CUBE_Q) + 1;   // words of a cube
 // chi and S are staged with the upwind halo, and for the second-order form also the
 // downwind layer (the downwind point of each vertex lies in the next plane):
 // edge TP, or TP + 1 with ORD = 1.
 template <int ORD>
 constexpr int stage_edge() { return ORD ? TP + 1 : TP; }
 template <int ORD>
-constexpr int stage_cells() { return stage_edge<ORD>() * stage_edge<ORD>() * stage_edge<ORD>(); }
+constexpr int stage_p() { return ORD ? 11 : CUBE_P; }      // pitches of the staged cube (edge 10: 11, 120)
+template <int ORD>
+constexpr int stage_q() { return ORD ? 120 : CUBE_Q; }
+template <int ORD>
+constexpr int stage_cells() { return (stage_edge<ORD>() - 1) * (1 + stage_p<ORD>() + stage_q<ORD>()) + 1; }
 // Reals of LDS per wave: the cube of I (or D) of its current ray, and when a wave
 // sweeps several rays of a tile (multi) nq partial-sum tiles that accumulate them
 constexpr int wave_lds(int nq, bool multi) { return TILE_LDS + (multi ? nq * T * T * T : 0); }
@@ -307,9 +316,9 @@ __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileC
     const uint32_t ox = (uint32_t)((c.g0z + w + 1) * px + (c.g0y + u + 1));
     const uint32_t oy = (uint32_t)((c.g0z + w + 1) * pxy + (c.g0x + u + 1));
     const uint32_t oz = (uint32_t)((c.g0y + w + 1) * pxy + (c.g0x + u + 1));
-    sh.slot[0] = okx ? ((w + 1) * TP + (u + 1)) * TP : -1;
-    sh.slot[1] = oky ? (w + 1) * TP * TP + (u + 1) : -1;
-    sh.slot[2] = okz ? (w + 1) * TP + (u + 1) : -1;
+    sh.slot[0] = okx ? (w + 1) * CUBE_Q + (u + 1) * CUBE_P : -1;
+    sh.slot[1] = oky ? (w + 1) * CUBE_Q + (u + 1) : -1;
+    sh.slot[2] = okz ? (w + 1) * CUBE_P + (u + 1) : -1;
     sh.v[0] = okx ? bx[ox] : Real(0);
     sh.v[1] = oky ? by[oy] : Real(0);
     sh.v[2] = okz ? bz[oz] : Real(0);
@@ -323,11 +332,11 @@ __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileC
     if (row_x) {            // x plane, z = -1, y = j - 1
         oke = j <= c.ey;
         oe = (uint32_t)(c.g0z * px + c.g0y + j);
-        se = j * TP;
+        se = j * CUBE_P;
     } else if (col_x) {     // x plane, y = -1, z = j
         oke = j < c.ez;
         oe = (uint32_t)((c.g0z + j + 1) * px + c.g0y);
-        se = (j + 1) * TP * TP;
+        se = (j + 1) * CUBE_Q;
     } else {                // y plane, z = -1, x = j
         oke = row_y && j < c.ex;
         oe = (uint32_t)(c.g0z * pxy + c.g0x + j + 1);
@@ -353,7 +362,7 @@ template <typename Real, bool DFORM, int ORD>
 __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray, int lane, const Real *Ic,
                             const double *SL)
 {
-    constexpr int SE = stage_edge<ORD>();   // edge of the staged S cube
+    constexpr int SP = stage_p<ORD>(), SQ = stage_q<ORD>();   // pitches of the staged S cube
     const int64_t rb = (int64_t)c.f * A.na + ray;
     const int u = lane % T, w = lane / T;   // T * T == 64 face vertices, one per lane
     // Per axis q the face goes to the next tile's slot of the padded planes (interior)
@@ -371,14 +380,14 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
     const bool px = !inx && A.periodic[0], py = !iny && A.periodic[1], pz = !inz && A.periodic[2];
     // x face: (y, z) = (u, w); y face: (x, z) = (u, w); z face: (x, y) = (u, w)
     const bool okx = u < c.ey && w < c.ez, oky = u < c.ex && w < c.ez, okz = u < c.ex && w < c.ey;
-    const Real vx = Ic[((w + 1) * TP + (u + 1)) * TP + c.ex];
-    const Real vy = Ic[((w + 1) * TP + c.ey) * TP + (u + 1)];
-    const Real vz = Ic[(c.ez * TP + (w + 1)) * TP + (u + 1)];
+    const Real vx = Ic[(w + 1) * CUBE_Q + (u + 1) * CUBE_P + c.ex];
+    const Real vy = Ic[(w + 1) * CUBE_Q + c.ey * CUBE_P + (u + 1)];
+    const Real vz = Ic[c.ez * CUBE_Q + (w + 1) * CUBE_P + (u + 1)];
     double ix = double(vx), iy = double(vy), iz = double(vz);
     if constexpr (DFORM) {   // the periodic memory keeps I = D + S
-        ix += SL[((w + 1) * SE + (u + 1)) * SE + c.ex];
-        iy += SL[((w + 1) * SE + c.ey) * SE + (u + 1)];
-        iz += SL[(c.ez * SE + (w + 1)) * SE + (u + 1)];
+        ix += SL[(w + 1) * SQ + (u + 1) * SP + c.ex];
+        iy += SL[(w + 1) * SQ + c.ey * SP + (u + 1)];
+        iz += SL[c.ez * SQ + (w + 1) * SP + (u + 1)];
     }
     const uint32_t ofx = (uint32_t)((c.g0z + w + 1) * (A.n[1] + 1) + (c.g0y + u + 1));
     const uint32_t ofy = (uint32_t)((c.g0z + w + 1) * (A.n[0] + 1) + (c.g0x + u + 1));
@@ -400,9 +409,9 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
     }
 }
 
-constexpr int lds_stride(int q) { return q == 0 ? 1 : (q == 1 ? TP : TP * TP); }
+constexpr int lds_stride(int q) { return q == 0 ? 1 : (q == 1 ? CUBE_P : CUBE_Q); }
 template <int ORD>
-constexpr int stage_stride(int q) { return q == 0 ? 1 : (q == 1 ? stage_edge<ORD>() : stage_edge<ORD>() * stage_edge<ORD>()); }
+constexpr int stage_stride(int q) { return q == 0 ? 1 : (q == 1 ? stage_p<ORD>() : stage_q<ORD>()); }
 constexpr int tile_stride(int q) { return q == 0 ? 1 : (q == 1 ? T : T * T); }
 
 // Plane-by-plane sweep of one ray through the tile along its first-crossed axis D
@@ -599,7 +608,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
                                            int nt1, int *err, uint64_t limit_ticks)
 {
     const int W = blockDim.x >> 6;
-    constexpr int SE = stage_edge<ORD>(), NS = stage_cells<ORD>();
+    constexpr int SE = stage_edge<ORD>(), NL = SE * SE * SE, NS = stage_cells<ORD>();
+    constexpr int SP = stage_p<ORD>(), SQ = stage_q<ORD>();
     // LDS: per-wave ray geometry, staged S and chi, per-wave cube and partial sums
     uint32_t *geoL = reinterpret_cast<uint32_t *>(lds_raw);
     double *SL = reinterpret_cast<double *>(lds_raw + W * GEO_BYTES);
@@ -651,7 +661,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
                                       A.n[0] + to_real(c.g0x - 1, c.sgx, A.n[0])
                             : 0;
     constexpr int STAGE_K = ORD ? 4 : 3;   // one pass for four or more waves
-    for (int base = 0; base < NS; base += STAGE_K * (int)blockDim.x) {
+    for (int base = 0; base < NL; base += STAGE_K * (int)blockDim.x) {
         Real cv[STAGE_K];
         double sv[STAGE_K];
         int li[STAGE_K];
@@ -659,7 +669,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
         for (int k = 0; k < STAGE_K; ++k) {
             const int idx = base + k * (int)blockDim.x + (int)threadIdx.x;
             const int lx = idx % SE, ly = (idx / SE) % SE, lz = idx / (SE * SE);
-            const bool ok = idx < NS && lx <= c.ex + ORD && ly <= c.ey + ORD && lz <= c.ez + ORD;
+            const bool ok = idx < NL && lx <= c.ex + ORD && ly <= c.ey + ORD && lz <= c.ez + ORD;
             int cell;
             if (inner) {
                 cell = cellH + (lx * dX + ly * dY + lz * dZ);
@@ -670,7 +680,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
                 cell = (rz * A.n[1] + ry) * A.n[0] + rx;
             }
             const uint32_t uc = ok ? (uint32_t)cell : 0u;
-            li[k] = ok ? idx : -1;
+            li[k] = ok ? lx + SP * ly + SQ * lz : -1;
             cv[k] = chif[uc];
             sv[k] = Sf[uc];
         }
@@ -783,7 +793,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             if (!ok[i]) continue;
             // the accumulated tiles (MULTI), or w v from each wave's cube
             Real vw[kMaxWaves];
-            const int ci = ((lz + 1) * TP + (ly + 1)) * TP + (lx + 1);
+            const int ci = (lz + 1) * CUBE_Q + (ly + 1) * CUBE_P + (lx + 1);
 #pragma unroll
             for (int w = 0; w < kMaxWaves; ++w) {
                 const int wr = w < W ? w : 0;
