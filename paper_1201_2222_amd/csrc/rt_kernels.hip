@@ -122,16 +122,18 @@ __device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
 {
     // both forms are evaluated and one is selected: no branch in the sweep step
     E = __expf(-dt);
+    // Horner steps as (-dt) acc + c: one instruction with the constant inline
+    const float m = -dt;
     float acc = 1.0f / 3628800.0f;                    // 1/10!
-    acc = 1.0f / 362880.0f - dt * acc;                // 1/9!
-    acc = 1.0f / 40320.0f - dt * acc;
-    acc = 1.0f / 5040.0f - dt * acc;
-    acc = 1.0f / 720.0f - dt * acc;
-    acc = 1.0f / 120.0f - dt * acc;
-    acc = 1.0f / 24.0f - dt * acc;
-    acc = 1.0f / 6.0f - dt * acc;
-    acc = 0.5f - dt * acc;
-    const float gs = 1.0f - dt * acc;
+    acc = fmaf(m, acc, 1.0f / 362880.0f);             // 1/9!
+    acc = fmaf(m, acc, 1.0f / 40320.0f);
+    acc = fmaf(m, acc, 1.0f / 5040.0f);
+    acc = fmaf(m, acc, 1.0f / 720.0f);
+    acc = fmaf(m, acc, 1.0f / 120.0f);
+    acc = fmaf(m, acc, 1.0f / 24.0f);
+    acc = fmaf(m, acc, 1.0f / 6.0f);
+    acc = fmaf(m, acc, 0.5f);
+    const float gs = fmaf(m, acc, 1.0f);
     const float gc = (1.0f - E) * __builtin_amdgcn_rcpf(dt);
     g = dt < 0.5f ? gs : gc;
 }
@@ -186,9 +188,10 @@ __device__ __forceinline__ void bezier_coeffs(float x, float &E, float &Ea, floa
     E = __expf(-x);
     constexpr int N = 10;
     const double c[16] = RT_INV_FACT3;
+    const float m = -x;
     float f = float(c[N - 1]);
 #pragma unroll
-    for (int n = N - 2; n >= 0; --n) f = float(c[n]) - x * f;
+    for (int n = N - 2; n >= 0; --n) f = fmaf(m, f, float(c[n]));
     const float as = x * (((x + 2.0f) * x + 2.0f) * f - 0.5f * x);
     const float gs = x * (1.0f - 2.0f * (x + 2.0f) * f);
     const float r = __builtin_amdgcn_rcpf(x);
@@ -450,7 +453,7 @@ struct SegIn {
 // ORD = 0: first order (linear source between S- and S0).  ORD = 1: second order
 // (quadratic Bezier source with the control point from S-, S0 and the downwind S+).
 template <typename Real, bool ACC, int NQ, int D, bool DFORM, int ORD>
-__device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int eb, int lane, Real *Ic,
+__device__ __forceinline__ void ray_planes(const RayGeo *G, int ea, int eb, int lane, Real *Ic,
                                            const Real *chiL, const double *SL, Real *Jw)
 {
     constexpr int DA = (D == 0) ? 1 : 0, DB = (D == 2) ? 1 : 2;
@@ -530,8 +533,10 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int 
             cc = pm * Real(Sm) + p0 * Real(x.s0);
         }
     };
-    // The recurrence along the ray, one plane per step.  Every lane steps (no
-    // branch): a lane outside a ragged tile writes only entries no active lane reads.
+    // The recurrence along the ray, one plane per step.  Every lane steps every plane
+    // (no branch, so the loads running ahead need no register copies at a join): a
+    // lane outside a ragged tile, and a plane past its end, write only cube entries no
+    // active lane reads.
     // When the wave sweeps several rays of the tile (ACC), w v (and in moments mode
     // w mu v, w mu mu v) is added to its partial-sum tiles per vertex; with one ray
     // per wave the cube itself keeps v for the sum over the waves.
@@ -540,7 +545,7 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ed, int ea, int 
     SegIn<Real> nx = load_seg(1);
 #pragma unroll
     for (int p = 0; p < T; ++p) {
-        if (p < ed) {
+        {
             const int l0 = lb + (p + 1) * SD;
             const int lu = l0 - SD;
             const Real i00 = Ic[lu], i10 = Ic[lu - SA], i01 = Ic[lu - SB], i11 = Ic[lu - SA - SB];
@@ -720,13 +725,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     auto sweep_ray = [&](int ray) {
         const int d = __builtin_amdgcn_readfirstlane(G->d), a = __builtin_amdgcn_readfirstlane(G->a);
         const int b = 3 - d - a;
-        const int ed = sel3(d, c.ex, c.ey, c.ez), ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
+        const int ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
         if (d == 0)
-            ray_planes<Real, MULTI, NQ, 0, DFORM, ORD>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 0, DFORM, ORD>(G, ea, eb, lane, Ic, chiL, SL, Jw);
         else if (d == 1)
-            ray_planes<Real, MULTI, NQ, 1, DFORM, ORD>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 1, DFORM, ORD>(G, ea, eb, lane, Ic, chiL, SL, Jw);
         else
-            ray_planes<Real, MULTI, NQ, 2, DFORM, ORD>(G, ed, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 2, DFORM, ORD>(G, ea, eb, lane, Ic, chiL, SL, Jw);
         wave_lds_sync();
     };
     if constexpr (!MULTI) {
