@@ -8,7 +8,9 @@ moment steps (this file).
 
 Paper: Davis, Stone & Jiang (2012), arXiv:1201.2222.
   * angle set ........ section 3.2 (n_a = n_mu (n_mu + 2), identical octants)
-  * formal solution .. section 3.3, eq. rtdisc, first-order form (``rt_oracle.c``)
+  * formal solution .. section 3.3, eq. rtdisc, first-order form, the second-order
+                       (Bezier) form, and the monotone quadratic upwind intensity
+                       with plane-ordered sweeps (``rt_oracle.c``)
   * Jacobi ALI ....... section 3.4, eqs. sourcefunc2 and dsjacobi, criterion eq. conv
   * boundaries ....... section 3.5 and the periodic iteration of section 3
   * moments .......... eqs. Jsum/Hsum/Ksum, VET f = K/J and Q_rad (section 4)
@@ -42,7 +44,8 @@ def build(force: bool = True) -> str:
 class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("nf", ctypes.c_int32), ("na", ctypes.c_int32),
                 ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
-                ("want_hk", ctypes.c_int32), ("h", ctypes.c_double * 3), ("order", ctypes.c_int32)]
+                ("want_hk", ctypes.c_int32), ("h", ctypes.c_double * 3), ("order", ctypes.c_int32),
+                ("interp", ctypes.c_int32)]
 
 
 _lib = None
@@ -65,6 +68,8 @@ def _load():
         lib.orc_bezier_coeffs.argtypes = [ctypes.c_double, D, D, D, D]
         lib.orc_control_point.argtypes = [ctypes.c_double] * 5
         lib.orc_control_point.restype = ctypes.c_double
+        lib.orc_quad_interp.argtypes = [ctypes.c_double] * 4
+        lib.orc_quad_interp.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -205,6 +210,12 @@ def control_point(Sm, S0, Sp, h1, h2):
     return _load().orc_control_point(float(Sm), float(S0), float(Sp), float(h1), float(h2))
 
 
+def quad_interp(fm, f0, f1, t):
+    """Monotone quadratic interpolant between f0 (t = 0) and f1 (t = 1) with the third
+    point fm at t = -1 (upwind intensity of the quadratic scheme)."""
+    return _load().orc_quad_interp(float(fm), float(f0), float(f1), float(t))
+
+
 def ray_info(mu, h=(1.0, 1.0, 1.0)):
     """(d, a, b, signs, s, fa, fb) of the short characteristic of one ray."""
     lib = _load()
@@ -231,11 +242,16 @@ class Problem:
 
     def __init__(self, shape, chi, eps, B, n_mu=4, mu=None, w=None, h=(1.0, 1.0, 1.0),
                  bc_lo=(PERIODIC, PERIODIC, THERMAL), bc_hi=(PERIODIC, PERIODIC, VACUUM),
-                 w_nu=None, fixed=None, order=0):
+                 w_nu=None, fixed=None, order=0, interp=0):
         nx, ny, nz = shape
         if order not in (0, 1):
             raise ValueError("order is 0 (first order) or 1 (second order, Bezier)")
+        if interp not in (0, 1):
+            raise ValueError("interp is 0 (bilinear I-) or 1 (monotone quadratic I-)")
+        if interp == 1 and order != 0:
+            raise ValueError("the quadratic upwind intensity is built with first-order segments only")
         self.order = int(order)
+        self.interp = int(interp)
         self.n = (int(nx), int(ny), int(nz))
         chi = np.asarray(chi, dtype=np.float64)
         self.nf = chi.size // (nx * ny * nz)
@@ -302,6 +318,7 @@ class Problem:
         g.want_hk = 1 if want_hk else 0
         g.h[:] = list(self.h)
         g.order = self.order
+        g.interp = self.interp
         shp = self.chi.shape
         J = np.zeros(shp)
         lam = np.zeros(shp)

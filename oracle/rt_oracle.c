@@ -43,6 +43,18 @@
  * the paper's Fig. f:sweep generalised to 3D.  Every upwind vertex then lies
  * earlier in that order, so I- is always known.
  *
+ * Upwind intensity (interp): bilinear on the 2 x 2 upwind face (0), or the
+ * monotone quadratic interpolation section 3.3 names as the alternative (1): on the
+ * 3 x 3 stencil of the upwind plane, each line is interpolated by a quadratic
+ * Bezier curve whose control point comes from the parabola through the three
+ * points and is clamped between the two bracketing values (orc_quad_interp),
+ * along a first and then along b.  Its stencil reaches one vertex past the vertex
+ * on the downwind side, so each ray is then swept plane by plane along the axis
+ * its characteristic crosses first (the section's reordering of the sweep for the
+ * rays that would otherwise be shallow), and in-plane periodic wraps read this
+ * sweep's values.  S and chi stay bilinear, so the coefficients and Lambda* are
+ * those of the first-order form.
+ *
  * Boundaries (section 3.5, and the iteration of section 3 for periodic
  * boundaries): a ghost vertex just outside the grid takes chi and S (and B) from
  * the boundary vertex (periodic axes wrap instead of clamp).  Its intensity is
@@ -78,6 +90,7 @@ typedef struct {
     int32_t want_hk;   /* non-zero: also accumulate H and K */
     double h[3];       /* dx, dy, dz */
     int32_t order;     /* 0: first order (linear), 1: second order (Bezier) */
+    int32_t interp;    /* upwind intensity: 0 bilinear, 1 monotone quadratic (plane order) */
 } orc_grid;
 
 /* Per-ray geometry of the upwind short characteristic (section 3.3). */
@@ -313,6 +326,57 @@ static double vertex_intensity(const orc_ctx *c, const int v[3])
 }
 
 /*
+ * Monotone quadratic interpolation of the upwind intensity (section 3.3 names a
+ * monotonic second-order scheme that neither overshoots nor loses positivity).  On
+ * one line of the upwind plane, f0 is the value in line with the vertex (t = 0), f1
+ * one step upwind (t = 1) and fm one step on the downwind side (t = -1); the point
+ * sits at t in [0, 1].  The parabola through the three points equals the quadratic
+ * Bezier curve on [0, 1] with control point c = f0 + (f1 - fm)/4; c is clamped to
+ * [min(f0, f1), max(f0, f1)], so the result lies between f0 and f1.  Collinear data
+ * give c = (f0 + f1)/2, the linear interpolant.
+ */
+double orc_quad_interp(double fm, double f0, double f1, double t)
+{
+    double c = f0 + 0.25 * (f1 - fm);
+    double lo = f0 < f1 ? f0 : f1;
+    double hi = f0 < f1 ? f1 : f0;
+    if (c < lo) c = lo;
+    if (c > hi) c = hi;
+    double u = 1.0 - t;
+    return (u * u * f0 + 2.0 * t * u * c) + t * t * f1;
+}
+
+/*
+ * Intensity at a point of the 3 x 3 stencil on the upwind plane of vertex vc for the
+ * quadratic scheme: ua, ub = +1 one step upwind along a, b, 0 in line with the vertex,
+ * -1 one step on the downwind side.  The sweep visits whole planes in order along
+ * d, so the upwind plane is complete: a wrap along a periodic in-plane axis reads this
+ * sweep's value.  Outside a non-periodic in-plane face, the upwind side is the face's
+ * incoming boundary intensity and the downwind side (an outgoing face) repeats the
+ * value in line with the vertex.  The plane before the first (along d) follows the
+ * ghost rules of vertex_intensity: previous sweep on a periodic d axis, boundary
+ * intensity otherwise.
+ */
+static double stencil_intensity(const orc_ctx *c, const orc_ray *r, const int vc[3], int ua, int ub)
+{
+    const orc_grid *g = c->g;
+    int v[3];
+    v[r->d] = vc[r->d] - r->sgn[r->d];
+    const int ax[2] = {r->a, r->b};
+    const int off[2] = {ua, ub};
+    for (int k = 0; k < 2; ++k) {
+        const int q = ax[k];
+        v[q] = vc[q] - off[k] * r->sgn[q];
+        if (v[q] >= 0 && v[q] < g->n[q]) continue;
+        if (is_periodic(g, q))
+            v[q] = (v[q] < 0) ? v[q] + g->n[q] : v[q] - g->n[q];
+        else if (off[k] < 0)
+            v[q] = vc[q];
+    }
+    return vertex_intensity(c, v);
+}
+
+/*
  * One formal solution: every ray swept once over every bin.
  *   mu  [na][3] direction cosines, w [na] weights (summing to 1)
  *   chi, B, S  [nf][nz][ny][nx]
@@ -368,12 +432,25 @@ int orc_sweep(const orc_grid *g, const double *mu, const double *w,
             const double wk = w[ray];
             const double mx = m[0], my = m[1], mz = m[2];
 
-            for (int kk = 0; kk < g->n[2]; ++kk) {
-                int k = (r.sgn[2] > 0) ? kk : g->n[2] - 1 - kk;
-                for (int jj = 0; jj < g->n[1]; ++jj) {
-                    int j = (r.sgn[1] > 0) ? jj : g->n[1] - 1 - jj;
-                    for (int ii = 0; ii < g->n[0]; ++ii) {
-                        int i = (r.sgn[0] > 0) ? ii : g->n[0] - 1 - ii;
+            for (int64_t idx = 0; idx < ncell; ++idx) {
+                {
+                    {
+                        /* visiting order: row-major from the upwind corner (x fastest), or,
+                           for the quadratic upwind intensity, plane by plane along d */
+                        int ol[3];
+                        if (g->interp == 1) {
+                            const int64_t per = (int64_t)g->n[r.a] * g->n[r.b];
+                            ol[r.d] = (int)(idx / per);
+                            ol[r.a] = (int)((idx % per) % g->n[r.a]);
+                            ol[r.b] = (int)((idx % per) / g->n[r.a]);
+                        } else {
+                            ol[0] = (int)(idx % g->n[0]);
+                            ol[1] = (int)((idx / g->n[0]) % g->n[1]);
+                            ol[2] = (int)(idx / ((int64_t)g->n[0] * g->n[1]));
+                        }
+                        const int i = (r.sgn[0] > 0) ? ol[0] : g->n[0] - 1 - ol[0];
+                        const int j = (r.sgn[1] > 0) ? ol[1] : g->n[1] - 1 - ol[1];
+                        const int k = (r.sgn[2] > 0) ? ol[2] : g->n[2] - 1 - ol[2];
                         int cpos[3] = {i, j, k};
                         double Iv[4], Sv[4], Cv[4];
                         for (int t = 0; t < 4; ++t) {
@@ -384,7 +461,20 @@ int orc_sweep(const orc_grid *g, const double *mu, const double *w,
                             Iv[t] = vertex_intensity(&c, v);
                             vertex_fields(&c, v, &Cv[t], &Sv[t]);
                         }
-                        double Im = ((wv[0] * Iv[0] + wv[1] * Iv[1]) + wv[2] * Iv[2]) + wv[3] * Iv[3];
+                        double Im;
+                        if (g->interp == 1) {
+                            /* rows at b offsets -1, 0, +1 (downwind side, vertex, upwind
+                               side), each interpolated along a, then along b */
+                            double row[3];
+                            for (int ub = -1; ub <= 1; ++ub) {
+                                double f[3];
+                                for (int ua = -1; ua <= 1; ++ua) f[ua + 1] = stencil_intensity(&c, &r, cpos, ua, ub);
+                                row[ub + 1] = orc_quad_interp(f[0], f[1], f[2], r.fa);
+                            }
+                            Im = orc_quad_interp(row[0], row[1], row[2], r.fb);
+                        } else {
+                            Im = ((wv[0] * Iv[0] + wv[1] * Iv[1]) + wv[2] * Iv[2]) + wv[3] * Iv[3];
+                        }
                         double Sm = ((wv[0] * Sv[0] + wv[1] * Sv[1]) + wv[2] * Sv[2]) + wv[3] * Sv[3];
                         double Cm = ((wv[0] * Cv[0] + wv[1] * Cv[1]) + wv[2] * Cv[2]) + wv[3] * Cv[3];
                         int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
