@@ -82,6 +82,19 @@ typedef enum { RT_SCHED_DEFAULT = 0, RT_SCHED_STAGES = 1, RT_SCHED_PERSISTENT = 
  * slope (S0 - S-)/dtau- is used.  Lambda* (section 3.4) is sum_k w_k beta_k. */
 typedef enum { RT_SC_LINEAR = 0, RT_SC_BEZIER = 1 } rt_sc_order;
 
+/* Interpolation of the upwind intensity I- on the upwind face (section 3.3).
+ * RT_INTERP_BILINEAR: bilinear in the 2 x 2 face vertices (tile wavefront sweep).
+ * RT_INTERP_QUADRATIC: monotone quadratic on the 3 x 3 vertices of the upwind plane
+ * (per line a quadratic Bezier curve whose control point, from the parabola through
+ * the three points, is clamped between the two bracketing values: no overshoot,
+ * positivity kept), along a then b.  Its stencil reaches the downwind side, so each
+ * ray is swept plane by plane along the axis it crosses first; in-plane periodic
+ * wraps read this sweep's values, and outside a non-periodic in-plane face the
+ * downwind side (an outgoing face) repeats the value in line with the vertex.  S and
+ * chi stay bilinear.  Requires order RT_SC_LINEAR; rt_moments, rt_ali_solve_batch and
+ * the server return RT_E_UNSUPPORTED for such problems. */
+typedef enum { RT_INTERP_BILINEAR = 0, RT_INTERP_QUADRATIC = 1 } rt_interp;
+
 typedef struct {
     int32_t nx, ny, nz;       /* grid vertices per axis, each >= 1 */
     int32_t nf;               /* frequency bins, >= 1 */
@@ -100,6 +113,7 @@ typedef struct {
     int32_t tile;             /* tile edge for the sweep (0 = default) */
     int32_t schedule;         /* rt_schedule: how the tile wavefront is executed */
     int32_t order;            /* rt_sc_order: first- or second-order segments */
+    int32_t interp;           /* rt_interp: bilinear or monotone quadratic upwind intensity */
 } rt_problem_desc;
 
 typedef struct rt_problem rt_problem;

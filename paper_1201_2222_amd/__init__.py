@@ -22,6 +22,7 @@ RT_F64, RT_F32 = 0, 1
 RT_BC_VACUUM, RT_BC_THERMAL, RT_BC_PERIODIC, RT_BC_FIXED = 0, 1, 2, 3
 RT_SCHED_DEFAULT, RT_SCHED_STAGES, RT_SCHED_PERSISTENT = 0, 1, 2
 RT_SC_LINEAR, RT_SC_BEZIER = 0, 1
+RT_INTERP_BILINEAR, RT_INTERP_QUADRATIC = 0, 1
 
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
@@ -45,7 +46,7 @@ class ProblemDesc(ctypes.Structure):
                 ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
                 ("I_fixed", ctypes.c_void_p * 6),
                 ("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("interp", ctypes.c_int32)]
 
 
 class AliOpts(ctypes.Structure):
@@ -153,7 +154,8 @@ def rt_quadrature(n_mu: int):
 
 
 def make_desc(shape, nf=1, h=(1.0, 1.0, 1.0), n_mu=4, bc_lo=(2, 2, 1), bc_hi=(2, 2, 0), precision=RT_F64,
-              mu=None, w=None, w_nu=None, I_fixed=None, tile=0, schedule=RT_SCHED_DEFAULT, order=RT_SC_LINEAR):
+              mu=None, w=None, w_nu=None, I_fixed=None, tile=0, schedule=RT_SCHED_DEFAULT, order=RT_SC_LINEAR,
+              interp=RT_INTERP_BILINEAR):
     d = ProblemDesc()
     d.nx, d.ny, d.nz = (int(x) for x in shape)
     d.nf = int(nf)
@@ -182,6 +184,7 @@ def make_desc(shape, nf=1, h=(1.0, 1.0, 1.0), n_mu=4, bc_lo=(2, 2, 1), bc_hi=(2,
     d.tile = int(tile)
     d.schedule = int(schedule)
     d.order = int(order)
+    d.interp = int(interp)
     d._keep = keep
     return d
 

@@ -225,6 +225,8 @@ RayGeo ray_geometry(const double m[3], const double h[3], double wk, int gidx)
     g.w4[1] = fa * (1.0 - fb);
     g.w4[2] = (1.0 - fa) * fb;
     g.w4[3] = fa * fb;
+    g.fa = fa;
+    g.fb = fb;
     g.wk = wk;
     for (int q = 0; q < 3; ++q) g.mu[q] = m[q];
     return g;
@@ -256,7 +258,16 @@ struct rt_problem {
     float *chi32 = nullptr;
     void *face[3]{};                   // Real [nf][na][nt_q][pplane_q]
     double *wrap[3]{};                 // [nf][na][2][plane_q] on periodic axes
-    void *part = nullptr;              // Real [8][nf][cells]
+    void *part = nullptr;              // Real [npart][nf][cells]
+    int npart = 8;                     // partial-sum slots: 8 octants, or kPlaneParts (plane order)
+    // plane-ordered sweep (quadratic upwind intensity)
+    bool plane_order = false;
+    void *planes = nullptr;            // Real [nf][na][2][pmax]
+    double *wrapI = nullptr;           // [nf][na][pmax] (difference form)
+    int64_t pmax = 0;
+    int *d_cls_off = nullptr;          // [kPlaneParts + 1]
+    int *d_cls_rays = nullptr;         // [na]
+    int plane_tiles_a[3]{}, plane_ntiles[3]{};
     int *frozen = nullptr, *parity = nullptr, *iters = nullptr, *flags = nullptr;
     double *resid = nullptr;
     unsigned long long *blockmax = nullptr;  // [nf][kUpdateBlocks]
@@ -311,6 +322,10 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
     if (d->schedule == RT_SCHED_PERSISTENT)
         return fail(RT_E_UNSUPPORTED, "the persistent sweep schedule is disabled in this build");
     if (d->order != RT_SC_LINEAR && d->order != RT_SC_BEZIER) return fail(RT_E_INVALID, "unknown order");
+    if (d->interp != RT_INTERP_BILINEAR && d->interp != RT_INTERP_QUADRATIC)
+        return fail(RT_E_INVALID, "unknown upwind interpolation");
+    if (d->interp == RT_INTERP_QUADRATIC && d->order != RT_SC_LINEAR)
+        return fail(RT_E_UNSUPPORTED, "the quadratic upwind intensity is built with first-order segments only");
     for (int q = 0; q < 3; ++q) {
         for (int k : {d->bc_lo[q], d->bc_hi[q]})
             if (k < RT_BC_VACUUM || k > RT_BC_FIXED) return fail(RT_E_INVALID, "unknown boundary kind on axis %d", q);
@@ -369,11 +384,19 @@ size_t state_bytes(const rt_problem_desc *d, int na)
     size_t b = 0;
     b += (size_t)nc * 8 * 4;                       // chi64, eps, B, lam
     if (d->precision == RT_F32) b += (size_t)nc * 4;  // chi32
-    for (int q = 0; q < 3; ++q) {
-        b += (size_t)d->nf * na * nt[q] * pplane[q] * rs;               // padded face planes
-        if (bc_per[q]) b += (size_t)d->nf * na * 2 * plane[q] * 8;      // periodic memory
+    if (d->interp == RT_INTERP_QUADRATIC) {
+        const int64_t pmax = std::max(plane[0], std::max(plane[1], plane[2]));
+        b += (size_t)d->nf * na * 2 * pmax * rs;   // two planes per ray
+        if (d->precision == RT_F32) b += (size_t)d->nf * na * pmax * 8;   // FP64 last planes
+        b += (size_t)kPlaneParts * nc * rs;        // partials per octant and first-crossed axis
+        b += (size_t)(kPlaneParts + 1 + na) * 4;
+    } else {
+        for (int q = 0; q < 3; ++q) {
+            b += (size_t)d->nf * na * nt[q] * pplane[q] * rs;           // padded face planes
+            if (bc_per[q]) b += (size_t)d->nf * na * 2 * plane[q] * 8;  // periodic memory
+        }
+        b += (size_t)8 * nc * rs;                  // partials
     }
-    b += (size_t)8 * nc * rs;                      // partials
     b += (size_t)d->nf * kUpdateBlocks * 8;        // residual block maxima
     b += (size_t)d->nf * 8 * nt[0] * nt[1] * nt[2] * 4 + 32;  // persistent-sweep flags
     b += (size_t)na * sizeof(RayGeo) + (size_t)nt[0] * nt[1] * nt[2] * 4 + (size_t)d->nf * 32 + 64;
@@ -451,7 +474,7 @@ rt_status collect_timing(rt_problem *p)
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
     p->prof_ms += ms;
-    p->prof_launches += p->persistent ? 1 : p->nstages;
+    p->prof_launches += p->persistent ? 1 : (p->plane_order ? std::max(p->n[0], std::max(p->n[1], p->n[2])) : p->nstages);
     p->prof_updates += p->prof_pending_updates;
     ++p->prof_sweeps;
     p->prof_pending = false;
@@ -472,9 +495,70 @@ struct SweepMode {
 };
 
 template <typename Real>
+PlaneArgs<Real> plane_args(const rt_problem *p, const double *S)
+{
+    PlaneArgs<Real> A;
+    for (int q = 0; q < 3; ++q) {
+        A.n[q] = p->n[q];
+        A.periodic[q] = p->periodic[q];
+        A.bc_lo[q] = p->desc.bc_lo[q];
+        A.bc_hi[q] = p->desc.bc_hi[q];
+        A.tiles_a[q] = p->plane_tiles_a[q];
+        A.ntiles[q] = p->plane_ntiles[q];
+    }
+    A.nf = p->nf;
+    A.na = p->na;
+    A.cells = p->cells;
+    A.rays = p->d_rays;
+    A.cls_off = p->d_cls_off;
+    A.cls_rays = p->d_cls_rays;
+    if constexpr (sizeof(Real) == 4)
+        A.chi = p->chi32;
+    else
+        A.chi = p->chi64;
+    A.S = S;
+    A.B = p->B;
+    for (int k = 0; k < 6; ++k) A.fixed[k] = p->desc.I_fixed[k];
+    A.planes = static_cast<Real *>(p->planes);
+    A.pmax = p->pmax;
+    A.wrapI = p->wrapI;
+    A.part = static_cast<Real *>(p->part);
+    A.f0 = 0;
+    A.nfc = p->nf;
+    A.frozen = p->frozen;
+    A.parity = p->parity;
+    return A;
+}
+
+// One formal solution in plane order (quadratic upwind intensity): step t of every
+// ray is one launch, t = 0 .. max(nx, ny, nz) - 1.
+template <typename Real>
+rt_status run_plane_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed, int active_bins)
+{
+    const PlaneArgs<Real> A = plane_args<Real>(p, S);
+    if (p->cold) {
+        HIP_TRY(launch_plane_cold<Real>(A, st));
+        p->cold = false;
+    }
+    timed = timed && p->prof && !p->prof_pending;
+    const int steps = std::max(p->n[0], std::max(p->n[1], p->n[2]));
+    for (int t = 0; t < steps; ++t) {
+        if (timed && t == 0) HIP_TRY(hipEventRecord(p->ev[0], st));
+        HIP_TRY(launch_plane_step<Real>(A, t, st));
+        if (timed && t == steps - 1) HIP_TRY(hipEventRecord(p->ev[1], st));
+    }
+    if (timed) {
+        p->prof_pending = true;
+        p->prof_pending_updates = (double)p->cells * p->na * active_bins;
+    }
+    return RT_OK;
+}
+
+template <typename Real>
 rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed = false, int active_bins = 0,
                     SweepMode mode = SweepMode())
 {
+    if (p->plane_order) return run_plane_sweep<Real>(p, S, st, timed, active_bins);
     SweepArgs<Real> A = sweep_args<Real>(p, S);
     if (mode.nfc > 0) {
         A.f0 = mode.f0;
@@ -1006,15 +1090,32 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     ALLOC(p->B, (size_t)nc);
     ALLOC(p->lam, (size_t)nc);
     if (p->f32) ALLOC(p->chi32, (size_t)nc);
-    for (int q = 0; q < 3; ++q) {
-        unsigned char *fb;
-        ALLOC(fb, (size_t)p->nf * na * p->nt[q] * p->pplane[q] * rs);
-        p->face[q] = fb;
-        if (p->periodic[q]) ALLOC(p->wrap[q], (size_t)p->nf * na * 2 * p->plane[q]);
+    p->plane_order = desc->interp == RT_INTERP_QUADRATIC;
+    p->npart = p->plane_order ? kPlaneParts : 8;
+    if (p->plane_order) {
+        p->pmax = std::max(p->plane[0], std::max(p->plane[1], p->plane[2]));
+        unsigned char *pl;
+        ALLOC(pl, (size_t)p->nf * na * 2 * p->pmax * rs);
+        p->planes = pl;
+        if (p->f32) ALLOC(p->wrapI, (size_t)p->nf * na * p->pmax);
+        ALLOC(p->d_cls_off, (size_t)kPlaneParts + 1);
+        ALLOC(p->d_cls_rays, (size_t)na);
+        for (int q = 0; q < 3; ++q) {
+            const int a = q == 0 ? 1 : 0, b = q == 2 ? 1 : 2;
+            p->plane_tiles_a[q] = (p->n[a] + kPlaneTile - 1) / kPlaneTile;
+            p->plane_ntiles[q] = p->plane_tiles_a[q] * ((p->n[b] + kPlaneTile - 1) / kPlaneTile);
+        }
+    } else {
+        for (int q = 0; q < 3; ++q) {
+            unsigned char *fb;
+            ALLOC(fb, (size_t)p->nf * na * p->nt[q] * p->pplane[q] * rs);
+            p->face[q] = fb;
+            if (p->periodic[q]) ALLOC(p->wrap[q], (size_t)p->nf * na * 2 * p->plane[q]);
+        }
     }
     {
         unsigned char *pb;
-        ALLOC(pb, (size_t)8 * nc * rs);
+        ALLOC(pb, (size_t)p->npart * nc * rs);
         p->part = pb;
     }
     ALLOC(p->frozen, (size_t)p->nf);
@@ -1064,6 +1165,19 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     if (e == hipSuccess) e = hipMemset(p->parity, 0, sizeof(int) * p->nf);
     if (e == hipSuccess) e = hipMemset(p->flags, 0, sizeof(int) * 4);
     if (e == hipSuccess) e = hipMemset(p->dag_done, 0, sizeof(int) * (size_t)p->nf * 8 * p->ntiles);
+    if (e == hipSuccess && p->plane_order) {
+        // classes (octant, first-crossed axis); a class without rays keeps zero partials
+        std::vector<int> off(kPlaneParts + 1, 0), list;
+        for (int c = 0; c < kPlaneParts; ++c) {
+            off[c] = (int)list.size();
+            for (int k = 0; k < na; ++k)
+                if (p->rays[k].oct * 3 + p->rays[k].d == c) list.push_back(k);
+        }
+        off[kPlaneParts] = (int)list.size();
+        e = hipMemcpy(p->d_cls_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->d_cls_rays, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(p->part, 0, (size_t)p->npart * nc * rs);
+    }
     if (e != hipSuccess) {
         rt_problem_destroy(p);
         return fail(RT_E_HIP, "problem initialisation failed: %s", hipGetErrorString(e));
@@ -1111,9 +1225,11 @@ rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lam
     s = sweep_current_S(p, S, st, true, p->nf);
     if (s != RT_OK) return s;
     if (p->f32)
-        HIP_TRY(launch_partial_sum<float>(static_cast<float *>(p->part), S, 1, p->nf, p->cells, nullptr, J, st));
+        HIP_TRY(launch_partial_sum<float>(static_cast<float *>(p->part), p->npart, S, 1, p->nf, p->cells, nullptr, J,
+                                          st));
     else
-        HIP_TRY(launch_partial_sum<double>(static_cast<double *>(p->part), S, 0, p->nf, p->cells, nullptr, J, st));
+        HIP_TRY(launch_partial_sum<double>(static_cast<double *>(p->part), p->npart, S, 0, p->nf, p->cells, nullptr,
+                                           J, st));
     HIP_TRY(launch_flip_parity(p->parity, p->frozen, 0, p->nf, st));
     if (lambda_star) HIP_TRY(hipMemcpyAsync(lambda_star, p->lam, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     return RT_OK;
@@ -1158,11 +1274,11 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
             rt_status s = sweep_current_S(p, S_inout, st, j == 0, active);
             if (s != RT_OK) return s;
             if (p->f32)
-                HIP_TRY(launch_ali_update<float>(static_cast<float *>(p->part), 1, p->nf, p->cells, p->B, p->eps, p->lam,
-                                                 S_inout, J_out, ctl, st));
+                HIP_TRY(launch_ali_update<float>(static_cast<float *>(p->part), p->npart, 1, p->nf, p->cells, p->B,
+                                                 p->eps, p->lam, S_inout, J_out, ctl, st));
             else
-                HIP_TRY(launch_ali_update<double>(static_cast<double *>(p->part), 0, p->nf, p->cells, p->B, p->eps,
-                                                  p->lam, S_inout, J_out, ctl, st));
+                HIP_TRY(launch_ali_update<double>(static_cast<double *>(p->part), p->npart, 0, p->nf, p->cells, p->B,
+                                                  p->eps, p->lam, S_inout, J_out, ctl, st));
             HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
         }
         it += k;
@@ -1248,6 +1364,7 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
     if (!S || !out) return fail(RT_E_INVALID, "S and out are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    if (p->plane_order) return fail(RT_E_UNSUPPORTED, "moments are not built for the quadratic upwind intensity");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool want_int = out->J_int || out->H_int || out->K_int || out->f_int || out->Q_int || out->heating;
     if (!(out->J || out->H || out->K || want_int)) return RT_OK;
@@ -1348,6 +1465,8 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
         if (!p) return fail(RT_E_INVALID, "problem %d is NULL", i);
         if (!S_inout[i] || !J_out[i]) return fail(RT_E_INVALID, "S_inout/J_out of problem %d missing", i);
         if (!p->have_fields) return fail(RT_E_INVALID, "problem %d: rt_problem_set_fields has not been called", i);
+        if (p->plane_order)
+            return fail(RT_E_UNSUPPORTED, "problem %d: batches are not built for the quadratic upwind intensity", i);
         for (int j = 0; j < i; ++j)
             if (problems[j] == p) return fail(RT_E_INVALID, "problem %d appears twice in the batch", i);
     }
@@ -1538,6 +1657,7 @@ rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opt
     if (!srv || !p || !opts || !S_inout || !J_out || !ticket)
         return fail(RT_E_INVALID, "server, problem, opts, S_inout, J_out and ticket are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    if (p->plane_order) return fail(RT_E_UNSUPPORTED, "the server is not built for the quadratic upwind intensity");
     {
         rt_status so = check_ali_opts(opts);
         if (so != RT_OK) return so;

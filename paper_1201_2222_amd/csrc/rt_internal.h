@@ -22,6 +22,7 @@ struct RayGeo {
     double w4[4];     // bilinear weights at upwind offsets (0,0) (1,0) (0,1) (1,1) along (a, b)
     double wk;        // quadrature weight
     double mu[3];     // direction cosines
+    double fa, fb;    // fractional offsets of the upwind face point along a and b
 };
 
 // Everything a sweep kernel reads about the problem; passed by value.
@@ -56,6 +57,41 @@ struct SweepArgs {
     const int *stage_tab;     // [nstages + 1] offsets of the stages in tiles (batched launches)
     int nstages;
     int order;                // 0: first-order segments, 1: second order (Bezier source)
+};
+
+// One step of the plane-ordered sweep (monotone quadratic upwind intensity): every
+// ray advances one plane along the axis its short characteristic crosses first.
+// Rays are grouped in classes c = octant * 3 + d; a class's partial sums go to their
+// own slot, so every vertex of a slot is written once per sweep.
+constexpr int kPlaneTile = 16;     // in-plane tile edge of a plane-step workgroup
+constexpr int kPlaneParts = 24;    // partial-sum slots: 8 octants x 3 first-crossed axes
+
+template <typename Real>
+struct PlaneArgs {
+    int n[3];
+    int nf, na;
+    int periodic[3];
+    int bc_lo[3], bc_hi[3];
+    int64_t cells;
+    const RayGeo *rays;       // [na]
+    const int *cls_off;       // [25]: class c holds cls_rays[cls_off[c] .. cls_off[c + 1])
+    const int *cls_rays;      // [na], ascending within a class
+    const Real *chi;          // [nf][cells]
+    const double *S;          // [nf][cells]
+    const double *B;          // [nf][cells]
+    const double *fixed[6];   // FIXED faces (real coordinates), or null
+    Real *planes;             // [nf][na][2][pmax]: two planes per ray (I, or D = I - S in the
+                              // difference form), indexed by the flipped in-plane coordinates
+                              // (a fastest); plane t is written to slot (t + parity n_d) & 1
+    int64_t pmax;
+    double *wrapI;            // [nf][na][pmax] difference form: I on each ray's last plane
+                              // (the next sweep's ghost plane on a periodic d axis), or null
+    Real *part;               // [24][nfc][cells]
+    int f0, nfc;
+    const int *frozen;        // [nf]
+    const int *parity;        // [nf]: sweeps run so far, modulo 2
+    int tiles_a[3];           // per first-crossed axis d: in-plane tiles along a
+    int ntiles[3];            // per d: in-plane tiles
 };
 
 // Dependency state of the persistent sweep: one completion flag per (bin, octant,
@@ -135,14 +171,22 @@ template <typename Real>
 hipError_t launch_ali_update_batch(const BatchUpdate *bu, int nprob, int nblk, int max_nf, hipStream_t st);
 hipError_t launch_ali_finalize_batch(const BatchUpdate *bu, int nprob, int *done, hipStream_t st);
 
+// npart: partial-sum slots summed per vertex (8 octants, or kPlaneParts)
 template <typename Real>
-hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,
+hipError_t launch_partial_sum(const Real *part, int npart, const double *S, int dform, int nf, int64_t cells,
                               const int *frozen, double *J, hipStream_t st);
 
 template <typename Real>
-hipError_t launch_ali_update(const Real *part, int dform, int nf, int64_t cells, const double *B,
+hipError_t launch_ali_update(const Real *part, int npart, int dform, int nf, int64_t cells, const double *B,
                              const double *eps, const double *lam, double *S64, double *J,
                              AliCtl ctl, hipStream_t st);
+
+// Plane-ordered sweep (rt_plane.hip): one step t of every active bin's rays, and the
+// cold periodic memory (the slot read at t = 0 holds S of the wrapped vertex).
+template <typename Real>
+hipError_t launch_plane_step(const PlaneArgs<Real> &A, int t, hipStream_t st);
+template <typename Real>
+hipError_t launch_plane_cold(const PlaneArgs<Real> &A, hipStream_t st);
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,
                                hipStream_t st);

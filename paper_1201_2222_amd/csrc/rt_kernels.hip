@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rt_internal.h"
+#include "rt_device.h"
 
 namespace rtsc {
 
@@ -73,69 +74,6 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// value of a per-axis quantity for a wave-uniform axis index
-template <typename V>
-__device__ __forceinline__ V sel3(int q, V x, V y, V z) { return q == 0 ? x : (q == 1 ? y : z); }
-
-__device__ __forceinline__ int to_real(int g, int sg, int n) { return sg > 0 ? g : n - 1 - g; }
-
-// One-step-outside index brought back in: wrap on periodic axes, clamp otherwise
-// (selects, no branch).
-__device__ __forceinline__ int fold(int x, int n, int periodic)
-{
-    const int lo = periodic ? x + n : 0, hi = periodic ? x - n : n - 1;
-    return x < 0 ? lo : (x >= n ? hi : x);
-}
-
-// ---- segment integration -------------------------------------------------------
-// FP64, plain form  I0 = I- E + psim S- + psi0 S0  with a source linear in tau:
-// E = e^-dt, psi0 = 1 - (1 - e^-dt)/dt, psim = (1 - e^-dt) - psi0.  Below dt = 0.1
-// psi0 comes from its Taylor series (Horner form) to avoid cancellation.
-__device__ __forceinline__ void seg_coeffs(double dt, double &E, double &psim, double &psi0)
-{
-    const double e0 = -expm1(-dt);
-    double p0;
-    if (dt < 0.1) {
-        // psi0 = dt/2! - dt^2/3! + dt^3/4! - ... (13 terms)
-        const double c[13] = {1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0,
-                              1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0,
-                              1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0,
-                              1.0 / 87178291200.0};
-        double acc = c[12];
-#pragma unroll
-        for (int i = 11; i >= 0; --i) acc = c[i] - dt * acc;
-        p0 = dt * acc;
-    } else {
-        p0 = 1.0 - e0 / dt;
-    }
-    E = exp(-dt);
-    psi0 = p0;
-    psim = e0 - p0;
-}
-
-// FP32, difference form  D0 = D- E + (S- - S0) g  with g = (1 - e^-dt)/dt = 1 - psi0,
-// which is the plain form rewritten with D = I - S (E + psim + psi0 = 1).  g comes
-// from its Taylor series sum_n (-dt)^n/(n+1)! below dt = 0.5 (10 terms).
-__device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
-{
-    // both forms are evaluated and one is selected: no branch in the sweep step
-    E = __expf(-dt);
-    // Horner steps as (-dt) acc + c: one instruction with the constant inline
-    const float m = -dt;
-    float acc = 1.0f / 3628800.0f;                    // 1/10!
-    acc = fmaf(m, acc, 1.0f / 362880.0f);             // 1/9!
-    acc = fmaf(m, acc, 1.0f / 40320.0f);
-    acc = fmaf(m, acc, 1.0f / 5040.0f);
-    acc = fmaf(m, acc, 1.0f / 720.0f);
-    acc = fmaf(m, acc, 1.0f / 120.0f);
-    acc = fmaf(m, acc, 1.0f / 24.0f);
-    acc = fmaf(m, acc, 1.0f / 6.0f);
-    acc = fmaf(m, acc, 0.5f);
-    const float gs = fmaf(m, acc, 1.0f);
-    const float gc = (1.0f - E) * __builtin_amdgcn_rcpf(dt);
-    g = dt < 0.5f ? gs : gc;
 }
 
 // ---- second-order segment (section 3.3, eq. rtdisc with Bezier source) -------------
@@ -1064,7 +1002,7 @@ __global__ void ghost_fill_batch_kernel(const SweepArgs<Real> *args)
     for (int f = 0; f < A.nf; ++f) ghost_fill_one<Real, DFORM>(A, blockIdx.y, f, e);
 }
 
-template <typename Real>
+template <typename Real, int NP>
 __global__ void partial_sum_kernel(const Real *part, const double *S, int dform, int nf, int64_t cells,
                                    const int *frozen, double *J)
 {
@@ -1075,7 +1013,7 @@ __global__ void partial_sum_kernel(const Real *part, const double *S, int dform,
     const int64_t stride = (int64_t)nf * cells;
     double acc = 0.0;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) acc += (double)part[o * stride + i];
+    for (int o = 0; o < NP; ++o) acc += (double)part[o * stride + i];
     J[i] = dform ? S[i] + acc : acc;
 }
 
@@ -1091,8 +1029,9 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 
 // Jacobi update (eq. dsjacobi) and the per-bin residual max |dS|/S^{n+1} (eq. conv),
 // both in FP64.  With dform the partials hold sum w (I - S), so J - S is summed
-// without cancellation.  Each block writes its max to blockmax (no atomics).
-template <typename Real>
+// without cancellation.  Each block writes its max to blockmax (no atomics).  NP
+// partial-sum slots (8 octants, or octant x first-crossed axis) are summed in order.
+template <typename Real, int NP = 8>
 __device__ __forceinline__ void ali_update_body(const Real *part, int dform, int nf, int64_t cells, const double *B,
                                                 const double *eps, const double *lam, double *S64, double *Jout,
                                                 const AliCtl &ctl, int f)
@@ -1105,7 +1044,7 @@ __device__ __forceinline__ void ali_update_body(const Real *part, int dform, int
         const int64_t i = (int64_t)f * cells + c;
         double sum = 0.0;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) sum += (double)part[o * stride + i];
+        for (int o = 0; o < NP; ++o) sum += (double)part[o * stride + i];
         const double S = S64[i], e = eps[i];
         double num;
         if (dform) {
@@ -1132,12 +1071,12 @@ __device__ __forceinline__ void ali_update_body(const Real *part, int dform, int
     }
 }
 
-template <typename Real>
+template <typename Real, int NP>
 __global__ void __launch_bounds__(256) ali_update_kernel(const Real *part, int dform, int nf, int64_t cells,
                                                          const double *B, const double *eps,
                                                          const double *lam, double *S64, double *Jout, AliCtl ctl)
 {
-    ali_update_body<Real>(part, dform, nf, cells, B, eps, lam, S64, Jout, ctl, blockIdx.y);
+    ali_update_body<Real, NP>(part, dform, nf, cells, B, eps, lam, S64, Jout, ctl, blockIdx.y);
 }
 
 // Batched form: blockIdx.z is the problem, blockIdx.y the bin, x the ctl.nblk blocks.
@@ -1547,31 +1486,40 @@ hipError_t launch_ali_finalize_batch(const BatchUpdate *bu, int nprob, int *done
 }
 
 template <typename Real>
-hipError_t launch_partial_sum(const Real *part, const double *S, int dform, int nf, int64_t cells,
+hipError_t launch_partial_sum(const Real *part, int npart, const double *S, int dform, int nf, int64_t cells,
                               const int *frozen, double *J, hipStream_t st)
 {
-    hipLaunchKernelGGL(partial_sum_kernel<Real>, dim3(blocks_for(cells * nf, 256)), dim3(256), 0, st, part, S,
-                       dform, nf, cells, frozen, J);
+    if (npart == kPlaneParts)
+        hipLaunchKernelGGL((partial_sum_kernel<Real, kPlaneParts>), dim3(blocks_for(cells * nf, 256)), dim3(256), 0,
+                           st, part, S, dform, nf, cells, frozen, J);
+    else
+        hipLaunchKernelGGL((partial_sum_kernel<Real, 8>), dim3(blocks_for(cells * nf, 256)), dim3(256), 0, st, part,
+                           S, dform, nf, cells, frozen, J);
     return hipGetLastError();
 }
-template hipError_t launch_partial_sum<double>(const double *, const double *, int, int, int64_t, const int *,
+template hipError_t launch_partial_sum<double>(const double *, int, const double *, int, int, int64_t, const int *,
                                                double *, hipStream_t);
-template hipError_t launch_partial_sum<float>(const float *, const double *, int, int, int64_t, const int *,
+template hipError_t launch_partial_sum<float>(const float *, int, const double *, int, int, int64_t, const int *,
                                               double *, hipStream_t);
 
 template <typename Real>
-hipError_t launch_ali_update(const Real *part, int dform, int nf, int64_t cells, const double *B,
+hipError_t launch_ali_update(const Real *part, int npart, int dform, int nf, int64_t cells, const double *B,
                              const double *eps, const double *lam, double *S64, double *J,
                              AliCtl ctl, hipStream_t st)
 {
     dim3 grid((unsigned)ctl.nblk, (unsigned)nf);
-    hipLaunchKernelGGL(ali_update_kernel<Real>, grid, dim3(256), 0, st, part, dform, nf, cells, B, eps, lam, S64,
-                       J, ctl);
+    if (npart == kPlaneParts)
+        hipLaunchKernelGGL((ali_update_kernel<Real, kPlaneParts>), grid, dim3(256), 0, st, part, dform, nf, cells, B,
+                           eps, lam, S64, J, ctl);
+    else
+        hipLaunchKernelGGL((ali_update_kernel<Real, 8>), grid, dim3(256), 0, st, part, dform, nf, cells, B, eps, lam,
+                           S64, J, ctl);
     return hipGetLastError();
 }
-template hipError_t launch_ali_update<double>(const double *, int, int, int64_t, const double *, const double *,
-                                              const double *, double *, double *, AliCtl, hipStream_t);
-template hipError_t launch_ali_update<float>(const float *, int, int, int64_t, const double *, const double *,
+template hipError_t launch_ali_update<double>(const double *, int, int, int, int64_t, const double *,
+                                              const double *, const double *, double *, double *, AliCtl,
+                                              hipStream_t);
+template hipError_t launch_ali_update<float>(const float *, int, int, int, int64_t, const double *, const double *,
                                              const double *, double *, double *, AliCtl, hipStream_t);
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,

@@ -70,6 +70,7 @@ def test_invalid_arguments_are_rejected(rt):
         dict(shape=(4, 4, 4), precision=7),
         dict(shape=(4, 4, 4), bc_lo=(9, 2, 1), bc_hi=(9, 2, 0)),
         dict(shape=(4, 4, 4), order=2),
+        dict(shape=(4, 4, 4), interp=2),
     ]
     for kw in cases:
         d = rt.make_desc(**kw)
@@ -87,6 +88,15 @@ def test_invalid_arguments_are_rejected(rt):
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_OK
     assert lib.rt_quadrature(3, None, None, None) == rt.RT_E_INVALID
     assert rt.load().rt_status_string(rt.RT_E_NONFINITE) == b"non-finite residual"
+
+
+def test_quadratic_upwind_intensity_needs_first_order(rt):
+    lib = rt.load()
+    b = ctypes.c_size_t()
+    d = rt.make_desc((8, 8, 8), interp=rt.RT_INTERP_QUADRATIC)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_OK
+    d = rt.make_desc((8, 8, 8), interp=rt.RT_INTERP_QUADRATIC, order=rt.RT_SC_BEZIER)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_UNSUPPORTED
 
 
 def test_state_bytes_scale(rt):
