@@ -39,11 +39,19 @@ OPS_PER_UPDATE_F32 = 12 + 2 + 5 + 6 + 3 + 1
 # the control point (t = h1/h2 by reciprocal 5, a - b t^2 2, / 2(1 + t) by reciprocal
 # 6, clamp between a and 0 4: 17), D update (3), accumulation (1).
 OPS_PER_UPDATE_BEZ_F32 = 20 + 4 + 5 + 15 + 4 + 17 + 3 + 1
+# Monotone quadratic upwind intensity, FP32 difference form: I = D + S at the 3 x 3
+# stencil (9, FP64), four 1D quadratic Bezier interpolations with the clamped
+# control point (9 each: 36), I- - S- and its conversion (2), S- (FP64) and chi-
+# bilinear (8), dtau (2), exp (5), g (6), D update (3), accumulation (1).
+OPS_PER_UPDATE_QUAD_F32 = 9 + 36 + 2 + 8 + 2 + 5 + 6 + 3 + 1
 
 
 TRAFFIC_PROFILE = {"linear": os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md"),
-                   "bezier": os.path.join(ROOT, "profiles", "sweep_stage_f32_bezier_scattering128_traffic.md")}
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip")
+                   "bezier": os.path.join(ROOT, "profiles", "sweep_stage_f32_bezier_scattering128_traffic.md"),
+                   "quadratic": os.path.join(ROOT, "profiles", "plane_step_f32_quadratic_scattering128_traffic.md")}
+KERNEL_SOURCE = {"linear": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
+                 "bezier": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
+                 "quadratic": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_plane.hip")}
 
 
 def measured_traffic(order="linear"):
@@ -55,7 +63,7 @@ def measured_traffic(order="linear"):
         text = open(TRAFFIC_PROFILE[order]).read()
         fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
                                                                                    "kernel_source_sha256:")))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = hashlib.sha256(open(KERNEL_SOURCE[order], "rb").read()).hexdigest()
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha:
@@ -68,13 +76,14 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q))
 
 
-def cpu_baseline(wl, sweeps, order=0):
+def cpu_baseline(wl, sweeps, order=0, interp=0):
     """FP64 oracle (single thread, as it stands) timed on a bounded number of formal
     solutions of the same workload."""
     import numpy as np
     import oracle
     oracle.build(force=False)
-    op = oracle.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, order=order)
+    op = oracle.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, order=order,
+                        interp=interp)
     S = wl.B.copy()
     t0 = time.perf_counter()
     for _ in range(sweeps):
@@ -83,7 +92,7 @@ def cpu_baseline(wl, sweeps, order=0):
     updates = wl.cells * wl.na * wl.nf * sweeps
     return {"value": updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{sweeps} formal solutions (sweeps) of the {wl.shape[0]}^3 x {wl.na}-ray workload"
-                      f"{' (second order)' if order else ''}, "
+                      f"{' (second order)' if order else ''}{' (quadratic upwind intensity)' if interp else ''}, "
                       f"{updates / 1e6:.1f} M updates in {dt:.1f} s, FP64, one thread"}
 
 
@@ -320,6 +329,9 @@ def main():
     ap.add_argument("--schedule", choices=["stages"], default="stages")
     ap.add_argument("--order", choices=["linear", "bezier"], default="linear",
                     help="scattering: first-order or second-order (Bezier) short characteristics")
+    ap.add_argument("--interp", choices=["bilinear", "quadratic"], default="bilinear",
+                    help="scattering: upwind intensity bilinear (tile wavefront) or monotone quadratic "
+                         "(plane-ordered sweep; no moments epilogue)")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="profiling mode: run exactly this many ALI iterations per step instead of converging")
     ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
@@ -378,9 +390,15 @@ def main():
            for k, m in (("J_int", 1), ("H_int", 3), ("K_int", 6), ("f_int", 6), ("Q_int", 1))}
     sched = rt.RT_SCHED_STAGES
     order = rt.RT_SC_BEZIER if args.order == "bezier" else rt.RT_SC_LINEAR
-    ops_per_update = OPS_PER_UPDATE_BEZ_F32 if order else OPS_PER_UPDATE_F32
+    quad = args.interp == "quadratic"
+    if quad and order:
+        print("--interp quadratic is built with first-order segments only", file=sys.stderr)
+        sys.exit(2)
+    interp = rt.RT_INTERP_QUADRATIC if quad else rt.RT_INTERP_BILINEAR
+    kind = "quadratic" if quad else args.order
+    ops_per_update = OPS_PER_UPDATE_QUAD_F32 if quad else (OPS_PER_UPDATE_BEZ_F32 if order else OPS_PER_UPDATE_F32)
     prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
-                      schedule=sched, order=order)
+                      schedule=sched, order=order, interp=interp)
 
     def step():
         prob.reset_periodic()
@@ -389,7 +407,8 @@ def main():
                                     fixed_iters=args.fixed_iters)
         if status != rt.RT_OK:
             raise RuntimeError(f"ALI did not converge: {st}")
-        st["heating"] = prob.moments(S, want_heating=True, **mom)   # moments epilogue on the converged S
+        # moments epilogue on the converged S (not built for the plane-ordered sweep)
+        st["heating"] = None if quad else prob.moments(S, want_heating=True, **mom)
         return st
 
     for _ in range(args.warmup):
@@ -413,14 +432,14 @@ def main():
     J32 = J.cpu().numpy()
 
     # one sweep per ALI iteration plus the moments sweep
-    updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + len(iters)))
+    updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + (0 if quad else len(iters))))
     value = updates / total
     kernel_s = prof["kernel_ms"] / 1e3
     achieved = prof["updates"] * ops_per_update / kernel_s / 1e12 if kernel_s > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(args.order),
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(kind),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": f"sweep_stage_kernel<float, true, 1, false, {order}>",
+                "kernel": "plane_step_kernel<float, true>" if quad else f"sweep_stage_kernel<float, true, 1, false, {order}>",
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
                 "ops_per_update": ops_per_update}
@@ -428,7 +447,7 @@ def main():
     extra = {}
     if not args.no_f64:
         p64 = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F64,
-                         schedule=sched, order=order)
+                         schedule=sched, order=order, interp=interp)
         p64.set_fields(chi, eps, B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -450,8 +469,9 @@ def main():
         "config": {"workload": f"scattering {wl.shape[0]}^3, 1 bin, {wl.na} rays, eps=1e-3, "
                                f"vertical tau 1e4, Jacobi ALI from S=B to max|dS/S|<=1e-6, "
                                f"FP32 sweeps + FP64 updates"
-                               f"{', second-order (Bezier) segments' if order else ''}",
-                   "grid": list(wl.shape), "rays": wl.na, "order": args.order,
+                               f"{', second-order (Bezier) segments' if order else ''}"
+                               f"{', monotone quadratic upwind intensity (plane order), no moments epilogue' if quad else ''}",
+                   "grid": list(wl.shape), "rays": wl.na, "order": args.order, "interp": args.interp,
                    "schedule": args.schedule,
                    "bins": wl.nf},
         "ali_solves_per_s": args.steps / total,
@@ -463,7 +483,7 @@ def main():
     }
     out.update(extra)
     if args.cpu_sweeps > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps, order)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps, order, 1 if quad else 0)
     prob.close()
     print(json.dumps(out), flush=True)
 
