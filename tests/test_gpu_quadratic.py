@@ -177,6 +177,28 @@ def test_quadratic_ali_converged_parity(env, oracle_mod, precision):
     gp.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_quadratic_workload_scattering_full_size(env, oracle_mod, precision):
+    """The 128^3 scattering workload at full size with the quadratic upwind intensity,
+    in the launch configuration the benchmark times: two Jacobi iterations from S = B."""
+    rt, torch = env
+    wl = W.scattering()
+    prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
+    op, gp = _pair(env, oracle_mod, wl, prec)
+    if "full" not in _REF:   # the oracle's two sweeps (~25 s) serve both precisions
+        _REF["full"] = op.ali(fixed_iters=2)
+    ref = _REF["full"]
+    n = wl.chi.size
+    S = torch.empty(n, dtype=torch.float64, device="cuda")
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    gp.ali_solve(S, J, fixed_iters=2)
+    torch.cuda.synchronize()
+    tol = TOL64 if precision == "f64" else TOL32
+    assert _rel(J.cpu().numpy().reshape(ref["J"].shape), ref["J"]) <= tol
+    assert _rel(S.cpu().numpy().reshape(ref["S"].shape), ref["S"]) <= tol
+    gp.close()
+
+
 def test_quadratic_unsupported_entry_points(env):
     """Moments, batches and the server refuse plane-ordered problems before any work."""
     rt, torch = env
