@@ -11,7 +11,8 @@
 // then per ray the window of the ray's upwind-plane intensities, and writes the ray's
 // new plane and the class's partial sum of w I (or w D).  Every vertex lies in
 // exactly one plane along d, so each class slot of the partial sums is written once
-// per sweep: no atomics, and the sum over the slots runs in a fixed order.
+// per sweep: no atomics, and the sum over the slots runs in a fixed order.  Up to
+// RMAX rays of a class are staged together, so their window loads go out at once.
 //
 // Ghost rules (the oracle's): along an in-plane periodic axis the window wraps to
 // this sweep's upwind plane; outside a non-periodic in-plane face the upwind side
@@ -40,6 +41,7 @@ namespace {
 constexpr int PT = kPlaneTile;
 constexpr int PW = PT + 2;            // window edge: one vertex on each side of the tile
 constexpr int PWIN = PW * PW;
+constexpr int RMAX = 4;               // rays of a class staged together
 
 // Monotone quadratic interpolation between f0 (t = 0) and f1 (t = 1) with the third
 // point fm at t = -1: the parabola through the three points as a quadratic Bezier
@@ -138,7 +140,7 @@ __global__ void __launch_bounds__(PT *PT) plane_step_kernel(PlaneArgs<Real> A, i
 
     __shared__ double sS[PWIN];      // S of the upwind window (folded vertices)
     __shared__ Real sC[PWIN];        // chi of the upwind window
-    __shared__ Real sV[PWIN];        // this ray's upwind-plane values (I, or D)
+    __shared__ Real sV[RMAX * PWIN]; // the rays' upwind-plane values (I, or D), one window each
     __shared__ int sSrc[PWIN];       // plane index (>= 0), or -1 - cell of a boundary ghost
     __shared__ int sFace[PWIN], sFidx[PWIN];
 
@@ -172,42 +174,55 @@ __global__ void __launch_bounds__(PT *PT) plane_step_kernel(PlaneArgs<Real> A, i
     const bool keep_i = DFORM && t == nd - 1 && sel3(d, A.periodic[0], A.periodic[1], A.periodic[2]);
     Real acc = Real(0);
     const int lx = tid % PT + 1, ly = tid / PT + 1;   // the vertex's column in the window
-    for (int ri = r0; ri < r1; ++ri) {
-        const int ray = A.cls_rays[ri];
-        const RayGeo *G = A.rays + ray;
-        const int64_t rbase = ((int64_t)f * A.na + ray) * 2 * A.pmax;
-        const Real *rd_plane = A.planes + rbase + (int64_t)(wsel ^ 1) * A.pmax;
-        Real *wr_plane = A.planes + rbase + (int64_t)wsel * A.pmax;
-        double *wrap_i = DFORM ? A.wrapI + ((int64_t)f * A.na + ray) * A.pmax : nullptr;
-        __syncthreads();   // window values of the previous ray are no longer read
+    // up to RMAX rays of the class per pass: all their window loads go out together
+    for (int rp = r0; rp < r1; rp += RMAX) {
+        const int nr = min(RMAX, r1 - rp);
+        int rays[RMAX];
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) rays[k] = A.cls_rays[rp + min(k, nr - 1)];
+        __syncthreads();   // the previous pass's windows are no longer read
         for (int e = tid; e < PWIN; e += PT * PT) {
             const int src = sSrc[e];
-            Real v;
+            Real v[RMAX];
             if (src >= 0) {
                 // t = 0 reads the previous sweep's last plane (periodic d)
-                v = (DFORM && t == 0) ? Real(wrap_i[src] - sS[e]) : rd_plane[src];
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) {
+                    const int64_t rb = (int64_t)f * A.na + rays[k];
+                    v[k] = (DFORM && t == 0) ? Real(A.wrapI[rb * A.pmax + src] - sS[e])
+                                             : A.planes[(rb * 2 + (wsel ^ 1)) * A.pmax + src];
+                }
             } else {
                 const int face = sFace[e];
                 const int kind = (face & 1) ? A.bc_hi[face >> 1] : A.bc_lo[face >> 1];
-                double I = 0.0;
-                if (kind == BC_THERMAL) {
-                    I = Bf[-1 - src];
-                } else if (kind == BC_FIXED) {
-                    const int q = face >> 1;
-                    const int64_t ps = q == 0 ? (int64_t)A.n[1] * A.n[2]
-                                              : (q == 1 ? (int64_t)A.n[0] * A.n[2] : (int64_t)A.n[0] * A.n[1]);
-                    I = A.fixed[face][((int64_t)f * A.na + G->gidx) * ps + sFidx[e]];
+                const int q = face >> 1;
+                const int64_t ps = q == 0 ? (int64_t)A.n[1] * A.n[2]
+                                          : (q == 1 ? (int64_t)A.n[0] * A.n[2] : (int64_t)A.n[0] * A.n[1]);
+#pragma unroll
+                for (int k = 0; k < RMAX; ++k) {
+                    double I = 0.0;
+                    if (kind == BC_THERMAL)
+                        I = Bf[-1 - src];
+                    else if (kind == BC_FIXED)
+                        I = A.fixed[face][((int64_t)f * A.na + A.rays[rays[k]].gidx) * ps + sFidx[e]];
+                    v[k] = DFORM ? Real(I - sS[e]) : Real(I);
                 }
-                v = DFORM ? Real(I - sS[e]) : Real(I);
             }
-            sV[e] = v;
+#pragma unroll
+            for (int k = 0; k < RMAX; ++k) sV[k * PWIN + e] = v[k];
         }
         __syncthreads();
-        if (act) {
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) {
+            if (k >= nr || !act) continue;
+            const int ray = rays[k];
+            const RayGeo *G = A.rays + ray;
+            const int64_t rb = (int64_t)f * A.na + ray;
+            const Real *win = sV + k * PWIN;
             const double fa = G->fa, fb = G->fb;
             auto Iat = [&](int ua, int ub) {
                 const int e = (ly - ub) * PW + (lx - ua);
-                return DFORM ? double(sV[e]) + sS[e] : double(sV[e]);
+                return DFORM ? double(win[e]) + sS[e] : double(win[e]);
             };
             double row[3];
 #pragma unroll
@@ -233,8 +248,8 @@ __global__ void __launch_bounds__(PT *PT) plane_step_kernel(PlaneArgs<Real> A, i
                 seg_coeffs(dt, E, pm, p0);
                 v = (Im * E + pm * Sm) + p0 * S0;
             }
-            wr_plane[ib * na_ + ia] = v;
-            if (keep_i) wrap_i[ib * na_ + ia] = double(v) + S0;
+            A.planes[(rb * 2 + wsel) * A.pmax + ib * na_ + ia] = v;
+            if (keep_i) A.wrapI[rb * A.pmax + ib * na_ + ia] = double(v) + S0;
             acc += Real(G->wk) * v;
         }
     }
