@@ -70,6 +70,9 @@ def _load():
         lib.orc_control_point.restype = ctypes.c_double
         lib.orc_quad_interp.argtypes = [ctypes.c_double] * 4
         lib.orc_quad_interp.restype = ctypes.c_double
+        lib.orc_gs_iteration.argtypes = [ctypes.POINTER(_Grid), P, P, P, P, P, P, P, P, ctypes.c_int, P, P,
+                                         P, P, P]
+        lib.orc_gs_iteration.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -302,16 +305,9 @@ class Problem:
         self.have_prev = 1
 
     # -- one formal solution ---------------------------------------------------
-    def sweep(self, S, want_hk=False, bin_active=None):
-        """J = Lambda[S] for every bin (plus H, K and the diagonal Lambda*).
-
-        Periodic ghosts come from the previous sweep of this problem (or from S
-        before the first one); afterwards the memory holds this sweep's planes."""
-        lib = _load()
-        nx, ny, nz = self.n
-        S = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(self.chi.shape))
+    def _grid(self, want_hk=False):
         g = _Grid()
-        g.n[:] = [nx, ny, nz]
+        g.n[:] = list(self.n)
         g.nf, g.na = self.nf, self.na
         g.bc_lo[:] = list(self.bc_lo)
         g.bc_hi[:] = list(self.bc_hi)
@@ -319,6 +315,16 @@ class Problem:
         g.h[:] = list(self.h)
         g.order = self.order
         g.interp = self.interp
+        return g
+
+    def sweep(self, S, want_hk=False, bin_active=None):
+        """J = Lambda[S] for every bin (plus H, K and the diagonal Lambda*).
+
+        Periodic ghosts come from the previous sweep of this problem (or from S
+        before the first one); afterwards the memory holds this sweep's planes."""
+        lib = _load()
+        S = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(self.chi.shape))
+        g = self._grid(want_hk)
         shp = self.chi.shape
         J = np.zeros(shp)
         lam = np.zeros(shp)
@@ -398,6 +404,81 @@ class Problem:
                 r = float(np.max(np.abs(dS[m]) / np.abs(Snew[m]))) if m.any() else 0.0
                 S[f] = Snew
                 J[f] = Jn
+                iters[f] = n + 1
+                resid[f] = r
+            if fixed_iters > 0:
+                continue
+            conv = resid <= delta_c
+            if per_bin_stop:
+                active &= ~conv
+                if not active.any():
+                    break
+            elif conv[active].all():
+                break
+        converged = bool(np.all(resid <= delta_c))
+        return {"S": S, "J": J, "iters": iters, "resid": resid, "lam": lam, "converged": converged}
+
+    def gs_iteration(self, S, bin_active=None):
+        """One Gauss-Seidel iteration (section 3.4, planes from the top down as the
+        blocks; see orc_gs_iteration): returns S^{n+1}, the J each vertex was updated
+        with, Lambda* and the update dS.  Periodic ghosts read this problem's memory
+        (S at the iteration's start before any sweep); afterwards the memory holds the
+        iteration's outgoing planes."""
+        if self.order != 0 or self.interp != 0:
+            raise ValueError("Gauss-Seidel is built with first-order segments and bilinear I- only")
+        if self.bc_lo[2] == PERIODIC:
+            raise ValueError("Gauss-Seidel orders the planes along a non-periodic z axis")
+        lib = _load()
+        shp = self.chi.shape
+        S = np.array(np.asarray(S, dtype=np.float64).reshape(shp), order="C")
+        J = np.zeros(shp)
+        lam = np.zeros(shp)
+        dS = np.zeros(shp)
+        fixed = (ctypes.c_void_p * 6)(*[a.ctypes.data if a is not None else None for a in self._fixed])
+        prev_in = (ctypes.c_void_p * 3)(*[a.ctypes.data if a is not None else None for a in self.prev])
+        new = [a.copy() if a is not None else None for a in self.prev]
+        prev_out = (ctypes.c_void_p * 3)(*[a.ctypes.data if a is not None else None for a in new])
+        act = None if bin_active is None else np.ascontiguousarray(bin_active, dtype=np.int32)
+        rc = lib.orc_gs_iteration(ctypes.byref(self._grid()), _ptr(self.mu), _ptr(self.w), _ptr(self.chi),
+                                  _ptr(self.B), _ptr(self.eps), _ptr(S), fixed, prev_in, int(self.have_prev),
+                                  prev_out, _ptr(act), _ptr(J), _ptr(lam), _ptr(dS))
+        if rc == -1:
+            raise MemoryError("oracle Gauss-Seidel iteration ran out of memory")
+        if rc != 0:
+            raise ValueError("unsupported problem for the Gauss-Seidel iteration")
+        self.prev = new
+        self.have_prev = 1
+        return {"S": S, "J": J, "lam": lam, "dS": dS}
+
+    def ali_gs(self, delta_c=1e-6, max_iter=10000, fixed_iters=0, S0=None, J_prev=None, per_bin_stop=True):
+        """Gauss-Seidel accelerated Lambda iteration (section 3.4): as ``ali`` with
+        each iteration a Gauss-Seidel pass (gs_iteration).  r = max |dS| / S^{n+1} per
+        bin (eq. conv); J is the J of each bin's last iteration."""
+        eps, B = self.eps, self.B
+        if S0 is not None:
+            S = np.array(S0, dtype=np.float64).reshape(B.shape)
+        elif J_prev is not None:
+            S = eps * B + (1.0 - eps) * np.asarray(J_prev, dtype=np.float64).reshape(B.shape)
+        else:
+            S = B.copy()
+        nf = self.nf
+        active = np.ones(nf, dtype=bool)
+        iters = np.zeros(nf, dtype=np.int64)
+        resid = np.full(nf, np.inf)
+        J = np.zeros_like(S)
+        lam = None
+        n_total = fixed_iters if fixed_iters > 0 else max_iter
+        for n in range(n_total):
+            out = self.gs_iteration(S, bin_active=active.astype(np.int32))
+            if lam is None:
+                lam = out["lam"].copy()
+            for f in np.nonzero(active)[0]:
+                Snew = out["S"][f]
+                dS = out["dS"][f]
+                m = Snew != 0.0
+                r = float(np.max(np.abs(dS[m]) / np.abs(Snew[m]))) if m.any() else 0.0
+                S[f] = Snew
+                J[f] = out["J"][f]
                 iters[f] = n + 1
                 resid[f] = r
             if fixed_iters > 0:

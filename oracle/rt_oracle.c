@@ -280,6 +280,7 @@ typedef struct {
     const double *const *fixed;   /* [6]: lo x, hi x, lo y, hi y, lo z, hi z */
     const double *const *prev;    /* [3]: per periodic axis, previous sweep */
     int have_prev;
+    const double *Scold;      /* S of the wrapped vertex before any sweep (periodic ghosts) */
 } orc_ctx;
 
 /* chi and S at vertex v (possibly a ghost vertex) */
@@ -316,7 +317,7 @@ static double vertex_intensity(const orc_ctx *c, const int v[3])
         return F[((int64_t)c->f * g->na + c->ray) * ps + plane_index(g, q, u)];
     }
     /* only periodic axes are outside */
-    if (!c->have_prev) return c->S[cell_index(g, u[0], u[1], u[2])];
+    if (!c->have_prev) return c->Scold[cell_index(g, u[0], u[1], u[2])];
     for (int q = 0; q < 3; ++q) {
         if (!outq[q]) continue;
         int64_t ps = plane_size(g, q);
@@ -376,6 +377,122 @@ static double stencil_intensity(const orc_ctx *c, const orc_ray *r, const int vc
     return vertex_intensity(c, v);
 }
 
+/* bilinear weights of the upwind face at offsets (0,0) (1,0) (0,1) (1,1) along (a, b) */
+static void face_weights(const orc_ray *r, double wv[4])
+{
+    wv[0] = (1.0 - r->fa) * (1.0 - r->fb);
+    wv[1] = r->fa * (1.0 - r->fb);
+    wv[2] = (1.0 - r->fa) * r->fb;
+    wv[3] = r->fa * r->fb;
+}
+
+/*
+ * The short characteristic of one ray ending at vertex cpos, with the intensities of
+ * the ray's current sweep in c->Icur and the source function c->S: returns I0 and the
+ * weight of S0 in it (the ray's share of Lambda*).
+ */
+static void vertex_solve(const orc_ctx *c, const orc_ray *r, const double wv[4], const int cpos[3], double *I0_out,
+                         double *ldiag_out)
+{
+    static const int oa[4] = {0, 1, 0, 1};
+    static const int ob[4] = {0, 0, 1, 1};
+    const orc_grid *g = c->g;
+    const int i = cpos[0], j = cpos[1], k = cpos[2];
+    double Iv[4], Sv[4], Cv[4];
+    for (int t = 0; t < 4; ++t) {
+        int v[3] = {i, j, k};
+        v[r->d] -= r->sgn[r->d];
+        v[r->a] -= oa[t] * r->sgn[r->a];
+        v[r->b] -= ob[t] * r->sgn[r->b];
+        Iv[t] = vertex_intensity(c, v);
+        vertex_fields(c, v, &Cv[t], &Sv[t]);
+    }
+    double Im;
+    if (g->interp == 1) {
+        /* rows at b offsets -1, 0, +1 (downwind side, vertex, upwind side), each
+           interpolated along a, then along b */
+        double row[3];
+        for (int ub = -1; ub <= 1; ++ub) {
+            double f[3];
+            for (int ua = -1; ua <= 1; ++ua) f[ua + 1] = stencil_intensity(c, r, cpos, ua, ub);
+            row[ub + 1] = orc_quad_interp(f[0], f[1], f[2], r->fa);
+        }
+        Im = orc_quad_interp(row[0], row[1], row[2], r->fb);
+    } else {
+        Im = ((wv[0] * Iv[0] + wv[1] * Iv[1]) + wv[2] * Iv[2]) + wv[3] * Iv[3];
+    }
+    double Sm = ((wv[0] * Sv[0] + wv[1] * Sv[1]) + wv[2] * Sv[2]) + wv[3] * Sv[3];
+    double Cm = ((wv[0] * Cv[0] + wv[1] * Cv[1]) + wv[2] * Cv[2]) + wv[3] * Cv[3];
+    int64_t id = cell_index(g, i, j, k);
+    double S0 = c->S[id];
+    double dt = r->s * (Cm + c->chi[id]) * 0.5;
+    double I0, ldiag;
+    if (g->order == 1) {
+        /* downwind point: the mirror image of the upwind one */
+        double Sp4[4], Cp4[4];
+        for (int t = 0; t < 4; ++t) {
+            int v[3] = {i, j, k};
+            v[r->d] += r->sgn[r->d];
+            v[r->a] += oa[t] * r->sgn[r->a];
+            v[r->b] += ob[t] * r->sgn[r->b];
+            vertex_fields(c, v, &Cp4[t], &Sp4[t]);
+        }
+        double Sp = ((wv[0] * Sp4[0] + wv[1] * Sp4[1]) + wv[2] * Sp4[2]) + wv[3] * Sp4[3];
+        double Cp = ((wv[0] * Cp4[0] + wv[1] * Cp4[1]) + wv[2] * Cp4[2]) + wv[3] * Cp4[3];
+        double dtp = r->s * (c->chi[id] + Cp) * 0.5;
+        double Sc = orc_control_point(Sm, S0, Sp, dt, dtp);
+        double E, al, be, ga;
+        orc_bezier_coeffs(dt, &E, &al, &be, &ga);
+        I0 = ((Im * E + al * Sm) + be * S0) + ga * Sc;
+        ldiag = be;
+    } else {
+        double E, psim, psi0;
+        orc_coeffs(dt, &E, &psim, &psi0);
+        I0 = (Im * E + psim * Sm) + psi0 * S0;
+        ldiag = psi0;
+    }
+    *I0_out = I0;
+    *ldiag_out = ldiag;
+}
+
+/* keep one ray's intensity on its outgoing plane of every periodic axis for the
+   next sweep */
+static void save_periodic(const orc_grid *g, const orc_ray *r, int f, int ray, const double *Icur,
+                          double *const *prev_out)
+{
+    for (int q = 0; q < 3; ++q) {
+        if (!is_periodic(g, q) || !prev_out || !prev_out[q]) continue;
+        int64_t ps = plane_size(g, q);
+        double *P = prev_out[q] + ((int64_t)f * g->na + ray) * ps;
+        int u[3];
+        for (u[2] = 0; u[2] < g->n[2]; ++u[2])
+            for (u[1] = 0; u[1] < g->n[1]; ++u[1])
+                for (u[0] = 0; u[0] < g->n[0]; ++u[0]) {
+                    int outc = (r->sgn[q] > 0) ? g->n[q] - 1 : 0;
+                    if (u[q] != outc) continue;
+                    P[plane_index(g, q, u)] = Icur[cell_index(g, u[0], u[1], u[2])];
+                }
+    }
+}
+
+/* visiting order of a ray: row-major from the upwind corner (x fastest), or, for the
+   quadratic upwind intensity, plane by plane along d; idx -> real coordinates */
+static void visit_position(const orc_grid *g, const orc_ray *r, int64_t idx, int cpos[3])
+{
+    int ol[3];
+    if (g->interp == 1) {
+        const int64_t per = (int64_t)g->n[r->a] * g->n[r->b];
+        ol[r->d] = (int)(idx / per);
+        ol[r->a] = (int)((idx % per) % g->n[r->a]);
+        ol[r->b] = (int)((idx % per) / g->n[r->a]);
+    } else {
+        ol[0] = (int)(idx % g->n[0]);
+        ol[1] = (int)((idx / g->n[0]) % g->n[1]);
+        ol[2] = (int)(idx / ((int64_t)g->n[0] * g->n[1]));
+    }
+    for (int q = 0; q < 3; ++q) cpos[q] = (r->sgn[q] > 0) ? ol[q] : g->n[q] - 1 - ol[q];
+}
+
 /*
  * One formal solution: every ray swept once over every bin.
  *   mu  [na][3] direction cosines, w [na] weights (summing to 1)
@@ -410,9 +527,6 @@ int orc_sweep(const orc_grid *g, const double *mu, const double *w,
     double *Icur = (double *)malloc(sizeof(double) * ncell);
     if (!Icur) return -1;
 
-    static const int oa[4] = {0, 1, 0, 1};
-    static const int ob[4] = {0, 0, 1, 1};
-
     for (int f = 0; f < g->nf; ++f) {
         if (bin_active && !bin_active[f]) continue;
         const double *chif = chi + f * ncell;
@@ -423,125 +537,192 @@ int orc_sweep(const orc_grid *g, const double *mu, const double *w,
             orc_ray r;
             ray_geometry(m, g->h, &r);
             double wv[4];
-            wv[0] = (1.0 - r.fa) * (1.0 - r.fb);
-            wv[1] = r.fa * (1.0 - r.fb);
-            wv[2] = (1.0 - r.fa) * r.fb;
-            wv[3] = r.fa * r.fb;
+            face_weights(&r, wv);
 
-            orc_ctx c = {g, f, ray, chif, Sf, Bf, Icur, fixed, prev_in, have_prev};
+            orc_ctx c = {g, f, ray, chif, Sf, Bf, Icur, fixed, prev_in, have_prev, Sf};
             const double wk = w[ray];
             const double mx = m[0], my = m[1], mz = m[2];
 
             for (int64_t idx = 0; idx < ncell; ++idx) {
-                {
-                    {
-                        /* visiting order: row-major from the upwind corner (x fastest), or,
-                           for the quadratic upwind intensity, plane by plane along d */
-                        int ol[3];
-                        if (g->interp == 1) {
-                            const int64_t per = (int64_t)g->n[r.a] * g->n[r.b];
-                            ol[r.d] = (int)(idx / per);
-                            ol[r.a] = (int)((idx % per) % g->n[r.a]);
-                            ol[r.b] = (int)((idx % per) / g->n[r.a]);
-                        } else {
-                            ol[0] = (int)(idx % g->n[0]);
-                            ol[1] = (int)((idx / g->n[0]) % g->n[1]);
-                            ol[2] = (int)(idx / ((int64_t)g->n[0] * g->n[1]));
-                        }
-                        const int i = (r.sgn[0] > 0) ? ol[0] : g->n[0] - 1 - ol[0];
-                        const int j = (r.sgn[1] > 0) ? ol[1] : g->n[1] - 1 - ol[1];
-                        const int k = (r.sgn[2] > 0) ? ol[2] : g->n[2] - 1 - ol[2];
-                        int cpos[3] = {i, j, k};
-                        double Iv[4], Sv[4], Cv[4];
-                        for (int t = 0; t < 4; ++t) {
-                            int v[3] = {i, j, k};
-                            v[r.d] -= r.sgn[r.d];
-                            v[r.a] -= oa[t] * r.sgn[r.a];
-                            v[r.b] -= ob[t] * r.sgn[r.b];
-                            Iv[t] = vertex_intensity(&c, v);
-                            vertex_fields(&c, v, &Cv[t], &Sv[t]);
-                        }
-                        double Im;
-                        if (g->interp == 1) {
-                            /* rows at b offsets -1, 0, +1 (downwind side, vertex, upwind
-                               side), each interpolated along a, then along b */
-                            double row[3];
-                            for (int ub = -1; ub <= 1; ++ub) {
-                                double f[3];
-                                for (int ua = -1; ua <= 1; ++ua) f[ua + 1] = stencil_intensity(&c, &r, cpos, ua, ub);
-                                row[ub + 1] = orc_quad_interp(f[0], f[1], f[2], r.fa);
-                            }
-                            Im = orc_quad_interp(row[0], row[1], row[2], r.fb);
-                        } else {
-                            Im = ((wv[0] * Iv[0] + wv[1] * Iv[1]) + wv[2] * Iv[2]) + wv[3] * Iv[3];
-                        }
-                        double Sm = ((wv[0] * Sv[0] + wv[1] * Sv[1]) + wv[2] * Sv[2]) + wv[3] * Sv[3];
-                        double Cm = ((wv[0] * Cv[0] + wv[1] * Cv[1]) + wv[2] * Cv[2]) + wv[3] * Cv[3];
-                        int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
-                        double S0 = Sf[id];
-                        double dt = r.s * (Cm + chif[id]) * 0.5;
-                        double I0, ldiag;
-                        if (g->order == 1) {
-                            /* downwind point: the mirror image of the upwind one */
-                            double Sp4[4], Cp4[4];
-                            for (int t = 0; t < 4; ++t) {
-                                int v[3] = {i, j, k};
-                                v[r.d] += r.sgn[r.d];
-                                v[r.a] += oa[t] * r.sgn[r.a];
-                                v[r.b] += ob[t] * r.sgn[r.b];
-                                vertex_fields(&c, v, &Cp4[t], &Sp4[t]);
-                            }
-                            double Sp = ((wv[0] * Sp4[0] + wv[1] * Sp4[1]) + wv[2] * Sp4[2]) + wv[3] * Sp4[3];
-                            double Cp = ((wv[0] * Cp4[0] + wv[1] * Cp4[1]) + wv[2] * Cp4[2]) + wv[3] * Cp4[3];
-                            double dtp = r.s * (chif[id] + Cp) * 0.5;
-                            double Sc = orc_control_point(Sm, S0, Sp, dt, dtp);
-                            double E, al, be, ga;
-                            orc_bezier_coeffs(dt, &E, &al, &be, &ga);
-                            I0 = ((Im * E + al * Sm) + be * S0) + ga * Sc;
-                            ldiag = be;
-                        } else {
-                            double E, psim, psi0;
-                            orc_coeffs(dt, &E, &psim, &psi0);
-                            I0 = (Im * E + psim * Sm) + psi0 * S0;
-                            ldiag = psi0;
-                        }
-                        Icur[id] = I0;
+                int cpos[3];
+                visit_position(g, &r, idx, cpos);
+                double I0, ldiag;
+                vertex_solve(&c, &r, wv, cpos, &I0, &ldiag);
+                int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
+                Icur[id] = I0;
 
-                        int64_t o = (int64_t)f * ncell + id;
-                        J[o] += wk * I0;
-                        lam[o] += wk * ldiag;
-                        if (g->want_hk) {
-                            H[0 * tot + o] += wk * mx * I0;
-                            H[1 * tot + o] += wk * my * I0;
-                            H[2 * tot + o] += wk * mz * I0;
-                            K[0 * tot + o] += wk * mx * mx * I0;
-                            K[1 * tot + o] += wk * my * my * I0;
-                            K[2 * tot + o] += wk * mz * mz * I0;
-                            K[3 * tot + o] += wk * mx * my * I0;
-                            K[4 * tot + o] += wk * mx * mz * I0;
-                            K[5 * tot + o] += wk * my * mz * I0;
-                        }
-                    }
+                int64_t o = (int64_t)f * ncell + id;
+                J[o] += wk * I0;
+                lam[o] += wk * ldiag;
+                if (g->want_hk) {
+                    H[0 * tot + o] += wk * mx * I0;
+                    H[1 * tot + o] += wk * my * I0;
+                    H[2 * tot + o] += wk * mz * I0;
+                    K[0 * tot + o] += wk * mx * mx * I0;
+                    K[1 * tot + o] += wk * my * my * I0;
+                    K[2 * tot + o] += wk * mz * mz * I0;
+                    K[3 * tot + o] += wk * mx * my * I0;
+                    K[4 * tot + o] += wk * mx * mz * I0;
+                    K[5 * tot + o] += wk * my * mz * I0;
                 }
             }
-            /* keep this ray's intensity on its outgoing plane of every periodic
-               axis for the next sweep */
-            for (int q = 0; q < 3; ++q) {
-                if (!is_periodic(g, q) || !prev_out || !prev_out[q]) continue;
-                int64_t ps = plane_size(g, q);
-                double *P = prev_out[q] + ((int64_t)f * g->na + ray) * ps;
-                int u[3];
-                for (u[2] = 0; u[2] < g->n[2]; ++u[2])
-                    for (u[1] = 0; u[1] < g->n[1]; ++u[1])
-                        for (u[0] = 0; u[0] < g->n[0]; ++u[0]) {
-                            int outc = (r.sgn[q] > 0) ? g->n[q] - 1 : 0;
-                            if (u[q] != outc) continue;
-                            P[plane_index(g, q, u)] = Icur[cell_index(g, u[0], u[1], u[2])];
-                        }
-            }
+            save_periodic(g, &r, f, ray, Icur, prev_out);
         }
     }
     free(Icur);
+    return 0;
+}
+
+/*
+ * One Gauss-Seidel iteration of the ALI (section 3.4): the scheme the paper takes
+ * from Trujillo Bueno & Fabiani Bendicho (1995) for one dimension and generalises to
+ * 2D and 3D with bilinear interpolation of the upwind intensity.  The update of
+ * eq. dsjacobi is applied to a vertex as soon as its J is complete, and every later
+ * short characteristic sees the new S.  The ordering here takes the horizontal
+ * planes as its blocks (z is the vertical, non-periodic axis):
+ *
+ *   1. the rays going up (direction sign +1 along z) are swept over the whole grid
+ *      with the old S; no vertex has been updated yet, so their intensities are
+ *      final, and their share of J is kept;
+ *   2. the planes are then taken from the top (k = nz - 1) down.  Every ray going
+ *      down is advanced over plane k in its row-major order (the planes above are
+ *      final, plane k still holds the old S), which completes J on plane k; the
+ *      plane's S is updated with eq. dsjacobi; and the plane's downward intensities
+ *      are computed again from the updated S, since the planes below read them (the
+ *      paper's update of the outgoing intensities).
+ *
+ * Every vertex of plane k is then updated with J = Lambda applied to S holding the
+ * new values on the planes above and the old ones elsewhere: Gauss-Seidel with the
+ * planes in descending order and Jacobi within a plane.  With first-order segments
+ * and bilinear interpolation a ray going up depends only on vertices at or below its
+ * own plane, so its contributions need no correction (the paper's correction of the
+ * upward share with saved weights arises with the parabolic source, which reads the
+ * downwind S).
+ *
+ * Periodic ghosts (x, y) read prev_in, the memory of the previous iteration, for the
+ * whole iteration; before any iteration they take S as it was when the iteration
+ * began.  prev_out receives the upward rays' outgoing planes from step 1 and the
+ * downward rays' from the recomputed planes of step 2.
+ *
+ *   eps, B, chi [nf][cells];  S [nf][cells] in: S^n, out: S^{n+1}
+ *   J   [nf][cells] out: the J each vertex was updated with
+ *   lam [nf][cells] out: Lambda* = sum_k w_k psi0_k
+ *   dS  [nf][cells] out: the update of eq. dsjacobi
+ * Needs order = 0, interp = 0 and a non-periodic z axis.  Bins with bin_active[f] = 0
+ * are skipped.  Returns 0, -1 when scratch memory runs out, -2 for an unsupported grid.
+ */
+int orc_gs_iteration(const orc_grid *g, const double *mu, const double *w,
+                     const double *chi, const double *B, const double *eps, double *S,
+                     const double *const *fixed, const double *const *prev_in, int have_prev,
+                     double *const *prev_out, const int32_t *bin_active,
+                     double *J, double *lam, double *dS)
+{
+    if (g->order != 0 || g->interp != 0 || is_periodic(g, 2)) return -2;
+    const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const int64_t nxy = (int64_t)nx * ny;
+    int ndown = 0;
+    for (int ray = 0; ray < g->na; ++ray) ndown += mu[3 * ray + 2] < 0.0;
+    double *Iup = (double *)malloc(sizeof(double) * ncell);
+    double *Idn = (double *)malloc(sizeof(double) * ncell * (ndown > 0 ? ndown : 1));
+    double *S0 = (double *)malloc(sizeof(double) * ncell);
+    if (!Iup || !Idn || !S0) {
+        free(Iup);
+        free(Idn);
+        free(S0);
+        return -1;
+    }
+
+    for (int f = 0; f < g->nf; ++f) {
+        if (bin_active && !bin_active[f]) continue;
+        const double *chif = chi + f * ncell;
+        const double *Bf = B + f * ncell;
+        const double *ef = eps + f * ncell;
+        double *Sf = S + f * ncell;
+        double *Jf = J + f * ncell;
+        double *lf = lam + f * ncell;
+        double *dSf = dS + f * ncell;
+        memcpy(S0, Sf, sizeof(double) * ncell);
+        memset(Jf, 0, sizeof(double) * ncell);
+        memset(lf, 0, sizeof(double) * ncell);
+
+        /* 1. rays going up, the whole grid with the old S */
+        for (int ray = 0; ray < g->na; ++ray) {
+            const double *m = mu + 3 * ray;
+            if (m[2] < 0.0) continue;
+            orc_ray r;
+            ray_geometry(m, g->h, &r);
+            double wv[4];
+            face_weights(&r, wv);
+            orc_ctx c = {g, f, ray, chif, Sf, Bf, Iup, fixed, prev_in, have_prev, S0};
+            for (int64_t idx = 0; idx < ncell; ++idx) {
+                int cpos[3];
+                visit_position(g, &r, idx, cpos);
+                double I0, ld;
+                vertex_solve(&c, &r, wv, cpos, &I0, &ld);
+                const int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
+                Iup[id] = I0;
+                Jf[id] += w[ray] * I0;
+                lf[id] += w[ray] * ld;
+            }
+            save_periodic(g, &r, f, ray, Iup, prev_out);
+        }
+
+        /* 2. planes from the top down: the downward rays over plane k with the current
+           S, the update of plane k, the plane's downward intensities again */
+        for (int kk = 0; kk < nz; ++kk) {
+            const int k = nz - 1 - kk;
+            for (int pass = 0; pass < 2; ++pass) {
+                int slot = 0;
+                for (int ray = 0; ray < g->na; ++ray) {
+                    const double *m = mu + 3 * ray;
+                    if (m[2] >= 0.0) continue;
+                    double *Ir = Idn + (int64_t)slot * ncell;
+                    ++slot;
+                    orc_ray r;
+                    ray_geometry(m, g->h, &r);
+                    double wv[4];
+                    face_weights(&r, wv);
+                    orc_ctx c = {g, f, ray, chif, Sf, Bf, Ir, fixed, prev_in, have_prev, S0};
+                    for (int64_t p = 0; p < nxy; ++p) {
+                        const int ox = (int)(p % nx), oy = (int)(p / nx);
+                        int cpos[3];
+                        cpos[0] = (r.sgn[0] > 0) ? ox : nx - 1 - ox;
+                        cpos[1] = (r.sgn[1] > 0) ? oy : ny - 1 - oy;
+                        cpos[2] = k;
+                        double I0, ld;
+                        vertex_solve(&c, &r, wv, cpos, &I0, &ld);
+                        const int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
+                        Ir[id] = I0;
+                        if (pass == 0) {
+                            Jf[id] += w[ray] * I0;
+                            lf[id] += w[ray] * ld;
+                        }
+                    }
+                }
+                if (pass == 1) break;
+                for (int64_t p = 0; p < nxy; ++p) {
+                    const int64_t id = (int64_t)k * nxy + p;
+                    const double e = ef[id];
+                    const double d = ((1.0 - e) * Jf[id] + e * Bf[id] - Sf[id]) / (1.0 - (1.0 - e) * lf[id]);
+                    dSf[id] = d;
+                    Sf[id] = Sf[id] + d;
+                }
+            }
+        }
+        int slot = 0;
+        for (int ray = 0; ray < g->na; ++ray) {
+            const double *m = mu + 3 * ray;
+            if (m[2] >= 0.0) continue;
+            orc_ray r;
+            ray_geometry(m, g->h, &r);
+            save_periodic(g, &r, f, ray, Idn + (int64_t)slot * ncell, prev_out);
+            ++slot;
+        }
+    }
+    free(Iup);
+    free(Idn);
+    free(S0);
     return 0;
 }
 
