@@ -332,6 +332,8 @@ def main():
     ap.add_argument("--interp", choices=["bilinear", "quadratic"], default="bilinear",
                     help="scattering: upwind intensity bilinear (tile wavefront) or monotone quadratic "
                          "(plane-ordered sweep; no moments epilogue)")
+    ap.add_argument("--ali", choices=["jacobi", "gauss-seidel"], default="jacobi",
+                    help="scattering: Jacobi ALI, or Gauss-Seidel with horizontal planes as the blocks")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="profiling mode: run exactly this many ALI iterations per step instead of converging")
     ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
@@ -395,6 +397,10 @@ def main():
         print("--interp quadratic is built with first-order segments only", file=sys.stderr)
         sys.exit(2)
     interp = rt.RT_INTERP_QUADRATIC if quad else rt.RT_INTERP_BILINEAR
+    gs = args.ali == "gauss-seidel"
+    if gs and (quad or order):
+        print("--ali gauss-seidel is built with first-order segments and bilinear I- only", file=sys.stderr)
+        sys.exit(2)
     kind = "quadratic" if quad else args.order
     ops_per_update = OPS_PER_UPDATE_QUAD_F32 if quad else (OPS_PER_UPDATE_BEZ_F32 if order else OPS_PER_UPDATE_F32)
     prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
@@ -403,8 +409,9 @@ def main():
     def step():
         prob.reset_periodic()
         prob.set_fields(chi, eps, B)
-        status, st = prob.ali_solve(S, J, delta_c=wl.delta_c, max_iter=50000, per_bin_stop=True,
-                                    fixed_iters=args.fixed_iters)
+        solve = prob.ali_solve_gs if gs else prob.ali_solve
+        status, st = solve(S, J, delta_c=wl.delta_c, max_iter=50000, per_bin_stop=True,
+                           fixed_iters=args.fixed_iters)
         if status != rt.RT_OK:
             raise RuntimeError(f"ALI did not converge: {st}")
         # moments epilogue on the converged S (not built for the plane-ordered sweep)
@@ -443,6 +450,10 @@ def main():
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
                 "ops_per_update": ops_per_update}
+    if gs:
+        # the timed-sweep hooks cover the Jacobi sweep only; the Gauss-Seidel kernels are
+        # timed with rocprofv3 (plane and chain launches are latency-bound)
+        roofline = None
 
     extra = {}
     if not args.no_f64:
@@ -451,7 +462,8 @@ def main():
         p64.set_fields(chi, eps, B)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        status, st64 = p64.ali_solve(S, J, delta_c=wl.delta_c, max_iter=50000, per_bin_stop=True)
+        status, st64 = (p64.ali_solve_gs if gs else p64.ali_solve)(S, J, delta_c=wl.delta_c, max_iter=50000,
+                                                                   per_bin_stop=True)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         J64 = J.cpu().numpy()
@@ -467,11 +479,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded, generated on the host)",
         "config": {"workload": f"scattering {wl.shape[0]}^3, 1 bin, {wl.na} rays, eps=1e-3, "
-                               f"vertical tau 1e4, Jacobi ALI from S=B to max|dS/S|<=1e-6, "
+                               f"vertical tau 1e4, {'Gauss-Seidel' if gs else 'Jacobi'} ALI from S=B to max|dS/S|<=1e-6, "
                                f"FP32 sweeps + FP64 updates"
                                f"{', second-order (Bezier) segments' if order else ''}"
                                f"{', monotone quadratic upwind intensity (plane order), no moments epilogue' if quad else ''}",
                    "grid": list(wl.shape), "rays": wl.na, "order": args.order, "interp": args.interp,
+                   "ali": args.ali,
                    "schedule": args.schedule,
                    "bins": wl.nf},
         "ali_solves_per_s": args.steps / total,

@@ -196,6 +196,28 @@ typedef struct {
 rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
                        rt_ali_stats *stats, void *stream);
 
+/*
+ * rt_ali_solve_gs -- Gauss-Seidel ALI (section 3.4: the update of eq. dsjacobi is
+ * applied as soon as J of a vertex is complete, so later short characteristics see
+ * the new S; the scheme the paper takes from Trujillo Bueno & Fabiani Bendicho 1995
+ * and generalises to 3D with bilinear interpolation).  The blocks of the ordering are
+ * the horizontal planes from the top (z = nz - 1) down: per iteration the rays going
+ * up (direction cosine along z >= 0) are swept with S^n, then for each plane from the
+ * top the rays going down complete J on it (planes above already updated), the plane
+ * is updated, and its downward intensities are recomputed with the new S.  Vertices of
+ * one plane are updated together (Jacobi within a plane); when every ray crosses a z
+ * face first (no coupling inside a plane) this is point Gauss-Seidel.  Periodic ghosts
+ * (x, y) read the previous iteration's outgoing intensities for the whole iteration.
+ * Arguments, start values, stopping rule (eq. conv per bin), outputs, statuses and
+ * rt_ali_bin_stats as for rt_ali_solve; J_out holds the J each vertex was last
+ * updated with.  Needs order = RT_SC_LINEAR, interp = RT_INTERP_BILINEAR, a
+ * non-periodic z axis, the staged schedule and nx, ny <= 256; else RT_E_UNSUPPORTED
+ * before any work.  The first call on a problem allocates its plane buffers
+ * (nf * (na/2) * 3 * nx * ny reals).
+ */
+rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+                          rt_ali_stats *stats, void *stream);
+
 /* Per-bin iteration counts and last residuals of the most recent rt_ali_solve
  * (host arrays [nf]; either may be NULL).  Synchronises the stream. */
 rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream);

@@ -27,7 +27,7 @@ RT_INTERP_BILINEAR, RT_INTERP_QUADRATIC = 0, 1
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
-           "rt_ali_solve", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
+           "rt_ali_solve", "rt_ali_solve_gs", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
            "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
            "rt_server_load", "rt_server_destroy")
 
@@ -94,6 +94,7 @@ def load():
     lib.rt_problem_reset_periodic.argtypes = [P, P]
     lib.rt_formal_solve.argtypes = [P, P, P, P, P]
     lib.rt_ali_solve.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
+    lib.rt_ali_solve_gs.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_ali_bin_stats.argtypes = [P, P, P, P]
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
     lib.rt_problem_profile.argtypes = [P, I32]
@@ -224,14 +225,15 @@ def rt_formal_solve(p, S, J, lambda_star=None, stream=None):
 
 
 def rt_ali_solve(p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True, warm_start=0,
-                 check_every=0, stream=None):
-    """Returns (status, stats dict); status is RT_OK or RT_NOT_CONVERGED, errors raise."""
+                 check_every=0, stream=None, gauss_seidel=False):
+    """Returns (status, stats dict); status is RT_OK or RT_NOT_CONVERGED, errors raise.
+    ``gauss_seidel`` calls rt_ali_solve_gs instead of the Jacobi rt_ali_solve."""
     o = AliOpts(float(delta_c), int(max_iter), int(fixed_iters), 1 if per_bin_stop else 0, int(warm_start),
                 int(check_every))
     st = AliStats()
     n = S.numel()
-    status = load().rt_ali_solve(p, ctypes.byref(o), _dptr(S, name="S"), _dptr(J, n, "J"), ctypes.byref(st),
-                                 _stream(stream))
+    fn = load().rt_ali_solve_gs if gauss_seidel else load().rt_ali_solve
+    status = fn(p, ctypes.byref(o), _dptr(S, name="S"), _dptr(J, n, "J"), ctypes.byref(st), _stream(stream))
     _check(status, allow=(RT_OK, RT_NOT_CONVERGED))
     return status, {"iterations": st.iterations, "bins_converged": st.bins_converged,
                     "max_rel_dS": st.max_rel_dS, "seconds": st.seconds}
@@ -352,6 +354,9 @@ class Problem:
 
     def ali_solve(self, S, J, **kw):
         return rt_ali_solve(self.handle, S, J, **kw)
+
+    def ali_solve_gs(self, S, J, **kw):
+        return rt_ali_solve(self.handle, S, J, gauss_seidel=True, **kw)
 
     def moments(self, S, **kw):
         return rt_moments(self.handle, S, **kw)

@@ -288,6 +288,11 @@ struct rt_problem {
     double *mom_sum = nullptr;         // [1024 + 1]
     double *h_sum = nullptr;           // pinned scalar
     int *dag_done = nullptr;           // [nf][8][ntiles] completion epochs
+    // Gauss-Seidel ALI (allocated on first use)
+    void *gs_planes = nullptr;         // Real [nf][nd][2][nx ny]
+    void *gs_part = nullptr;           // Real [nd][nf][nx ny]
+    int *d_gs_down = nullptr;          // [nd] rays going down, shallow ones first
+    int gs_nd = 0, gs_ns = 0;
     int *h_flags = nullptr;            // pinned host copy of flags
     int *h_frozen = nullptr;           // pinned host copy of frozen
     std::vector<void *> allocs;
@@ -450,6 +455,7 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
     A.stage_tab = p->d_stage_tab;
     A.nstages = p->nstages;
     A.order = p->desc.order;
+    A.noct = 8;
     return A;
 }
 
@@ -1235,6 +1241,122 @@ rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lam
     return RT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Gauss-Seidel state of a problem: the rays going down (those crossing an x or y face
+// first ahead of those crossing a z face first), their plane buffers and partial sums.
+rt_status gs_prepare(rt_problem *p)
+{
+    if (p->gs_planes) return RT_OK;
+    std::vector<int> down, steep;
+    for (int k = 0; k < p->na; ++k) {
+        if (!(p->rays[k].oct & 4)) continue;
+        (p->rays[k].d == 2 ? steep : down).push_back(k);
+    }
+    const int ns = (int)down.size();
+    down.insert(down.end(), steep.begin(), steep.end());
+    const int nd = (int)down.size();
+    const size_t rs = p->f32 ? sizeof(float) : sizeof(double);
+    const size_t pxy = (size_t)p->n[0] * p->n[1];
+    unsigned char *planes = nullptr, *part = nullptr;
+    int *d_down = nullptr;
+    rt_status s = dalloc(p, &planes, (size_t)p->nf * std::max(nd, 1) * 2 * pxy * rs);
+    if (s == RT_OK) s = dalloc(p, &part, (size_t)std::max(nd, 1) * p->nf * pxy * rs);
+    if (s == RT_OK) s = dalloc(p, &d_down, (size_t)std::max(nd, 1));
+    if (s != RT_OK) return s;
+    if (nd > 0) HIP_TRY(hipMemcpy(d_down, down.data(), sizeof(int) * nd, hipMemcpyHostToDevice));
+    p->gs_planes = planes;
+    p->gs_part = part;
+    p->d_gs_down = d_down;
+    p->gs_nd = nd;
+    p->gs_ns = ns;
+    return RT_OK;
+}
+
+template <typename Real>
+GsArgs<Real> gs_args(rt_problem *p, double *S, double *J)
+{
+    GsArgs<Real> A{};
+    for (int q = 0; q < 3; ++q) {
+        A.n[q] = p->n[q];
+        A.periodic[q] = p->periodic[q];
+        A.bc_lo[q] = p->desc.bc_lo[q];
+        A.bc_hi[q] = p->desc.bc_hi[q];
+        A.wrap[q] = p->wrap[q];
+    }
+    A.nf = p->nf;
+    A.na = p->na;
+    A.cells = p->cells;
+    A.pxy = (int64_t)p->n[0] * p->n[1];
+    A.rays = p->d_rays;
+    A.down = p->d_gs_down;
+    A.nd = p->gs_nd;
+    A.ns = p->gs_ns;
+    if constexpr (sizeof(Real) == 4)
+        A.chi = p->chi32;
+    else
+        A.chi = p->chi64;
+    A.S = S;
+    A.B = p->B;
+    A.eps = p->eps;
+    A.lam = p->lam;
+    for (int k = 0; k < 6; ++k) A.fixed[k] = p->desc.I_fixed[k];
+    A.planes = static_cast<Real *>(p->gs_planes);
+    A.part = static_cast<Real *>(p->gs_part);
+    A.part_up = static_cast<const Real *>(p->part);
+    A.J = J;
+    A.frozen = p->frozen;
+    A.parity = p->parity;
+    A.blockmax = p->blockmax;
+    A.nblk = kUpdateBlocks;
+    A.tiles_x = (p->n[0] + kGsTile - 1) / kGsTile;
+    A.ntiles = A.tiles_x * ((p->n[1] + kGsTile - 1) / kGsTile);
+    return A;
+}
+
+// One Gauss-Seidel iteration: the rays going up over the whole grid with the old S
+// (octants 0 .. 3 of the tile wavefront), then the rays going down plane by plane from
+// the top with each plane's update as soon as its J is complete.
+template <typename Real>
+rt_status gs_iteration(rt_problem *p, double *S, double *J, hipStream_t st)
+{
+    HIP_TRY(launch_gs_clear(p->blockmax, (int64_t)p->nf * kUpdateBlocks, st));
+    SweepArgs<Real> U = sweep_args<Real>(p, S);
+    U.noct = 4;
+    if (p->cold) {
+        HIP_TRY(launch_periodic_cold<Real>(U, st));
+        p->cold = false;
+    }
+    HIP_TRY(launch_ghost_fill<Real>(U, st));
+    for (int s = 0; s < p->nstages; ++s) {
+        U.stage_off = p->stage_off[s];
+        U.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
+        U.stage = s;
+        if constexpr (sizeof(Real) == 8)
+            HIP_TRY(launch_sweep_stage_f64(U, p->waves, 1, st));
+        else
+            HIP_TRY(launch_sweep_stage_f32(U, p->waves, 1, st));
+    }
+    const GsArgs<Real> A = gs_args<Real>(p, S, J);
+    const int nz = p->n[2];
+    // launch nz recomputes plane 0 only for the periodic memory of the in-plane axes
+    const int last = (p->periodic[0] || p->periodic[1]) ? nz : nz - 1;
+    for (int t = 0; t <= last; ++t) {
+        HIP_TRY(launch_gs_plane<Real>(A, t, st));
+        if (t < nz) HIP_TRY(launch_gs_update<Real>(A, nz - 1 - t, st));
+    }
+    return RT_OK;
+}
+
+rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out, rt_ali_stats *stats,
+                  hipStream_t st, std::chrono::steady_clock::time_point t0, bool gs);
+
+}  // namespace
+
+extern "C" {
+
 rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out, rt_ali_stats *stats,
                        void *stream)
 {
@@ -1246,12 +1368,38 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
         rt_status so = check_ali_opts(opts);
         if (so != RT_OK) return so;
     }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t nc = p->cells * p->nf;
-    const size_t bytes = sizeof(double) * nc;
+    return ali_run(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, false);
+}
 
-    (void)nc;
-    (void)bytes;
+rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+                          rt_ali_stats *stats, void *stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (!p || !opts) return fail(RT_E_INVALID, "problem and opts are required");
+    if (!S_inout || !J_out) return fail(RT_E_INVALID, "S_inout and J_out are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    {
+        rt_status so = check_ali_opts(opts);
+        if (so != RT_OK) return so;
+    }
+    if (p->desc.order != RT_SC_LINEAR || p->plane_order)
+        return fail(RT_E_UNSUPPORTED, "Gauss-Seidel needs first-order segments and bilinear upwind intensities");
+    if (p->periodic[2]) return fail(RT_E_UNSUPPORTED, "Gauss-Seidel orders the planes along z, which must not be periodic");
+    if (p->persistent) return fail(RT_E_UNSUPPORTED, "Gauss-Seidel runs with the staged sweep schedule");
+    if (p->n[0] > kGsMaxLanes || p->n[1] > kGsMaxLanes)
+        return fail(RT_E_UNSUPPORTED, "Gauss-Seidel needs nx and ny <= %d", kGsMaxLanes);
+    rt_status s = gs_prepare(p);
+    if (s != RT_OK) return s;
+    return ali_run(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out, rt_ali_stats *stats,
+                  hipStream_t st, std::chrono::steady_clock::time_point t0, bool gs)
+{
     {
         rt_status s0 = ali_start(p, opts, S_inout, J_out, st);
         if (s0 != RT_OK) return s0;
@@ -1271,6 +1419,13 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
     for (int it = 0; it < total && !done;) {
         const int k = fixed ? total : std::min(every, total - it);
         for (int j = 0; j < k; ++j) {
+            if (gs) {
+                rt_status s = p->f32 ? gs_iteration<float>(p, S_inout, J_out, st)
+                                     : gs_iteration<double>(p, S_inout, J_out, st);
+                if (s != RT_OK) return s;
+                HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
+                continue;
+            }
             rt_status s = sweep_current_S(p, S_inout, st, j == 0, active);
             if (s != RT_OK) return s;
             if (p->f32)
@@ -1320,6 +1475,10 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
     if (!fixed && conv < p->nf) return RT_NOT_CONVERGED;
     return RT_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream)
 {

@@ -57,6 +57,7 @@ struct SweepArgs {
     const int *stage_tab;     // [nstages + 1] offsets of the stages in tiles (batched launches)
     int nstages;
     int order;                // 0: first-order segments, 1: second order (Bezier source)
+    int noct;                 // octants swept: 8, or 4 (the rays going up, octants 0 .. 3)
 };
 
 // One step of the plane-ordered sweep (monotone quadratic upwind intensity): every
@@ -92,6 +93,45 @@ struct PlaneArgs {
     const int *parity;        // [nf]: sweeps run so far, modulo 2
     int tiles_a[3];           // per first-crossed axis d: in-plane tiles along a
     int ntiles[3];            // per d: in-plane tiles
+};
+
+// Gauss-Seidel ALI (rt_gs.hip): the rays going up are swept over the whole grid with
+// the tile kernel (octants 0 .. 3); the rays going down then advance from the top
+// plane down.  Launch t recomputes plane nz - t with its updated S and computes plane
+// nz - 1 - t with the current S; the update of that plane follows.  Rays that cross a
+// z face first ("steep") take 16 x 16 tiles of the plane; the others ("shallow",
+// first-crossed axis d = x or y) depend on vertices of their own plane and run as a
+// chain along d in one workgroup, lanes along the other in-plane axis e.
+constexpr int kGsTile = 16;       // in-plane tile edge of a steep-ray workgroup
+constexpr int kGsChainCols = 4;   // columns (along d) per coefficient block of a chain
+constexpr int kGsMaxLanes = 256;  // largest extent along e of a chain (4 vertices per lane)
+
+template <typename Real>
+struct GsArgs {
+    int n[3];
+    int nf, na;
+    int periodic[3];
+    int bc_lo[3], bc_hi[3];
+    int64_t cells, pxy;           // vertices of the grid and of one z plane
+    const RayGeo *rays;           // [na]
+    const int *down;              // [nd] rays going down: the shallow ones first
+    int nd, ns;                   // rays going down, shallow ones among them
+    const Real *chi;              // [nf][cells]
+    double *S;                    // [nf][cells] source function, updated plane by plane
+    const double *B, *eps, *lam;  // [nf][cells]
+    const double *fixed[6];       // FIXED faces (real coordinates), or null
+    double *wrap[3];              // periodic memory, the layout of SweepArgs::wrap
+    Real *planes;                 // [nf][nd][2][pxy] final values (I, or D = I - S) of each
+                                  // downward ray on plane k in slot k & 1; steep rays in
+                                  // real layout (x fastest), shallow rays along e fastest
+    Real *part;                   // [nd][nf][pxy] w I (w D) of the plane being computed
+    const Real *part_up;          // [8][nf][cells] per-octant partials of the upward sweep
+    double *J;                    // [nf][cells] the J each vertex was updated with
+    const int *frozen;            // [nf]
+    const int *parity;            // [nf] periodic slot read this iteration
+    unsigned long long *blockmax; // [nf][nblk] residual maxima (bit patterns), zeroed per iteration
+    int nblk;
+    int tiles_x, ntiles;          // steep-ray tiles along x and per plane
 };
 
 // Dependency state of the persistent sweep: one completion flag per (bin, octant,
@@ -187,6 +227,14 @@ template <typename Real>
 hipError_t launch_plane_step(const PlaneArgs<Real> &A, int t, hipStream_t st);
 template <typename Real>
 hipError_t launch_plane_cold(const PlaneArgs<Real> &A, hipStream_t st);
+
+// Gauss-Seidel backward sweep (rt_gs.hip): launch t of the plane pass, the update of
+// plane k, and the cleared residual maxima of an iteration.
+template <typename Real>
+hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st);
+template <typename Real>
+hipError_t launch_gs_update(const GsArgs<Real> &A, int k, hipStream_t st);
+hipError_t launch_gs_clear(unsigned long long *blockmax, int64_t n, hipStream_t st);
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,
                                hipStream_t st);

@@ -762,14 +762,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     if (last >= 0) write_faces<Real, DFORM, ORD>(A, c, last, lane, Ic, SL);
 }
 
-// One stage (all tiles with tx + ty + tz = s) of all octants and the active bins
+// One stage (all tiles with tx + ty + tz = s) of all octants (NOCT = 8) or of the
+// octants of the rays going up (NOCT = 4: octants 0 .. 3) and the active bins
 // f0 .. f0 + nfc - 1.
-template <typename Real, bool DFORM, int NQ, bool MULTI, int ORD>
+template <typename Real, bool DFORM, int NQ, bool MULTI, int ORD, int NOCT = 8>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int oct = blockIdx.x & 7;
-    const int item = blockIdx.x >> 3;
+    const int oct = blockIdx.x & (NOCT - 1);
+    const int item = blockIdx.x / NOCT;
     const int f = A.f0 + blockIdx.y;
     const int frozen = A.frozen[f];
     const int par = A.parity[f];
@@ -1319,9 +1320,21 @@ size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi, int order)
 template <typename Real, bool DFORM, int NQ, int ORD>
 static void launch_stage_ord(const SweepArgs<Real> &A, int waves, hipStream_t st)
 {
-    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
     const bool multi = A.R > waves;
     const size_t lds = sweep_lds_bytes((int)sizeof(Real), waves, NQ, multi, ORD);
+    if constexpr (NQ == 1 && ORD == 0) {
+        if (A.noct == 4) {
+            dim3 grid4((unsigned)A.stage_cnt * 4u, (unsigned)A.nfc);
+            if (multi)
+                hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, 1, true, 0, 4>), grid4, dim3(64 * waves), lds, st,
+                                   A);
+            else
+                hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, 1, false, 0, 4>), grid4, dim3(64 * waves), lds,
+                                   st, A);
+            return;
+        }
+    }
+    dim3 grid((unsigned)A.stage_cnt * 8u, (unsigned)A.nfc);
     if (multi)
         hipLaunchKernelGGL((sweep_stage_kernel<Real, DFORM, NQ, true, ORD>), grid, dim3(64 * waves), lds, st, A);
     else

@@ -140,3 +140,12 @@ def test_batch_and_server_argument_errors(rt):
     assert lib.rt_server_submit(None, None, ctypes.byref(o), None, None, ctypes.byref(t)) == rt.RT_E_INVALID
     assert lib.rt_server_create(0, -1, ctypes.byref(ctypes.c_void_p())) == rt.RT_E_INVALID
     assert lib.rt_status_string(rt.RT_E_BUSY) == b"busy"
+
+
+def test_gauss_seidel_argument_errors(rt):
+    """rt_ali_solve_gs checks its arguments before any device work."""
+    lib = rt.load()
+    o = rt.AliOpts(1e-6, 100, 0, 1, 0, 0)
+    st = rt.AliStats()
+    assert lib.rt_ali_solve_gs(None, ctypes.byref(o), None, None, ctypes.byref(st), None) == rt.RT_E_INVALID
+    assert lib.rt_ali_solve_gs(None, None, None, None, None, None) == rt.RT_E_INVALID
