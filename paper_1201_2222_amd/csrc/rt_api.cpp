@@ -291,6 +291,11 @@ struct rt_problem {
     // Gauss-Seidel ALI (allocated on first use)
     void *gs_planes = nullptr;         // Real [nf][nd][2][nx ny]
     void *gs_part = nullptr;           // Real [nd][nf][nx ny]
+    void *gs_coef = nullptr;           // Real [nf][ns][4][nx ny]
+    void *gs_gh = nullptr;             // Real [nf][ns][6][max(nx, ny)]
+    double *gs_ghS = nullptr;          // [nf][ns][2][max(nx, ny)]
+    void *gs_chi_t = nullptr;          // Real [nf][nz][nx][ny]
+    double *gs_S_t = nullptr;          // [nf][nz][nx][ny]
     int *d_gs_down = nullptr;          // [nd] rays going down, shallow ones first
     int gs_nd = 0, gs_ns = 0;
     int *h_flags = nullptr;            // pinned host copy of flags
@@ -1260,15 +1265,29 @@ rt_status gs_prepare(rt_problem *p)
     const int nd = (int)down.size();
     const size_t rs = p->f32 ? sizeof(float) : sizeof(double);
     const size_t pxy = (size_t)p->n[0] * p->n[1];
-    unsigned char *planes = nullptr, *part = nullptr;
+    unsigned char *planes = nullptr, *part = nullptr, *chi_t = nullptr;
+    double *S_t = nullptr;
     int *d_down = nullptr;
     rt_status s = dalloc(p, &planes, (size_t)p->nf * std::max(nd, 1) * 2 * pxy * rs);
     if (s == RT_OK) s = dalloc(p, &part, (size_t)std::max(nd, 1) * p->nf * pxy * rs);
+    if (s == RT_OK) s = dalloc(p, &chi_t, (size_t)p->nf * p->cells * rs);
+    if (s == RT_OK) s = dalloc(p, &S_t, (size_t)p->nf * p->cells);
+    unsigned char *coef = nullptr, *gh = nullptr;
+    const size_t nmax = (size_t)std::max(p->n[0], p->n[1]);
+    if (s == RT_OK) s = dalloc(p, &coef, (size_t)p->nf * std::max(ns, 1) * 4 * pxy * rs);
+    if (s == RT_OK) s = dalloc(p, &gh, (size_t)p->nf * std::max(ns, 1) * 6 * nmax * rs);
+    double *ghS = nullptr;
+    if (s == RT_OK) s = dalloc(p, &ghS, (size_t)p->nf * std::max(ns, 1) * 2 * nmax);
     if (s == RT_OK) s = dalloc(p, &d_down, (size_t)std::max(nd, 1));
     if (s != RT_OK) return s;
     if (nd > 0) HIP_TRY(hipMemcpy(d_down, down.data(), sizeof(int) * nd, hipMemcpyHostToDevice));
     p->gs_planes = planes;
     p->gs_part = part;
+    p->gs_chi_t = chi_t;
+    p->gs_coef = coef;
+    p->gs_gh = gh;
+    p->gs_ghS = ghS;
+    p->gs_S_t = S_t;
     p->d_gs_down = d_down;
     p->gs_nd = nd;
     p->gs_ns = ns;
@@ -1299,6 +1318,8 @@ GsArgs<Real> gs_args(rt_problem *p, double *S, double *J)
     else
         A.chi = p->chi64;
     A.S = S;
+    A.chi_t = static_cast<const Real *>(p->gs_chi_t);
+    A.S_t = p->gs_S_t;
     A.B = p->B;
     A.eps = p->eps;
     A.lam = p->lam;
@@ -1313,6 +1334,11 @@ GsArgs<Real> gs_args(rt_problem *p, double *S, double *J)
     A.nblk = kUpdateBlocks;
     A.tiles_x = (p->n[0] + kGsTile - 1) / kGsTile;
     A.ntiles = A.tiles_x * ((p->n[1] + kGsTile - 1) / kGsTile);
+    A.coef = static_cast<Real *>(p->gs_coef);
+    A.gh = static_cast<Real *>(p->gs_gh);
+    A.ghS = p->gs_ghS;
+    A.nmax = std::max(p->n[0], p->n[1]);
+    A.steep_blocks = ((A.nd - A.ns) * A.ntiles + 7) / 8 * 8;
     return A;
 }
 
@@ -1388,6 +1414,7 @@ rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inou
     if (p->persistent) return fail(RT_E_UNSUPPORTED, "Gauss-Seidel runs with the staged sweep schedule");
     if (p->n[0] > kGsMaxLanes || p->n[1] > kGsMaxLanes)
         return fail(RT_E_UNSUPPORTED, "Gauss-Seidel needs nx and ny <= %d", kGsMaxLanes);
+    if (p->na / 2 > kGsMaxDown) return fail(RT_E_UNSUPPORTED, "Gauss-Seidel takes at most %d rays", 2 * kGsMaxDown);
     rt_status s = gs_prepare(p);
     if (s != RT_OK) return s;
     return ali_run(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, true);
@@ -1403,6 +1430,14 @@ rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, doubl
     {
         rt_status s0 = ali_start(p, opts, S_inout, J_out, st);
         if (s0 != RT_OK) return s0;
+    }
+    if (gs) {
+        // y-fastest copies of chi and of the start S for the chains along x
+        if (p->f32)
+            HIP_TRY(launch_gs_transpose<float>(p->chi32, static_cast<float *>(p->gs_chi_t), p->nf, p->n, st));
+        else
+            HIP_TRY(launch_gs_transpose<double>(p->chi64, static_cast<double *>(p->gs_chi_t), p->nf, p->n, st));
+        HIP_TRY(launch_gs_transpose<double>(S_inout, p->gs_S_t, p->nf, p->n, st));
     }
 
     const bool fixed = opts->fixed_iters > 0;

@@ -17,16 +17,17 @@
 // one halo row and column on the upwind side, then plane ko on the tile.  A ray that
 // crosses an x or y face first ("shallow", axis d) also depends on the previous
 // vertex of its own plane along d, one vertex apart along the other in-plane axis e
-// at most: it runs as a chain along d, one workgroup per ray and bin.  Per vertex
+// at most: it runs as a chain along d, one wave per ray and bin.  Per vertex
 //   I_kn = E_n (w0 x + w1 y) + Q_n,   I_ko = E_o (w0 u + w1 v + w2 x + w3 y) + Q_o,
 // with x, y (u, v) the chain's values on the previous column at e and at the upwind
 // neighbour along e on plane kn (ko), and w the bilinear weights of the upwind face
 // (along e, then z).  E and Q (the plane-above and source terms) do not depend on the
-// chain: fifteen waves of the workgroup compute them for the next block of columns
-// into LDS while wave 0 runs the recurrence over the current block; the values of the
-// neighbour along e come from the next lane (a shuffle).  Ghost vertices (outside the
-// grid) enter as constants: folded into Q above the grid, and as the starting column
-// and the upwind neighbour of the lane at the grid's face along e.
+// chain: they are computed for every vertex of every chain in parallel, in the launch
+// of the steep tiles, and the chain's wave streams them a few columns ahead of its
+// step; the values of the neighbour along e come from the next lane (a shuffle).
+// Ghost vertices (outside the grid) enter as constants: folded into Q above the grid,
+// and as the starting column and the upwind neighbour of the lane at the grid's face
+// along e.
 //
 // The FP32 path carries D = I - S (D0 = D- E + (S- - S0) g with S- - S0 formed in
 // FP64); the periodic memory keeps I in FP64 in the layout of the sweep kernels (the
@@ -44,8 +45,6 @@ namespace {
 constexpr int GT = kGsTile;
 constexpr int GH = GT + 1;            // steep tile plus one vertex on the upwind side
 constexpr int GHN = GH * GH;
-constexpr int CHAIN_WAVES = 16;       // wave 0 runs the recurrence, the others fill blocks
-constexpr int CHAIN_MAX_COLS = 16;
 
 __device__ __forceinline__ int flip(int r, int sg, int n) { return sg > 0 ? r : n - 1 - r; }
 
@@ -145,17 +144,15 @@ __device__ __forceinline__ void store_wrap(const GsArgs<Real> &A, int f, int ray
 // Steep rays: one (ray, tile, bin) per workgroup of 256 lanes.
 // ---------------------------------------------------------------------------------
 template <typename Real, bool DFORM>
-__global__ void __launch_bounds__(256) gs_steep_kernel(GsArgs<Real> A, int t)
+__device__ __forceinline__ void steep_tile(const GsArgs<Real> &A, int f, int item, int t)
 {
     __shared__ Real Iw[GHN];
     __shared__ Real Cw[GHN];
     __shared__ double Sw[GHN];
-    const int f = blockIdx.y;
-    if (A.frozen[f]) return;
     const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
     const int kn = nz - t, ko = nz - 1 - t;
-    const int di = A.ns + (int)blockIdx.x / A.ntiles;
-    const int tile = (int)blockIdx.x % A.ntiles;
+    const int di = A.ns + item / A.ntiles;
+    const int tile = item % A.ntiles;
     const int ray = A.down[di];
     const RayGeo &G = A.rays[ray];
     const int sx = (G.oct & 1) ? -1 : 1, sy = (G.oct & 2) ? -1 : 1;
@@ -239,21 +236,34 @@ __global__ void __launch_bounds__(256) gs_steep_kernel(GsArgs<Real> A, int t)
 }
 
 // ---------------------------------------------------------------------------------
-// Shallow rays: one chain (ray, bin) per workgroup of CHAIN_WAVES waves.
+// Shallow rays.  The coefficients of every vertex of planes kn and ko of every chain
+// are computed in parallel (with the steep tiles, in one launch); one wave per chain
+// then runs the recurrence, lanes along e, streaming the coefficients a few columns
+// ahead of the step.
 // ---------------------------------------------------------------------------------
 template <typename Real>
 struct Chain {
-    int f, di, ray, d, sd, se, Nd, Ne, nep, cols, t, kn, ko;
-    Real w0, w1, w2, w3, s_half, wk;
-    double w0d, w1d, w2d, w3d;
-    // LDS, per buffer: [4][cols][nep] coefficients E_n, Q_n, E_o, Q_o; [cols][nep] S of
-    // plane kn (the difference form's periodic memory keeps I = D + S); [cols] ghost
-    // neighbours along e of the boundary lane on planes kn and ko
-    double *s0[2];
-    Real *coef[2];
-    Real *gy[2], *gv[2];
-    Real *x0, *u0;   // [nep] the column before the first (ghosts) on planes kn and ko
+    int f, di, ray, d, e, sd, se, Nd, Ne, kn, ko;
 };
+
+template <typename Real>
+__device__ __forceinline__ Chain<Real> chain_of(const GsArgs<Real> &A, int f, int di, int t)
+{
+    Chain<Real> C;
+    C.f = f;
+    C.di = di;
+    C.ray = A.down[di];
+    const RayGeo &G = A.rays[C.ray];
+    C.d = G.d;
+    C.e = 1 - C.d;
+    C.sd = (G.oct >> C.d) & 1 ? -1 : 1;
+    C.se = (G.oct >> C.e) & 1 ? -1 : 1;
+    C.Nd = A.n[C.d];
+    C.Ne = A.n[C.e];
+    C.kn = A.n[2] - t;
+    C.ko = A.n[2] - 1 - t;
+    return C;
+}
 
 template <typename Real>
 __device__ __forceinline__ void chain_xy(const Chain<Real> &C, int pd, int pe, int &x, int &y)
@@ -262,220 +272,287 @@ __device__ __forceinline__ void chain_xy(const Chain<Real> &C, int pd, int pe, i
     y = C.d == 0 ? pe : pd;
 }
 
-// Coefficients of the columns c0 .. c0 + cols - 1 into buffer `buf`.
+// Index of (pd, pe, z) in the chain's own ordering of chi and S: [z][pd][pe], which is
+// the grid layout for chains along y and the y-fastest copy for chains along x.  pd
+// and pe may be one step outside (folded like any ghost vertex); z is clamped.
+template <typename Real>
+__device__ __forceinline__ int64_t ch_idx(const GsArgs<Real> &A, const Chain<Real> &C, int pd, int pe, int z)
+{
+    const int fd = fold(pd, C.Nd, A.periodic[C.d]), fe = fold(pe, C.Ne, A.periodic[C.e]);
+    const int fz = z < A.n[2] ? z : A.n[2] - 1;
+    return (int64_t)C.f * A.cells + ((int64_t)fz * C.Nd + fd) * C.Ne + fe;
+}
+
+// Coefficients of one vertex (pd, pe) of a chain, chain layout o = pd Ne + pe:
+// E_n, Q_n (plane kn), E_o, Q_o (plane ko).  The vertex in the first column (pd = 0)
+// also writes the column before the first (ghosts) at its pe; the vertex at pe = 0
+// writes the ghost neighbours along e of the boundary lane for its column.
 template <typename Real, bool DFORM>
-__device__ void chain_fill(const GsArgs<Real> &A, const Chain<Real> &C, int buf, int c0, int tid, int nthr)
+__device__ __forceinline__ void chain_coef(const GsArgs<Real> &A, const Chain<Real> &C, int64_t v, int t)
 {
     const int nz = A.n[2];
     const int kn = C.kn, ko = C.ko;
-    const int64_t slot = (int64_t)C.cols * C.nep;
-    Real *cf = C.coef[buf];
-    const Real *above = A.planes + (((int64_t)C.f * A.nd + C.di) * 2 + ((kn + 1) & 1)) * A.pxy;
-    for (int it = tid; it < C.cols * C.nep; it += nthr) {
-        const int cc = it / C.nep, pe = it - cc * C.nep;
-        const int c = c0 + cc;
-        Real En = Real(0), Qn = Real(0), Eo = Real(0), Qo = Real(0);
-        double s0 = 0.0;
-        if (c < C.Nd && pe < C.Ne) {
-            const int pd = C.sd > 0 ? c : C.Nd - 1 - c;
-            const int ud = pd - C.sd, ue = pe - C.se;
-            int x, y, xu, yu, xv, yv;
-            chain_xy(C, pd, pe, x, y);
+    const RayGeo &G = A.rays[C.ray];
+    const Real s_half = Real(0.5 * G.s);
+    const Real w0 = Real(G.w4[0]), w1 = Real(G.w4[1]), w2 = Real(G.w4[2]), w3 = Real(G.w4[3]);
+    const double w0d = G.w4[0], w1d = G.w4[1], w2d = G.w4[2], w3d = G.w4[3];
+    const Real *chi = C.d == 0 ? A.chi_t : A.chi;
+    const double *S = C.d == 0 ? A.S_t : A.S;
+    const int pd = (int)(v / C.Ne), pe = (int)(v - (int64_t)pd * C.Ne);
+    const int ud = pd - C.sd, ue = pe - C.se;
+    Real En = Real(0), Qn = Real(0), Eo = Real(0), Qo = Real(0);
+    if (t == 0) {
+        // the plane above the grid stands in for plane kn
+        int x, y;
+        chain_xy(C, pd, pe, x, y);
+        Qn = ghost_val<Real, DFORM>(A, C.f, C.ray, x, y, nz);
+    } else {
+        // upwind face corners along (e, z): (0, 0) (1, 0) in plane kn, (0, 1) (1, 1) above
+        const Real *above = A.planes + (((int64_t)C.f * A.nd + C.di) * 2 + ((kn + 1) & 1)) * A.pxy;
+        const int64_t cu = ch_idx(A, C, ud, pe, kn), cv = ch_idx(A, C, ud, ue, kn);
+        const int64_t cu1 = ch_idx(A, C, ud, pe, kn + 1), cv1 = ch_idx(A, C, ud, ue, kn + 1);
+        const int64_t c0v = ch_idx(A, C, pd, pe, kn);
+        const bool in_u = kn + 1 < nz && ud >= 0 && ud < C.Nd;
+        const bool in_v = in_u && ue >= 0 && ue < C.Ne;
+        Real Iu1, Iv1;
+        if (in_v) {
+            Iu1 = above[(int64_t)ud * C.Ne + pe];
+            Iv1 = above[(int64_t)ud * C.Ne + ue];
+        } else {
+            int xu, yu, xv, yv;
             chain_xy(C, ud, pe, xu, yu);
             chain_xy(C, ud, ue, xv, yv);
-            const int64_t cu = cell_of(A, C.f, xu, yu, kn), cv = cell_of(A, C.f, xv, yv, kn);
-            if (C.t == 0) {
-                // the plane above the grid stands in for plane kn
-                Qn = ghost_val<Real, DFORM>(A, C.f, C.ray, x, y, nz);
-            } else {
-                // upwind face corners along (e, z): (0, 0) (1, 0) in plane kn, (0, 1) (1, 1) above
-                const int64_t cu1 = cell_of(A, C.f, xu, yu, kn + 1), cv1 = cell_of(A, C.f, xv, yv, kn + 1);
-                const int64_t c0v = cell_of(A, C.f, x, y, kn);
-                const bool in_u = kn + 1 < nz && ud >= 0 && ud < C.Nd;
-                const bool in_v = in_u && ue >= 0 && ue < C.Ne;
-                const Real Iu1 = in_u ? above[(int64_t)ud * C.Ne + pe] : ghost_val<Real, DFORM>(A, C.f, C.ray, xu, yu, kn + 1);
-                const Real Iv1 = in_v ? above[(int64_t)ud * C.Ne + ue] : ghost_val<Real, DFORM>(A, C.f, C.ray, xv, yv, kn + 1);
-                const Real Cm = C.w0 * A.chi[cu] + C.w1 * A.chi[cv] + C.w2 * A.chi[cu1] + C.w3 * A.chi[cv1];
-                const double Sm = C.w0d * A.S[cu] + C.w1d * A.S[cv] + C.w2d * A.S[cu1] + C.w3d * A.S[cv1];
-                Real E, src;
-                segment<Real, DFORM>(C.s_half, Cm, A.chi[c0v], Sm, A.S[c0v], E, src);
-                En = E;
-                Qn = E * (C.w2 * Iu1 + C.w3 * Iv1) + src;
-                s0 = A.S[c0v];
-            }
-            if (ko >= 0) {
-                const int64_t du = cell_of(A, C.f, xu, yu, ko), dv = cell_of(A, C.f, xv, yv, ko);
-                const int64_t c0o = cell_of(A, C.f, x, y, ko);
-                const Real Cm = C.w0 * A.chi[du] + C.w1 * A.chi[dv] + C.w2 * A.chi[cu] + C.w3 * A.chi[cv];
-                const double Sm = C.w0d * A.S[du] + C.w1d * A.S[dv] + C.w2d * A.S[cu] + C.w3d * A.S[cv];
-                segment<Real, DFORM>(C.s_half, Cm, A.chi[c0o], Sm, A.S[c0o], Eo, Qo);
-            }
+            Iu1 = in_u ? above[(int64_t)ud * C.Ne + pe] : ghost_val<Real, DFORM>(A, C.f, C.ray, xu, yu, kn + 1);
+            Iv1 = ghost_val<Real, DFORM>(A, C.f, C.ray, xv, yv, kn + 1);
         }
-        cf[0 * slot + it] = En;
-        cf[1 * slot + it] = Qn;
-        cf[2 * slot + it] = Eo;
-        cf[3 * slot + it] = Qo;
-        if constexpr (DFORM) C.s0[buf][it] = s0;
+        const Real Cm = w0 * chi[cu] + w1 * chi[cv] + w2 * chi[cu1] + w3 * chi[cv1];
+        const double Sm = w0d * S[cu] + w1d * S[cv] + w2d * S[cu1] + w3d * S[cv1];
+        Real E, src;
+        segment<Real, DFORM>(s_half, Cm, chi[c0v], Sm, S[c0v], E, src);
+        En = E;
+        Qn = E * (w2 * Iu1 + w3 * Iv1) + src;
     }
-    // the boundary lane's upwind neighbour along e lies outside the grid
-    for (int cc = tid; cc < C.cols; cc += nthr) {
-        const int c = c0 + cc;
-        Real gy = Real(0), gv = Real(0);
-        if (c < C.Nd) {
-            const int pd = C.sd > 0 ? c : C.Nd - 1 - c;
-            const int pb = C.se > 0 ? 0 : C.Ne - 1;
-            int xv, yv;
-            chain_xy(C, pd - C.sd, pb - C.se, xv, yv);
-            gy = ghost_val<Real, DFORM>(A, C.f, C.ray, xv, yv, kn);
-            if (ko >= 0) gv = ghost_val<Real, DFORM>(A, C.f, C.ray, xv, yv, ko);
-        }
-        C.gy[buf][cc] = gy;
-        C.gv[buf][cc] = gv;
+    if (ko >= 0) {
+        const int64_t du = ch_idx(A, C, ud, pe, ko), dv = ch_idx(A, C, ud, ue, ko);
+        const int64_t cu = ch_idx(A, C, ud, pe, ko + 1), cv = ch_idx(A, C, ud, ue, ko + 1);
+        const int64_t c0o = ch_idx(A, C, pd, pe, ko);
+        const Real Cm = w0 * chi[du] + w1 * chi[dv] + w2 * chi[cu] + w3 * chi[cv];
+        const double Sm = w0d * S[du] + w1d * S[dv] + w2d * S[cu] + w3d * S[cv];
+        segment<Real, DFORM>(s_half, Cm, chi[c0o], Sm, S[c0o], Eo, Qo);
+    }
+    Real *cf = A.coef + (((int64_t)C.f * A.ns + C.di) * A.pxy + v) * 4;
+    cf[0] = En;
+    cf[1] = Qn;
+    cf[2] = Eo;
+    cf[3] = Qo;
+    Real *gh = A.gh + ((int64_t)C.f * A.ns + C.di) * 6 * A.nmax;
+    if (DFORM && t > 0) {
+        // S where the chain writes the periodic memory (I = D + S): the outgoing face
+        // along e (per column) and the last column (per pe)
+        const int64_t c0v = ch_idx(A, C, pd, pe, kn);
+        const double *S = C.d == 0 ? A.S_t : A.S;
+        if (pe == (C.se > 0 ? C.Ne - 1 : 0)) reinterpret_cast<double *>(A.ghS)[((int64_t)C.f * A.ns + C.di) * 2 * A.nmax + pd] = S[c0v];
+        if (pd == (C.sd > 0 ? C.Nd - 1 : 0)) reinterpret_cast<double *>(A.ghS)[((int64_t)C.f * A.ns + C.di) * 2 * A.nmax + A.nmax + pe] = S[c0v];
+    }
+    if (pe == 0) {
+        // the boundary lane's upwind neighbour along e lies outside the grid
+        const int pb = C.se > 0 ? 0 : C.Ne - 1;
+        int xv, yv;
+        chain_xy(C, ud, pb - C.se, xv, yv);
+        gh[pd] = ghost_val<Real, DFORM>(A, C.f, C.ray, xv, yv, kn);
+        gh[A.nmax + pd] = ko >= 0 ? ghost_val<Real, DFORM>(A, C.f, C.ray, xv, yv, ko) : Real(0);
+    }
+    if (pd == 0) {
+        // the column before the first along d
+        int x, y;
+        chain_xy(C, C.sd > 0 ? -1 : C.Nd, pe, x, y);
+        gh[2 * A.nmax + pe] = ghost_val<Real, DFORM>(A, C.f, C.ray, x, y, kn);
+        gh[3 * A.nmax + pe] = ko >= 0 ? ghost_val<Real, DFORM>(A, C.f, C.ray, x, y, ko) : Real(0);
     }
 }
 
-template <typename Real, bool DFORM, int M>
-__global__ void __launch_bounds__(64 * CHAIN_WAVES) gs_chain_kernel(GsArgs<Real> A, int t, int cols)
+// Launch t, first part: the steep tiles, then the chain coefficients.
+template <typename Real, bool DFORM>
+__global__ void __launch_bounds__(256) gs_prep_kernel(GsArgs<Real> A, int t)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int f = blockIdx.y;
     if (A.frozen[f]) return;
-    Chain<Real> C;
-    C.f = f;
-    C.di = blockIdx.x;
-    C.ray = A.down[C.di];
+    if ((int)blockIdx.x < A.steep_blocks) {
+        if ((int)blockIdx.x < (A.nd - A.ns) * A.ntiles) steep_tile<Real, DFORM>(A, f, blockIdx.x, t);
+        return;
+    }
+    // Workgroups are dealt to the 8 XCDs in turn: coefficient block j goes to XCD
+    // j % 8 (steep_blocks is a multiple of 8), and serves a chain di with di % 8 equal
+    // to it, whose wave (block di of the chain launch) runs on the same XCD and reads
+    // the coefficients from that XCD's L2.
+    const int j = (int)blockIdx.x - A.steep_blocks;
+    const int q = j & 7, r = j >> 3;
+    const int cb = (int)((A.pxy + 255) / 256);            // blocks per chain
+    const int di = q + 8 * (r / cb);
+    if (di >= A.ns) return;
+    const int64_t v = (int64_t)(r % cb) * 256 + threadIdx.x;
+    if (v >= A.pxy) return;
+    chain_coef<Real, DFORM>(A, chain_of(A, f, di, t), v, t);
+}
+
+// Launch t, second part: one wave per chain (ray, bin).  Lane l holds the M vertices
+// pe = l M .. l M + M - 1 of the current column; the upwind neighbour along e of the
+// first (se > 0) or last (se < 0) of them is in the next lane.  The columns are taken
+// in groups of P: the coefficients of the next group are loaded at the start of a
+// group, so the wait for them at the group's end finds loads issued P steps before.
+template <typename Real, bool DFORM, int M>
+__global__ void __launch_bounds__(64) gs_chain_kernel(GsArgs<Real> A, int t)
+{
+    constexpr int P = (sizeof(Real) == 4 ? 16 : 8) / M;
+    const int f = blockIdx.y;
+    if (A.frozen[f]) return;
+    const Chain<Real> C = chain_of(A, f, blockIdx.x, t);
     const RayGeo &G = A.rays[C.ray];
-    C.d = G.d;
-    const int e = 1 - C.d;
-    C.sd = (G.oct >> C.d) & 1 ? -1 : 1;
-    C.se = (G.oct >> e) & 1 ? -1 : 1;
-    C.Nd = A.n[C.d];
-    C.Ne = A.n[e];
-    C.nep = 64 * M;
-    C.cols = cols;
-    C.t = t;
-    C.kn = A.n[2] - t;
-    C.ko = A.n[2] - 1 - t;
-    C.w0 = Real(G.w4[0]);
-    C.w1 = Real(G.w4[1]);
-    C.w2 = Real(G.w4[2]);
-    C.w3 = Real(G.w4[3]);
-    C.w0d = G.w4[0];
-    C.w1d = G.w4[1];
-    C.w2d = G.w4[2];
-    C.w3d = G.w4[3];
-    C.s_half = Real(0.5 * G.s);
-    C.wk = Real(G.wk);
-    {
-        const int64_t slot = (int64_t)cols * C.nep;
-        unsigned char *p = lds_raw;
-        for (int b = 0; b < 2; ++b) {
-            C.s0[b] = reinterpret_cast<double *>(p);
-            p += DFORM ? slot * sizeof(double) : 0;
-        }
-        for (int b = 0; b < 2; ++b) {
-            C.coef[b] = reinterpret_cast<Real *>(p);
-            p += 4 * slot * sizeof(Real);
-        }
-        for (int b = 0; b < 2; ++b) {
-            C.gy[b] = reinterpret_cast<Real *>(p);
-            p += cols * sizeof(Real);
-            C.gv[b] = reinterpret_cast<Real *>(p);
-            p += cols * sizeof(Real);
-        }
-        C.x0 = reinterpret_cast<Real *>(p);
-        p += C.nep * sizeof(Real);
-        C.u0 = reinterpret_cast<Real *>(p);
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-
-    // prologue: block 0 and the column before the first
-    chain_fill<Real, DFORM>(A, C, 0, 0, threadIdx.x, blockDim.x);
-    for (int pe = threadIdx.x; pe < C.nep; pe += blockDim.x) {
-        Real x0 = Real(0), u0 = Real(0);
-        if (pe < C.Ne) {
-            const int ud = C.sd > 0 ? -1 : C.Nd;
-            int x, y;
-            chain_xy(C, ud, pe, x, y);
-            x0 = ghost_val<Real, DFORM>(A, f, C.ray, x, y, C.kn);
-            if (C.ko >= 0) u0 = ghost_val<Real, DFORM>(A, f, C.ray, x, y, C.ko);
-        }
-        C.x0[pe] = x0;
-        C.u0[pe] = u0;
-    }
-    __syncthreads();
-
-    Real xr[M], ur[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        xr[m] = C.x0[lane * M + m];
-        ur[m] = C.u0[lane * M + m];
-    }
+    const Real w0 = Real(G.w4[0]), w1 = Real(G.w4[1]), w2 = Real(G.w4[2]), w3 = Real(G.w4[3]);
+    const Real wk = Real(G.wk);
+    const int lane = threadIdx.x;
+    const Real *cf = A.coef + ((int64_t)f * A.ns + C.di) * A.pxy * 4;
+    const Real *gh = A.gh + ((int64_t)f * A.ns + C.di) * 6 * A.nmax;
+    const double *ghS = reinterpret_cast<const double *>(A.ghS) + ((int64_t)f * A.ns + C.di) * 2 * A.nmax;
     Real *plane_n = A.planes + (((int64_t)f * A.nd + C.di) * 2 + (C.kn & 1)) * A.pxy;
     Real *part = A.part + ((int64_t)C.di * A.nf + f) * A.pxy;
-    const int nb = (C.Nd + cols - 1) / cols;
-    const int64_t slot = (int64_t)cols * C.nep;
-    for (int b = 0; b < nb; ++b) {
-        if (wave == 0) {
-            const int buf = b & 1;
-            const Real *cf = C.coef[buf];
-            for (int cc = 0; cc < cols; ++cc) {
-                const int c = b * cols + cc;
-                if (c >= C.Nd) break;   // uniform over the wave
-                const int pd = C.sd > 0 ? c : C.Nd - 1 - c;
-                const Real gy = C.gy[buf][cc], gv = C.gv[buf][cc];
-                // neighbours along e from the next lane: its first (se < 0) or last
-                // (se > 0) value
-                const Real sx = C.se > 0 ? __shfl_up(xr[M - 1], 1) : __shfl_down(xr[0], 1);
-                const Real su = C.se > 0 ? __shfl_up(ur[M - 1], 1) : __shfl_down(ur[0], 1);
-                Real xn[M], un[M];
+    const bool do_plane = t > 0, do_part = C.ko >= 0;
+    // periodic memory written by the chain (final values of plane kn): on the outgoing
+    // face along e one vertex per column (plane normal to e, index fz N_d + flipped d,
+    // which is the step c), and on the last column every vertex (plane normal to d,
+    // index fz N_e + flipped e)
+    const int par1 = A.parity[f] ^ 1;
+    const int64_t rb = ((int64_t)f * A.na + C.ray) * 2 + par1;
+    const int fz = flip(C.kn < A.n[2] ? C.kn : 0, -1, A.n[2]);   // rays going down: z flipped
+    const bool wrap_e = do_plane && A.periodic[C.e] != 0, wrap_d = do_plane && A.periodic[C.d] != 0;
+    double *we = wrap_e ? A.wrap[C.e] + rb * ((int64_t)C.Nd * A.n[2]) + (int64_t)fz * C.Nd : nullptr;
+    double *wd = wrap_d ? A.wrap[C.d] + rb * ((int64_t)C.Ne * A.n[2]) + (int64_t)fz * C.Ne : nullptr;
+    const int pe_out = C.se > 0 ? C.Ne - 1 : 0;    // the ray's outgoing face along e
+    int pe_m[M];
+    bool ok_m[M], out_m[M];
+    int fe_m[M];   // flipped coordinate along e
 #pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    const int pe = lane * M + m;
-                    Real y, v;
-                    if (C.se > 0) {
-                        y = m > 0 ? xr[m - 1] : sx;
-                        v = m > 0 ? ur[m - 1] : su;
-                        if (pe == 0) {
-                            y = gy;
-                            v = gv;
-                        }
-                    } else {
-                        y = m < M - 1 ? xr[m + 1] : sx;
-                        v = m < M - 1 ? ur[m + 1] : su;
-                        if (pe == C.Ne - 1) {
-                            y = gy;
-                            v = gv;
-                        }
-                    }
-                    const int o = cc * C.nep + pe;
-                    const Real En = cf[o], Qn = cf[slot + o], Eo = cf[2 * slot + o], Qo = cf[3 * slot + o];
-                    xn[m] = En * (C.w0 * xr[m] + C.w1 * y) + Qn;
-                    un[m] = Eo * (C.w0 * ur[m] + C.w1 * v + C.w2 * xr[m] + C.w3 * y) + Qo;
+    for (int m = 0; m < M; ++m) {
+        pe_m[m] = lane * M + m;
+        ok_m[m] = pe_m[m] < C.Ne;
+        out_m[m] = wrap_e && pe_m[m] == pe_out;
+        fe_m[m] = C.se > 0 ? pe_m[m] : C.Ne - 1 - pe_m[m];
+    }
+    // the lane holding the neighbour of this lane's boundary vertex, and which vertex
+    const int src = C.se > 0 ? lane - 1 : lane + 1;
+    const bool first_is_nb = C.se < 0;   // the next lane's first vertex (se < 0) or last
+    Real xr[M], ur[M];
+    double sl[M];   // S on the last column (difference form, periodic d)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int pe = ok_m[m] ? pe_m[m] : 0;
+        xr[m] = ok_m[m] ? gh[2 * A.nmax + pe] : Real(0);
+        ur[m] = ok_m[m] ? gh[3 * A.nmax + pe] : Real(0);
+        sl[m] = (DFORM && do_plane) ? ghS[A.nmax + pe] : 0.0;
+    }
+    // per-column values (ghost neighbours of the boundary lane, S on the outgoing face
+    // along e) staged in LDS
+    __shared__ Real s_gy[kGsMaxLanes], s_gv[kGsMaxLanes];
+    __shared__ double s_Se[kGsMaxLanes];
+    for (int k = lane; k < C.Nd; k += 64) {
+        s_gy[k] = gh[k];
+        s_gv[k] = gh[A.nmax + k];
+        s_Se[k] = (DFORM && do_plane) ? ghS[k] : 0.0;
+    }
+    __syncthreads();
+    Real aEn[P][M], aQn[P][M], aEo[P][M], aQo[P][M];
+    Real bEn[P][M], bQn[P][M], bEo[P][M], bQo[P][M];
+    auto fetch = [&](int c, Real (&En)[M], Real (&Qn)[M], Real (&Eo)[M], Real (&Qo)[M]) {
+        const int cc = c < C.Nd ? c : C.Nd - 1;      // past the end: any valid column
+        const int pd = C.sd > 0 ? cc : C.Nd - 1 - cc;
+        const int64_t ob = (int64_t)pd * C.Ne;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int64_t o = ob + (ok_m[m] ? pe_m[m] : 0);
+            if constexpr (sizeof(Real) == 4) {
+                const float4 q4 = *reinterpret_cast<const float4 *>(cf + o * 4);
+                En[m] = q4.x;
+                Qn[m] = q4.y;
+                Eo[m] = q4.z;
+                Qo[m] = q4.w;
+            } else {
+                const double2 a2 = *reinterpret_cast<const double2 *>(cf + o * 4);
+                const double2 b2 = *reinterpret_cast<const double2 *>(cf + o * 4 + 2);
+                En[m] = a2.x;
+                Qn[m] = a2.y;
+                Eo[m] = b2.x;
+                Qo[m] = b2.y;
+            }
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < P; ++j) fetch(j, aEn[j], aQn[j], aEo[j], aQo[j]);
+    for (int c0 = 0; c0 < C.Nd; c0 += P) {
+        // the next group's coefficients first
+#pragma unroll
+        for (int j = 0; j < P; ++j) fetch(c0 + P + j, bEn[j], bQn[j], bEo[j], bQo[j]);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int c = c0 + j;
+            const int cc = c < C.Nd ? c : C.Nd - 1;
+            const int pd = C.sd > 0 ? cc : C.Nd - 1 - cc;
+            const Real gy = s_gy[pd], gv = s_gv[pd];
+            // the neighbour along e of this lane's boundary vertex, from the next lane
+            const Real sx = __shfl(first_is_nb ? xr[0] : xr[M - 1], src);
+            const Real su = __shfl(first_is_nb ? ur[0] : ur[M - 1], src);
+            Real xn[M], un[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                Real y, v;
+                if (M == 1) {
+                    y = sx;
+                    v = su;
+                } else if (m == 0) {
+                    y = first_is_nb ? xr[1] : sx;
+                    v = first_is_nb ? ur[1] : su;
+                } else if (m == M - 1) {
+                    y = first_is_nb ? sx : xr[M - 2];
+                    v = first_is_nb ? su : ur[M - 2];
+                } else {
+                    y = first_is_nb ? xr[m + 1] : xr[m - 1];
+                    v = first_is_nb ? ur[m + 1] : ur[m - 1];
                 }
+                // the vertex at the grid's face along e takes the ghost neighbour
+                const bool edge = pe_m[m] == (C.se > 0 ? 0 : C.Ne - 1);
+                y = edge ? gy : y;
+                v = edge ? gv : v;
+                xn[m] = aEn[j][m] * (w0 * xr[m] + w1 * y) + aQn[j][m];
+                un[m] = aEo[j][m] * (w0 * ur[m] + w1 * v + w2 * xr[m] + w3 * y) + aQo[j][m];
+            }
+            if (c < C.Nd) {   // uniform over the wave
+                const int64_t ob = (int64_t)pd * C.Ne;
+                const double se_S = s_Se[pd];
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
-                    const int pe = lane * M + m;
-                    if (pe < C.Ne) {
-                        const int64_t o = (int64_t)pd * C.Ne + pe;
-                        if (t > 0) {
-                            plane_n[o] = xn[m];
-                            int x, y;
-                            chain_xy(C, pd, pe, x, y);
-                            double I = double(xn[m]);
-                            if constexpr (DFORM) I += C.s0[buf][cc * C.nep + pe];
-                            store_wrap(A, f, C.ray, x, y, C.kn, I);
-                        }
-                        if (C.ko >= 0) part[o] = C.wk * un[m];
-                    }
-                    xr[m] = xn[m];
-                    ur[m] = un[m];
+                    if (!ok_m[m]) continue;
+                    const int64_t o = ob + pe_m[m];
+                    if (do_plane) plane_n[o] = xn[m];
+                    if (do_part) part[o] = wk * un[m];
+                    if (out_m[m]) we[c] = double(xn[m]) + (DFORM ? se_S : 0.0);
+                    if (wrap_d && c == C.Nd - 1) wd[fe_m[m]] = double(xn[m]) + (DFORM ? sl[m] : 0.0);
                 }
             }
-        } else if (b + 1 < nb) {
-            chain_fill<Real, DFORM>(A, C, (b + 1) & 1, (b + 1) * cols, threadIdx.x - 64, blockDim.x - 64);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                xr[m] = xn[m];
+                ur[m] = un[m];
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                aEn[j][m] = bEn[j][m];
+                aQn[j][m] = bQn[j][m];
+                aEo[j][m] = bEo[j][m];
+                aQo[j][m] = bQo[j][m];
+            }
+        }
     }
 }
 
@@ -496,22 +573,26 @@ template <typename Real, bool DFORM>
 __global__ void __launch_bounds__(256) gs_update_kernel(GsArgs<Real> A, int k)
 {
     __shared__ unsigned long long red[4];
+    __shared__ unsigned char xchain[kGsMaxDown];   // ray di runs as a chain along x
     const int f = blockIdx.y;
     if (A.frozen[f]) return;
+    for (int di = threadIdx.x; di < A.nd; di += 256) xchain[di] = A.rays[A.down[di]].d == 0;
+    __syncthreads();
     const int nx = A.n[0], ny = A.n[1];
     const int64_t stride_up = (int64_t)A.nf * A.cells;
     unsigned long long rb = 0ull;
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < A.pxy; p += (int64_t)gridDim.x * 256) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < A.pxy) {
         const int x = (int)(p % nx), y = (int)(p / nx);
         const int64_t i = (int64_t)f * A.cells + (int64_t)k * A.pxy + p;
+        const int64_t px = (int64_t)x * ny + y;   // chains along x keep the plane y fastest
+        const Real *pp = A.part + (int64_t)f * A.pxy;
+        const int64_t pstride = (int64_t)A.nf * A.pxy;
         double sum = 0.0;
 #pragma unroll
         for (int o = 0; o < 4; ++o) sum += (double)A.part_up[o * stride_up + i];
-        for (int di = 0; di < A.nd; ++di) {
-            // chains along x keep the plane with y fastest
-            const int64_t idx = A.rays[A.down[di]].d == 0 ? (int64_t)x * ny + y : p;
-            sum += (double)A.part[((int64_t)di * A.nf + f) * A.pxy + idx];
-        }
+#pragma unroll 8
+        for (int di = 0; di < A.nd; ++di) sum += (double)pp[di * pstride + (xchain[di] ? px : p)];
         const double S = A.S[i], e = A.eps[i];
         double num;
         if constexpr (DFORM) {
@@ -524,9 +605,9 @@ __global__ void __launch_bounds__(256) gs_update_kernel(GsArgs<Real> A, int k)
         const double dS = num / (1.0 - (1.0 - e) * A.lam[i]);
         const double Sn = S + dS;
         A.S[i] = Sn;
+        A.S_t[(int64_t)f * A.cells + (int64_t)k * A.pxy + px] = Sn;
         const double r = (Sn != 0.0) ? fabs(dS) / fabs(Sn) : 0.0;
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(r);
-        rb = bits > rb ? bits : rb;
+        rb = (unsigned long long)__double_as_longlong(r);
     }
     rb = wave_max_bits(rb);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rb;
@@ -539,36 +620,30 @@ __global__ void __launch_bounds__(256) gs_update_kernel(GsArgs<Real> A, int k)
     }
 }
 
+// [nf][nz][ny][nx] -> [nf][nz][nx][ny] through a 32 x 32 LDS tile (coalesced on both
+// sides); blockIdx.z runs over the bins and planes.
+template <typename T>
+__global__ void __launch_bounds__(256) gs_transpose_kernel(const T *src, T *dst, int nx, int ny)
+{
+    __shared__ T tile[32][33];
+    const int64_t base = (int64_t)blockIdx.z * nx * ny;
+    const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < 32; j += 8) {
+        const int x = x0 + tx, y = y0 + j;
+        if (x < nx && y < ny) tile[j][tx] = src[base + (int64_t)y * nx + x];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int y = y0 + tx, x = x0 + j;
+        if (x < nx && y < ny) dst[base + (int64_t)x * ny + y] = tile[tx][j];
+    }
+}
+
 __global__ void gs_clear_kernel(unsigned long long *p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
-}
-
-// Dynamic LDS of a chain workgroup with `cols` columns per block.
-template <typename Real, bool DFORM>
-size_t chain_lds(int nep, int cols)
-{
-    const size_t slot = (size_t)cols * nep;
-    return 2 * ((DFORM ? slot * sizeof(double) : 0) + 4 * slot * sizeof(Real) + 2 * cols * sizeof(Real)) +
-           2 * (size_t)nep * sizeof(Real);
-}
-
-template <typename Real, bool DFORM>
-int chain_cols(int nep)
-{
-    int cols = CHAIN_MAX_COLS;
-    while (cols > 1 && chain_lds<Real, DFORM>(nep, cols) > 64 * 1024) --cols;
-    return cols;
-}
-
-template <typename Real, bool DFORM, int M>
-void launch_chain(const GsArgs<Real> &A, int t, hipStream_t st)
-{
-    const int cols = chain_cols<Real, DFORM>(64 * M);
-    const size_t lds = chain_lds<Real, DFORM>(64 * M, cols);
-    hipLaunchKernelGGL((gs_chain_kernel<Real, DFORM, M>), dim3((unsigned)A.ns, (unsigned)A.nf),
-                       dim3(64 * CHAIN_WAVES), lds, st, A, t, cols);
 }
 
 }  // namespace
@@ -577,17 +652,20 @@ template <typename Real>
 hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st)
 {
     constexpr bool DF = sizeof(Real) == 4;
-    if (A.nd > A.ns)
-        hipLaunchKernelGGL((gs_steep_kernel<Real, DF>), dim3((unsigned)((A.nd - A.ns) * A.ntiles), (unsigned)A.nf),
-                           dim3(256), 0, st, A, t);
+    const int64_t cb = (A.pxy + 255) / 256;
+    const int64_t coef_blocks = A.ns > 0 ? 8 * ((A.ns + 7) / 8) * cb : 0;
+    const int64_t blocks = A.steep_blocks + coef_blocks;
+    if (blocks > 0)
+        hipLaunchKernelGGL((gs_prep_kernel<Real, DF>), dim3((unsigned)blocks, (unsigned)A.nf), dim3(256), 0, st, A, t);
     if (A.ns > 0) {
+        const dim3 grid((unsigned)A.ns, (unsigned)A.nf);
         const int ne = std::max(A.n[0], A.n[1]);
         if (ne <= 64)
-            launch_chain<Real, DF, 1>(A, t, st);
+            hipLaunchKernelGGL((gs_chain_kernel<Real, DF, 1>), grid, dim3(64), 0, st, A, t);
         else if (ne <= 128)
-            launch_chain<Real, DF, 2>(A, t, st);
+            hipLaunchKernelGGL((gs_chain_kernel<Real, DF, 2>), grid, dim3(64), 0, st, A, t);
         else
-            launch_chain<Real, DF, 4>(A, t, st);
+            hipLaunchKernelGGL((gs_chain_kernel<Real, DF, 4>), grid, dim3(64), 0, st, A, t);
     }
     return hipGetLastError();
 }
@@ -596,8 +674,8 @@ template <typename Real>
 hipError_t launch_gs_update(const GsArgs<Real> &A, int k, hipStream_t st)
 {
     constexpr bool DF = sizeof(Real) == 4;
-    const int64_t per = std::max<int64_t>(1, std::min<int64_t>(64, (A.pxy + 2047) / 2048));
-    hipLaunchKernelGGL((gs_update_kernel<Real, DF>), dim3((unsigned)per, (unsigned)A.nf), dim3(256), 0, st, A, k);
+    hipLaunchKernelGGL((gs_update_kernel<Real, DF>), dim3((unsigned)((A.pxy + 255) / 256), (unsigned)A.nf), dim3(256),
+                       0, st, A, k);
     return hipGetLastError();
 }
 
@@ -607,6 +685,17 @@ hipError_t launch_gs_clear(unsigned long long *blockmax, int64_t n, hipStream_t 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_gs_transpose(const T *src, T *dst, int nf, const int n[3], hipStream_t st)
+{
+    hipLaunchKernelGGL((gs_transpose_kernel<T>), dim3((unsigned)((n[0] + 31) / 32), (unsigned)((n[1] + 31) / 32),
+                                                     (unsigned)((int64_t)nf * n[2])),
+                       dim3(256), 0, st, src, dst, n[0], n[1]);
+    return hipGetLastError();
+}
+
+template hipError_t launch_gs_transpose<float>(const float *, float *, int, const int[3], hipStream_t);
+template hipError_t launch_gs_transpose<double>(const double *, double *, int, const int[3], hipStream_t);
 template hipError_t launch_gs_plane<float>(const GsArgs<float> &, int, hipStream_t);
 template hipError_t launch_gs_plane<double>(const GsArgs<double> &, int, hipStream_t);
 template hipError_t launch_gs_update<float>(const GsArgs<float> &, int, hipStream_t);

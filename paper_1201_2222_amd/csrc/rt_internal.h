@@ -103,8 +103,8 @@ struct PlaneArgs {
 // first-crossed axis d = x or y) depend on vertices of their own plane and run as a
 // chain along d in one workgroup, lanes along the other in-plane axis e.
 constexpr int kGsTile = 16;       // in-plane tile edge of a steep-ray workgroup
-constexpr int kGsChainCols = 4;   // columns (along d) per coefficient block of a chain
 constexpr int kGsMaxLanes = 256;  // largest extent along e of a chain (4 vertices per lane)
+constexpr int kGsMaxDown = 256;   // largest number of rays going down
 
 template <typename Real>
 struct GsArgs {
@@ -118,6 +118,8 @@ struct GsArgs {
     int nd, ns;                   // rays going down, shallow ones among them
     const Real *chi;              // [nf][cells]
     double *S;                    // [nf][cells] source function, updated plane by plane
+    const Real *chi_t;            // [nf][nz][nx][ny] chi with y fastest (chains along x)
+    double *S_t;                  // [nf][nz][nx][ny] S with y fastest, kept with S
     const double *B, *eps, *lam;  // [nf][cells]
     const double *fixed[6];       // FIXED faces (real coordinates), or null
     double *wrap[3];              // periodic memory, the layout of SweepArgs::wrap
@@ -125,6 +127,13 @@ struct GsArgs {
                                   // downward ray on plane k in slot k & 1; steep rays in
                                   // real layout (x fastest), shallow rays along e fastest
     Real *part;                   // [nd][nf][pxy] w I (w D) of the plane being computed
+    Real *coef;                   // [nf][ns][pxy][4] chain coefficients E_n, Q_n, E_o, Q_o
+    Real *gh;                     // [nf][ns][6][nmax] chain ghosts: boundary-lane neighbours
+                                  // on kn and ko per column, the column before the first
+    void *ghS;                    // double [nf][ns][2][nmax]: S on the chain's outgoing face
+                                  // along e (per column) and on its last column (per pe)
+    int nmax;                     // max(nx, ny)
+    int steep_blocks;             // workgroups of the steep tiles in a launch (a multiple of 8)
     const Real *part_up;          // [8][nf][cells] per-octant partials of the upward sweep
     double *J;                    // [nf][cells] the J each vertex was updated with
     const int *frozen;            // [nf]
@@ -235,6 +244,9 @@ hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st);
 template <typename Real>
 hipError_t launch_gs_update(const GsArgs<Real> &A, int k, hipStream_t st);
 hipError_t launch_gs_clear(unsigned long long *blockmax, int64_t n, hipStream_t st);
+// [nf][nz][ny][nx] -> [nf][nz][nx][ny]
+template <typename T>
+hipError_t launch_gs_transpose(const T *src, T *dst, int nf, const int n[3], hipStream_t st);
 
 hipError_t launch_ali_finalize(AliCtl ctl, int nf, double delta_c, int per_bin_stop, int fixed_mode,
                                hipStream_t st);
