@@ -13,7 +13,8 @@
  *     extrema appear);
  *   - the Jacobi accelerated Lambda iteration with the diagonal operator
  *     Lambda* (section 3.4, eq. dsjacobi) for S = (1 - eps) J + eps B
- *     (section 2, eq. sourcefunc), stopped by eq. conv;
+ *     (section 2, eq. sourcefunc), stopped by eq. conv, and its Gauss-Seidel form
+ *     (section 3.4, horizontal planes as the blocks of the ordering);
  *   - the moments J, H, K (section 3.2, eqs. Jsum/Hsum/Ksum), the variable
  *     Eddington tensor f = K/J and the heating rate Q_rad (section 4).
  *
@@ -217,6 +218,20 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
  */
 rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
                           rt_ali_stats *stats, void *stream);
+
+/*
+ * rt_problem_use_graphs -- rt_ali_solve and rt_ali_solve_gs run their iterations in
+ * chunks of check_every (the host reads the convergence flags between chunks).  With
+ * graphs enabled (the default) a chunk is captured once as a HIP graph on a stream of
+ * the problem's own and then replayed on the caller's stream; kernels of converged
+ * bins return at once, so a chunk that passes convergence costs little.  The captured
+ * launches are those of the eager path, in the same order with the same arguments, so
+ * results are bitwise the same either way.  A problem caches two graphs (the full chunk
+ * and a shorter last one) keyed by the S and J pointers and the stopping options; the
+ * one-time periodic initialisation and any sweep timed by rt_problem_profile run
+ * eagerly.  enable = 0 runs every launch from the host.  Host-only call.
+ */
+rt_status rt_problem_use_graphs(rt_problem *p, int32_t enable);
 
 /* Per-bin iteration counts and last residuals of the most recent rt_ali_solve
  * (host arrays [nf]; either may be NULL).  Synchronises the stream. */

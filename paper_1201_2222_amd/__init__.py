@@ -27,7 +27,7 @@ RT_INTERP_BILINEAR, RT_INTERP_QUADRATIC = 0, 1
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
-           "rt_ali_solve", "rt_ali_solve_gs", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
+           "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
            "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
            "rt_server_load", "rt_server_destroy")
 
@@ -95,6 +95,7 @@ def load():
     lib.rt_formal_solve.argtypes = [P, P, P, P, P]
     lib.rt_ali_solve.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_ali_solve_gs.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
+    lib.rt_problem_use_graphs.argtypes = [P, I32]
     lib.rt_ali_bin_stats.argtypes = [P, P, P, P]
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
     lib.rt_problem_profile.argtypes = [P, I32]
@@ -357,6 +358,9 @@ class Problem:
 
     def ali_solve_gs(self, S, J, **kw):
         return rt_ali_solve(self.handle, S, J, gauss_seidel=True, **kw)
+
+    def use_graphs(self, enable=True):
+        _check(load().rt_problem_use_graphs(self.handle, 1 if enable else 0))
 
     def moments(self, S, **kw):
         return rt_moments(self.handle, S, **kw)

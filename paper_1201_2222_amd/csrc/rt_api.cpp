@@ -301,6 +301,20 @@ struct rt_problem {
     int *h_flags = nullptr;            // pinned host copy of flags
     int *h_frozen = nullptr;           // pinned host copy of frozen
     std::vector<void *> allocs;
+    // ALI chunks captured as graphs (rt_problem_use_graphs); at most two cached: the
+    // full chunk and the last, shorter one
+    struct GraphEntry {
+        int k = 0;
+        bool gs = false;
+        const double *S = nullptr, *J = nullptr;
+        double delta_c = 0.0;
+        int per_bin_stop = 0, fixed = 0;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;  // capture stream (non-blocking, default priority)
+    std::vector<GraphEntry> graphs;
     // sweep-kernel timing (rt_problem_profile)
     bool prof = false;
     bool prof_pending = false;
@@ -1019,6 +1033,11 @@ rt_status rt_problem_destroy(rt_problem *p)
     if (p->h_sum) (void)hipHostFree(p->h_sum);
     if (p->h_frozen) (void)hipHostFree(p->h_frozen);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    for (auto &g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
     return RT_OK;
 }
@@ -1379,6 +1398,56 @@ rt_status gs_iteration(rt_problem *p, double *S, double *J, hipStream_t st)
 rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out, rt_ali_stats *stats,
                   hipStream_t st, std::chrono::steady_clock::time_point t0, bool gs);
 
+// The executable graph of a chunk of k iterations with these arguments: cached, or
+// captured from `body` on the problem's capture stream.  Capture always ends, also
+// when the body fails.
+template <typename Body>
+rt_status chunk_graph(rt_problem *p, int k, bool gs, const double *S, const double *J, double delta_c,
+                      int per_bin_stop, int fixed, Body body, hipGraphExec_t *out)
+{
+    for (auto &g : p->graphs)
+        if (g.k == k && g.gs == gs && g.S == S && g.J == J && g.delta_c == delta_c && g.per_bin_stop == per_bin_stop &&
+            g.fixed == fixed) {
+            *out = g.exec;
+            return RT_OK;
+        }
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const rt_status s = body(p->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (s != RT_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return s != RT_OK ? s : fail(RT_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(RT_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    if (p->graphs.size() >= 2) {
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        (void)hipGraphDestroy(p->graphs.front().graph);
+        p->graphs.erase(p->graphs.begin());
+    }
+    rt_problem::GraphEntry g;
+    g.k = k;
+    g.gs = gs;
+    g.S = S;
+    g.J = J;
+    g.delta_c = delta_c;
+    g.per_bin_stop = per_bin_stop;
+    g.fixed = fixed;
+    g.graph = graph;
+    g.exec = exec;
+    p->graphs.push_back(g);
+    *out = exec;
+    return RT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1451,25 +1520,57 @@ rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, doubl
         rt_status s = collect_timing(p);
         if (s != RT_OK) return s;
     }
-    for (int it = 0; it < total && !done;) {
-        const int k = fixed ? total : std::min(every, total - it);
+    // k iterations on stream cs; the first one's sweep is timed when profiling is on
+    auto chunk = [&](int k, hipStream_t cs) -> rt_status {
         for (int j = 0; j < k; ++j) {
             if (gs) {
-                rt_status s = p->f32 ? gs_iteration<float>(p, S_inout, J_out, st)
-                                     : gs_iteration<double>(p, S_inout, J_out, st);
+                rt_status s = p->f32 ? gs_iteration<float>(p, S_inout, J_out, cs)
+                                     : gs_iteration<double>(p, S_inout, J_out, cs);
                 if (s != RT_OK) return s;
-                HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
+                HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, cs));
                 continue;
             }
-            rt_status s = sweep_current_S(p, S_inout, st, j == 0, active);
+            rt_status s = sweep_current_S(p, S_inout, cs, j == 0, active);
             if (s != RT_OK) return s;
             if (p->f32)
                 HIP_TRY(launch_ali_update<float>(static_cast<float *>(p->part), p->npart, 1, p->nf, p->cells, p->B,
-                                                 p->eps, p->lam, S_inout, J_out, ctl, st));
+                                                 p->eps, p->lam, S_inout, J_out, ctl, cs));
             else
                 HIP_TRY(launch_ali_update<double>(static_cast<double *>(p->part), p->npart, 0, p->nf, p->cells, p->B,
-                                                  p->eps, p->lam, S_inout, J_out, ctl, st));
-            HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, st));
+                                                  p->eps, p->lam, S_inout, J_out, ctl, cs));
+            HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, cs));
+        }
+        return RT_OK;
+    };
+    // Chunks run as captured graphs (the same launches with the same arguments every
+    // chunk; frozen bins make their kernels return at once), except while the sweep
+    // is being timed.  The one-time periodic initialisation runs before, eagerly.
+    const bool use_graph = p->use_graphs && !p->prof;
+    if (use_graph && p->cold) {
+        if (p->plane_order) {
+            if (p->f32)
+                HIP_TRY(launch_plane_cold<float>(plane_args<float>(p, S_inout), st));
+            else
+                HIP_TRY(launch_plane_cold<double>(plane_args<double>(p, S_inout), st));
+        } else {
+            if (p->f32)
+                HIP_TRY(launch_periodic_cold<float>(sweep_args<float>(p, S_inout), st));
+            else
+                HIP_TRY(launch_periodic_cold<double>(sweep_args<double>(p, S_inout), st));
+        }
+        p->cold = false;
+    }
+    for (int it = 0; it < total && !done;) {
+        const int k = std::min(every, total - it);
+        if (use_graph) {
+            hipGraphExec_t ex = nullptr;
+            rt_status s = chunk_graph(p, k, gs, S_inout, J_out, opts->delta_c, opts->per_bin_stop ? 1 : 0,
+                                      fixed ? 1 : 0, [&](hipStream_t cs) { return chunk(k, cs); }, &ex);
+            if (s != RT_OK) return s;
+            HIP_TRY(hipGraphLaunch(ex, st));
+        } else {
+            rt_status s = chunk(k, st);
+            if (s != RT_OK) return s;
         }
         it += k;
         HIP_TRY(hipMemcpyAsync(p->h_flags, p->flags, sizeof(int) * 3, hipMemcpyDeviceToHost, st));
@@ -1486,7 +1587,6 @@ rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, doubl
             active = 0;
             for (int f = 0; f < p->nf; ++f) active += p->h_frozen[f] == 0;
         }
-        if (fixed) break;
     }
     std::vector<int> iters(p->nf);
     std::vector<double> resid(p->nf);
@@ -1514,6 +1614,13 @@ rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, doubl
 }  // namespace
 
 extern "C" {
+
+rt_status rt_problem_use_graphs(rt_problem *p, int32_t enable)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    p->use_graphs = enable != 0;
+    return RT_OK;
+}
 
 rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream)
 {
