@@ -220,6 +220,26 @@ rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inou
                           rt_ali_stats *stats, void *stream);
 
 /*
+ * Launch shape of the tile-wavefront sweep.  A sweep workgroup takes one 8^3 tile of
+ * one octant and bin with `waves` 64-lane waves; with fewer waves than rays per octant
+ * (R = na/8) each wave runs several rays in turn.  rt_problem_create picks
+ * min(R, 10) waves (as many as fit the device's LDS).
+ *
+ * rt_problem_set_waves -- use `waves` in [1, min(R, 10)] (RT_E_INVALID outside,
+ * RT_E_UNSUPPORTED if the LDS does not fit or for the plane-ordered sweep).  Results
+ * change only in the rounding of the sums over the waves.  Host-only call.
+ *
+ * rt_problem_tune -- time `reps` formal solutions of S (device [nf][cells] FP64, fields
+ * set) for every wave count that fits, keep the fastest, and report it in *waves_out;
+ * ms_out (host [10] or NULL) receives the milliseconds per sweep of each count (-1
+ * where it does not fit).  The periodic memory the next solve reads is left as it was
+ * (a problem with no sweep yet stays cold).  Synchronises the stream.
+ */
+rt_status rt_problem_set_waves(rt_problem *p, int32_t waves);
+rt_status rt_problem_tune(rt_problem *p, const double *S, int32_t reps, int32_t *waves_out, float *ms_out,
+                          void *stream);
+
+/*
  * rt_problem_use_graphs -- rt_ali_solve and rt_ali_solve_gs run their iterations in
  * chunks of check_every (the host reads the convergence flags between chunks).  With
  * graphs enabled (the default) a chunk is captured once as a HIP graph on a stream of

@@ -27,7 +27,8 @@ RT_INTERP_BILINEAR, RT_INTERP_QUADRATIC = 0, 1
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
-           "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
+           "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_problem_set_waves",
+           "rt_problem_tune", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
            "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
            "rt_server_load", "rt_server_destroy")
 
@@ -96,6 +97,8 @@ def load():
     lib.rt_ali_solve.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_ali_solve_gs.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_problem_use_graphs.argtypes = [P, I32]
+    lib.rt_problem_set_waves.argtypes = [P, I32]
+    lib.rt_problem_tune.argtypes = [P, P, I32, ctypes.POINTER(I32), P, P]
     lib.rt_ali_bin_stats.argtypes = [P, P, P, P]
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
     lib.rt_problem_profile.argtypes = [P, I32]
@@ -361,6 +364,17 @@ class Problem:
 
     def use_graphs(self, enable=True):
         _check(load().rt_problem_use_graphs(self.handle, 1 if enable else 0))
+
+    def set_waves(self, waves):
+        _check(load().rt_problem_set_waves(self.handle, int(waves)))
+
+    def tune(self, S, reps=3, stream=None):
+        """Time the sweep for every wave count, keep the fastest: (waves, {waves: ms})."""
+        best = ctypes.c_int32()
+        ms = (ctypes.c_float * 10)(*([-1.0] * 10))
+        _check(load().rt_problem_tune(self.handle, _dptr(S, name="S"), int(reps), ctypes.byref(best), ms,
+                                      _stream(stream)))
+        return best.value, {w + 1: ms[w] for w in range(10) if ms[w] >= 0.0}
 
     def moments(self, S, **kw):
         return rt_moments(self.handle, S, **kw)

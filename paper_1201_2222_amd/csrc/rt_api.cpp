@@ -272,6 +272,7 @@ struct rt_problem {
     double *resid = nullptr;
     unsigned long long *blockmax = nullptr;  // [nf][kUpdateBlocks]
     int waves = 1;                     // waves per sweep workgroup
+    size_t lds_limit = 65536;          // LDS bytes a workgroup may use on the device
     bool persistent = false;           // one launch per sweep (dependency flags)
     int ntiles = 0;                    // tiles per (bin, octant)
     int bpo = 1;                       // persistent workgroups per octant
@@ -1170,6 +1171,7 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
         (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     (void)hipGetLastError();
     p->waves = sweep_waves(p->R, p->f32, desc->order, (size_t)lds_limit);
+    p->lds_limit = (size_t)lds_limit;
     p->persistent = desc->schedule == RT_SCHED_PERSISTENT;
     if (p->persistent) {
         int per_cu = 0, ncu = 0;
@@ -1614,6 +1616,87 @@ rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, doubl
 }  // namespace
 
 extern "C" {
+
+namespace {
+void drop_graphs(rt_problem *p)
+{
+    for (auto &g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    p->graphs.clear();
+}
+}  // namespace
+
+rt_status rt_problem_set_waves(rt_problem *p, int32_t waves)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    if (p->plane_order) return fail(RT_E_UNSUPPORTED, "the plane-ordered sweep has no wave count");
+    const int wmax = std::min(p->R, kMaxWaves);
+    if (waves < 1 || waves > wmax) return fail(RT_E_INVALID, "waves must be in [1, %d]", wmax);
+    if (sweep_lds_bytes(p->f32 ? 4 : 8, waves, 1, p->R > waves, p->desc.order) > p->lds_limit)
+        return fail(RT_E_UNSUPPORTED, "%d waves need more LDS than the device allows", (int)waves);
+    if (waves != p->waves) drop_graphs(p);   // captured launches carry the old shape
+    p->waves = waves;
+    return RT_OK;
+}
+
+rt_status rt_problem_tune(rt_problem *p, const double *S, int32_t reps, int32_t *waves_out, float *ms_out,
+                          void *stream)
+{
+    if (!p || !S || !waves_out) return fail(RT_E_INVALID, "problem, S and waves_out are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    if (p->plane_order) return fail(RT_E_UNSUPPORTED, "the plane-ordered sweep has no wave count");
+    if (reps < 1) return fail(RT_E_INVALID, "reps must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int wmax = std::min(p->R, kMaxWaves);
+    const bool cold = p->cold;
+    const int keep = p->waves;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RT_E_HIP, "hipEventCreate: %s", hipGetErrorString(he));
+    }
+    rt_status s = RT_OK;
+    int best = keep;
+    float best_ms = 0.0f;
+    he = hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st);
+    for (int w = 1; w <= wmax && s == RT_OK && he == hipSuccess; ++w) {
+        if (ms_out) ms_out[w - 1] = -1.0f;
+        if (sweep_lds_bytes(p->f32 ? 4 : 8, w, 1, p->R > w, p->desc.order) > p->lds_limit) continue;
+        p->waves = w;
+        s = sweep_current_S(p, S, st);   // untimed: caches warm, cold memory filled
+        if (s == RT_OK) he = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == RT_OK && he == hipSuccess; ++r) s = sweep_current_S(p, S, st);
+        if (s == RT_OK && he == hipSuccess) he = hipEventRecord(e1, st);
+        if (s == RT_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (s == RT_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (s != RT_OK || he != hipSuccess) break;
+        ms /= (float)reps;
+        if (ms_out) ms_out[w - 1] = ms;
+        if (best_ms == 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the sweeps wrote only the periodic slot the next sweep overwrites; a cold problem
+    // stays cold (its next solve fills the memory from its own S)
+    p->cold = cold;
+    if (best != keep) drop_graphs(p);
+    p->waves = best;
+    if (s != RT_OK) return s;
+    if (he != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RT_E_HIP, "timing the sweep failed: %s", hipGetErrorString(he));
+    }
+    *waves_out = best;
+    return RT_OK;
+}
 
 rt_status rt_problem_use_graphs(rt_problem *p, int32_t enable)
 {
