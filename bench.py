@@ -331,7 +331,7 @@ def main():
                     help="scattering: first-order or second-order (Bezier) short characteristics")
     ap.add_argument("--interp", choices=["bilinear", "quadratic"], default="bilinear",
                     help="scattering: upwind intensity bilinear (tile wavefront) or monotone quadratic "
-                         "(plane-ordered sweep; no moments epilogue)")
+                         "(plane-ordered sweep)")
     ap.add_argument("--ali", choices=["jacobi", "gauss-seidel"], default="jacobi",
                     help="scattering: Jacobi ALI, or Gauss-Seidel with horizontal planes as the blocks")
     ap.add_argument("--fixed-iters", type=int, default=0,
@@ -414,8 +414,8 @@ def main():
                            fixed_iters=args.fixed_iters)
         if status != rt.RT_OK:
             raise RuntimeError(f"ALI did not converge: {st}")
-        # moments epilogue on the converged S (not built for the plane-ordered sweep)
-        st["heating"] = None if quad else prob.moments(S, want_heating=True, **mom)
+        # moments epilogue on the converged S
+        st["heating"] = prob.moments(S, want_heating=True, **mom)
         return st
 
     for _ in range(args.warmup):
@@ -445,14 +445,14 @@ def main():
     print(f"profiled step: {prof['launches']} timed launches", file=sys.stderr, flush=True)
 
     # one sweep per ALI iteration plus the moments sweep
-    updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + (0 if quad else len(iters))))
+    updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + len(iters)))
     value = updates / total
     kernel_s = prof["kernel_ms"] / 1e3
     achieved = prof["updates"] * ops_per_update / kernel_s / 1e12 if kernel_s > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(kind),
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "plane_step_kernel<float, true>" if quad else f"sweep_stage_kernel<float, true, 1, false, {order}>",
+                "kernel": "plane_step_kernel<float, true, 1>" if quad else f"sweep_stage_kernel<float, true, 1, false, {order}, 8>",
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
                 "ops_per_update": ops_per_update}
@@ -488,7 +488,7 @@ def main():
                                f"vertical tau 1e4, {'Gauss-Seidel' if gs else 'Jacobi'} ALI from S=B to max|dS/S|<=1e-6, "
                                f"FP32 sweeps + FP64 updates"
                                f"{', second-order (Bezier) segments' if order else ''}"
-                               f"{', monotone quadratic upwind intensity (plane order), no moments epilogue' if quad else ''}",
+                               f"{', monotone quadratic upwind intensity (plane order)' if quad else ''}",
                    "grid": list(wl.shape), "rays": wl.na, "order": args.order, "interp": args.interp,
                    "ali": args.ali,
                    "schedule": args.schedule,

@@ -92,8 +92,8 @@ typedef enum { RT_SC_LINEAR = 0, RT_SC_BEZIER = 1 } rt_sc_order;
  * ray is swept plane by plane along the axis it crosses first; in-plane periodic
  * wraps read this sweep's values, and outside a non-periodic in-plane face the
  * downwind side (an outgoing face) repeats the value in line with the vertex.  S and
- * chi stay bilinear.  Requires order RT_SC_LINEAR; rt_moments, rt_ali_solve_batch and
- * the server return RT_E_UNSUPPORTED for such problems. */
+ * chi stay bilinear.  Requires order RT_SC_LINEAR; rt_ali_solve_batch and the server
+ * return RT_E_UNSUPPORTED for such problems. */
 typedef enum { RT_INTERP_BILINEAR = 0, RT_INTERP_QUADRATIC = 1 } rt_interp;
 
 typedef struct {

@@ -559,18 +559,24 @@ PlaneArgs<Real> plane_args(const rt_problem *p, const double *S)
 // One formal solution in plane order (quadratic upwind intensity): step t of every
 // ray is one launch, t = 0 .. max(nx, ny, nz) - 1.
 template <typename Real>
-rt_status run_plane_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed, int active_bins)
+rt_status run_plane_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed, int active_bins,
+                          const SweepMode &mode)
 {
-    const PlaneArgs<Real> A = plane_args<Real>(p, S);
+    PlaneArgs<Real> A = plane_args<Real>(p, S);
     if (p->cold) {
         HIP_TRY(launch_plane_cold<Real>(A, st));
         p->cold = false;
     }
-    timed = timed && p->prof && !p->prof_pending;
+    if (mode.nfc > 0) {
+        A.f0 = mode.f0;
+        A.nfc = mode.nfc;
+    }
+    if (mode.part) A.part = static_cast<Real *>(mode.part);
+    timed = timed && p->prof && !p->prof_pending && mode.nq == 1;
     const int steps = std::max(p->n[0], std::max(p->n[1], p->n[2]));
     for (int t = 0; t < steps; ++t) {
         if (timed && t == 0) HIP_TRY(hipEventRecord(p->ev[0], st));
-        HIP_TRY(launch_plane_step<Real>(A, t, st));
+        HIP_TRY(launch_plane_step<Real>(A, t, mode.nq, st));
         if (timed && t == steps - 1) HIP_TRY(hipEventRecord(p->ev[1], st));
     }
     if (timed) {
@@ -584,7 +590,7 @@ template <typename Real>
 rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed = false, int active_bins = 0,
                     SweepMode mode = SweepMode())
 {
-    if (p->plane_order) return run_plane_sweep<Real>(p, S, st, timed, active_bins);
+    if (p->plane_order) return run_plane_sweep<Real>(p, S, st, timed, active_bins, mode);
     SweepArgs<Real> A = sweep_args<Real>(p, S);
     if (mode.nfc > 0) {
         A.f0 = mode.f0;
@@ -1748,21 +1754,21 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
     if (!S || !out) return fail(RT_E_INVALID, "S and out are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
-    if (p->plane_order) return fail(RT_E_UNSUPPORTED, "moments are not built for the quadratic upwind intensity");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool want_int = out->J_int || out->H_int || out->K_int || out->f_int || out->Q_int || out->heating;
     if (!(out->J || out->H || out->K || want_int)) return RT_OK;
     const int64_t cells = p->cells;
     const size_t rs = p->f32 ? sizeof(float) : sizeof(double);
 
-    // scratch: bins are processed in chunks so the per-octant moment partials fit
+    // scratch: bins are processed in chunks so the moment partials fit (per octant, or
+    // per class of the plane-ordered sweep)
     if (!p->mom_part) {
-        const size_t per_bin = (size_t)cells * (8 * 10 * rs + 11 * sizeof(double));
+        const size_t per_bin = (size_t)cells * ((size_t)p->npart * 10 * rs + 11 * sizeof(double));
         const size_t budget = (size_t)4 << 30;
         p->mom_nfc = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->nf, budget / std::max<size_t>(per_bin, 1)));
         rt_status a;
         unsigned char *pb = nullptr;
-        if ((a = dalloc(p, &pb, (size_t)8 * 10 * p->mom_nfc * cells * rs)) != RT_OK) return a;
+        if ((a = dalloc(p, &pb, (size_t)p->npart * 10 * p->mom_nfc * cells * rs)) != RT_OK) return a;
         p->mom_part = pb;
         if ((a = dalloc(p, &p->mom_tmp, (size_t)10 * p->mom_nfc * cells)) != RT_OK) return a;
         if ((a = dalloc(p, &p->mom_q, (size_t)p->mom_nfc * cells)) != RT_OK) return a;
@@ -1807,11 +1813,11 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
         if (s != RT_OK) return s;
         HIP_TRY(launch_flip_parity(p->parity, p->frozen, f0, cnt, st));
         if (p->f32)
-            HIP_TRY(launch_moments_combine<float>(static_cast<float *>(p->mom_part), S, 1, f0, cnt, p->nf, cells, mc,
-                                                  out->J, out->H, out->K, p->mom_tmp, st));
+            HIP_TRY(launch_moments_combine<float>(static_cast<float *>(p->mom_part), p->npart, S, 1, f0, cnt, p->nf,
+                                                  cells, mc, out->J, out->H, out->K, p->mom_tmp, st));
         else
-            HIP_TRY(launch_moments_combine<double>(static_cast<double *>(p->mom_part), S, 0, f0, cnt, p->nf, cells, mc,
-                                                   out->J, out->H, out->K, p->mom_tmp, st));
+            HIP_TRY(launch_moments_combine<double>(static_cast<double *>(p->mom_part), p->npart, S, 0, f0, cnt, p->nf,
+                                                   cells, mc, out->J, out->H, out->K, p->mom_tmp, st));
         if (Qint) HIP_TRY(launch_moments_q(p->mom_tmp, f0, cnt, p->n, h, p->periodic, p->chi64, p->eps, p->B, p->mom_q, st));
         if (want_int) {
             const bool needK = out->K_int || out->f_int;

@@ -232,8 +232,10 @@ hipError_t launch_ali_update(const Real *part, int npart, int dform, int nf, int
 
 // Plane-ordered sweep (rt_plane.hip): one step t of every active bin's rays, and the
 // cold periodic memory (the slot read at t = 0 holds S of the wrapped vertex).
+// nq = 1: the class partials of w I (or w D); nq = 10: also w mu_i I and w mu_i mu_j I,
+// slots [class][q]
 template <typename Real>
-hipError_t launch_plane_step(const PlaneArgs<Real> &A, int t, hipStream_t st);
+hipError_t launch_plane_step(const PlaneArgs<Real> &A, int t, int nq, hipStream_t st);
 template <typename Real>
 hipError_t launch_plane_cold(const PlaneArgs<Real> &A, hipStream_t st);
 
@@ -257,9 +259,11 @@ hipError_t launch_flip_parity(int *parity, const int *frozen, int f0, int cnt, h
 struct MomConst {
     double m[10];
 };
+// npart: partial-sum slots per quantity (8 octants, or kPlaneParts classes)
 template <typename Real>
-hipError_t launch_moments_combine(const Real *part, const double *S, int dform, int f0, int nfc, int nf, int64_t cells,
-                                  const MomConst &mc, double *J, double *H, double *K, double *tmp, hipStream_t st);
+hipError_t launch_moments_combine(const Real *part, int npart, const double *S, int dform, int f0, int nfc, int nf,
+                                  int64_t cells, const MomConst &mc, double *J, double *H, double *K, double *tmp,
+                                  hipStream_t st);
 hipError_t launch_moments_q(const double *tmp, int f0, int nfc, const int n[3], const double h[3], const int per[3],
                             const double *chi, const double *eps, const double *B, double *Qt, hipStream_t st);
 hipError_t launch_moments_integrate(const double *tmp, const double *Qt, const double *w_nu, int f0, int nfc,

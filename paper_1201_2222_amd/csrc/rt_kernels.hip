@@ -1183,7 +1183,7 @@ __global__ void warm_start_kernel(const double *B, const double *eps, const doub
 // Per-octant partials of w I, w mu_i I, w mu_i mu_j I are summed in fixed octant
 // order; the difference form adds S times the angle set's own sums (1, sum w mu_i,
 // sum w mu_i mu_j).  tmp holds [10][nfc][cells] for the Q and integration kernels.
-template <typename Real>
+template <typename Real, int NP>
 __global__ void moments_combine_kernel(const Real *part, const double *S, int dform, int f0, int nfc, int nf,
                                        int64_t cells, MomConst mc, double *J, double *H, double *K, double *tmp)
 {
@@ -1197,7 +1197,7 @@ __global__ void moments_combine_kernel(const Real *part, const double *S, int df
     for (int q = 0; q < 10; ++q) {
         double acc = 0.0;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) acc += (double)part[(((int64_t)o * 10 + q) * nfc + fl) * cells + c];
+        for (int o = 0; o < NP; ++o) acc += (double)part[(((int64_t)o * 10 + q) * nfc + fl) * cells + c];
         if (dform) acc = (q == 0) ? Sv + acc : acc + Sv * mc.m[q];
         tmp[((int64_t)q * nfc + fl) * cells + c] = acc;
         if (q == 0 && J) J[(int64_t)f * cells + c] = acc;
@@ -1549,17 +1549,22 @@ hipError_t launch_flip_parity(int *parity, const int *frozen, int f0, int cnt, h
 }
 
 template <typename Real>
-hipError_t launch_moments_combine(const Real *part, const double *S, int dform, int f0, int nfc, int nf, int64_t cells,
-                                  const MomConst &mc, double *J, double *H, double *K, double *tmp, hipStream_t st)
+hipError_t launch_moments_combine(const Real *part, int npart, const double *S, int dform, int f0, int nfc, int nf,
+                                  int64_t cells, const MomConst &mc, double *J, double *H, double *K, double *tmp,
+                                  hipStream_t st)
 {
-    hipLaunchKernelGGL(moments_combine_kernel<Real>, dim3(blocks_for(cells * nfc, 256)), dim3(256), 0, st, part, S,
-                       dform, f0, nfc, nf, cells, mc, J, H, K, tmp);
+    if (npart == kPlaneParts)
+        hipLaunchKernelGGL((moments_combine_kernel<Real, kPlaneParts>), dim3(blocks_for(cells * nfc, 256)), dim3(256), 0,
+                           st, part, S, dform, f0, nfc, nf, cells, mc, J, H, K, tmp);
+    else
+        hipLaunchKernelGGL((moments_combine_kernel<Real, 8>), dim3(blocks_for(cells * nfc, 256)), dim3(256), 0, st,
+                           part, S, dform, f0, nfc, nf, cells, mc, J, H, K, tmp);
     return hipGetLastError();
 }
-template hipError_t launch_moments_combine<double>(const double *, const double *, int, int, int, int, int64_t,
+template hipError_t launch_moments_combine<double>(const double *, int, const double *, int, int, int, int, int64_t,
                                                    const MomConst &, double *, double *, double *, double *,
                                                    hipStream_t);
-template hipError_t launch_moments_combine<float>(const float *, const double *, int, int, int, int, int64_t,
+template hipError_t launch_moments_combine<float>(const float *, int, const double *, int, int, int, int, int64_t,
                                                   const MomConst &, double *, double *, double *, double *,
                                                   hipStream_t);
 

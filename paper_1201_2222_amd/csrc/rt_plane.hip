@@ -9,7 +9,8 @@
 // ("class") and runs the class's rays one after the other: it stages chi and S of the
 // tile's upwind window (18 x 18 vertices of plane t - 1) and of its own vertices once,
 // then per ray the window of the ray's upwind-plane intensities, and writes the ray's
-// new plane and the class's partial sum of w I (or w D).  Every vertex lies in
+// new plane and the class's partial sum of w I (or w D; in the moments sweep also
+// w mu_i I and w mu_i mu_j I).  Every vertex lies in
 // exactly one plane along d, so each class slot of the partial sums is written once
 // per sweep: no atomics, and the sum over the slots runs in a fixed order.  Up to
 // RMAX rays of a class are staged together, so their window loads go out at once.
@@ -117,7 +118,28 @@ __device__ __forceinline__ WinSrc window_source(const PlaneArgs<Real> &A, int t,
     return w;
 }
 
-template <typename Real, bool DFORM>
+// Weight of a ray in accumulated quantity q: w (J), w mu_i (H), w mu_i mu_j (K: xx yy
+// zz xy xz yz).
+__device__ __forceinline__ double plane_weight(const RayGeo *G, int q)
+{
+    const double *m = G->mu;
+    switch (q) {
+    case 0: return G->wk;
+    case 1: return G->wk * m[0];
+    case 2: return G->wk * m[1];
+    case 3: return G->wk * m[2];
+    case 4: return G->wk * m[0] * m[0];
+    case 5: return G->wk * m[1] * m[1];
+    case 6: return G->wk * m[2] * m[2];
+    case 7: return G->wk * m[0] * m[1];
+    case 8: return G->wk * m[0] * m[2];
+    default: return G->wk * m[1] * m[2];
+    }
+}
+
+// NQ = 1: the class's partial sum of w I (w D); NQ = 10: also w mu_i I and w mu_i mu_j I
+// (the moments sweep), slot [class][q].
+template <typename Real, bool DFORM, int NQ>
 __global__ void __launch_bounds__(PT *PT) plane_step_kernel(PlaneArgs<Real> A, int t)
 {
     const int c = blockIdx.y;
@@ -172,7 +194,9 @@ __global__ void __launch_bounds__(PT *PT) plane_step_kernel(PlaneArgs<Real> A, i
     const int par = A.parity[f];
     const int wsel = (t + par * nd) & 1;
     const bool keep_i = DFORM && t == nd - 1 && sel3(d, A.periodic[0], A.periodic[1], A.periodic[2]);
-    Real acc = Real(0);
+    Real acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = Real(0);
     const int lx = tid % PT + 1, ly = tid / PT + 1;   // the vertex's column in the window
     // up to RMAX rays of the class per pass: all their window loads go out together
     for (int rp = r0; rp < r1; rp += RMAX) {
@@ -250,10 +274,14 @@ __global__ void __launch_bounds__(PT *PT) plane_step_kernel(PlaneArgs<Real> A, i
             }
             A.planes[(rb * 2 + wsel) * A.pmax + ib * na_ + ia] = v;
             if (keep_i) A.wrapI[rb * A.pmax + ib * na_ + ia] = double(v) + S0;
-            acc += Real(G->wk) * v;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] += Real(plane_weight(G, q)) * v;
         }
     }
-    if (act) A.part[((int64_t)c * A.nfc + fl) * A.cells + vcell] = acc;
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) A.part[(((int64_t)c * NQ + q) * A.nfc + fl) * A.cells + vcell] = acc[q];
+    }
 }
 
 // Before the first sweep (and after a reset of the periodic memory) the plane read at
@@ -292,18 +320,19 @@ inline unsigned blocks_of(int64_t n, int bs) { return (unsigned)((n + bs - 1) / 
 }  // namespace
 
 template <typename Real>
-hipError_t launch_plane_step(const PlaneArgs<Real> &A, int t, hipStream_t st)
+hipError_t launch_plane_step(const PlaneArgs<Real> &A, int t, int nq, hipStream_t st)
 {
     const int tiles = std::max(A.ntiles[0], std::max(A.ntiles[1], A.ntiles[2]));
     dim3 grid((unsigned)tiles, (unsigned)kPlaneParts, (unsigned)A.nfc);
-    if constexpr (sizeof(Real) == 4)
-        hipLaunchKernelGGL((plane_step_kernel<float, true>), grid, dim3(PT * PT), 0, st, A, t);
+    constexpr bool DF = sizeof(Real) == 4;
+    if (nq == 10)
+        hipLaunchKernelGGL((plane_step_kernel<Real, DF, 10>), grid, dim3(PT * PT), 0, st, A, t);
     else
-        hipLaunchKernelGGL((plane_step_kernel<double, false>), grid, dim3(PT * PT), 0, st, A, t);
+        hipLaunchKernelGGL((plane_step_kernel<Real, DF, 1>), grid, dim3(PT * PT), 0, st, A, t);
     return hipGetLastError();
 }
-template hipError_t launch_plane_step<float>(const PlaneArgs<float> &, int, hipStream_t);
-template hipError_t launch_plane_step<double>(const PlaneArgs<double> &, int, hipStream_t);
+template hipError_t launch_plane_step<float>(const PlaneArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_plane_step<double>(const PlaneArgs<double> &, int, int, hipStream_t);
 
 template <typename Real>
 hipError_t launch_plane_cold(const PlaneArgs<Real> &A, hipStream_t st)

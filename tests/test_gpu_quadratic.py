@@ -199,16 +199,56 @@ def test_quadratic_workload_scattering_full_size(env, oracle_mod, precision):
     gp.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_quadratic_moments_parity(env, oracle_mod, precision):
+    """The moments epilogue on the quadratic sweep: per-bin J, H, K and the frequency-
+    integrated J, H, K, f, Q and heating against the oracle's moments with the same
+    upwind interpolation (two bins, fixed faces, non-cubic cells)."""
+    rt, torch = env
+    wl = W.random_problem((15, 12, 11), nf=2, seed=730, n_mu=4, bc_lo=(P, F, T), bc_hi=(P, V, V),
+                          h=(1.2, 0.9, 1.0))
+    fixed = _fixed_faces(wl)
+    prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
+    op, gp = _pair(env, oracle_mod, wl, prec, fixed)
+    rng = np.random.default_rng(731)
+    S = (0.5 + rng.random(wl.chi.shape)) * wl.B
+    ref = op.moments(S)
+    n = wl.chi.size
+    c = n // wl.nf
+    out = {k: torch.empty(m, dtype=torch.float64, device="cuda")
+           for k, m in (("J", n), ("H", 3 * n), ("K", 6 * n), ("J_int", c), ("H_int", 3 * c), ("K_int", 6 * c),
+                        ("f_int", 6 * c), ("Q_int", c))}
+    heat = gp.moments(_dev(torch, S), want_heating=True, **out)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    tol = TOL64 if precision == "f64" else TOL32
+    Jref = ref["J"]
+    scale = np.max(np.abs(Jref))
+    assert _rel(g["J"].reshape(Jref.shape), Jref) <= tol
+    # H and K carry no scale of their own: compared against that of J
+    assert np.max(np.abs(g["H"].reshape(ref["H"].shape) - ref["H"])) <= tol * scale
+    assert np.max(np.abs(g["K"].reshape(ref["K"].shape) - ref["K"])) <= tol * scale
+    Jint = ref["J_int"]
+    assert _rel(g["J_int"].reshape(Jint.shape), Jint) <= 2 * tol
+    iscale = np.max(np.abs(Jint))
+    assert np.max(np.abs(g["H_int"].reshape(ref["H_int"].shape) - ref["H_int"])) <= 2 * tol * iscale
+    assert np.max(np.abs(g["K_int"].reshape(ref["K_int"].shape) - ref["K_int"])) <= 2 * tol * iscale
+    assert np.max(np.abs(g["f_int"].reshape(ref["f_int"].shape) - ref["f_int"])) <= 6 * tol
+    h = wl.h
+    qtol = 4 * np.pi * tol * scale * np.sum(np.abs(wl.w_nu)) * (np.max(wl.chi) + 6.0 / min(h)) * 2
+    assert np.max(np.abs(g["Q_int"].reshape(ref["Q_int"].shape) - ref["Q_int"])) <= qtol
+    assert abs(heat - ref["heating"]) <= qtol * c * h[0] * h[1] * h[2]
+    gp.close()
+
+
 def test_quadratic_unsupported_entry_points(env):
-    """Moments, batches and the server refuse plane-ordered problems before any work."""
+    """Batches and the server refuse plane-ordered problems before any work."""
     rt, torch = env
     wl = W.random_problem((8, 8, 8), nf=1, seed=720, n_mu=4)
     gp = rt.Problem(wl.shape, nf=1, n_mu=4, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, interp=rt.RT_INTERP_QUADRATIC)
     gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
     S = _dev(torch, wl.B)
     J = torch.empty_like(S)
-    with pytest.raises(rt.RtError):
-        gp.moments(S, J=J)
     with pytest.raises(rt.RtError):
         rt.rt_ali_solve_batch([gp.handle], [S], [J], fixed_iters=1)
     gp.close()
