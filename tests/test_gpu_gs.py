@@ -179,3 +179,36 @@ def test_gs_unsupported_configurations(env):
         with pytest.raises(rt.RtError):
             gp.ali_solve_gs(S, J, fixed_iters=1)
         gp.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gs_bins_stop_at_different_iterations(env, oracle_mod, precision):
+    """Two bins of very different eps converge after different numbers of iterations:
+    the first one frozen stays untouched while the other goes on (every Gauss-Seidel
+    kernel skips frozen bins), as in the oracle."""
+    rt, torch = env
+    wl = W.scattering(20, eps=1e-2, tau_bottom=1e3)
+    chi = np.concatenate([wl.chi, wl.chi * 0.5])
+    eps = np.concatenate([np.full_like(wl.eps, 0.3), np.full_like(wl.eps, 3e-3)])
+    B = np.concatenate([wl.B, wl.B * 1.3])
+    wl2 = W.Workload("two-bin", wl.shape, wl.n_mu, chi, eps, B, np.array([1.0, 0.5]), bc_lo=wl.bc_lo,
+                     bc_hi=wl.bc_hi, h=wl.h)
+    prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
+    op, gp = _pair(env, oracle_mod, wl2, prec)
+    ref = op.ali_gs(delta_c=1e-6, max_iter=5000, per_bin_stop=True)
+    assert ref["iters"][0] < ref["iters"][1] // 2
+    n = wl2.chi.size
+    S = torch.empty(n, dtype=torch.float64, device="cuda")
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    status, stats = gp.ali_solve_gs(S, J, delta_c=1e-6, max_iter=5000, per_bin_stop=True)
+    torch.cuda.synchronize()
+    assert status == rt.RT_OK
+    it, _ = rt.rt_ali_bin_stats(gp.handle, wl2.nf)
+    tol = TOL64 if precision == "f64" else TOL32
+    if precision == "f64":
+        assert list(it) == list(ref["iters"])
+    else:
+        assert np.all(np.abs(it - ref["iters"]) <= np.maximum(3, 0.02 * ref["iters"]))
+    assert _rel(S.cpu().numpy().reshape(ref["S"].shape), ref["S"]) <= tol
+    assert _rel(J.cpu().numpy().reshape(ref["J"].shape), ref["J"]) <= tol
+    gp.close()

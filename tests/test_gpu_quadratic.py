@@ -252,3 +252,39 @@ def test_quadratic_unsupported_entry_points(env):
     with pytest.raises(rt.RtError):
         rt.rt_ali_solve_batch([gp.handle], [S], [J], fixed_iters=1)
     gp.close()
+
+
+@pytest.mark.parametrize("interp", [0, 1])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_crossing_beams(env, oracle_mod, interp, precision):
+    """Two narrow beams crossing in vacuum (the oracle's crossing-beam pin): the GPU
+    sweep with either upwind interpolation follows the oracle (compared against the
+    beam's peak: J vanishes in most of the box)."""
+    rt, torch = env
+    N = 32
+    d = np.array([0.5, 0.45, 0.74])
+    d /= np.linalg.norm(d)
+    mu = np.array([[sx * d[0], sy * d[1], sz * d[2]] for sz in (1, -1) for sy in (1, -1) for sx in (1, -1)])
+    w = np.full(8, 1.0 / 8.0)
+    fxl = np.zeros((1, 8, N * N))
+    fxh = np.zeros((1, 8, N * N))
+    fxl[0, 0, 3 * N + 4] = 1.0
+    fxh[0, 1, 3 * N + 4] = 1.0
+    fixed = [fxl, fxh, None, None, None, None]
+    n = N ** 3
+    op = oracle_mod.Problem((N, N, N), np.zeros(n), 1.0, np.zeros(n), mu=mu, w=w, interp=interp,
+                            bc_lo=(F, V, V), bc_hi=(F, V, V), fixed=fixed)
+    ref = op.sweep(np.zeros(n))["J"][0]
+    dfix = [None if a is None else _dev(torch, a) for a in fixed]
+    gp = rt.Problem((N, N, N), nf=1, mu=mu, w=w, bc_lo=(F, V, V), bc_hi=(F, V, V), I_fixed=dfix,
+                    precision=rt.RT_F64 if precision == "f64" else rt.RT_F32,
+                    interp=rt.RT_INTERP_QUADRATIC if interp else rt.RT_INTERP_BILINEAR)
+    z = _dev(torch, np.zeros(n))
+    gp.set_fields(_dev(torch, np.full(n, 1e-30)), _dev(torch, np.ones(n)), z)
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    gp.formal_solve(z, J)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().reshape(ref.shape)
+    tol = TOL64 if precision == "f64" else TOL32
+    assert np.max(np.abs(Jg - ref)) <= tol * np.max(ref)
+    gp.close()

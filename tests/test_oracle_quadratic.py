@@ -202,3 +202,59 @@ def test_ali_converges_to_a_fixed_point(oracle_mod):
     J = p.sweep(S)["J"]
     resid = np.max(np.abs((1 - eps.reshape(S.shape)) * J + eps.reshape(S.shape) * B.reshape(S.shape) - S) / S)
     assert resid <= 1e-8
+
+
+def _crossing_beams(o, interp, N=32, beams=(True, True)):
+    """Two narrow beams through vacuum that cross: beam A rides the ray (+, +, +) in from
+    one vertex of the x-lo face, beam B the ray (-, +, +) in from the mirror vertex of the
+    x-hi face; both climb in y and z, A towards +x and B towards -x, and they cross half
+    way.  Returns J."""
+    mu, w = _octant_rays((0.5, 0.45, 0.74))
+    assert tuple(np.sign(mu[0])) == (1, 1, 1) and tuple(np.sign(mu[1])) == (-1, 1, 1)
+    n = N ** 3
+    na = len(w)
+    fxl = np.zeros((1, na, N * N))
+    fxh = np.zeros((1, na, N * N))
+    if beams[0]:
+        fxl[0, 0, 3 * N + 4] = 1.0     # x-lo face, (y, z) = (4, 3), ray (+, +, +)
+    if beams[1]:
+        fxh[0, 1, 3 * N + 4] = 1.0     # x-hi face, (y, z) = (4, 3), ray (-, +, +)
+    p = o.Problem((N, N, N), np.zeros(n), 1.0, np.zeros(n), mu=mu, w=w, interp=interp,
+                  bc_lo=(o.FIXED, o.VACUUM, o.VACUUM), bc_hi=(o.FIXED, o.VACUUM, o.VACUUM),
+                  fixed=[fxl, fxh, None, None, None, None])
+    return p.sweep(np.zeros(n))["J"][0]
+
+
+def _spot(plane):
+    """Total, centre along x and second moment about the centre of a 2D intensity spot."""
+    Y, X = np.mgrid[0:plane.shape[0], 0:plane.shape[1]]
+    tot = plane.sum()
+    cx, cy = (plane * X).sum() / tot, (plane * Y).sum() / tot
+    return tot, cx, float((plane * ((X - cx) ** 2 + (Y - cy) ** 2)).sum() / tot)
+
+
+def test_crossing_beams_stay_narrow_and_bounded(oracle_mod):
+    """The crossing-beam test of section 3.3: linear interpolation of I- spreads a beam
+    over neighbouring vertices at every step; the monotone quadratic scheme keeps a beam
+    narrower after the crossing (second moment of its spot on a plane near the top)
+    and keeps more of its peak, while J stays non-negative and bounded by the incident
+    intensity.  In vacuum each ray is transported on its own, so J of the crossing pair
+    is exactly the sum of the two beams alone, for either interpolation, and the two
+    beams are mirror images in x."""
+    o = oracle_mod
+    N = 32
+    widths, peaks = [], []
+    for interp in (0, 1):
+        J = _crossing_beams(o, interp, N)
+        JA = _crossing_beams(o, interp, N, (True, False))
+        JB = _crossing_beams(o, interp, N, (False, True))
+        assert np.max(np.abs(J - (JA + JB))) <= 1e-16
+        assert np.min(J) >= 0.0
+        assert np.max(J) <= 1.0 / 8.0 + 1e-15
+        assert np.max(np.abs(JA - JB[:, :, ::-1])) <= 1e-16     # mirror images in x
+        tot, cx, width = _spot(JA[N - 3])
+        assert cx > (N - 1) / 2                                   # beam A has crossed the middle
+        widths.append(width)
+        peaks.append(float(JA[N - 3].max()))
+    assert widths[1] < 0.7 * widths[0]
+    assert peaks[1] > 1.2 * peaks[0]
