@@ -92,8 +92,8 @@ typedef enum { RT_SC_LINEAR = 0, RT_SC_BEZIER = 1 } rt_sc_order;
  * ray is swept plane by plane along the axis it crosses first; in-plane periodic
  * wraps read this sweep's values, and outside a non-periodic in-plane face the
  * downwind side (an outgoing face) repeats the value in line with the vertex.  S and
- * chi stay bilinear.  Requires order RT_SC_LINEAR; rt_ali_solve_batch and the server
- * return RT_E_UNSUPPORTED for such problems. */
+ * chi stay bilinear.  Requires order RT_SC_LINEAR.  In a batch (and in the server) such
+ * a problem runs its own launches within the batch's iterations. */
 typedef enum { RT_INTERP_BILINEAR = 0, RT_INTERP_QUADRATIC = 1 } rt_interp;
 
 typedef struct {
@@ -263,7 +263,8 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
  * bins, boundaries and precision; they may all differ.  Problems of the same sweep
  * precision and waves per workgroup share every launch: per iteration one ghost-value
  * launch, one launch per stage index covering that hyperplane of all of them, one
- * update and one convergence launch.  A problem that meets the stopping rule (or its
+ * update and one convergence launch.  A problem with the quadratic upwind intensity
+ * runs its own plane-step, update and convergence launches in the same iterations.  A problem that meets the stopping rule (or its
  * max_iter / fixed_iters) leaves the batch at the next check; the others go on.
  * Results per problem are those rt_ali_solve gives for it alone (identical
  * arithmetic).  problems: host array [n] of distinct problems with fields set;

@@ -737,7 +737,7 @@ class BatchRunner {
         rt_problem *p = it.p;
         rt_status s = ali_start(p, &it.opts, it.S, it.J, st_);
         if (s != RT_OK) return s;
-        if (p->cold) {
+        if (p->cold && !p->plane_order) {   // a plane-ordered member's first sweep fills its own
             if (p->f32)
                 HIP_TRY(launch_periodic_cold<float>(sweep_args<float>(p, it.S), st_));
             else
@@ -765,6 +765,23 @@ class BatchRunner {
         for (int j = 0; j < k; ++j)
             for (Class &c : classes_) {
                 const int n = (int)c.idx.size();
+                if (c.plane) {
+                    // a plane-ordered member on its own: its sweep (one launch per plane
+                    // step), the update over its 24 class slots, the batch's convergence launch
+                    const BatchItem &it = items_[c.idx[0]];
+                    rt_problem *p = it.p;
+                    const AliCtl ctl = c.h_upd[0].ctl;
+                    rt_status s = sweep_current_S(p, it.S, st_);
+                    if (s != RT_OK) return s;
+                    if (p->f32)
+                        HIP_TRY(launch_ali_update<float>(static_cast<float *>(p->part), p->npart, 1, p->nf, p->cells,
+                                                         p->B, p->eps, p->lam, it.S, it.J, ctl, st_));
+                    else
+                        HIP_TRY(launch_ali_update<double>(static_cast<double *>(p->part), p->npart, 0, p->nf, p->cells,
+                                                          p->B, p->eps, p->lam, it.S, it.J, ctl, st_));
+                    HIP_TRY(launch_ali_finalize_batch(c.d_upd, 1, d_done_ + 2 * c.done_off, st_));
+                    continue;
+                }
                 if (c.f32) {
                     const SweepArgs<float> *a = static_cast<const SweepArgs<float> *>(c.d_args);
                     HIP_TRY(launch_ghost_fill_batch<float>(a, n, c.max_ghost, c.max_na, st_));
@@ -807,6 +824,7 @@ class BatchRunner {
   private:
     struct Class {
         bool f32 = false;
+        bool plane = false;                   // one plane-ordered member, launches of its own
         int waves = 1;
         bool multi = false;
         int order = 0;
@@ -860,15 +878,18 @@ class BatchRunner {
             const rt_problem *p = items_[i].p;
             const bool multi = p->R > p->waves;
             Class *cls = nullptr;
-            for (Class &c : classes_)
-                if (c.f32 == p->f32 && c.waves == p->waves && c.multi == multi && c.order == p->desc.order)
-                    cls = &c;
+            if (!p->plane_order)
+                for (Class &c : classes_)
+                    if (!c.plane && c.f32 == p->f32 && c.waves == p->waves && c.multi == multi &&
+                        c.order == p->desc.order)
+                        cls = &c;
             if (!cls) {
                 Class c;
                 if (!spare_.empty()) {
                     c = std::move(spare_.back());
                     spare_.pop_back();
                 }
+                c.plane = p->plane_order;
                 c.f32 = p->f32;
                 c.waves = p->waves;
                 c.multi = multi;
@@ -1855,8 +1876,6 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
         if (!p) return fail(RT_E_INVALID, "problem %d is NULL", i);
         if (!S_inout[i] || !J_out[i]) return fail(RT_E_INVALID, "S_inout/J_out of problem %d missing", i);
         if (!p->have_fields) return fail(RT_E_INVALID, "problem %d: rt_problem_set_fields has not been called", i);
-        if (p->plane_order)
-            return fail(RT_E_UNSUPPORTED, "problem %d: batches are not built for the quadratic upwind intensity", i);
         for (int j = 0; j < i; ++j)
             if (problems[j] == p) return fail(RT_E_INVALID, "problem %d appears twice in the batch", i);
     }
@@ -2047,7 +2066,6 @@ rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opt
     if (!srv || !p || !opts || !S_inout || !J_out || !ticket)
         return fail(RT_E_INVALID, "server, problem, opts, S_inout, J_out and ticket are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
-    if (p->plane_order) return fail(RT_E_UNSUPPORTED, "the server is not built for the quadratic upwind intensity");
     {
         rt_status so = check_ali_opts(opts);
         if (so != RT_OK) return so;

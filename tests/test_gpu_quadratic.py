@@ -241,17 +241,38 @@ def test_quadratic_moments_parity(env, oracle_mod, precision):
     gp.close()
 
 
-def test_quadratic_unsupported_entry_points(env):
-    """Batches and the server refuse plane-ordered problems before any work."""
+def test_quadratic_in_a_batch_equals_its_single_solve(env):
+    """A plane-ordered problem in a batch with tile-wavefront problems (it runs its own
+    launches within the batch's iterations) gives bitwise its single solve; so do the
+    others."""
     rt, torch = env
-    wl = W.random_problem((8, 8, 8), nf=1, seed=720, n_mu=4)
-    gp = rt.Problem(wl.shape, nf=1, n_mu=4, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, interp=rt.RT_INTERP_QUADRATIC)
-    gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
-    S = _dev(torch, wl.B)
-    J = torch.empty_like(S)
-    with pytest.raises(rt.RtError):
-        rt.rt_ali_solve_batch([gp.handle], [S], [J], fixed_iters=1)
-    gp.close()
+    specs = [((14, 12, 10), 4, rt.RT_INTERP_QUADRATIC, rt.RT_F32, 740),
+             ((12, 10, 9), 4, rt.RT_INTERP_BILINEAR, rt.RT_F32, 741),
+             ((10, 9, 8), 6, rt.RT_INTERP_QUADRATIC, rt.RT_F64, 742)]
+    probs, single = [], []
+    for shape, n_mu, interp, prec, seed in specs:
+        wl = W.random_problem(shape, nf=2, seed=seed, n_mu=n_mu, eps_range=(1e-2, 1.0))
+        out = []
+        for _ in range(2):
+            gp = rt.Problem(wl.shape, nf=2, n_mu=n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=prec, interp=interp)
+            gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+            S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+            J = torch.empty_like(S)
+            out.append((gp, S, J))
+        probs.append(out[0])
+        gp, S, J = out[1]
+        gp.ali_solve(S, J, delta_c=1e-7, max_iter=2000)
+        torch.cuda.synchronize()
+        single.append((S.cpu().numpy(), J.cpu().numpy()))
+        gp.close()
+    status, per, stats = rt.rt_ali_solve_batch([p[0].handle for p in probs], [p[1] for p in probs],
+                                               [p[2] for p in probs], delta_c=1e-7, max_iter=2000)
+    torch.cuda.synchronize()
+    assert status == rt.RT_OK
+    for (gp, S, J), (S1, J1) in zip(probs, single):
+        assert np.array_equal(S.cpu().numpy(), S1)
+        assert np.array_equal(J.cpu().numpy(), J1)
+        gp.close()
 
 
 @pytest.mark.parametrize("interp", [0, 1])
@@ -288,3 +309,42 @@ def test_crossing_beams(env, oracle_mod, interp, precision):
     tol = TOL64 if precision == "f64" else TOL32
     assert np.max(np.abs(Jg - ref)) <= tol * np.max(ref)
     gp.close()
+
+
+def test_quadratic_through_the_server(env):
+    """A plane-ordered request and a tile-wavefront request through the serving loop
+    give their single solves bitwise."""
+    import time
+    rt, torch = env
+    srv = rt.rt_server_create(1 << 32, check_every=8)
+    jobs = []
+    for shape, interp, seed in (((13, 11, 9), rt.RT_INTERP_QUADRATIC, 750), ((12, 12, 8), rt.RT_INTERP_BILINEAR, 751)):
+        wl = W.random_problem(shape, nf=1, seed=seed, n_mu=4, eps_range=(1e-2, 1.0))
+        ref = rt.Problem(wl.shape, nf=1, n_mu=4, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32, interp=interp)
+        ref.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+        S1 = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+        J1 = torch.empty_like(S1)
+        ref.ali_solve(S1, J1, delta_c=1e-7, max_iter=2000)
+        torch.cuda.synchronize()
+        gp = rt.Problem(wl.shape, nf=1, n_mu=4, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32, interp=interp)
+        gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+        torch.cuda.synchronize()
+        S = torch.empty_like(S1)
+        J = torch.empty_like(S1)
+        t = rt.rt_server_submit(srv, gp.handle, S, J, delta_c=1e-7, max_iter=2000)
+        jobs.append((t, gp, ref, S, J, S1.cpu().numpy(), J1.cpu().numpy()))
+    for t, gp, ref, S, J, S1, J1 in jobs:
+        t0 = time.time()
+        r = None
+        while r is None and time.time() - t0 < 120:
+            r = rt.rt_server_poll(srv, t)
+            if r is None:
+                time.sleep(0.01)
+        assert r is not None and r[0] == rt.RT_OK
+        torch.cuda.synchronize()
+        assert np.array_equal(S.cpu().numpy(), S1)
+        assert np.array_equal(J.cpu().numpy(), J1)
+        rt.rt_server_release(srv, t)
+        gp.close()
+        ref.close()
+    rt.rt_server_destroy(srv)
