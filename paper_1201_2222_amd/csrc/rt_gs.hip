@@ -400,7 +400,11 @@ __global__ void __launch_bounds__(256) gs_prep_kernel(GsArgs<Real> A, int t)
 // first (se > 0) or last (se < 0) of them is in the next lane.  The columns are taken
 // in groups of P: the coefficients of the next group are loaded at the start of a
 // group, so the wait for them at the group's end finds loads issued P steps before.
-template <typename Real, bool DFORM, int M>
+// NEW: plane kn is recomputed (t > 0); OLD: plane ko is computed (t < nz); FULL: every
+// lane holds M vertices of the column (Ne = 64 M).  The periodic memory of plane kn is
+// written after the recurrence: the outgoing face along e from the plane just written,
+// the last column from the registers.
+template <typename Real, bool DFORM, int M, bool NEW, bool OLD, bool FULL>
 __global__ void __launch_bounds__(64) gs_chain_kernel(GsArgs<Real> A, int t)
 {
     constexpr int P = (sizeof(Real) == 4 ? 16 : 8) / M;
@@ -416,56 +420,38 @@ __global__ void __launch_bounds__(64) gs_chain_kernel(GsArgs<Real> A, int t)
     const double *ghS = reinterpret_cast<const double *>(A.ghS) + ((int64_t)f * A.ns + C.di) * 2 * A.nmax;
     Real *plane_n = A.planes + (((int64_t)f * A.nd + C.di) * 2 + (C.kn & 1)) * A.pxy;
     Real *part = A.part + ((int64_t)C.di * A.nf + f) * A.pxy;
-    const bool do_plane = t > 0, do_part = C.ko >= 0;
-    // periodic memory written by the chain (final values of plane kn): on the outgoing
-    // face along e one vertex per column (plane normal to e, index fz N_d + flipped d,
-    // which is the step c), and on the last column every vertex (plane normal to d,
-    // index fz N_e + flipped e)
-    const int par1 = A.parity[f] ^ 1;
-    const int64_t rb = ((int64_t)f * A.na + C.ray) * 2 + par1;
-    const int fz = flip(C.kn < A.n[2] ? C.kn : 0, -1, A.n[2]);   // rays going down: z flipped
-    const bool wrap_e = do_plane && A.periodic[C.e] != 0, wrap_d = do_plane && A.periodic[C.d] != 0;
-    double *we = wrap_e ? A.wrap[C.e] + rb * ((int64_t)C.Nd * A.n[2]) + (int64_t)fz * C.Nd : nullptr;
-    double *wd = wrap_d ? A.wrap[C.d] + rb * ((int64_t)C.Ne * A.n[2]) + (int64_t)fz * C.Ne : nullptr;
-    const int pe_out = C.se > 0 ? C.Ne - 1 : 0;    // the ray's outgoing face along e
     int pe_m[M];
-    bool ok_m[M], out_m[M];
-    int fe_m[M];   // flipped coordinate along e
+    bool ok_m[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         pe_m[m] = lane * M + m;
-        ok_m[m] = pe_m[m] < C.Ne;
-        out_m[m] = wrap_e && pe_m[m] == pe_out;
-        fe_m[m] = C.se > 0 ? pe_m[m] : C.Ne - 1 - pe_m[m];
+        ok_m[m] = FULL || pe_m[m] < C.Ne;
     }
     // the lane holding the neighbour of this lane's boundary vertex, and which vertex
     const int src = C.se > 0 ? lane - 1 : lane + 1;
     const bool first_is_nb = C.se < 0;   // the next lane's first vertex (se < 0) or last
+    const int pe_edge = C.se > 0 ? 0 : C.Ne - 1;   // the vertex whose neighbour is a ghost
     Real xr[M], ur[M];
-    double sl[M];   // S on the last column (difference form, periodic d)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int pe = ok_m[m] ? pe_m[m] : 0;
         xr[m] = ok_m[m] ? gh[2 * A.nmax + pe] : Real(0);
         ur[m] = ok_m[m] ? gh[3 * A.nmax + pe] : Real(0);
-        sl[m] = (DFORM && do_plane) ? ghS[A.nmax + pe] : 0.0;
     }
-    // per-column values (ghost neighbours of the boundary lane, S on the outgoing face
-    // along e) staged in LDS
+    // ghost neighbours of the boundary lane per column, staged in LDS
     __shared__ Real s_gy[kGsMaxLanes], s_gv[kGsMaxLanes];
-    __shared__ double s_Se[kGsMaxLanes];
     for (int k = lane; k < C.Nd; k += 64) {
         s_gy[k] = gh[k];
         s_gv[k] = gh[A.nmax + k];
-        s_Se[k] = (DFORM && do_plane) ? ghS[k] : 0.0;
     }
     __syncthreads();
     Real aEn[P][M], aQn[P][M], aEo[P][M], aQo[P][M];
     Real bEn[P][M], bQn[P][M], bEo[P][M], bQo[P][M];
+    const int64_t dstep = C.sd > 0 ? C.Ne : -(int64_t)C.Ne;      // chain offset per column
+    const int64_t o0 = C.sd > 0 ? 0 : (int64_t)(C.Nd - 1) * C.Ne;  // column c = 0
     auto fetch = [&](int c, Real (&En)[M], Real (&Qn)[M], Real (&Eo)[M], Real (&Qo)[M]) {
         const int cc = c < C.Nd ? c : C.Nd - 1;      // past the end: any valid column
-        const int pd = C.sd > 0 ? cc : C.Nd - 1 - cc;
-        const int64_t ob = (int64_t)pd * C.Ne;
+        const int64_t ob = o0 + cc * dstep;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int64_t o = ob + (ok_m[m] ? pe_m[m] : 0);
@@ -496,51 +482,50 @@ __global__ void __launch_bounds__(64) gs_chain_kernel(GsArgs<Real> A, int t)
             const int c = c0 + j;
             const int cc = c < C.Nd ? c : C.Nd - 1;
             const int pd = C.sd > 0 ? cc : C.Nd - 1 - cc;
-            const Real gy = s_gy[pd], gv = s_gv[pd];
+            const Real gy = s_gy[pd], gv = OLD ? s_gv[pd] : Real(0);
             // the neighbour along e of this lane's boundary vertex, from the next lane
             const Real sx = __shfl(first_is_nb ? xr[0] : xr[M - 1], src);
-            const Real su = __shfl(first_is_nb ? ur[0] : ur[M - 1], src);
+            Real su = Real(0);
+            if constexpr (OLD) su = __shfl(first_is_nb ? ur[0] : ur[M - 1], src);
             Real xn[M], un[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
-                Real y, v;
+                Real y, v = Real(0);
                 if (M == 1) {
                     y = sx;
                     v = su;
                 } else if (m == 0) {
                     y = first_is_nb ? xr[1] : sx;
-                    v = first_is_nb ? ur[1] : su;
+                    if constexpr (OLD) v = first_is_nb ? ur[1] : su;
                 } else if (m == M - 1) {
                     y = first_is_nb ? sx : xr[M - 2];
-                    v = first_is_nb ? su : ur[M - 2];
+                    if constexpr (OLD) v = first_is_nb ? su : ur[M - 2];
                 } else {
                     y = first_is_nb ? xr[m + 1] : xr[m - 1];
-                    v = first_is_nb ? ur[m + 1] : ur[m - 1];
+                    if constexpr (OLD) v = first_is_nb ? ur[m + 1] : ur[m - 1];
                 }
                 // the vertex at the grid's face along e takes the ghost neighbour
-                const bool edge = pe_m[m] == (C.se > 0 ? 0 : C.Ne - 1);
+                const bool edge = pe_m[m] == pe_edge;
                 y = edge ? gy : y;
-                v = edge ? gv : v;
                 xn[m] = aEn[j][m] * (w0 * xr[m] + w1 * y) + aQn[j][m];
-                un[m] = aEo[j][m] * (w0 * ur[m] + w1 * v + w2 * xr[m] + w3 * y) + aQo[j][m];
+                if constexpr (OLD) {
+                    v = edge ? gv : v;
+                    un[m] = aEo[j][m] * (w0 * ur[m] + w1 * v + w2 * xr[m] + w3 * y) + aQo[j][m];
+                }
             }
-            if (c < C.Nd) {   // uniform over the wave
-                const int64_t ob = (int64_t)pd * C.Ne;
-                const double se_S = s_Se[pd];
+            if (c < C.Nd) {   // uniform over the wave; past the end nothing is kept
+                const int64_t ob = o0 + c * dstep;
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     if (!ok_m[m]) continue;
-                    const int64_t o = ob + pe_m[m];
-                    if (do_plane) plane_n[o] = xn[m];
-                    if (do_part) part[o] = wk * un[m];
-                    if (out_m[m]) we[c] = double(xn[m]) + (DFORM ? se_S : 0.0);
-                    if (wrap_d && c == C.Nd - 1) wd[fe_m[m]] = double(xn[m]) + (DFORM ? sl[m] : 0.0);
+                    if constexpr (NEW) plane_n[ob + pe_m[m]] = xn[m];
+                    if constexpr (OLD) part[ob + pe_m[m]] = wk * un[m];
                 }
-            }
 #pragma unroll
-            for (int m = 0; m < M; ++m) {
-                xr[m] = xn[m];
-                ur[m] = un[m];
+                for (int m = 0; m < M; ++m) {
+                    xr[m] = xn[m];
+                    if constexpr (OLD) ur[m] = un[m];
+                }
             }
         }
 #pragma unroll
@@ -551,6 +536,37 @@ __global__ void __launch_bounds__(64) gs_chain_kernel(GsArgs<Real> A, int t)
                 aQn[j][m] = bQn[j][m];
                 aEo[j][m] = bEo[j][m];
                 aQo[j][m] = bQo[j][m];
+            }
+        }
+    }
+    if constexpr (NEW) {
+        __syncthreads();   // the plane's stores by every lane before the reads below
+        // periodic memory of plane kn (I in FP64; the difference form adds S): on the
+        // outgoing face along e one vertex per column (plane normal to e, index
+        // fz N_d + flipped d = fz N_d + c), and on the last column every vertex (plane
+        // normal to d, index fz N_e + flipped e)
+        const int par1 = A.parity[f] ^ 1;
+        const int64_t rb = ((int64_t)f * A.na + C.ray) * 2 + par1;
+        const int fz = A.n[2] - 1 - C.kn;             // rays going down: z flipped
+        if (A.periodic[C.e]) {
+            double *we = A.wrap[C.e] + rb * ((int64_t)C.Nd * A.n[2]) + (int64_t)fz * C.Nd;
+            const int pe_out = C.se > 0 ? C.Ne - 1 : 0;
+            for (int c = lane; c < C.Nd; c += 64) {
+                const int pd = C.sd > 0 ? c : C.Nd - 1 - c;
+                double I = double(plane_n[(int64_t)pd * C.Ne + pe_out]);
+                if constexpr (DFORM) I += ghS[pd];
+                we[c] = I;
+            }
+        }
+        if (A.periodic[C.d]) {
+            double *wd = A.wrap[C.d] + rb * ((int64_t)C.Ne * A.n[2]) + (int64_t)fz * C.Ne;
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (!ok_m[m]) continue;
+                const int fe = C.se > 0 ? pe_m[m] : C.Ne - 1 - pe_m[m];
+                double I = double(xr[m]);
+                if constexpr (DFORM) I += ghS[A.nmax + pe_m[m]];
+                wd[fe] = I;
             }
         }
     }
@@ -646,6 +662,27 @@ __global__ void gs_clear_kernel(unsigned long long *p, int64_t n)
     if (i < n) p[i] = 0ull;
 }
 
+template <typename Real, bool DF, int M, bool FULL>
+void launch_chain_f(const GsArgs<Real> &A, int t, int kind, hipStream_t st)
+{
+    const dim3 grid((unsigned)A.ns, (unsigned)A.nf);
+    if (kind == 0)
+        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, false, true, FULL>), grid, dim3(64), 0, st, A, t);
+    else if (kind == 1)
+        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, true, true, FULL>), grid, dim3(64), 0, st, A, t);
+    else
+        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, true, false, FULL>), grid, dim3(64), 0, st, A, t);
+}
+
+template <typename Real, bool DF, int M>
+void launch_chain_m(const GsArgs<Real> &A, int t, int kind, bool full, hipStream_t st)
+{
+    if (full)
+        launch_chain_f<Real, DF, M, true>(A, t, kind, st);
+    else
+        launch_chain_f<Real, DF, M, false>(A, t, kind, st);
+}
+
 }  // namespace
 
 template <typename Real>
@@ -658,14 +695,18 @@ hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st)
     if (blocks > 0)
         hipLaunchKernelGGL((gs_prep_kernel<Real, DF>), dim3((unsigned)blocks, (unsigned)A.nf), dim3(256), 0, st, A, t);
     if (A.ns > 0) {
-        const dim3 grid((unsigned)A.ns, (unsigned)A.nf);
         const int ne = std::max(A.n[0], A.n[1]);
-        if (ne <= 64)
-            hipLaunchKernelGGL((gs_chain_kernel<Real, DF, 1>), grid, dim3(64), 0, st, A, t);
-        else if (ne <= 128)
-            hipLaunchKernelGGL((gs_chain_kernel<Real, DF, 2>), grid, dim3(64), 0, st, A, t);
+        const int M = ne <= 64 ? 1 : (ne <= 128 ? 2 : 4);
+        // every chain's lanes are full when both in-plane extents are 64 M
+        const bool full = A.n[0] == 64 * M && A.n[1] == 64 * M;
+        const int nz = A.n[2];
+        const int kind = t == 0 ? 0 : (t == nz ? 2 : 1);   // old only, both, new only
+        if (M == 1)
+            launch_chain_m<Real, DF, 1>(A, t, kind, full, st);
+        else if (M == 2)
+            launch_chain_m<Real, DF, 2>(A, t, kind, full, st);
         else
-            hipLaunchKernelGGL((gs_chain_kernel<Real, DF, 4>), grid, dim3(64), 0, st, A, t);
+            launch_chain_m<Real, DF, 4>(A, t, kind, full, st);
     }
     return hipGetLastError();
 }
