@@ -12,6 +12,8 @@ Paper: Davis, Stone & Jiang (2012), arXiv:1201.2222.
                        (Bezier) form, and the monotone quadratic upwind intensity
                        with plane-ordered sweeps (``rt_oracle.c``)
   * Jacobi ALI ....... section 3.4, eqs. sourcefunc2 and dsjacobi, criterion eq. conv
+  * Gauss-Seidel ALI . section 3.4, horizontal planes from the top down as the blocks
+                       (``orc_gs_iteration`` in ``rt_oracle.c``, ``Problem.ali_gs``)
   * boundaries ....... section 3.5 and the periodic iteration of section 3
   * moments .......... eqs. Jsum/Hsum/Ksum, VET f = K/J and Q_rad (section 4)
 """

@@ -68,6 +68,9 @@
  * same time, the non-periodic face with the highest axis (z, then y, then x)
  * gives the intensity.
  *
+ * The Gauss-Seidel form of the Lambda iteration (section 3.4), with the horizontal
+ * planes as the blocks of its ordering, is orc_gs_iteration below.
+ *
  * Arithmetic is plain FP64 in the order written; build with
  * -ffp-contract=off so that no multiply-add is fused.
  */

@@ -293,7 +293,7 @@ struct rt_problem {
     void *gs_planes = nullptr;         // Real [nf][nd][2][nx ny]
     void *gs_part = nullptr;           // Real [nd][nf][nx ny]
     void *gs_coef = nullptr;           // Real [nf][ns][4][nx ny]
-    void *gs_gh = nullptr;             // Real [nf][ns][6][max(nx, ny)]
+    void *gs_gh = nullptr;             // Real [nf][ns][4][max(nx, ny)]
     double *gs_ghS = nullptr;          // [nf][ns][2][max(nx, ny)]
     void *gs_chi_t = nullptr;          // Real [nf][nz][nx][ny]
     double *gs_S_t = nullptr;          // [nf][nz][nx][ny]
@@ -1323,7 +1323,7 @@ rt_status gs_prepare(rt_problem *p)
     unsigned char *coef = nullptr, *gh = nullptr;
     const size_t nmax = (size_t)std::max(p->n[0], p->n[1]);
     if (s == RT_OK) s = dalloc(p, &coef, (size_t)p->nf * std::max(ns, 1) * 4 * pxy * rs);
-    if (s == RT_OK) s = dalloc(p, &gh, (size_t)p->nf * std::max(ns, 1) * 6 * nmax * rs);
+    if (s == RT_OK) s = dalloc(p, &gh, (size_t)p->nf * std::max(ns, 1) * 4 * nmax * rs);
     double *ghS = nullptr;
     if (s == RT_OK) s = dalloc(p, &ghS, (size_t)p->nf * std::max(ns, 1) * 2 * nmax);
     if (s == RT_OK) s = dalloc(p, &d_down, (size_t)std::max(nd, 1));

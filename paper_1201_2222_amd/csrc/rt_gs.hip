@@ -345,7 +345,7 @@ __device__ __forceinline__ void chain_coef(const GsArgs<Real> &A, const Chain<Re
     cf[1] = Qn;
     cf[2] = Eo;
     cf[3] = Qo;
-    Real *gh = A.gh + ((int64_t)C.f * A.ns + C.di) * 6 * A.nmax;
+    Real *gh = A.gh + ((int64_t)C.f * A.ns + C.di) * 4 * A.nmax;
     if (DFORM && t > 0) {
         // S where the chain writes the periodic memory (I = D + S): the outgoing face
         // along e (per column) and the last column (per pe)
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(64) gs_chain_kernel(GsArgs<Real> A, int t)
     const Real wk = Real(G.wk);
     const int lane = threadIdx.x;
     const Real *cf = A.coef + ((int64_t)f * A.ns + C.di) * A.pxy * 4;
-    const Real *gh = A.gh + ((int64_t)f * A.ns + C.di) * 6 * A.nmax;
+    const Real *gh = A.gh + ((int64_t)f * A.ns + C.di) * 4 * A.nmax;
     const double *ghS = reinterpret_cast<const double *>(A.ghS) + ((int64_t)f * A.ns + C.di) * 2 * A.nmax;
     Real *plane_n = A.planes + (((int64_t)f * A.nd + C.di) * 2 + (C.kn & 1)) * A.pxy;
     Real *part = A.part + ((int64_t)C.di * A.nf + f) * A.pxy;

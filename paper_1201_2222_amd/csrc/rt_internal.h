@@ -128,7 +128,7 @@ struct GsArgs {
                                   // real layout (x fastest), shallow rays along e fastest
     Real *part;                   // [nd][nf][pxy] w I (w D) of the plane being computed
     Real *coef;                   // [nf][ns][pxy][4] chain coefficients E_n, Q_n, E_o, Q_o
-    Real *gh;                     // [nf][ns][6][nmax] chain ghosts: boundary-lane neighbours
+    Real *gh;                     // [nf][ns][4][nmax] chain ghosts: boundary-lane neighbours
                                   // on kn and ko per column, the column before the first
     void *ghS;                    // double [nf][ns][2][nmax]: S on the chain's outgoing face
                                   // along e (per column) and on its last column (per pe)
