@@ -353,8 +353,9 @@ def main():
                     help="only run a 1 GiB device-to-device copy (for scaling rocprofv3 FETCH/WRITE_SIZE) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(how the path would shard is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (bins and independent "
+              "problems would shard across GPUs with no communication but a few reduced scalars)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
