@@ -50,7 +50,7 @@ typedef enum {
     RT_E_OOM = -2,          /* device allocation failed */
     RT_E_HIP = -3,          /* a HIP runtime call failed */
     RT_E_NONFINITE = -4,    /* a residual became NaN or Inf */
-    RT_E_UNSUPPORTED = -5,  /* valid request this build does not implement */
+    RT_E_UNSUPPORTED = -5,  /* valid request the library does not implement */
     RT_E_BUSY = -6          /* rt_server_poll: the request is queued or running */
 } rt_status;
 
@@ -68,7 +68,7 @@ typedef enum { RT_BC_VACUUM = 0, RT_BC_THERMAL = 1, RT_BC_PERIODIC = 2, RT_BC_FI
 /* Execution of the tile wavefront of one formal solution.  RT_SCHED_STAGES: one
  * launch per tile hyperplane (the default).  RT_SCHED_PERSISTENT (one launch,
  * workgroups drawing tiles in hyperplane order and waiting on completion flags of
- * their upwind neighbours) is disabled in this build: rt_problem_create returns
+ * their upwind neighbours) is disabled in this library: rt_problem_create returns
  * RT_E_UNSUPPORTED for it. */
 typedef enum { RT_SCHED_DEFAULT = 0, RT_SCHED_STAGES = 1, RT_SCHED_PERSISTENT = 2 } rt_schedule;
 

@@ -345,7 +345,7 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
     // The persistent schedule did not complete on the device in testing and its
     // cause is not established; it is refused until it is.
     if (d->schedule == RT_SCHED_PERSISTENT)
-        return fail(RT_E_UNSUPPORTED, "the persistent sweep schedule is disabled in this build");
+        return fail(RT_E_UNSUPPORTED, "the persistent sweep schedule is disabled in this library");
     if (d->order != RT_SC_LINEAR && d->order != RT_SC_BEZIER) return fail(RT_E_INVALID, "unknown order");
     if (d->interp != RT_INTERP_BILINEAR && d->interp != RT_INTERP_QUADRATIC)
         return fail(RT_E_INVALID, "unknown upwind interpolation");
