@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 METRIC = "cell·ray·freq updates/s per formal solve; ALI solves/s; p50/p99 latency"
 
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 VALU lane-operations/s
-# (one non-packed FP32 op per lane per cycle; packed FP32 is disabled in this build).
+# (one non-packed FP32 op per lane per cycle; the library is compiled without packed FP32).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic VALU lane-operations of one FP32 difference-form update (closed-form
 # branch): 3 bilinear interpolations (I-, S-, chi-: 4 each), dtau (2), exp (scale 1 +
