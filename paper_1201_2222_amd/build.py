@@ -20,16 +20,20 @@ SOURCES = ["rt_kernels.hip", "rt_plane.hip", "rt_gs.hip", "rt_api.cpp"]
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source (all at once, one hipcc each) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for proc, cmd in procs if proc.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
