@@ -158,6 +158,32 @@ rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *
 rt_status rt_problem_reset_periodic(rt_problem *p, void *stream);
 
 /*
+ * Checkpoint and resume of the periodic memory.  Besides S (the caller's), the only
+ * state an iteration hands to the next is what section 3's iteration for periodic
+ * boundaries keeps: the intensities each ray carried out of its periodic faces on the
+ * last sweep, which the next sweep reads as ghosts (or, on a cold problem, the flag
+ * that S of the wrapped vertex stands in for them).  Saving that memory with S and
+ * loading both into a problem of the same description continues an ALI (warm_start =
+ * 1) with bitwise the results of the uninterrupted run, in this or another process.
+ *
+ * rt_problem_state_bytes -- size of the saved state (a header, the per-bin slot
+ *   selectors and the periodic buffers, about nf * na * 2 * (sum over periodic axes of
+ *   the face's vertices) * 8 bytes; for the quadratic interpolation the plane buffers
+ *   nf * na * 2 * (largest face) reals plus, in FP32, nf * na * (largest face) * 8).
+ * rt_problem_save_state -- write the state to dst (host or device, `bytes` >= the
+ *   size above, else RT_E_INVALID).  Synchronises the stream first: the state is the
+ *   one left by the work queued before the call.
+ * rt_problem_load_state -- read a state saved from a problem with the same shape, bin
+ *   count, angle set, precision, interpolation and periodic axes (else RT_E_INVALID,
+ *   and the problem is unchanged).  rt_problem_set_fields resets the periodic memory,
+ *   so load after setting the fields.  Synchronises the stream first.
+ * Neither call may overlap a batch or a server solve of the same problem.
+ */
+rt_status rt_problem_state_bytes(rt_problem *p, size_t *bytes);
+rt_status rt_problem_save_state(rt_problem *p, void *dst, size_t bytes, void *stream);
+rt_status rt_problem_load_state(rt_problem *p, const void *src, size_t bytes, void *stream);
+
+/*
  * rt_formal_solve -- one formal solution J = Lambda[S] (section 3.4, eq. formalsol):
  * every ray is integrated once over the grid (section 3.3).  Periodic ghosts come
  * from the previous sweep of this problem (section 3's iteration for periodic

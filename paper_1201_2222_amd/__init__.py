@@ -26,7 +26,8 @@ RT_INTERP_BILINEAR, RT_INTERP_QUADRATIC = 0, 1
 
 # names of the C entry points (include/rt.h); every one is looked up at load time
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
-           "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_formal_solve",
+           "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_problem_state_bytes",
+           "rt_problem_save_state", "rt_problem_load_state", "rt_formal_solve",
            "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_problem_set_waves",
            "rt_problem_tune", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
            "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
@@ -93,6 +94,9 @@ def load():
     lib.rt_problem_destroy.argtypes = [P]
     lib.rt_problem_set_fields.argtypes = [P, P, P, P, P]
     lib.rt_problem_reset_periodic.argtypes = [P, P]
+    lib.rt_problem_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.rt_problem_save_state.argtypes = [P, P, ctypes.c_size_t, P]
+    lib.rt_problem_load_state.argtypes = [P, P, ctypes.c_size_t, P]
     lib.rt_formal_solve.argtypes = [P, P, P, P, P]
     lib.rt_ali_solve.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_ali_solve_gs.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
@@ -220,6 +224,38 @@ def rt_problem_set_fields(p, chi, eps, B, stream=None):
 
 def rt_problem_reset_periodic(p, stream=None):
     return _check(load().rt_problem_reset_periodic(p, _stream(stream)))
+
+
+def _raw(buf):
+    """Address and size in bytes of a contiguous numpy array or torch tensor."""
+    if isinstance(buf, np.ndarray):
+        if not buf.flags["C_CONTIGUOUS"]:
+            raise ValueError("state buffer must be contiguous")
+        return ctypes.c_void_p(buf.ctypes.data), buf.nbytes
+    if not buf.is_contiguous():
+        raise ValueError("state buffer must be contiguous")
+    return ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
+
+
+def rt_problem_state_bytes(p):
+    b = ctypes.c_size_t()
+    _check(load().rt_problem_state_bytes(p, ctypes.byref(b)))
+    return b.value
+
+
+def rt_problem_save_state(p, dst=None, stream=None):
+    """Save the periodic memory into ``dst`` (numpy array or torch tensor, host or
+    device) or, if None, into a new host uint8 array, which is returned."""
+    if dst is None:
+        dst = np.zeros(rt_problem_state_bytes(p), dtype=np.uint8)
+    ptr, nb = _raw(dst)
+    _check(load().rt_problem_save_state(p, ptr, nb, _stream(stream)))
+    return dst
+
+
+def rt_problem_load_state(p, src, stream=None):
+    ptr, nb = _raw(src)
+    return _check(load().rt_problem_load_state(p, ptr, nb, _stream(stream)))
 
 
 def rt_formal_solve(p, S, J, lambda_star=None, stream=None):
@@ -352,6 +388,15 @@ class Problem:
 
     def reset_periodic(self, stream=None):
         rt_problem_reset_periodic(self.handle, stream)
+
+    def state_bytes(self):
+        return rt_problem_state_bytes(self.handle)
+
+    def save_state(self, dst=None, stream=None):
+        return rt_problem_save_state(self.handle, dst, stream)
+
+    def load_state(self, src, stream=None):
+        rt_problem_load_state(self.handle, src, stream)
 
     def formal_solve(self, S, J, lambda_star=None, stream=None):
         rt_formal_solve(self.handle, S, J, lambda_star, stream)

@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <utility>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -1268,6 +1269,107 @@ rt_status rt_problem_reset_periodic(rt_problem *p, void *stream)
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
     HIP_TRY(hipMemsetAsync(p->parity, 0, sizeof(int) * p->nf, static_cast<hipStream_t>(stream)));
     p->cold = true;
+    return RT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Saved periodic memory: this header, the per-bin slot selectors, then the buffers
+// the next sweep may read, each padded to 256 bytes.
+struct StateHeader {
+    char magic[8];
+    int32_t n[3], nf, na, f32, plane_order, periodic, cold, pad;
+    int64_t bytes;
+};
+constexpr char kStateMagic[8] = {'R', 'T', 'S', 'C', 'S', 'T', '0', '1'};
+
+inline size_t pad256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// The device buffers that carry the periodic memory from one sweep to the next.
+std::vector<std::pair<void *, size_t>> state_buffers(rt_problem *p)
+{
+    std::vector<std::pair<void *, size_t>> v;
+    v.push_back({p->parity, sizeof(int) * p->nf});
+    const size_t rs = p->f32 ? 4 : 8;
+    if (p->plane_order) {
+        v.push_back({p->planes, (size_t)p->nf * p->na * 2 * p->pmax * rs});
+        if (p->wrapI) v.push_back({p->wrapI, (size_t)p->nf * p->na * p->pmax * 8});
+    } else {
+        for (int q = 0; q < 3; ++q)
+            if (p->wrap[q]) v.push_back({p->wrap[q], (size_t)p->nf * p->na * 2 * p->plane[q] * 8});
+    }
+    return v;
+}
+
+StateHeader state_header(rt_problem *p)
+{
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    for (int q = 0; q < 3; ++q) h.n[q] = p->n[q];
+    h.nf = p->nf;
+    h.na = p->na;
+    h.f32 = p->f32;
+    h.plane_order = p->plane_order;
+    h.periodic = p->periodic[0] | p->periodic[1] << 1 | p->periodic[2] << 2;
+    h.cold = p->cold;
+    h.bytes = (int64_t)pad256(sizeof(StateHeader));
+    for (auto &b : state_buffers(p)) h.bytes += (int64_t)pad256(b.second);
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+rt_status rt_problem_state_bytes(rt_problem *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(RT_E_INVALID, "problem and bytes are required");
+    *bytes = (size_t)state_header(p).bytes;
+    return RT_OK;
+}
+
+rt_status rt_problem_save_state(rt_problem *p, void *dst, size_t bytes, void *stream)
+{
+    if (!p || !dst) return fail(RT_E_INVALID, "problem and dst are required");
+    const StateHeader h = state_header(p);
+    if (bytes < (size_t)h.bytes) return fail(RT_E_INVALID, "dst holds %zu bytes, the state needs %lld", bytes,
+                                             (long long)h.bytes);
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    unsigned char *o = static_cast<unsigned char *>(dst);
+    HIP_TRY(hipMemcpy(o, &h, sizeof h, hipMemcpyDefault));
+    size_t off = pad256(sizeof h);
+    for (auto &b : state_buffers(p)) {
+        HIP_TRY(hipMemcpy(o + off, b.first, b.second, hipMemcpyDefault));
+        off += pad256(b.second);
+    }
+    return RT_OK;
+}
+
+rt_status rt_problem_load_state(rt_problem *p, const void *src, size_t bytes, void *stream)
+{
+    if (!p || !src) return fail(RT_E_INVALID, "problem and src are required");
+    if (bytes < sizeof(StateHeader)) return fail(RT_E_INVALID, "src holds %zu bytes, less than a header", bytes);
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    StateHeader h;
+    HIP_TRY(hipMemcpy(&h, src, sizeof h, hipMemcpyDefault));
+    const StateHeader mine = state_header(p);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(RT_E_INVALID, "src is not a saved problem state");
+    const bool cold = h.cold != 0;
+    h.cold = mine.cold;   // the one field that may differ
+    if (std::memcmp(&h, &mine, sizeof h) != 0)
+        return fail(RT_E_INVALID, "the saved state belongs to a problem of another shape, bin count, angle set, "
+                                  "precision, interpolation or periodic axes");
+    if (bytes < (size_t)h.bytes) return fail(RT_E_INVALID, "src holds %zu bytes, the state needs %lld", bytes,
+                                             (long long)h.bytes);
+    const unsigned char *in = static_cast<const unsigned char *>(src);
+    size_t off = pad256(sizeof h);
+    for (auto &b : state_buffers(p)) {
+        HIP_TRY(hipMemcpy(b.first, in + off, b.second, hipMemcpyDefault));
+        off += pad256(b.second);
+    }
+    p->cold = cold;
     return RT_OK;
 }
 

@@ -149,3 +149,12 @@ def test_gauss_seidel_argument_errors(rt):
     st = rt.AliStats()
     assert lib.rt_ali_solve_gs(None, ctypes.byref(o), None, None, ctypes.byref(st), None) == rt.RT_E_INVALID
     assert lib.rt_ali_solve_gs(None, None, None, None, None, None) == rt.RT_E_INVALID
+
+
+def test_checkpoint_argument_errors(rt):
+    lib = rt.load()
+    b = ctypes.c_size_t()
+    buf = (ctypes.c_ubyte * 64)()
+    assert lib.rt_problem_state_bytes(None, ctypes.byref(b)) == rt.RT_E_INVALID
+    assert lib.rt_problem_save_state(None, buf, 64, None) == rt.RT_E_INVALID
+    assert lib.rt_problem_load_state(None, buf, 64, None) == rt.RT_E_INVALID
