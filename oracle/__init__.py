@@ -56,9 +56,12 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("RTSC_ORACLE_LIB")   # another build of rt_oracle.c (sanitizers)
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.orc_sweep.argtypes = [ctypes.POINTER(_Grid), P, P, P, P, P, P, P, ctypes.c_int, P, P,
                                   P, P, P, P]
