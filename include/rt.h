@@ -32,6 +32,10 @@
  *     rt_last_error().  No call throws.
  *   - Streams are hipStream_t values passed as void* (NULL = the null stream).
  *   - A problem is used by one host thread at a time.
+ *   - Environment: RTSC_TILE_ORDER_SEED = n (n != 0) when a problem is created makes
+ *     each launch of the tile wavefront take the tiles of its stage in an order
+ *     shuffled with seed n.  Tiles of one stage are independent, so results are
+ *     bitwise those of the default order; the switch exists to check that.
  */
 #ifndef RTSC_RT_H
 #define RTSC_RT_H

@@ -12,12 +12,14 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <random>
 #include <thread>
 #include <utility>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -1130,6 +1132,17 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
             }
     }
     p->stage_off[p->nstages] = (int)tiles.size();
+    // RTSC_TILE_ORDER_SEED = n != 0: the tiles of every stage in a pseudo-random order
+    // seeded with n.  Tiles of one stage are independent, so results stay bitwise the
+    // same; a test of that checks the schedule for races.
+    if (const char *seed = std::getenv("RTSC_TILE_ORDER_SEED")) {
+        const unsigned long long v = std::strtoull(seed, nullptr, 10);
+        if (v != 0) {
+            std::mt19937_64 gen(v);
+            for (int s2 = 0; s2 < p->nstages; ++s2)
+                std::shuffle(tiles.begin() + p->stage_off[s2], tiles.begin() + p->stage_off[s2 + 1], gen);
+        }
+    }
 
     const int64_t nc = p->cells * p->nf;
     const size_t rs = real_size(desc);
