@@ -1,0 +1,153 @@
+"""Failure reporting of the Lambda iteration, forced from the host: an iteration cap
+below what the tolerance needs gives RT_NOT_CONVERGED with the results of exactly that
+many iterations; a NaN or an Inf in the fields gives RT_E_NONFINITE (the residual
+reduction flags it) in single solves, Gauss-Seidel, batches (only the problem at fault;
+the others finish with their own results) and the serving loop, which keeps serving."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1201_2222_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (20, 14, 12)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1201_2222_amd as rt
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    rt.load()
+    return rt, torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _make(env, wl, precision, chi=None, B=None):
+    rt, torch = env
+    p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
+                   precision=precision)
+    p.set_fields(_dev(torch, wl.chi if chi is None else chi), _dev(torch, wl.eps),
+                 _dev(torch, wl.B if B is None else B))
+    n = wl.chi.size
+    return p, torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("gs", [False, True])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_iteration_cap_reports_not_converged(env, gs, prec):
+    rt, torch = env
+    precision = rt.RT_F64 if prec == "f64" else rt.RT_F32
+    wl = W.random_problem(SHAPE, nf=2, seed=1500, n_mu=4, eps_range=(1e-3, 1e-2))
+    for cap in (1, 5):
+        p, S, J = _make(env, wl, precision)
+        solve = p.ali_solve_gs if gs else p.ali_solve
+        status, stats = solve(S, J, delta_c=1e-12, max_iter=cap, check_every=2)
+        torch.cuda.synchronize()
+        assert status == rt.RT_NOT_CONVERGED
+        assert stats["iterations"] == cap and stats["bins_converged"] == 0
+        assert np.isfinite(stats["max_rel_dS"]) and stats["max_rel_dS"] > 1e-12
+        iters, resid = rt.rt_ali_bin_stats(p.handle, wl.nf)
+        assert list(iters) == [cap] * wl.nf and np.all(resid > 1e-12)
+        q, S2, J2 = _make(env, wl, precision)
+        status2, _ = (q.ali_solve_gs if gs else q.ali_solve)(S2, J2, fixed_iters=cap, check_every=2)
+        torch.cuda.synchronize()
+        assert status2 == rt.RT_OK
+        assert np.array_equal(S.cpu().numpy(), S2.cpu().numpy())
+        assert np.array_equal(J.cpu().numpy(), J2.cpu().numpy())
+        p.close()
+        q.close()
+
+
+def _poisoned(wl, what):
+    chi, B = wl.chi.copy(), wl.B.copy()
+    if what == "nan_chi":
+        chi[1, 5, 3, 7] = np.nan
+    else:
+        B[0, 2, 9, 11] = np.inf
+    return chi, B
+
+
+@pytest.mark.parametrize("gs", [False, True])
+@pytest.mark.parametrize("what", ["nan_chi", "inf_B"])
+def test_nonfinite_fields_are_reported(env, gs, what):
+    rt, torch = env
+    wl = W.random_problem(SHAPE, nf=2, seed=1510, n_mu=4)
+    chi, B = _poisoned(wl, what)
+    for fixed in (0, 6):
+        p, S, J = _make(env, wl, rt.RT_F32, chi=chi, B=B)
+        with pytest.raises(rt.RtError) as e:
+            (p.ali_solve_gs if gs else p.ali_solve)(S, J, delta_c=1e-6, max_iter=200, fixed_iters=fixed,
+                                                     check_every=4)
+        assert e.value.status == rt.RT_E_NONFINITE
+        p.close()
+    # the library still works: a clean problem solves
+    p, S, J = _make(env, wl, rt.RT_F32)
+    status, _ = (p.ali_solve_gs if gs else p.ali_solve)(S, J, delta_c=1e-6, max_iter=2000, check_every=4)
+    assert status == rt.RT_OK
+    p.close()
+
+
+def test_batch_flags_only_the_problem_at_fault(env):
+    rt, torch = env
+    wls = [W.random_problem(SHAPE, nf=2, seed=1520 + k, n_mu=4) for k in range(3)]
+    chi, B = _poisoned(wls[1], "nan_chi")
+    made = [_make(env, wls[0], rt.RT_F32), _make(env, wls[1], rt.RT_F32, chi=chi, B=B),
+            _make(env, wls[2], rt.RT_F64)]
+    status, res, stats = rt.rt_ali_solve_batch([m[0].handle for m in made], [m[1] for m in made],
+                                               [m[2] for m in made], delta_c=1e-6, max_iter=3000, check_every=8)
+    torch.cuda.synchronize()
+    assert status == rt.RT_E_NONFINITE
+    assert res[0] == rt.RT_OK and res[1] == rt.RT_E_NONFINITE and res[2] == rt.RT_OK
+    for k in (0, 2):
+        p, S, J = _make(env, wls[k], rt.RT_F32 if k == 0 else rt.RT_F64)
+        p.ali_solve(S, J, delta_c=1e-6, max_iter=3000, check_every=8)
+        torch.cuda.synchronize()
+        assert np.array_equal(made[k][1].cpu().numpy(), S.cpu().numpy())
+        p.close()
+    for m in made:
+        m[0].close()
+
+
+def _wait(rt, srv, tickets, limit=60.0):
+    out, t0 = {}, time.time()
+    while len(out) < len(tickets):
+        assert time.time() - t0 < limit, "server did not finish"
+        for t in tickets:
+            if t not in out:
+                r = rt.rt_server_poll(srv, t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.005)
+    return out
+
+
+def test_server_reports_each_request(env):
+    rt, torch = env
+    wls = [W.random_problem(SHAPE, nf=2, seed=1530 + k, n_mu=4, eps_range=(1e-3, 1e-2)) for k in range(3)]
+    chi, B = _poisoned(wls[1], "inf_B")
+    ok = _make(env, wls[0], rt.RT_F32)
+    bad = _make(env, wls[1], rt.RT_F32, chi=chi, B=B)
+    capped = _make(env, wls[2], rt.RT_F32)
+    srv = rt.rt_server_create(1 << 34, check_every=4)
+    t_ok = rt.rt_server_submit(srv, ok[0].handle, ok[1], ok[2], delta_c=1e-6, max_iter=5000)
+    t_bad = rt.rt_server_submit(srv, bad[0].handle, bad[1], bad[2], delta_c=1e-6, max_iter=5000)
+    t_cap = rt.rt_server_submit(srv, capped[0].handle, capped[1], capped[2], delta_c=1e-12, max_iter=6)
+    out = _wait(rt, srv, [t_ok, t_bad, t_cap])
+    assert out[t_ok][0] == rt.RT_OK
+    assert out[t_bad][0] == rt.RT_E_NONFINITE
+    assert out[t_cap][0] == rt.RT_NOT_CONVERGED and out[t_cap][1]["iterations"] == 6
+    for t in (t_ok, t_bad, t_cap):
+        rt.rt_server_release(srv, t)
+    # still serving after the failures: the first problem again, warm-started
+    t2 = rt.rt_server_submit(srv, ok[0].handle, ok[1], ok[2], delta_c=1e-6, max_iter=5000, warm_start=1)
+    again = _wait(rt, srv, [t2])[t2]
+    assert again[0] == rt.RT_OK and again[1]["iterations"] < out[t_ok][1]["iterations"]
+    rt.rt_server_destroy(srv)
+    for m in (ok, bad, capped):
+        m[0].close()
