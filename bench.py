@@ -9,7 +9,8 @@ residuals until max |dS|/S <= 1e-6, then the moments epilogue (J, H, K, f = K/J,
 Q and the heating sum) on the converged S.  Inputs are resident in HBM before the timed
 region.  The JSON line reports cell*ray*bin updates per second over the timed
 steps, ALI solves/s, p50/p99 solve latency, the sweep kernel against its roofline
-(VALU-bound; durations from HIP events inside the library, see rt_problem_profile),
+(VALU-bound; durations from HIP events inside the library, see rt_problem_profile;
+with --ali gauss-seidel the chain kernel of the downward pass against HBM),
 the plain FP64 GPU solve for comparison, and the FP64 CPU oracle on a bounded
 sample of the same workload.
 """
@@ -44,14 +45,25 @@ OPS_PER_UPDATE_BEZ_F32 = 20 + 4 + 5 + 15 + 4 + 17 + 3 + 1
 # control point (9 each: 36), I- - S- and its conversion (2), S- (FP64) and chi-
 # bilinear (8), dtau (2), exp (5), g (6), D update (3), accumulation (1).
 OPS_PER_UPDATE_QUAD_F32 = 9 + 36 + 2 + 8 + 2 + 5 + 6 + 3 + 1
+# HBM: 8 TB/s.  The Gauss-Seidel chain kernel does 9 VALU operations per update
+# (3 for the new intensity, 5 for the recomputed one, 1 for its weight) against 24
+# bytes, so HBM is its roof.  Algorithmic bytes of one FP32 chain update (one vertex,
+# one ray crossing an x or y face first, one bin, in a step that computes a plane and
+# recomputes the one above): the four coefficients E and Q of the new and the
+# recomputed intensity read (16), the new intensity and the weighted recomputed one
+# written (8).
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CHAIN_UPDATE_F32 = 16 + 4 + 4
 
 
 TRAFFIC_PROFILE = {"linear": os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md"),
                    "bezier": os.path.join(ROOT, "profiles", "sweep_stage_f32_bezier_scattering128_traffic.md"),
-                   "quadratic": os.path.join(ROOT, "profiles", "plane_step_f32_quadratic_scattering128_traffic.md")}
+                   "quadratic": os.path.join(ROOT, "profiles", "plane_step_f32_quadratic_scattering128_traffic.md"),
+                   "gauss-seidel": os.path.join(ROOT, "profiles", "gs_chain_f32_scattering128_traffic.md")}
 KERNEL_SOURCE = {"linear": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
                  "bezier": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
-                 "quadratic": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_plane.hip")}
+                 "quadratic": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_plane.hip"),
+                 "gauss-seidel": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_gs.hip")}
 
 
 def measured_traffic(order="linear"):
@@ -443,7 +455,8 @@ def main():
     torch.cuda.synchronize()
     prof = rt.rt_problem_profile_read(prob.handle)
     rt.rt_problem_profile(prob.handle, False)
-    print(f"profiled step: {prof['launches']} timed launches", file=sys.stderr, flush=True)
+    print(f"profiled step: {prof['launches']} timed sweep launches, {prof['chain_launches']} timed chain launches",
+          file=sys.stderr, flush=True)
 
     # one sweep per ALI iteration plus the moments sweep
     updates = float(wl.cells * wl.na * wl.nf * (sum(iters) + len(iters)))
@@ -458,9 +471,18 @@ def main():
                 "timed_launches": prof["launches"],
                 "ops_per_update": ops_per_update}
     if gs:
-        # the timed-sweep hooks cover the Jacobi sweep only; the Gauss-Seidel kernels are
-        # timed with rocprofv3 (plane and chain launches are latency-bound)
-        roofline = None
+        # the dominant kernel of Gauss-Seidel is the chain kernel of the downward pass
+        chain_s = prof["chain_ms"] / 1e3
+        achieved = prof["chain_updates"] * BYTES_PER_CHAIN_UPDATE_F32 / chain_s / 1e9 if chain_s > 0 else 0.0
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("gauss-seidel"),
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "kernel": "gs_chain_kernel<float, true, 2, true, true, true>",
+                    "avg_launch_us": prof["chain_ms"] * 1e3 / max(prof["chain_launches"], 1),
+                    "timed_launches": prof["chain_launches"],
+                    "algorithmic_bytes_per_launch": prof["chain_updates"] * BYTES_PER_CHAIN_UPDATE_F32
+                    / max(prof["chain_launches"], 1),
+                    "bytes_per_update": BYTES_PER_CHAIN_UPDATE_F32}
 
     extra = {}
     if not args.no_f64:

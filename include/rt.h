@@ -377,15 +377,21 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
  * each convergence-check interval of rt_ali_solve, and every rt_formal_solve) are
  * bracketed by two HIP events on the call's stream, after the ghost-value pass and
  * after the last stage; the durations are summed when the events have completed,
- * so a launch's share includes the gap to the next launch.  Enabling (or
- * disabling) resets the totals.
+ * so a launch's share includes the gap to the next launch.  In rt_ali_solve_gs the
+ * same first iteration of each interval also times the chain launches of the
+ * downward pass that compute a plane and recompute the one above (steps 1 .. nz-1;
+ * rays crossing an x or y face first), each by a pair of events that take the start
+ * and end of that dispatch itself; the chain_* fields sum those.  Enabling (or disabling) resets the totals.
  */
 typedef struct {
-    double kernel_ms;     /* summed duration of the timed back-to-back stage launches */
-    int64_t launches;     /* number of timed launches */
-    int64_t sweeps;       /* number of timed formal solutions */
-    double updates;       /* cell*ray*bin updates done by those launches */
-    int32_t stages;       /* launches per formal solution */
+    double kernel_ms;       /* summed duration of the timed back-to-back stage launches */
+    int64_t launches;       /* number of timed launches */
+    int64_t sweeps;         /* number of timed formal solutions */
+    double updates;         /* cell*ray*bin updates done by those launches */
+    int32_t stages;         /* launches per formal solution */
+    double chain_ms;        /* Gauss-Seidel: summed duration of the timed chain launches */
+    int64_t chain_launches; /* number of timed chain launches */
+    double chain_updates;   /* vertex*ray*bin chain updates they did (each a new and a recomputed intensity) */
 } rt_profile;
 
 rt_status rt_problem_profile(rt_problem *p, int32_t enable);

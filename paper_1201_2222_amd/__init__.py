@@ -69,7 +69,8 @@ class MomentsOut(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("launches", ctypes.c_int64), ("sweeps", ctypes.c_int64),
-                ("updates", ctypes.c_double), ("stages", ctypes.c_int32)]
+                ("updates", ctypes.c_double), ("stages", ctypes.c_int32), ("chain_ms", ctypes.c_double),
+                ("chain_launches", ctypes.c_int64), ("chain_updates", ctypes.c_double)]
 
 
 _lib = None
@@ -370,7 +371,8 @@ def rt_problem_profile_read(p):
     out = Profile()
     _check(load().rt_problem_profile_read(p, ctypes.byref(out)))
     return {"kernel_ms": out.kernel_ms, "launches": out.launches, "sweeps": out.sweeps, "updates": out.updates,
-            "stages": out.stages}
+            "stages": out.stages, "chain_ms": out.chain_ms, "chain_launches": out.chain_launches,
+            "chain_updates": out.chain_updates}
 
 
 class Problem:

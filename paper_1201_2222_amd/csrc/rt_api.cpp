@@ -301,6 +301,11 @@ struct rt_problem {
     void *gs_chi_t = nullptr;          // Real [nf][nz][nx][ny]
     double *gs_S_t = nullptr;          // [nf][nz][nx][ny]
     int *d_gs_down = nullptr;          // [nd] rays going down, shallow ones first
+    // timing of the Gauss-Seidel chain launches (one iteration per check interval)
+    std::vector<hipEvent_t> gs_ev;     // [2 nz]: before and after the chain launch of step t
+    bool gs_prof_pending = false;
+    double gs_prof_ms = 0.0, gs_prof_updates = 0.0, gs_pending_updates = 0.0;
+    int64_t gs_prof_launches = 0;
     int gs_nd = 0, gs_ns = 0;
     int *h_flags = nullptr;            // pinned host copy of flags
     int *h_frozen = nullptr;           // pinned host copy of frozen
@@ -498,6 +503,20 @@ int sweep_waves(int R, bool f32, int order, size_t lds_limit)
 // every launch), so a launch's share includes the gap to the next launch.
 rt_status collect_timing(rt_problem *p)
 {
+    if (p->gs_prof_pending) {
+        // chain launches of steps 1 .. nz-1 (those that compute a plane and recompute
+        // the one above: one kernel variant)
+        const int nz = p->n[2];
+        HIP_TRY(hipEventSynchronize(p->gs_ev[2 * (nz - 1) + 1]));
+        for (int t = 1; t < nz; ++t) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, p->gs_ev[2 * t], p->gs_ev[2 * t + 1]));
+            p->gs_prof_ms += ms;
+        }
+        p->gs_prof_launches += nz - 1;
+        p->gs_prof_updates += p->gs_pending_updates;
+        p->gs_prof_pending = false;
+    }
     if (!p->prof_pending) return RT_OK;
     HIP_TRY(hipEventSynchronize(p->ev[1]));
     float ms = 0.0f;
@@ -1064,6 +1083,7 @@ rt_status rt_problem_destroy(rt_problem *p)
     if (p->h_sum) (void)hipHostFree(p->h_sum);
     if (p->h_frozen) (void)hipHostFree(p->h_frozen);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->gs_ev) (void)hipEventDestroy(e);
     for (auto &g : p->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -1509,7 +1529,7 @@ GsArgs<Real> gs_args(rt_problem *p, double *S, double *J)
 // (octants 0 .. 3 of the tile wavefront), then the rays going down plane by plane from
 // the top with each plane's update as soon as its J is complete.
 template <typename Real>
-rt_status gs_iteration(rt_problem *p, double *S, double *J, hipStream_t st)
+rt_status gs_iteration(rt_problem *p, double *S, double *J, hipStream_t st, bool timed, int active_bins)
 {
     HIP_TRY(launch_gs_clear(p->blockmax, (int64_t)p->nf * kUpdateBlocks, st));
     SweepArgs<Real> U = sweep_args<Real>(p, S);
@@ -1532,9 +1552,19 @@ rt_status gs_iteration(rt_problem *p, double *S, double *J, hipStream_t st)
     const int nz = p->n[2];
     // launch nz recomputes plane 0 only for the periodic memory of the in-plane axes
     const int last = (p->periodic[0] || p->periodic[1]) ? nz : nz - 1;
+    timed = timed && p->prof && !p->gs_prof_pending && nz > 1 && p->gs_ns > 0;
+    if (timed && p->gs_ev.empty()) {
+        p->gs_ev.resize(2 * (size_t)nz);
+        for (auto &e : p->gs_ev) HIP_TRY(hipEventCreate(&e));
+    }
     for (int t = 0; t <= last; ++t) {
-        HIP_TRY(launch_gs_plane<Real>(A, t, st));
+        const bool tt = timed && t >= 1 && t < nz;
+        HIP_TRY(launch_gs_plane<Real>(A, t, st, tt ? p->gs_ev[2 * t] : nullptr, tt ? p->gs_ev[2 * t + 1] : nullptr));
         if (t < nz) HIP_TRY(launch_gs_update<Real>(A, nz - 1 - t, st));
+    }
+    if (timed) {
+        p->gs_prof_pending = true;
+        p->gs_pending_updates = (double)(nz - 1) * p->gs_ns * (double)p->n[0] * p->n[1] * active_bins;
     }
     return RT_OK;
 }
@@ -1668,8 +1698,8 @@ rt_status ali_run(rt_problem *p, const rt_ali_opts *opts, double *S_inout, doubl
     auto chunk = [&](int k, hipStream_t cs) -> rt_status {
         for (int j = 0; j < k; ++j) {
             if (gs) {
-                rt_status s = p->f32 ? gs_iteration<float>(p, S_inout, J_out, cs)
-                                     : gs_iteration<double>(p, S_inout, J_out, cs);
+                rt_status s = p->f32 ? gs_iteration<float>(p, S_inout, J_out, cs, j == 0, active)
+                                     : gs_iteration<double>(p, S_inout, J_out, cs, j == 0, active);
                 if (s != RT_OK) return s;
                 HIP_TRY(launch_ali_finalize(ctl, p->nf, opts->delta_c, opts->per_bin_stop ? 1 : 0, fixed ? 1 : 0, cs));
                 continue;
@@ -1869,6 +1899,8 @@ rt_status rt_problem_profile(rt_problem *p, int32_t enable)
     p->prof = enable != 0;
     p->prof_ms = p->prof_updates = 0.0;
     p->prof_launches = p->prof_sweeps = 0;
+    p->gs_prof_ms = p->gs_prof_updates = 0.0;
+    p->gs_prof_launches = 0;
     return RT_OK;
 }
 
@@ -1882,6 +1914,9 @@ rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out)
     out->sweeps = p->prof_sweeps;
     out->updates = p->prof_updates;
     out->stages = p->nstages;
+    out->chain_ms = p->gs_prof_ms;
+    out->chain_launches = p->gs_prof_launches;
+    out->chain_updates = p->gs_prof_updates;
     return RT_OK;
 }
 

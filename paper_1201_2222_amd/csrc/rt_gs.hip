@@ -33,6 +33,7 @@
 // FP64); the periodic memory keeps I in FP64 in the layout of the sweep kernels (the
 // flipped coordinates of each ray's octant).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 
@@ -662,31 +663,41 @@ __global__ void gs_clear_kernel(unsigned long long *p, int64_t n)
     if (i < n) p[i] = 0ull;
 }
 
-template <typename Real, bool DF, int M, bool FULL>
-void launch_chain_f(const GsArgs<Real> &A, int t, int kind, hipStream_t st)
+// e0/e1 (or null): events that take the start and end time of this dispatch
+template <typename Real, bool DF, int M, bool NEW, bool OLD, bool FULL>
+void launch_chain_k(const GsArgs<Real> &A, int t, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid((unsigned)A.ns, (unsigned)A.nf);
-    if (kind == 0)
-        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, false, true, FULL>), grid, dim3(64), 0, st, A, t);
-    else if (kind == 1)
-        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, true, true, FULL>), grid, dim3(64), 0, st, A, t);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(gs_chain_kernel<Real, DF, M, NEW, OLD, FULL>, grid, dim3(64), 0, st, e0, e1, 0, A, t);
     else
-        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, true, false, FULL>), grid, dim3(64), 0, st, A, t);
+        hipLaunchKernelGGL((gs_chain_kernel<Real, DF, M, NEW, OLD, FULL>), grid, dim3(64), 0, st, A, t);
+}
+
+template <typename Real, bool DF, int M, bool FULL>
+void launch_chain_f(const GsArgs<Real> &A, int t, int kind, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    if (kind == 0)
+        launch_chain_k<Real, DF, M, false, true, FULL>(A, t, st, e0, e1);
+    else if (kind == 1)
+        launch_chain_k<Real, DF, M, true, true, FULL>(A, t, st, e0, e1);
+    else
+        launch_chain_k<Real, DF, M, true, false, FULL>(A, t, st, e0, e1);
 }
 
 template <typename Real, bool DF, int M>
-void launch_chain_m(const GsArgs<Real> &A, int t, int kind, bool full, hipStream_t st)
+void launch_chain_m(const GsArgs<Real> &A, int t, int kind, bool full, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     if (full)
-        launch_chain_f<Real, DF, M, true>(A, t, kind, st);
+        launch_chain_f<Real, DF, M, true>(A, t, kind, st, e0, e1);
     else
-        launch_chain_f<Real, DF, M, false>(A, t, kind, st);
+        launch_chain_f<Real, DF, M, false>(A, t, kind, st, e0, e1);
 }
 
 }  // namespace
 
 template <typename Real>
-hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st)
+hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st, hipEvent_t before, hipEvent_t after)
 {
     constexpr bool DF = sizeof(Real) == 4;
     const int64_t cb = (A.pxy + 255) / 256;
@@ -702,11 +713,11 @@ hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st)
         const int nz = A.n[2];
         const int kind = t == 0 ? 0 : (t == nz ? 2 : 1);   // old only, both, new only
         if (M == 1)
-            launch_chain_m<Real, DF, 1>(A, t, kind, full, st);
+            launch_chain_m<Real, DF, 1>(A, t, kind, full, st, before, after);
         else if (M == 2)
-            launch_chain_m<Real, DF, 2>(A, t, kind, full, st);
+            launch_chain_m<Real, DF, 2>(A, t, kind, full, st, before, after);
         else
-            launch_chain_m<Real, DF, 4>(A, t, kind, full, st);
+            launch_chain_m<Real, DF, 4>(A, t, kind, full, st, before, after);
     }
     return hipGetLastError();
 }
@@ -737,8 +748,8 @@ hipError_t launch_gs_transpose(const T *src, T *dst, int nf, const int n[3], hip
 
 template hipError_t launch_gs_transpose<float>(const float *, float *, int, const int[3], hipStream_t);
 template hipError_t launch_gs_transpose<double>(const double *, double *, int, const int[3], hipStream_t);
-template hipError_t launch_gs_plane<float>(const GsArgs<float> &, int, hipStream_t);
-template hipError_t launch_gs_plane<double>(const GsArgs<double> &, int, hipStream_t);
+template hipError_t launch_gs_plane<float>(const GsArgs<float> &, int, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_gs_plane<double>(const GsArgs<double> &, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_gs_update<float>(const GsArgs<float> &, int, hipStream_t);
 template hipError_t launch_gs_update<double>(const GsArgs<double> &, int, hipStream_t);
 

@@ -240,9 +240,11 @@ template <typename Real>
 hipError_t launch_plane_cold(const PlaneArgs<Real> &A, hipStream_t st);
 
 // Gauss-Seidel backward sweep (rt_gs.hip): launch t of the plane pass, the update of
-// plane k, and the cleared residual maxima of an iteration.
+// plane k, and the cleared residual maxima of an iteration.  before/after (or null):
+// events that take the start and end time of the chain launch of step t.
 template <typename Real>
-hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st);
+hipError_t launch_gs_plane(const GsArgs<Real> &A, int t, hipStream_t st, hipEvent_t before = nullptr,
+                           hipEvent_t after = nullptr);
 template <typename Real>
 hipError_t launch_gs_update(const GsArgs<Real> &A, int k, hipStream_t st);
 hipError_t launch_gs_clear(unsigned long long *blockmax, int64_t n, hipStream_t st);

@@ -212,3 +212,36 @@ def test_gs_bins_stop_at_different_iterations(env, oracle_mod, precision):
     assert _rel(S.cpu().numpy().reshape(ref["S"].shape), ref["S"]) <= tol
     assert _rel(J.cpu().numpy().reshape(ref["J"].shape), ref["J"]) <= tol
     gp.close()
+
+
+def test_gs_chain_launch_timing(env):
+    """rt_problem_profile times the chain launches of steps 1 .. nz-1 in the first
+    iteration of every check interval (the benchmark's roofline for Gauss-Seidel); the
+    counts follow the rays crossing an x or y face first, and timing leaves the results
+    as they are."""
+    rt, torch = env
+    wl = W.random_problem((20, 14, 12), nf=2, seed=1600, n_mu=4)
+    mu, _ = rt.rt_quadrature(4)
+    shallow = int(np.sum((mu[:, 2] < 0) & (np.argmax(np.abs(mu), axis=1) != 2)))
+    assert shallow == 8
+    out = []
+    for prof in (False, True):
+        gp = rt.Problem(wl.shape, nf=wl.nf, n_mu=4, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32)
+        gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+        gp.use_graphs(False)
+        rt.rt_problem_profile(gp.handle, prof)
+        S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+        J = torch.empty_like(S)
+        gp.ali_solve_gs(S, J, fixed_iters=8, check_every=4)
+        torch.cuda.synchronize()
+        p = rt.rt_problem_profile_read(gp.handle)
+        nz = wl.shape[2]
+        if prof:
+            assert p["chain_launches"] == 2 * (nz - 1)
+            assert p["chain_updates"] == 2 * (nz - 1) * shallow * 20 * 14 * wl.nf
+            assert p["chain_ms"] > 0.0
+        else:
+            assert p["chain_launches"] == 0 and p["chain_ms"] == 0.0
+        out.append((S.cpu().numpy(), J.cpu().numpy()))
+        gp.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
