@@ -83,6 +83,13 @@ def measured_traffic(order="linear"):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def _traffic_rate(roofline):
+    """Measured HBM bytes of one launch over its average duration (GB/s), or None."""
+    if roofline["traffic"] is None or roofline["avg_launch_us"] <= 0:
+        return None
+    return roofline["traffic"] / (roofline["avg_launch_us"] * 1e-6) / 1e9
+
+
 def _pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -470,6 +477,7 @@ def main():
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
                 "ops_per_update": ops_per_update}
+    roofline["traffic_gbs"] = _traffic_rate(roofline)
     if gs:
         # the dominant kernel of Gauss-Seidel is the chain kernel of the downward pass
         chain_s = prof["chain_ms"] / 1e3
@@ -483,6 +491,7 @@ def main():
                     "algorithmic_bytes_per_launch": prof["chain_updates"] * BYTES_PER_CHAIN_UPDATE_F32
                     / max(prof["chain_launches"], 1),
                     "bytes_per_update": BYTES_PER_CHAIN_UPDATE_F32}
+        roofline["traffic_gbs"] = _traffic_rate(roofline)
 
     extra = {}
     if not args.no_f64:
