@@ -21,8 +21,9 @@
  * Conventions shared by every entry point
  *   - Field layout: FP64, C order [nf][nz][ny][nx] (x fastest), one value per
  *     vertex and frequency bin.  "cells" = nx*ny*nz.
- *   - Device pointers are HIP device memory on the context's device; host
- *     pointers are ordinary host memory.  The caller owns every buffer it passes
+ *   - Device pointers are HIP device memory on the device that was current when
+ *     the problem was created, and calls on a problem are made with that device
+ *     current; host pointers are ordinary host memory.  The caller owns every buffer it passes
  *     and must keep device buffers alive until the stream work has finished.
  *     The library owns the per-problem state it allocates (internal copies of
  *     the fields, Lambda*, the periodic memory, scratch) and frees it in
