@@ -1,0 +1,128 @@
+"""Parity at the full sizes of the multi-frequency and batched workloads, in the launch
+configurations the benchmark times.
+
+* Multi-frequency: 192^3 with 80 rays on 8 of the 64 bins (one GPU's share; bins are
+  independent), all 8 bins in one problem as the benchmark runs them.  One Jacobi
+  iteration from S = B; J and S of one bin against the FP64 oracle on that bin alone
+  (a full formal solution at full size, about half a minute of CPU), and every bin
+  against the same bin solved alone on the GPU (bitwise: bins never interact).
+* Batched: all 96 uneven problems submitted at once to one server, three fixed
+  iterations each; sampled members (every angle set, one to sixteen bins) bitwise
+  equal to their single solves, and the smallest member within 2e-5 of the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1201_2222_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1201_2222_amd as rt
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    rt.load()
+    return rt, torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def _gpu_problem(rt, torch, wl):
+    p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
+                   precision=rt.RT_F32)
+    p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+    S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
+    return p, S, torch.empty_like(S)
+
+
+@pytest.mark.timeout(600)
+def test_multifreq_share_full_size(env, oracle_mod):
+    rt, torch = env
+    bins = np.linspace(0, 63, 8).round().astype(int)
+    wl = W.multifreq(n=192, nf=64, bins=bins)
+    p, S, J = _gpu_problem(rt, torch, wl)
+    p.ali_solve(S, J, fixed_iters=1)
+    torch.cuda.synchronize()
+    print("multifreq: 8 bins solved on the GPU", flush=True)
+    S_all = S.cpu().numpy().reshape(wl.chi.shape)
+    J_all = J.cpu().numpy().reshape(wl.chi.shape)
+    p.close()
+    del S, J
+    k = 3   # x_nu = 0.80: absorption and scattering both matter
+    one = W.Workload("multifreq", wl.shape, wl.n_mu, wl.chi[k:k + 1], wl.eps[k:k + 1], wl.B[k:k + 1],
+                     wl.w_nu[k:k + 1])
+    q, S1, J1 = _gpu_problem(rt, torch, one)
+    q.ali_solve(S1, J1, fixed_iters=1)
+    torch.cuda.synchronize()
+    assert np.array_equal(S1.cpu().numpy().reshape(S_all[k].shape), S_all[k])
+    assert np.array_equal(J1.cpu().numpy().reshape(J_all[k].shape), J_all[k])
+    q.close()
+    t0 = time.time()
+    op = oracle_mod.Problem(one.shape, one.chi, one.eps, one.B, n_mu=one.n_mu, bc_lo=one.bc_lo, bc_hi=one.bc_hi,
+                            w_nu=one.w_nu)
+    ref = op.ali(fixed_iters=1)
+    print(f"oracle: one iteration of one bin at 192^3 x 80 rays in {time.time() - t0:.1f} s", flush=True)
+    assert _rel(J_all[k], ref["J"][0]) <= TOL32
+    assert _rel(S_all[k], ref["S"][0]) <= TOL32
+
+
+@pytest.mark.timeout(600)
+def test_batched_members_full_size(env, oracle_mod):
+    rt, torch = env
+    count = 96
+    wls, made = [], []
+    for k in range(count):
+        wl = W.batched_problem(k)
+        made.append(_gpu_problem(rt, torch, wl))
+        wls.append(wl)
+    free, _ = torch.cuda.mem_get_info()
+    srv = rt.rt_server_create(int(0.8 * free), check_every=16)
+    tickets = [rt.rt_server_submit(srv, p.handle, S, J, fixed_iters=3) for p, S, J in made]
+    done = {}
+    t0 = time.time()
+    while len(done) < count:
+        assert time.time() - t0 < 100.0, "server did not finish"
+        for t in tickets:
+            if t not in done:
+                r = rt.rt_server_poll(srv, t)
+                if r is not None:
+                    done[t] = r
+        time.sleep(0.01)
+    rt.rt_server_destroy(srv)
+    print(f"batched: {count} problems served", flush=True)
+    assert all(done[t][0] == rt.RT_OK for t in tickets)
+    sizes = [w.cells * w.na * w.nf for w in wls]
+    smallest = int(np.argmin(sizes))
+    sample = {smallest, int(np.argmax(sizes))}
+    for na in (24, 48, 80):   # the largest member of each angle set and the one with most bins
+        ks = [k for k in range(count) if wls[k].na == na]
+        sample.add(max(ks, key=lambda k: sizes[k]))
+        sample.add(max(ks, key=lambda k: wls[k].nf))
+    for k in sorted(sample):
+        q, S1, J1 = _gpu_problem(rt, torch, wls[k])
+        q.ali_solve(S1, J1, fixed_iters=3)
+        torch.cuda.synchronize()
+        _, S, J = made[k]
+        assert np.array_equal(S1.cpu().numpy(), S.cpu().numpy()), k
+        assert np.array_equal(J1.cpu().numpy(), J.cpu().numpy()), k
+        q.close()
+    wl = wls[smallest]
+    op = oracle_mod.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi,
+                            w_nu=wl.w_nu)
+    ref = op.ali(fixed_iters=3)
+    _, S, J = made[smallest]
+    assert _rel(J.cpu().numpy().reshape(ref["J"].shape), ref["J"]) <= TOL32
+    assert _rel(S.cpu().numpy().reshape(ref["S"].shape), ref["S"]) <= TOL32
+    for p, _, _ in made:
+        p.close()
