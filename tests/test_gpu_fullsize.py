@@ -1,4 +1,4 @@
-"""Parity at the full sizes of the multi-frequency and batched workloads, in the launch
+"""Parity at the full sizes of the multi-frequency, batched and serving workloads, in the launch
 configurations the benchmark times.
 
 * Multi-frequency: 192^3 with 80 rays on 8 of the 64 bins (one GPU's share; bins are
@@ -8,7 +8,8 @@ configurations the benchmark times.
   against the same bin solved alone on the GPU (bitwise: bins never interact).
 * Batched: all 96 uneven problems submitted at once to one server, three fixed
   iterations each; sampled members (every angle set, one to sixteen bins) bitwise
-  equal to their single solves, and the smallest member within 2e-5 of the oracle."""
+  equal to their single solves, and the smallest member within 2e-5 of the oracle.
+* Serving: the request pool at its real sizes through one server that must queue."""
 import time
 
 import numpy as np
@@ -125,4 +126,72 @@ def test_batched_members_full_size(env, oracle_mod):
     assert _rel(J.cpu().numpy().reshape(ref["J"].shape), ref["J"]) <= TOL32
     assert _rel(S.cpu().numpy().reshape(ref["S"].shape), ref["S"]) <= TOL32
     for p, _, _ in made:
+        p.close()
+
+
+@pytest.mark.timeout(600)
+def test_serving_pool_full_size(env, oracle_mod):
+    """The serving pool at its real sizes (12 requests, 35^3 to 115^3, 9 to 31 bins, 48
+    rays) through one server whose budget holds about two requests, so requests queue and
+    are admitted while others run: each request's result is bitwise that of a twin
+    solved alone.  A second round warm-starts four drifting streams from eps B + (1-eps) J
+    with their new B, against their twins warm-started the same way; the smallest request
+    agrees with the oracle."""
+    rt, torch = env
+    pool = 12
+    wls = [W.serving_problem(k) for k in range(pool)]
+    served = [_gpu_problem(rt, torch, wl) for wl in wls]
+    twins = [_gpu_problem(rt, torch, wl) for wl in wls]
+    need = sorted(rt.rt_problem_bytes(p.desc) for p, _, _ in served)
+    srv = rt.rt_server_create(need[-1] + need[-2], check_every=4)
+
+    def serve(items, **kw):
+        tickets = [rt.rt_server_submit(srv, p.handle, S, J, fixed_iters=3, **kw) for p, S, J in items]
+        done, t0 = {}, time.time()
+        while len(done) < len(tickets):
+            assert time.time() - t0 < 200.0, "server did not finish"
+            for t in tickets:
+                if t not in done:
+                    r = rt.rt_server_poll(srv, t)
+                    if r is not None:
+                        done[t] = r
+            time.sleep(0.01)
+        for t in tickets:
+            assert done[t][0] == rt.RT_OK
+            rt.rt_server_release(srv, t)
+
+    serve(served)
+    print(f"serving: {pool} requests served", flush=True)
+    for (p, S, J), (q, S1, J1) in zip(served, twins):
+        q.ali_solve(S1, J1, fixed_iters=3)
+        torch.cuda.synchronize()
+        assert np.array_equal(S1.cpu().numpy(), S.cpu().numpy())
+        assert np.array_equal(J1.cpu().numpy(), J.cpu().numpy())
+    streams = range(4)
+    for k in streams:
+        wl = wls[k]
+        T = W.drift(wl.meta["T"], 1)
+        x = np.logspace(np.log10(0.05), np.log10(50.0), wl.nf)
+        B = np.stack([x[b] ** 3 / np.expm1(x[b] / T) for b in range(wl.nf)])
+        for p, _, _ in (served[k], twins[k]):
+            p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, B))
+    torch.cuda.synchronize()
+    serve([served[k] for k in streams], warm_start=2)
+    for k in streams:
+        q, S1, J1 = twins[k]
+        q.ali_solve(S1, J1, fixed_iters=3, warm_start=2)
+        torch.cuda.synchronize()
+        _, S, J = served[k]
+        assert np.array_equal(S1.cpu().numpy(), S.cpu().numpy()), k
+        assert np.array_equal(J1.cpu().numpy(), J.cpu().numpy()), k
+    rt.rt_server_destroy(srv)
+    k = int(np.argmin([w.cells * w.na * w.nf for w in wls[4:]])) + 4   # the streams' fields changed
+    wl = wls[k]
+    op = oracle_mod.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi,
+                            w_nu=wl.w_nu)
+    ref = op.ali(fixed_iters=3)
+    _, S, J = served[k]
+    assert _rel(J.cpu().numpy().reshape(ref["J"].shape), ref["J"]) <= TOL32
+    assert _rel(S.cpu().numpy().reshape(ref["S"].shape), ref["S"]) <= TOL32
+    for p, _, _ in served + twins:
         p.close()
