@@ -99,3 +99,39 @@ def test_moments_isotropic_exact(env):
     f = f_int.cpu().numpy().reshape(6, cells)
     assert np.allclose(f[:3], 1.0 / 3.0, rtol=1e-14) and np.max(np.abs(f[3:])) < 1e-15
     gp.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("variant", ["linear", "bezier", "quadratic"])
+def test_moments_full_size(env, oracle_mod, variant):
+    """The moments epilogue as the benchmark runs it (128^3 scattering workload, 48 rays,
+    FP32, frequency-integrated outputs and the heating sum) against the oracle's, for
+    each formal-solution variant of the benchmark."""
+    rt, torch = env
+    wl = W.scattering()
+    rng = np.random.default_rng(5)
+    S = (0.9 + 0.2 * rng.random(wl.chi.shape)) * wl.B
+    kw = {"order": 1 if variant == "bezier" else 0, "interp": 1 if variant == "quadratic" else 0}
+    op = oracle_mod.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi,
+                            w_nu=wl.w_nu, **kw)
+    ref = op.moments(S)
+    gp = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
+                    w_nu=wl.w_nu, order=kw["order"], interp=kw["interp"])
+    gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+    cells = wl.cells
+    z = lambda k: torch.zeros(k * cells, dtype=torch.float64, device="cuda")
+    out = dict(J_int=z(1), H_int=z(3), K_int=z(6), f_int=z(6), Q_int=z(1))
+    heat = gp.moments(_dev(torch, S), want_heating=True, **out)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    gp.close()
+    tol = 2e-5
+    Jint = ref["J_int"]
+    iscale = np.max(np.abs(Jint))
+    assert np.max(np.abs(g["J_int"].reshape(Jint.shape) - Jint) / Jint) <= 2 * tol
+    assert np.max(np.abs(g["H_int"].reshape(ref["H_int"].shape) - ref["H_int"])) <= 2 * tol * iscale
+    assert np.max(np.abs(g["K_int"].reshape(ref["K_int"].shape) - ref["K_int"])) <= 2 * tol * iscale
+    assert np.max(np.abs(g["f_int"].reshape(ref["f_int"].shape) - ref["f_int"])) <= 6 * tol
+    qtol = 4 * np.pi * tol * iscale * np.sum(np.abs(wl.w_nu)) * (np.max(wl.chi) + 6.0) * 2
+    assert np.max(np.abs(g["Q_int"].reshape(ref["Q_int"].shape) - ref["Q_int"])) <= qtol
+    assert abs(heat - ref["heating"]) <= qtol * cells
