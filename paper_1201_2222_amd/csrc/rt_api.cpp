@@ -1313,9 +1313,11 @@ namespace {
 // the next sweep may read, each padded to 256 bytes.
 struct StateHeader {
     char magic[8];
-    int32_t n[3], nf, na, f32, plane_order, periodic, cold, pad;
+    int32_t n[3], nf, na, f32, plane_order, periodic, cold;
+    uint32_t rays;    // FNV-1a hash of the rays' direction cosines and weights, in sweep order
     int64_t bytes;
 };
+static_assert(sizeof(StateHeader) == 56, "saved-state header layout");
 constexpr char kStateMagic[8] = {'R', 'T', 'S', 'C', 'S', 'T', '0', '1'};
 
 inline size_t pad256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -1347,6 +1349,13 @@ StateHeader state_header(rt_problem *p)
     h.plane_order = p->plane_order;
     h.periodic = p->periodic[0] | p->periodic[1] << 1 | p->periodic[2] << 2;
     h.cold = p->cold;
+    uint32_t fnv = 2166136261u;
+    for (const RayGeo &g : p->rays) {
+        const double v[4] = {g.mu[0], g.mu[1], g.mu[2], g.wk};
+        const unsigned char *c = reinterpret_cast<const unsigned char *>(v);
+        for (size_t i = 0; i < sizeof v; ++i) fnv = (fnv ^ c[i]) * 16777619u;
+    }
+    h.rays = fnv;
     h.bytes = (int64_t)pad256(sizeof(StateHeader));
     for (auto &b : state_buffers(p)) h.bytes += (int64_t)pad256(b.second);
     return h;

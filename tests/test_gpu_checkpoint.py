@@ -140,6 +140,10 @@ def test_foreign_or_damaged_states_are_refused(env):
         (W.random_problem((20, 14, 13), nf=2, seed=1333, n_mu=4), {"precision": rt.RT_F32}),
         (wl, {"precision": rt.RT_F32, "interp": rt.RT_INTERP_QUADRATIC}),
     ]
+    # the same 24 directions with other weights: another angle set of the same size
+    mu, w = rt.rt_quadrature(4)
+    w2 = w * (1.0 + 0.01 * (np.arange(w.size) % 2))
+    others.append((wl, {"precision": rt.RT_F32, "mu": mu, "w": w2 / w2.sum()}))
     for owl, kw in others:
         o = _problem(env, owl, **kw)
         with pytest.raises(rt.RtError) as e:
