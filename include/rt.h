@@ -102,7 +102,7 @@ typedef enum { RT_SC_LINEAR = 0, RT_SC_BEZIER = 1 } rt_sc_order;
 typedef enum { RT_INTERP_BILINEAR = 0, RT_INTERP_QUADRATIC = 1 } rt_interp;
 
 typedef struct {
-    int32_t nx, ny, nz;       /* grid vertices per axis, each >= 1 */
+    int32_t nx, ny, nz;       /* grid vertices per axis, each in [1, 8000], nx*ny*nz < 2^31 */
     int32_t nf;               /* frequency bins, >= 1 */
     double dx, dy, dz;        /* vertex spacing, > 0 */
     int32_t n_mu;             /* angle set LQ_{n_mu}, n_mu in {2,4,6,8,10,12}; used when mu == NULL */

@@ -71,6 +71,8 @@ def test_invalid_arguments_are_rejected(rt):
         dict(shape=(4, 4, 4), bc_lo=(9, 2, 1), bc_hi=(9, 2, 0)),
         dict(shape=(4, 4, 4), order=2),
         dict(shape=(4, 4, 4), interp=2),
+        dict(shape=(8001, 4, 4)),                                          # above the per-axis limit
+        dict(shape=(2048, 1024, 1024)),                                    # 2^31 cells in a bin
     ]
     for kw in cases:
         d = rt.make_desc(**kw)
@@ -83,6 +85,10 @@ def test_invalid_arguments_are_rejected(rt):
     mu2[0] = -mu2[0]
     d = rt.make_desc((4, 4, 4), mu=mu2, w=w)
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID
+    # the largest grids that pass
+    for shape in ((8000, 4, 4), (2047, 1024, 1024)):
+        d = rt.make_desc(shape)
+        assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_OK, shape
     # ... and a valid explicit table
     d = rt.make_desc((4, 4, 4), mu=mu, w=w)
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_OK
