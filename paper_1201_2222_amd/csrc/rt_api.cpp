@@ -340,9 +340,6 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
 {
     if (!d) return fail(RT_E_INVALID, "desc is NULL");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(RT_E_INVALID, "grid dimensions must be >= 1");
-    // cell offsets inside a bin are 32-bit
-    if ((int64_t)d->nx * d->ny * d->nz > (int64_t)INT32_MAX)
-        return fail(RT_E_INVALID, "nx * ny * nz must be below 2^31");
     if (d->nx > 8000 || d->ny > 8000 || d->nz > 8000) return fail(RT_E_INVALID, "grid dimension above 8000");
     if (d->nf < 1 || d->nf > 65535) return fail(RT_E_INVALID, "nf must be in [1, 65535]");
     if ((int64_t)d->nx * d->ny * d->nz > INT32_MAX)
