@@ -119,7 +119,14 @@ def cpu_baseline(wl, sweeps, order=0, interp=0):
         op.sweep(S)
     dt = time.perf_counter() - t0
     updates = wl.cells * wl.na * wl.nf * sweeps
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": updates / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "host": {"cpu": model, "threads": os.cpu_count()},
             "sample": f"{sweeps} formal solutions (sweeps) of the {wl.shape[0]}^3 x {wl.na}-ray workload"
                       f"{' (second order)' if order else ''}{' (quadratic upwind intensity)' if interp else ''}, "
                       f"{updates / 1e6:.1f} M updates in {dt:.1f} s, FP64, one thread"}
