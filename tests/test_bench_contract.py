@@ -1,0 +1,42 @@
+"""The benchmark's command-line contract: one JSON line with the metric, the whole-job
+value, the timing fields, the roofline of the dominant kernel and the oracle's CPU
+baseline; more than one GPU is refused before any GPU work."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    run = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                         capture_output=True, text=True, timeout=120)
+    assert run.returncode == 2
+    assert "one GPU" in run.stderr and run.stdout == ""
+
+
+@pytest.mark.gpu
+@pytest.mark.timeout(600)
+def test_bench_prints_one_json_line():
+    run = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--n", "32", "--steps", "2",
+                          "--warmup", "1", "--cpu-sweeps", "1"], cwd=ROOT, capture_output=True, text=True,
+                         timeout=500)
+    assert run.returncode == 0, run.stderr[-3000:]
+    lines = [l for l in run.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in out, key
+    assert out["n_gpus"] == 1 and out["steps"] == 2 and out["warmup"] == 1
+    assert out["value"] > 0 and out["ms_per_step"] > 0 and out["higher_is_better"] is True
+    assert "workload" in out["config"] and out["vs_baseline"] is None
+    r = out["roofline"]
+    assert r["bound"] == "alu" and r["unit"] == "Tops/s" and 0 < r["frac"] < 1
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+    assert r["traffic"] is None   # byte counters were taken on the 128^3 workload only
+    c = out["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0 and c["sample"]
