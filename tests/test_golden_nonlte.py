@@ -1,0 +1,48 @@
+"""The paper's worked example of section 5.1 (tests/golden/nonlte_atmosphere_1d.txt):
+a uniform-temperature non-LTE atmosphere with epsilon = 1e-6 and nine zones per decade
+of optical depth, started in LTE, solved by Jacobi and by Gauss-Seidel ALI in the
+oracle.  Pinned: both converge, and Gauss-Seidel needs nearly half the iterations of
+Jacobi, as the paper reports (after TF95)."""
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "nonlte_atmosphere_1d.txt")
+
+
+def _fixture():
+    out = {}
+    for line in open(GOLDEN):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            key, value = line.split(":", 1)
+            out[key.strip()] = value.split()
+    return out
+
+
+def _atmosphere(o, fx):
+    eps = float(fx["epsilon"][0])
+    zpd = int(fx["zones_per_decade"][0])
+    lo, hi = (int(v) for v in fx["tau_decades"])
+    m = int(fx["columns"][0])
+    nz = zpd * (hi - lo) + 1
+    tau = np.logspace(hi, lo, nz)                  # vertex k = 0 is the bottom
+    chi = tau * np.log(10.0) / zpd                 # exponential: dtau/dz = tau ln(10) / zpd
+    chi = np.broadcast_to(chi[:, None, None], (nz, m, m)).copy()[None]
+    B = np.ones_like(chi)                          # uniform temperature
+    return o.Problem((m, m, nz), chi, eps, B, n_mu=int(fx["n_mu"][0]),
+                     bc_lo=(o.PERIODIC, o.PERIODIC, o.THERMAL), bc_hi=(o.PERIODIC, o.PERIODIC, o.VACUUM))
+
+
+def test_gauss_seidel_converges_nearly_twice_as_fast(oracle_mod):
+    fx = _fixture()
+    assert fx["initial_condition"] == ["lte"] and fx["top_boundary"] == ["vacuum"]
+    assert fx["bottom_boundary"] == ["thermal"] and fx["source"] == ["uniform"]
+    dc = float(fx["delta_c"][0])
+    jac = _atmosphere(oracle_mod, fx).ali(delta_c=dc, max_iter=100000)   # S0 = B: LTE start
+    gs = _atmosphere(oracle_mod, fx).ali_gs(delta_c=dc, max_iter=100000)
+    assert jac["converged"] and gs["converged"]
+    ratio = jac["iters"][0] / gs["iters"][0]
+    lo, hi = (float(v) for v in fx["gs_over_jacobi_band"])
+    assert lo <= ratio <= hi, (jac["iters"], gs["iters"])
+    assert abs(float(fx["gs_over_jacobi"][0]) - ratio) < 0.5
