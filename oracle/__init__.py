@@ -12,8 +12,12 @@ Paper: Davis, Stone & Jiang (2012), arXiv:1201.2222.
                        (Bezier) form, and the monotone quadratic upwind intensity
                        with plane-ordered sweeps (``rt_oracle.c``)
   * Jacobi ALI ....... section 3.4, eqs. sourcefunc2 and dsjacobi, criterion eq. conv
-  * Gauss-Seidel ALI . section 3.4, horizontal planes from the top down as the blocks
-                       (``orc_gs_iteration`` in ``rt_oracle.c``, ``Problem.ali_gs``)
+  * Gauss-Seidel ALI . section 3.4: the paper's zone order (the backward sweep of
+                       Fig. f:sweep, zones updated one at a time from the top corner;
+                       ``orc_gs_point_iteration``, ``Problem.ali_gs(ordering="zone")``)
+                       and the variant with horizontal planes from the top down as the
+                       blocks that the GPU runs (``orc_gs_iteration``,
+                       ``ordering="plane"``)
   * boundaries ....... section 3.5 and the periodic iteration of section 3
   * moments .......... eqs. Jsum/Hsum/Ksum, VET f = K/J and Q_rad (section 4)
 """
@@ -78,6 +82,8 @@ def _load():
         lib.orc_gs_iteration.argtypes = [ctypes.POINTER(_Grid), P, P, P, P, P, P, P, P, ctypes.c_int, P, P,
                                          P, P, P]
         lib.orc_gs_iteration.restype = ctypes.c_int
+        lib.orc_gs_point_iteration.argtypes = lib.orc_gs_iteration.argtypes
+        lib.orc_gs_point_iteration.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -423,12 +429,19 @@ class Problem:
         converged = bool(np.all(resid <= delta_c))
         return {"S": S, "J": J, "iters": iters, "resid": resid, "lam": lam, "converged": converged}
 
-    def gs_iteration(self, S, bin_active=None):
-        """One Gauss-Seidel iteration (section 3.4, planes from the top down as the
-        blocks; see orc_gs_iteration): returns S^{n+1}, the J each vertex was updated
-        with, Lambda* and the update dS.  Periodic ghosts read this problem's memory
-        (S at the iteration's start before any sweep); afterwards the memory holds the
+    def gs_iteration(self, S, bin_active=None, ordering="plane"):
+        """One Gauss-Seidel iteration (section 3.4): returns S^{n+1}, the J each vertex
+        was updated with, Lambda* and the update dS.
+
+        ordering="zone": the paper's order, zones updated one at a time in the
+        backward sweep of Fig. f:sweep (from the top corner, i fastest), each with J
+        from the current S (orc_gs_point_iteration).  ordering="plane": horizontal
+        planes from the top down as the blocks, Jacobi inside a plane (the variant the
+        GPU runs; orc_gs_iteration).  Periodic ghosts read this problem's memory (S at
+        the iteration's start before any sweep); afterwards the memory holds the
         iteration's outgoing planes."""
+        if ordering not in ("plane", "zone"):
+            raise ValueError("ordering is 'zone' (the paper's) or 'plane' (horizontal planes as blocks)")
         if self.order != 0 or self.interp != 0:
             raise ValueError("Gauss-Seidel is built with first-order segments and bilinear I- only")
         if self.bc_lo[2] == PERIODIC:
@@ -444,9 +457,10 @@ class Problem:
         new = [a.copy() if a is not None else None for a in self.prev]
         prev_out = (ctypes.c_void_p * 3)(*[a.ctypes.data if a is not None else None for a in new])
         act = None if bin_active is None else np.ascontiguousarray(bin_active, dtype=np.int32)
-        rc = lib.orc_gs_iteration(ctypes.byref(self._grid()), _ptr(self.mu), _ptr(self.w), _ptr(self.chi),
-                                  _ptr(self.B), _ptr(self.eps), _ptr(S), fixed, prev_in, int(self.have_prev),
-                                  prev_out, _ptr(act), _ptr(J), _ptr(lam), _ptr(dS))
+        fn = lib.orc_gs_point_iteration if ordering == "zone" else lib.orc_gs_iteration
+        rc = fn(ctypes.byref(self._grid()), _ptr(self.mu), _ptr(self.w), _ptr(self.chi),
+                _ptr(self.B), _ptr(self.eps), _ptr(S), fixed, prev_in, int(self.have_prev),
+                prev_out, _ptr(act), _ptr(J), _ptr(lam), _ptr(dS))
         if rc == -1:
             raise MemoryError("oracle Gauss-Seidel iteration ran out of memory")
         if rc != 0:
@@ -455,9 +469,11 @@ class Problem:
         self.have_prev = 1
         return {"S": S, "J": J, "lam": lam, "dS": dS}
 
-    def ali_gs(self, delta_c=1e-6, max_iter=10000, fixed_iters=0, S0=None, J_prev=None, per_bin_stop=True):
+    def ali_gs(self, delta_c=1e-6, max_iter=10000, fixed_iters=0, S0=None, J_prev=None, per_bin_stop=True,
+               ordering="plane"):
         """Gauss-Seidel accelerated Lambda iteration (section 3.4): as ``ali`` with
-        each iteration a Gauss-Seidel pass (gs_iteration).  r = max |dS| / S^{n+1} per
+        each iteration a Gauss-Seidel pass (gs_iteration with the given ordering:
+        "zone", the paper's, or "plane", the GPU's blocks).  r = max |dS| / S^{n+1} per
         bin (eq. conv); J is the J of each bin's last iteration."""
         eps, B = self.eps, self.B
         if S0 is not None:
@@ -474,7 +490,7 @@ class Problem:
         lam = None
         n_total = fixed_iters if fixed_iters > 0 else max_iter
         for n in range(n_total):
-            out = self.gs_iteration(S, bin_active=active.astype(np.int32))
+            out = self.gs_iteration(S, bin_active=active.astype(np.int32), ordering=ordering)
             if lam is None:
                 lam = out["lam"].copy()
             for f in np.nonzero(active)[0]:

@@ -68,8 +68,9 @@
  * same time, the non-periodic face with the highest axis (z, then y, then x)
  * gives the intensity.
  *
- * The Gauss-Seidel form of the Lambda iteration (section 3.4), with the horizontal
- * planes as the blocks of its ordering, is orc_gs_iteration below.
+ * The Gauss-Seidel form of the Lambda iteration (section 3.4) is here twice: in the
+ * paper's zone order (orc_gs_point_iteration) and with the horizontal planes as the
+ * blocks of its ordering (orc_gs_iteration), the variant the GPU library runs.
  *
  * Arithmetic is plain FP64 in the order written; build with
  * -ffp-contract=off so that no multiply-add is fused.
@@ -725,6 +726,150 @@ int orc_gs_iteration(const orc_grid *g, const double *mu, const double *w,
     }
     free(Iup);
     free(Idn);
+    free(S0);
+    return 0;
+}
+
+/*
+ * One Gauss-Seidel iteration in the zone order of section 3.4 (Fig. f:sweep): the
+ * sweep advances with i the fastest index, then j, then k; the backward sweep runs
+ * it in reverse, so the zones are updated one at a time from the top corner
+ * (nx-1, ny-1, nz-1) down to (0, 0, 0): planes from the top, rows from the back,
+ * i descending.  When a zone is updated, every intensity it sums has been computed
+ * with the current S: the new S of every zone updated before it in this iteration
+ * and the old S elsewhere.  This is what the paper's corrections with saved weights
+ * and its update of the outgoing intensities achieve once they are carried through
+ * completely; written out here without them, as the definition of the iteration:
+ *
+ *     for each zone z in the order above:
+ *         J_z = sum_k w_k I_k(z)   with I_k from the current S
+ *         S_z += ((1 - eps) J_z + eps B - S_z) / (1 - (1 - eps) Lambda*_z)   (eq. dsjacobi)
+ *
+ * Evaluation.  The intensities on plane k depend only on plane k itself, on the
+ * plane upwind along z and on S; when plane k is being updated, the planes above are
+ * final (their zones are all updated) and the planes below still hold the old S.  So
+ * the rays going up are swept once over the whole grid with the old S (their values
+ * below plane k stay exact while plane k is updated); the rays going down are swept
+ * over plane k once the plane above is final; and before each zone of plane k is
+ * updated every ray's intensities on plane k are computed again from the current S
+ * (each ray in its own row-major order inside the plane).  After the last zone of the
+ * plane the downward intensities on plane k are computed once more with its final S,
+ * for the plane below.  This costs n_rays * nx * ny vertex solutions per zone: the
+ * oracle is for small grids.
+ *
+ * Ghost vertices follow the rules of the formal solution: chi and S of the folded
+ * vertex (current values), intensity from the boundary condition, or on periodic
+ * axes the memory of the previous iteration (before any iteration: S of the wrapped
+ * vertex as the iteration began).  prev_out receives the rays going up from the
+ * sweep with the old S and the rays going down from their final planes.
+ *
+ * Arguments and layouts as orc_gs_iteration.  Needs order = 0, interp = 0 and a
+ * non-periodic z axis.  Returns 0, -1 when scratch memory runs out, -2 for an
+ * unsupported grid.
+ */
+int orc_gs_point_iteration(const orc_grid *g, const double *mu, const double *w,
+                           const double *chi, const double *B, const double *eps, double *S,
+                           const double *const *fixed, const double *const *prev_in, int have_prev,
+                           double *const *prev_out, const int32_t *bin_active,
+                           double *J, double *lam, double *dS)
+{
+    if (g->order != 0 || g->interp != 0 || is_periodic(g, 2)) return -2;
+    const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t ncell = (int64_t)nx * ny * nz;
+    const int64_t nxy = (int64_t)nx * ny;
+    double *I = (double *)malloc(sizeof(double) * ncell * (g->na > 0 ? g->na : 1));
+    double *S0 = (double *)malloc(sizeof(double) * ncell);
+    if (!I || !S0) {
+        free(I);
+        free(S0);
+        return -1;
+    }
+
+    for (int f = 0; f < g->nf; ++f) {
+        if (bin_active && !bin_active[f]) continue;
+        const double *chif = chi + f * ncell;
+        const double *Bf = B + f * ncell;
+        const double *ef = eps + f * ncell;
+        double *Sf = S + f * ncell;
+        double *Jf = J + f * ncell;
+        double *lf = lam + f * ncell;
+        double *dSf = dS + f * ncell;
+        memcpy(S0, Sf, sizeof(double) * ncell);
+
+        /* the rays going up over the whole grid with the old S */
+        for (int ray = 0; ray < g->na; ++ray) {
+            const double *m = mu + 3 * ray;
+            if (m[2] < 0.0) continue;
+            orc_ray r;
+            ray_geometry(m, g->h, &r);
+            double wv[4];
+            face_weights(&r, wv);
+            double *Ir = I + (int64_t)ray * ncell;
+            orc_ctx c = {g, f, ray, chif, Sf, Bf, Ir, fixed, prev_in, have_prev, S0};
+            for (int64_t idx = 0; idx < ncell; ++idx) {
+                int cpos[3];
+                visit_position(g, &r, idx, cpos);
+                double I0, ld;
+                vertex_solve(&c, &r, wv, cpos, &I0, &ld);
+                Ir[cell_index(g, cpos[0], cpos[1], cpos[2])] = I0;
+            }
+            save_periodic(g, &r, f, ray, Ir, prev_out);
+        }
+
+        for (int kk = 0; kk < nz; ++kk) {
+            const int k = nz - 1 - kk;
+            /* zones of plane k in the backward order; last pass: the final plane */
+            for (int64_t zz = 0; zz <= nxy; ++zz) {
+                const int last = zz == nxy;
+                const int zi = last ? 0 : nx - 1 - (int)(zz % nx);
+                const int zj = last ? 0 : ny - 1 - (int)(zz / nx);
+                const int64_t zid = cell_index(g, zi, zj, k);
+                double Jz = 0.0, lz = 0.0;
+                for (int ray = 0; ray < g->na; ++ray) {
+                    const double *m = mu + 3 * ray;
+                    if (last && m[2] >= 0.0) continue;
+                    orc_ray r;
+                    ray_geometry(m, g->h, &r);
+                    double wv[4];
+                    face_weights(&r, wv);
+                    double *Ir = I + (int64_t)ray * ncell;
+                    orc_ctx c = {g, f, ray, chif, Sf, Bf, Ir, fixed, prev_in, have_prev, S0};
+                    /* the ray's intensities on plane k from the current S, row-major
+                       from its upwind corner inside the plane */
+                    for (int64_t p = 0; p < nxy; ++p) {
+                        const int ox = (int)(p % nx), oy = (int)(p / nx);
+                        int cpos[3];
+                        cpos[0] = (r.sgn[0] > 0) ? ox : nx - 1 - ox;
+                        cpos[1] = (r.sgn[1] > 0) ? oy : ny - 1 - oy;
+                        cpos[2] = k;
+                        double I0, ld;
+                        vertex_solve(&c, &r, wv, cpos, &I0, &ld);
+                        const int64_t id = cell_index(g, cpos[0], cpos[1], cpos[2]);
+                        Ir[id] = I0;
+                        if (id == zid) {
+                            Jz += w[ray] * I0;
+                            lz += w[ray] * ld;
+                        }
+                    }
+                }
+                if (last) break;
+                const double e = ef[zid];
+                const double d = ((1.0 - e) * Jz + e * Bf[zid] - Sf[zid]) / (1.0 - (1.0 - e) * lz);
+                Jf[zid] = Jz;
+                lf[zid] = lz;
+                dSf[zid] = d;
+                Sf[zid] = Sf[zid] + d;
+            }
+        }
+        for (int ray = 0; ray < g->na; ++ray) {
+            const double *m = mu + 3 * ray;
+            if (m[2] >= 0.0) continue;
+            orc_ray r;
+            ray_geometry(m, g->h, &r);
+            save_periodic(g, &r, f, ray, I + (int64_t)ray * ncell, prev_out);
+        }
+    }
+    free(I);
     free(S0);
     return 0;
 }

@@ -2,7 +2,8 @@
 a uniform-temperature non-LTE atmosphere with epsilon = 1e-6 and nine zones per decade
 of optical depth, started in LTE, solved by Jacobi and by Gauss-Seidel ALI in the
 oracle.  Pinned: both converge, and Gauss-Seidel needs nearly half the iterations of
-Jacobi, as the paper reports (after TF95)."""
+Jacobi, as the paper reports (after TF95), in the paper's zone order and with the
+horizontal planes as blocks."""
 import os
 
 import numpy as np
@@ -41,12 +42,19 @@ def test_gauss_seidel_converges_nearly_twice_as_fast(oracle_mod):
     assert fx["bottom_boundary"] == ["thermal"] and fx["source"] == ["uniform"]
     dc = float(fx["delta_c"][0])
     jac = _atmosphere(oracle_mod, fx).ali(delta_c=dc, max_iter=100000)   # S0 = B: LTE start
-    gs = _atmosphere(oracle_mod, fx).ali_gs(delta_c=dc, max_iter=100000)
-    assert jac["converged"] and gs["converged"]
-    ratio = jac["iters"][0] / gs["iters"][0]
     lo, hi = (float(v) for v in fx["gs_over_jacobi_band"])
-    assert lo <= ratio <= hi, (jac["iters"], gs["iters"])
-    assert abs(float(fx["gs_over_jacobi"][0]) - ratio) < 0.5
+    iters = {}
+    for ordering in ("zone", "plane"):
+        gs = _atmosphere(oracle_mod, fx).ali_gs(delta_c=dc, max_iter=100000, ordering=ordering)
+        assert jac["converged"] and gs["converged"]
+        ratio = jac["iters"][0] / gs["iters"][0]
+        assert lo <= ratio <= hi, (ordering, jac["iters"], gs["iters"])
+        assert abs(float(fx["gs_over_jacobi"][0]) - ratio) < 0.5
+        iters[ordering] = gs["iters"][0]
+    # with n_mu = 2 every ray crosses a z face first, so the zones of a plane couple only
+    # through the vacuum ghosts above the top plane (which copy S from the plane): the
+    # paper's zone order and the plane blocks take nearly the same number of iterations
+    assert abs(iters["zone"] - iters["plane"]) <= 0.02 * iters["plane"], iters
 
 
 @pytest.mark.gpu

@@ -216,3 +216,67 @@ def test_moments_epilogue_isotropic(oracle_mod):
     assert np.allclose(m["Q"][0], q0, rtol=1e-13)
     assert np.max(np.abs(m["Q"][1])) < 1e-12   # chi dx = 4 > 1: -4 pi div H with H = 0
     assert np.allclose(m["heating"], 0.25 * q0 * n, rtol=1e-12)
+
+
+def _sinusoid_q(o, chi0, N, L=4.0, B1=0.3):
+    """Pure absorber (S = B), uniform chi, B = 1 + B1 cos(k x) + B1/2 sin(k y) on an
+    N x N x 1 grid with every face periodic: Q_int, Q_dif and the epilogue's Q."""
+    kw = 2 * np.pi / L
+    h = L / N
+    x = (np.arange(N) + 0.5) * h
+    X, Y = np.meshgrid(x, x)
+    B = (1.0 + B1 * np.cos(kw * X) + 0.5 * B1 * np.sin(kw * Y))[None, None]
+    p = o.Problem((N, N, 1), np.full(B.shape, chi0), 1.0, B, n_mu=4, h=(h, h, h),
+                  bc_lo=(o.PERIODIC,) * 3, bc_hi=(o.PERIODIC,) * 3)
+    m = p.moments(B, converge_periodic=1e-14)
+    q_int = 4 * np.pi * p.eps[0] * p.chi[0] * (m["J"][0] - p.B[0])
+    q_dif = -4 * np.pi * o.divergence(m["H"][:, 0], p.h, [True] * 3)
+    return q_int, q_dif, m["Q"][0], chi0 * h
+
+
+@pytest.mark.parametrize("chi0, Ns, last", [(4.0, (8, 16, 32, 64), 0.08), (16.0, (16, 32, 64), 0.3)])
+def test_q_dif_converges_to_q_int(oracle_mod, chi0, Ns, last):
+    """The zeroth moment of the transfer equation (eq. rade with eq. radsource) makes
+    -4 pi div H equal to 4 pi eps chi (J - B) for the exact radiation field, so the
+    two forms of Q_rad (section 4) must agree as the grid is refined.  On a smooth
+    periodic field (no boundary layer) their difference, relative to max |Q_int|,
+    falls with every doubling of the resolution (measured about 2x per doubling at
+    chi = 4: 0.54, 0.28, 0.13, 0.061), also on grids where chi dx > 1 selects Q_dif.
+    A wrong sign of Q_dif would leave a difference of order 2, a wrong factor one of
+    order 1, at every resolution."""
+    o = oracle_mod
+    errs = []
+    for N in Ns:
+        q_int, q_dif, Q, chih = _sinusoid_q(o, chi0, N)
+        errs.append(np.max(np.abs(q_dif - q_int)) / np.max(np.abs(q_int)))
+        # the epilogue selects Q_dif where chi dx > 1, Q_int elsewhere (reading R13)
+        assert np.array_equal(Q, q_dif if chih > 1.0 else q_int)
+    for a, b in zip(errs, errs[1:]):
+        assert b < 0.75 * a, errs
+    assert errs[-1] < last, errs
+
+
+def test_q_dif_sign_on_a_cooling_slab(oracle_mod):
+    """A slab that loses radiation through a vacuum top (thermal bottom, uniform B,
+    pure absorber, so S = B): near the top J < B, so the gas cools.  The net outward
+    flux grows toward the surface, so Q_dif = -4 pi div H is negative there too, and
+    the two forms agree (measured: within 3% below the top cell, 14% at the top cell
+    where the difference is one-sided)."""
+    o = oracle_mod
+    nx = ny = 4
+    nz = 24
+    h = 0.25
+    chi = np.full((1, nz, ny, nx), 1.0)
+    B = np.ones_like(chi)
+    p = o.Problem((nx, ny, nz), chi, 1.0, B, n_mu=4, h=(h, h, h),
+                  bc_lo=(o.PERIODIC, o.PERIODIC, o.THERMAL), bc_hi=(o.PERIODIC, o.PERIODIC, o.VACUUM))
+    m = p.moments(B, converge_periodic=1e-14)
+    q_int = 4 * np.pi * p.eps[0] * p.chi[0] * (m["J"][0] - p.B[0])
+    q_dif = -4 * np.pi * o.divergence(m["H"][:, 0], p.h, [True, True, False])
+    Hz = m["H"][2, 0].mean(axis=(1, 2))
+    assert np.all(Hz[nz // 2:] > 0) and Hz[-1] > Hz[nz // 2]      # net outward flux, growing upward
+    top = slice(nz - 6, nz)
+    assert np.all(q_int[top] < 0) and np.all(q_dif[top] < 0)
+    # the two forms agree to within the discretisation error in the top layers
+    assert np.max(np.abs(q_dif[top] - q_int[top])) < 0.2 * np.max(np.abs(q_int[top]))
+    assert np.max(np.abs(q_dif[nz - 6:nz - 1] - q_int[nz - 6:nz - 1]) / np.abs(q_int[nz - 6:nz - 1])) < 0.05
