@@ -54,13 +54,20 @@ OPS_PER_UPDATE_QUAD_F32 = 9 + 36 + 2 + 8 + 2 + 5 + 6 + 3 + 1
 # written (8).
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CHAIN_UPDATE_F32 = 16 + 4 + 4
+# Algorithmic bytes of the FP32 sweep kernel per cell and bin and formal solution: each
+# of the 8 octant passes reads chi (4) and S (4 as FP32) and writes its J partial (4),
+# 96 bytes, shared by the rays of the angle set: 1.2 bytes per update at 80 rays.
+BYTES_PER_CELL_BIN_SWEEP_F32 = 8 * (4 + 4 + 4)
+BYTES_PER_UPDATE_SWEEP_F32_80 = BYTES_PER_CELL_BIN_SWEEP_F32 / 80
 
 
-TRAFFIC_PROFILE = {"linear": os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md"),
+TRAFFIC_PROFILE = {"multifreq": os.path.join(ROOT, "profiles", "sweep_stage_f32_multifreq192_traffic.md"),
+                   "linear": os.path.join(ROOT, "profiles", "sweep_stage_f32_scattering128_traffic.md"),
                    "bezier": os.path.join(ROOT, "profiles", "sweep_stage_f32_bezier_scattering128_traffic.md"),
                    "quadratic": os.path.join(ROOT, "profiles", "plane_step_f32_quadratic_scattering128_traffic.md"),
                    "gauss-seidel": os.path.join(ROOT, "profiles", "gs_chain_f32_scattering128_traffic.md")}
-KERNEL_SOURCE = {"linear": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
+KERNEL_SOURCE = {"multifreq": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
+                 "linear": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
                  "bezier": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_kernels.hip"),
                  "quadratic": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_plane.hip"),
                  "gauss-seidel": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_gs.hip")}
@@ -215,44 +222,188 @@ def bench_batched(args, rt, W, torch, np):
     }
 
 
-def bench_multifreq(args, rt, W, torch, np):
-    """192^3 x 80 rays on a subset of the 64 frequency bins (bins are independent, so a
-    subset is one GPU's share of the full problem): Jacobi ALI iterations on all bins."""
-    nf_total = 64
-    bins = np.linspace(0, nf_total - 1, args.bins).round().astype(int)
-    wl = W.multifreq(n=args.mf_n, nf=nf_total, bins=bins)
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    chi, eps, B = dev(wl.chi), dev(wl.eps), dev(wl.B)
-    print(f"multifreq: {wl.shape[0]}^3 x {len(bins)} bins set up", file=sys.stderr, flush=True)
-    prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
-                      precision=rt.RT_F32)
-    prob.set_fields(chi, eps, B)
-    S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
-    J = torch.empty_like(S)
-    prob.ali_solve(S, J, fixed_iters=1)
-    torch.cuda.synchronize()
-    rt.rt_problem_profile(prob.handle, True)
+def _host_threads():
+    """Host cores this process may use (the affinity mask), at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        return None
+
+
+def oracle_rate(wl, units, threads, sweeps=1):
+    """The FP64 oracle, as it stands, on independent (bin, ray subset) units of a
+    workload: each unit is a one-bin oracle problem over some of the rays (rays and
+    bins do not couple within one formal solution), swept ``sweeps`` times.  Units run
+    on a thread pool of ``threads`` workers (the C sweep releases the GIL).  Returns
+    (updates/s, updates, seconds)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    oracle.build(force=False)
+    mu, w = oracle.quadrature(wl.n_mu)
+    probs = []
+    for b, rays in units:
+        rays = np.asarray(rays)
+        probs.append((oracle.Problem(wl.shape, wl.chi[b], wl.eps[b], wl.B[b], mu=mu[rays], w=w[rays],
+                                     bc_lo=wl.bc_lo, bc_hi=wl.bc_hi), wl.B[b], len(rays)))
+
+    def run(u):
+        op, S, _ = u
+        for _ in range(sweeps):
+            op.sweep(S)
+
     t0 = time.perf_counter()
-    status, st = prob.ali_solve(S, J, fixed_iters=args.mf_iters, check_every=args.mf_iters)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, probs))
+    dt = time.perf_counter() - t0
+    updates = float(sum(wl.cells * nr * sweeps for _, _, nr in probs))
+    return updates / dt, updates, dt
+
+
+def cpu_baseline_multifreq(n, nf_total, sample_bins, rays_per_octant=10, single_octants=2):
+    """Oracle baseline on the multi-frequency workload: one thread over one bin and
+    ``single_octants`` octants of its rays, and every host thread (at most 16) over
+    (bin, octant) units of ``sample_bins``; one sweep each, extrapolated to the full
+    workload through updates/s (sweeps cost the same per update in every bin)."""
+    from paper_1201_2222_amd import workloads as W
+    wl = W.multifreq(n=n, nf=nf_total, bins=sample_bins)
+    oct_rays = lambda o: list(range(o * rays_per_octant, (o + 1) * rays_per_octant))
+    r1, u1, t1 = oracle_rate(wl, [(0, sum((oct_rays(o) for o in range(single_octants)), []))], 1)
+    threads = _host_threads()
+    units = [(b, oct_rays(o)) for b in range(len(sample_bins)) for o in range(8)][:max(threads, 1) * 1]
+    rN, uN, tN = oracle_rate(wl, units, threads)
+    return {"value": rN, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "host": {"cpu": _cpu_model(), "threads_visible": os.cpu_count()},
+            "sample": f"{len(units)} (bin, octant) units of bins {[int(b) for b in wl.meta['bins']]} of the "
+                      f"{n}^3 x {nf_total}-bin x {wl.na}-ray workload, one sweep each on {threads} threads: "
+                      f"{uN / 1e6:.0f} M updates in {tN:.1f} s, FP64; extrapolated to the full workload at "
+                      f"this rate ({wl.cells * nf_total * wl.na / rN:.0f} s per sweep of all bins)",
+            "single_thread": {"value": r1, "unit": "updates/s", "cores": 1,
+                              "sample": f"bin {int(wl.meta['bins'][0])}, {single_octants} octants "
+                                        f"({single_octants * rays_per_octant} rays), one sweep: "
+                                        f"{u1 / 1e6:.0f} M updates in {t1:.1f} s"}}
+
+
+def bench_multifreq(args, rt, W, torch, np):
+    """Multi-frequency workload at full size: 192^3 x 64 bins x 80 rays in one problem
+    (about 100 GB of device memory).  A step is one Jacobi ALI iteration over all 64
+    bins (one formal solution of every bin plus the update); inputs are resident in
+    HBM before the timed region."""
+    nf_total = 64
+    n = args.mf_n
+    bins = np.arange(nf_total) if args.bins >= nf_total else \
+        np.linspace(0, nf_total - 1, args.bins).round().astype(int)
+    nfb = len(bins)
+    cells = n ** 3
+    chi = torch.empty(nfb * cells, dtype=torch.float64, device="cuda")
+    eps = torch.empty_like(chi)
+    B = torch.empty_like(chi)
+    t_gen = time.perf_counter()
+    w_nu = np.zeros(nfb)
+    for c0 in range(0, nfb, 8):
+        sel = bins[c0:c0 + 8]
+        wl = W.multifreq(n=n, nf=nf_total, bins=sel)
+        sl = slice(c0 * cells, (c0 + len(sel)) * cells)
+        for dst, src in ((chi, wl.chi), (eps, wl.eps), (B, wl.B)):
+            dst[sl].copy_(torch.from_numpy(np.ascontiguousarray(src).reshape(-1)))
+        w_nu[c0:c0 + len(sel)] = wl.w_nu
+        print(f"multifreq: bins {int(sel[0])}..{int(sel[-1])} generated and copied "
+              f"({time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    shape, n_mu, bc_lo, bc_hi = wl.shape, wl.n_mu, wl.bc_lo, wl.bc_hi
+    na = n_mu * (n_mu + 2)
+    del wl
+    prob = rt.Problem(shape, nf=nfb, n_mu=n_mu, bc_lo=bc_lo, bc_hi=bc_hi, w_nu=w_nu, precision=rt.RT_F32)
+    desc_bytes = rt.rt_problem_bytes(prob.desc)
+    prob.set_fields(chi, eps, B)
+    torch.cuda.synchronize()
+    del chi, eps, B          # the library keeps its own copies
+    S = torch.empty(nfb * cells, dtype=torch.float64, device="cuda")
+    J = torch.empty_like(S)
+    free, total_mem = torch.cuda.mem_get_info()
+    print(f"multifreq: {n}^3 x {nfb} bins x {na} rays set up, library state {desc_bytes / 1e9:.1f} GB, "
+          f"{(total_mem - free) / 1e9:.1f} GB of device memory in use", file=sys.stderr, flush=True)
+
+    K, Wm = args.steps, args.warmup
+    if Wm > 0:
+        prob.ali_solve(S, J, fixed_iters=Wm, check_every=Wm)
+    torch.cuda.synchronize()
+    print(f"multifreq: {Wm} warm-up iterations done", file=sys.stderr, flush=True)
+    # timed: K Jacobi iterations of all bins (the production path: graph-replayed chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, st = prob.ali_solve(S, J, fixed_iters=K, check_every=K)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    print(f"multifreq: {K} timed iterations in {dt:.3f} s", file=sys.stderr, flush=True)
+    updates = float(cells) * na * nfb * K
+    # one more iteration with the sweep kernel's launches timed by events
+    rt.rt_problem_profile(prob.handle, True)
+    prob.ali_solve(S, J, fixed_iters=1, check_every=1)
+    torch.cuda.synchronize()
     prof = rt.rt_problem_profile_read(prob.handle)
     rt.rt_problem_profile(prob.handle, False)
-    print(f"multifreq: {args.mf_iters} iterations in {dt:.2f} s", file=sys.stderr, flush=True)
-    updates = float(wl.cells) * wl.na * wl.nf * args.mf_iters
     kernel_s = prof["kernel_ms"] / 1e3
-    achieved = prof["updates"] * OPS_PER_UPDATE_F32 / kernel_s / 1e12 if kernel_s > 0 else 0.0
-    prob.close()
-    return {
-        "metric": METRIC, "value": updates / dt, "unit": "updates/s", "n_gpus": 1, "steps": args.mf_iters,
-        "warmup": 1, "ms_per_step": dt / args.mf_iters * 1e3, "higher_is_better": True, "scaling": "weak",
+    sweep_rate = prof["updates"] / kernel_s if kernel_s > 0 else 0.0
+    achieved = sweep_rate * OPS_PER_UPDATE_F32 / 1e12
+    launches = max(prof["launches"], 1)
+    # the committed byte counters were taken on the full 192^3 x 64-bin workload
+    traffic = measured_traffic("multifreq") if (n == 192 and nfb == 64) else None
+    avg_us = prof["kernel_ms"] * 1e3 / launches
+    hbm_alg = sweep_rate * BYTES_PER_UPDATE_SWEEP_F32_80 / 1e9
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": "sweep_stage_kernel<float, true, 1, false, 0, 8>",
+                "avg_launch_us": avg_us, "timed_launches": prof["launches"],
+                "ops_per_update": OPS_PER_UPDATE_F32, "sweep_updates_per_s": sweep_rate,
+                "hbm": {"achieved": hbm_alg, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_alg / HBM_PEAK_GBS,
+                        "bytes_per_update": BYTES_PER_UPDATE_SWEEP_F32_80,
+                        "measured_gbs": (traffic / (avg_us * 1e-6) / 1e9) if traffic else None,
+                        "measured_frac": (traffic / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
+    out = {
+        "metric": METRIC, "value": updates / dt, "unit": "updates/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded, generated on the host)",
-        "config": {"workload": f"multifreq {wl.shape[0]}^3, {wl.na} rays, {wl.nf} of {nf_total} bins "
-                               f"(x_nu in [0.05, 50]), Jacobi ALI iterations, FP32 sweeps", "bins": bins.tolist()},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "sweep_updates_per_s": prof["updates"] / kernel_s if kernel_s > 0 else None},
+        "config": {"workload": f"multifreq {n}^3 x {nfb} bins x {na} rays (x_nu log-spaced in [0.05, 50], free-free "
+                               f"chi_abs ~ x^-3 rho with rho lognormal(0.8), grey scattering tau 10, Planck B_nu "
+                               f"with T lognormal(0.3)); a step is one Jacobi ALI iteration over all bins, "
+                               f"FP32 sweeps + FP64 updates and residuals",
+                   "grid": list(shape), "bins": nfb, "rays": na, "device_bytes_library": desc_bytes},
+        "roofline": roofline,
     }
+    if args.mf_converge:
+        # the whole solve to max |dS/S| <= 1e-6 per bin from S = B, in chunks of 100
+        # iterations (each later chunk continues from S; a bin already converged stops
+        # after one iteration of the chunk)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it_total = np.zeros(nfb, dtype=np.int64)
+        status = rt.RT_NOT_CONVERGED
+        while status != rt.RT_OK and it_total.max() < args.max_iter:
+            status, st = prob.ali_solve(S, J, delta_c=1e-6, max_iter=100, per_bin_stop=True,
+                                        warm_start=1 if it_total.max() > 0 else 0)
+            it_bins, res = rt.rt_ali_bin_stats(prob.handle, nfb)
+            it_total += it_bins
+            print(f"multifreq: converging, {int(it_total.max())} iterations, max residual {float(res.max()):.2e} "
+                  f"({time.perf_counter() - t1:.1f} s)", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - t1
+        out["converged_solve"] = {"seconds": tc, "status": int(status), "iterations_max": int(it_total.max()),
+                                  "iterations_per_bin": it_total.tolist(),
+                                  "updates_per_s": float(cells) * na * float(np.sum(it_total)) / tc}
+    prob.close()
+    del S, J
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_serving(args, rt, W, torch, np):
@@ -354,70 +505,10 @@ def bench_serving(args, rt, W, torch, np):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=128, help="grid edge of the scattering workload")
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
-    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 GPU comparison solve")
-    ap.add_argument("--schedule", choices=["stages"], default="stages")
-    ap.add_argument("--order", choices=["linear", "bezier"], default="linear",
-                    help="scattering: first-order or second-order (Bezier) short characteristics")
-    ap.add_argument("--interp", choices=["bilinear", "quadratic"], default="bilinear",
-                    help="scattering: upwind intensity bilinear (tile wavefront) or monotone quadratic "
-                         "(plane-ordered sweep)")
-    ap.add_argument("--ali", choices=["jacobi", "gauss-seidel"], default="jacobi",
-                    help="scattering: Jacobi ALI, or Gauss-Seidel with horizontal planes as the blocks")
-    ap.add_argument("--fixed-iters", type=int, default=0,
-                    help="profiling mode: run exactly this many ALI iterations per step instead of converging")
-    ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
-    ap.add_argument("--streams", type=int, default=4, help="serving: pool problems that are drifting streams")
-    ap.add_argument("--requests", type=int, default=24, help="serving: requests per arrival rate")
-    ap.add_argument("--workload", choices=["scattering", "batched", "multifreq", "serving"], default="scattering",
-                    help="scattering: the single-problem benchmark (default); batched: many uneven problems; "
-                         "multifreq: 192^3 x 80 rays on a subset of 64 bins")
-    ap.add_argument("--bins", type=int, default=8, help="multifreq: bins of the 64 to run")
-    ap.add_argument("--mf-n", type=int, default=192, help="multifreq: grid edge")
-    ap.add_argument("--mf-iters", type=int, default=3, help="multifreq: timed Jacobi iterations")
-    ap.add_argument("--count", type=int, default=96, help="problems of the batched workload")
-    ap.add_argument("--max-iter", type=int, default=20000)
-    ap.add_argument("--seq-sample", type=int, default=0,
-                    help="batched workload: also solve this many of its problems one at a time")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 1 GiB device-to-device copy (for scaling rocprofv3 FETCH/WRITE_SIZE) and exit")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (bins and independent "
-              "problems would shard across GPUs with no communication but a few reduced scalars)",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_1201_2222_amd as rt
-    from paper_1201_2222_amd import workloads as W
-
-    torch.cuda.set_device(0)
-    if args.copy_calibration:
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "copies": 3}), flush=True)
-        return
-    if args.workload == "batched":
-        print(json.dumps(bench_batched(args, rt, W, torch, np)), flush=True)
-        return
-    if args.workload == "serving":
-        print(json.dumps(bench_serving(args, rt, W, torch, np)), flush=True)
-        return
-    if args.workload == "multifreq":
-        print(json.dumps(bench_multifreq(args, rt, W, torch, np)), flush=True)
-        return
+def bench_scattering(args, rt, W, torch, np, steps, warmup, cpu=True):
+    """The 128^3 scattering workload: ALI solves from S = B to max |dS/S| <= 1e-6 plus the
+    moments epilogue, timed per solve (the FP32 production path, graph-replayed chunks),
+    the sweep kernel against its roofline, and the plain FP64 GPU solve."""
     wl = W.scattering(args.n)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     chi, eps, B = dev(wl.chi), dev(wl.eps), dev(wl.B)
@@ -431,13 +522,11 @@ def main():
     order = rt.RT_SC_BEZIER if args.order == "bezier" else rt.RT_SC_LINEAR
     quad = args.interp == "quadratic"
     if quad and order:
-        print("--interp quadratic is built with first-order segments only", file=sys.stderr)
-        sys.exit(2)
+        raise SystemExit("--interp quadratic is built with first-order segments only")
     interp = rt.RT_INTERP_QUADRATIC if quad else rt.RT_INTERP_BILINEAR
     gs = args.ali == "gauss-seidel"
     if gs and (quad or order):
-        print("--ali gauss-seidel is built with first-order segments and bilinear I- only", file=sys.stderr)
-        sys.exit(2)
+        raise SystemExit("--ali gauss-seidel is built with first-order segments and bilinear I- only")
     kind = "quadratic" if quad else args.order
     ops_per_update = OPS_PER_UPDATE_QUAD_F32 if quad else (OPS_PER_UPDATE_BEZ_F32 if order else OPS_PER_UPDATE_F32)
     prob = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
@@ -455,14 +544,14 @@ def main():
         st["heating"] = prob.moments(S, want_heating=True, **mom)
         return st
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     # timed steps: the production path (ALI chunks replayed as HIP graphs)
     lat, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         t0 = time.perf_counter()
         st = step()
         torch.cuda.synchronize()
@@ -531,8 +620,8 @@ def main():
         p64.close()
 
     out = {
-        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": total / steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded, generated on the host)",
         "config": {"workload": f"scattering {wl.shape[0]}^3, 1 bin, {wl.na} rays, eps=1e-3, "
@@ -544,7 +633,7 @@ def main():
                    "ali": args.ali,
                    "schedule": args.schedule,
                    "bins": wl.nf},
-        "ali_solves_per_s": args.steps / total,
+        "ali_solves_per_s": steps / total,
         "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
         "iterations": iters,
         "heating": st["heating"],
@@ -552,9 +641,90 @@ def main():
         "roofline": roofline,
     }
     out.update(extra)
-    if args.cpu_sweeps > 0:
+    if cpu and args.cpu_sweeps > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sweeps, order, 1 if quad else 0)
     prob.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (multifreq: ALI iterations over all bins)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128, help="grid edge of the scattering workload")
+    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 GPU comparison solve")
+    ap.add_argument("--schedule", choices=["stages"], default="stages")
+    ap.add_argument("--order", choices=["linear", "bezier"], default="linear",
+                    help="scattering: first-order or second-order (Bezier) short characteristics")
+    ap.add_argument("--interp", choices=["bilinear", "quadratic"], default="bilinear",
+                    help="scattering: upwind intensity bilinear (tile wavefront) or monotone quadratic "
+                         "(plane-ordered sweep)")
+    ap.add_argument("--ali", choices=["jacobi", "gauss-seidel"], default="jacobi",
+                    help="scattering: Jacobi ALI, or Gauss-Seidel with horizontal planes as the blocks")
+    ap.add_argument("--fixed-iters", type=int, default=0,
+                    help="profiling mode: run exactly this many ALI iterations per step instead of converging")
+    ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
+    ap.add_argument("--streams", type=int, default=4, help="serving: pool problems that are drifting streams")
+    ap.add_argument("--requests", type=int, default=24, help="serving: requests per arrival rate")
+    ap.add_argument("--workload", choices=["multifreq", "scattering", "batched", "serving"], default="multifreq",
+                    help="multifreq: 192^3 x 64 bins x 80 rays, a step is one Jacobi iteration over all bins "
+                         "(default; the 128^3 scattering solves are reported beside it); scattering: the 128^3 "
+                         "single-bin solve; batched: many uneven problems; serving: the request loop")
+    ap.add_argument("--bins", type=int, default=64, help="multifreq: bins of the 64 to run")
+    ap.add_argument("--mf-n", type=int, default=192, help="multifreq: grid edge")
+    ap.add_argument("--mf-converge", action="store_true", help="multifreq: also one whole solve to 1e-6 per bin")
+    ap.add_argument("--scattering-steps", type=int, default=3,
+                    help="multifreq: converged 128^3 scattering solves reported beside the line (0 = skip)")
+    ap.add_argument("--count", type=int, default=96, help="problems of the batched workload")
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--seq-sample", type=int, default=0,
+                    help="batched workload: also solve this many of its problems one at a time")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (for scaling rocprofv3 FETCH/WRITE_SIZE) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (bins and independent "
+              "problems would shard across GPUs with no communication but a few reduced scalars)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1201_2222_amd as rt
+    from paper_1201_2222_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args, rt, W, torch, np)), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(bench_serving(args, rt, W, torch, np)), flush=True)
+        return
+    if args.workload == "scattering":
+        print(json.dumps(bench_scattering(args, rt, W, torch, np, args.steps, args.warmup)), flush=True)
+        return
+    out = bench_multifreq(args, rt, W, torch, np)
+    if args.scattering_steps > 0:
+        sc = bench_scattering(args, rt, W, torch, np, args.scattering_steps, 1, cpu=False)
+        out["scattering_128"] = {k: sc[k] for k in ("config", "ali_solves_per_s", "latency_ms", "iterations",
+                                                   "value", "unit", "ms_per_step", "steps")}
+        out["scattering_128"]["roofline"] = {k: sc["roofline"][k] for k in ("bound", "achieved", "peak", "unit",
+                                                                           "frac", "avg_launch_us")}
+        if "f64_gpu_solve" in sc:
+            out["scattering_128"]["f64_gpu_solve"] = sc["f64_gpu_solve"]
+    if args.cpu_sweeps > 0:
+        out["cpu_baseline"] = cpu_baseline_multifreq(args.mf_n, 64, [16, 48])
     print(json.dumps(out), flush=True)
 
 

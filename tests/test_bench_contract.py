@@ -21,9 +21,9 @@ def test_more_than_one_gpu_is_refused():
 @pytest.mark.gpu
 @pytest.mark.timeout(600)
 def test_bench_prints_one_json_line():
-    run = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--n", "32", "--steps", "2",
-                          "--warmup", "1", "--cpu-sweeps", "1"], cwd=ROOT, capture_output=True, text=True,
-                         timeout=500)
+    run = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", "scattering", "--n",
+                          "32", "--steps", "2", "--warmup", "1", "--cpu-sweeps", "1"], cwd=ROOT, capture_output=True,
+                         text=True, timeout=500)
     assert run.returncode == 0, run.stderr[-3000:]
     lines = [l for l in run.stdout.splitlines() if l.strip()]
     assert len(lines) == 1
@@ -40,3 +40,29 @@ def test_bench_prints_one_json_line():
     assert r["traffic"] is None   # byte counters were taken on the 128^3 workload only
     c = out["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] == 1 and c["value"] > 0 and c["sample"]
+
+
+@pytest.mark.gpu
+@pytest.mark.timeout(600)
+def test_bench_default_multifreq_line():
+    """The default line (multi-frequency workload, here on a small grid and 4 bins): one
+    JSON line whose roofline carries the VALU and the HBM fractions, the 128^3 scattering
+    solves beside it (here 32^3), and a CPU baseline with its single-thread leg."""
+    run = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--mf-n", "32", "--bins", "4",
+                          "--steps", "3", "--warmup", "1", "--n", "32", "--scattering-steps", "1"], cwd=ROOT,
+                         capture_output=True, text=True, timeout=500)
+    assert run.returncode == 0, run.stderr[-3000:]
+    lines = [l for l in run.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    assert out["steps"] == 3 and out["warmup"] == 1 and out["value"] > 0
+    assert out["config"]["bins"] == 4 and out["config"]["rays"] == 80
+    r = out["roofline"]
+    assert r["bound"] == "alu" and 0 < r["frac"] < 1 and r["traffic"] is None
+    h = r["hbm"]
+    assert h["unit"] == "GB/s" and abs(h["frac"] - h["achieved"] / h["peak"]) < 1e-12
+    assert abs(h["bytes_per_update"] - 1.2) < 1e-12
+    assert out["scattering_128"]["ali_solves_per_s"] > 0
+    c = out["cpu_baseline"]
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0
+    assert c["single_thread"]["cores"] == 1 and c["single_thread"]["value"] > 0
