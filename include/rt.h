@@ -19,20 +19,28 @@
  *     Eddington tensor f = K/J and the heating rate Q_rad (section 4).
  *
  * Conventions shared by every entry point
- *   - Field layout: FP64, C order [nf][nz][ny][nx] (x fastest), one value per
- *     vertex and frequency bin.  "cells" = nx*ny*nz.
- *   - Device pointers are HIP device memory on the device that was current when
- *     the problem was created, and calls on a problem are made with that device
- *     current; host pointers are ordinary host memory.  The caller owns every buffer it passes
- *     and must keep device buffers alive until the stream work has finished.
- *     The library owns the per-problem state it allocates (internal copies of
- *     the fields, Lambda*, the periodic memory, scratch) and frees it in
+ *   - Field layout: C order [nf][nz][ny][nx] (x fastest), one value per vertex and
+ *     frequency bin.  "cells" = nx*ny*nz.  The caller's field arrays (chi, eps, B,
+ *     S, J, Lambda* and the moments outputs) are FP64 or, with
+ *     rt_problem_desc.in_dtype = RT_DTYPE_F32, FP32; they are passed as void*.
+ *     The library computes in FP64 (and in FP32 inside the RT_F32 sweeps) either
+ *     way: FP32 arrays are widened on the device when read and rounded when written.
+ *     Fixed incident intensities (I_fixed) are always FP64.
+ *   - Device pointers are HIP device memory on the device that holds the problem:
+ *     the device of its context (rt_context_create), or, created without one, the
+ *     device current at creation.  Every call on a problem (and on a server) makes
+ *     that device current for its duration and restores the caller's on return.
+ *     Host pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes and must keep device buffers alive until the stream work has finished.
+ *     The library owns the per-problem state it allocates (internal copies of the
+ *     fields, Lambda*, the periodic memory, scratch) and frees it in
  *     rt_problem_destroy.
  *   - Every argument is validated before any device work is queued: a call that
  *     returns RT_E_INVALID has changed nothing.  The reason is kept in
- *     rt_last_error().  No call throws.
+ *     rt_last_error(): per context for calls on its problems, servers and batches,
+ *     and per host thread for every call.  No call throws.
  *   - Streams are hipStream_t values passed as void* (NULL = the null stream).
- *   - A problem is used by one host thread at a time.
+ *   - A problem, and a context, is used by one host thread at a time.
  *   - Environment: RTSC_TILE_ORDER_SEED = n (n != 0) when a problem is created makes
  *     each launch of the tile wavefront take the tiles of its stage in an order
  *     shuffled with seed n.  Tiles of one stage are independent, so results are
@@ -63,6 +71,9 @@ typedef enum {
  * RT_F32 integrates D = I - S in FP32 (algebraically the same recurrence);
  * Lambda*, the ALI update, residuals and all sums stay FP64 in both. */
 typedef enum { RT_F64 = 0, RT_F32 = 1 } rt_precision;
+
+/* Element type of the caller's field arrays (rt_problem_desc.in_dtype). */
+typedef enum { RT_DTYPE_F64 = 0, RT_DTYPE_F32 = 1 } rt_dtype;
 
 /* Boundary kinds (section 3.5): intensity entering through a face is zero
  * (VACUUM), the thermal source function B of the boundary vertex (THERMAL),
@@ -120,13 +131,30 @@ typedef struct {
     int32_t schedule;         /* rt_schedule: how the tile wavefront is executed */
     int32_t order;            /* rt_sc_order: first- or second-order segments */
     int32_t interp;           /* rt_interp: bilinear or monotone quadratic upwind intensity */
+    int32_t in_dtype;         /* rt_dtype of the caller's field arrays (0 = FP64) */
 } rt_problem_desc;
 
 typedef struct rt_problem rt_problem;
 
-/* Human-readable text of a status / of the last failure on this thread. */
+/*
+ * A context: one HIP device and the last error of the calls made through it.
+ * rt_context_create -- device: a HIP device ordinal (RT_E_INVALID if there is no such
+ *   device).  Problems created in the context live on that device; batches and servers
+ *   given the context run there.  NULL may be passed wherever a context is taken: the
+ *   device current at the call is used and errors are kept per thread only.
+ * rt_context_destroy -- frees the context; its problems and servers must be destroyed
+ *   first.
+ */
+typedef struct rt_context rt_context;
+
+rt_status rt_context_create(int32_t device, rt_context **out);
+rt_status rt_context_destroy(rt_context *ctx);
+
+/* Human-readable text of a status; the last failure recorded in a context (ctx), or
+ * on the calling thread (ctx = NULL).  The text stays valid until the next call on
+ * the same thread. */
 const char *rt_status_string(rt_status s);
-const char *rt_last_error(void);
+const char *rt_last_error(const rt_context *ctx);
 
 /*
  * rt_quadrature -- the level-symmetric angle set of section 3.2: n_a = n_mu (n_mu + 2)
@@ -143,20 +171,22 @@ rt_status rt_quadrature(int32_t n_mu, double *mu_out, double *w_out, int32_t *na
 /* Device bytes rt_problem_create would allocate for this description. */
 rt_status rt_problem_bytes(const rt_problem_desc *desc, size_t *bytes);
 
-/* Create the per-problem device state on the current HIP device. */
-rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out);
+/* Create the per-problem device state on the context's device (ctx may be NULL: the
+ * current device). */
+rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_problem **out);
 rt_status rt_problem_destroy(rt_problem *p);
 
 /*
  * rt_problem_set_fields -- radiative properties per vertex and bin (section 2,
  * eq. sourcefunc; section 3.1): chi = chi_abs + chi_sc (> 0 or 0), eps =
- * chi_abs/chi_tot in [0, 1], B the thermal source function.  Device FP64
- * [nf][nz][ny][nx].  The values are copied; the caller may reuse its buffers once
- * the stream has passed this call.  Computes Lambda* (the diagonal of section 3.4)
- * and resets the periodic memory to its cold state.
+ * chi_abs/chi_tot in [0, 1], B the thermal source function.  Device
+ * [nf][nz][ny][nx] in the problem's in_dtype.  The values are copied (widened to
+ * FP64); the caller may reuse its buffers once the stream has passed this call.
+ * Computes Lambda* (the diagonal of section 3.4) and resets the periodic memory to
+ * its cold state.
  */
-rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *eps,
-                                const double *B, void *stream);
+rt_status rt_problem_set_fields(rt_problem *p, const void *chi, const void *eps,
+                                const void *B, void *stream);
 
 /* Forget the previous sweep: periodic ghosts read S of the wrapped vertex on the
  * next sweep (cold start of the periodic iteration, section 3). */
@@ -192,11 +222,12 @@ rt_status rt_problem_load_state(rt_problem *p, const void *src, size_t bytes, vo
  * rt_formal_solve -- one formal solution J = Lambda[S] (section 3.4, eq. formalsol):
  * every ray is integrated once over the grid (section 3.3).  Periodic ghosts come
  * from the previous sweep of this problem (section 3's iteration for periodic
- * boundaries) or, after create/reset, from S.  S: device [nf][cells] FP64 (read);
- * J: device [nf][cells] FP64 (written); lambda_star: device [nf][cells] or NULL,
- * receives Lambda*_ii = sum_k w_k psi0_k.  Asynchronous on the stream.
+ * boundaries) or, after create/reset, from S.  S: device [nf][cells] (read); J:
+ * device [nf][cells] (written); lambda_star: device [nf][cells] or NULL, receives
+ * Lambda*_ii = sum_k w_k psi0_k; all in the problem's in_dtype.  Asynchronous on the
+ * stream.
  */
-rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lambda_star,
+rt_status rt_formal_solve(rt_problem *p, const void *S, void *J, void *lambda_star,
                           void *stream);
 
 typedef struct {
@@ -221,11 +252,13 @@ typedef struct {
  *   S^{n+1} = S^n + dS;  r = max over cells with S^{n+1} != 0 of |dS|/|S^{n+1}|  (eq. conv)
  * per bin, in FP64.  On return S_inout holds S^{n+1} and J_out holds J^n of each
  * bin's last iteration.  Start values per opts->warm_start; S_inout, J_out: device
- * [nf][cells] FP64.  Synchronises the stream every check_every iterations to read
- * the convergence flags; stats (host, may be NULL) reports them.
+ * [nf][cells] in the problem's in_dtype (with FP32 arrays the iteration runs on FP64
+ * copies the library keeps, and S and J are rounded to FP32 at the end).
+ * Synchronises the stream every check_every iterations to read the convergence
+ * flags; stats (host, may be NULL) reports them.
  * Returns RT_OK, RT_NOT_CONVERGED or RT_E_NONFINITE (outputs then undefined).
  */
-rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, void *S_inout, void *J_out,
                        rt_ali_stats *stats, void *stream);
 
 /*
@@ -247,7 +280,7 @@ rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, 
  * before any work.  The first call on a problem allocates its plane buffers
  * (nf * (na/2) * 3 * nx * ny reals).
  */
-rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, void *S_inout, void *J_out,
                           rt_ali_stats *stats, void *stream);
 
 /*
@@ -260,14 +293,14 @@ rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inou
  * RT_E_UNSUPPORTED if the LDS does not fit or for the plane-ordered sweep).  Results
  * change only in the rounding of the sums over the waves.  Host-only call.
  *
- * rt_problem_tune -- time `reps` formal solutions of S (device [nf][cells] FP64, fields
- * set) for every wave count that fits, keep the fastest, and report it in *waves_out;
+ * rt_problem_tune -- time `reps` formal solutions of S (device [nf][cells] in the
+ * problem's in_dtype, fields set) for every wave count that fits, keep the fastest, and report it in *waves_out;
  * ms_out (host [10] or NULL) receives the milliseconds per sweep of each count (-1
  * where it does not fit).  The periodic memory the next solve reads is left as it was
  * (a problem with no sweep yet stays cold).  Synchronises the stream.
  */
 rt_status rt_problem_set_waves(rt_problem *p, int32_t waves);
-rt_status rt_problem_tune(rt_problem *p, const double *S, int32_t reps, int32_t *waves_out, float *ms_out,
+rt_status rt_problem_tune(rt_problem *p, const void *S, int32_t reps, int32_t *waves_out, float *ms_out,
                           void *stream);
 
 /*
@@ -298,22 +331,25 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
  * runs its own plane-step, update and convergence launches in the same iterations.  A problem that meets the stopping rule (or its
  * max_iter / fixed_iters) leaves the batch at the next check; the others go on.
  * Results per problem are those rt_ali_solve gives for it alone (identical
- * arithmetic).  problems: host array [n] of distinct problems with fields set;
- * S_inout, J_out: host arrays [n] of device pointers as for rt_ali_solve; stats,
+ * arithmetic).  ctx: the context whose device runs the batch and keeps its errors,
+ * or NULL (the current device); every problem must live on that device.  problems:
+ * host array [n] of distinct problems with fields set; S_inout, J_out: host arrays
+ * [n] of device pointers as for rt_ali_solve (each in its problem's in_dtype); stats,
  * results: host arrays [n] or NULL (per-problem RT_OK / RT_NOT_CONVERGED /
  * RT_E_NONFINITE; stats.seconds = wall time until that problem left the batch).
  * opts apply to every problem.  Returns RT_E_NONFINITE if any problem hit a
  * non-finite residual, else RT_NOT_CONVERGED if any did not converge, else RT_OK.
  * Synchronises the stream every check_every iterations.
  */
-rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_ali_opts *opts,
-                             double *const *S_inout, double *const *J_out, rt_ali_stats *stats,
+rt_status rt_ali_solve_batch(rt_context *ctx, rt_problem *const *problems, int32_t n, const rt_ali_opts *opts,
+                             void *const *S_inout, void *const *J_out, rt_ali_stats *stats,
                              rt_status *results, void *stream);
 
 /*
  * Serving loop: ALI solves submitted at any time run together in one batch (as in
  * rt_ali_solve_batch) on a worker thread of the server with its own stream on the
- * device that was current at rt_server_create.  Requests are admitted in arrival
+ * device of its context (ctx, or with ctx = NULL the device current at
+ * rt_server_create); submitted problems must live on that device.  Requests are admitted in arrival
  * order at the batch's convergence checks while the summed rt_problem_bytes of the
  * admitted problems stays within hbm_budget (a request larger than the budget runs
  * alone); the rest wait in the queue.  A problem keeps its device state between
@@ -324,12 +360,19 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
  */
 typedef struct rt_server rt_server;
 
-rt_status rt_server_create(size_t hbm_budget, int32_t check_every, rt_server **out);
+rt_status rt_server_create(rt_context *ctx, size_t hbm_budget, int32_t check_every, rt_server **out);
 
 /* Queue an ALI solve (arguments as for rt_ali_solve); *ticket identifies it.
- * The problem must not be part of another queued or running request. */
-rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opts, double *S_inout,
-                           double *J_out, uint64_t *ticket);
+ * The problem must not be part of another queued or running request.  `stream` is the
+ * caller's stream that produced the request's inputs (the problem's fields, S, J): the
+ * call records an event on it, and the server's stream waits for that event before
+ * any of the request's device work, so work the caller queued on that stream before
+ * the call (set_fields, writes to S or J) is complete when the solve reads it.
+ * Inputs written on other streams must be complete before the call.  The caller
+ * must not touch S or J (or destroy the problem) until rt_server_poll reports the
+ * request finished; the library only holds the pointers. */
+rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opts, void *S_inout,
+                           void *J_out, void *stream, uint64_t *ticket);
 
 /* RT_E_BUSY while the request is queued or running; RT_OK once it has finished,
  * with *result its solve status (RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE, or the
@@ -342,21 +385,25 @@ rt_status rt_server_poll(rt_server *srv, uint64_t ticket, rt_ali_stats *stats, r
 /* Forget a finished ticket's record. */
 rt_status rt_server_release(rt_server *srv, uint64_t ticket);
 
-/* Counts of queued and running requests (either may be NULL). */
-rt_status rt_server_load(rt_server *srv, int32_t *queued, int32_t *running);
+/* Counts of queued and running requests, and the summed rt_problem_bytes of the
+ * running ones (admission keeps it within hbm_budget unless one request larger than
+ * the budget runs alone); any output may be NULL. */
+rt_status rt_server_load(rt_server *srv, int32_t *queued, int32_t *running, size_t *running_bytes);
 
 /* Finish every queued and running request, stop the worker and free the server. */
 rt_status rt_server_destroy(rt_server *srv);
 
+/* Device outputs in the problem's in_dtype (FP64 sums rounded once at the end when
+ * FP32); heating is a host FP64 scalar either way. */
 typedef struct {
-    double *J;         /* device [nf][cells] or NULL */
-    double *H;         /* device [3][nf][cells] or NULL */
-    double *K;         /* device [6][nf][cells] (xx yy zz xy xz yz) or NULL */
-    double *J_int;     /* device [cells]: sum_nu w_nu J_nu, or NULL */
-    double *H_int;     /* device [3][cells] or NULL */
-    double *K_int;     /* device [6][cells] or NULL */
-    double *f_int;     /* device [6][cells]: K_int/J_int (0 where J_int = 0), or NULL; needs J_int, K_int */
-    double *Q_int;     /* device [cells]: sum_nu w_nu Q_nu, or NULL */
+    void *J;           /* device [nf][cells] or NULL */
+    void *H;           /* device [3][nf][cells] or NULL */
+    void *K;           /* device [6][nf][cells] (xx yy zz xy xz yz) or NULL */
+    void *J_int;       /* device [cells]: sum_nu w_nu J_nu, or NULL */
+    void *H_int;       /* device [3][cells] or NULL */
+    void *K_int;       /* device [6][cells] or NULL */
+    void *f_int;       /* device [6][cells]: K_int/J_int (0 where J_int = 0), or NULL; needs J_int, K_int */
+    void *Q_int;       /* device [cells]: sum_nu w_nu Q_nu, or NULL */
     double *heating;   /* host scalar: sum over cells of Q_int dV, or NULL (synchronises) */
 } rt_moments_out;
 
@@ -370,7 +417,7 @@ typedef struct {
  * advances by one sweep).  Asynchronous unless heating is requested (then the stream
  * is synchronised to return the FP64 sum over cells of Q_int dV).
  */
-rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream);
+rt_status rt_moments(rt_problem *p, const void *S, const rt_moments_out *out, void *stream);
 
 /*
  * Sweep-kernel timing, for measuring the formal solution against its roofline.

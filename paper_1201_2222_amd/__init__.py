@@ -23,9 +23,10 @@ RT_BC_VACUUM, RT_BC_THERMAL, RT_BC_PERIODIC, RT_BC_FIXED = 0, 1, 2, 3
 RT_SCHED_DEFAULT, RT_SCHED_STAGES, RT_SCHED_PERSISTENT = 0, 1, 2
 RT_SC_LINEAR, RT_SC_BEZIER = 0, 1
 RT_INTERP_BILINEAR, RT_INTERP_QUADRATIC = 0, 1
+RT_DTYPE_F64, RT_DTYPE_F32 = 0, 1
 
 # names of the C entry points (include/rt.h); every one is looked up at load time
-EXPORTS = ("rt_status_string", "rt_last_error", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
+EXPORTS = ("rt_status_string", "rt_last_error", "rt_context_create", "rt_context_destroy", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_problem_state_bytes",
            "rt_problem_save_state", "rt_problem_load_state", "rt_formal_solve",
            "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_problem_set_waves",
@@ -48,7 +49,7 @@ class ProblemDesc(ctypes.Structure):
                 ("bc_lo", ctypes.c_int32 * 3), ("bc_hi", ctypes.c_int32 * 3),
                 ("I_fixed", ctypes.c_void_p * 6),
                 ("precision", ctypes.c_int32), ("tile", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("interp", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("interp", ctypes.c_int32), ("in_dtype", ctypes.c_int32)]
 
 
 class AliOpts(ctypes.Structure):
@@ -88,10 +89,12 @@ def load():
     lib.rt_status_string.restype = ctypes.c_char_p
     lib.rt_status_string.argtypes = [ctypes.c_int]
     lib.rt_last_error.restype = ctypes.c_char_p
-    lib.rt_last_error.argtypes = []
+    lib.rt_last_error.argtypes = [P]
+    lib.rt_context_create.argtypes = [I32, ctypes.POINTER(P)]
+    lib.rt_context_destroy.argtypes = [P]
     lib.rt_quadrature.argtypes = [I32, P, P, P]
     lib.rt_problem_bytes.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_size_t)]
-    lib.rt_problem_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
+    lib.rt_problem_create.argtypes = [P, ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
     lib.rt_problem_destroy.argtypes = [P]
     lib.rt_problem_set_fields.argtypes = [P, P, P, P, P]
     lib.rt_problem_reset_periodic.argtypes = [P, P]
@@ -108,12 +111,12 @@ def load():
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
     lib.rt_problem_profile.argtypes = [P, I32]
     lib.rt_problem_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
-    lib.rt_ali_solve_batch.argtypes = [P, I32, ctypes.POINTER(AliOpts), P, P, P, P, P]
-    lib.rt_server_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
-    lib.rt_server_submit.argtypes = [P, P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.rt_ali_solve_batch.argtypes = [P, P, I32, ctypes.POINTER(AliOpts), P, P, P, P, P]
+    lib.rt_server_create.argtypes = [P, ctypes.c_size_t, I32, ctypes.POINTER(P)]
+    lib.rt_server_submit.argtypes = [P, P, ctypes.POINTER(AliOpts), P, P, P, ctypes.POINTER(ctypes.c_uint64)]
     lib.rt_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(AliStats), ctypes.POINTER(ctypes.c_int)]
     lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
-    lib.rt_server_load.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    lib.rt_server_load.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_size_t)]
     lib.rt_server_destroy.argtypes = [P]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
@@ -124,8 +127,25 @@ def load():
 def _check(status, allow=(RT_OK,)):
     if status not in allow:
         lib = load()
-        raise RtError(status, lib.rt_last_error().decode())
+        raise RtError(status, lib.rt_last_error(None).decode())
     return status
+
+
+def _hval(h):
+    """Integer value of a library handle (ctypes.c_void_p or int)."""
+    return h.value if isinstance(h, ctypes.c_void_p) else int(h)
+
+
+# Shape of every live problem handle, for the size checks of the marshalling:
+# handle value -> (cells, nf, in_dtype, na)
+_SHAPES = {}
+
+
+def _shape(p):
+    try:
+        return _SHAPES[_hval(p)]
+    except KeyError:
+        raise ValueError("unknown or destroyed problem handle") from None
 
 
 def _stream(stream):
@@ -137,18 +157,35 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dptr(t, n=None, name="tensor"):
-    """Device pointer of a contiguous float64 CUDA tensor with n elements."""
+def _dptr(t, n=None, name="tensor", dtype=RT_DTYPE_F64):
+    """Device pointer of a contiguous CUDA tensor of the given element type (float64, or
+    float32 for RT_DTYPE_F32) with n elements; refuses any other tensor before the
+    library sees it, so a short buffer never reaches a kernel."""
     if t is None:
         return None
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+    if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a device tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous():
-        raise TypeError(f"{name} must be contiguous float64")
+    want = torch.float32 if dtype == RT_DTYPE_F32 else torch.float64
+    if t.dtype != want or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous {str(want).replace('torch.', '')}")
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _field(p, t, name, per=1):
+    """Pointer of a field array of problem p: per * nf * cells elements in its in_dtype."""
+    cells, nf, dt, _ = _shape(p)
+    return _dptr(t, per * nf * cells, name, dt)
+
+
+def _cellfield(p, t, name, per=1):
+    """Pointer of a frequency-integrated array of problem p: per * cells elements."""
+    cells, _, dt, _ = _shape(p)
+    return _dptr(t, per * cells, name, dt)
 
 
 def rt_quadrature(n_mu: int):
@@ -165,7 +202,7 @@ def rt_quadrature(n_mu: int):
 
 def make_desc(shape, nf=1, h=(1.0, 1.0, 1.0), n_mu=4, bc_lo=(2, 2, 1), bc_hi=(2, 2, 0), precision=RT_F64,
               mu=None, w=None, w_nu=None, I_fixed=None, tile=0, schedule=RT_SCHED_DEFAULT, order=RT_SC_LINEAR,
-              interp=RT_INTERP_BILINEAR):
+              interp=RT_INTERP_BILINEAR, in_dtype=RT_DTYPE_F64):
     d = ProblemDesc()
     d.nx, d.ny, d.nz = (int(x) for x in shape)
     d.nf = int(nf)
@@ -186,15 +223,20 @@ def make_desc(shape, nf=1, h=(1.0, 1.0, 1.0), n_mu=4, bc_lo=(2, 2, 1), bc_hi=(2,
     d.bc_lo[:] = [int(x) for x in bc_lo]
     d.bc_hi[:] = [int(x) for x in bc_hi]
     if I_fixed is not None:
+        na = d.na if mu is not None else d.n_mu * (d.n_mu + 2)
+        n3 = (d.nx, d.ny, d.nz)
         for k, t in enumerate(I_fixed):
             if t is not None:
-                d.I_fixed[k] = _dptr(t, name="I_fixed").value
+                q = k // 2
+                face = int(np.prod([n3[a] for a in range(3) if a != q]))
+                d.I_fixed[k] = _dptr(t, d.nf * na * face, name="I_fixed").value
                 keep.append(t)
     d.precision = int(precision)
     d.tile = int(tile)
     d.schedule = int(schedule)
     d.order = int(order)
     d.interp = int(interp)
+    d.in_dtype = int(in_dtype)
     d._keep = keep
     return d
 
@@ -206,21 +248,40 @@ def rt_problem_bytes(desc: ProblemDesc) -> int:
     return b.value
 
 
-def rt_problem_create(desc: ProblemDesc):
+def rt_context_create(device=0):
+    """A context on HIP device ``device`` (rt_context_create)."""
+    h = ctypes.c_void_p()
+    _check(load().rt_context_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def rt_context_destroy(ctx):
+    return _check(load().rt_context_destroy(ctx))
+
+
+def rt_last_error(ctx=None):
+    """The last failure recorded in a context, or on this thread (ctx None)."""
+    return load().rt_last_error(ctx).decode()
+
+
+def rt_problem_create(desc: ProblemDesc, ctx=None):
     lib = load()
     h = ctypes.c_void_p()
-    _check(lib.rt_problem_create(ctypes.byref(desc), ctypes.byref(h)))
+    _check(lib.rt_problem_create(ctx, ctypes.byref(desc), ctypes.byref(h)))
+    na = desc.na if desc.mu else desc.n_mu * (desc.n_mu + 2)
+    _SHAPES[h.value] = (int(desc.nx) * int(desc.ny) * int(desc.nz), int(desc.nf), int(desc.in_dtype), int(na))
     return h
 
 
 def rt_problem_destroy(p):
-    return _check(load().rt_problem_destroy(p))
+    st = _check(load().rt_problem_destroy(p))
+    _SHAPES.pop(_hval(p), None)
+    return st
 
 
 def rt_problem_set_fields(p, chi, eps, B, stream=None):
-    n = chi.numel()
-    return _check(load().rt_problem_set_fields(p, _dptr(chi, name="chi"), _dptr(eps, n, "eps"),
-                                               _dptr(B, n, "B"), _stream(stream)))
+    return _check(load().rt_problem_set_fields(p, _field(p, chi, "chi"), _field(p, eps, "eps"), _field(p, B, "B"),
+                                               _stream(stream)))
 
 
 def rt_problem_reset_periodic(p, stream=None):
@@ -260,9 +321,8 @@ def rt_problem_load_state(p, src, stream=None):
 
 
 def rt_formal_solve(p, S, J, lambda_star=None, stream=None):
-    n = S.numel()
-    return _check(load().rt_formal_solve(p, _dptr(S, name="S"), _dptr(J, n, "J"),
-                                         _dptr(lambda_star, n, "lambda_star"), _stream(stream)))
+    return _check(load().rt_formal_solve(p, _field(p, S, "S"), _field(p, J, "J"),
+                                         _field(p, lambda_star, "lambda_star"), _stream(stream)))
 
 
 def rt_ali_solve(p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True, warm_start=0,
@@ -272,16 +332,15 @@ def rt_ali_solve(p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_s
     o = AliOpts(float(delta_c), int(max_iter), int(fixed_iters), 1 if per_bin_stop else 0, int(warm_start),
                 int(check_every))
     st = AliStats()
-    n = S.numel()
     fn = load().rt_ali_solve_gs if gauss_seidel else load().rt_ali_solve
-    status = fn(p, ctypes.byref(o), _dptr(S, name="S"), _dptr(J, n, "J"), ctypes.byref(st), _stream(stream))
+    status = fn(p, ctypes.byref(o), _field(p, S, "S"), _field(p, J, "J"), ctypes.byref(st), _stream(stream))
     _check(status, allow=(RT_OK, RT_NOT_CONVERGED))
     return status, {"iterations": st.iterations, "bins_converged": st.bins_converged,
                     "max_rel_dS": st.max_rel_dS, "seconds": st.seconds}
 
 
 def rt_ali_solve_batch(problems, S_list, J_list, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True,
-                       warm_start=0, check_every=0, stream=None):
+                       warm_start=0, check_every=0, stream=None, ctx=None):
     """Batched ALI over independent problems (handles); returns (status, [per-problem status],
     [per-problem stats dict]).  RT_E_NONFINITE is returned, not raised, so the per-problem
     results can be inspected; other errors raise."""
@@ -292,30 +351,40 @@ def rt_ali_solve_batch(problems, S_list, J_list, delta_c=1e-6, max_iter=10000, f
                 int(check_every))
     probs = (ctypes.c_void_p * n)(*[ctypes.c_void_p(h.value if isinstance(h, ctypes.c_void_p) else h)
                                     for h in problems])
-    Sp = (ctypes.c_void_p * n)(*[_dptr(S, name="S").value for S in S_list])
-    Jp = (ctypes.c_void_p * n)(*[_dptr(J, S.numel(), "J").value for S, J in zip(S_list, J_list)])
+    Sp = (ctypes.c_void_p * n)(*[_field(p, S, "S").value for p, S in zip(problems, S_list)])
+    Jp = (ctypes.c_void_p * n)(*[_field(p, J, "J").value for p, J in zip(problems, J_list)])
     st = (AliStats * n)()
     res = (ctypes.c_int * n)()
-    status = load().rt_ali_solve_batch(probs, n, ctypes.byref(o), Sp, Jp, st, res, _stream(stream))
+    status = load().rt_ali_solve_batch(ctx, probs, n, ctypes.byref(o), Sp, Jp, st, res, _stream(stream))
     _check(status, allow=(RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE))
     stats = [{"iterations": x.iterations, "bins_converged": x.bins_converged, "max_rel_dS": x.max_rel_dS,
               "seconds": x.seconds} for x in st]
     return status, list(res), stats
 
 
-def rt_server_create(hbm_budget, check_every=0):
+# S and J of every unfinished server request, held until its release: the worker
+# keeps only the pointers.  server handle value -> {ticket: (S, J)}
+_PENDING = {}
+
+
+def rt_server_create(hbm_budget, check_every=0, ctx=None):
     h = ctypes.c_void_p()
-    _check(load().rt_server_create(int(hbm_budget), int(check_every), ctypes.byref(h)))
+    _check(load().rt_server_create(ctx, int(hbm_budget), int(check_every), ctypes.byref(h)))
+    _PENDING[h.value] = {}
     return h
 
 
 def rt_server_submit(srv, p, S, J, delta_c=1e-6, max_iter=10000, fixed_iters=0, per_bin_stop=True, warm_start=0,
-                     check_every=0):
+                     check_every=0, stream=None):
+    """Queue a solve; the server's stream waits for the work queued on ``stream`` (the
+    current stream when None) before the request's first kernel.  S and J are held here
+    until rt_server_release."""
     o = AliOpts(float(delta_c), int(max_iter), int(fixed_iters), 1 if per_bin_stop else 0, int(warm_start),
                 int(check_every))
     t = ctypes.c_uint64()
-    _check(load().rt_server_submit(srv, p, ctypes.byref(o), _dptr(S, name="S"), _dptr(J, S.numel(), "J"),
+    _check(load().rt_server_submit(srv, p, ctypes.byref(o), _field(p, S, "S"), _field(p, J, "J"), _stream(stream),
                                    ctypes.byref(t)))
+    _PENDING.setdefault(_hval(srv), {})[t.value] = (S, J)
     return t.value
 
 
@@ -332,17 +401,23 @@ def rt_server_poll(srv, ticket):
 
 
 def rt_server_release(srv, ticket):
-    return _check(load().rt_server_release(srv, ctypes.c_uint64(ticket)))
+    st = _check(load().rt_server_release(srv, ctypes.c_uint64(ticket)))
+    _PENDING.get(_hval(srv), {}).pop(ticket, None)
+    return st
 
 
-def rt_server_load(srv):
-    q, r = ctypes.c_int32(), ctypes.c_int32()
-    _check(load().rt_server_load(srv, ctypes.byref(q), ctypes.byref(r)))
-    return q.value, r.value
+def rt_server_load(srv, with_bytes=False):
+    """(queued, running) requests, and with_bytes: also the summed rt_problem_bytes of
+    the running ones."""
+    q, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(load().rt_server_load(srv, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)))
+    return (q.value, r.value, b.value) if with_bytes else (q.value, r.value)
 
 
 def rt_server_destroy(srv):
-    return _check(load().rt_server_destroy(srv))
+    st = _check(load().rt_server_destroy(srv))   # finishes every request first
+    _PENDING.pop(_hval(srv), None)
+    return st
 
 
 def rt_ali_bin_stats(p, nf, stream=None):
@@ -356,10 +431,12 @@ def rt_ali_bin_stats(p, nf, stream=None):
 def rt_moments(p, S, J=None, H=None, K=None, J_int=None, H_int=None, K_int=None, f_int=None, Q_int=None,
                want_heating=False, stream=None):
     heat = ctypes.c_double(0.0)
-    out = MomentsOut(*[(_dptr(t).value if t is not None else None) for t in (J, H, K, J_int, H_int, K_int,
-                                                                            f_int, Q_int)],
+    ptrs = [_field(p, J, "J"), _field(p, H, "H", 3), _field(p, K, "K", 6), _cellfield(p, J_int, "J_int"),
+            _cellfield(p, H_int, "H_int", 3), _cellfield(p, K_int, "K_int", 6), _cellfield(p, f_int, "f_int", 6),
+            _cellfield(p, Q_int, "Q_int")]
+    out = MomentsOut(*[(x.value if x is not None else None) for x in ptrs],
                      ctypes.addressof(heat) if want_heating else None)
-    _check(load().rt_moments(p, _dptr(S, name="S"), ctypes.byref(out), _stream(stream)))
+    _check(load().rt_moments(p, _field(p, S, "S"), ctypes.byref(out), _stream(stream)))
     return heat.value if want_heating else None
 
 
@@ -378,11 +455,11 @@ def rt_problem_profile_read(p):
 class Problem:
     """Owner of one ``rt_problem`` handle (marshalling only)."""
 
-    def __init__(self, shape, nf=1, **kw):
+    def __init__(self, shape, nf=1, ctx=None, **kw):
         self.shape = tuple(int(x) for x in shape)
         self.nf = int(nf)
         self.desc = make_desc(shape, nf=nf, **kw)
-        self.handle = rt_problem_create(self.desc)
+        self.handle = rt_problem_create(self.desc, ctx)
         self.cells = int(np.prod(self.shape))
 
     def set_fields(self, chi, eps, B, stream=None):
@@ -419,7 +496,7 @@ class Problem:
         """Time the sweep for every wave count, keep the fastest: (waves, {waves: ms})."""
         best = ctypes.c_int32()
         ms = (ctypes.c_float * 10)(*([-1.0] * 10))
-        _check(load().rt_problem_tune(self.handle, _dptr(S, name="S"), int(reps), ctypes.byref(best), ms,
+        _check(load().rt_problem_tune(self.handle, _field(self.handle, S, "S"), int(reps), ctypes.byref(best), ms,
                                       _stream(stream)))
         return best.value, {w + 1: ms[w] for w in range(10) if ms[w] >= 0.0}
 

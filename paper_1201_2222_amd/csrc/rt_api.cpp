@@ -30,9 +30,17 @@
 
 using namespace rtsc;
 
+// A device and the last error of the calls made through it (rt_context_create).
+struct rt_context {
+    int device = 0;
+    std::mutex mu;
+    std::string err;
+};
+
 namespace {
 
 thread_local std::string g_err;
+thread_local rt_context *t_ctx = nullptr;   // context of the call in progress on this thread
 
 rt_status fail(rt_status s, const char *fmt, ...)
 {
@@ -42,8 +50,39 @@ rt_status fail(rt_status s, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    if (t_ctx) {
+        std::lock_guard<std::mutex> lk(t_ctx->mu);
+        t_ctx->err = buf;
+    }
     return s;
 }
+
+// For the duration of one entry point: failures are recorded in `ctx` too, and the
+// device of the problem (or context) is current; the caller's context and device
+// are restored on return.
+class CallScope {
+  public:
+    CallScope(rt_context *ctx, int device) : prev_ctx_(t_ctx)
+    {
+        t_ctx = ctx;
+        int cur = -1;
+        if (device >= 0 && hipGetDevice(&cur) == hipSuccess && cur != device && hipSetDevice(device) == hipSuccess) {
+            prev_dev_ = cur;
+        }
+        (void)hipGetLastError();
+    }
+    ~CallScope()
+    {
+        if (prev_dev_ >= 0) (void)hipSetDevice(prev_dev_);
+        t_ctx = prev_ctx_;
+    }
+    CallScope(const CallScope &) = delete;
+    CallScope &operator=(const CallScope &) = delete;
+
+  private:
+    rt_context *prev_ctx_;
+    int prev_dev_ = -1;
+};
 
 #define HIP_TRY(call)                                                                           \
     do {                                                                                        \
@@ -239,6 +278,13 @@ RayGeo ray_geometry(const double m[3], const double h[3], double wk, int gidx)
 
 struct rt_problem {
     rt_problem_desc desc{};
+    rt_context *ctx = nullptr;         // context it was created in, or null
+    int device = 0;                    // HIP device holding its state
+    // caller arrays in FP32 (desc.in_dtype): FP64 copies of the caller's S and J that
+    // the solvers work on, and FP64 staging of the moments outputs (made on first use)
+    bool usr32 = false;
+    double *stS = nullptr, *stJ = nullptr;
+    double *mst[8]{};
     int n[3]{};
     int nf = 0, na = 0, R = 0;
     int nt[3]{};
@@ -348,6 +394,7 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
         !std::isfinite(d->dz))
         return fail(RT_E_INVALID, "dx, dy, dz must be finite and > 0");
     if (d->precision != RT_F64 && d->precision != RT_F32) return fail(RT_E_INVALID, "unknown precision");
+    if (d->in_dtype != RT_DTYPE_F64 && d->in_dtype != RT_DTYPE_F32) return fail(RT_E_INVALID, "unknown in_dtype");
     if (d->tile != 0 && d->tile != kTile) return fail(RT_E_UNSUPPORTED, "tile edge %d not built (only %d)", d->tile, kTile);
     if (d->schedule < RT_SCHED_DEFAULT || d->schedule > RT_SCHED_PERSISTENT) return fail(RT_E_INVALID, "unknown schedule");
     // The persistent schedule did not complete on the device in testing and its
@@ -430,6 +477,7 @@ size_t state_bytes(const rt_problem_desc *d, int na)
         }
         b += (size_t)8 * nc * rs;                  // partials
     }
+    if (d->in_dtype == RT_DTYPE_F32) b += (size_t)nc * 8 * 2;   // FP64 copies of the caller's S and J
     b += (size_t)d->nf * kUpdateBlocks * 8;        // residual block maxima
     b += (size_t)d->nf * 8 * nt[0] * nt[1] * nt[2] * 4 + 32;  // persistent-sweep flags
     b += (size_t)na * sizeof(RayGeo) + (size_t)nt[0] * nt[1] * nt[2] * 4 + (size_t)d->nf * 32 + 64;
@@ -1048,7 +1096,38 @@ const char *rt_status_string(rt_status s)
     return "unknown status";
 }
 
-const char *rt_last_error(void) { return g_err.c_str(); }
+const char *rt_last_error(const rt_context *ctx)
+{
+    if (!ctx) return g_err.c_str();
+    thread_local std::string copy;
+    {
+        std::lock_guard<std::mutex> lk(const_cast<rt_context *>(ctx)->mu);
+        copy = ctx->err;
+    }
+    return copy.c_str();
+}
+
+rt_status rt_context_create(int32_t device, rt_context **out)
+{
+    if (!out) return fail(RT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) {
+        (void)hipGetLastError();
+        count = 0;
+    }
+    if (device < 0 || device >= count) return fail(RT_E_INVALID, "no HIP device %d (%d visible)", device, count);
+    rt_context *c = new rt_context();
+    c->device = device;
+    *out = c;
+    return RT_OK;
+}
+
+rt_status rt_context_destroy(rt_context *ctx)
+{
+    delete ctx;
+    return RT_OK;
+}
 
 rt_status rt_quadrature(int32_t n_mu, double *mu_out, double *w_out, int32_t *na_out)
 {
@@ -1078,6 +1157,7 @@ rt_status rt_problem_bytes(const rt_problem_desc *desc, size_t *bytes)
 rt_status rt_problem_destroy(rt_problem *p)
 {
     if (!p) return RT_OK;
+    CallScope scope(p->ctx, p->device);
     for (void *v : p->allocs) (void)hipFree(v);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     if (p->h_sum) (void)hipHostFree(p->h_sum);
@@ -1093,8 +1173,9 @@ rt_status rt_problem_destroy(rt_problem *p)
     return RT_OK;
 }
 
-rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
+rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_problem **out)
 {
+    CallScope scope(ctx, ctx ? ctx->device : -1);
     if (!out) return fail(RT_E_INVALID, "out is NULL");
     *out = nullptr;
     int na;
@@ -1102,6 +1183,13 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     if (s != RT_OK) return s;
 
     rt_problem *p = new rt_problem();
+    p->ctx = ctx;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return fail(RT_E_HIP, "no current HIP device");
+    }
+    p->usr32 = desc->in_dtype == RT_DTYPE_F32;
     p->desc = *desc;
     p->desc.mu = nullptr;
     p->desc.w = nullptr;
@@ -1182,6 +1270,10 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     ALLOC(p->B, (size_t)nc);
     ALLOC(p->lam, (size_t)nc);
     if (p->f32) ALLOC(p->chi32, (size_t)nc);
+    if (p->usr32) {
+        ALLOC(p->stS, (size_t)nc);
+        ALLOC(p->stJ, (size_t)nc);
+    }
     p->plane_order = desc->interp == RT_INTERP_QUADRATIC;
     p->npart = p->plane_order ? kPlaneParts : 8;
     if (p->plane_order) {
@@ -1279,15 +1371,23 @@ rt_status rt_problem_create(const rt_problem_desc *desc, rt_problem **out)
     return RT_OK;
 }
 
-rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *eps, const double *B, void *stream)
+rt_status rt_problem_set_fields(rt_problem *p, const void *chi, const void *eps, const void *B, void *stream)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
     if (!chi || !eps || !B) return fail(RT_E_INVALID, "chi, eps and B are required");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t bytes = sizeof(double) * p->cells * p->nf;
-    HIP_TRY(hipMemcpyAsync(p->chi64, chi, bytes, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(p->eps, eps, bytes, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(hipMemcpyAsync(p->B, B, bytes, hipMemcpyDeviceToDevice, st));
+    const int64_t nc = p->cells * p->nf;
+    if (p->usr32) {
+        HIP_TRY(launch_convert_f64(static_cast<const float *>(chi), p->chi64, nc, st));
+        HIP_TRY(launch_convert_f64(static_cast<const float *>(eps), p->eps, nc, st));
+        HIP_TRY(launch_convert_f64(static_cast<const float *>(B), p->B, nc, st));
+    } else {
+        const size_t bytes = sizeof(double) * nc;
+        HIP_TRY(hipMemcpyAsync(p->chi64, chi, bytes, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(p->eps, eps, bytes, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(p->B, B, bytes, hipMemcpyDeviceToDevice, st));
+    }
     if (p->f32) HIP_TRY(launch_convert_f32(p->chi64, p->chi32, p->cells * p->nf, st));
     HIP_TRY(launch_lambda_star(p->n, p->desc.bc_lo, p->desc.bc_hi, p->nf, p->na, p->desc.order, p->d_rays, p->chi64,
                                p->lam, st));
@@ -1300,6 +1400,7 @@ rt_status rt_problem_set_fields(rt_problem *p, const double *chi, const double *
 rt_status rt_problem_reset_periodic(rt_problem *p, void *stream)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
     HIP_TRY(hipMemsetAsync(p->parity, 0, sizeof(int) * p->nf, static_cast<hipStream_t>(stream)));
     p->cold = true;
     return RT_OK;
@@ -1368,6 +1469,7 @@ extern "C" {
 rt_status rt_problem_state_bytes(rt_problem *p, size_t *bytes)
 {
     if (!p || !bytes) return fail(RT_E_INVALID, "problem and bytes are required");
+    CallScope scope(p->ctx, p->device);
     *bytes = (size_t)state_header(p).bytes;
     return RT_OK;
 }
@@ -1375,6 +1477,7 @@ rt_status rt_problem_state_bytes(rt_problem *p, size_t *bytes)
 rt_status rt_problem_save_state(rt_problem *p, void *dst, size_t bytes, void *stream)
 {
     if (!p || !dst) return fail(RT_E_INVALID, "problem and dst are required");
+    CallScope scope(p->ctx, p->device);
     const StateHeader h = state_header(p);
     if (bytes < (size_t)h.bytes) return fail(RT_E_INVALID, "dst holds %zu bytes, the state needs %lld", bytes,
                                              (long long)h.bytes);
@@ -1392,6 +1495,7 @@ rt_status rt_problem_save_state(rt_problem *p, void *dst, size_t bytes, void *st
 rt_status rt_problem_load_state(rt_problem *p, const void *src, size_t bytes, void *stream)
 {
     if (!p || !src) return fail(RT_E_INVALID, "problem and src are required");
+    CallScope scope(p->ctx, p->device);
     if (bytes < sizeof(StateHeader)) return fail(RT_E_INVALID, "src holds %zu bytes, less than a header", bytes);
     HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
     StateHeader h;
@@ -1415,13 +1519,21 @@ rt_status rt_problem_load_state(rt_problem *p, const void *src, size_t bytes, vo
     return RT_OK;
 }
 
-rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lambda_star, void *stream)
+rt_status rt_formal_solve(rt_problem *p, const void *S_usr, void *J_usr, void *lambda_star, void *stream)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
-    if (!S || !J) return fail(RT_E_INVALID, "S and J are required");
+    CallScope scope(p->ctx, p->device);
+    if (!S_usr || !J_usr) return fail(RT_E_INVALID, "S and J are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nc = p->cells * p->nf;
+    const double *S = static_cast<const double *>(S_usr);
+    double *J = static_cast<double *>(J_usr);
+    if (p->usr32) {
+        HIP_TRY(launch_convert_f64(static_cast<const float *>(S_usr), p->stS, nc, st));
+        S = p->stS;
+        J = p->stJ;
+    }
     HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
     rt_status s = collect_timing(p);
     if (s != RT_OK) return s;
@@ -1434,7 +1546,12 @@ rt_status rt_formal_solve(rt_problem *p, const double *S, double *J, double *lam
         HIP_TRY(launch_partial_sum<double>(static_cast<double *>(p->part), p->npart, S, 0, p->nf, p->cells, nullptr,
                                            J, st));
     HIP_TRY(launch_flip_parity(p->parity, p->frozen, 0, p->nf, st));
-    if (lambda_star) HIP_TRY(hipMemcpyAsync(lambda_star, p->lam, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    if (p->usr32) {
+        HIP_TRY(launch_convert_f32(p->stJ, static_cast<float *>(J_usr), nc, st));
+        if (lambda_star) HIP_TRY(launch_convert_f32(p->lam, static_cast<float *>(lambda_star), nc, st));
+    } else if (lambda_star) {
+        HIP_TRY(hipMemcpyAsync(lambda_star, p->lam, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    }
     return RT_OK;
 }
 
@@ -1631,29 +1748,50 @@ rt_status chunk_graph(rt_problem *p, int k, bool gs, const double *S, const doub
     return RT_OK;
 }
 
+// An ALI solve on the caller's S and J, or, for FP32 caller arrays, on the problem's
+// FP64 copies of them: widened before (as far as the start values read them) and
+// rounded back after.
+rt_status ali_user(rt_problem *p, const rt_ali_opts *opts, void *S_usr, void *J_usr, rt_ali_stats *stats,
+                   hipStream_t st, std::chrono::steady_clock::time_point t0, bool gs)
+{
+    if (!p->usr32)
+        return ali_run(p, opts, static_cast<double *>(S_usr), static_cast<double *>(J_usr), stats, st, t0, gs);
+    const int64_t nc = p->cells * p->nf;
+    if (opts->warm_start == 1) HIP_TRY(launch_convert_f64(static_cast<const float *>(S_usr), p->stS, nc, st));
+    if (opts->warm_start == 2) HIP_TRY(launch_convert_f64(static_cast<const float *>(J_usr), p->stJ, nc, st));
+    const rt_status s = ali_run(p, opts, p->stS, p->stJ, stats, st, t0, gs);
+    if (s == RT_OK || s == RT_NOT_CONVERGED || s == RT_E_NONFINITE) {
+        HIP_TRY(launch_convert_f32(p->stS, static_cast<float *>(S_usr), nc, st));
+        HIP_TRY(launch_convert_f32(p->stJ, static_cast<float *>(J_usr), nc, st));
+    }
+    return s;
+}
+
 }  // namespace
 
 extern "C" {
 
-rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out, rt_ali_stats *stats,
+rt_status rt_ali_solve(rt_problem *p, const rt_ali_opts *opts, void *S_inout, void *J_out, rt_ali_stats *stats,
                        void *stream)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!p || !opts) return fail(RT_E_INVALID, "problem and opts are required");
+    CallScope scope(p->ctx, p->device);
     if (!S_inout || !J_out) return fail(RT_E_INVALID, "S_inout and J_out are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
     {
         rt_status so = check_ali_opts(opts);
         if (so != RT_OK) return so;
     }
-    return ali_run(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, false);
+    return ali_user(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, false);
 }
 
-rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
+rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, void *S_inout, void *J_out,
                           rt_ali_stats *stats, void *stream)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!p || !opts) return fail(RT_E_INVALID, "problem and opts are required");
+    CallScope scope(p->ctx, p->device);
     if (!S_inout || !J_out) return fail(RT_E_INVALID, "S_inout and J_out are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
     {
@@ -1669,7 +1807,7 @@ rt_status rt_ali_solve_gs(rt_problem *p, const rt_ali_opts *opts, double *S_inou
     if (p->na / 2 > kGsMaxDown) return fail(RT_E_UNSUPPORTED, "Gauss-Seidel takes at most %d rays", 2 * kGsMaxDown);
     rt_status s = gs_prepare(p);
     if (s != RT_OK) return s;
-    return ali_run(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, true);
+    return ali_user(p, opts, S_inout, J_out, stats, static_cast<hipStream_t>(stream), t0, true);
 }
 
 }  // extern "C"
@@ -1812,6 +1950,7 @@ void drop_graphs(rt_problem *p)
 rt_status rt_problem_set_waves(rt_problem *p, int32_t waves)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
     if (p->plane_order) return fail(RT_E_UNSUPPORTED, "the plane-ordered sweep has no wave count");
     const int wmax = std::min(p->R, kMaxWaves);
     if (waves < 1 || waves > wmax) return fail(RT_E_INVALID, "waves must be in [1, %d]", wmax);
@@ -1822,14 +1961,20 @@ rt_status rt_problem_set_waves(rt_problem *p, int32_t waves)
     return RT_OK;
 }
 
-rt_status rt_problem_tune(rt_problem *p, const double *S, int32_t reps, int32_t *waves_out, float *ms_out,
+rt_status rt_problem_tune(rt_problem *p, const void *S_usr, int32_t reps, int32_t *waves_out, float *ms_out,
                           void *stream)
 {
-    if (!p || !S || !waves_out) return fail(RT_E_INVALID, "problem, S and waves_out are required");
+    if (!p || !S_usr || !waves_out) return fail(RT_E_INVALID, "problem, S and waves_out are required");
+    CallScope scope(p->ctx, p->device);
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
     if (p->plane_order) return fail(RT_E_UNSUPPORTED, "the plane-ordered sweep has no wave count");
     if (reps < 1) return fail(RT_E_INVALID, "reps must be >= 1");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const double *S = static_cast<const double *>(S_usr);
+    if (p->usr32) {
+        HIP_TRY(launch_convert_f64(static_cast<const float *>(S_usr), p->stS, p->cells * p->nf, st));
+        S = p->stS;
+    }
     const int wmax = std::min(p->R, kMaxWaves);
     const bool cold = p->cold;
     const int keep = p->waves;
@@ -1882,6 +2027,7 @@ rt_status rt_problem_tune(rt_problem *p, const double *S, int32_t reps, int32_t 
 rt_status rt_problem_use_graphs(rt_problem *p, int32_t enable)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
     p->use_graphs = enable != 0;
     return RT_OK;
 }
@@ -1889,6 +2035,7 @@ rt_status rt_problem_use_graphs(rt_problem *p, int32_t enable)
 rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *stream)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (iters) HIP_TRY(hipMemcpyAsync(iters, p->iters, sizeof(int) * p->nf, hipMemcpyDeviceToHost, st));
     if (resid) HIP_TRY(hipMemcpyAsync(resid, p->resid, sizeof(double) * p->nf, hipMemcpyDeviceToHost, st));
@@ -1899,6 +2046,7 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
 rt_status rt_problem_profile(rt_problem *p, int32_t enable)
 {
     if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
     rt_status s = collect_timing(p);
     if (s != RT_OK) return s;
     if (enable && p->ev.empty()) {
@@ -1916,6 +2064,7 @@ rt_status rt_problem_profile(rt_problem *p, int32_t enable)
 rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out)
 {
     if (!p || !out) return fail(RT_E_INVALID, "problem and out are required");
+    CallScope scope(p->ctx, p->device);
     rt_status s = collect_timing(p);
     if (s != RT_OK) return s;
     out->kernel_ms = p->prof_ms;
@@ -1929,14 +2078,21 @@ rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out)
     return RT_OK;
 }
 
-rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Outputs of the moments epilogue in FP64 (the caller's arrays, or the problem's FP64
+// staging of FP32 caller arrays).
+struct MomOut64 {
+    double *J, *H, *K, *J_int, *H_int, *K_int, *f_int, *Q_int;
+    double *heating;
+};
+
+rt_status moments_core(rt_problem *p, const double *S, const MomOut64 &out, hipStream_t st)
 {
-    if (!p) return fail(RT_E_INVALID, "problem is NULL");
-    if (!S || !out) return fail(RT_E_INVALID, "S and out are required");
-    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool want_int = out->J_int || out->H_int || out->K_int || out->f_int || out->Q_int || out->heating;
-    if (!(out->J || out->H || out->K || want_int)) return RT_OK;
+    const bool want_int = out.J_int || out.H_int || out.K_int || out.f_int || out.Q_int || out.heating;
+    if (!(out.J || out.H || out.K || want_int)) return RT_OK;
     const int64_t cells = p->cells;
     const size_t rs = p->f32 ? sizeof(float) : sizeof(double);
 
@@ -1977,7 +2133,7 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
         mc.m[9] += g.wk * m[1] * m[2];
     }
     const double h[3] = {p->desc.dx, p->desc.dy, p->desc.dz};
-    double *Qint = out->Q_int ? out->Q_int : (out->heating ? p->mom_qint : nullptr);
+    double *Qint = out.Q_int ? out.Q_int : (out.heating ? p->mom_qint : nullptr);
     HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
     for (int f0 = 0; f0 < p->nf; f0 += p->mom_nfc) {
         const int cnt = std::min(p->mom_nfc, p->nf - f0);
@@ -1994,36 +2150,81 @@ rt_status rt_moments(rt_problem *p, const double *S, const rt_moments_out *out, 
         HIP_TRY(launch_flip_parity(p->parity, p->frozen, f0, cnt, st));
         if (p->f32)
             HIP_TRY(launch_moments_combine<float>(static_cast<float *>(p->mom_part), p->npart, S, 1, f0, cnt, p->nf,
-                                                  cells, mc, out->J, out->H, out->K, p->mom_tmp, st));
+                                                  cells, mc, out.J, out.H, out.K, p->mom_tmp, st));
         else
             HIP_TRY(launch_moments_combine<double>(static_cast<double *>(p->mom_part), p->npart, S, 0, f0, cnt, p->nf,
-                                                   cells, mc, out->J, out->H, out->K, p->mom_tmp, st));
+                                                   cells, mc, out.J, out.H, out.K, p->mom_tmp, st));
         if (Qint) HIP_TRY(launch_moments_q(p->mom_tmp, f0, cnt, p->n, h, p->periodic, p->chi64, p->eps, p->B, p->mom_q, st));
         if (want_int) {
-            const bool needK = out->K_int || out->f_int;
-            double *Jt = (out->J_int || out->f_int) ? out->J_int : nullptr;
-            HIP_TRY(launch_moments_integrate(p->mom_tmp, p->mom_q, p->mom_wnu, f0, cnt, cells, f0 == 0, Jt, out->H_int,
-                                             needK ? out->K_int : nullptr, Qint, st));
+            const bool needK = out.K_int || out.f_int;
+            double *Jt = (out.J_int || out.f_int) ? out.J_int : nullptr;
+            HIP_TRY(launch_moments_integrate(p->mom_tmp, p->mom_q, p->mom_wnu, f0, cnt, cells, f0 == 0, Jt, out.H_int,
+                                             needK ? out.K_int : nullptr, Qint, st));
         }
     }
-    if (out->f_int) {
-        if (!out->J_int || !out->K_int) return fail(RT_E_INVALID, "f_int needs J_int and K_int buffers");
-        HIP_TRY(launch_eddington(out->J_int, out->K_int, cells, out->f_int, st));
+    if (out.f_int) {
+        if (!out.J_int || !out.K_int) return fail(RT_E_INVALID, "f_int needs J_int and K_int buffers");
+        HIP_TRY(launch_eddington(out.J_int, out.K_int, cells, out.f_int, st));
     }
-    if (out->heating) {
+    if (out.heating) {
         const int nblk = (int)std::min<int64_t>(1024, (cells + 255) / 256);
         HIP_TRY(launch_sum(Qint, cells, h[0] * h[1] * h[2], p->mom_sum, nblk, p->mom_sum + 1024, st));
         HIP_TRY(hipMemcpyAsync(p->h_sum, p->mom_sum + 1024, sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        *out->heating = *p->h_sum;
+        *out.heating = *p->h_sum;
     }
     return RT_OK;
 }
 
-rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_ali_opts *opts, double *const *S_inout,
-                             double *const *J_out, rt_ali_stats *stats, rt_status *results, void *stream)
+}  // namespace
+
+extern "C" {
+
+rt_status rt_moments(rt_problem *p, const void *S_usr, const rt_moments_out *out, void *stream)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    CallScope scope(p->ctx, p->device);
+    if (!S_usr || !out) return fail(RT_E_INVALID, "S and out are required");
+    if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    if (out->f_int && (!out->J_int || !out->K_int)) return fail(RT_E_INVALID, "f_int needs J_int and K_int buffers");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *const user[8] = {out->J, out->H, out->K, out->J_int, out->H_int, out->K_int, out->f_int, out->Q_int};
+    if (!p->usr32) {
+        MomOut64 o{};
+        double **f64[8] = {&o.J, &o.H, &o.K, &o.J_int, &o.H_int, &o.K_int, &o.f_int, &o.Q_int};
+        for (int k = 0; k < 8; ++k) *f64[k] = static_cast<double *>(user[k]);
+        o.heating = out->heating;
+        return moments_core(p, static_cast<const double *>(S_usr), o, st);
+    }
+    // FP32 caller arrays: S widened, every requested output computed into FP64 staging
+    // (allocated on first use) and rounded into the caller's array
+    const int64_t nc = p->cells * p->nf, c = p->cells;
+    const int64_t count[8] = {nc, 3 * nc, 6 * nc, c, 3 * c, 6 * c, 6 * c, c};
+    MomOut64 o{};
+    double **f64[8] = {&o.J, &o.H, &o.K, &o.J_int, &o.H_int, &o.K_int, &o.f_int, &o.Q_int};
+    for (int k = 0; k < 8; ++k) {
+        if (!user[k]) continue;
+        if (!p->mst[k]) {
+            rt_status a = dalloc(p, &p->mst[k], (size_t)count[k]);
+            if (a != RT_OK) return a;
+        }
+        *f64[k] = p->mst[k];
+    }
+    o.heating = out->heating;
+    HIP_TRY(launch_convert_f64(static_cast<const float *>(S_usr), p->stS, nc, st));
+    rt_status s = moments_core(p, p->stS, o, st);
+    if (s != RT_OK) return s;
+    for (int k = 0; k < 8; ++k)
+        if (user[k]) HIP_TRY(launch_convert_f32(p->mst[k], static_cast<float *>(user[k]), count[k], st));
+    return RT_OK;
+}
+
+rt_status rt_ali_solve_batch(rt_context *ctx, rt_problem *const *problems, int32_t n, const rt_ali_opts *opts,
+                             void *const *S_inout, void *const *J_out, rt_ali_stats *stats, rt_status *results,
+                             void *stream)
 {
     auto t0 = std::chrono::steady_clock::now();
+    CallScope scope(ctx, ctx ? ctx->device : -1);
     if (!problems || !opts || !S_inout || !J_out) return fail(RT_E_INVALID, "problems, opts, S_inout and J_out are required");
     if (n < 1) return fail(RT_E_INVALID, "n must be >= 1");
     {
@@ -2038,13 +2239,28 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
         for (int j = 0; j < i; ++j)
             if (problems[j] == p) return fail(RT_E_INVALID, "problem %d appears twice in the batch", i);
     }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    for (int i = 0; i < n; ++i)
+        if (problems[i]->device != dev)
+            return fail(RT_E_INVALID, "problem %d lives on device %d, the batch runs on %d", i, problems[i]->device, dev);
     hipStream_t st = static_cast<hipStream_t>(stream);
     BatchRunner run(st);
     for (int i = 0; i < n; ++i) {
+        rt_problem *p = problems[i];
         BatchItem it;
-        it.p = problems[i];
-        it.S = S_inout[i];
-        it.J = J_out[i];
+        it.p = p;
+        if (p->usr32) {
+            // FP64 copies of FP32 caller arrays, as far as the start values read them
+            const int64_t nc = p->cells * p->nf;
+            if (opts->warm_start == 1) HIP_TRY(launch_convert_f64(static_cast<const float *>(S_inout[i]), p->stS, nc, st));
+            if (opts->warm_start == 2) HIP_TRY(launch_convert_f64(static_cast<const float *>(J_out[i]), p->stJ, nc, st));
+            it.S = p->stS;
+            it.J = p->stJ;
+        } else {
+            it.S = static_cast<double *>(S_inout[i]);
+            it.J = static_cast<double *>(J_out[i]);
+        }
         it.opts = *opts;
         it.total = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
         it.tag = (uint64_t)i;
@@ -2067,8 +2283,14 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
     }
     rt_status worst = RT_OK;
     for (int i = 0; i < n; ++i) {
+        rt_problem *p = problems[i];
+        if (p->usr32) {
+            const int64_t nc = p->cells * p->nf;
+            HIP_TRY(launch_convert_f32(p->stS, static_cast<float *>(S_inout[i]), nc, st));
+            HIP_TRY(launch_convert_f32(p->stJ, static_cast<float *>(J_out[i]), nc, st));
+        }
         rt_status r = RT_OK;
-        rt_status s = ali_stats(problems[i], opts, nonfin[i] != 0, secs[i], stats ? &stats[i] : nullptr, st, &r);
+        rt_status s = ali_stats(p, opts, nonfin[i] != 0, secs[i], stats ? &stats[i] : nullptr, st, &r);
         if (s != RT_OK) return s;
         if (results) results[i] = r;
         if (r == RT_E_NONFINITE) worst = RT_E_NONFINITE;
@@ -2088,12 +2310,15 @@ rt_status rt_ali_solve_batch(rt_problem *const *problems, int32_t n, const rt_al
 struct rt_server {
     struct Request {
         BatchItem item;
+        void *S_usr = nullptr, *J_usr = nullptr;   // the caller's arrays (FP32 ones are widened)
+        hipEvent_t ready = nullptr;                 // recorded on the caller's stream at submission
         size_t bytes = 0;
         std::chrono::steady_clock::time_point t_submit;
         bool done = false;
         rt_status result = RT_OK;
         rt_ali_stats stats{};
     };
+    rt_context *ctx = nullptr;
     int device = 0;
     size_t budget = 0;
     int every = 16;
@@ -2119,18 +2344,26 @@ struct rt_server {
         --running;
     }
 
+    // a queued request that will never run: its submission event is no longer needed
+    void abandon(uint64_t t, rt_status r)
+    {
+        Request &q = reqs[t];
+        q.done = true;
+        q.result = r;
+        if (q.ready) (void)hipEventDestroy(q.ready);
+        q.ready = nullptr;
+    }
+
     void run()
     {
+        t_ctx = ctx;
         (void)hipSetDevice(device);
         hipStream_t st = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
             std::lock_guard<std::mutex> lk(mu);
             dead = true;
-            for (uint64_t t : queue) {
-                reqs[t].done = true;
-                reqs[t].result = RT_E_HIP;
-            }
+            for (uint64_t t : queue) abandon(t, RT_E_HIP);
             queue.clear();
             cv.notify_all();
             return;
@@ -2154,11 +2387,33 @@ struct rt_server {
                 }
                 for (uint64_t t : admit) {
                     BatchItem it;
+                    hipEvent_t ready = nullptr;
+                    void *S_usr = nullptr, *J_usr = nullptr;
                     {
                         std::lock_guard<std::mutex> lk(mu);
-                        it = reqs[t].item;
+                        Request &q = reqs[t];
+                        it = q.item;
+                        ready = q.ready;
+                        q.ready = nullptr;
+                        S_usr = q.S_usr;
+                        J_usr = q.J_usr;
                     }
-                    rt_status s = batch.add(it);
+                    // the caller's work on its stream before the submission comes first
+                    rt_status s = RT_OK;
+                    if (ready) {
+                        if (hipStreamWaitEvent(st, ready, 0) != hipSuccess) s = fail(RT_E_HIP, "hipStreamWaitEvent failed");
+                        (void)hipEventDestroy(ready);
+                    }
+                    rt_problem *p = it.p;
+                    if (s == RT_OK && p->usr32) {
+                        const int64_t nc = p->cells * p->nf;
+                        hipError_t e = hipSuccess;
+                        if (it.opts.warm_start == 1) e = launch_convert_f64(static_cast<const float *>(S_usr), p->stS, nc, st);
+                        if (e == hipSuccess && it.opts.warm_start == 2)
+                            e = launch_convert_f64(static_cast<const float *>(J_usr), p->stJ, nc, st);
+                        if (e != hipSuccess) s = fail(RT_E_HIP, "conversion launch failed: %s", hipGetErrorString(e));
+                    }
+                    if (s == RT_OK) s = batch.add(it);
                     if (s != RT_OK) {
                         std::lock_guard<std::mutex> lk(mu);
                         finish(t, s, rt_ali_stats{});
@@ -2177,7 +2432,23 @@ struct rt_server {
                 for (const BatchItem &b : fin) {
                     rt_ali_stats sts{};
                     rt_status r = RT_OK;
-                    rt_status s2 = ali_stats(b.p, &b.opts, b.nonfinite, 0.0, &sts, st, &r);
+                    rt_status s2 = RT_OK;
+                    if (b.p->usr32) {
+                        // round the FP64 copies into the caller's FP32 arrays (the
+                        // synchronisation in ali_stats completes them before the request
+                        // is reported finished)
+                        void *S_usr = nullptr, *J_usr = nullptr;
+                        {
+                            std::lock_guard<std::mutex> lk(mu);
+                            S_usr = reqs[b.tag].S_usr;
+                            J_usr = reqs[b.tag].J_usr;
+                        }
+                        const int64_t nc = b.p->cells * b.p->nf;
+                        hipError_t e = launch_convert_f32(b.p->stS, static_cast<float *>(S_usr), nc, st);
+                        if (e == hipSuccess) e = launch_convert_f32(b.p->stJ, static_cast<float *>(J_usr), nc, st);
+                        if (e != hipSuccess) s2 = fail(RT_E_HIP, "conversion launch failed: %s", hipGetErrorString(e));
+                    }
+                    if (s2 == RT_OK) s2 = ali_stats(b.p, &b.opts, b.nonfinite, 0.0, &sts, st, &r);
                     std::lock_guard<std::mutex> lk(mu);
                     finish(b.tag, s2 != RT_OK ? s2 : r, sts);
                 }
@@ -2187,11 +2458,7 @@ struct rt_server {
         {
             // anything still queued after a failure ends with that failure
             std::lock_guard<std::mutex> lk(mu);
-            for (uint64_t t : queue) {
-                Request &q = reqs[t];
-                q.done = true;
-                q.result = RT_E_HIP;
-            }
+            for (uint64_t t : queue) abandon(t, RT_E_HIP);
             queue.clear();
         }
         if (st) (void)hipStreamDestroy(st);
@@ -2205,43 +2472,61 @@ struct rt_server {
 
 extern "C" {
 
-rt_status rt_server_create(size_t hbm_budget, int32_t check_every, rt_server **out)
+rt_status rt_server_create(rt_context *ctx, size_t hbm_budget, int32_t check_every, rt_server **out)
 {
+    CallScope scope(ctx, ctx ? ctx->device : -1);
     if (!out) return fail(RT_E_INVALID, "out is NULL");
     *out = nullptr;
     if (check_every < 0) return fail(RT_E_INVALID, "check_every must be >= 0");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
     rt_server *srv = new rt_server();
+    srv->ctx = ctx;
+    srv->device = dev;
     srv->budget = hbm_budget;
     srv->every = check_every > 0 ? check_every : 16;
-    HIP_TRY(hipGetDevice(&srv->device));
     srv->worker = std::thread([srv] { srv->run(); });
     *out = srv;
     return RT_OK;
 }
 
-rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opts, double *S_inout, double *J_out,
-                           uint64_t *ticket)
+rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opts, void *S_inout, void *J_out,
+                           void *stream, uint64_t *ticket)
 {
-    if (!srv || !p || !opts || !S_inout || !J_out || !ticket)
+    if (!srv) return fail(RT_E_INVALID, "server is NULL");
+    CallScope scope(srv->ctx, srv->device);
+    if (!p || !opts || !S_inout || !J_out || !ticket)
         return fail(RT_E_INVALID, "server, problem, opts, S_inout, J_out and ticket are required");
     if (!p->have_fields) return fail(RT_E_INVALID, "rt_problem_set_fields has not been called");
+    if (p->device != srv->device)
+        return fail(RT_E_INVALID, "the problem lives on device %d, the server on %d", p->device, srv->device);
     {
         rt_status so = check_ali_opts(opts);
         if (so != RT_OK) return so;
     }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) return fail(RT_E_INVALID, "server is shutting down");
+        if (srv->dead) return fail(RT_E_HIP, "server worker stopped after a device failure");
+        for (const auto &kv : srv->reqs)
+            if (!kv.second.done && kv.second.item.p == p) return fail(RT_E_INVALID, "problem already has a pending request");
+    }
     rt_server::Request q;
     q.item.p = p;
-    q.item.S = S_inout;
-    q.item.J = J_out;
+    q.item.S = p->usr32 ? p->stS : static_cast<double *>(S_inout);
+    q.item.J = p->usr32 ? p->stJ : static_cast<double *>(J_out);
+    q.S_usr = S_inout;
+    q.J_usr = J_out;
     q.item.opts = *opts;
     q.item.total = opts->fixed_iters > 0 ? opts->fixed_iters : opts->max_iter;
     q.bytes = state_bytes(&p->desc, p->na);
+    HIP_TRY(hipEventCreateWithFlags(&q.ready, hipEventDisableTiming));
+    if (hipEventRecord(q.ready, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipEventDestroy(q.ready);
+        return fail(RT_E_HIP, "hipEventRecord on the caller's stream failed");
+    }
     q.t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (srv->stop) return fail(RT_E_INVALID, "server is shutting down");
-    if (srv->dead) return fail(RT_E_HIP, "server worker stopped after a device failure");
-    for (const auto &kv : srv->reqs)
-        if (!kv.second.done && kv.second.item.p == p) return fail(RT_E_INVALID, "problem already has a pending request");
     const uint64_t t = srv->next_ticket++;
     q.item.tag = t;
     srv->reqs[t] = q;
@@ -2254,6 +2539,7 @@ rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opt
 rt_status rt_server_poll(rt_server *srv, uint64_t ticket, rt_ali_stats *stats, rt_status *result)
 {
     if (!srv) return fail(RT_E_INVALID, "server is NULL");
+    CallScope scope(srv->ctx, -1);
     std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->reqs.find(ticket);
     if (it == srv->reqs.end()) return fail(RT_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
@@ -2266,6 +2552,7 @@ rt_status rt_server_poll(rt_server *srv, uint64_t ticket, rt_ali_stats *stats, r
 rt_status rt_server_release(rt_server *srv, uint64_t ticket)
 {
     if (!srv) return fail(RT_E_INVALID, "server is NULL");
+    CallScope scope(srv->ctx, -1);
     std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->reqs.find(ticket);
     if (it == srv->reqs.end()) return fail(RT_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
@@ -2274,12 +2561,13 @@ rt_status rt_server_release(rt_server *srv, uint64_t ticket)
     return RT_OK;
 }
 
-rt_status rt_server_load(rt_server *srv, int32_t *queued, int32_t *running)
+rt_status rt_server_load(rt_server *srv, int32_t *queued, int32_t *running, size_t *running_bytes)
 {
     if (!srv) return fail(RT_E_INVALID, "server is NULL");
     std::lock_guard<std::mutex> lk(srv->mu);
     if (queued) *queued = (int32_t)srv->queue.size();
     if (running) *running = srv->running;
+    if (running_bytes) *running_bytes = srv->running_bytes;
     return RT_OK;
 }
 

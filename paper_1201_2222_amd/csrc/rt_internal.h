@@ -274,6 +274,7 @@ hipError_t launch_moments_integrate(const double *tmp, const double *Qt, const d
 hipError_t launch_eddington(const double *J_int, const double *K_int, int64_t cells, double *f_int, hipStream_t st);
 hipError_t launch_sum(const double *x, int64_t n, double scale, double *partial, int nblk, double *out, hipStream_t st);
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t st);
+hipError_t launch_convert_f64(const float *src, double *dst, int64_t n, hipStream_t st);
 hipError_t launch_warm_start(const double *B, const double *eps, const double *J, double *S, int64_t n,
                              hipStream_t st);
 

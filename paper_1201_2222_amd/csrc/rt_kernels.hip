@@ -1173,6 +1173,13 @@ __global__ void convert_f32_kernel(const double *src, float *dst, int64_t n)
     if (i < n) dst[i] = (float)src[i];
 }
 
+// caller arrays given in FP32 (rt_problem_desc::in_dtype) widened to the library's FP64
+__global__ void convert_f64_kernel(const float *src, double *dst, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (double)src[i];
+}
+
 __global__ void warm_start_kernel(const double *B, const double *eps, const double *J, double *S, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1605,6 +1612,12 @@ hipError_t launch_sum(const double *x, int64_t n, double scale, double *partial,
 hipError_t launch_convert_f32(const double *src, float *dst, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(convert_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f64(const float *src, double *dst, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(convert_f64_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 

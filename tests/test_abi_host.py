@@ -77,7 +77,7 @@ def test_invalid_arguments_are_rejected(rt):
         d = rt.make_desc(**kw)
         st = lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b))
         assert st == rt.RT_E_INVALID, kw
-        assert len(lib.rt_last_error()) > 0
+        assert len(lib.rt_last_error(None)) > 0
     # a ray table whose octants are unequal
     mu, w = rt.rt_quadrature(4)
     mu2 = mu.copy()
@@ -131,22 +131,22 @@ def test_batch_and_server_argument_errors(rt):
     lib = rt.load()
     o = rt.AliOpts(1e-6, 100, 0, 1, 0, 0)
     # empty or NULL batches
-    assert lib.rt_ali_solve_batch(None, 0, ctypes.byref(o), None, None, None, None, None) == rt.RT_E_INVALID
+    assert lib.rt_ali_solve_batch(None, None, 0, ctypes.byref(o), None, None, None, None, None) == rt.RT_E_INVALID
     probs = (ctypes.c_void_p * 1)(None)
     ptrs = (ctypes.c_void_p * 1)(None)
-    assert lib.rt_ali_solve_batch(probs, 1, ctypes.byref(o), ptrs, ptrs, None, None, None) == rt.RT_E_INVALID
+    assert lib.rt_ali_solve_batch(None, probs, 1, ctypes.byref(o), ptrs, ptrs, None, None, None) == rt.RT_E_INVALID
     bad = rt.AliOpts(1e-6, 0, 0, 1, 0, 0)    # max_iter 0 without fixed_iters
-    assert lib.rt_ali_solve_batch(probs, 0, ctypes.byref(bad), ptrs, ptrs, None, None, None) == rt.RT_E_INVALID
+    assert lib.rt_ali_solve_batch(None, probs, 0, ctypes.byref(bad), ptrs, ptrs, None, None, None) == rt.RT_E_INVALID
     # server calls on a NULL server
     st = rt.AliStats()
     res = ctypes.c_int()
     assert lib.rt_server_poll(None, ctypes.c_uint64(1), ctypes.byref(st), ctypes.byref(res)) == rt.RT_E_INVALID
     assert lib.rt_server_release(None, ctypes.c_uint64(1)) == rt.RT_E_INVALID
-    assert lib.rt_server_load(None, None, None) == rt.RT_E_INVALID
+    assert lib.rt_server_load(None, None, None, None) == rt.RT_E_INVALID
     assert lib.rt_server_destroy(None) == rt.RT_OK
     t = ctypes.c_uint64()
-    assert lib.rt_server_submit(None, None, ctypes.byref(o), None, None, ctypes.byref(t)) == rt.RT_E_INVALID
-    assert lib.rt_server_create(0, -1, ctypes.byref(ctypes.c_void_p())) == rt.RT_E_INVALID
+    assert lib.rt_server_submit(None, None, ctypes.byref(o), None, None, None, ctypes.byref(t)) == rt.RT_E_INVALID
+    assert lib.rt_server_create(None, 0, -1, ctypes.byref(ctypes.c_void_p())) == rt.RT_E_INVALID
     assert lib.rt_status_string(rt.RT_E_BUSY) == b"busy"
 
 
@@ -166,3 +166,61 @@ def test_checkpoint_argument_errors(rt):
     assert lib.rt_problem_state_bytes(None, ctypes.byref(b)) == rt.RT_E_INVALID
     assert lib.rt_problem_save_state(None, buf, 64, None) == rt.RT_E_INVALID
     assert lib.rt_problem_load_state(None, buf, 64, None) == rt.RT_E_INVALID
+
+
+def test_context_and_in_dtype_validation(rt):
+    """A context names an existing device (none here: refused, message kept per thread);
+    in_dtype is validated with the description and FP32 caller arrays add the FP64
+    copies of S and J to the state size."""
+    lib = rt.load()
+    ctx = ctypes.c_void_p()
+    assert lib.rt_context_create(-1, ctypes.byref(ctx)) == rt.RT_E_INVALID
+    assert b"device" in lib.rt_last_error(None)
+    assert lib.rt_context_create(0, None) == rt.RT_E_INVALID
+    assert lib.rt_context_destroy(None) == rt.RT_OK
+    b = ctypes.c_size_t()
+    d = rt.make_desc((8, 8, 8), in_dtype=2)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID
+    f64 = rt.rt_problem_bytes(rt.make_desc((8, 8, 8), nf=2))
+    f32 = rt.rt_problem_bytes(rt.make_desc((8, 8, 8), nf=2, in_dtype=rt.RT_DTYPE_F32))
+    assert f32 - f64 == 2 * 8 * 8 * 8 * 2 * 8
+
+
+def test_marshalling_refuses_wrong_sizes_and_types(rt):
+    """The binding checks every array against the problem's shape and element type
+    before the library sees it: a short or long buffer, the wrong dtype, or a
+    non-contiguous view is refused with an exception (here with host tensors and a
+    shape registered for a stand-in handle, so no device is needed; the arguments are
+    checked in order, so each case puts the faulty one first)."""
+    import torch
+    h = 0x1234567
+    rt._SHAPES[h] = (4 * 3 * 2, 2, rt.RT_DTYPE_F64, 24)   # cells, nf, in_dtype, rays
+    nc = 4 * 3 * 2 * 2
+    try:
+        ok = torch.zeros(nc, dtype=torch.float64)
+        with pytest.raises(ValueError):
+            rt.rt_formal_solve(h, torch.zeros(nc - 1, dtype=torch.float64), ok)
+        with pytest.raises(ValueError):
+            rt.rt_ali_solve(h, torch.zeros(nc + 1, dtype=torch.float64), ok)
+        with pytest.raises(ValueError):
+            rt.rt_moments(h, ok, H=torch.zeros(nc, dtype=torch.float64))         # H needs 3 nf cells
+        with pytest.raises(ValueError):
+            rt.rt_moments(h, ok, K_int=torch.zeros(3 * 24, dtype=torch.float64))  # K_int needs 6 cells
+        with pytest.raises(ValueError):
+            rt.rt_problem_set_fields(h, torch.zeros(2 * nc, dtype=torch.float64), ok, ok)
+        with pytest.raises(TypeError):
+            rt.rt_formal_solve(h, torch.zeros(nc, dtype=torch.float32), ok)       # FP64 problem
+        with pytest.raises(TypeError):
+            rt.rt_formal_solve(h, torch.zeros(2 * nc, dtype=torch.float64)[::2], ok)
+        with pytest.raises(TypeError):
+            rt.rt_formal_solve(h, ok, ok)                                           # right size, host memory
+        rt._SHAPES[h] = (4 * 3 * 2, 2, rt.RT_DTYPE_F32, 24)
+        with pytest.raises(TypeError):
+            rt.rt_formal_solve(h, ok, ok)                                           # FP32 problem
+        with pytest.raises(ValueError):
+            rt.rt_formal_solve(h, torch.zeros(nc + 2, dtype=torch.float32), torch.zeros(nc, dtype=torch.float32))
+        with pytest.raises(ValueError):
+            rt.make_desc((4, 3, 2), nf=2, bc_lo=(3, 2, 1), bc_hi=(0, 2, 0),
+                         I_fixed=[torch.zeros(5, dtype=torch.float64)] + [None] * 5)
+    finally:
+        rt._SHAPES.pop(h, None)

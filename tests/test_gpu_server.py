@@ -59,8 +59,23 @@ def test_server_queue_matches_single(env):
     budget = max(rt.rt_problem_bytes(p.desc) for p, _, _ in probs) * 2   # at most ~two at a time
     srv = rt.rt_server_create(budget, check_every=8)
     tickets = [rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=3000) for p, S, J in probs]
-    q, r = rt.rt_server_load(srv)
-    assert q + r <= len(tickets)
+    # admission by HBM footprint: while more than one request runs, the summed
+    # rt_problem_bytes of the running ones stays within the budget
+    sizes = sorted(rt.rt_problem_bytes(p.desc) for p, _, _ in probs)
+    seen_running, t0 = 0, time.time()
+    while True:
+        q, r, b = rt.rt_server_load(srv, with_bytes=True)
+        assert q + r <= len(tickets)
+        if r > 1:
+            assert b <= budget, (r, b, budget)
+        if r == 1:
+            assert b in sizes
+        seen_running = max(seen_running, r)
+        if q == 0 and r == 0:
+            break
+        assert time.time() - t0 < 120.0, "server requests did not finish"
+        time.sleep(0.0005)
+    assert seen_running >= 1
     res = _wait(rt, srv, tickets)
     for (p, S, J), t, spec, k in zip(probs, tickets, SPECS, range(len(SPECS))):
         status, st = res[t]
