@@ -445,6 +445,29 @@ typedef struct {
 rt_status rt_problem_profile(rt_problem *p, int32_t enable);
 rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out);
 
+/*
+ * rt_formal_solve_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * formal solution of rt_formal_solve on a newly created problem with these fields
+ * (periodic ghosts cold: S of the wrapped vertex), computed with the same kernels and
+ * launch shape, so J and lambda_star are bitwise those of rt_problem_create +
+ * rt_problem_set_fields + rt_formal_solve.  It allocates nothing: its internal
+ * state lives in a library-owned device array of 64 MiB per GPU, held until the
+ * process ends, and the ray table and tile list are built on the device from kernel
+ * arguments.  desc: as for rt_problem_create, with in_dtype RT_DTYPE_F64, the
+ * bilinear upwind intensity and at most 80 rays (n_mu <= 8); chi, B: device FP64
+ * [nf][cells] (B for thermal boundaries); S (read), J (written), lambda_star (written
+ * or NULL): device FP64 [nf][cells]; I_fixed as in the description.  Problems whose
+ * workspace exceeds the 64 MiB (about 64^3 x 48 rays x 1 bin in FP32) return
+ * RT_E_UNSUPPORTED, other bad arguments RT_E_INVALID, before any device work.
+ * Asynchronous on the stream, on the current device.  Every call on a GPU shares its
+ * array and keeps the last call's contents: calls that overlap on one GPU (other
+ * streams or host threads before the previous one finished) race, and must be
+ * serialised by the caller.
+ */
+rt_status rt_formal_solve_noalloc(const rt_problem_desc *desc, const void *chi, const void *B, const void *S,
+                                  void *J, void *lambda_star, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -32,7 +32,7 @@ EXPORTS = ("rt_status_string", "rt_last_error", "rt_context_create", "rt_context
            "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_problem_set_waves",
            "rt_problem_tune", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
            "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
-           "rt_server_load", "rt_server_destroy")
+           "rt_server_load", "rt_server_destroy", "rt_formal_solve_noalloc")
 
 
 class RtError(RuntimeError):
@@ -118,6 +118,7 @@ def load():
     lib.rt_server_release.argtypes = [P, ctypes.c_uint64]
     lib.rt_server_load.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_size_t)]
     lib.rt_server_destroy.argtypes = [P]
+    lib.rt_formal_solve_noalloc.argtypes = [ctypes.POINTER(ProblemDesc), P, P, P, P, P, P]
     for name in EXPORTS:
         getattr(lib, name).restype = getattr(lib, name).restype or ctypes.c_int
     _lib = lib
@@ -412,6 +413,15 @@ def rt_server_load(srv, with_bytes=False):
     q, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
     _check(load().rt_server_load(srv, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)))
     return (q.value, r.value, b.value) if with_bytes else (q.value, r.value)
+
+
+def rt_formal_solve_noalloc(desc, chi, B, S, J, lambda_star=None, stream=None):
+    """One formal solution with the library's fixed workspace (no device allocation):
+    desc as for a problem, chi, B, S, J (and lambda_star) device FP64 [nf][cells]."""
+    nc = int(desc.nx) * int(desc.ny) * int(desc.nz) * int(desc.nf)
+    return _check(load().rt_formal_solve_noalloc(ctypes.byref(desc), _dptr(chi, nc, "chi"), _dptr(B, nc, "B"),
+                                                 _dptr(S, nc, "S"), _dptr(J, nc, "J"),
+                                                 _dptr(lambda_star, nc, "lambda_star"), _stream(stream)))
 
 
 def rt_server_destroy(srv):

@@ -16,7 +16,7 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function", "-pthread"]
 
-SOURCES = ["rt_kernels.hip", "rt_plane.hip", "rt_gs.hip", "rt_api.cpp"]
+SOURCES = ["rt_kernels.hip", "rt_plane.hip", "rt_gs.hip", "rt_noalloc.hip", "rt_api.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -1079,6 +1079,14 @@ rt_status ali_stats(rt_problem *p, const rt_ali_opts *opts, bool nonfinite, doub
 
 }  // namespace
 
+namespace rtsc {
+
+// for the no-allocation formal solution (rt_noalloc.hip)
+rt_status validate_desc(const rt_problem_desc *d, int *na_out) { return validate(d, na_out); }
+void record_error(const char *msg) { (void)fail(RT_OK, "%s", msg); }
+
+}  // namespace rtsc
+
 extern "C" {
 
 const char *rt_status_string(rt_status s)
