@@ -81,11 +81,13 @@ typedef enum { RT_DTYPE_F64 = 0, RT_DTYPE_F32 = 1 } rt_dtype;
  * at the opposite face (PERIODIC; both faces of the axis must be periodic). */
 typedef enum { RT_BC_VACUUM = 0, RT_BC_THERMAL = 1, RT_BC_PERIODIC = 2, RT_BC_FIXED = 3 } rt_bc_kind;
 
-/* Execution of the tile wavefront of one formal solution.  RT_SCHED_STAGES: one
- * launch per tile hyperplane (the default).  RT_SCHED_PERSISTENT (one launch,
- * workgroups drawing tiles in hyperplane order and waiting on completion flags of
- * their upwind neighbours) is disabled in this library: rt_problem_create returns
- * RT_E_UNSUPPORTED for it. */
+/* Execution of the tile wavefront of one formal solution (section 3.1).
+ * RT_SCHED_STAGES: one launch per tile hyperplane (the default).
+ * RT_SCHED_PERSISTENT: one launch per formal solution; workgroups draw tiles in
+ * hyperplane order from a per-octant counter and wait on completion flags of their
+ * upwind neighbours (each wait bounded in time: a wait that runs out makes the call
+ * return RT_E_HIP).  Built for RT_SC_LINEAR with RT_INTERP_BILINEAR; other
+ * combinations get RT_E_UNSUPPORTED, and so does Gauss-Seidel with it. */
 typedef enum { RT_SCHED_DEFAULT = 0, RT_SCHED_STAGES = 1, RT_SCHED_PERSISTENT = 2 } rt_schedule;
 
 /* Order of the short-characteristic integration (section 3.3, eq. rtdisc).

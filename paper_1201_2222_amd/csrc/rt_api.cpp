@@ -397,15 +397,13 @@ rt_status validate(const rt_problem_desc *d, int *na_out)
     if (d->in_dtype != RT_DTYPE_F64 && d->in_dtype != RT_DTYPE_F32) return fail(RT_E_INVALID, "unknown in_dtype");
     if (d->tile != 0 && d->tile != kTile) return fail(RT_E_UNSUPPORTED, "tile edge %d not built (only %d)", d->tile, kTile);
     if (d->schedule < RT_SCHED_DEFAULT || d->schedule > RT_SCHED_PERSISTENT) return fail(RT_E_INVALID, "unknown schedule");
-    // The persistent schedule did not complete on the device in testing and its
-    // cause is not established; it is refused until it is.
-    if (d->schedule == RT_SCHED_PERSISTENT)
-        return fail(RT_E_UNSUPPORTED, "the persistent sweep schedule is disabled in this library");
     if (d->order != RT_SC_LINEAR && d->order != RT_SC_BEZIER) return fail(RT_E_INVALID, "unknown order");
     if (d->interp != RT_INTERP_BILINEAR && d->interp != RT_INTERP_QUADRATIC)
         return fail(RT_E_INVALID, "unknown upwind interpolation");
     if (d->interp == RT_INTERP_QUADRATIC && d->order != RT_SC_LINEAR)
         return fail(RT_E_UNSUPPORTED, "the quadratic upwind intensity is built with first-order segments only");
+    if (d->schedule == RT_SCHED_PERSISTENT && (d->order != RT_SC_LINEAR || d->interp != RT_INTERP_BILINEAR))
+        return fail(RT_E_UNSUPPORTED, "the persistent schedule is built for first-order segments with bilinear upwind values");
     for (int q = 0; q < 3; ++q) {
         for (int k : {d->bc_lo[q], d->bc_hi[q]})
             if (k < RT_BC_VACUUM || k > RT_BC_FIXED) return fail(RT_E_INVALID, "unknown boundary kind on axis %d", q);

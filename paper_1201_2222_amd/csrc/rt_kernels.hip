@@ -805,34 +805,54 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_batch_stage_kernel(const
 
 // Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
 // octant o: they draw tickets from that octant's counter; ticket t is tile
-// tiles[t % ntiles] of bin t / ntiles, so every tile's upwind neighbours carry
+// tiles[t % ntiles] of bin f0 + t / ntiles, so every tile's upwind neighbours carry
 // smaller tickets and are held by running (or finished) workgroups.  Completion
 // is published per tile with the sweep's epoch (agent-scope release).
+//
+// Every value that decides the loop's course (the ticket, the bin's frozen flag, the
+// tile, the parity) is taken into a scalar register.  Held in vector registers they
+// make the loop divergent as far as the compiler can tell, and it may then let the
+// lanes of one wave run different iterations: lanes 1..63 of wave 0 pass the
+// barriers of the next iteration (re-reading the old ticket) while lane 0 waits to
+// draw the new one, and the workgroup sweeps the same tile forever.  Thread 0
+// publishes the previous tile and draws the next ticket in one block at the top of
+// the loop, so no lane-divergent code sits between a tile's last barrier and the
+// next ticket's first.
 template <typename Real, bool DFORM>
 __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepArgs<Real> A, DagArgs D)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int s_ticket;
     const int oct = blockIdx.x & 7;
-    const int items = D.ntiles * A.nf;
+    const int items = D.ntiles * A.nfc;
+    int done_f = -1, done_tile = -1;   // the tile this workgroup finished last (uniform)
     for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(D.counter + oct, 1);
+        if (threadIdx.x == 0) {
+            if (done_tile >= 0)
+                __hip_atomic_store(D.done + ((int64_t)done_f * 8 + oct) * D.ntiles + done_tile, D.epoch,
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = atomicAdd(D.counter + oct, 1);
+        }
         __syncthreads();
-        const int t = s_ticket;
+        const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();
         if (t >= items) break;
-        const int f = t / D.ntiles;
-        const int tile = t - f * D.ntiles;
-        if (A.frozen[f]) continue;
-        const int packed = A.tiles[tile];
-        sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, A.parity[f], lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
-                                      D.nt1, D.err, D.wait_ticks);
+        const int fc = t / D.ntiles;
+        const int tile = t - fc * D.ntiles;
+        const int f = A.f0 + fc;
+        const int frozen = __builtin_amdgcn_readfirstlane(A.frozen[f]);
+        const int packed = __builtin_amdgcn_readfirstlane(A.tiles[tile]);
+        const int par = __builtin_amdgcn_readfirstlane(A.parity[f]);
+        done_tile = -1;
+        if (frozen | (packed < 0) | (par < 0)) continue;
+        sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, par, lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
+                                                  D.nt1, D.err, D.wait_ticks);
+        // every wave's stores of the tile reach the device scope before the barrier
+        // after which thread 0 publishes the tile
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const int tx = packed & 1023, ty = (packed >> 10) & 1023, tz = (packed >> 20) & 1023;
-            __hip_atomic_store(D.done + ((int64_t)f * 8 + oct) * D.ntiles + D.tile_id(tx, ty, tz), D.epoch,
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        done_f = f;
+        done_tile = D.tile_id(packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023);
     }
 }
 
@@ -1104,7 +1124,9 @@ __device__ __forceinline__ void ali_finalize_body(const AliCtl &ctl, int nf, dou
     }
     __syncthreads();
     for (int f = 0; f < nf; ++f) {
-        if (ctl.frozen[f]) continue;   // uniform across the block
+        // uniform across the block, and held in a scalar register so that the compiler
+        // keeps the loop (which has barriers) uniform too
+        if (__builtin_amdgcn_readfirstlane(ctl.frozen[f])) continue;
         unsigned long long m = 0ull;
         for (int k = threadIdx.x; k < ctl.nblk; k += blockDim.x) {
             const unsigned long long v = ctl.blockmax[(int64_t)f * ctl.nblk + k];

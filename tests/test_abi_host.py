@@ -116,10 +116,15 @@ def test_state_bytes_scale(rt):
     assert f32 < big
 
 
-def test_disabled_schedule_is_refused(rt):
+def test_schedule_validation(rt):
     lib = rt.load()
     b = ctypes.c_size_t()
     d = rt.make_desc((8, 8, 8), schedule=rt.RT_SCHED_PERSISTENT)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_OK
+    # the persistent kernel is built for first-order segments and bilinear upwind values
+    d = rt.make_desc((8, 8, 8), schedule=rt.RT_SCHED_PERSISTENT, order=rt.RT_SC_BEZIER)
+    assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_UNSUPPORTED
+    d = rt.make_desc((8, 8, 8), schedule=rt.RT_SCHED_PERSISTENT, interp=rt.RT_INTERP_QUADRATIC)
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_UNSUPPORTED
     d = rt.make_desc((8, 8, 8), schedule=7)
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID

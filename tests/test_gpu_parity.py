@@ -72,13 +72,6 @@ CASES = [
 
 
 SCHEDULES = {"stages": 1, "persistent": 2}
-PERSISTENT_SKIP = ("persistent sweep schedule disabled: its first device run did not complete and the cause "
-                   "is not established (the library refuses the schedule)")
-
-
-def _skip_disabled(schedule):
-    if schedule == "persistent":
-        pytest.skip(PERSISTENT_SKIP)
 
 
 @pytest.mark.parametrize("case", range(len(CASES)))
@@ -87,7 +80,6 @@ def _skip_disabled(schedule):
 def test_formal_solve_parity(env, oracle_mod, case, precision, schedule):
     """Two consecutive formal solutions (the second reads the first one's periodic
     memory) on random S; J and Lambda* against the oracle."""
-    _skip_disabled(schedule)
     rt, torch = env
     shape, n_mu, lo, hi, h, nf = CASES[case]
     wl = W.random_problem(shape, nf=nf, seed=100 + case, n_mu=n_mu, bc_lo=lo, bc_hi=hi, h=h)
@@ -114,7 +106,6 @@ def test_formal_solve_parity(env, oracle_mod, case, precision, schedule):
 @pytest.mark.parametrize("schedule", ["stages", "persistent"])
 def test_ali_fixed_iterations_parity(env, oracle_mod, precision, schedule):
     """Three Jacobi iterations from S = B on a multi-bin random problem."""
-    _skip_disabled(schedule)
     rt, torch = env
     wl = W.random_problem((17, 10, 12), nf=3, seed=11, n_mu=4, eps_range=(1e-3, 1.0))
     prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
@@ -138,7 +129,6 @@ def test_ali_converged_parity(env, oracle_mod, precision, schedule):
     """Scattering atmosphere (the 128^3 workload's structure at 24^3, two bins with
     different eps): Jacobi ALI to max|dS/S| <= 1e-6 with per-bin stopping.  FP64 must
     take the same iteration counts and agree to 1e-12; FP32 must agree to 2e-5."""
-    _skip_disabled(schedule)
     rt, torch = env
     base = W.scattering(24, eps=1e-2, tau_bottom=1e3)
     wl2 = W.scattering(24, seed=77, eps=1e-1, tau_bottom=1e3)
@@ -188,7 +178,6 @@ def test_workload_plain_full_size(env, oracle_mod):
 def test_workload_scattering_full_size(env, oracle_mod, precision, schedule):
     """The 128^3 scattering workload at full size, in the launch configurations the
     benchmark times: two Jacobi iterations from S = B against the oracle."""
-    _skip_disabled(schedule)
     rt, torch = env
     wl = W.scattering()
     prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
