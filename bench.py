@@ -107,6 +107,16 @@ def _chain_kernel_name(shape):
     return f"gs_chain_kernel<float, true, {m}, true, true, {'true' if full else 'false'}>"
 
 
+def _schedule(args, rt):
+    return rt.RT_SCHED_PERSISTENT if args.schedule == "persistent" else rt.RT_SCHED_STAGES
+
+
+def _sweep_kernel_name(args, order):
+    if args.schedule == "persistent":
+        return "sweep_persistent_kernel<float, true>"
+    return f"sweep_stage_kernel<float, true, 1, false, {order}, 8>"
+
+
 def _pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -321,7 +331,8 @@ def bench_multifreq(args, rt, W, torch, np):
     shape, n_mu, bc_lo, bc_hi = wl.shape, wl.n_mu, wl.bc_lo, wl.bc_hi
     na = n_mu * (n_mu + 2)
     del wl
-    prob = rt.Problem(shape, nf=nfb, n_mu=n_mu, bc_lo=bc_lo, bc_hi=bc_hi, w_nu=w_nu, precision=rt.RT_F32)
+    prob = rt.Problem(shape, nf=nfb, n_mu=n_mu, bc_lo=bc_lo, bc_hi=bc_hi, w_nu=w_nu, precision=rt.RT_F32,
+                      schedule=_schedule(args, rt))
     desc_bytes = rt.rt_problem_bytes(prob.desc)
     prob.set_fields(chi, eps, B)
     torch.cuda.synchronize()
@@ -333,21 +344,23 @@ def bench_multifreq(args, rt, W, torch, np):
           f"{(total_mem - free) / 1e9:.1f} GB of device memory in use", file=sys.stderr, flush=True)
 
     K, Wm = args.steps, args.warmup
+    gs = args.ali == "gauss-seidel"
+    solve = prob.ali_solve_gs if gs else prob.ali_solve
     if Wm > 0:
-        prob.ali_solve(S, J, fixed_iters=Wm, check_every=Wm)
+        solve(S, J, fixed_iters=Wm, check_every=Wm)
     torch.cuda.synchronize()
     print(f"multifreq: {Wm} warm-up iterations done", file=sys.stderr, flush=True)
     # timed: K Jacobi iterations of all bins (the production path: graph-replayed chunk)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    status, st = prob.ali_solve(S, J, fixed_iters=K, check_every=K)
+    status, st = solve(S, J, fixed_iters=K, check_every=K)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"multifreq: {K} timed iterations in {dt:.3f} s", file=sys.stderr, flush=True)
     updates = float(cells) * na * nfb * K
     # one more iteration with the sweep kernel's launches timed by events
     rt.rt_problem_profile(prob.handle, True)
-    prob.ali_solve(S, J, fixed_iters=1, check_every=1)
+    solve(S, J, fixed_iters=1, check_every=1)
     torch.cuda.synchronize()
     prof = rt.rt_problem_profile_read(prob.handle)
     rt.rt_problem_profile(prob.handle, False)
@@ -356,19 +369,32 @@ def bench_multifreq(args, rt, W, torch, np):
     achieved = sweep_rate * OPS_PER_UPDATE_F32 / 1e12
     launches = max(prof["launches"], 1)
     # the committed byte counters were taken on the full 192^3 x 64-bin workload
-    traffic = measured_traffic("multifreq") if (n == 192 and nfb == 64) else None
+    traffic = measured_traffic("multifreq") if (n == 192 and nfb == 64 and args.schedule == "stages") else None
     avg_us = prof["kernel_ms"] * 1e3 / launches
     hbm_alg = sweep_rate * BYTES_PER_UPDATE_SWEEP_F32_80 / 1e9
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "sweep_stage_kernel<float, true, 1, false, 0, 8>",
+                "kernel": _sweep_kernel_name(args, 0),
                 "avg_launch_us": avg_us, "timed_launches": prof["launches"],
                 "ops_per_update": OPS_PER_UPDATE_F32, "sweep_updates_per_s": sweep_rate,
                 "hbm": {"achieved": hbm_alg, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_alg / HBM_PEAK_GBS,
                         "bytes_per_update": BYTES_PER_UPDATE_SWEEP_F32_80,
                         "measured_gbs": (traffic / (avg_us * 1e-6) / 1e9) if traffic else None,
                         "measured_frac": (traffic / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
+    if gs:
+        # the dominant kernel of Gauss-Seidel is the chain kernel of the downward pass
+        chain_s = prof["chain_ms"] / 1e3
+        ach = prof["chain_updates"] * BYTES_PER_CHAIN_UPDATE_F32 / chain_s / 1e9 if chain_s > 0 else 0.0
+        roofline = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                    "kernel": _chain_kernel_name(shape),
+                    "avg_launch_us": prof["chain_ms"] * 1e3 / max(prof["chain_launches"], 1),
+                    "timed_launches": prof["chain_launches"],
+                    "bytes_per_update": BYTES_PER_CHAIN_UPDATE_F32,
+                    "upward_sweep": {"kernel": _sweep_kernel_name(args, 0), "avg_launch_us": avg_us,
+                                     "updates_per_s": sweep_rate}}
     out = {
         "metric": METRIC, "value": updates / dt, "unit": "updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -376,8 +402,10 @@ def bench_multifreq(args, rt, W, torch, np):
         "config": {"workload": f"multifreq {n}^3 x {nfb} bins x {na} rays (x_nu log-spaced in [0.05, 50], free-free "
                                f"chi_abs ~ x^-3 rho with rho lognormal(0.8), grey scattering tau 10, Planck B_nu "
                                f"with T lognormal(0.3)); a step is one Jacobi ALI iteration over all bins, "
-                               f"FP32 sweeps + FP64 updates and residuals",
-                   "grid": list(shape), "bins": nfb, "rays": na, "device_bytes_library": desc_bytes},
+                               f"FP32 sweeps + FP64 updates and residuals"
+                               f"{'; Gauss-Seidel ALI (plane-block order)' if gs else ''}",
+                   "grid": list(shape), "bins": nfb, "rays": na, "schedule": args.schedule, "ali": args.ali,
+                   "device_bytes_library": desc_bytes},
         "roofline": roofline,
     }
     if args.mf_converge:
@@ -389,8 +417,8 @@ def bench_multifreq(args, rt, W, torch, np):
         it_total = np.zeros(nfb, dtype=np.int64)
         status = rt.RT_NOT_CONVERGED
         while status != rt.RT_OK and it_total.max() < args.max_iter:
-            status, st = prob.ali_solve(S, J, delta_c=1e-6, max_iter=100, per_bin_stop=True,
-                                        warm_start=1 if it_total.max() > 0 else 0)
+            status, st = solve(S, J, delta_c=1e-6, max_iter=100, per_bin_stop=True,
+                               warm_start=1 if it_total.max() > 0 else 0)
             it_bins, res = rt.rt_ali_bin_stats(prob.handle, nfb)
             it_total += it_bins
             print(f"multifreq: converging, {int(it_total.max())} iterations, max residual {float(res.max()):.2e} "
@@ -406,102 +434,212 @@ def bench_multifreq(args, rt, W, torch, np):
     return out
 
 
+class _ServingRun:
+    """One serving run: requests arrive at given times, are created on the device (a
+    new problem with its own fields, or the next snapshot of a drifting stream) and
+    submitted to the server as long as the summed rt_problem_bytes of the requests in
+    flight stays within the budget (oldest first; a stream's snapshot waits for its
+    previous one), and their latency runs from arrival to completion."""
+
+    def __init__(self, rt, W, torch, np, srv, budget, streams, max_iter, label, max_n=160):
+        self.max_n = max_n
+        self.rt, self.W, self.torch, self.np = rt, W, torch, np
+        self.srv, self.budget, self.streams, self.max_iter, self.label = srv, budget, streams, max_iter, label
+        self.inflight = {}        # ticket -> record
+        self.bytes = 0
+        self.done = []
+
+    def _make(self, kind, key):
+        rt, torch = self.rt, self.torch
+        if kind == "stream":
+            st = self.streams[key]
+            if st["busy"]:
+                return None
+            if st["problem"] is None:
+                req = self.W.serving_request(10_000 + key, n=st["n"], nf=st["nf"])
+                p = rt.Problem(req["shape"], nf=req["nf"], n_mu=req["n_mu"], w_nu=req["w_nu"], precision=rt.RT_F32)
+                p.set_fields(req["chi"], req["eps"], req["B"])
+                st.update(problem=p, req=req, S=torch.empty_like(req["B"]), J=torch.empty_like(req["B"]),
+                          bytes=rt.rt_problem_bytes(p.desc) + 2 * req["B"].numel() * 8, step=0, warm=0)
+            else:
+                st["step"] += 1
+                B = self.W.serving_drift(st["req"], st["step"])
+                st["problem"].set_fields(st["req"]["chi"], st["req"]["eps"], B)
+                st["warm"] = 2     # S = eps B + (1 - eps) J of the previous snapshot, on the device
+            st["busy"] = True
+            return st["problem"], st["S"], st["J"], st["bytes"], st["warm"], False
+        req = self.W.serving_request(key, max_n=self.max_n)
+        desc = rt.make_desc(req["shape"], nf=req["nf"], n_mu=req["n_mu"], w_nu=req["w_nu"], precision=rt.RT_F32)
+        nbytes = rt.rt_problem_bytes(desc) + 2 * req["B"].numel() * 8    # with the caller's S and J
+        if self.inflight and self.bytes + nbytes > self.budget:
+            return "full"
+        p = rt.Problem(req["shape"], nf=req["nf"], n_mu=req["n_mu"], w_nu=req["w_nu"], precision=rt.RT_F32)
+        p.set_fields(req["chi"], req["eps"], req["B"])
+        S, J = torch.empty_like(req["B"]), torch.empty_like(req["B"])
+        del req
+        return p, S, J, nbytes, 0, True
+
+    def run(self, arrivals, kinds, t_admit_end=None, drain=True):
+        """arrivals: seconds from the start; kinds: ("fresh", index) or ("stream", s).
+        Requests not admitted by t_admit_end (None: never stop) stay unserved."""
+        import time
+        rt = self.rt
+        pending, nxt, t0 = [], 0, time.perf_counter()
+        unserved = 0
+        while True:
+            now = time.perf_counter() - t0
+            while nxt < len(arrivals) and arrivals[nxt] <= now:
+                pending.append((arrivals[nxt], kinds[nxt]))
+                nxt += 1
+            admitting = t_admit_end is None or now <= t_admit_end
+            i = 0
+            while admitting and i < len(pending):
+                arr, (kind, key) = pending[i]
+                if kind == "stream" and self.streams[key]["problem"] is not None and \
+                        self.streams[key]["bytes"] + self.bytes > self.budget and self.inflight:
+                    break
+                made = self._make(kind, key)
+                if made == "full":
+                    break                      # oldest fresh request first
+                if made is None:
+                    i += 1                     # its stream is busy: later requests may go
+                    continue
+                p, S, J, nbytes, warm, fresh = made
+                t = rt.rt_server_submit(self.srv, p.handle, S, J, delta_c=1e-6, max_iter=self.max_iter,
+                                        warm_start=warm)
+                self.inflight[t] = {"arr": arr, "p": p, "S": S, "J": J, "bytes": nbytes, "fresh": fresh,
+                                    "kind": kind, "key": key, "cells": p.cells, "nf": p.nf}
+                self.bytes += nbytes
+                pending.pop(i)
+            for t in list(self.inflight):
+                r = rt.rt_server_poll(self.srv, t)
+                if r is None:
+                    continue
+                rec = self.inflight.pop(t)
+                now = time.perf_counter() - t0
+                rt.rt_server_release(self.srv, t)
+                it_bins, _ = rt.rt_ali_bin_stats(rec["p"].handle, rec["nf"])
+                self.bytes -= rec["bytes"]
+                if rec["fresh"]:
+                    rec["p"].close()
+                else:
+                    self.streams[rec["key"]]["busy"] = False
+                self.done.append({"latency": now - rec["arr"], "iterations": r[1]["iterations"], "status": r[0],
+                                  "kind": rec["kind"], "updates": float(rec["cells"]) * 48 * float(self.np.sum(it_bins)),
+                                  "t_done": now})
+                print(f"{self.label}: {len(self.done)} done ({rec['kind']}), latency {self.done[-1]['latency']:.2f} s, "
+                      f"{r[1]['iterations']} iterations, {len(self.inflight)} in flight, {len(pending)} waiting",
+                      file=sys.stderr, flush=True)
+            if nxt >= len(arrivals) and not self.inflight and (not pending or not admitting):
+                unserved = len(pending)
+                break
+            if not admitting and not self.inflight:
+                unserved = len(pending) + (len(arrivals) - nxt)
+                break
+            time.sleep(0.0005)
+        span = time.perf_counter() - t0
+        return span, unserved
+
+
 def bench_serving(args, rt, W, torch, np):
-    """Serving loop: a pool of request problems (some of them drifting snapshot streams
-    that are warm-started) behind one server; capacity at saturation, then Poisson
-    arrivals at fractions of it and at the overload rate, latency from arrival to
-    completion (queueing included)."""
+    """Serving loop at the workload's stated size: every request a new problem (cubic N
+    log-uniform in 32..160, 8..32 bins, 48 rays, eps 10^U[-4,0]) generated on the device,
+    30% of them successive snapshots of 16 drifting streams warm-started from their
+    device-resident S and J; admission by HBM footprint.  First the capacity (a
+    saturated window), then Poisson arrivals at 0.25, 0.5 and 0.9 of it and at 200
+    requests/s over 30 s windows; latency from arrival to completion, queueing
+    included.  At 200 requests/s the GPU is overloaded: requests still waiting when the
+    window closes are reported as unserved (their latency exceeds the window)."""
     rng = np.random.default_rng(2005)
-    pool, streams = [], []
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    for k in range(args.pool):
-        wl = W.serving_problem(k)
-        p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
-                       precision=rt.RT_F32)
-        p.set_fields(dev(wl.chi), dev(wl.eps), dev(wl.B))
-        S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
-        J = torch.empty_like(S)
-        entry = {"p": p, "S": S, "J": J, "nf": wl.nf, "busy": False, "stream": k < args.streams, "step": 0,
-                 "T": wl.meta["T"] if k < args.streams else None, "wl": wl if k < args.streams else None,
-                 "cells": wl.cells, "na": wl.na}
-        pool.append(entry)
-        print(f"serving: pool problem {k} ({wl.shape[0]}^3, {wl.nf} bins) set up", file=sys.stderr, flush=True)
-        if k >= args.streams:
-            del wl
     torch.cuda.synchronize()
     free, _ = torch.cuda.mem_get_info()
-    srv = rt.rt_server_create(int(0.8 * free), check_every=16)
+    # the library's state and the callers' S and J of the admitted requests; the rest
+    # of the memory is left to request generation
+    budget = int(0.6 * free)
+    srv = rt.rt_server_create(budget, check_every=16)
+    runs = []
+    srng = np.random.default_rng(3005)
+    streams = [{"n": int(round(np.exp(srng.uniform(np.log(32), np.log(args.serve_max_n))))),
+                "nf": int(srng.integers(8, 33)),
+                "problem": None, "busy": False} for _ in range(args.streams)]
+    try:
+        counter = [0]
 
-    def submit(e, warm):
-        if e["stream"] and warm:
-            e["step"] += 1
-            T = W.drift(e["T"], e["step"])
-            e["T"] = T
-            wl = e["wl"]
-            x = np.logspace(np.log10(0.05), np.log10(50.0), wl.nf)
-            B = np.stack([x[b] ** 3 / np.expm1(x[b] / T) for b in range(wl.nf)])
-            e["p"].set_fields(dev(wl.chi), dev(wl.eps), dev(B))
-            torch.cuda.synchronize()
-            return rt.rt_server_submit(srv, e["p"].handle, e["S"], e["J"], delta_c=1e-6, max_iter=args.max_iter,
-                                       warm_start=2)
-        return rt.rt_server_submit(srv, e["p"].handle, e["S"], e["J"], delta_c=1e-6, max_iter=args.max_iter)
+        def kinds_for(m):
+            out = []
+            for _ in range(m):
+                if rng.random() < 0.3:
+                    out.append(("stream", int(rng.integers(len(streams)))))
+                else:
+                    out.append(("fresh", counter[0]))
+                    counter[0] += 1
+            return out
 
-    # capacity: every pool problem at once, cold
-    t0 = time.perf_counter()
-    tickets = [submit(e, False) for e in pool]
-    done = _wait_all(rt, srv, tickets, "serving capacity")
-    cap_s = time.perf_counter() - t0
-    capacity = len(pool) / cap_s
-    for t in tickets:
-        rt.rt_server_release(srv, t)
+        def summary(run, span, unserved, rate, window):
+            lat = [d["latency"] for d in run.done]
+            served = len(run.done)
+            warm = [d["iterations"] for d in run.done if d["kind"] == "stream"]
+            cold = [d["iterations"] for d in run.done if d["kind"] == "fresh"]
+            out = {"rate_per_s": rate, "window_s": window, "arrived": served + unserved, "served": served,
+                   "unserved": unserved, "solves_per_s": served / span if span > 0 else 0.0,
+                   "updates_per_s": sum(d["updates"] for d in run.done) / span if span > 0 else 0.0,
+                   "latency_ms": {"p50": _pct(lat, 50) * 1e3 if lat else None, "p99": _pct(lat, 99) * 1e3 if lat else None},
+                   "iterations_cold_median": float(np.median(cold)) if cold else None,
+                   "iterations_warm_median": float(np.median(warm)) if warm else None,
+                   "not_converged": sum(d["status"] != rt.RT_OK for d in run.done)}
+            if unserved:
+                out["latency_note"] = (f"{unserved} requests were still waiting when the window closed; their latency "
+                                       f"exceeds {window:.0f} s and is not in the percentiles")
+            return out
 
-    def run_rate(rate, nreq, label):
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
-        backlog, inflight, lat, t_start = [], {}, [], time.perf_counter()
-        nxt = 0
-        while nxt < nreq or backlog or inflight:
-            now = time.perf_counter() - t_start
-            while nxt < nreq and arrivals[nxt] <= now:
-                backlog.append(arrivals[nxt])
-                nxt += 1
-            # admit backlog to idle problems (30% of requests go to the drifting streams)
-            while backlog:
-                want_stream = rng.random() < 0.3
-                idle = [e for e in pool if not e["busy"] and e["stream"] == want_stream] or \
-                       [e for e in pool if not e["busy"]]
-                if not idle:
-                    break
-                e = idle[rng.integers(len(idle))]
-                e["busy"] = True
-                t = submit(e, warm=e["stream"])
-                inflight[t] = (e, backlog.pop(0))
-            for t in list(inflight):
-                r = rt.rt_server_poll(srv, t)
-                if r is not None:
-                    e, arr = inflight.pop(t)
-                    e["busy"] = False
-                    lat.append(time.perf_counter() - t_start - arr)
-                    rt.rt_server_release(srv, t)
-                    print(f"{label}: {len(lat)}/{nreq} done, latency {lat[-1] * 1e3:.0f} ms", file=sys.stderr,
-                          flush=True)
-            time.sleep(0.0005)
-        span = time.perf_counter() - t_start
-        return {"rate_per_s": rate, "requests": nreq, "solves_per_s": nreq / span,
-                "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3}}
-
-    curve = [run_rate(f * capacity, args.requests, f"serving {f:.2f}x") for f in (0.25, 0.5, 0.9)]
-    over = run_rate(200.0, args.requests * 2, "serving 200/s")
-    rt.rt_server_destroy(srv)
-    for e in pool:
-        e["p"].close()
+        # capacity: a saturated window (requests always waiting)
+        cap_window = args.serve_window / 2
+        n_cap = 400
+        cap_run = _ServingRun(rt, W, torch, np, srv, budget, streams, args.max_iter, "serving capacity", args.serve_max_n)
+        runs.append(cap_run)
+        span, _ = cap_run.run(np.zeros(n_cap), kinds_for(n_cap), t_admit_end=cap_window)
+        capacity = len(cap_run.done) / span
+        print(f"serving: capacity {capacity:.2f} solves/s ({len(cap_run.done)} in {span:.1f} s)", file=sys.stderr,
+              flush=True)
+        results = []
+        for frac in (0.25, 0.5, 0.9):
+            rate = frac * capacity
+            arr = np.cumsum(rng.exponential(1.0 / rate, int(rate * args.serve_window * 2) + 8))
+            arr = arr[arr < args.serve_window]
+            run = _ServingRun(rt, W, torch, np, srv, budget, streams, args.max_iter, f"serving {frac:.2f}x", args.serve_max_n)
+            runs.append(run)
+            span, unserved = run.run(arr, kinds_for(len(arr)))
+            results.append(summary(run, span, unserved, rate, args.serve_window))
+        rate = 200.0
+        arr = np.cumsum(rng.exponential(1.0 / rate, int(rate * args.serve_window * 1.2) + 8))
+        arr = arr[arr < args.serve_window]
+        run = _ServingRun(rt, W, torch, np, srv, budget, streams, args.max_iter, "serving 200/s", args.serve_max_n)
+        runs.append(run)
+        span, unserved = run.run(arr, kinds_for(len(arr)), t_admit_end=args.serve_window)
+        over = summary(run, span, unserved, rate, args.serve_window)
+    finally:
+        # every request finishes before any of its problems is freed, also when a run
+        # above raised
+        rt.rt_server_destroy(srv)
+        for r in runs:
+            for rec in r.inflight.values():
+                if rec["fresh"]:
+                    rec["p"].close()
+        for st in streams:
+            if st.get("problem") is not None:
+                st["problem"].close()
     return {
-        "metric": METRIC, "value": over["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": over["requests"],
-        "warmup": 0, "ms_per_step": 1e3 / over["solves_per_s"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded, generated on the host)",
-        "config": {"workload": f"serving: pool of {args.pool} request problems (N 32..160 cubed, 8..32 bins, "
-                               f"48 rays, eps 1e-4..1; {args.streams} drifting warm-started streams), Poisson "
-                               f"arrivals, Jacobi ALI to 1e-6 per bin, FP32 sweeps"},
-        "capacity_solves_per_s": capacity, "latency_vs_rate": curve, "overload_200_per_s": over,
+        "metric": METRIC, "value": over["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": over["served"], "warmup": 0,
+        "ms_per_step": 1e3 / over["solves_per_s"] if over["solves_per_s"] > 0 else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded; every request's fields generated on the device)",
+        "config": {"workload": f"serving: Poisson arrivals at 200 requests/s over {args.serve_window:.0f} s, each a "
+                               f"new problem (N log-uniform 32..{args.serve_max_n} cubed, 8..32 bins, 48 rays, eps 10^U[-4,0]); 30% "
+                               f"successive snapshots of {args.streams} drifting streams (T x (1 + 0.02 h) per step) "
+                               "warm-started from device-resident S and J; HBM-bounded admission; Jacobi ALI to "
+                               "1e-6 per bin, FP32 sweeps", "hbm_budget_bytes": budget},
+        "capacity_solves_per_s": capacity, "latency_vs_rate": results, "overload_200_per_s": over,
     }
 
 
@@ -518,7 +656,7 @@ def bench_scattering(args, rt, W, torch, np, steps, warmup, cpu=True):
     cells = wl.cells
     mom = {k: torch.empty(m * cells, dtype=torch.float64, device="cuda")
            for k, m in (("J_int", 1), ("H_int", 3), ("K_int", 6), ("f_int", 6), ("Q_int", 1))}
-    sched = rt.RT_SCHED_STAGES
+    sched = _schedule(args, rt)
     order = rt.RT_SC_BEZIER if args.order == "bezier" else rt.RT_SC_LINEAR
     quad = args.interp == "quadratic"
     if quad and order:
@@ -578,9 +716,9 @@ def bench_scattering(args, rt, W, torch, np, steps, warmup, cpu=True):
     kernel_s = prof["kernel_ms"] / 1e3
     achieved = prof["updates"] * ops_per_update / kernel_s / 1e12 if kernel_s > 0 else 0.0
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(kind) if profiled_size else None,
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(kind) if profiled_size and args.schedule == "stages" else None,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": "plane_step_kernel<float, true, 1>" if quad else f"sweep_stage_kernel<float, true, 1, false, {order}, 8>",
+                "kernel": "plane_step_kernel<float, true, 1>" if quad else _sweep_kernel_name(args, order),
                 "avg_launch_us": prof["kernel_ms"] * 1e3 / max(prof["launches"], 1),
                 "timed_launches": prof["launches"],
                 "ops_per_update": ops_per_update}
@@ -655,7 +793,8 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="grid edge of the scattering workload")
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 GPU comparison solve")
-    ap.add_argument("--schedule", choices=["stages"], default="stages")
+    ap.add_argument("--schedule", choices=["stages", "persistent"], default="stages",
+                    help="tile wavefront: one launch per hyperplane, or one persistent launch per sweep")
     ap.add_argument("--order", choices=["linear", "bezier"], default="linear",
                     help="scattering: first-order or second-order (Bezier) short characteristics")
     ap.add_argument("--interp", choices=["bilinear", "quadratic"], default="bilinear",
@@ -665,9 +804,9 @@ def main():
                     help="scattering: Jacobi ALI, or Gauss-Seidel with horizontal planes as the blocks")
     ap.add_argument("--fixed-iters", type=int, default=0,
                     help="profiling mode: run exactly this many ALI iterations per step instead of converging")
-    ap.add_argument("--pool", type=int, default=12, help="serving: request problems kept on the device")
-    ap.add_argument("--streams", type=int, default=4, help="serving: pool problems that are drifting streams")
-    ap.add_argument("--requests", type=int, default=24, help="serving: requests per arrival rate")
+    ap.add_argument("--streams", type=int, default=16, help="serving: drifting snapshot streams")
+    ap.add_argument("--serve-window", type=float, default=30.0, help="serving: arrival window per rate (s)")
+    ap.add_argument("--serve-max-n", type=int, default=160, help="serving: largest grid edge of a request")
     ap.add_argument("--workload", choices=["multifreq", "scattering", "batched", "serving"], default="multifreq",
                     help="multifreq: 192^3 x 64 bins x 80 rays, a step is one Jacobi iteration over all bins "
                          "(default; the 128^3 scattering solves are reported beside it); scattering: the 128^3 "

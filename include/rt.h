@@ -64,7 +64,7 @@ typedef enum {
     RT_E_HIP = -3,          /* a HIP runtime call failed */
     RT_E_NONFINITE = -4,    /* a residual became NaN or Inf */
     RT_E_UNSUPPORTED = -5,  /* valid request the library does not implement */
-    RT_E_BUSY = -6          /* rt_server_poll: the request is queued or running */
+    RT_E_BUSY = -6          /* rt_server_poll, rt_problem_destroy: a request is queued or running */
 } rt_status;
 
 /* Sweep arithmetic.  RT_F64 integrates I itself in FP64 ("plain form").
@@ -176,6 +176,8 @@ rt_status rt_problem_bytes(const rt_problem_desc *desc, size_t *bytes);
 /* Create the per-problem device state on the context's device (ctx may be NULL: the
  * current device). */
 rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_problem **out);
+/* Frees the problem's device state.  RT_E_BUSY (nothing freed) while a server
+ * request on the problem is queued or running. */
 rt_status rt_problem_destroy(rt_problem *p);
 
 /*

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -280,6 +281,7 @@ struct rt_problem {
     rt_problem_desc desc{};
     rt_context *ctx = nullptr;         // context it was created in, or null
     int device = 0;                    // HIP device holding its state
+    std::atomic<int> server_refs{0};   // queued or running server requests on it
     // caller arrays in FP32 (desc.in_dtype): FP64 copies of the caller's S and J that
     // the solvers work on, and FP64 staging of the moments outputs (made on first use)
     bool usr32 = false;
@@ -1164,6 +1166,8 @@ rt_status rt_problem_destroy(rt_problem *p)
 {
     if (!p) return RT_OK;
     CallScope scope(p->ctx, p->device);
+    // a server's worker may still launch kernels on its state
+    if (p->server_refs.load() > 0) return fail(RT_E_BUSY, "the problem has a queued or running server request");
     for (void *v : p->allocs) (void)hipFree(v);
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     if (p->h_sum) (void)hipHostFree(p->h_sum);
@@ -2342,6 +2346,7 @@ struct rt_server {
     void finish(uint64_t t, rt_status r, const rt_ali_stats &st)
     {
         Request &q = reqs[t];
+        q.item.p->server_refs.fetch_sub(1);
         q.done = true;
         q.result = r;
         q.stats = st;
@@ -2354,6 +2359,7 @@ struct rt_server {
     void abandon(uint64_t t, rt_status r)
     {
         Request &q = reqs[t];
+        q.item.p->server_refs.fetch_sub(1);
         q.done = true;
         q.result = r;
         if (q.ready) (void)hipEventDestroy(q.ready);
@@ -2536,6 +2542,7 @@ rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opt
     const uint64_t t = srv->next_ticket++;
     q.item.tag = t;
     srv->reqs[t] = q;
+    p->server_refs.fetch_add(1);
     srv->queue.push_back(t);
     *ticket = t;
     srv->cv.notify_all();

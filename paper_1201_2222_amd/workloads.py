@@ -25,7 +25,9 @@ Workloads (grid, rays, physics):
   serving    request problems (seed 1005 + index): cubic N log-uniform in [32, 160],
              8..32 Planck bins, 48 rays, eps = 10^U[-4, 0], chi and T as batched;
              drifting snapshot streams scale T by 1 + 0.02 h with h a smooth 8-mode
-             field (max |h| = 1) per step.
+             field (max |h| = 1) per step.  serving_request draws the same recipe
+             with its per-cell fields generated on the device (one new problem per
+             request of the serving benchmark).
 """
 from __future__ import annotations
 
@@ -210,3 +212,70 @@ def drift(T, step, seed=1005):
     nz, ny, nx = T.shape
     h = _fourier_field(rng, (nx, ny, nz))
     return T * (1.0 + 0.02 * h)
+
+
+# ---- serving requests generated on the device ---------------------------------------
+# The serving workload draws a new problem for every request (thousands per run), so its
+# fields are drawn with torch on the device: the request's scalars (grid edge, bins,
+# eps) from numpy with the request's seed, the per-cell fields from a torch generator
+# seeded from it.  The arrays follow serving_problem's recipe.
+
+def _torch_planck(x, T):
+    import torch
+    return x ** 3 / torch.expm1(x / T)
+
+
+def _torch_fourier(gen, n, device, modes=8, kmax=4):
+    """Smooth field of 8 random Fourier modes on an n^3 grid, max |h| = 1."""
+    import torch
+    ax = torch.arange(n, device=device, dtype=torch.float64)
+    z, y, x = torch.meshgrid(ax, ax, ax, indexing="ij")
+    g = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    for _ in range(modes):
+        while True:
+            kv = torch.randint(-kmax, kmax + 1, (3,), generator=gen, device=device)
+            if bool((kv != 0).any()):
+                break
+        a = 0.5 + 0.5 * torch.rand((), generator=gen, device=device, dtype=torch.float64)
+        phi = 2.0 * np.pi * torch.rand((), generator=gen, device=device, dtype=torch.float64)
+        g += a * torch.cos(2.0 * np.pi * (kv[0] * x + kv[1] * y + kv[2] * z) / n + phi)
+    return g / g.abs().max()
+
+
+def serving_request(index, device="cuda", seed=1005, min_n=32, max_n=160, n=None, nf=None):
+    """Request ``index`` of the serving workload with its fields on ``device``: cubic N
+    log-uniform in [32, 160] (or ``n``), 8..32 Planck bins (or ``nf``), 48 rays, eps =
+    10^U[-4, 0], grey chi lognormal(0, 1) scaled to a vertical tau of 10, T ~
+    U[0.5, 1.5].  Returns a dict of flat device tensors chi, eps, B ([nf][n^3]), the
+    frequency weights and T ([n^3]) for drifting streams."""
+    import torch
+    rng = np.random.default_rng(seed + 7919 * index)
+    n_ = int(round(np.exp(rng.uniform(np.log(min_n), np.log(max_n))))) if n is None else int(n)
+    nf_ = int(rng.integers(8, 33)) if nf is None else int(nf)
+    eps = float(10.0 ** rng.uniform(-4.0, 0.0))
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(0, 2 ** 62)))
+    chi1 = torch.exp(torch.randn((n_, n_, n_), generator=gen, device=device, dtype=torch.float64))
+    chi1 *= 10.0 / chi1.sum(dim=0).mean()
+    T = 0.5 + torch.rand((n_, n_, n_), generator=gen, device=device, dtype=torch.float64)
+    x = np.logspace(np.log10(0.05), np.log10(50.0), nf_)
+    w = np.zeros(nf_)
+    w[1:] += 0.5 * np.diff(x)
+    w[:-1] += 0.5 * np.diff(x)
+    B = torch.stack([_torch_planck(float(xb), T) for xb in x]).reshape(-1)
+    chi = chi1.reshape(1, -1).expand(nf_, -1).reshape(-1).contiguous()
+    return {"shape": (n_, n_, n_), "nf": nf_, "n_mu": 6, "eps_value": eps, "chi": chi,
+            "eps": torch.full_like(chi, eps), "B": B, "w_nu": w, "x_nu": x, "T": T.reshape(-1), "gen": gen}
+
+
+def serving_drift(req, step, device="cuda", seed=1005):
+    """Next snapshot of a drifting stream: T (1 + 0.02 h) with a smooth 8-mode field h
+    drawn for this step (max |h| = 1); returns the new B (the stream's chi and eps stay)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed * 1000003 + 101 * step + req["shape"][0])
+    n = req["shape"][0]
+    h = _torch_fourier(gen, n, device).reshape(-1)
+    req["T"] = req["T"] * (1.0 + 0.02 * h)
+    req["B"] = torch.stack([_torch_planck(float(xb), req["T"]) for xb in req["x_nu"]]).reshape(-1)
+    return req["B"]

@@ -66,3 +66,26 @@ def test_bench_default_multifreq_line():
     c = out["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0
     assert c["single_thread"]["cores"] == 1 and c["single_thread"]["value"] > 0
+
+
+@pytest.mark.gpu
+@pytest.mark.timeout(600)
+def test_bench_serving_line():
+    """The serving workload at a reduced request size and window: one JSON line with the
+    overload figure, the capacity and the latency curve."""
+    run = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--workload", "serving",
+                          "--serve-window", "3", "--streams", "2", "--serve-max-n", "40"],
+                         cwd=ROOT, capture_output=True, text=True, timeout=500)
+    assert run.returncode == 0, run.stderr[-3000:]
+    lines = [l for l in run.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    assert out["unit"] == "solves/s" and out["value"] > 0 and out["capacity_solves_per_s"] > 0
+    assert [round(r["rate_per_s"] / out["capacity_solves_per_s"], 2) for r in out["latency_vs_rate"]] == \
+        [0.25, 0.5, 0.9]
+    for r in out["latency_vs_rate"] + [out["overload_200_per_s"]]:
+        assert r["served"] + r["unserved"] == r["arrived"]
+        if r["served"]:
+            assert 0 < r["latency_ms"]["p50"] <= r["latency_ms"]["p99"]
+        assert r["not_converged"] == 0
+    assert out["overload_200_per_s"]["arrived"] > 0

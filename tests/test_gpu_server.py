@@ -112,3 +112,72 @@ def test_server_warm_start_and_errors(env):
         rt.rt_server_submit(srv, p.handle, S, J, fixed_iters=-2)
     rt.rt_server_destroy(srv)
     p.close()
+
+
+def test_serving_requests_match_solo(env):
+    """Requests of the serving workload (fields generated on the device, several in
+    flight at once) give bitwise the results of the same problems solved alone, also
+    for a drifting stream's second snapshot warm-started from its first."""
+    rt, torch = env
+    reqs = [W.serving_request(k, n=n, nf=nf) for k, (n, nf) in enumerate([(24, 8), (36, 9), (17, 12)])]
+
+    def problem(req):
+        p = rt.Problem(req["shape"], nf=req["nf"], n_mu=req["n_mu"], w_nu=req["w_nu"], precision=rt.RT_F32)
+        p.set_fields(req["chi"], req["eps"], req["B"])
+        return p
+
+    served = [(problem(r), torch.empty_like(r["B"]), torch.empty_like(r["B"])) for r in reqs]
+    srv = rt.rt_server_create(sum(rt.rt_problem_bytes(p.desc) for p, _, _ in served), check_every=8)
+    tickets = [rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=4000) for p, S, J in served]
+    res = _wait(rt, srv, tickets)
+    for (p, S, J), r, t in zip(served, reqs, tickets):
+        assert res[t][0] == rt.RT_OK
+        q = problem(r)
+        S1, J1 = torch.empty_like(r["B"]), torch.empty_like(r["B"])
+        st, _ = q.ali_solve(S1, J1, delta_c=1e-6, max_iter=4000, check_every=8)
+        assert st == rt.RT_OK
+        torch.cuda.synchronize()
+        assert torch.equal(S, S1) and torch.equal(J, J1)
+        q.close()
+    # a drifting stream: snapshot 1 warm-started (S = eps B + (1 - eps) J) from snapshot 0
+    p0, S0, J0 = served[0]
+    rt.rt_server_release(srv, tickets[0])
+    B0 = reqs[0]["B"]
+    B1 = W.serving_drift(reqs[0], 1)      # the stream's request now holds snapshot 1
+    p0.set_fields(reqs[0]["chi"], reqs[0]["eps"], B1)
+    t1 = rt.rt_server_submit(srv, p0.handle, S0, J0, delta_c=1e-6, max_iter=4000, warm_start=2)
+    (st1, stats1), = _wait(rt, srv, [t1]).values()
+    assert st1 == rt.RT_OK
+    q = problem(dict(reqs[0], B=B0))   # snapshot 0 alone, then snapshot 1 warm-started the same way
+    Sa, Ja = torch.empty_like(B1), torch.empty_like(B1)
+    assert q.ali_solve(Sa, Ja, delta_c=1e-6, max_iter=4000, check_every=8)[0] == rt.RT_OK
+    q.set_fields(reqs[0]["chi"], reqs[0]["eps"], B1)
+    st, stats = q.ali_solve(Sa, Ja, delta_c=1e-6, max_iter=4000, warm_start=2, check_every=8)
+    assert st == rt.RT_OK
+    torch.cuda.synchronize()
+    assert torch.equal(S0, Sa) and torch.equal(J0, Ja)
+    assert stats["iterations"] == stats1["iterations"]
+    for t in tickets[1:] + [t1]:
+        rt.rt_server_release(srv, t)
+    rt.rt_server_destroy(srv)
+    for p, _, _ in served:
+        p.close()
+    q.close()
+
+
+def test_problem_with_pending_request_is_not_freed(env):
+    """rt_problem_destroy refuses (RT_E_BUSY, nothing freed) while a server request on
+    the problem is queued or running, and frees it once the request has finished."""
+    rt, torch = env
+    p, S, J = _make(rt, torch, 1, SPECS[1])
+    srv = rt.rt_server_create(1 << 34, check_every=50)
+    t = rt.rt_server_submit(srv, p.handle, S, J, fixed_iters=3000)
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_problem_destroy(p.handle)
+    assert e.value.status == rt.RT_E_BUSY
+    res = _wait(rt, srv, [t])[t]
+    assert res[0] == rt.RT_OK and res[1]["iterations"] == 3000
+    rt.rt_server_release(srv, t)
+    rt.rt_server_destroy(srv)
+    p.close()
+    assert p.handle is None
