@@ -327,7 +327,6 @@ struct rt_problem {
     bool persistent = false;           // one launch per sweep (dependency flags)
     int ntiles = 0;                    // tiles per (bin, octant)
     int bpo = 1;                       // persistent workgroups per octant
-    int epoch = 0;                     // sweeps run by the persistent kernel
     uint64_t wait_ticks = 0;           // 20 ms in device wall-clock ticks
     int *dag_counter = nullptr;        // [8] ticket counters
     // moments epilogue scratch (allocated on first use)
@@ -479,7 +478,7 @@ size_t state_bytes(const rt_problem_desc *d, int na)
     }
     if (d->in_dtype == RT_DTYPE_F32) b += (size_t)nc * 8 * 2;   // FP64 copies of the caller's S and J
     b += (size_t)d->nf * kUpdateBlocks * 8;        // residual block maxima
-    b += (size_t)d->nf * 8 * nt[0] * nt[1] * nt[2] * 4 + 32;  // persistent-sweep flags
+    b += (size_t)d->nf * 8 * nt[0] * nt[1] * nt[2] * 4 + 64;  // persistent-sweep flags
     b += (size_t)na * sizeof(RayGeo) + (size_t)nt[0] * nt[1] * nt[2] * 4 + (size_t)d->nf * 32 + 64;
     return b;
 }
@@ -680,13 +679,14 @@ rt_status run_sweep(rt_problem *p, const double *S, hipStream_t st, bool timed =
         D.done = p->dag_done;
         D.err = p->flags + 2;
         D.wait_ticks = p->wait_ticks;
-        D.epoch = ++p->epoch;
         D.ntiles = p->ntiles;
         D.nt0 = p->nt[0];
         D.nt1 = p->nt[1];
         A.stage_off = 0;
         A.stage_cnt = p->ntiles;
-        HIP_TRY(hipMemsetAsync(p->dag_counter, 0, 8 * sizeof(int), st));
+        // counters zeroed and the epoch advanced by a kernel (also under graph capture:
+        // no memset node, and no epoch fixed at capture time)
+        HIP_TRY(launch_dag_begin(p->dag_counter, st));
         if (timed) HIP_TRY(hipEventRecord(p->ev[0], st));
         if constexpr (sizeof(Real) == 8)
             HIP_TRY(launch_sweep_persistent_f64(A, D, W, p->bpo, st));
@@ -1319,7 +1319,7 @@ rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_pro
     ALLOC(p->blockmax, (size_t)p->nf * kUpdateBlocks);
     ALLOC(p->flags, 4);
     p->ntiles = p->nt[0] * p->nt[1] * p->nt[2];
-    ALLOC(p->dag_counter, 8);
+    ALLOC(p->dag_counter, 16);
     ALLOC(p->dag_done, (size_t)p->nf * 8 * p->ntiles);
 #undef ALLOC
     if (hipHostMalloc((void **)&p->h_flags, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
@@ -1360,6 +1360,7 @@ rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_pro
     if (e == hipSuccess) e = hipMemset(p->parity, 0, sizeof(int) * p->nf);
     if (e == hipSuccess) e = hipMemset(p->flags, 0, sizeof(int) * 4);
     if (e == hipSuccess) e = hipMemset(p->dag_done, 0, sizeof(int) * (size_t)p->nf * 8 * p->ntiles);
+    if (e == hipSuccess) e = hipMemset(p->dag_counter, 0, sizeof(int) * 16);   // tickets and the epoch
     if (e == hipSuccess && p->plane_order) {
         // classes (octant, first-crossed axis); a class without rays keeps zero partials
         std::vector<int> off(kPlaneParts + 1, 0), list;

@@ -144,14 +144,15 @@ struct GsArgs {
 };
 
 // Dependency state of the persistent sweep: one completion flag per (bin, octant,
-// tile) holding the epoch of the sweep that last finished it, and one ticket
-// counter per octant (zeroed before each sweep).
+// tile) holding the epoch of the sweep that last finished it, one ticket counter per
+// octant and the epoch itself, both in device memory: a small kernel before each
+// sweep zeroes the counters and advances the epoch, so a sweep replayed from a
+// captured graph gets a new epoch and fresh counters like one launched directly.
 struct DagArgs {
-    int *counter;             // [8]
+    int *counter;             // [8] tickets per octant, [8] the epoch of the current sweep
     int *done;                // [nf][8][ntiles]
     int *err;                 // set when a dependency wait ran out
     uint64_t wait_ticks;      // bound of one wait in wall-clock ticks
-    int epoch;
     int ntiles;
     int nt0, nt1;             // tiles along x and y
     __host__ __device__ int tile_id(int tx, int ty, int tz) const { return (tz * nt1 + ty) * nt0 + tx; }
@@ -189,6 +190,7 @@ hipError_t launch_sweep_stage_f64(const SweepArgs<double> &A, int waves, int nq,
 hipError_t launch_sweep_stage_f32(const SweepArgs<float> &A, int waves, int nq, hipStream_t st);
 // dynamic LDS bytes of one sweep workgroup with the given number of waves
 size_t sweep_lds_bytes(int real_bytes, int waves, int nq, bool multi, int order);
+hipError_t launch_dag_begin(int *counter, hipStream_t st);
 hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs &D, int waves, int blocks_per_octant,
                                        hipStream_t st);
 hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int blocks_per_octant,

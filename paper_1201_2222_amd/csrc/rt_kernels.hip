@@ -803,6 +803,13 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_batch_stage_kernel(const
     sweep_tile<Real, DFORM, false, 1, MULTI, ORD>(A, oct, f, packed, par, lds_raw, nullptr, 0, 0, 0, 0, nullptr, 0);
 }
 
+// Before each persistent sweep: zero the octants' ticket counters, advance the epoch.
+__global__ void dag_begin_kernel(int *counter)
+{
+    if (threadIdx.x < 8) counter[threadIdx.x] = 0;
+    if (threadIdx.x == 0) counter[8] += 1;
+}
+
 // Whole formal solution in one launch.  Workgroups with blockIdx.x % 8 == o serve
 // octant o: they draw tickets from that octant's counter; ticket t is tile
 // tiles[t % ntiles] of bin f0 + t / ntiles, so every tile's upwind neighbours carry
@@ -825,18 +832,19 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
     __shared__ int s_ticket;
     const int oct = blockIdx.x & 7;
     const int items = D.ntiles * A.nfc;
+    const int epoch = __builtin_amdgcn_readfirstlane(D.counter[8]);   // set by dag_begin_kernel
     int done_f = -1, done_tile = -1;   // the tile this workgroup finished last (uniform)
     for (;;) {
         if (threadIdx.x == 0) {
             if (done_tile >= 0)
-                __hip_atomic_store(D.done + ((int64_t)done_f * 8 + oct) * D.ntiles + done_tile, D.epoch,
+                __hip_atomic_store(D.done + ((int64_t)done_f * 8 + oct) * D.ntiles + done_tile, epoch,
                                    __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             s_ticket = atomicAdd(D.counter + oct, 1);
         }
         __syncthreads();
         const int t = __builtin_amdgcn_readfirstlane(s_ticket);
         __syncthreads();
-        if (t >= items) break;
+        if (t < 0 || t >= items) break;
         const int fc = t / D.ntiles;
         const int tile = t - fc * D.ntiles;
         const int f = A.f0 + fc;
@@ -845,7 +853,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
         const int par = __builtin_amdgcn_readfirstlane(A.parity[f]);
         done_tile = -1;
         if (frozen | (packed < 0) | (par < 0)) continue;
-        sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, par, lds_raw, D.done, D.epoch, D.ntiles, D.nt0,
+        sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, par, lds_raw, D.done, epoch, D.ntiles, D.nt0,
                                                   D.nt1, D.err, D.wait_ticks);
         // every wave's stores of the tile reach the device scope before the barrier
         // after which thread 0 publishes the tile
@@ -1435,6 +1443,12 @@ static hipError_t launch_persistent(const SweepArgs<Real> &A, const DagArgs &D, 
 {
     hipLaunchKernelGGL((sweep_persistent_kernel<Real, DFORM>), dim3(8u * (unsigned)blocks_per_octant), dim3(64 * waves),
                        sweep_lds_bytes(sizeof(Real), waves, 1, true, 0), st, A, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_dag_begin(int *counter, hipStream_t st)
+{
+    hipLaunchKernelGGL(dag_begin_kernel, dim3(1), dim3(64), 0, st, counter);
     return hipGetLastError();
 }
 

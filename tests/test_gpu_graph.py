@@ -53,12 +53,15 @@ def _sequence(env, wl, graphs, precision, gs=False, **kw):
     return out
 
 
-@pytest.mark.parametrize("variant", ["f64", "f32", "bezier", "quadratic", "gs64", "gs32"])
+@pytest.mark.parametrize("variant", ["f64", "f32", "bezier", "quadratic", "gs64", "gs32", "persistent64",
+                                     "persistent32"])
 def test_graph_replays_match_eager(env, variant):
     rt, torch = env
     wl = W.random_problem((20, 14, 12), nf=2, seed=1200, n_mu=4, eps_range=(1e-2, 1.0))
-    prec = rt.RT_F32 if variant in ("f32", "bezier", "quadratic", "gs32") else rt.RT_F64
+    prec = rt.RT_F32 if variant in ("f32", "bezier", "quadratic", "gs32", "persistent32") else rt.RT_F64
     kw = {}
+    if variant.startswith("persistent"):
+        kw["schedule"] = rt.RT_SCHED_PERSISTENT
     if variant == "bezier":
         kw["order"] = rt.RT_SC_BEZIER
     if variant == "quadratic":
@@ -72,6 +75,29 @@ def test_graph_replays_match_eager(env, variant):
             assert np.array_equal(a, b)
         else:
             assert a == b
+
+
+def test_persistent_graph_of_one_iteration(env):
+    """The persistent schedule replayed from a one-iteration graph many times in a row
+    (every replay needs its own epoch and fresh ticket counters, set on the device)
+    gives bitwise the host-issued iterations."""
+    rt, torch = env
+    wl = W.random_problem((26, 17, 21), nf=2, seed=1300, n_mu=6, eps_range=(1e-2, 1.0))
+    out = []
+    for graphs in (False, True):
+        gp = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=rt.RT_F32,
+                        schedule=rt.RT_SCHED_PERSISTENT)
+        gp.use_graphs(graphs)
+        gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+        n = wl.chi.size
+        S = torch.empty(n, dtype=torch.float64, device="cuda")
+        J = torch.empty(n, dtype=torch.float64, device="cuda")
+        st, stats = gp.ali_solve(S, J, fixed_iters=40, check_every=1)
+        torch.cuda.synchronize()
+        assert st == rt.RT_OK and stats["iterations"] == 40
+        out.append((S.cpu().numpy(), J.cpu().numpy()))
+        gp.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
 def test_graph_cache_follows_the_buffers(env, oracle_mod):
