@@ -293,7 +293,7 @@ struct rt_problem {
     int nstages = 0;
     int64_t cells = 0;
     int64_t plane[3]{};
-    int64_t pplane[3]{};               // face planes padded by the row and column at -1
+    int64_t pplane[3]{};               // values per face-plane slot (FacePlane::slot)
     int periodic[3]{};
     bool f32 = false;
     bool cold = true;
@@ -457,8 +457,8 @@ size_t state_bytes(const rt_problem_desc *d, int na)
     int nt[3];
     tile_counts(d, nt);
     const int64_t plane[3] = {(int64_t)d->ny * d->nz, (int64_t)d->nx * d->nz, (int64_t)d->nx * d->ny};
-    const int64_t pplane[3] = {(int64_t)(d->ny + 1) * (d->nz + 1), (int64_t)(d->nx + 1) * (d->nz + 1),
-                               (int64_t)(d->nx + 1) * (d->ny + 1)};
+    const int64_t pplane[3] = {FacePlane(d->ny, d->nz).slot(), FacePlane(d->nx, d->nz).slot(),
+                               FacePlane(d->nx, d->ny).slot()};
     const int bc_per[3] = {d->bc_lo[0] == RT_BC_PERIODIC, d->bc_lo[1] == RT_BC_PERIODIC, d->bc_lo[2] == RT_BC_PERIODIC};
     size_t b = 0;
     b += (size_t)nc * 8 * 4;                       // chi64, eps, B, lam
@@ -471,7 +471,7 @@ size_t state_bytes(const rt_problem_desc *d, int na)
         b += (size_t)(kPlaneParts + 1 + na) * 4;
     } else {
         for (int q = 0; q < 3; ++q) {
-            b += (size_t)d->nf * na * nt[q] * pplane[q] * rs;           // padded face planes
+            b += (size_t)d->nf * na * nt[q] * pplane[q] * rs;           // face planes
             if (bc_per[q]) b += (size_t)d->nf * na * 2 * plane[q] * 8;  // periodic memory
         }
         b += (size_t)8 * nc * rs;                  // partials
@@ -1215,9 +1215,9 @@ rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_pro
     p->plane[0] = (int64_t)desc->ny * desc->nz;
     p->plane[1] = (int64_t)desc->nx * desc->nz;
     p->plane[2] = (int64_t)desc->nx * desc->ny;
-    p->pplane[0] = (int64_t)(desc->ny + 1) * (desc->nz + 1);
-    p->pplane[1] = (int64_t)(desc->nx + 1) * (desc->nz + 1);
-    p->pplane[2] = (int64_t)(desc->nx + 1) * (desc->ny + 1);
+    p->pplane[0] = FacePlane(desc->ny, desc->nz).slot();
+    p->pplane[1] = FacePlane(desc->nx, desc->nz).slot();
+    p->pplane[2] = FacePlane(desc->nx, desc->ny).slot();
     for (int q = 0; q < 3; ++q) p->periodic[q] = desc->bc_lo[q] == RT_BC_PERIODIC;
     tile_counts(desc, p->nt);
     p->w_nu.assign(desc->nf, 1.0);

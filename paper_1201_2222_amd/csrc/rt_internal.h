@@ -11,6 +11,30 @@ enum { BC_VACUUM = 0, BC_THERMAL = 1, BC_PERIODIC = 2, BC_FIXED = 3 };
 constexpr int kTile = 8;        // tile edge of the wavefront sweep
 constexpr int kMaxWaves = 10;   // waves per sweep workgroup (one ray each at a time)
 
+// Face planes (SweepArgs::face): one slot holds the vertices (a, b), a = -1 .. n_a - 1,
+// b = -1 .. n_b - 1, of the two axes other than q (a: y for q = x, else x; b: z for
+// q = x or y, else y), laid out so that a tile reads and writes aligned runs:
+//   [0, 64 nblk)          a, b >= 0 in 8 x 8 blocks [b / 8][a / 8][b % 8][a % 8]
+//   [64 nblk, 72 nblk)    every block's last column (a % 8 == 7) again, [b / 8][a / 8][b % 8]
+//   then n_a + 1 values   the row b = -1 (a = -1 .. n_a - 1)
+//   then n_b values       the column a = -1 (b = 0 .. n_b - 1)
+// with nblk = ceil(n_a / 8) ceil(n_b / 8); a slot is padded to a multiple of 64 values.
+struct FacePlane {
+    int na, nb, nba, nblk;
+    __host__ __device__ FacePlane(int na_, int nb_)
+        : na(na_), nb(nb_), nba((na_ + 7) >> 3), nblk(((na_ + 7) >> 3) * ((nb_ + 7) >> 3)) {}
+    __host__ __device__ int64_t slot() const { return ((int64_t)nblk * 72 + na + 1 + nb + 63) / 64 * 64; }
+    // vertex (a, b), a, b >= -1
+    __host__ __device__ int at(int a, int b) const
+    {
+        if (b < 0) return nblk * 72 + a + 1;
+        if (a < 0) return nblk * 72 + na + 1 + b;
+        return (((b >> 3) * nba + (a >> 3)) << 6) + ((b & 7) << 3) + (a & 7);
+    }
+    // the copy of vertex (a, b) with a % 8 == 7, a, b >= 0, among the blocks' last columns
+    __host__ __device__ int col(int a, int b) const { return (nblk << 6) + (((b >> 3) * nba + (a >> 3)) << 3) + (b & 7); }
+};
+
 // Geometry of one ray's upwind short characteristic on a uniform grid
 // (section 3.3): identical for every vertex, so computed once on the host.
 struct RayGeo {
@@ -35,7 +59,7 @@ struct SweepArgs {
     int periodic[3];
     int64_t cells;
     int64_t plane[3];         // vertices in the plane normal to each axis
-    int64_t pplane[3];        // same, padded by one vertex row and column at -1
+    int64_t pplane[3];        // values per slot of the face planes (FacePlane::slot)
     const RayGeo *rays;       // [na], octant-major
     const Real *chi;          // [nf][cells]
     const double *S;          // [nf][cells] source function (always FP64)

@@ -249,14 +249,14 @@ __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileC
     const Real *bx = A.face[0] + (rb * A.nt[0] + c.tx) * A.pplane[0];
     const Real *by = A.face[1] + (rb * A.nt[1] + c.ty) * A.pplane[1];
     const Real *bz = A.face[2] + (rb * A.nt[2] + c.tz) * A.pplane[2];
-    const int px = A.n[1] + 1;    // row pitch of an x plane (y fastest, then z)
-    const int pxy = A.n[0] + 1;   // row pitch of y and z planes (x fastest)
+    const FacePlane Fx(A.n[1], A.n[2]), Fy(A.n[0], A.n[2]), Fz(A.n[0], A.n[1]);
     const int u = lane & (T - 1), w = lane / T;
-    // interiors: x plane (y, z) = (u, w); y plane (x, z) = (u, w); z plane (x, y) = (u, w)
+    // interiors: x plane (y, z) = (u, w); y plane (x, z) = (u, w); z plane (x, y) = (u, w);
+    // each one aligned 8 x 8 block
     const bool okx = u < c.ey && w < c.ez, oky = u < c.ex && w < c.ez, okz = u < c.ex && w < c.ey;
-    const uint32_t ox = (uint32_t)((c.g0z + w + 1) * px + (c.g0y + u + 1));
-    const uint32_t oy = (uint32_t)((c.g0z + w + 1) * pxy + (c.g0x + u + 1));
-    const uint32_t oz = (uint32_t)((c.g0y + w + 1) * pxy + (c.g0x + u + 1));
+    const uint32_t ox = (uint32_t)Fx.at(c.g0y + u, c.g0z + w);
+    const uint32_t oy = (uint32_t)Fy.at(c.g0x + u, c.g0z + w);
+    const uint32_t oz = (uint32_t)Fz.at(c.g0x + u, c.g0y + w);
     sh.slot[0] = okx ? (w + 1) * CUBE_Q + (u + 1) * CUBE_P : -1;
     sh.slot[1] = oky ? (w + 1) * CUBE_Q + (u + 1) : -1;
     sh.slot[2] = okz ? (w + 1) * CUBE_P + (u + 1) : -1;
@@ -270,17 +270,17 @@ __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileC
     bool oke;
     uint32_t oe;
     int se;
-    if (row_x) {            // x plane, z = -1, y = j - 1
+    if (row_x) {            // x plane, z = -1, y = j - 1: the last row of the block below
         oke = j <= c.ey;
-        oe = (uint32_t)(c.g0z * px + c.g0y + j);
+        oe = (uint32_t)Fx.at(c.g0y + j - 1, c.g0z - 1);
         se = j * CUBE_P;
-    } else if (col_x) {     // x plane, y = -1, z = j
+    } else if (col_x) {     // x plane, y = -1, z = j: the copied last column of the block beside
         oke = j < c.ez;
-        oe = (uint32_t)((c.g0z + j + 1) * px + c.g0y);
+        oe = (uint32_t)(c.g0y > 0 ? Fx.col(c.g0y - 1, c.g0z + j) : Fx.at(-1, c.g0z + j));
         se = (j + 1) * CUBE_Q;
     } else {                // y plane, z = -1, x = j
         oke = row_y && j < c.ex;
-        oe = (uint32_t)(c.g0z * pxy + c.g0x + j + 1);
+        oe = (uint32_t)Fy.at(c.g0x + j, c.g0z - 1);
         se = j + 1;
     }
     sh.slot[3] = oke ? se : -1;
@@ -330,23 +330,42 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
         iy += SL[(w + 1) * SQ + c.ey * SP + (u + 1)];
         iz += SL[c.ez * SQ + (w + 1) * SP + (u + 1)];
     }
-    const uint32_t ofx = (uint32_t)((c.g0z + w + 1) * (A.n[1] + 1) + (c.g0y + u + 1));
-    const uint32_t ofy = (uint32_t)((c.g0z + w + 1) * (A.n[0] + 1) + (c.g0x + u + 1));
-    const uint32_t ofz = (uint32_t)((c.g0y + w + 1) * (A.n[0] + 1) + (c.g0x + u + 1));
+    const FacePlane Fx(A.n[1], A.n[2]), Fy(A.n[0], A.n[2]), Fz(A.n[0], A.n[1]);
+    const uint32_t ofx = (uint32_t)Fx.at(c.g0y + u, c.g0z + w);
+    const uint32_t ofy = (uint32_t)Fy.at(c.g0x + u, c.g0z + w);
+    const uint32_t ofz = (uint32_t)Fz.at(c.g0x + u, c.g0y + w);
+    // lanes on a full block's last column also write its copy (read by the next tile
+    // along a as its halo column)
+    const bool lastc = u == T - 1;
+    const uint32_t cfx = (uint32_t)Fx.col(c.g0y + u, c.g0z + w);
+    const uint32_t cfy = (uint32_t)Fy.col(c.g0x + u, c.g0z + w);
+    const uint32_t cfz = (uint32_t)Fz.col(c.g0x + u, c.g0y + w);
     const uint32_t owx = (uint32_t)((c.g0z + w) * A.n[1] + (c.g0y + u));
     const uint32_t owy = (uint32_t)((c.g0z + w) * A.n[0] + (c.g0x + u));
     const uint32_t owz = (uint32_t)((c.g0y + w) * A.n[0] + (c.g0x + u));
     if (okx) {
-        if (inx) fx[ofx] = vx;
-        else if (px) wx[owx] = ix;
+        if (inx) {
+            fx[ofx] = vx;
+            if (lastc) fx[cfx] = vx;
+        } else if (px) {
+            wx[owx] = ix;
+        }
     }
     if (oky) {
-        if (iny) fy[ofy] = vy;
-        else if (py) wy[owy] = iy;
+        if (iny) {
+            fy[ofy] = vy;
+            if (lastc) fy[cfy] = vy;
+        } else if (py) {
+            wy[owy] = iy;
+        }
     }
     if (okz) {
-        if (inz) fz[ofz] = vz;
-        else if (pz) wz[owz] = iz;
+        if (inz) {
+            fz[ofz] = vz;
+            if (lastc) fz[cfz] = vz;
+        } else if (pz) {
+            wz[owz] = iz;
+        }
     }
 }
 
@@ -992,7 +1011,12 @@ __device__ __forceinline__ void ghost_fill_one(const SweepArgs<Real> &A, int oct
     c.sgz = (oct & 4) ? -1 : 1;
     const int ntq = sel3(q, A.nt[0], A.nt[1], A.nt[2]);
     Real *Fq = (q == 0) ? A.face[0] : (q == 1 ? A.face[1] : A.face[2]);
-    const int64_t pos = (int64_t)t * P0 + (ib + 1) * (na_ + 1) + (ia + 1);
+    const FacePlane F(na_, nb_);
+    const int64_t slot = sel3(q, A.pplane[0], A.pplane[1], A.pplane[2]);
+    const int64_t pos = (int64_t)t * slot + F.at(ia, ib);
+    // slot 0 inside the grid: a full block's last column also goes to its copy
+    const bool copy = ia >= 0 && ib >= 0 && (ia & (T - 1)) == T - 1;
+    const int64_t cpos = (int64_t)t * slot + (copy ? F.col(ia, ib) : 0);
     // S of the folded vertex is the same for every ray of the octant: loaded once
     double Sg = 0.0;
     for (int r = 0; r < A.R; ++r) {
@@ -1002,7 +1026,10 @@ __device__ __forceinline__ void ghost_fill_one(const SweepArgs<Real> &A, int oct
         ghost_source(A, c, vx, vy, vz, ray, A.rays[ray].gidx, src, scell);
         if (DFORM && r == 0) Sg = A.S[scell];
         const double I = src ? *src : 0.0;
-        Fq[((int64_t)f * A.na + ray) * ntq * P0 + pos] = DFORM ? Real(I - Sg) : Real(I);
+        const Real v = DFORM ? Real(I - Sg) : Real(I);
+        Real *base = Fq + ((int64_t)f * A.na + ray) * ntq * slot;
+        base[pos] = v;
+        if (copy) base[cpos] = v;
     }
 }
 

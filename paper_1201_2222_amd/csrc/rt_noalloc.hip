@@ -173,9 +173,9 @@ rt_status noalloc_run(const rt_problem_desc *d, int na, const RayInput &rin, con
     A.plane[0] = (int64_t)n[1] * n[2];
     A.plane[1] = (int64_t)n[0] * n[2];
     A.plane[2] = (int64_t)n[0] * n[1];
-    A.pplane[0] = (int64_t)(n[1] + 1) * (n[2] + 1);
-    A.pplane[1] = (int64_t)(n[0] + 1) * (n[2] + 1);
-    A.pplane[2] = (int64_t)(n[0] + 1) * (n[1] + 1);
+    A.pplane[0] = FacePlane(n[1], n[2]).slot();
+    A.pplane[1] = FacePlane(n[0], n[2]).slot();
+    A.pplane[2] = FacePlane(n[0], n[1]).slot();
     for (int q = 0; q < 3; ++q) {
         A.face[q] = reinterpret_cast<Real *>(carve(sizeof(Real) * (size_t)d->nf * na * nt[q] * A.pplane[q]));
         A.wrap[q] = A.periodic[q] ? reinterpret_cast<double *>(carve(sizeof(double) * (size_t)d->nf * na * 2 * A.plane[q]))
@@ -258,8 +258,8 @@ size_t noalloc_bytes(const rt_problem_desc *d, int na)
     const size_t cells = (size_t)n[0] * n[1] * n[2], nc = cells * d->nf;
     const size_t rs = d->precision == RT_F32 ? 4 : 8;
     const size_t plane[3] = {(size_t)n[1] * n[2], (size_t)n[0] * n[2], (size_t)n[0] * n[1]};
-    const size_t pplane[3] = {(size_t)(n[1] + 1) * (n[2] + 1), (size_t)(n[0] + 1) * (n[2] + 1),
-                              (size_t)(n[0] + 1) * (n[1] + 1)};
+    const size_t pplane[3] = {(size_t)FacePlane(n[1], n[2]).slot(), (size_t)FacePlane(n[0], n[2]).slot(),
+                              (size_t)FacePlane(n[0], n[1]).slot()};
     size_t b = align256(sizeof(RayGeo) * na) + align256(sizeof(int) * nt[0] * nt[1] * nt[2]) +
                align256(sizeof(int) * 2 * d->nf);
     if (rs == 4) b += align256(4 * nc);
