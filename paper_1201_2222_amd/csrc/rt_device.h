@@ -48,24 +48,20 @@ __device__ __forceinline__ void seg_coeffs(double dt, double &E, double &psim, d
 }
 
 // FP32, difference form  D0 = D- E + (S- - S0) g  with g = (1 - e^-dt)/dt = 1 - psi0,
-// which is the plain form rewritten with D = I - S (E + psim + psi0 = 1).  g comes
-// from its Taylor series sum_n (-dt)^n/(n+1)! below dt = 0.5 (10 terms).
+// which is the plain form rewritten with D = I - S (E + psim + psi0 = 1).  One
+// exponential, h = e^(-dt/2), gives both: E = h^2 and g = h sinh(y)/y with y = dt/2.
+// Below dt = 0.5 the factor sinh(y)/y comes from its series 1 + y^2/3! + y^4/5! +
+// y^6/7! in z = dt^2 (the next term is below 5e-11 there), which avoids the
+// cancellation in 1 - E; above, g = (1 - E)/dt.
 __device__ __forceinline__ void seg_coeffs(float dt, float &E, float &g)
 {
     // both forms are evaluated and one is selected: no branch in the sweep step
-    E = __expf(-dt);
-    // Horner steps as (-dt) acc + c: one instruction with the constant inline
-    const float m = -dt;
-    float acc = 1.0f / 3628800.0f;                    // 1/10!
-    acc = fmaf(m, acc, 1.0f / 362880.0f);             // 1/9!
-    acc = fmaf(m, acc, 1.0f / 40320.0f);
-    acc = fmaf(m, acc, 1.0f / 5040.0f);
-    acc = fmaf(m, acc, 1.0f / 720.0f);
-    acc = fmaf(m, acc, 1.0f / 120.0f);
-    acc = fmaf(m, acc, 1.0f / 24.0f);
-    acc = fmaf(m, acc, 1.0f / 6.0f);
-    acc = fmaf(m, acc, 0.5f);
-    const float gs = fmaf(m, acc, 1.0f);
+    const float h = __builtin_amdgcn_exp2f(dt * -0.72134752f);   // 2^(-dt log2(e) / 2)
+    E = h * h;
+    const float z = dt * dt;
+    float acc = fmaf(z, 1.0f / 322560.0f, 1.0f / 1920.0f);   // y^6/7!, y^4/5! in z
+    acc = fmaf(z, acc, 1.0f / 24.0f);                          // y^2/3!
+    const float gs = h * fmaf(z, acc, 1.0f);
     const float gc = (1.0f - E) * __builtin_amdgcn_rcpf(dt);
     g = dt < 0.5f ? gs : gc;
 }

@@ -781,11 +781,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     if (last >= 0) write_faces<Real, DFORM, ORD>(A, c, last, lane, Ic, SL);
 }
 
+// Waves per SIMD the stage kernel is compiled for.  The FP32 one-ray-per-wave forms
+// fit eight (at most 64 VGPRs and 96 SGPRs, no spills), so three workgroups of ten
+// waves share a CU; left to itself the compiler settles on 106 SGPRs, seven waves per
+// SIMD and two such workgroups.  The other forms keep the compiler's choice.
+template <typename Real, bool MULTI>
+constexpr int stage_waves_per_simd() { return (sizeof(Real) == 4 && !MULTI) ? 8 : 1; }
+
 // One stage (all tiles with tx + ty + tz = s) of all octants (NOCT = 8) or of the
 // octants of the rays going up (NOCT = 4: octants 0 .. 3) and the active bins
 // f0 .. f0 + nfc - 1.
 template <typename Real, bool DFORM, int NQ, bool MULTI, int ORD, int NOCT = 8>
-__global__ void __launch_bounds__(64 * kMaxWaves) sweep_stage_kernel(SweepArgs<Real> A)
+__global__ void __launch_bounds__(64 * kMaxWaves, (stage_waves_per_simd<Real, MULTI>()))
+    sweep_stage_kernel(SweepArgs<Real> A)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int oct = blockIdx.x & (NOCT - 1);
