@@ -369,7 +369,7 @@ def bench_multifreq(args, rt, W, torch, np):
     achieved = sweep_rate * OPS_PER_UPDATE_F32 / 1e12
     launches = max(prof["launches"], 1)
     # the committed byte counters were taken on the full 192^3 x 64-bin workload
-    traffic = measured_traffic("multifreq") if (n == 192 and nfb == 64 and args.schedule == "stages") else None
+    traffic = measured_traffic("multifreq") if (n == 192 and nfb == 64 and args.schedule == "stages" and not gs) else None
     avg_us = prof["kernel_ms"] * 1e3 / launches
     hbm_alg = sweep_rate * BYTES_PER_UPDATE_SWEEP_F32_80 / 1e9
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
@@ -380,8 +380,9 @@ def bench_multifreq(args, rt, W, torch, np):
                 "ops_per_update": OPS_PER_UPDATE_F32, "sweep_updates_per_s": sweep_rate,
                 "hbm": {"achieved": hbm_alg, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_alg / HBM_PEAK_GBS,
                         "bytes_per_update": BYTES_PER_UPDATE_SWEEP_F32_80,
-                        "measured_gbs": (traffic / (avg_us * 1e-6) / 1e9) if traffic else None,
-                        "measured_frac": (traffic / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS) if traffic else None}}
+                        "measured_gbs": (traffic / (avg_us * 1e-6) / 1e9) if traffic and avg_us > 0 else None,
+                        "measured_frac": (traffic / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS)
+                        if traffic and avg_us > 0 else None}}
     if gs:
         # the dominant kernel of Gauss-Seidel is the chain kernel of the downward pass
         chain_s = prof["chain_ms"] / 1e3
@@ -508,9 +509,11 @@ class _ServingRun:
                 t = rt.rt_server_submit(self.srv, p.handle, S, J, delta_c=1e-6, max_iter=self.max_iter,
                                         warm_start=warm)
                 self.inflight[t] = {"arr": arr, "p": p, "S": S, "J": J, "bytes": nbytes, "fresh": fresh,
-                                    "kind": kind, "key": key, "cells": p.cells, "nf": p.nf}
+                                    "kind": kind, "key": key, "cells": p.cells, "nf": p.nf,
+                                    "t_submit": time.perf_counter() - t0}
                 self.bytes += nbytes
                 pending.pop(i)
+                break          # one request per round, so completions are polled in between
             for t in list(self.inflight):
                 r = rt.rt_server_poll(self.srv, t)
                 if r is None:
@@ -524,7 +527,10 @@ class _ServingRun:
                     rec["p"].close()
                 else:
                     self.streams[rec["key"]]["busy"] = False
-                self.done.append({"latency": now - rec["arr"], "iterations": r[1]["iterations"], "status": r[0],
+                # arrival to submission (waiting, then the request's fields and problem
+                # made on the device) plus the server's submission-to-completion time
+                lat = rec["t_submit"] - rec["arr"] + r[1]["seconds"]
+                self.done.append({"latency": lat, "iterations": r[1]["iterations"], "status": r[0],
                                   "kind": rec["kind"], "updates": float(rec["cells"]) * 48 * float(self.np.sum(it_bins)),
                                   "t_done": now})
                 print(f"{self.label}: {len(self.done)} done ({rec['kind']}), latency {self.done[-1]['latency']:.2f} s, "

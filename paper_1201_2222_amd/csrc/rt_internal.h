@@ -33,6 +33,10 @@ struct FacePlane {
     }
     // the copy of vertex (a, b) with a % 8 == 7, a, b >= 0, among the blocks' last columns
     __host__ __device__ int col(int a, int b) const { return (nblk << 6) + (((b >> 3) * nba + (a >> 3)) << 3) + (b & 7); }
+    // first value of the block of tile (ta, tb) (vertex (8 ta + u, 8 tb + w) is at + 8 w + u),
+    // and of its last column's copy (vertex (8 ta + 7, 8 tb + w) is at + w)
+    __host__ __device__ int blk(int ta, int tb) const { return (tb * nba + ta) << 6; }
+    __host__ __device__ int colblk(int ta, int tb) const { return (nblk << 6) + ((tb * nba + ta) << 3); }
 };
 
 // Geometry of one ray's upwind short characteristic on a uniform grid

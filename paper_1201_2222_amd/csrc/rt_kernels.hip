@@ -254,9 +254,9 @@ __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileC
     // interiors: x plane (y, z) = (u, w); y plane (x, z) = (u, w); z plane (x, y) = (u, w);
     // each one aligned 8 x 8 block
     const bool okx = u < c.ey && w < c.ez, oky = u < c.ex && w < c.ez, okz = u < c.ex && w < c.ey;
-    const uint32_t ox = (uint32_t)Fx.at(c.g0y + u, c.g0z + w);
-    const uint32_t oy = (uint32_t)Fy.at(c.g0x + u, c.g0z + w);
-    const uint32_t oz = (uint32_t)Fz.at(c.g0x + u, c.g0y + w);
+    const uint32_t ox = (uint32_t)(Fx.blk(c.ty, c.tz) + lane);   // lane = 8 w + u
+    const uint32_t oy = (uint32_t)(Fy.blk(c.tx, c.tz) + lane);
+    const uint32_t oz = (uint32_t)(Fz.blk(c.tx, c.ty) + lane);
     sh.slot[0] = okx ? (w + 1) * CUBE_Q + (u + 1) * CUBE_P : -1;
     sh.slot[1] = oky ? (w + 1) * CUBE_Q + (u + 1) : -1;
     sh.slot[2] = okz ? (w + 1) * CUBE_P + (u + 1) : -1;
@@ -276,7 +276,7 @@ __device__ __forceinline__ void shell_load(const SweepArgs<Real> &A, const TileC
         se = j * CUBE_P;
     } else if (col_x) {     // x plane, y = -1, z = j: the copied last column of the block beside
         oke = j < c.ez;
-        oe = (uint32_t)(c.g0y > 0 ? Fx.col(c.g0y - 1, c.g0z + j) : Fx.at(-1, c.g0z + j));
+        oe = (uint32_t)(c.ty > 0 ? Fx.colblk(c.ty - 1, c.tz) + j : Fx.at(-1, c.g0z + j));
         se = (j + 1) * CUBE_Q;
     } else {                // y plane, z = -1, x = j
         oke = row_y && j < c.ex;
@@ -331,15 +331,15 @@ __device__ void write_faces(const SweepArgs<Real> &A, const TileCtx &c, int ray,
         iz += SL[c.ez * SQ + (w + 1) * SP + (u + 1)];
     }
     const FacePlane Fx(A.n[1], A.n[2]), Fy(A.n[0], A.n[2]), Fz(A.n[0], A.n[1]);
-    const uint32_t ofx = (uint32_t)Fx.at(c.g0y + u, c.g0z + w);
-    const uint32_t ofy = (uint32_t)Fy.at(c.g0x + u, c.g0z + w);
-    const uint32_t ofz = (uint32_t)Fz.at(c.g0x + u, c.g0y + w);
+    const uint32_t ofx = (uint32_t)(Fx.blk(c.ty, c.tz) + lane);   // lane = 8 w + u
+    const uint32_t ofy = (uint32_t)(Fy.blk(c.tx, c.tz) + lane);
+    const uint32_t ofz = (uint32_t)(Fz.blk(c.tx, c.ty) + lane);
     // lanes on a full block's last column also write its copy (read by the next tile
     // along a as its halo column)
     const bool lastc = u == T - 1;
-    const uint32_t cfx = (uint32_t)Fx.col(c.g0y + u, c.g0z + w);
-    const uint32_t cfy = (uint32_t)Fy.col(c.g0x + u, c.g0z + w);
-    const uint32_t cfz = (uint32_t)Fz.col(c.g0x + u, c.g0y + w);
+    const uint32_t cfx = (uint32_t)(Fx.colblk(c.ty, c.tz) + w);
+    const uint32_t cfy = (uint32_t)(Fy.colblk(c.tx, c.tz) + w);
+    const uint32_t cfz = (uint32_t)(Fz.colblk(c.tx, c.ty) + w);
     const uint32_t owx = (uint32_t)((c.g0z + w) * A.n[1] + (c.g0y + u));
     const uint32_t owy = (uint32_t)((c.g0z + w) * A.n[0] + (c.g0x + u));
     const uint32_t owz = (uint32_t)((c.g0y + w) * A.n[0] + (c.g0x + u));

@@ -74,9 +74,17 @@ static void check(int na, int nb, int slot_index)
         for (int ta = 0; ta < nta; ++ta) {
             const int g0a = ta * T, g0b = tb * T;
             const int ea = na - g0a < T ? na - g0a : T, eb = nb - g0b < T ? nb - g0b : T;
+            for (int w = 0; w < T; ++w)
+                for (int u = 0; u < T; ++u) {   // the kernels' forms: block base + lane
+                    CHECK(F.blk(ta, tb) + 8 * w + u == F.at(g0a + u, g0b + w), "na %d nb %d: block base (%d, %d)", na,
+                          nb, ta, tb);
+                    if (u == T - 1)
+                        CHECK(F.colblk(ta, tb) + w == F.col(g0a + u, g0b + w), "na %d nb %d: column base (%d, %d)", na,
+                              nb, ta, tb);
+                }
             for (int w = 0; w < eb; ++w)
                 for (int u = 0; u < ea; ++u) {
-                    const long p = F.at(g0a + u, g0b + w);
+                    const long p = F.blk(ta, tb) + 8 * w + u;
                     CHECK(p >= 0 && p < S && mem[p] == id(g0a + u, g0b + w), "na %d nb %d slot %d: interior (%d, %d)",
                           na, nb, slot_index, g0a + u, g0b + w);
                 }
@@ -86,7 +94,7 @@ static void check(int na, int nb, int slot_index)
                       nb, slot_index, g0a + j - 1, g0b - 1);
             }
             for (int j = 0; j < eb; ++j) {    // the column at a = g0a - 1, b = g0b .. g0b + eb - 1
-                const long p = g0a > 0 ? F.col(g0a - 1, g0b + j) : F.at(-1, g0b + j);
+                const long p = ta > 0 ? F.colblk(ta - 1, tb) + j : F.at(-1, g0b + j);
                 CHECK(p >= 0 && p < S && mem[p] == id(g0a - 1, g0b + j), "na %d nb %d slot %d: column (%d, %d)", na,
                       nb, slot_index, g0a - 1, g0b + j);
             }
