@@ -73,16 +73,28 @@ KERNEL_SOURCE = {"multifreq": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", 
                  "gauss-seidel": os.path.join(ROOT, "paper_1201_2222_amd", "csrc", "rt_gs.hip")}
 
 
+# device code every kernel above also compiles in
+KERNEL_HEADERS = [os.path.join(ROOT, "paper_1201_2222_amd", "csrc", h) for h in ("rt_device.h", "rt_internal.h")]
+
+
+def kernel_source_sha256(order):
+    """SHA-256 over the kernel's source file and the device headers it includes."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in [KERNEL_SOURCE[order]] + KERNEL_HEADERS:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(order="linear"):
     """HBM bytes per sweep-stage launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary (calibrated against a plain copy), or None when the kernel source has changed
-    since the counters were taken."""
-    import hashlib
+    summary (calibrated against a plain copy), or None when the kernel source or the
+    device headers have changed since the counters were taken."""
     try:
         text = open(TRAFFIC_PROFILE[order]).read()
         fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
                                                                                    "kernel_source_sha256:")))
-        sha = hashlib.sha256(open(KERNEL_SOURCE[order], "rb").read()).hexdigest()
+        sha = kernel_source_sha256(order)
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha:
