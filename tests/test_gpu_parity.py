@@ -157,6 +157,45 @@ def test_ali_converged_parity(env, oracle_mod, precision, schedule):
     gp.close()
 
 
+_REF40 = {}
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_ali_converged_parity_40(env, oracle_mod, precision):
+    """The scattering atmosphere at 40^3 (48 rays, eps = 0.03, tau_bottom = 1e3; 5^3 tiles in
+    13 stages, face planes of 5 x 5 blocks): Jacobi ALI
+    to max|dS/S| <= 1e-6 against the oracle's converged solve (about 40 s of CPU, shared
+    by both precisions).  FP64: the oracle's iteration count and J, S within 1e-12;
+    FP32: within 2% of the count and 2e-5."""
+    rt, torch = env
+    wl = W.scattering(40, eps=3e-2, tau_bottom=1e3)
+    if "ref" not in _REF40:
+        op = oracle_mod.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, h=wl.h, bc_lo=wl.bc_lo,
+                                bc_hi=wl.bc_hi, w_nu=wl.w_nu)
+        _REF40["ref"] = op.ali(delta_c=1e-6, max_iter=5000, per_bin_stop=True)
+    ref = _REF40["ref"]
+    prec = rt.RT_F64 if precision == "f64" else rt.RT_F32
+    gp = rt.Problem(wl.shape, nf=wl.nf, h=wl.h, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, precision=prec,
+                    w_nu=wl.w_nu)
+    gp.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+    n = wl.chi.size
+    S = torch.empty(n, dtype=torch.float64, device="cuda")
+    J = torch.empty(n, dtype=torch.float64, device="cuda")
+    status, stats = gp.ali_solve(S, J, delta_c=1e-6, max_iter=5000, per_bin_stop=True)
+    torch.cuda.synchronize()
+    assert status == rt.RT_OK
+    Jg = J.cpu().numpy().reshape(ref["J"].shape)
+    Sg = S.cpu().numpy().reshape(ref["S"].shape)
+    if precision == "f64":
+        assert stats["iterations"] == int(ref["iters"][0])
+        assert _rel(Jg, ref["J"]) <= TOL64 and _rel(Sg, ref["S"]) <= TOL64
+    else:
+        assert abs(stats["iterations"] - int(ref["iters"][0])) <= max(3, 0.02 * int(ref["iters"][0]))
+        assert _rel(Jg, ref["J"]) <= TOL32 and _rel(Sg, ref["S"]) <= TOL32
+    gp.close()
+
+
 def test_workload_plain_full_size(env, oracle_mod):
     """The 32^3 grey LTE workload (24 rays, FP64): one formal solution plus a second
     with warm periodic memory, full size."""
