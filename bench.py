@@ -86,18 +86,22 @@ def kernel_source_sha256(order):
     return h.hexdigest()
 
 
-def measured_traffic(order="linear"):
-    """HBM bytes per sweep-stage launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary (calibrated against a plain copy), or None when the kernel source or the
-    device headers have changed since the counters were taken."""
+def measured_traffic(order="linear", kernel=None):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary (calibrated against a plain copy), or None when the
+    kernel source or the device headers have changed since the counters were taken, or
+    when the summary is of another kernel than `kernel`."""
     try:
         text = open(TRAFFIC_PROFILE[order]).read()
         fields = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
-                                                                                   "kernel_source_sha256:")))
+                                                                                   "kernel_source_sha256:",
+                                                                                   "kernel:")))
         sha = kernel_source_sha256(order)
     except OSError:
         return None
     if fields.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    if kernel is not None and fields.get("kernel", "").strip() != kernel:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
@@ -123,10 +127,12 @@ def _schedule(args, rt):
     return rt.RT_SCHED_PERSISTENT if args.schedule == "persistent" else rt.RT_SCHED_STAGES
 
 
-def _sweep_kernel_name(args, order):
+def _sweep_kernel_name(args, order, multi=False):
+    """The FP32 sweep kernel the library launches (multi: fewer waves than rays per octant,
+    each wave sweeping several rays)."""
     if args.schedule == "persistent":
         return "sweep_persistent_kernel<float, true>"
-    return f"sweep_stage_kernel<float, true, 1, false, {order}, 8>"
+    return f"sweep_stage_kernel<float, true, 1, {'true' if multi else 'false'}, {order}, 8>"
 
 
 def _pct(xs, q):
@@ -362,6 +368,19 @@ def bench_multifreq(args, rt, W, torch, np):
         solve(S, J, fixed_iters=Wm, check_every=Wm)
     torch.cuda.synchronize()
     print(f"multifreq: {Wm} warm-up iterations done", file=sys.stderr, flush=True)
+    # the library's launch-shape tuner picks the waves per sweep workgroup for this
+    # problem (formal solutions timed per wave count; setup, not part of the timed step)
+    waves, tune_ms = None, None
+    if args.waves > 0:
+        prob.set_waves(args.waves)
+        waves = args.waves
+    elif not args.no_tune and args.schedule == "stages":
+        if Wm <= 0:
+            solve(S, J, fixed_iters=1, check_every=1)
+        waves, tune_ms = prob.tune(S, reps=2)
+        torch.cuda.synchronize()
+        print(f"multifreq: tuned {waves} waves per workgroup "
+              f"({', '.join(f'{w}: {m:.1f}' for w, m in tune_ms.items())} ms per sweep)", file=sys.stderr, flush=True)
     # timed: K Jacobi iterations of all bins (the production path: graph-replayed chunk)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -381,13 +400,15 @@ def bench_multifreq(args, rt, W, torch, np):
     achieved = sweep_rate * OPS_PER_UPDATE_F32 / 1e12
     launches = max(prof["launches"], 1)
     # the committed byte counters were taken on the full 192^3 x 64-bin workload
-    traffic = measured_traffic("multifreq") if (n == 192 and nfb == 64 and args.schedule == "stages" and not gs) else None
+    kname = _sweep_kernel_name(args, 0, multi=waves is not None and waves < na // 8)
+    traffic = measured_traffic("multifreq", kname) if (n == 192 and nfb == 64 and args.schedule == "stages" and
+                                                     not gs) else None
     avg_us = prof["kernel_ms"] * 1e3 / launches
     hbm_alg = sweep_rate * BYTES_PER_UPDATE_SWEEP_F32_80 / 1e9
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": _sweep_kernel_name(args, 0),
+                "kernel": kname,
                 "avg_launch_us": avg_us, "timed_launches": prof["launches"],
                 "ops_per_update": OPS_PER_UPDATE_F32, "sweep_updates_per_s": sweep_rate,
                 "hbm": {"achieved": hbm_alg, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm_alg / HBM_PEAK_GBS,
@@ -418,6 +439,7 @@ def bench_multifreq(args, rt, W, torch, np):
                                f"FP32 sweeps + FP64 updates and residuals"
                                f"{'; Gauss-Seidel ALI (plane-block order)' if gs else ''}",
                    "grid": list(shape), "bins": nfb, "rays": na, "schedule": args.schedule, "ali": args.ali,
+                   "waves_per_workgroup": waves, "tuner_ms_per_sweep": tune_ms,
                    "device_bytes_library": desc_bytes},
         "roofline": roofline,
     }
@@ -832,6 +854,8 @@ def main():
     ap.add_argument("--bins", type=int, default=64, help="multifreq: bins of the 64 to run")
     ap.add_argument("--mf-n", type=int, default=192, help="multifreq: grid edge")
     ap.add_argument("--mf-converge", action="store_true", help="multifreq: also one whole solve to 1e-6 per bin")
+    ap.add_argument("--no-tune", action="store_true", help="multifreq: keep the default waves per workgroup")
+    ap.add_argument("--waves", type=int, default=0, help="multifreq: waves per sweep workgroup instead of the tuner's")
     ap.add_argument("--scattering-steps", type=int, default=3,
                     help="multifreq: converged 128^3 scattering solves reported beside the line (0 = skip)")
     ap.add_argument("--count", type=int, default=96, help="problems of the batched workload")
