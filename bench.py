@@ -194,7 +194,7 @@ def bench_batched(args, rt, W, torch, np):
         wl = W.batched_problem(k)
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
-                       precision=rt.RT_F32)
+                       precision=rt.RT_F32, schedule=_schedule(args, rt))
         p.set_fields(dev(wl.chi), dev(wl.eps), dev(wl.B))
         S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
         J = torch.empty_like(S)
@@ -242,7 +242,7 @@ def bench_batched(args, rt, W, torch, np):
         "dtype": "f32", "data": "synthetic (seeded, generated on the host)",
         "config": {"workload": f"batched: {count} uneven problems (axes 24..96, 24/48/80 rays, 1..16 bins, "
                                f"eps 1e-4..1), Jacobi ALI to max|dS/S|<=1e-6 per bin, FP32 sweeps",
-                   "problems": count},
+                   "problems": count, "schedule": args.schedule},
         "ali_solves_per_s": count / total,
         "latency_ms": {"p50": _pct(lat, 50) * 1e3, "p99": _pct(lat, 99) * 1e3},
         "iterations": {"min": int(min(iters)), "median": float(np.median(iters)), "max": int(max(iters))},

@@ -797,6 +797,8 @@ class BatchRunner {
         for (Class &c : spare_) free_class(c);
         if (d_done_) (void)hipFree(d_done_);
         if (h_done_) (void)hipHostFree(h_done_);
+        if (d_err_) (void)hipFree(d_err_);
+        if (h_err_) (void)hipHostFree(h_err_);
     }
     size_t size() const { return items_.size(); }
     const std::vector<BatchItem> &items() const { return items_; }
@@ -855,23 +857,37 @@ class BatchRunner {
                 if (c.f32) {
                     const SweepArgs<float> *a = static_cast<const SweepArgs<float> *>(c.d_args);
                     HIP_TRY(launch_ghost_fill_batch<float>(a, n, c.max_ghost, c.max_na, st_));
-                    for (size_t st = 0; st < c.max_items.size(); ++st)
-                        HIP_TRY(launch_sweep_batch_stage_f32(a, n, (int)st, c.max_items[st], c.waves, c.multi,
-                                                             c.order, st_));
+                    if (c.persist)
+                        HIP_TRY(launch_sweep_persistent_batch_f32(a, c.d_mem, c.d_items, c.nitems, n, c.d_dag, d_err_,
+                                                                  c.wait_ticks, c.waves, c.bpo, st_));
+                    else
+                        for (size_t st = 0; st < c.max_items.size(); ++st)
+                            HIP_TRY(launch_sweep_batch_stage_f32(a, n, (int)st, c.max_items[st], c.waves, c.multi,
+                                                                 c.order, st_));
                     HIP_TRY(launch_ali_update_batch<float>(c.d_upd, n, kBatchUpdateBlocks, c.max_nf, st_));
                 } else {
                     const SweepArgs<double> *a = static_cast<const SweepArgs<double> *>(c.d_args);
                     HIP_TRY(launch_ghost_fill_batch<double>(a, n, c.max_ghost, c.max_na, st_));
-                    for (size_t st = 0; st < c.max_items.size(); ++st)
-                        HIP_TRY(launch_sweep_batch_stage_f64(a, n, (int)st, c.max_items[st], c.waves, c.multi,
-                                                             c.order, st_));
+                    if (c.persist)
+                        HIP_TRY(launch_sweep_persistent_batch_f64(a, c.d_mem, c.d_items, c.nitems, n, c.d_dag, d_err_,
+                                                                  c.wait_ticks, c.waves, c.bpo, st_));
+                    else
+                        for (size_t st = 0; st < c.max_items.size(); ++st)
+                            HIP_TRY(launch_sweep_batch_stage_f64(a, n, (int)st, c.max_items[st], c.waves, c.multi,
+                                                                 c.order, st_));
                     HIP_TRY(launch_ali_update_batch<double>(c.d_upd, n, kBatchUpdateBlocks, c.max_nf, st_));
                 }
                 HIP_TRY(launch_ali_finalize_batch(c.d_upd, n, d_done_ + 2 * c.done_off, st_));
             }
         for (BatchItem &it : items_) it.issued += k;
         HIP_TRY(hipMemcpyAsync(h_done_, d_done_, sizeof(int) * 2 * items_.size(), hipMemcpyDeviceToHost, st_));
+        HIP_TRY(hipMemcpyAsync(h_err_, d_err_, sizeof(int), hipMemcpyDeviceToHost, st_));
         HIP_TRY(hipStreamSynchronize(st_));
+        if (*h_err_) {
+            HIP_TRY(hipMemsetAsync(d_err_, 0, sizeof(int), st_));
+            HIP_TRY(hipStreamSynchronize(st_));
+            return fail(RT_E_HIP, "persistent sweep: a tile dependency wait ran out");
+        }
         std::vector<int> pos(items_.size());   // member -> its slot in the flag array
         for (const Class &c : classes_)
             for (size_t j = 0; j < c.idx.size(); ++j) pos[c.idx[j]] = c.done_off + (int)j;
@@ -907,6 +923,16 @@ class BatchRunner {
         std::vector<int> max_items;           // per stage index: max workgroups over members
         int64_t max_ghost = 0;
         int max_na = 0, max_nf = 0, done_off = 0;
+        // persistent schedule: the whole sweep of every member in one launch
+        bool persist = false;
+        std::vector<PersistItem> h_items;
+        std::vector<PersistMember> h_mem;
+        PersistItem *d_items = nullptr;
+        PersistMember *d_mem = nullptr;
+        int *d_dag = nullptr;                 // [8] ticket counters of the octants
+        size_t items_cap = 0, mem_cap = 0;
+        int nitems = 0, bpo = 1;
+        uint64_t wait_ticks = 0;
     };
     hipStream_t st_;
     std::vector<BatchItem> items_;
@@ -914,6 +940,8 @@ class BatchRunner {
     int *d_done_ = nullptr;
     int *h_done_ = nullptr;
     size_t done_cap_ = 0;
+    int *d_err_ = nullptr;      // set by a persistent sweep whose dependency wait ran out
+    int *h_err_ = nullptr;
     bool dirty_ = true;
 
     static void free_class(Class &c)
@@ -923,6 +951,86 @@ class BatchRunner {
         c.d_args = nullptr;
         c.d_upd = nullptr;
         c.cap = 0;
+        free_persist(c);
+    }
+
+    static void free_persist(Class &c)
+    {
+        if (c.d_items) (void)hipFree(c.d_items);
+        if (c.d_mem) (void)hipFree(c.d_mem);
+        if (c.d_dag) (void)hipFree(c.d_dag);
+        c.d_items = nullptr;
+        c.d_mem = nullptr;
+        c.d_dag = nullptr;
+        c.items_cap = c.mem_cap = 0;
+    }
+
+    // Work list of a persistent class: stage by stage, then member, bin and tile, so
+    // upwind neighbours always come first (and are drawn earlier).
+    rt_status build_persist(Class &c)
+    {
+        const size_t n = c.idx.size();
+        c.h_mem.resize(n);
+        c.h_items.clear();
+        int max_stages = 0;
+        for (size_t j = 0; j < n; ++j) {
+            rt_problem *p = items_[c.idx[j]].p;
+            PersistMember &m = c.h_mem[j];
+            m.done = p->dag_done;
+            m.counter = p->dag_counter;
+            m.ntiles = p->ntiles;
+            m.nt0 = p->nt[0];
+            m.nt1 = p->nt[1];
+            m.pad = 0;
+            max_stages = std::max(max_stages, p->nstages);
+        }
+        for (int s2 = 0; s2 < max_stages; ++s2)
+            for (size_t j = 0; j < n; ++j) {
+                const rt_problem *p = items_[c.idx[j]].p;
+                if (s2 >= p->nstages) continue;
+                for (int f = 0; f < p->nf; ++f)
+                    for (int z = p->stage_off[s2]; z < p->stage_off[s2 + 1]; ++z)
+                        c.h_items.push_back(PersistItem{(int)j, f, z, 0});
+            }
+        if (c.h_items.size() > (size_t)INT32_MAX) return fail(RT_E_UNSUPPORTED, "persistent batch: too many tiles");
+        c.nitems = (int)c.h_items.size();
+        hipError_t e = hipSuccess;
+        if (!c.d_dag) {
+            e = hipMalloc((void **)&c.d_dag, sizeof(int) * 16);
+            if (e == hipSuccess) e = hipMemsetAsync(c.d_dag, 0, sizeof(int) * 16, st_);
+        }
+        if (e == hipSuccess && c.items_cap < c.h_items.size()) {
+            if (c.d_items) (void)hipFree(c.d_items);
+            c.d_items = nullptr;
+            c.items_cap = 0;
+            e = hipMalloc((void **)&c.d_items, sizeof(PersistItem) * std::max<size_t>(c.h_items.size(), 1));
+            if (e == hipSuccess) c.items_cap = c.h_items.size();
+        }
+        if (e == hipSuccess && c.mem_cap < n) {
+            if (c.d_mem) (void)hipFree(c.d_mem);
+            c.d_mem = nullptr;
+            c.mem_cap = 0;
+            e = hipMalloc((void **)&c.d_mem, sizeof(PersistMember) * std::max<size_t>(n, 8));
+            if (e == hipSuccess) c.mem_cap = std::max<size_t>(n, 8);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            free_persist(c);
+            return fail(RT_E_OOM, "persistent batch work list allocation failed");
+        }
+        if (c.nitems > 0)
+            HIP_TRY(hipMemcpyAsync(c.d_items, c.h_items.data(), sizeof(PersistItem) * c.h_items.size(),
+                                   hipMemcpyHostToDevice, st_));
+        HIP_TRY(hipMemcpyAsync(c.d_mem, c.h_mem.data(), sizeof(PersistMember) * n, hipMemcpyHostToDevice, st_));
+        int dev = 0, per_cu = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            persistent_batch_blocks_per_cu(c.f32 ? 4 : 8, c.waves, &per_cu) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 8) ncu = 8;
+        (void)hipGetLastError();
+        c.bpo = std::max(1, std::min(per_cu * ncu / 8, c.nitems));
+        c.wait_ticks = items_[c.idx[0]].p->wait_ticks;
+        return RT_OK;
     }
 
     template <typename Real>
@@ -951,7 +1059,7 @@ class BatchRunner {
             if (!p->plane_order)
                 for (Class &c : classes_)
                     if (!c.plane && c.f32 == p->f32 && c.waves == p->waves && c.multi == multi &&
-                        c.order == p->desc.order)
+                        c.order == p->desc.order && c.persist == p->persistent)
                         cls = &c;
             if (!cls) {
                 Class c;
@@ -964,6 +1072,7 @@ class BatchRunner {
                 c.waves = p->waves;
                 c.multi = multi;
                 c.order = p->desc.order;
+                c.persist = p->persistent;
                 classes_.push_back(std::move(c));
                 cls = &classes_.back();
             }
@@ -1021,6 +1130,10 @@ class BatchRunner {
             }
             HIP_TRY(hipMemcpyAsync(c.d_args, c.h_args.data(), c.h_args.size(), hipMemcpyHostToDevice, st_));
             HIP_TRY(hipMemcpyAsync(c.d_upd, c.h_upd.data(), n * sizeof(BatchUpdate), hipMemcpyHostToDevice, st_));
+            if (c.persist) {
+                rt_status ps = build_persist(c);
+                if (ps != RT_OK) return ps;
+            }
             c.done_off = off;
             off += (int)n;
         }
@@ -1038,6 +1151,18 @@ class BatchRunner {
                 return fail(RT_E_OOM, "batch flag allocation failed");
             }
             done_cap_ = cap;
+        }
+        if (!d_err_) {
+            hipError_t e = hipMalloc((void **)&d_err_, sizeof(int));
+            if (e == hipSuccess) e = hipHostMalloc((void **)&h_err_, sizeof(int), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipMemsetAsync(d_err_, 0, sizeof(int), st_);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                if (d_err_) (void)hipFree(d_err_);
+                d_err_ = nullptr;
+                return fail(RT_E_OOM, "batch flag allocation failed");
+            }
+            *h_err_ = 0;
         }
         // host arrays must outlive the copies: wait for them here
         HIP_TRY(hipStreamSynchronize(st_));

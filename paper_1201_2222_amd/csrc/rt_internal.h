@@ -225,6 +225,30 @@ hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs 
                                        hipStream_t st);
 hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks);
 
+// Batched persistent sweep (rt_ali_solve_batch over problems with the persistent
+// schedule).  An item is a tile of one bin of one member: the member's index in the
+// class, the bin, and the tile's position in the member's tile list.  Items are listed
+// by stage (tx + ty + tz), then member, bin and tile.
+struct PersistItem {
+    int member, f, tile, pad;
+};
+// A member's dependency state: its completion flags [nf][8][ntiles] and its counter
+// array, whose [8] is the member's epoch (advanced before every sweep).
+struct PersistMember {
+    int *done;
+    int *counter;
+    int ntiles, nt0, nt1, pad;
+};
+// dag_begin for the batch (class tickets zeroed, every member's epoch advanced), then
+// one persistent launch of 8 x bpo workgroups over nitems items.
+hipError_t launch_sweep_persistent_batch_f64(const SweepArgs<double> *args, const PersistMember *mem,
+                                             const PersistItem *items, int nitems, int nmem, int *counter, int *err,
+                                             uint64_t wait_ticks, int waves, int bpo, hipStream_t st);
+hipError_t launch_sweep_persistent_batch_f32(const SweepArgs<float> *args, const PersistMember *mem,
+                                             const PersistItem *items, int nitems, int nmem, int *counter, int *err,
+                                             uint64_t wait_ticks, int waves, int bpo, hipStream_t st);
+hipError_t persistent_batch_blocks_per_cu(int real_bytes, int waves, int *blocks);
+
 hipError_t launch_lambda_star(const int n[3], const int bc_lo[3], const int bc_hi[3], int nf, int na, int order,
                               const RayGeo *rays, const double *chi, double *lam, hipStream_t st);
 

@@ -891,6 +891,63 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
     }
 }
 
+// Before a batched persistent sweep: zero the octants' ticket counters of the batch,
+// advance the epoch of every member (each member's completion flags carry its own
+// epochs, also those of its single solves).
+__global__ void dag_begin_batch_kernel(int *counter, const PersistMember *mem, int nmem)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 8) counter[threadIdx.x] = 0;
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j < nmem) mem[j].counter[8] += 1;
+}
+
+// Formal solutions of all members of a batch class in one launch (bins and problems
+// are independent, section 3.1).  The work items are listed stage by stage: every
+// tile with tx + ty + tz = s of every member and bin comes before any tile of stage
+// s + 1, so a tile's upwind neighbours (same member, bin and octant, stage s - 1)
+// always carry smaller tickets.  Otherwise the loop is the single-problem one: the
+// workgroups of octant o draw tickets from counter[o], wait on the member's
+// completion flags, and publish each finished tile with the member's epoch.
+template <typename Real, bool DFORM>
+__global__ void __launch_bounds__(64 * kMaxWaves)
+    sweep_persistent_batch_kernel(const SweepArgs<Real> *args, const PersistMember *mem, const PersistItem *items,
+                                  int nitems, int *counter, int *err, uint64_t wait_ticks)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int s_ticket;
+    const int oct = blockIdx.x & 7;
+    int *pub = nullptr;      // completion flag of the tile this workgroup finished last
+    int pub_epoch = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            if (pub) __hip_atomic_store(pub, pub_epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            s_ticket = atomicAdd(counter + oct, 1);
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+        __syncthreads();
+        if (t < 0 || t >= nitems) break;
+        const int j = __builtin_amdgcn_readfirstlane(items[t].member);
+        const int f = __builtin_amdgcn_readfirstlane(items[t].f);
+        const int z = __builtin_amdgcn_readfirstlane(items[t].tile);
+        const SweepArgs<Real> &A = args[j];
+        const PersistMember &M = mem[j];
+        const int frozen = __builtin_amdgcn_readfirstlane(A.frozen[f]);
+        const int packed = __builtin_amdgcn_readfirstlane(A.tiles[z]);
+        const int par = __builtin_amdgcn_readfirstlane(A.parity[f]);
+        const int epoch = __builtin_amdgcn_readfirstlane(M.counter[8]);
+        pub = nullptr;
+        if (frozen | (packed < 0) | (par < 0)) continue;
+        sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, par, lds_raw, M.done, epoch, M.ntiles, M.nt0,
+                                                  M.nt1, err, wait_ticks);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        const int tid = (((packed >> 20) & 1023) * M.nt1 + ((packed >> 10) & 1023)) * M.nt0 + (packed & 1023);
+        pub = M.done + ((int64_t)f * 8 + oct) * M.ntiles + tid;
+        pub_epoch = epoch;
+    }
+}
+
 // ---- Lambda*: diagonal of the formal-solution operator (section 3.4) -----------------
 // Lambda*_ii = sum_k w_k psi0_k: the weight of S at the vertex itself in its own
 // update.  psi0 depends only on the upwind chi, so this is a pointwise kernel.  In the
@@ -1495,6 +1552,44 @@ hipError_t launch_sweep_persistent_f64(const SweepArgs<double> &A, const DagArgs
 hipError_t launch_sweep_persistent_f32(const SweepArgs<float> &A, const DagArgs &D, int waves, int bpo, hipStream_t st)
 {
     return launch_persistent<float, true>(A, D, waves, bpo, st);
+}
+
+template <typename Real, bool DFORM>
+static hipError_t launch_persistent_batch(const SweepArgs<Real> *args, const PersistMember *mem,
+                                          const PersistItem *items, int nitems, int nmem, int *counter, int *err,
+                                          uint64_t wait_ticks, int waves, int bpo, hipStream_t st)
+{
+    hipLaunchKernelGGL(dag_begin_batch_kernel, dim3((unsigned)((nmem + 63) / 64)), dim3(64), 0, st, counter, mem, nmem);
+    hipLaunchKernelGGL((sweep_persistent_batch_kernel<Real, DFORM>), dim3(8u * (unsigned)bpo), dim3(64 * waves),
+                       sweep_lds_bytes(sizeof(Real), waves, 1, true, 0), st, args, mem, items, nitems, counter, err,
+                       wait_ticks);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_persistent_batch_f64(const SweepArgs<double> *args, const PersistMember *mem,
+                                             const PersistItem *items, int nitems, int nmem, int *counter, int *err,
+                                             uint64_t wait_ticks, int waves, int bpo, hipStream_t st)
+{
+    return launch_persistent_batch<double, false>(args, mem, items, nitems, nmem, counter, err, wait_ticks, waves,
+                                                  bpo, st);
+}
+
+hipError_t launch_sweep_persistent_batch_f32(const SweepArgs<float> *args, const PersistMember *mem,
+                                             const PersistItem *items, int nitems, int nmem, int *counter, int *err,
+                                             uint64_t wait_ticks, int waves, int bpo, hipStream_t st)
+{
+    return launch_persistent_batch<float, true>(args, mem, items, nitems, nmem, counter, err, wait_ticks, waves, bpo,
+                                                st);
+}
+
+hipError_t persistent_batch_blocks_per_cu(int real_bytes, int waves, int *blocks)
+{
+    const size_t lds = sweep_lds_bytes(real_bytes, waves, 1, true, 0);
+    if (real_bytes == 8)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_batch_kernel<double, false>,
+                                                            64 * waves, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, sweep_persistent_batch_kernel<float, true>, 64 * waves,
+                                                        lds);
 }
 
 hipError_t persistent_blocks_per_cu(int real_bytes, int waves, int *blocks)

@@ -18,6 +18,11 @@ faces, that all waves of a workgroup agree on each ticket, that no wait runs out
 and that the launch ends, also for two launches in a row on the same flags (the
 epoch) and with frozen bins.
 
+The batched form (one launch over the members of a batch class) is modelled the same
+way: its work list runs stage by stage over all members, bins and tiles, each member
+keeps its own completion flags and epoch (advanced before every sweep, so flags left by
+the member's single solves are stale), and the octants' counters are shared.
+
 It also models the control flow the compiler once produced for this loop, when the
 ticket lived in a vector register: after a tile's last barrier lane 0 of wave 0
 (the only lane that publishes and draws) waited for lanes 1..63 to leave the
@@ -279,3 +284,178 @@ def test_schedule_indices_stay_in_bounds():
             for q in [(tx - 1, ty, tz), (tx, ty - 1, tz), (tx, ty, tz - 1)]:
                 if min(q) >= 0:
                     assert pos[q[0] | (q[1] << 10) | (q[2] << 20)] < pos[p]
+
+
+def batch_work_list(members):
+    """Items (member, bin, position in the member's tile list), stage by stage, then
+    member, bin and tile: the list the host builds for a persistent batch class."""
+    sched = []
+    for shape, nf in members:
+        nt, tiles = tile_schedule(shape)
+        stage_off = [0] * (nt[0] + nt[1] + nt[2] - 1)
+        for i, p in enumerate(tiles):
+            st = (p & 1023) + ((p >> 10) & 1023) + ((p >> 20) & 1023)
+            stage_off[st + 1] = i + 1
+        for k in range(1, len(stage_off)):
+            stage_off[k] = max(stage_off[k], stage_off[k - 1])
+        sched.append((nt, tiles, stage_off))
+    items = []
+    for st in range(max(len(o) - 1 for _, _, o in sched)):
+        for j, ((shape, nf), (nt, tiles, off)) in enumerate(zip(members, sched)):
+            if st >= len(off) - 1:
+                continue
+            for f in range(nf):
+                for z in range(off[st], off[st + 1]):
+                    items.append((j, f, z))
+    return sched, items
+
+
+class BatchLaunch(Launch):
+    """One persistent launch over several members of different shapes and bins."""
+
+    def __init__(self, members, waves, bpo, resident, frozen=None, seed=0, poll_limit=20000, stale=None):
+        self.members = members
+        self.sched, items = batch_work_list(members)
+        self.items = Checked(items)
+        self.W = waves
+        self.frozen = [Checked([1 if (frozen and f in frozen.get(j, ())) else 0 for f in range(nf)])
+                       for j, (_, nf) in enumerate(members)]
+        self.rng = random.Random(seed)
+        # flags left by earlier sweeps of each member (its single solves included): any
+        # value up to the member's last epoch; the batch sweep runs with the next one
+        self.epochs = []
+        self.done = []
+        for j, (shape, nf) in enumerate(members):
+            ntiles = len(self.sched[j][1])
+            last = stale[j] if stale else self.rng.randrange(0, 50)
+            self.done.append(Checked([self.rng.randrange(0, last + 1) for _ in range(nf * 8 * ntiles)]))
+            self.epochs.append(last + 1)
+        self.counter = Checked([0] * 8)
+        self.err = 0
+        self.split = False
+        self.poll_limit = poll_limit
+        self.grid = 8 * bpo
+        self.resident = resident
+        self.faces, self.swept, self.violations = {}, {}, []
+
+    def wave(self, b, w, wg):
+        oct = b & 7
+        pub = None            # (member, flag index) of the tile finished last, and its epoch
+        seen = set()
+        while True:
+            if w == 0:
+                if pub is not None:
+                    j0, i0, e0 = pub
+                    self.done[j0][i0] = e0
+                wg["ticket"] = self.counter[oct]
+                self.counter[oct] += 1
+            yield "bar"
+            t = wg["ticket"]
+            wg.setdefault("reads", {}).setdefault(wg["iter"][w], set()).add(t)
+            wg["iter"][w] += 1
+            yield "bar"
+            if t < 0 or t >= len(self.items):
+                return
+            j, f, z = self.items[t]
+            nt, tiles, _ = self.sched[j]
+            packed = Checked(tiles)[z]
+            epoch = self.epochs[j]
+            pub = None
+            if self.frozen[j][f] or packed < 0:
+                continue
+            if t in seen:
+                raise Livelock(f"workgroup {b} swept ticket {t} twice")
+            seen.add(t)
+            tx, ty, tz = packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023
+            assert tx < nt[0] and ty < nt[1] and tz < nt[2]
+            tid = (tz * nt[1] + ty) * nt[0] + tx
+            ntiles = len(tiles)
+            ups = []
+            if tx > 0:
+                ups.append(tid - 1)
+            if ty > 0:
+                ups.append(tid - nt[0])
+            if tz > 0:
+                ups.append(tid - nt[0] * nt[1])
+            if w == 0:
+                for u in ups:
+                    polls = 0
+                    while self.done[j][(f * 8 + oct) * ntiles + u] != epoch:
+                        if self.err:
+                            break
+                        polls += 1
+                        if polls > self.poll_limit:
+                            self.err = 1
+                            break
+                        yield "poll"
+            yield "bar"
+            for u in ups:
+                if self.faces.get((j, f, oct, u), 0) != self.W:
+                    self.violations.append((b, t, j, u))
+            yield "bar"
+            yield "poll"
+            yield "bar"
+            key = (j, f, oct, tid)
+            self.faces[key] = self.faces.get(key, 0) + 1
+            if w == 0:
+                self.swept[key] = self.swept.get(key, 0) + 1
+            yield "bar"
+            pub = (j, (f * 8 + oct) * ntiles + tid, epoch)
+
+
+BATCH_CASES = [
+    # members (shape, bins), waves, workgroups per octant, resident workgroups, frozen bins per member
+    ([((19, 13, 11), 2), ((8, 8, 8), 1), ((24, 9, 17), 3)], 3, 12, 96, {}),
+    ([((19, 13, 11), 2), ((8, 8, 8), 1), ((24, 9, 17), 3)], 2, 3, 10, {2: (1,)}),
+    ([((40, 8, 16), 1), ((9, 17, 8), 2)], 1, 6, 8, {0: (0,)}),
+    ([((16, 16, 16), 1)] * 4, 3, 20, 160, {}),
+    ([((7, 7, 7), 1), ((33, 25, 9), 2)], 4, 2, 3, {}),
+]
+
+
+@pytest.mark.parametrize("case", range(len(BATCH_CASES)))
+def test_persistent_batch_sweeps_every_member_tile_once_in_order(case):
+    members, waves, bpo, resident, frozen = BATCH_CASES[case]
+    for seed in range(3):
+        L = BatchLaunch(members, waves, bpo, resident, frozen=frozen, seed=100 * case + seed)
+        L.run()
+        assert L.violations == [] and L.err == 0
+        for j, (shape, nf) in enumerate(members):
+            ntiles = len(L.sched[j][1])
+            for f in range(nf):
+                off = f in frozen.get(j, ())
+                for oct in range(8):
+                    for tid in range(ntiles):
+                        assert L.swept.get((j, f, oct, tid), 0) == (0 if off else 1), (j, f, oct, tid)
+                        if not off:
+                            assert L.done[j][(f * 8 + oct) * ntiles + tid] == L.epochs[j]
+        assert all(c >= len(L.items) for c in L.counter)
+
+
+def test_persistent_batch_work_list_order():
+    """Every tile of every member and bin is listed once, and a tile's upwind
+    neighbours (same member and bin) are listed before it."""
+    members = [((19, 13, 11), 2), ((8, 8, 8), 1), ((24, 9, 17), 3), ((1, 1, 1), 2)]
+    sched, items = batch_work_list(members)
+    pos = {}
+    for i, (j, f, z) in enumerate(items):
+        nt, tiles, _ = sched[j]
+        p = tiles[z]
+        key = (j, f, p & 1023, (p >> 10) & 1023, (p >> 20) & 1023)
+        assert key not in pos
+        pos[key] = i
+    assert len(items) == sum(nf * len(sched[j][1]) for j, (_, nf) in enumerate(members))
+    for (j, f, tx, ty, tz), i in pos.items():
+        for q in [(tx - 1, ty, tz), (tx, ty - 1, tz), (tx, ty, tz - 1)]:
+            if min(q) >= 0:
+                assert pos[(j, f) + q] < i
+
+
+def test_persistent_batch_stale_epoch_would_be_caught():
+    """The epoch check is live: flags of one member left at the epoch of the batch sweep
+    (an epoch not advanced) let its tiles read upwind faces not yet written."""
+    members = [((24, 24, 24), 1), ((16, 8, 8), 1)]
+    L = BatchLaunch(members, 3, 27, 216, seed=4, stale=[5, 5])
+    L.done[0] = Checked([L.epochs[0]] * len(L.done[0]))
+    L.run()
+    assert L.violations
