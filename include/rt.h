@@ -331,7 +331,10 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
  * bins, boundaries and precision; they may all differ.  Problems of the same sweep
  * precision and waves per workgroup share every launch: per iteration one ghost-value
  * launch, one launch per stage index covering that hyperplane of all of them, one
- * update and one convergence launch.  A problem with the quadratic upwind intensity
+ * update and one convergence launch.  Problems created with RT_SCHED_PERSISTENT form
+ * classes of their own, whose sweep is one persistent launch over the tiles of all
+ * their members (listed stage by stage, so every tile's upwind neighbours come
+ * first; each member keeps its own completion flags).  A problem with the quadratic upwind intensity
  * runs its own plane-step, update and convergence launches in the same iterations.  A problem that meets the stopping rule (or its
  * max_iter / fixed_iters) leaves the batch at the next check; the others go on.
  * Results per problem are those rt_ali_solve gives for it alone (identical
