@@ -410,7 +410,7 @@ struct SegIn {
 // ORD = 0: first order (linear source between S- and S0).  ORD = 1: second order
 // (quadratic Bezier source with the control point from S-, S0 and the downwind S+).
 template <typename Real, bool ACC, int NQ, int D, bool DFORM, int ORD>
-__device__ __forceinline__ void ray_planes(const RayGeo *G, int ea, int eb, int lane, Real *Ic,
+__device__ __forceinline__ void ray_planes(const RayGeo *G, int lane, Real *Ic,
                                            const Real *chiL, const double *SL, Real *Jw)
 {
     constexpr int DA = (D == 0) ? 1 : 0, DB = (D == 2) ? 1 : 2;
@@ -418,7 +418,6 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ea, int eb, int 
     constexpr int XD = stage_stride<ORD>(D), XA = stage_stride<ORD>(DA), XB = stage_stride<ORD>(DB);
     constexpr int JD = tile_stride(D), JA = tile_stride(DA), JB = tile_stride(DB);
     const int ia = lane & (T - 1), ib = lane / T;
-    const bool act = ia < ea && ib < eb;
     const int lb = (ia + 1) * SA + (ib + 1) * SB;    // in the cube of I
     const int ls = (ia + 1) * XA + (ib + 1) * XB;    // in the staged chi and S
     const int jbase = ia * JA + ib * JB;
@@ -513,11 +512,12 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int ea, int eb, int 
             const Real v = (w00 * i00 + w10 * i10 + w01 * i01 + w11 * i11) * E + cc;
             Ic[l0] = v;
             if constexpr (ACC) {
+                // every lane adds (a lane outside a ragged tile adds to an entry the sum
+                // over the waves never reads), so the read of the entry needs no branch
+                // and goes out with the plane's other loads
                 const int j = jbase + p * JD;
-                if (act) {
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + j] += cq[q] * v;
-                }
+                for (int q = 0; q < NQ; ++q) Jw[q * T * T * T + j] += cq[q] * v;
             }
             wave_lds_order();
             E = En;
@@ -680,15 +680,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
     // for their stores stands between the sweep and the sum.
     int last = -1;
     auto sweep_ray = [&](int ray) {
-        const int d = __builtin_amdgcn_readfirstlane(G->d), a = __builtin_amdgcn_readfirstlane(G->a);
-        const int b = 3 - d - a;
-        const int ea = sel3(a, c.ex, c.ey, c.ez), eb = sel3(b, c.ex, c.ey, c.ez);
+        const int d = __builtin_amdgcn_readfirstlane(G->d);
         if (d == 0)
-            ray_planes<Real, MULTI, NQ, 0, DFORM, ORD>(G, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 0, DFORM, ORD>(G, lane, Ic, chiL, SL, Jw);
         else if (d == 1)
-            ray_planes<Real, MULTI, NQ, 1, DFORM, ORD>(G, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 1, DFORM, ORD>(G, lane, Ic, chiL, SL, Jw);
         else
-            ray_planes<Real, MULTI, NQ, 2, DFORM, ORD>(G, ea, eb, lane, Ic, chiL, SL, Jw);
+            ray_planes<Real, MULTI, NQ, 2, DFORM, ORD>(G, lane, Ic, chiL, SL, Jw);
         wave_lds_sync();
     };
     if constexpr (!MULTI) {
