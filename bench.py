@@ -427,8 +427,9 @@ def bench_multifreq(args, rt, W, torch, np):
                     "avg_launch_us": prof["chain_ms"] * 1e3 / max(prof["chain_launches"], 1),
                     "timed_launches": prof["chain_launches"],
                     "bytes_per_update": BYTES_PER_CHAIN_UPDATE_F32,
-                    "upward_sweep": {"kernel": _sweep_kernel_name(args, 0), "avg_launch_us": avg_us,
-                                     "updates_per_s": sweep_rate}}
+                    "upward_sweep": {"kernel": "sweep_stage_kernel<float, true, 1, "
+                                               f"{'true' if waves is not None and waves < na // 8 else 'false'}, 0, 4>",
+                                     "avg_launch_us": avg_us, "updates_per_s": sweep_rate}}
     out = {
         "metric": METRIC, "value": updates / dt, "unit": "updates/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",

@@ -1801,14 +1801,22 @@ rt_status gs_iteration(rt_problem *p, double *S, double *J, hipStream_t st, bool
         p->cold = false;
     }
     HIP_TRY(launch_ghost_fill<Real>(U, st));
+    // a profiled iteration also times the upward sweep's stage launches
+    const bool tu = timed && p->prof && !p->prof_pending;
     for (int s = 0; s < p->nstages; ++s) {
         U.stage_off = p->stage_off[s];
         U.stage_cnt = p->stage_off[s + 1] - p->stage_off[s];
         U.stage = s;
+        if (tu && s == 0) HIP_TRY(hipEventRecord(p->ev[0], st));
         if constexpr (sizeof(Real) == 8)
             HIP_TRY(launch_sweep_stage_f64(U, p->waves, 1, st));
         else
             HIP_TRY(launch_sweep_stage_f32(U, p->waves, 1, st));
+        if (tu && s == p->nstages - 1) HIP_TRY(hipEventRecord(p->ev[1], st));
+    }
+    if (tu) {
+        p->prof_pending = true;
+        p->prof_pending_updates = (double)p->cells * (p->na / 2) * active_bins;   // octants 0 .. 3
     }
     const GsArgs<Real> A = gs_args<Real>(p, S, J);
     const int nz = p->n[2];

@@ -31,10 +31,11 @@ SPECS = [((14, 12, 10), 2, 4, "f32", (1e-2, 1.0)), ((16, 9, 13), 1, 6, "f32", (1
          ((9, 11, 7), 2, 6, "f64", (0.01, 0.2))]
 
 
-def _make(rt, torch, k, spec):
+def _make(rt, torch, k, spec, schedule=0):
     shape, nf, n_mu, prec, er = spec
     wl = W.random_problem(shape, nf=nf, seed=700 + k, n_mu=n_mu, eps_range=er)
-    p = rt.Problem(shape, nf=nf, n_mu=n_mu, w_nu=wl.w_nu, precision=rt.RT_F32 if prec == "f32" else rt.RT_F64)
+    p = rt.Problem(shape, nf=nf, n_mu=n_mu, w_nu=wl.w_nu, precision=rt.RT_F32 if prec == "f32" else rt.RT_F64,
+                   schedule=schedule)
     p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
     n = wl.chi.size
     return p, torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda")
@@ -53,9 +54,13 @@ def _wait(rt, srv, tickets, limit=120.0):
     return out
 
 
-def test_server_queue_matches_single(env):
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_server_queue_matches_single(env, schedule):
+    """Requests queue under the budget and each result is bitwise its single solve; with
+    the persistent schedule the running requests of a class share one sweep launch."""
     rt, torch = env
-    probs = [_make(rt, torch, k, s) for k, s in enumerate(SPECS)]
+    sched = rt.RT_SCHED_PERSISTENT if schedule == "persistent" else rt.RT_SCHED_STAGES
+    probs = [_make(rt, torch, k, s, sched) for k, s in enumerate(SPECS)]
     budget = max(rt.rt_problem_bytes(p.desc) for p, _, _ in probs) * 2   # at most ~two at a time
     srv = rt.rt_server_create(budget, check_every=8)
     tickets = [rt.rt_server_submit(srv, p.handle, S, J, delta_c=1e-6, max_iter=3000) for p, S, J in probs]
@@ -80,7 +85,7 @@ def test_server_queue_matches_single(env):
     for (p, S, J), t, spec, k in zip(probs, tickets, SPECS, range(len(SPECS))):
         status, st = res[t]
         assert status == rt.RT_OK
-        p2, S2, J2 = _make(rt, torch, k, spec)
+        p2, S2, J2 = _make(rt, torch, k, spec, sched)
         s2, st2 = p2.ali_solve(S2, J2, delta_c=1e-6, max_iter=3000, check_every=8)
         torch.cuda.synchronize()
         assert st["iterations"] == st2["iterations"]
