@@ -8,8 +8,9 @@ configurations the benchmark times.
   the GPU (bitwise: bins never interact), and the thickest and thinnest bins against
   the FP64 oracle on those bins alone.
 * Batched: all 96 uneven problems submitted at once to one server, three fixed
-  iterations each; sampled members (every angle set, one to sixteen bins) bitwise
-  equal to their single solves, and the smallest member of each angle set within 2e-5 of the oracle.
+  iterations each, with stage launches and with the persistent schedule; sampled members
+  (every angle set, one to sixteen bins) bitwise equal to their single solves, and the
+  smallest member of each angle set within 2e-5 of the oracle.
 * Serving: the request pool at its real sizes through one server that must queue."""
 import time
 
@@ -41,9 +42,9 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
 
 
-def _gpu_problem(rt, torch, wl):
+def _gpu_problem(rt, torch, wl, schedule=0):
     p = rt.Problem(wl.shape, nf=wl.nf, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu,
-                   precision=rt.RT_F32)
+                   precision=rt.RT_F32, schedule=schedule)
     p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
     S = torch.empty(wl.chi.size, dtype=torch.float64, device="cuda")
     return p, S, torch.empty_like(S)
@@ -127,13 +128,17 @@ def test_multifreq_full_size(env, oracle_mod):
 
 
 @pytest.mark.timeout(600)
-def test_batched_members_full_size(env, oracle_mod):
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_batched_members_full_size(env, oracle_mod, schedule):
+    """All 96 problems through one server, three fixed iterations; with the persistent
+    schedule each batch class sweeps all of its members in one launch per iteration."""
     rt, torch = env
+    sched = rt.RT_SCHED_PERSISTENT if schedule == "persistent" else rt.RT_SCHED_STAGES
     count = 96
     wls, made = [], []
     for k in range(count):
         wl = W.batched_problem(k)
-        made.append(_gpu_problem(rt, torch, wl))
+        made.append(_gpu_problem(rt, torch, wl, sched))
         wls.append(wl)
     free, _ = torch.cuda.mem_get_info()
     srv = rt.rt_server_create(int(0.8 * free), check_every=16)
@@ -159,7 +164,7 @@ def test_batched_members_full_size(env, oracle_mod):
         sample.add(max(ks, key=lambda k: sizes[k]))
         sample.add(max(ks, key=lambda k: wls[k].nf))
     for k in sorted(sample):
-        q, S1, J1 = _gpu_problem(rt, torch, wls[k])
+        q, S1, J1 = _gpu_problem(rt, torch, wls[k], sched)
         q.ali_solve(S1, J1, fixed_iters=3)
         torch.cuda.synchronize()
         _, S, J = made[k]
