@@ -229,7 +229,9 @@ rt_status rt_problem_load_state(rt_problem *p, const void *src, size_t bytes, vo
  * boundaries) or, after create/reset, from S.  S: device [nf][cells] (read); J:
  * device [nf][cells] (written); lambda_star: device [nf][cells] or NULL, receives
  * Lambda*_ii = sum_k w_k psi0_k; all in the problem's in_dtype.  Asynchronous on the
- * stream.
+ * stream, except with RT_SCHED_PERSISTENT outside stream capture: then the call
+ * synchronises the stream after the sweep to read the dependency-wait flag, and
+ * returns RT_E_HIP if a wait ran out (under capture that check is skipped).
  */
 rt_status rt_formal_solve(rt_problem *p, const void *S, void *J, void *lambda_star,
                           void *stream);
@@ -462,7 +464,8 @@ rt_status rt_problem_profile_read(rt_problem *p, rt_profile *out);
  * state lives in a library-owned device array of 64 MiB per GPU, held until the
  * process ends, and the ray table and tile list are built on the device from kernel
  * arguments.  desc: as for rt_problem_create, with in_dtype RT_DTYPE_F64, the
- * bilinear upwind intensity and at most 80 rays (n_mu <= 8); chi, B: device FP64
+ * bilinear upwind intensity, the staged schedule (RT_SCHED_PERSISTENT gets
+ * RT_E_UNSUPPORTED) and at most 80 rays (n_mu <= 8); chi, B: device FP64
  * [nf][cells] (B for thermal boundaries); S (read), J (written), lambda_star (written
  * or NULL): device FP64 [nf][cells]; I_fixed as in the description.  Problems whose
  * workspace exceeds the 64 MiB (about 64^3 x 48 rays x 1 bin in FP32) return

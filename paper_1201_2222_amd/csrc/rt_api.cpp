@@ -1673,8 +1673,22 @@ rt_status rt_formal_solve(rt_problem *p, const void *S_usr, void *J_usr, void *l
     HIP_TRY(hipMemsetAsync(p->frozen, 0, sizeof(int) * p->nf, st));
     rt_status s = collect_timing(p);
     if (s != RT_OK) return s;
+    // the persistent schedule's dependency waits are bounded: one that ran out is
+    // reported here, which needs a synchronisation (not possible under stream capture)
+    bool check_waits = false;
+    if (p->persistent) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(st, &cs));
+        check_waits = cs == hipStreamCaptureStatusNone;
+        if (check_waits) HIP_TRY(hipMemsetAsync(p->flags + 2, 0, sizeof(int), st));
+    }
     s = sweep_current_S(p, S, st, true, p->nf);
     if (s != RT_OK) return s;
+    if (check_waits) {
+        HIP_TRY(hipMemcpyAsync(p->h_flags + 2, p->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (p->h_flags[2]) return fail(RT_E_HIP, "persistent sweep: a tile dependency wait ran out");
+    }
     if (p->f32)
         HIP_TRY(launch_partial_sum<float>(static_cast<float *>(p->part), p->npart, S, 1, p->nf, p->cells, nullptr, J,
                                           st));

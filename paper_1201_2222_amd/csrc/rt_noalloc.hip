@@ -283,6 +283,8 @@ extern "C" rt_status rt_formal_solve_noalloc(const rt_problem_desc *desc, const 
     int na = 0;
     rt_status s = validate_desc(desc, &na);
     if (s != RT_OK) return s;
+    if (desc->schedule == RT_SCHED_PERSISTENT)
+        return nfail(RT_E_UNSUPPORTED, "the no-allocation call runs the staged schedule (one launch per hyperplane)");
     if (!chi || !B || !S || !J) return nfail(RT_E_INVALID, "chi, B, S and J are required");
     if (desc->in_dtype != RT_DTYPE_F64) return nfail(RT_E_UNSUPPORTED, "the no-allocation call takes FP64 arrays");
     if (desc->interp != RT_INTERP_BILINEAR)

@@ -92,3 +92,8 @@ def test_noalloc_refuses_beyond_its_capacity(env):
     with pytest.raises(rt.RtError) as e:
         rt.rt_formal_solve_noalloc(rt.make_desc((8, 8, 8), n_mu=10), x[:512], x[:512], x[:512], x[:512])
     assert e.value.status == rt.RT_E_UNSUPPORTED
+    # the staged schedule only (its results are those of rt_formal_solve with it)
+    with pytest.raises(rt.RtError) as e:
+        rt.rt_formal_solve_noalloc(rt.make_desc((8, 8, 8), schedule=rt.RT_SCHED_PERSISTENT), x[:512], x[:512],
+                                   x[:512], x[:512])
+    assert e.value.status == rt.RT_E_UNSUPPORTED and "staged" in str(e.value)
