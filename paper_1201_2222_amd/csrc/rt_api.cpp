@@ -537,6 +537,19 @@ SweepArgs<Real> sweep_args(rt_problem *p, const double *S)
 // Waves per sweep workgroup: one per ray of the octant, capped so the dynamic LDS
 // (chi and S tiles; a cube of I and a partial-sum tile per wave) fits
 // the device's per-workgroup limit.
+// Workgroups per octant of the persistent sweep: as many as fit on the device at the
+// problem's wave count, at most one per tile and bin.
+void persistent_grid(rt_problem *p)
+{
+    int dev = 0, per_cu = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        persistent_blocks_per_cu(p->f32 ? 4 : 8, p->waves, &per_cu) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 8) ncu = 8;
+    (void)hipGetLastError();
+    p->bpo = std::max(1, std::min(per_cu * ncu / 8, p->ntiles * p->nf));
+}
+
 int sweep_waves(int R, bool f32, int order, size_t lds_limit)
 {
     int w = std::min(R, kMaxWaves);
@@ -1462,11 +1475,7 @@ rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_pro
     p->lds_limit = (size_t)lds_limit;
     p->persistent = desc->schedule == RT_SCHED_PERSISTENT;
     if (p->persistent) {
-        int per_cu = 0, ncu = 0;
-        if (persistent_blocks_per_cu(p->f32 ? 4 : 8, p->waves, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 8) ncu = 8;
-        (void)hipGetLastError();
-        p->bpo = std::max(1, std::min(per_cu * ncu / 8, p->ntiles * p->nf));
+        persistent_grid(p);
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
         (void)hipGetLastError();
@@ -2116,6 +2125,7 @@ rt_status rt_problem_set_waves(rt_problem *p, int32_t waves)
         return fail(RT_E_UNSUPPORTED, "%d waves need more LDS than the device allows", (int)waves);
     if (waves != p->waves) drop_graphs(p);   // captured launches carry the old shape
     p->waves = waves;
+    if (p->persistent) persistent_grid(p);
     return RT_OK;
 }
 
@@ -2151,6 +2161,7 @@ rt_status rt_problem_tune(rt_problem *p, const void *S_usr, int32_t reps, int32_
         if (ms_out) ms_out[w - 1] = -1.0f;
         if (sweep_lds_bytes(p->f32 ? 4 : 8, w, 1, p->R > w, p->desc.order) > p->lds_limit) continue;
         p->waves = w;
+        if (p->persistent) persistent_grid(p);
         s = sweep_current_S(p, S, st);   // untimed: caches warm, cold memory filled
         if (s == RT_OK) he = hipEventRecord(e0, st);
         for (int r = 0; r < reps && s == RT_OK && he == hipSuccess; ++r) s = sweep_current_S(p, S, st);
@@ -2173,6 +2184,7 @@ rt_status rt_problem_tune(rt_problem *p, const void *S_usr, int32_t reps, int32_
     p->cold = cold;
     if (best != keep) drop_graphs(p);
     p->waves = best;
+    if (p->persistent) persistent_grid(p);
     if (s != RT_OK) return s;
     if (he != hipSuccess) {
         (void)hipGetLastError();

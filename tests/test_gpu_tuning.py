@@ -1,6 +1,6 @@
 """Every wave count of the sweep workgroup (fewer waves than rays: each wave runs several
-rays) keeps parity with the oracle, and the autotuner picks one of them without
-disturbing the next solve."""
+rays) keeps parity with the oracle, also with the persistent schedule (whose grid follows
+the wave count), and the autotuner picks one of them without disturbing the next solve."""
 import numpy as np
 import pytest
 
@@ -34,16 +34,17 @@ def _problem(env, wl, prec, **kw):
 
 
 @pytest.mark.parametrize("waves", [1, 2, 4, 6])
-@pytest.mark.parametrize("variant", ["f64", "f32", "bezier32", "gs64"])
+@pytest.mark.parametrize("variant", ["f64", "f32", "bezier32", "gs64", "persistent32"])
 def test_wave_counts_keep_parity(env, oracle_mod, waves, variant):
     rt, torch = env
     wl = W.random_problem((19, 17, 12), nf=2, seed=1300, n_mu=6, eps_range=(1e-2, 1.0))
     order = 1 if variant == "bezier32" else 0
     prec = rt.RT_F64 if variant in ("f64", "gs64") else rt.RT_F32
     gs = variant == "gs64"
+    sched = rt.RT_SCHED_PERSISTENT if variant == "persistent32" else rt.RT_SCHED_STAGES
     op = oracle_mod.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, order=order)
     ref = op.ali_gs(fixed_iters=3) if gs else op.ali(fixed_iters=3)
-    gp = _problem(env, wl, prec, order=order)
+    gp = _problem(env, wl, prec, order=order, schedule=sched)
     gp.set_waves(waves)
     n = wl.chi.size
     S = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -56,12 +57,14 @@ def test_wave_counts_keep_parity(env, oracle_mod, waves, variant):
     gp.close()
 
 
-def test_tune_picks_a_count_and_leaves_the_solve_alone(env, oracle_mod):
+@pytest.mark.parametrize("schedule", ["stages", "persistent"])
+def test_tune_picks_a_count_and_leaves_the_solve_alone(env, oracle_mod, schedule):
     rt, torch = env
     wl = W.random_problem((24, 20, 16), nf=1, seed=1310, n_mu=6, eps_range=(1e-2, 1.0))
     op = oracle_mod.Problem(wl.shape, wl.chi, wl.eps, wl.B, n_mu=wl.n_mu, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi)
     ref = op.ali(fixed_iters=4)
-    gp = _problem(env, wl, rt.RT_F32)
+    gp = _problem(env, wl, rt.RT_F32,
+                  schedule=rt.RT_SCHED_PERSISTENT if schedule == "persistent" else rt.RT_SCHED_STAGES)
     best, ms = gp.tune(_dev(torch, wl.B), reps=2)     # cold problem: stays cold
     assert 1 <= best <= 6 and set(ms) == {1, 2, 3, 4, 5, 6}
     assert ms[best] == min(ms.values())
