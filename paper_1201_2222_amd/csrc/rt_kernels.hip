@@ -76,6 +76,13 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A wave's global stores have completed (vmcnt(0): the memory system has taken
+// them) before the workgroup barrier that precedes the publication of its tile.
+__device__ __forceinline__ void tile_stores_done()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt and lgkmcnt not waited for
+}
+
 // ---- second-order segment (section 3.3, eq. rtdisc with Bezier source) -------------
 // Over an upwind segment of optical depth x the source is the quadratic Bezier curve
 // from S0 (u = 0) through the control point Sc to S- (u = 1), u = t/x, and
@@ -528,18 +535,15 @@ __device__ __forceinline__ void ray_planes(const RayGeo *G, int lane, Real *Ic,
 }
 
 // Wait until a tile's completion flag carries this sweep's epoch.  The loop polls
-// with relaxed agent-scope loads (no cache invalidation per poll) and takes one
-// agent-scope acquire fence once the flag is seen.  The wait is bounded by the
-// constant-rate wall clock (limit_ticks) and gives up at once when another wait
+// with relaxed agent-scope loads (no cache invalidation per poll); the caller takes
+// one agent-scope acquire fence after all of a tile's waits.  The wait is bounded by
+// the constant-rate wall clock (limit_ticks) and gives up at once when another wait
 // has already run out (*err set), so every wave exits.
 __device__ __forceinline__ bool wait_done(const int *flag, int epoch, const int *err, uint64_t limit_ticks)
 {
     const uint64_t t0 = wall_clock64();
     for (int i = 0;; ++i) {
-        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return true;
-        }
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return true;
         if ((i & 15) == 15) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
             if (wall_clock64() - t0 > limit_ticks) return false;
@@ -665,6 +669,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<Real> &A, int oct, in
             if (c.tx > 0) ok = ok && wait_done(fl + (c.tz * nt1 + c.ty) * nt0 + c.tx - 1, epoch, err, limit_ticks);
             if (c.ty > 0) ok = ok && wait_done(fl + (c.tz * nt1 + c.ty - 1) * nt0 + c.tx, epoch, err, limit_ticks);
             if (c.tz > 0) ok = ok && wait_done(fl + ((c.tz - 1) * nt1 + c.ty) * nt0 + c.tx, epoch, err, limit_ticks);
+            // one acquire for the flags read above: the neighbours' faces are visible
+            // to this workgroup's loads after the barrier below
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             if (!ok) atomicOr(err, 1);
         }
         __syncthreads();
@@ -861,9 +868,11 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
     int done_f = -1, done_tile = -1;   // the tile this workgroup finished last (uniform)
     for (;;) {
         if (threadIdx.x == 0) {
-            if (done_tile >= 0)
+            if (done_tile >= 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __hip_atomic_store(D.done + ((int64_t)done_f * 8 + oct) * D.ntiles + done_tile, epoch,
-                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             s_ticket = atomicAdd(D.counter + oct, 1);
         }
         __syncthreads();
@@ -880,9 +889,10 @@ __global__ void __launch_bounds__(64 * kMaxWaves) sweep_persistent_kernel(SweepA
         if (frozen | (packed < 0) | (par < 0)) continue;
         sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, par, lds_raw, D.done, epoch, D.ntiles, D.nt0,
                                                   D.nt1, D.err, D.wait_ticks);
-        // every wave's stores of the tile reach the device scope before the barrier
-        // after which thread 0 publishes the tile
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // every wave waits for its own stores of the tile to complete before the
+        // barrier; thread 0 then publishes the tile behind one agent-scope release
+        // fence (at the top of the loop), which covers the whole workgroup's stores
+        tile_stores_done();
         __syncthreads();
         done_f = f;
         done_tile = D.tile_id(packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023);
@@ -918,7 +928,10 @@ __global__ void __launch_bounds__(64 * kMaxWaves)
     int pub_epoch = 0;
     for (;;) {
         if (threadIdx.x == 0) {
-            if (pub) __hip_atomic_store(pub, pub_epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (pub) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(pub, pub_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             s_ticket = atomicAdd(counter + oct, 1);
         }
         __syncthreads();
@@ -938,7 +951,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves)
         if (frozen | (packed < 0) | (par < 0)) continue;
         sweep_tile<Real, DFORM, true, 1, true, 0>(A, oct, f, packed, par, lds_raw, M.done, epoch, M.ntiles, M.nt0,
                                                   M.nt1, err, wait_ticks);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        tile_stores_done();
         __syncthreads();
         const int tid = (((packed >> 20) & 1023) * M.nt1 + ((packed >> 10) & 1023)) * M.nt0 + (packed & 1023);
         pub = M.done + ((int64_t)f * 8 + oct) * M.ntiles + tid;
