@@ -161,7 +161,7 @@ class Launch:
             self.faces[key] = self.faces.get(key, 0) + 1     # this wave's outgoing faces
             if w == 0:
                 self.swept[key] = self.swept.get(key, 0) + 1
-            yield "bar"      # after the agent-scope release of every wave
+            yield "bar"      # every wave's stores complete; thread 0 releases at the loop top
             done_f, done_tile = f, tid
             first = False
 
