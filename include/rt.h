@@ -310,6 +310,19 @@ rt_status rt_problem_tune(rt_problem *p, const void *S, int32_t reps, int32_t *w
                           void *stream);
 
 /*
+ * rt_problem_set_wait_limit -- bound of one dependency wait of the persistent schedule
+ * (section 3.1: a tile waits for its upwind neighbours), in microseconds of the
+ * device's constant-rate clock; the default is 20000.  A wait that runs out makes
+ * the call that ran the sweep return RT_E_HIP (the launch still completes; its
+ * results are not valid).  For devices shared with other work a longer bound may be
+ * needed; 0 makes every wait whose flag is not already set fail (a test of that path
+ * needs nothing else).  In a batch the largest bound among a class's members applies.
+ * RT_E_INVALID for a negative, non-finite or larger than 1e9 value.  No effect on the
+ * staged schedule.  Host-only call.
+ */
+rt_status rt_problem_set_wait_limit(rt_problem *p, double microseconds);
+
+/*
  * rt_problem_use_graphs -- rt_ali_solve and rt_ali_solve_gs run their iterations in
  * chunks of check_every (the host reads the convergence flags between chunks).  With
  * graphs enabled (the default) a chunk is captured once as a HIP graph on a stream of

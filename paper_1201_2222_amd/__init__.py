@@ -29,7 +29,7 @@ RT_DTYPE_F64, RT_DTYPE_F32 = 0, 1
 EXPORTS = ("rt_status_string", "rt_last_error", "rt_context_create", "rt_context_destroy", "rt_quadrature", "rt_problem_bytes", "rt_problem_create",
            "rt_problem_destroy", "rt_problem_set_fields", "rt_problem_reset_periodic", "rt_problem_state_bytes",
            "rt_problem_save_state", "rt_problem_load_state", "rt_formal_solve",
-           "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_problem_set_waves",
+           "rt_ali_solve", "rt_ali_solve_gs", "rt_problem_use_graphs", "rt_problem_set_waves", "rt_problem_set_wait_limit",
            "rt_problem_tune", "rt_ali_bin_stats", "rt_moments", "rt_problem_profile", "rt_problem_profile_read",
            "rt_ali_solve_batch", "rt_server_create", "rt_server_submit", "rt_server_poll", "rt_server_release",
            "rt_server_load", "rt_server_destroy", "rt_formal_solve_noalloc")
@@ -106,6 +106,7 @@ def load():
     lib.rt_ali_solve_gs.argtypes = [P, ctypes.POINTER(AliOpts), P, P, ctypes.POINTER(AliStats), P]
     lib.rt_problem_use_graphs.argtypes = [P, I32]
     lib.rt_problem_set_waves.argtypes = [P, I32]
+    lib.rt_problem_set_wait_limit.argtypes = [P, ctypes.c_double]
     lib.rt_problem_tune.argtypes = [P, P, I32, ctypes.POINTER(I32), P, P]
     lib.rt_ali_bin_stats.argtypes = [P, P, P, P]
     lib.rt_moments.argtypes = [P, P, ctypes.POINTER(MomentsOut), P]
@@ -501,6 +502,9 @@ class Problem:
 
     def set_waves(self, waves):
         _check(load().rt_problem_set_waves(self.handle, int(waves)))
+
+    def set_wait_limit(self, microseconds):
+        _check(load().rt_problem_set_wait_limit(self.handle, float(microseconds)))
 
     def tune(self, S, reps=3, stream=None):
         """Time the sweep for every wave count, keep the fastest: (waves, {waves: ms})."""

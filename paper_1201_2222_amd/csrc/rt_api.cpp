@@ -327,7 +327,8 @@ struct rt_problem {
     bool persistent = false;           // one launch per sweep (dependency flags)
     int ntiles = 0;                    // tiles per (bin, octant)
     int bpo = 1;                       // persistent workgroups per octant
-    uint64_t wait_ticks = 0;           // 20 ms in device wall-clock ticks
+    uint64_t wait_ticks = 0;           // bound of one dependency wait in device wall-clock ticks
+    int wall_khz = 100000;             // the device's constant-rate clock
     int *dag_counter = nullptr;        // [8] ticket counters
     // moments epilogue scratch (allocated on first use)
     int mom_nfc = 0;                   // bins per moments chunk
@@ -1042,7 +1043,8 @@ class BatchRunner {
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 8) ncu = 8;
         (void)hipGetLastError();
         c.bpo = std::max(1, std::min(per_cu * ncu / 8, c.nitems));
-        c.wait_ticks = items_[c.idx[0]].p->wait_ticks;
+        c.wait_ticks = 0;
+        for (size_t j = 0; j < n; ++j) c.wait_ticks = std::max(c.wait_ticks, items_[c.idx[j]].p->wait_ticks);
         return RT_OK;
     }
 
@@ -1474,13 +1476,14 @@ rt_status rt_problem_create(rt_context *ctx, const rt_problem_desc *desc, rt_pro
     p->waves = sweep_waves(p->R, p->f32, desc->order, (size_t)lds_limit);
     p->lds_limit = (size_t)lds_limit;
     p->persistent = desc->schedule == RT_SCHED_PERSISTENT;
-    if (p->persistent) {
-        persistent_grid(p);
+    {
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
         (void)hipGetLastError();
+        p->wall_khz = khz;
         p->wait_ticks = (uint64_t)khz * 20;   // 20 ms
     }
+    if (p->persistent) persistent_grid(p);
     if (sweep_lds_bytes(p->f32 ? 4 : 8, p->waves, 1, p->R > p->waves, desc->order) > (size_t)lds_limit) {
         rt_problem_destroy(p);
         return fail(RT_E_UNSUPPORTED, "sweep needs %zu bytes of LDS, device allows %d",
@@ -2126,6 +2129,16 @@ rt_status rt_problem_set_waves(rt_problem *p, int32_t waves)
     if (waves != p->waves) drop_graphs(p);   // captured launches carry the old shape
     p->waves = waves;
     if (p->persistent) persistent_grid(p);
+    return RT_OK;
+}
+
+rt_status rt_problem_set_wait_limit(rt_problem *p, double microseconds)
+{
+    if (!p) return fail(RT_E_INVALID, "problem is NULL");
+    if (!(microseconds >= 0.0) || microseconds > 1e9) return fail(RT_E_INVALID, "wait limit must be in [0, 1e9] us");
+    const uint64_t ticks = (uint64_t)(microseconds * 1e-3 * (double)p->wall_khz);
+    if (ticks != p->wait_ticks) drop_graphs(p);   // captured launches carry the old bound
+    p->wait_ticks = ticks;
     return RT_OK;
 }
 

@@ -2,7 +2,9 @@
 below what the tolerance needs gives RT_NOT_CONVERGED with the results of exactly that
 many iterations; a NaN or an Inf in the fields gives RT_E_NONFINITE (the residual
 reduction flags it) in single solves, Gauss-Seidel, batches (only the problem at fault;
-the others finish with their own results) and the serving loop, which keeps serving."""
+the others finish with their own results) and the serving loop, which keeps serving; a
+dependency wait of the persistent schedule that runs out (a wait bound of zero) gives
+RT_E_HIP, after which the problem works again."""
 import time
 
 import numpy as np
@@ -151,3 +153,45 @@ def test_server_reports_each_request(env):
     rt.rt_server_destroy(srv)
     for m in (ok, bad, capped):
         m[0].close()
+
+
+@pytest.mark.parametrize("path", ["formal", "ali", "batch"])
+def test_persistent_wait_that_runs_out_is_reported(env, path):
+    """With a wait bound of zero every dependency wait of the persistent sweep whose
+    flag is not already set gives up at once (the launch still completes), and the call
+    reports RT_E_HIP; with the default bound again the problem's next formal solution
+    is bitwise that of a fresh problem (no periodic axis, so nothing carries over)."""
+    rt, torch = env
+    shape = (40, 32, 24)
+    wl = W.random_problem(shape, nf=2, seed=1540, n_mu=6, bc_lo=(W.THERMAL,) * 3, bc_hi=(W.VACUUM,) * 3)
+
+    def make():
+        p = rt.Problem(shape, nf=2, n_mu=6, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu, precision=rt.RT_F32,
+                       schedule=rt.RT_SCHED_PERSISTENT)
+        p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+        return p
+
+    p = make()
+    S = _dev(torch, wl.B)
+    J = torch.empty_like(S)
+    p.set_wait_limit(0)
+    with pytest.raises(rt.RtError) as e:
+        if path == "formal":
+            p.formal_solve(S, J)
+        elif path == "ali":
+            p.ali_solve(S.clone(), J, fixed_iters=2)
+        else:
+            rt.rt_ali_solve_batch([p.handle], [S.clone()], [J], fixed_iters=2)
+    torch.cuda.synchronize()
+    assert e.value.status == rt.RT_E_HIP and "wait ran out" in str(e.value)
+    p.set_wait_limit(20000)
+    p.formal_solve(S, J)
+    q = make()
+    J2 = torch.empty_like(S)
+    q.formal_solve(S, J2)
+    torch.cuda.synchronize()
+    assert np.array_equal(J.cpu().numpy(), J2.cpu().numpy())
+    with pytest.raises(rt.RtError):
+        p.set_wait_limit(-1.0)
+    p.close()
+    q.close()
