@@ -359,9 +359,12 @@ rt_status rt_ali_bin_stats(rt_problem *p, int32_t *iters, double *resid, void *s
  * [n] of device pointers as for rt_ali_solve (each in its problem's in_dtype); stats,
  * results: host arrays [n] or NULL (per-problem RT_OK / RT_NOT_CONVERGED /
  * RT_E_NONFINITE; stats.seconds = wall time until that problem left the batch).
- * opts apply to every problem.  Returns RT_E_NONFINITE if any problem hit a
- * non-finite residual, else RT_NOT_CONVERGED if any did not converge, else RT_OK.
- * Synchronises the stream every check_every iterations.
+ * opts apply to every problem.  A dependency wait of a persistent sweep that runs
+ * out (rt_problem_set_wait_limit) ends the members of the persistent classes with
+ * RT_E_HIP at that check; the others go on.  Returns RT_E_HIP if any member ended so,
+ * else RT_E_NONFINITE if any problem hit a non-finite residual, else
+ * RT_NOT_CONVERGED if any did not converge, else RT_OK.  Synchronises the stream
+ * every check_every iterations.
  */
 rt_status rt_ali_solve_batch(rt_context *ctx, rt_problem *const *problems, int32_t n, const rt_ali_opts *opts,
                              void *const *S_inout, void *const *J_out, rt_ali_stats *stats,
@@ -397,8 +400,9 @@ rt_status rt_server_submit(rt_server *srv, rt_problem *p, const rt_ali_opts *opt
                            void *J_out, void *stream, uint64_t *ticket);
 
 /* RT_E_BUSY while the request is queued or running; RT_OK once it has finished,
- * with *result its solve status (RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE, or the
- * error that stopped the batch) and *stats its statistics (seconds = time from
+ * with *result its solve status (RT_OK, RT_NOT_CONVERGED, RT_E_NONFINITE, RT_E_HIP
+ * for a persistent-schedule request whose dependency wait ran out (the server goes
+ * on), or the error that stopped the server) and *stats its statistics (seconds = time from
  * submission to completion, queueing included).  Either output may be NULL.  A
  * finished ticket can be polled until rt_server_release; unknown tickets give
  * RT_E_INVALID.  Never blocks on the device. */

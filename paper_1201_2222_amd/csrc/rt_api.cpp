@@ -789,6 +789,7 @@ struct BatchItem {
     int issued = 0;        // iterations issued so far
     int total = 0;         // fixed_iters, or max_iter
     bool nonfinite = false;
+    rt_status err = RT_OK; // a sweep of this member failed (the persistent schedule's wait ran out)
     uint64_t tag = 0;      // caller's handle (batch index, server ticket)
 };
 
@@ -897,20 +898,29 @@ class BatchRunner {
         HIP_TRY(hipMemcpyAsync(h_done_, d_done_, sizeof(int) * 2 * items_.size(), hipMemcpyDeviceToHost, st_));
         HIP_TRY(hipMemcpyAsync(h_err_, d_err_, sizeof(int), hipMemcpyDeviceToHost, st_));
         HIP_TRY(hipStreamSynchronize(st_));
-        if (*h_err_) {
+        // a dependency wait of a persistent sweep ran out: the members of the persistent
+        // classes leave the batch with RT_E_HIP (the flag does not say which class), the
+        // others go on
+        const bool wait_failed = *h_err_ != 0;
+        if (wait_failed) {
             HIP_TRY(hipMemsetAsync(d_err_, 0, sizeof(int), st_));
             HIP_TRY(hipStreamSynchronize(st_));
-            return fail(RT_E_HIP, "persistent sweep: a tile dependency wait ran out");
+            *h_err_ = 0;
         }
         std::vector<int> pos(items_.size());   // member -> its slot in the flag array
+        std::vector<char> persist(items_.size(), 0);
         for (const Class &c : classes_)
-            for (size_t j = 0; j < c.idx.size(); ++j) pos[c.idx[j]] = c.done_off + (int)j;
+            for (size_t j = 0; j < c.idx.size(); ++j) {
+                pos[c.idx[j]] = c.done_off + (int)j;
+                persist[c.idx[j]] = c.persist;
+            }
         std::vector<BatchItem> keep;
         for (size_t i = 0; i < items_.size(); ++i) {
             BatchItem it = items_[i];
             const int g = pos[i];
             it.nonfinite = h_done_[2 * g + 1] != 0;
-            if (h_done_[2 * g] || it.issued >= it.total)
+            if (wait_failed && persist[i]) it.err = RT_E_HIP;
+            if (it.err != RT_OK || h_done_[2 * g] || it.issued >= it.total)
                 finished.push_back(it);
             else
                 keep.push_back(it);
@@ -2454,6 +2464,7 @@ rt_status rt_ali_solve_batch(rt_context *ctx, rt_problem *const *problems, int32
     std::vector<BatchItem> finished;
     std::vector<double> secs(n, 0.0);
     std::vector<char> nonfin(n, 0);
+    std::vector<rt_status> errs(n, RT_OK);
     while (run.size() > 0) {
         const size_t before = finished.size();
         rt_status s = run.chunk(every, finished);
@@ -2462,6 +2473,7 @@ rt_status rt_ali_solve_batch(rt_context *ctx, rt_problem *const *problems, int32
         for (size_t k = before; k < finished.size(); ++k) {
             secs[finished[k].tag] = t;
             nonfin[finished[k].tag] = finished[k].nonfinite;
+            errs[finished[k].tag] = finished[k].err;
         }
     }
     rt_status worst = RT_OK;
@@ -2475,10 +2487,14 @@ rt_status rt_ali_solve_batch(rt_context *ctx, rt_problem *const *problems, int32
         rt_status r = RT_OK;
         rt_status s = ali_stats(p, opts, nonfin[i] != 0, secs[i], stats ? &stats[i] : nullptr, st, &r);
         if (s != RT_OK) return s;
+        if (errs[i] != RT_OK) r = errs[i];
         if (results) results[i] = r;
-        if (r == RT_E_NONFINITE) worst = RT_E_NONFINITE;
+        if (r == RT_E_HIP) worst = RT_E_HIP;
+        else if (r == RT_E_NONFINITE && worst != RT_E_HIP) worst = RT_E_NONFINITE;
         else if (r == RT_NOT_CONVERGED && worst == RT_OK) worst = RT_NOT_CONVERGED;
     }
+    if (worst == RT_E_HIP)
+        return fail(RT_E_HIP, "persistent sweep: a tile dependency wait ran out in a problem of the batch");
     if (worst == RT_E_NONFINITE) return fail(RT_E_NONFINITE, "non-finite residual in at least one problem of the batch");
     return worst;
 }
@@ -2634,6 +2650,7 @@ struct rt_server {
                         if (e != hipSuccess) s2 = fail(RT_E_HIP, "conversion launch failed: %s", hipGetErrorString(e));
                     }
                     if (s2 == RT_OK) s2 = ali_stats(b.p, &b.opts, b.nonfinite, 0.0, &sts, st, &r);
+                    if (s2 == RT_OK && b.err != RT_OK) r = b.err;
                     std::lock_guard<std::mutex> lk(mu);
                     finish(b.tag, s2 != RT_OK ? s2 : r, sts);
                 }

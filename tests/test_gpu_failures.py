@@ -195,3 +195,43 @@ def test_persistent_wait_that_runs_out_is_reported(env, path):
         p.set_wait_limit(-1.0)
     p.close()
     q.close()
+
+
+def test_server_goes_on_after_a_wait_that_runs_out(env):
+    """In the serving loop a persistent-schedule request whose dependency wait runs out
+    ends with RT_E_HIP while a staged request in the same batch finishes with the
+    result of its solve alone, and the server keeps serving (a later persistent
+    request with the default bound is fine)."""
+    rt, torch = env
+    shape = (32, 24, 16)
+    wls = [W.random_problem(shape, nf=2, seed=1550 + k, n_mu=6, bc_lo=(W.THERMAL,) * 3, bc_hi=(W.VACUUM,) * 3)
+           for k in range(2)]
+
+    def make(wl, sched):
+        p = rt.Problem(shape, nf=2, n_mu=6, bc_lo=wl.bc_lo, bc_hi=wl.bc_hi, w_nu=wl.w_nu, precision=rt.RT_F32,
+                       schedule=sched)
+        p.set_fields(_dev(torch, wl.chi), _dev(torch, wl.eps), _dev(torch, wl.B))
+        n = wl.chi.size
+        return p, torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda")
+
+    bad = make(wls[0], rt.RT_SCHED_PERSISTENT)
+    good = make(wls[1], rt.RT_SCHED_STAGES)
+    bad[0].set_wait_limit(0)
+    srv = rt.rt_server_create(1 << 34, check_every=4)
+    torch.cuda.synchronize()
+    tb = rt.rt_server_submit(srv, bad[0].handle, bad[1], bad[2], fixed_iters=8)
+    tg = rt.rt_server_submit(srv, good[0].handle, good[1], good[2], fixed_iters=8)
+    out = _wait(rt, srv, [tb, tg])
+    assert out[tb][0] == rt.RT_E_HIP
+    assert out[tg][0] == rt.RT_OK
+    alone = make(wls[1], rt.RT_SCHED_STAGES)
+    alone[0].ali_solve(alone[1], alone[2], fixed_iters=8, check_every=4)
+    torch.cuda.synchronize()
+    assert np.array_equal(good[1].cpu().numpy(), alone[1].cpu().numpy())
+    # the server is alive: the same problem again with the default bound
+    bad[0].set_wait_limit(20000)
+    t2 = rt.rt_server_submit(srv, bad[0].handle, bad[1], bad[2], fixed_iters=8)
+    assert _wait(rt, srv, [t2])[t2][0] == rt.RT_OK
+    rt.rt_server_destroy(srv)
+    for m in (bad, good, alone):
+        m[0].close()
