@@ -130,6 +130,13 @@ def test_schedule_validation(rt):
     assert lib.rt_problem_bytes(ctypes.byref(d), ctypes.byref(b)) == rt.RT_E_INVALID
 
 
+def test_problem_call_argument_errors(rt):
+    """Calls on a NULL problem are refused before any device work."""
+    lib = rt.load()
+    assert lib.rt_problem_set_wait_limit(None, ctypes.c_double(1.0)) == rt.RT_E_INVALID
+    assert lib.rt_problem_set_waves(None, 2) == rt.RT_E_INVALID
+
+
 def test_batch_and_server_argument_errors(rt):
     """Argument checks of the batched solve and the serving loop, which run before any
     device work (no GPU needed)."""
